@@ -1,0 +1,92 @@
+"""Pins for the oracle's GoDec loops (Algorithm 1; Eq. 3-4; Theorem 1)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import godec_ref as g
+from oracle.rng_ref import a1_gaussian
+from paper_1309_0302_amd import workloads as wl
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def w1_runs():
+    w = wl.w1()
+    A1 = a1_gaussian(w.seed, w.X.shape[1], w.r)
+    tb = g.godec_brp(w.X, w.r, w.k, w.q, A1, w.iters, keep_supports=True)
+    tn = g.godec_naive(w.X, w.r, w.k, w.iters, keep_supports=True)
+    return w, tb, tn
+
+
+def test_w1_trajectory_equals_naive_svd_godec(w1_runs):
+    """P3: on the 500 x 500 workload Algorithm 1 and the naive SVD GoDec
+    (Eq. 4) select identical supports in every iteration and end at the same
+    L to rounding."""
+    w, tb, tn = w1_runs
+    for a, b in zip(tb.supports, tn.supports):
+        assert np.array_equal(a, b)
+    assert g.rel_fro(tb.L, tn.L) < 1e-12
+    assert g.rel_fro(tb.S, tn.S) < 1e-12
+
+
+def test_s_step_monotone_and_invariants(w1_runs):
+    """Theorem 1, first inequality (exact for the top-k S step), and the
+    cardinality / rank invariants."""
+    w, tb, _ = w1_runs
+    for e1, e2 in zip(tb.e1, tb.e2):
+        assert e2 <= e1 * (1 + 1e-14)
+    assert np.count_nonzero(tb.S) == w.k
+    s = np.linalg.svd(tb.L, compute_uv=False)
+    assert s[w.r] <= 1e-12 * s[0]
+    # converged to the noise floor: ||G||^2/||X||^2 with G std sqrt(1e-3)
+    floor = 1e-3 * w.X.size / np.sum(w.X ** 2)
+    assert tb.rel_err_sq[-1] < 1.2 * floor
+
+
+def test_naive_exact_recovery_noiseless():
+    w = wl.tiny(60, 50, 3, rho=0.03, amp=5.0, noise_std=0.0, seed=4)
+    tn = g.godec_naive(w.X, 3, w.k, 30)
+    assert g.rel_fro(tn.L, w.L0) < 1e-10
+
+
+def test_brp_exact_recovery_noiseless():
+    w = wl.tiny(80, 60, 3, rho=0.03, amp=5.0, noise_std=0.0, seed=5)
+    A1 = a1_gaussian(1, 60, 3)
+    tb = g.godec_brp(w.X, 3, w.k, 1, A1, 30)
+    assert g.rel_fro(tb.L, w.L0) < 1e-10
+    assert np.array_equal(np.flatnonzero(tb.S), w.S0_idx)
+
+
+def test_rank_drop_carries_to_later_iterations():
+    rng = np.random.default_rng(3)
+    L0 = rng.standard_normal((40, 2)) @ rng.standard_normal((2, 30))
+    tb = g.godec_brp(L0, 4, 20, 1, rng.standard_normal((30, 4)), 3)
+    assert tb.r_eff == 2 and tb.left.shape[1] == 2
+    assert g.rel_fro(tb.L, L0) < 1e-12
+
+
+def test_table1_row500_regime():
+    """P8: regenerate the Table 1 setup at size 500 and check the errors are
+    in the printed regime (statistical, not parity)."""
+    with open(os.path.join(GOLD, "table1_row500.json")) as f:
+        gold = json.load(f)
+    n, r, card = gold["size"], gold["rank"], gold["card"]
+    rng = np.random.default_rng(2013)
+    A, B = rng.standard_normal((n, r)), rng.standard_normal((r, n))
+    L = A @ B
+    S = np.zeros((n, n))
+    S.flat[rng.choice(n * n, card, replace=False)] = rng.standard_normal(card)
+    X = L + S + 1e-3 * rng.standard_normal((n, n))
+    tr = g.godec_brp(X, r, card, gold["q"], rng.standard_normal((n, r)), 200,
+                     eps=gold["eps"])
+    rx = tr.rel_err_sq[-1]
+    rl = np.sum((L - tr.L) ** 2) / np.sum(L ** 2)
+    rs = np.sum((S - tr.S) ** 2) / np.sum(S ** 2)
+    pg = gold["printed_godec"]
+    assert rx <= gold["eps"]
+    for got, ref in ((rx, pg["rel_err_X"]), (rl, pg["rel_err_L"]),
+                     (rs, pg["rel_err_S"])):
+        assert ref / 30 <= got <= ref * 30
