@@ -1,0 +1,192 @@
+"""Benchmark of GoDec by bilateral random projection on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 30] [--warmup 5]
+
+Workload: the 10000 x 10000 FP32 matrix X = U V^T + S0 + G (U, V 10000 x 20,
+unit-variance U V^T entries; 2e6 sparse entries U[-5, 5]; noise std 0.01),
+r = 20, k = 2e6, q = 2, synthetic and seeded (paper_1309_0302_amd.workloads).
+A step is one GoDec iteration (Algorithm 1: the BRP low-rank update with the
+power scheme, then the top-k sparse update) over the whole matrix, with X
+already resident in device memory.  `--steps K` iterations are timed as one
+solve from S_0 = 0; in the headline mixed-precision form the last iteration
+is the FP32 refinement.  The same K iterations are also timed in plain FP32.
+
+Prints one JSON line with the headline value (iterations/s of the bf16 +
+refinement form), the FP32 plain figure beside it, the roofline of the
+dominant streaming kernel (HIP events on the library's stream), and the FP64
+oracle timed on the host cores on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("GoDec-BRP iter/s @10k×10k r=20: BF16-MFMA+refine vs FP32 plain "
+          "at 1e-5 err")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def rel_diff_factors(a_l, a_r, b_l, b_r):
+    """||A_l A_r^T - B_l B_r^T||_F / ||B_l B_r^T||_F in FP64 on the device."""
+    import torch
+
+    def inner(p1, q1, p2, q2):
+        return float(torch.sum((p1.T @ p2) * (q1.T @ q2)))
+    a_l, a_r, b_l, b_r = (t.double() for t in (a_l, a_r, b_l, b_r))
+    aa = inner(a_l, a_r, a_l, a_r)
+    bb = inner(b_l, b_r, b_l, b_r)
+    ab = inner(a_l, a_r, b_l, b_r)
+    return max(aa - 2 * ab + bb, 0.0) ** 0.5 / bb ** 0.5
+
+
+def run_form(X, w, prec, steps, warmup, seed):
+    """Time `steps` iterations (one solve); returns timing, stats, factors."""
+    import torch
+    from paper_1309_0302_amd.binding import GoDec
+    stream = torch.cuda.current_stream()
+    if warmup > 0:
+        g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1)
+        g.step(warmup, warmup)
+        g.info()
+        g.close()
+    g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    g.step(steps, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    info = g.info()
+    UL, VL = g.factors()
+    g.close()
+    # the same solve again with per-kernel event timing switched on
+    g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1)
+    g.profile(True)
+    g.step(steps, steps)
+    stats = g.profile_read()
+    g.profile(False)
+    g.close()
+    return dict(ms=ev_ms, wall_s=wall, info=info, UL=UL, VL=VL, stats=stats)
+
+
+def roofline_of(stats):
+    dom = max(stats, key=lambda s: s["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(avg_ms * 1e3, 2),
+            "bytes_per_launch": dom["bytes_per_launch"],
+            "launches": dom["launches"]}
+
+
+def cpu_baseline(w, iters):
+    """The FP64 oracle on the host cores, `iters` iterations of the same X."""
+    import numpy as np
+    from oracle import godec_ref as g
+    from oracle.rng_ref import a1_gaussian
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(i.get("num_threads", 1) for i in threadpool_info()) or 1
+    except Exception:
+        threads = os.cpu_count() or 1
+    A1 = a1_gaussian(w.seed, w.X.shape[1], w.r)
+    X = w.X.astype(np.float64)
+    t0 = time.perf_counter()
+    g.godec_brp(X, w.r, w.k, w.q, A1, iters)
+    dt = time.perf_counter() - t0
+    return {"value": round(iters / dt, 4), "unit": "iter/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{iters} FP64 oracle iterations of the full "
+                      f"{w.X.shape[0]}x{w.X.shape[1]} workload (numpy/OpenBLAS), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=1003)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--size", type=int, default=10000,
+                    help="square size (default: the 10000 x 10000 workload)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the multi-GPU row sharding is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GODEC_PREC_BF16_REFINE, GODEC_PREC_NATIVE
+
+    log(f"[bench] generating workload {args.size}x{args.size}")
+    w = workloads.w3(seed=args.seed, m=args.size, n=args.size)
+    X = torch.from_numpy(w.X).cuda()
+    torch.cuda.synchronize()
+    log("[bench] bf16 + refinement form")
+    bf = run_form(X, w, GODEC_PREC_BF16_REFINE, args.steps, args.warmup, args.seed)
+    log(f"[bench] bf16+refine {args.steps / (bf['ms'] * 1e-3):.1f} iter/s")
+    fp = None
+    if not args.skip_fp32:
+        log("[bench] fp32 plain form")
+        fp = run_form(X, w, GODEC_PREC_NATIVE, args.steps, args.warmup, args.seed)
+        log(f"[bench] fp32 {args.steps / (fp['ms'] * 1e-3):.1f} iter/s")
+    value = args.steps / (bf["ms"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(bf["ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": w.name + "_f32", "m": int(w.X.shape[0]),
+                   "n": int(w.X.shape[1]), "r": w.r, "k": w.k, "q": w.q,
+                   "iterations_per_solve": args.steps, "refine_iters": 1,
+                   "form": "bf16 panels (fp32 accumulate) + fp32 refinement, "
+                           "fp64 r x r core"},
+        "roofline": roofline_of(bf["stats"]),
+        "final_rel_err_sq": bf["info"]["rel_err_sq"],
+    }
+    if fp is not None:
+        out["fp32_plain"] = {"value": round(args.steps / (fp["ms"] * 1e-3), 2),
+                             "ms_per_step": round(fp["ms"] / args.steps, 4),
+                             "roofline": roofline_of(fp["stats"]),
+                             "final_rel_err_sq": fp["info"]["rel_err_sq"]}
+        out["speedup_vs_fp32_plain"] = round(value / out["fp32_plain"]["value"], 3)
+        out["rel_diff_L_bf16_refine_vs_fp32"] = rel_diff_factors(
+            bf["UL"], bf["VL"], fp["UL"], fp["VL"])
+    out["kernels"] = bf["stats"]
+    if not args.skip_cpu:
+        log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * godec.h -- C ABI of libgodec, GoDec by bilateral random projection on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhou & Tao, "Unmixing Incoherent Structures of Big Data by
+ * Randomized or Greedy Decomposition" (arXiv 1309.0302).  GoDec splits a
+ * dense m x n matrix X into a low-rank part L (rank <= r) and a sparse part
+ * S (at most k nonzeros) by minimising ||X - L - S||_F^2 (Sec. 2, Eq. 1-2)
+ * with the alternating updates of Algorithm 1 (Sec. 3.1.3):
+ *   L_t = BRP power-scheme approximation of X - S_{t-1}  (Eq. 5-9),
+ *   S_t = P_Omega(X - L_t), Omega = the nonzero subset of the k largest
+ *         entries of |X - L_t|                             (Eq. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major.  X has leading dimension ldx >= n (elements).
+ * - Pointers named *_dev are device pointers (HIP device memory on the
+ *   current device); *_host are host pointers.
+ * - The caller owns all memory.  The library never allocates device memory:
+ *   every device buffer it needs lives in the caller's workspace, whose size
+ *   godec_workspace_size() reports.  X is borrowed: it must stay alive and
+ *   unmodified until godec_destroy().
+ * - All device work is enqueued on the stream given in godec_opts.stream
+ *   (a hipStream_t; NULL means the default stream).  Calls that return host
+ *   values synchronise that stream; the others are asynchronous.
+ * - Errors are returned as godec_status codes; nothing is thrown across the
+ *   ABI.  godec_last_error() gives a message for the calling thread's last
+ *   failure.  On an error no device work has been enqueued by that call
+ *   unless the code is GODEC_E_DEVICE.
+ * - Tie-break of the sparse step (Eq. 4 and Algorithm 1 leave it open):
+ *   entries are ordered by |R| descending then by row-major linear index
+ *   i*n + j ascending; exact zeros are never selected, so
+ *   nnz(S) = min(k, number of nonzero residuals).
+ * - Rank check (Algorithm 1, "if rank(A2^T Y1) < r"): the numerical rank of
+ *   C = A2^T Y1 = Y2^T Y2 is the number of squared singular values of Y2
+ *   above rank_tol times the largest; default rank_tol = r * 2^-52 (the
+ *   MATLAB rank() default for an r x r matrix).  On a drop the current
+ *   iteration keeps the leading r' singular directions and later iterations
+ *   use the first r' columns of A1.
+ */
+#ifndef GODEC_H
+#define GODEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GODEC_OK = 0,
+  GODEC_E_INVAL = 1,       /* invalid argument (sizes, pointers, options) */
+  GODEC_E_NOMEM = 2,       /* workspace smaller than godec_workspace_size */
+  GODEC_E_DEVICE = 3,      /* a HIP runtime call failed */
+  GODEC_E_NUMERIC = 4,     /* NaN/Inf in X, or a non-finite r x r core */
+  GODEC_E_STATE = 5,       /* call not valid in the context's state */
+  GODEC_E_UNSUPPORTED = 6  /* valid request outside this build's limits */
+} godec_status;
+
+typedef enum { GODEC_F64 = 0, GODEC_F32 = 1 } godec_dtype;
+
+/* Arithmetic of the panel passes.  NATIVE computes in the dtype of X.
+ * BF16_REFINE (X must be GODEC_F32) keeps a bfloat16 copy of X - S and runs
+ * the panel products on the matrix cores with FP32 accumulation; the last
+ * refine_iters iterations redo the final subspace pass, the B chain and the
+ * residual in FP32.  The r x r core is FP64 in every mode. */
+typedef enum { GODEC_PREC_NATIVE = 0, GODEC_PREC_BF16_REFINE = 1 } godec_prec;
+
+#define GODEC_MAX_RANK 32   /* largest r this build supports */
+
+typedef struct {
+  uint32_t size;          /* sizeof(godec_opts); set by godec_opts_default */
+  int32_t prec;           /* godec_prec */
+  int32_t refine_iters;   /* BF16_REFINE only: trailing FP32 iterations (>= 0) */
+  int32_t reserved0;
+  double rank_tol;        /* <= 0: default r * 2^-52 (see above) */
+  const double* a1_host;  /* optional n x r row-major A1 replacing the seeded
+                             draw (test hook); copied during godec_init */
+  void* stream;           /* hipStream_t, NULL = default stream */
+} godec_opts;
+
+typedef struct {
+  int64_t iters;          /* iterations completed */
+  int64_t nnz;            /* nonzeros of the current S */
+  int32_t rank_eff;       /* r after the rank checks so far */
+  int32_t flags;          /* bit 0: NaN/Inf seen; bit 1: rank dropped;
+                             bit 2: selection took the slow exact path */
+  double rel_err_sq;      /* ||X - L - S||_F^2 / ||X||_F^2 (Sec. 5 measure) */
+  double threshold;       /* |R| of the last selected entry (the k-th key) */
+  double sum_r2;          /* ||X - L||_F^2 of the last iteration */
+  double norm_x2;         /* ||X||_F^2 */
+} godec_info;
+
+typedef struct godec_ctx godec_ctx;
+
+/* Fill *opts with defaults: NATIVE, refine_iters = 1, default rank_tol,
+ * seeded A1, default stream. */
+void godec_opts_default(godec_opts* opts);
+
+/* Bytes of device workspace godec_init needs for this problem.
+ * Errors: GODEC_E_INVAL for m, n < 1, r < 1, r > min(m, n), k < 0,
+ * k > m*n, q < 0, bad dtype/prec; GODEC_E_UNSUPPORTED for r > GODEC_MAX_RANK. */
+godec_status godec_workspace_size(int64_t m, int64_t n, int32_t r, int64_t k,
+                                  int32_t q, godec_dtype dtype,
+                                  const godec_opts* opts, size_t* bytes);
+
+/* Set up a decomposition of X_dev (m x n, leading dimension ldx, dtype).
+ * Draws A1 (n x r standard Gaussian) from `seed` with the counter-based
+ * generator of godec_draw_a1 unless opts->a1_host is given, computes
+ * ||X||_F^2, checks X for NaN/Inf (GODEC_E_NUMERIC), and sets S_0 = 0.
+ * workspace_dev must be 256-byte aligned and at least the size reported by
+ * godec_workspace_size for the same arguments (else GODEC_E_NOMEM).
+ * Synchronises the stream once (for the NaN check).  *out receives a host
+ * handle freed by godec_destroy. */
+godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype,
+                        int64_t m, int64_t n, int64_t ldx, int32_t r,
+                        int64_t k, int32_t q, uint64_t seed,
+                        void* workspace_dev, size_t workspace_bytes,
+                        const godec_opts* opts);
+
+/* Run `iters` iterations of Algorithm 1 (both updates each).  Asynchronous.
+ * In BF16_REFINE mode, `total_iters` (>= the iterations run so far + iters)
+ * tells which iterations are the trailing refine_iters ones; pass 0 to use
+ * the iterations of this call as the total. */
+godec_status godec_step(godec_ctx* ctx, int32_t iters, int32_t total_iters);
+
+/* Convenience: init, `iters` steps, copy the results out, destroy.
+ * UL_dev (m x r) and VL_dev (n x r) receive L = UL * VL^T (dtype of X);
+ * S_idx_dev (int64, capacity k) and S_val_dev (dtype of X, capacity k)
+ * receive S sorted by linear index; info (may be NULL) the final state. */
+godec_status godec_solve(const void* X_dev, godec_dtype dtype, int64_t m,
+                         int64_t n, int64_t ldx, int32_t r, int64_t k,
+                         int32_t q, uint64_t seed, int32_t iters,
+                         void* workspace_dev, size_t workspace_bytes,
+                         const godec_opts* opts, void* UL_dev, void* VL_dev,
+                         int64_t* S_idx_dev, void* S_val_dev,
+                         godec_info* info);
+
+/* L = UL * VL^T: UL_dev m x r, VL_dev n x r, row-major, dtype of X.
+ * Columns past rank_eff are zero.  Asynchronous. */
+godec_status godec_get_factors(godec_ctx* ctx, void* UL_dev, void* VL_dev);
+
+/* Dense L (m x n, leading dimension ldl >= n, dtype of X).  Asynchronous. */
+godec_status godec_get_L_dense(godec_ctx* ctx, void* L_dev, int64_t ldl);
+
+/* Current S as linear indices (int64, ascending) and values (dtype of X);
+ * both buffers need capacity k.  Synchronises; *nnz_host gets the count. */
+godec_status godec_get_S(godec_ctx* ctx, int64_t* idx_dev, void* val_dev,
+                         int64_t* nnz_host);
+
+/* Residual R = X - L of the last iteration, computed with exactly the
+ * arithmetic the selection used (m x n, leading dimension ldr, dtype of X;
+ * FP32 in BF16_REFINE mode).  Asynchronous. */
+godec_status godec_get_residual(godec_ctx* ctx, void* R_dev, int64_t ldr);
+
+/* Copy the n x r A1 in use (FP64, row-major) to the host.  Synchronous. */
+godec_status godec_get_A1(godec_ctx* ctx, double* a1_host);
+
+/* Synchronise the stream and report the state. */
+godec_status godec_get_info(godec_ctx* ctx, godec_info* info);
+
+/* Release the handle (no device memory is freed: the caller owns it). */
+godec_status godec_destroy(godec_ctx* ctx);
+
+/* Message for the calling thread's last error ("" if none). */
+const char* godec_last_error(void);
+
+/* Host-only: draw the n x r standard Gaussian A1 for `seed` (row-major):
+ * element (i, c) is Gaussian number i*r + c of the SplitMix64 stream
+ * (Steele, Lea, Flood 2014) mapped to 53-bit uniforms in (0,1) and paired
+ * by the Box-Muller transform.  Needs no GPU. */
+godec_status godec_draw_a1(uint64_t seed, int64_t n, int32_t r,
+                           double* a1_host);
+
+/* ---- Per-kernel timing (tracing) -------------------------------------
+ * While enabled, the library records a pair of HIP events on its stream
+ * around every launch of the streaming kernels, grouped by class.  Timing
+ * adds no host synchronisation; godec_profile_read synchronises the stream
+ * and reports, per class, the launch count, the summed event time and the
+ * algorithmic bytes one launch must move (the m x n operand it streams). */
+typedef struct {
+  char name[32];            /* kernel class */
+  int64_t launches;
+  double total_ms;
+  double bytes_per_launch;
+} godec_kernel_stat;
+
+/* enable != 0 starts (and clears) collection; 0 stops it. */
+godec_status godec_profile(godec_ctx* ctx, int32_t enable);
+/* Copy up to cap class records into out; *count receives the number of
+ * classes with at least one launch.  Synchronous. */
+godec_status godec_profile_read(godec_ctx* ctx, godec_kernel_stat* out,
+                                int32_t cap, int32_t* count);
+
+/* Build information string (static storage). */
+const char* godec_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GODEC_H */

@@ -1,0 +1,319 @@
+"""Thin Python binding of libgodec (include/godec.h).
+
+The functions below mirror the C entry points one to one and only marshal
+arguments: every step of the decomposition runs in the HIP library.  PyTorch
+provides device memory (the workspace and outputs are torch tensors) and the
+stream.  If the built library is missing the import of this module still
+works, but ``load()`` raises: there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgodec.so")
+
+GODEC_OK = 0
+STATUS = {0: "GODEC_OK", 1: "GODEC_E_INVAL", 2: "GODEC_E_NOMEM",
+          3: "GODEC_E_DEVICE", 4: "GODEC_E_NUMERIC", 5: "GODEC_E_STATE",
+          6: "GODEC_E_UNSUPPORTED"}
+GODEC_F64, GODEC_F32 = 0, 1
+GODEC_PREC_NATIVE, GODEC_PREC_BF16_REFINE = 0, 1
+GODEC_MAX_RANK = 32
+
+
+class godec_opts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("prec", ctypes.c_int32),
+                ("refine_iters", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("rank_tol", ctypes.c_double), ("a1_host", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+class godec_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rank_eff", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("rel_err_sq", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("sum_r2", ctypes.c_double), ("norm_x2", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class godec_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double),
+                ("bytes_per_launch", ctypes.c_double)]
+
+
+class GodecError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SIG = {
+    "godec_opts_default": (None, [ctypes.POINTER(godec_opts)]),
+    "godec_workspace_size": (_I32, [_I64, _I64, _I32, _I64, _I32, _I32,
+                                    ctypes.POINTER(godec_opts),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "godec_init": (_I32, [ctypes.POINTER(_P), _P, _I32, _I64, _I64, _I64, _I32,
+                          _I64, _I32, ctypes.c_uint64, _P, ctypes.c_size_t,
+                          ctypes.POINTER(godec_opts)]),
+    "godec_step": (_I32, [_P, _I32, _I32]),
+    "godec_solve": (_I32, [_P, _I32, _I64, _I64, _I64, _I32, _I64, _I32,
+                           ctypes.c_uint64, _I32, _P, ctypes.c_size_t,
+                           ctypes.POINTER(godec_opts), _P, _P, _P, _P,
+                           ctypes.POINTER(godec_info)]),
+    "godec_get_factors": (_I32, [_P, _P, _P]),
+    "godec_get_L_dense": (_I32, [_P, _P, _I64]),
+    "godec_get_S": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
+    "godec_get_residual": (_I32, [_P, _P, _I64]),
+    "godec_get_A1": (_I32, [_P, _P]),
+    "godec_get_info": (_I32, [_P, ctypes.POINTER(godec_info)]),
+    "godec_destroy": (_I32, [_P]),
+    "godec_last_error": (ctypes.c_char_p, []),
+    "godec_draw_a1": (_I32, [ctypes.c_uint64, _I64, _I32, _P]),
+    "godec_version": (ctypes.c_char_p, []),
+    "godec_profile": (_I32, [_P, _I32]),
+    "godec_profile_read": (_I32, [_P, ctypes.POINTER(godec_kernel_stat), _I32,
+                                  ctypes.POINTER(_I32)]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libgodec.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libgodec.so not found at {path}; build it with "
+            "`python -m paper_1309_0302_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIG.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != GODEC_OK:
+        msg = load().godec_last_error().decode(errors="replace")
+        raise GodecError(status, msg)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return GODEC_F64
+    if t.dtype == torch.float32:
+        return GODEC_F32
+    raise ValueError("X must be float32 or float64")
+
+
+def make_opts(prec=GODEC_PREC_NATIVE, refine_iters=1, rank_tol=0.0, a1=None,
+              stream=None):
+    o = godec_opts()
+    load().godec_opts_default(ctypes.byref(o))
+    o.prec = prec
+    o.refine_iters = refine_iters
+    o.rank_tol = rank_tol
+    keep = None
+    if a1 is not None:
+        keep = np.ascontiguousarray(a1, dtype=np.float64)
+        o.a1_host = keep.ctypes.data
+    o.stream = stream
+    return o, keep
+
+
+# ---- one-to-one wrappers of the C entry points ----------------------------
+
+def godec_workspace_size(m, n, r, k, q, dtype, opts=None):
+    out = ctypes.c_size_t(0)
+    _check(load().godec_workspace_size(m, n, r, k, q, dtype,
+                                       ctypes.byref(opts) if opts else None,
+                                       ctypes.byref(out)))
+    return out.value
+
+
+def godec_init(X_ptr, dtype, m, n, ldx, r, k, q, seed, ws_ptr, ws_bytes,
+               opts=None):
+    ctx = ctypes.c_void_p()
+    _check(load().godec_init(ctypes.byref(ctx), X_ptr, dtype, m, n, ldx, r, k,
+                             q, seed, ws_ptr, ws_bytes,
+                             ctypes.byref(opts) if opts else None))
+    return ctx
+
+
+def godec_step(ctx, iters, total_iters=0):
+    _check(load().godec_step(ctx, iters, total_iters))
+
+
+def godec_get_factors(ctx, ul_ptr, vl_ptr):
+    _check(load().godec_get_factors(ctx, ul_ptr, vl_ptr))
+
+
+def godec_get_L_dense(ctx, l_ptr, ldl):
+    _check(load().godec_get_L_dense(ctx, l_ptr, ldl))
+
+
+def godec_get_S(ctx, idx_ptr, val_ptr):
+    nnz = _I64(0)
+    _check(load().godec_get_S(ctx, idx_ptr, val_ptr, ctypes.byref(nnz)))
+    return nnz.value
+
+
+def godec_get_residual(ctx, r_ptr, ldr):
+    _check(load().godec_get_residual(ctx, r_ptr, ldr))
+
+
+def godec_get_A1(ctx, n, r):
+    out = np.empty((n, r), dtype=np.float64)
+    _check(load().godec_get_A1(ctx, out.ctypes.data))
+    return out
+
+
+def godec_get_info(ctx):
+    info = godec_info()
+    _check(load().godec_get_info(ctx, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def godec_destroy(ctx):
+    _check(load().godec_destroy(ctx))
+
+
+def godec_draw_a1(seed, n, r):
+    out = np.empty((n, r), dtype=np.float64)
+    _check(load().godec_draw_a1(seed, n, r, out.ctypes.data))
+    return out
+
+
+def godec_profile(ctx, enable):
+    _check(load().godec_profile(ctx, 1 if enable else 0))
+
+
+def godec_profile_read(ctx):
+    arr = (godec_kernel_stat * 16)()
+    cnt = _I32(0)
+    _check(load().godec_profile_read(ctx, arr, 16, ctypes.byref(cnt)))
+    out = []
+    for i in range(min(cnt.value, 16)):
+        st = arr[i]
+        out.append(dict(name=st.name.decode(), launches=st.launches,
+                        total_ms=st.total_ms,
+                        bytes_per_launch=st.bytes_per_launch))
+    return out
+
+
+def godec_solve(X, r, k, q, seed, iters, opts=None):
+    """init + step + results + destroy; returns (UL, VL, S_idx, S_val, info)."""
+    import torch
+    m, n = X.shape
+    dt = _dtype_code(X)
+    opts = opts if opts is not None else make_opts()[0]
+    ws_bytes = godec_workspace_size(m, n, r, k, q, dt, opts)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    UL = torch.zeros((m, r), dtype=X.dtype, device=X.device)
+    VL = torch.zeros((n, r), dtype=X.dtype, device=X.device)
+    sidx = torch.zeros(max(k, 1), dtype=torch.int64, device=X.device)
+    sval = torch.zeros(max(k, 1), dtype=X.dtype, device=X.device)
+    info = godec_info()
+    _check(load().godec_solve(X.data_ptr(), dt, m, n, X.stride(0), r, k, q,
+                              seed, iters, base, ws_bytes, ctypes.byref(opts),
+                              UL.data_ptr(), VL.data_ptr(), sidx.data_ptr(),
+                              sval.data_ptr(), ctypes.byref(info)))
+    nnz = info.nnz
+    return UL, VL, sidx[:nnz], sval[:nnz], info.as_dict()
+
+
+# ---- convenience object -----------------------------------------------------
+
+class GoDec:
+    """One decomposition of a CUDA/HIP tensor X (float32 or float64)."""
+
+    def __init__(self, X, r, k, q, seed=0, prec=GODEC_PREC_NATIVE,
+                 refine_iters=1, rank_tol=0.0, a1=None, stream=None):
+        import torch
+        if not X.is_cuda:
+            raise ValueError("X must be a device tensor")
+        if X.stride(1) != 1:
+            raise ValueError("X must be row-major with unit column stride")
+        self.X = X
+        self.m, self.n = X.shape
+        self.r, self.k, self.q = r, k, q
+        self.dtype = _dtype_code(X)
+        if stream is None:
+            stream = torch.cuda.current_stream(X.device).cuda_stream
+        self.opts, self._a1_keep = make_opts(prec, refine_iters, rank_tol, a1,
+                                             stream)
+        self.ws_bytes = godec_workspace_size(self.m, self.n, r, k, q,
+                                             self.dtype, self.opts)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
+                              device=X.device)
+        base = (self.ws.data_ptr() + 255) // 256 * 256
+        self.ctx = godec_init(X.data_ptr(), self.dtype, self.m, self.n,
+                              X.stride(0), r, k, q, seed, base, self.ws_bytes,
+                              self.opts)
+
+    def step(self, iters=1, total_iters=0):
+        godec_step(self.ctx, iters, total_iters)
+
+    def factors(self):
+        import torch
+        UL = torch.empty((self.m, self.r), dtype=self.X.dtype, device=self.X.device)
+        VL = torch.empty((self.n, self.r), dtype=self.X.dtype, device=self.X.device)
+        godec_get_factors(self.ctx, UL.data_ptr(), VL.data_ptr())
+        return UL, VL
+
+    def L_dense(self):
+        import torch
+        L = torch.empty((self.m, self.n), dtype=self.X.dtype, device=self.X.device)
+        godec_get_L_dense(self.ctx, L.data_ptr(), self.n)
+        return L
+
+    def residual(self):
+        import torch
+        R = torch.empty((self.m, self.n), dtype=self.X.dtype, device=self.X.device)
+        godec_get_residual(self.ctx, R.data_ptr(), self.n)
+        return R
+
+    def S(self):
+        import torch
+        kk = max(self.k, 1)
+        idx = torch.empty(kk, dtype=torch.int64, device=self.X.device)
+        val = torch.empty(kk, dtype=self.X.dtype, device=self.X.device)
+        nnz = godec_get_S(self.ctx, idx.data_ptr(), val.data_ptr())
+        return idx[:nnz], val[:nnz]
+
+    def A1(self):
+        return godec_get_A1(self.ctx, self.n, self.r)
+
+    def info(self):
+        return godec_get_info(self.ctx)
+
+    def profile(self, enable=True):
+        godec_profile(self.ctx, enable)
+
+    def profile_read(self):
+        return godec_profile_read(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            godec_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

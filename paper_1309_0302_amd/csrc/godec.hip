@@ -1,0 +1,625 @@
+// libgodec host side: the C ABI of include/godec.h.
+//
+// One iteration of Algorithm 1 (Sec. 3.1.3) is enqueued as:
+//   subspace chain  p = 2q+1 passes  Z <- orth(D^T (D Z)), Z_0 = A1,
+//                   keeping Y2 = (D^T D)^p A1 = Q2 R2 (R2 in FP64),
+//   B chain         q passes Y <- orth(D^T (D Y)), Y_0 = Q2, tracking T,
+//                   then B' = D Y_q, so B = L~ Q2 = B' T,
+//   core            rank check on R2, eigen-decomposition of B^T B,
+//                   U_L = B' T K with K = V S^{(1-p)/p} V^T, V_L = Q2,
+//   sparse step     fused residual / radix select / compaction of S_t,
+//   D update        D <- X on supp(S_{t-1}), D <- X - S_t on supp(S_t).
+// Everything runs on the caller's stream with no host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/godec.h"
+#include "godec_internal.h"
+
+using namespace godec;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+godec_status fail(godec_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess)                                                    \
+      return fail(GODEC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the workspace (base == nullptr only measures).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  void* take(size_t bytes) {
+    off = align_up(off, 256);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+struct godec_ctx {
+  // problem
+  int64_t m, n, ldx, ldd, k;
+  int r, rp, q, p;
+  uint64_t seed;
+  godec_dtype dtype;
+  int prec, refine_iters;
+  double rank_tol;
+  const void* X;
+  hipStream_t stream;
+  int num_cu;
+  bool f64;            // panel / residual type is double
+  size_t ta;           // sizeof panel type
+  // workspace
+  void* D = nullptr;       // native-precision working copy
+  void* D16 = nullptr;     // bf16 working copy (BF16_REFINE)
+  double* A1 = nullptr;    // n x r FP64
+  void *P0, *P1, *VL, *W, *Zpart, *Bp, *UL, *Kp, *Rinvp;
+  double* Gpart;
+  SmallState* st;
+  SelPlan* plan[2];
+  unsigned long long* hist;
+  unsigned long long* counters;
+  int64_t* cand_idx;
+  void* cand_val;
+  int64_t cap;
+  int64_t* tie_idx;
+  int64_t* s_idx[2];
+  void* s_val[2];
+  uint32_t *bitmap, *wpre, *bsum;
+  unsigned long long* boff;
+  double* norm_x2;
+  int* nonfinite;
+  // schedule
+  int64_t nchunks, rows_per_chunk;
+  int gram_blocks_n, gram_blocks_m;
+  // state
+  int64_t iters_done = 0;
+  int cur = 0;
+  std::vector<double> a1_host;
+  // tracing
+  bool prof = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+};
+
+namespace {
+
+struct Sizes {
+  int64_t ldd, nchunks, rpc, cap;
+  int gbn, gbm;
+};
+
+Sizes plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
+  Sizes s;
+  s.ldd = (n + 15) / 16 * 16;
+  const int64_t ctiles = (s.ldd + 1023) / 1024;
+  int64_t want = std::max<int64_t>(1, (4LL * num_cu + ctiles - 1) / ctiles);
+  want = std::min<int64_t>(want, std::max<int64_t>(1, (m + 63) / 64));
+  s.rpc = (m + want - 1) / want;
+  s.rpc = (s.rpc + 15) / 16 * 16;
+  s.nchunks = (m + s.rpc - 1) / s.rpc;
+  s.cap = std::min<int64_t>(m * n, k + std::max<int64_t>(k / 2, 65536));
+  s.gbn = (int)std::min<int64_t>(256, std::max<int64_t>(1, (s.ldd + 63) / 64));
+  s.gbm = (int)std::min<int64_t>(256, std::max<int64_t>(1, (m + 63) / 64));
+  return s;
+}
+
+// Carve every buffer; returns the total size.  ctx may be a measuring dummy.
+size_t carve(godec_ctx* c, void* base) {
+  Carver cv{(char*)base};
+  const int64_t m = c->m, ldd = c->ldd, rp = c->rp;
+  const size_t ta = c->ta;
+  const size_t dsz = c->f64 ? 8 : 4;
+  c->D = cv.take((size_t)m * ldd * dsz);
+  c->D16 = (c->prec == GODEC_PREC_BF16_REFINE) ? cv.take((size_t)m * ldd * 2) : nullptr;
+  c->A1 = (double*)cv.take((size_t)c->n * c->r * 8);
+  c->P0 = cv.take((size_t)ldd * rp * ta);
+  c->P1 = cv.take((size_t)ldd * rp * ta);
+  c->VL = cv.take((size_t)ldd * rp * ta);
+  c->W = cv.take((size_t)m * rp * ta);
+  c->Zpart = cv.take((size_t)c->nchunks * ldd * rp * ta);
+  c->Bp = cv.take((size_t)m * rp * ta);
+  c->UL = cv.take((size_t)m * rp * ta);
+  c->Kp = cv.take((size_t)rp * rp * ta);
+  c->Rinvp = cv.take((size_t)rp * rp * ta);
+  c->Gpart = (double*)cv.take((size_t)256 * rp * rp * 8);
+  c->st = (SmallState*)cv.take(sizeof(SmallState));
+  c->plan[0] = (SelPlan*)cv.take(sizeof(SelPlan));
+  c->plan[1] = (SelPlan*)cv.take(sizeof(SelPlan));
+  c->hist = (unsigned long long*)cv.take((size_t)kHistBins * 8);
+  c->counters = (unsigned long long*)cv.take(64);
+  c->cand_idx = (int64_t*)cv.take((size_t)c->cap * 8);
+  c->cand_val = cv.take((size_t)c->cap * ta);
+  c->tie_idx = (int64_t*)cv.take((size_t)c->cap * 8);
+  const int64_t kk = std::max<int64_t>(c->k, 1);
+  for (int b = 0; b < 2; ++b) {
+    c->s_idx[b] = (int64_t*)cv.take((size_t)kk * 8);
+    c->s_val[b] = cv.take((size_t)kk * ta);
+  }
+  const int64_t nwords = (m * c->n + 31) / 32;
+  const int64_t nb = (nwords + 1023) / 1024;
+  c->bitmap = (uint32_t*)cv.take((size_t)nwords * 4);
+  c->wpre = (uint32_t*)cv.take((size_t)nwords * 4);
+  c->bsum = (uint32_t*)cv.take((size_t)nb * 4);
+  c->boff = (unsigned long long*)cv.take((size_t)nb * 8);
+  c->norm_x2 = (double*)cv.take(8);
+  c->nonfinite = (int*)cv.take(8);
+  return align_up(cv.off, 256);
+}
+
+godec_status validate(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
+                      godec_dtype dtype, const godec_opts* o) {
+  if (m < 1 || n < 1) return fail(GODEC_E_INVAL, "m and n must be >= 1");
+  if (r < 1 || r > std::min<int64_t>(m, n)) return fail(GODEC_E_INVAL, "need 1 <= r <= min(m, n)");
+  if (r > GODEC_MAX_RANK) return fail(GODEC_E_UNSUPPORTED, "r exceeds GODEC_MAX_RANK");
+  if (k < 0 || k > m * n) return fail(GODEC_E_INVAL, "need 0 <= k <= m*n");
+  if (q < 0 || q > 16) return fail(GODEC_E_INVAL, "need 0 <= q <= 16");
+  if (dtype != GODEC_F64 && dtype != GODEC_F32) return fail(GODEC_E_INVAL, "bad dtype");
+  if (o) {
+    if (o->size != sizeof(godec_opts)) return fail(GODEC_E_INVAL, "opts.size mismatch");
+    if (o->prec != GODEC_PREC_NATIVE && o->prec != GODEC_PREC_BF16_REFINE)
+      return fail(GODEC_E_INVAL, "bad opts.prec");
+    if (o->prec == GODEC_PREC_BF16_REFINE && dtype != GODEC_F32)
+      return fail(GODEC_E_INVAL, "BF16_REFINE needs an FP32 X");
+    if (o->refine_iters < 0) return fail(GODEC_E_INVAL, "refine_iters < 0");
+  }
+  return GODEC_OK;
+}
+
+void fill_ctx_params(godec_ctx* c, int64_t m, int64_t n, int32_t r, int64_t k,
+                     int32_t q, godec_dtype dtype, const godec_opts* o, int num_cu) {
+  c->m = m; c->n = n; c->r = r; c->k = k; c->q = q; c->p = 2 * q + 1;
+  c->dtype = dtype;
+  c->prec = o ? o->prec : GODEC_PREC_NATIVE;
+  c->refine_iters = o ? o->refine_iters : 1;
+  c->rank_tol = (o && o->rank_tol > 0) ? o->rank_tol : (double)r * std::ldexp(1.0, -52);
+  c->rp = round_rp(r);
+  c->f64 = dtype == GODEC_F64;
+  c->ta = c->f64 ? 8 : 4;
+  c->num_cu = num_cu;
+  Sizes s = plan_sizes(m, n, k, num_cu);
+  c->ldd = s.ldd; c->nchunks = s.nchunks; c->rows_per_chunk = s.rpc; c->cap = s.cap;
+  c->gram_blocks_n = s.gbn; c->gram_blocks_m = s.gbm;
+}
+
+// Counter-based SplitMix64 (Steele, Lea, Flood 2014): output i of the stream
+// seeded with `seed` is mix(seed + (i + 1) * golden_gamma).
+uint64_t splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double uniform53(uint64_t seed, uint64_t i) {
+  return ((double)(splitmix64(seed, i) >> 11) + 0.5) * std::ldexp(1.0, -53);
+}
+
+// Box-Muller pair j -> Gaussians 2j (cos) and 2j+1 (sin).
+double gaussian(uint64_t seed, uint64_t j) {
+  const uint64_t pair = j / 2;
+  const double u1 = uniform53(seed, 2 * pair);
+  const double u2 = uniform53(seed, 2 * pair + 1);
+  const double rad = std::sqrt(-2.0 * std::log(u1));
+  const double ang = (2.0 * M_PI) * u2;
+  return rad * ((j % 2 == 0) ? std::cos(ang) : std::sin(ang));
+}
+
+Launch launch_of(const godec_ctx* c) { return Launch{c->stream, c->num_cu}; }
+
+// Kernel classes timed by godec_profile.
+enum ProfClass { PC_APPLY = 0, PC_APPLY_T, PC_APPLY_BF16, PC_APPLY_T_BF16, PC_SEL_PASS,
+                 PC_COUNT };
+const char* kProfNames[PC_COUNT] = {"panel_apply(D*Z)", "panel_apply_t(D^T*W)",
+                                    "panel_apply_bf16(D*Z)", "panel_apply_t_bf16(D^T*W)",
+                                    "select_pass(hist)"};
+const double kProfElemBytes[PC_COUNT] = {0, 0, 2, 2, 0};   // 0: element size of X
+
+hipEvent_t prof_event(godec_ctx* c) {
+  if (c->pool_used == c->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->pool.push_back(e);
+  }
+  return c->pool[c->pool_used++];
+}
+
+// Scoped pair of events around one launch (no-op unless profiling).
+struct ProfScope {
+  godec_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(godec_ctx* ctx, int k) : c(ctx), cls(k) {
+    if (!c->prof) return;
+    a = prof_event(c);
+    b = prof_event(c);
+    if (a && b) (void)hipEventRecord(a, c->stream);
+  }
+  ~ProfScope() {
+    if (!c->prof || !a || !b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->recs.push_back({cls, a, b});
+  }
+};
+
+// One Gram pass: out = D^T (D in), through W and the chunk partials.
+void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* out) {
+  const Launch L = launch_of(c);
+  {
+    ProfScope ps(c, td == BF16 ? PC_APPLY_BF16 : PC_APPLY);
+    launch_apply(L, td, c->rp, Dsrc, c->ldd, c->m, in, c->W);
+  }
+  {
+    ProfScope ps(c, td == BF16 ? PC_APPLY_T_BF16 : PC_APPLY_T);
+    launch_apply_t(L, td, c->rp, Dsrc, c->ldd, c->m, c->W, c->Zpart, c->rows_per_chunk,
+                   c->nchunks);
+  }
+  launch_reduce_chunks(L, c->f64, c->rp, c->Zpart, c->nchunks, c->ldd, out);
+}
+
+// Orthonormalise `in` (ldd x RP) into `out` by one Cholesky QR step,
+// accumulating its R factor into acc (reset when reset != 0).
+void chol_qr(godec_ctx* c, const void* in, void* out, double* acc, int reset) {
+  const Launch L = launch_of(c);
+  launch_gram(L, c->f64, c->rp, in, c->ldd, c->Gpart, c->gram_blocks_n);
+  launch_chol(L, c->f64, c->rp, c->Gpart, c->gram_blocks_n, c->st, acc, c->Rinvp, reset,
+              acc == c->st->R2 ? 1 : 0);
+  launch_apply_small(L, c->f64, c->rp, in, c->ldd, c->Rinvp, out);
+}
+
+godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
+  const Launch L = launch_of(c);
+  const DType native = c->f64 ? F64 : F32;
+  const bool mixed = c->prec == GODEC_PREC_BF16_REFINE;
+  const bool refine = mixed && total > 0 && t >= total - c->refine_iters;
+  // ---- subspace chain: Q2 = orth((D^T D)^p A1), R2 tracked ----
+  launch_copy_panel(L, c->f64, c->rp, c->A1, c->n, c->ldd, c->r, c->st, c->P0);
+  const void* in = c->P0;
+  for (int j = 0; j < c->p; ++j) {
+    const bool low = mixed && !(refine && j == c->p - 1);
+    gram_pass(c, low ? BF16 : native, low ? c->D16 : c->D, in, c->P1);
+    chol_qr(c, c->P1, c->P0, c->st->R2, j == 0);
+    in = c->P0;
+  }
+  // second Cholesky QR round on Q2 (restores orthonormality to working
+  // precision); its R factor joins R2.
+  chol_qr(c, c->P0, c->VL, c->st->R2, 0);
+  // ---- B chain: (D^T D)^q Q2 = Y_q T, then B' = D Y_q ----
+  const bool low_b = mixed && !refine;
+  const DType tdb = low_b ? BF16 : native;
+  const void* Db = low_b ? c->D16 : c->D;
+  in = c->VL;
+  for (int j = 0; j < c->q; ++j) {
+    gram_pass(c, tdb, Db, in, c->P1);
+    chol_qr(c, c->P1, c->P0, c->st->T, j == 0);
+    in = c->P0;
+  }
+  launch_apply(L, tdb, c->rp, Db, c->ldd, c->m, in, c->Bp);
+  // ---- core ----
+  launch_gram(L, c->f64, c->rp, c->Bp, c->m, c->Gpart, c->gram_blocks_m);
+  launch_core(L, c->f64, c->rp, c->Gpart, c->gram_blocks_m, c->st, c->p, c->rank_tol,
+              c->q == 0 ? 1 : 0, c->Kp);
+  launch_apply_small(L, c->f64, c->rp, c->Bp, c->m, c->Kp, c->UL);
+  // ---- sparse step ----
+  const int prev = c->cur;
+  const int nxt = c->cur ^ 1;
+  SelectArgs a;
+  a.X = c->X; a.ldx = c->ldx; a.UL = c->UL; a.VL = c->VL; a.m = c->m; a.n = c->n; a.k = c->k;
+  a.plan = c->plan[nxt]; a.hist = c->hist; a.counters = c->counters;
+  a.cand_idx = c->cand_idx; a.cand_val = c->cand_val; a.cap = c->cap;
+  a.s_idx = c->s_idx[nxt]; a.s_val = c->s_val[nxt]; a.tie_idx = c->tie_idx;
+  if (c->prof) {
+    a.ev_a = prof_event(c);
+    a.ev_b = prof_event(c);
+    if (a.ev_a && a.ev_b) c->recs.push_back({PC_SEL_PASS, a.ev_a, a.ev_b});
+  }
+  launch_select(L, c->f64, c->rp, a);
+  // ---- D update ----
+  const int64_t kk = std::max<int64_t>(c->k, 1);
+  if (c->iters_done > 0) {
+    launch_update_d(L, native, c->f64, c->D, c->ldd, c->X, c->ldx, c->n, c->s_idx[prev],
+                    nullptr, c->plan[prev], kk);
+    if (mixed)
+      launch_update_d(L, BF16, false, c->D16, c->ldd, c->X, c->ldx, c->n, c->s_idx[prev],
+                      nullptr, c->plan[prev], kk);
+  }
+  launch_update_d(L, native, c->f64, c->D, c->ldd, c->X, c->ldx, c->n, c->s_idx[nxt],
+                  c->s_val[nxt], c->plan[nxt], kk);
+  if (mixed)
+    launch_update_d(L, BF16, false, c->D16, c->ldd, c->X, c->ldx, c->n, c->s_idx[nxt],
+                    c->s_val[nxt], c->plan[nxt], kk);
+  c->cur = nxt;
+  c->iters_done += 1;
+  HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void godec_opts_default(godec_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->size = sizeof(godec_opts);
+  o->prec = GODEC_PREC_NATIVE;
+  o->refine_iters = 1;
+  o->rank_tol = 0.0;
+  o->a1_host = nullptr;
+  o->stream = nullptr;
+}
+
+godec_status godec_draw_a1(uint64_t seed, int64_t n, int32_t r, double* a1_host) {
+  if (n < 1 || r < 1 || !a1_host) return fail(GODEC_E_INVAL, "bad arguments");
+  const uint64_t total = (uint64_t)n * (uint64_t)r;
+  for (uint64_t j = 0; j < total; ++j) a1_host[j] = gaussian(seed, j);
+  return GODEC_OK;
+}
+
+static int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+    return 256;
+  return cu;
+}
+
+godec_status godec_workspace_size(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
+                                  godec_dtype dtype, const godec_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(GODEC_E_INVAL, "bytes is NULL");
+  godec_status s = validate(m, n, r, k, q, dtype, opts);
+  if (s != GODEC_OK) return s;
+  godec_ctx tmp;
+  // size with the largest chunk count any device would use (256 CUs)
+  fill_ctx_params(&tmp, m, n, r, k, q, dtype, opts, 256);
+  *bytes = carve(&tmp, nullptr);
+  return GODEC_OK;
+}
+
+godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, int64_t m,
+                        int64_t n, int64_t ldx, int32_t r, int64_t k, int32_t q, uint64_t seed,
+                        void* ws, size_t ws_bytes, const godec_opts* opts) {
+  if (!out) return fail(GODEC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  godec_status s = validate(m, n, r, k, q, dtype, opts);
+  if (s != GODEC_OK) return s;
+  if (!X_dev || !ws) return fail(GODEC_E_INVAL, "X or workspace is NULL");
+  if (ldx < n) return fail(GODEC_E_INVAL, "ldx < n");
+  if (((uintptr_t)ws) % 256 != 0) return fail(GODEC_E_INVAL, "workspace not 256-byte aligned");
+  if (((uintptr_t)X_dev) % (dtype == GODEC_F64 ? 8 : 4) != 0)
+    return fail(GODEC_E_INVAL, "X not aligned to its element size");
+  godec_ctx* c = new godec_ctx();
+  fill_ctx_params(c, m, n, r, k, q, dtype, opts, 256);
+  c->ldx = ldx;
+  c->seed = seed;
+  c->X = X_dev;
+  c->stream = opts ? (hipStream_t)opts->stream : nullptr;
+  const size_t need = carve(c, nullptr);
+  if (ws_bytes < need) {
+    delete c;
+    return fail(GODEC_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  c->num_cu = device_cu_count();
+  carve(c, ws);
+  c->a1_host.resize((size_t)n * r);
+  if (opts && opts->a1_host)
+    std::memcpy(c->a1_host.data(), opts->a1_host, sizeof(double) * n * r);
+  else
+    godec_draw_a1(seed, n, r, c->a1_host.data());
+  const Launch L = launch_of(c);
+  auto cleanup = [&](godec_status st, const std::string& msg) {
+    delete c;
+    return fail(st, msg);
+  };
+  hipError_t e = hipMemcpyAsync(c->A1, c->a1_host.data(), sizeof(double) * n * r,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
+  launch_init_d(L, c->f64 ? F64 : F32, c->f64, c->D, c->ldd, X_dev, ldx, m, n);
+  if (c->D16) launch_init_d(L, BF16, false, c->D16, c->ldd, X_dev, ldx, m, n);
+  launch_small_init(L, c->st, r);
+  // zero the small scalars, plans and the (unused) panel padding
+  e = hipMemsetAsync(c->norm_x2, 0, 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->nonfinite, 0, 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->plan[0], 0, sizeof(SelPlan), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->plan[1], 0, sizeof(SelPlan), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->VL, 0, (size_t)c->ldd * c->rp * c->ta, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->UL, 0, (size_t)c->m * c->rp * c->ta, c->stream);
+  if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
+  launch_norm_check(L, c->f64, X_dev, ldx, m, n, c->norm_x2, c->nonfinite);
+  e = hipGetLastError();
+  if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
+  int bad = 0;
+  e = hipMemcpyAsync(&bad, c->nonfinite, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
+  if (bad) return cleanup(GODEC_E_NUMERIC, "X contains NaN or Inf");
+  *out = c;
+  return GODEC_OK;
+}
+
+godec_status godec_step(godec_ctx* c, int32_t iters, int32_t total_iters) {
+  if (!c) return fail(GODEC_E_INVAL, "ctx is NULL");
+  if (iters < 0) return fail(GODEC_E_INVAL, "iters < 0");
+  int64_t total = total_iters > 0 ? total_iters : c->iters_done + iters;
+  for (int32_t i = 0; i < iters; ++i) {
+    godec_status s = run_iteration(c, c->iters_done, total);
+    if (s != GODEC_OK) return s;
+  }
+  return GODEC_OK;
+}
+
+godec_status godec_get_factors(godec_ctx* c, void* UL_dev, void* VL_dev) {
+  if (!c || !UL_dev || !VL_dev) return fail(GODEC_E_INVAL, "NULL argument");
+  const Launch L = launch_of(c);
+  launch_cast_panel(L, c->f64, c->rp, c->UL, c->m, c->r, UL_dev);
+  launch_cast_panel(L, c->f64, c->rp, c->VL, c->n, c->r, VL_dev);
+  HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
+godec_status godec_get_L_dense(godec_ctx* c, void* L_dev, int64_t ldl) {
+  if (!c || !L_dev || ldl < c->n) return fail(GODEC_E_INVAL, "bad argument");
+  launch_residual(launch_of(c), c->f64, c->rp, c->X, c->ldx, c->UL, c->VL, c->m, c->n, L_dev,
+                  ldl, 1);
+  HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
+godec_status godec_get_residual(godec_ctx* c, void* R_dev, int64_t ldr) {
+  if (!c || !R_dev || ldr < c->n) return fail(GODEC_E_INVAL, "bad argument");
+  launch_residual(launch_of(c), c->f64, c->rp, c->X, c->ldx, c->UL, c->VL, c->m, c->n, R_dev,
+                  ldr, 0);
+  HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
+godec_status godec_get_S(godec_ctx* c, int64_t* idx_dev, void* val_dev, int64_t* nnz_host) {
+  if (!c || !nnz_host) return fail(GODEC_E_INVAL, "NULL argument");
+  if (c->iters_done == 0) {
+    *nnz_host = 0;
+    return GODEC_OK;
+  }
+  if (!idx_dev || !val_dev) return fail(GODEC_E_INVAL, "NULL output buffer");
+  const Launch L = launch_of(c);
+  launch_sort_s(L, c->f64, c->s_idx[c->cur], c->s_val[c->cur], c->plan[c->cur], c->m * c->n,
+                std::max<int64_t>(c->k, 1), c->bitmap, c->wpre, c->bsum, c->boff, idx_dev,
+                val_dev);
+  SelPlan hp;
+  HIP_TRY(hipMemcpyAsync(&hp, c->plan[c->cur], sizeof(SelPlan), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *nnz_host = hp.nnz;
+  return GODEC_OK;
+}
+
+godec_status godec_get_A1(godec_ctx* c, double* a1_host) {
+  if (!c || !a1_host) return fail(GODEC_E_INVAL, "NULL argument");
+  std::memcpy(a1_host, c->a1_host.data(), sizeof(double) * c->n * c->r);
+  return GODEC_OK;
+}
+
+godec_status godec_get_info(godec_ctx* c, godec_info* info) {
+  if (!c || !info) return fail(GODEC_E_INVAL, "NULL argument");
+  SelPlan hp;
+  std::memset(&hp, 0, sizeof(hp));
+  double nx2 = 0.0;
+  int r_eff = c->r, flags = 0;
+  HIP_TRY(hipMemcpyAsync(&nx2, c->norm_x2, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&r_eff, &c->st->r_eff, 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&flags, &c->st->flags, 4, hipMemcpyDeviceToHost, c->stream));
+  if (c->iters_done > 0)
+    HIP_TRY(hipMemcpyAsync(&hp, c->plan[c->cur], sizeof(SelPlan), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  info->iters = c->iters_done;
+  info->nnz = hp.nnz;
+  info->rank_eff = r_eff;
+  info->flags = (flags & 1) | (flags & 2) | (hp.slow ? 4 : 0) | (hp.overflow ? 8 : 0);
+  info->sum_r2 = hp.sum_r2;
+  info->norm_x2 = nx2;
+  info->rel_err_sq = nx2 > 0 ? (hp.sum_r2 - hp.sum_sel2) / nx2 : 0.0;
+  if (info->rel_err_sq < 0) info->rel_err_sq = 0.0;
+  info->threshold = hp.threshold;
+  if (flags & 1) return fail(GODEC_E_NUMERIC, "non-finite value in the r x r core");
+  return GODEC_OK;
+}
+
+godec_status godec_destroy(godec_ctx* c) {
+  if (c) {
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+  }
+  return GODEC_OK;
+}
+
+godec_status godec_profile(godec_ctx* c, int32_t enable) {
+  if (!c) return fail(GODEC_E_INVAL, "ctx is NULL");
+  if (enable) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->recs.clear();
+    c->pool_used = 0;
+  }
+  c->prof = enable != 0;
+  return GODEC_OK;
+}
+
+godec_status godec_profile_read(godec_ctx* c, godec_kernel_stat* out, int32_t cap,
+                                int32_t* count) {
+  if (!c || !count) return fail(GODEC_E_INVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double ms[PC_COUNT] = {0};
+  int64_t n[PC_COUNT] = {0};
+  for (const auto& r : c->recs) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    n[r.cls] += 1;
+  }
+  const double ds = c->f64 ? 8.0 : 4.0;
+  const double mn = (double)c->m * (double)c->n;
+  int32_t k = 0;
+  for (int cls = 0; cls < PC_COUNT; ++cls) {
+    if (n[cls] == 0) continue;
+    if (out && k < cap) {
+      godec_kernel_stat& st = out[k];
+      std::memset(&st, 0, sizeof(st));
+      std::snprintf(st.name, sizeof(st.name), "%s", kProfNames[cls]);
+      st.launches = n[cls];
+      st.total_ms = ms[cls];
+      // one streaming read of the m x n operand per launch
+      st.bytes_per_launch = mn * (kProfElemBytes[cls] > 0 ? kProfElemBytes[cls] : ds);
+    }
+    ++k;
+  }
+  *count = k;
+  return GODEC_OK;
+}
+
+const char* godec_last_error(void) { return g_last_error.c_str(); }
+
+godec_status godec_solve(const void* X_dev, godec_dtype dtype, int64_t m, int64_t n, int64_t ldx,
+                         int32_t r, int64_t k, int32_t q, uint64_t seed, int32_t iters, void* ws,
+                         size_t ws_bytes, const godec_opts* opts, void* UL_dev, void* VL_dev,
+                         int64_t* S_idx_dev, void* S_val_dev, godec_info* info) {
+  godec_ctx* c = nullptr;
+  godec_status s = godec_init(&c, X_dev, dtype, m, n, ldx, r, k, q, seed, ws, ws_bytes, opts);
+  if (s != GODEC_OK) return s;
+  s = godec_step(c, iters, iters);
+  if (s == GODEC_OK && UL_dev && VL_dev) s = godec_get_factors(c, UL_dev, VL_dev);
+  int64_t nnz = 0;
+  if (s == GODEC_OK && S_idx_dev && S_val_dev) s = godec_get_S(c, S_idx_dev, S_val_dev, &nnz);
+  if (s == GODEC_OK && info) s = godec_get_info(c, info);
+  if (s == GODEC_OK) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = fail(GODEC_E_DEVICE, hipGetErrorString(e));
+  }
+  godec_destroy(c);
+  return s;
+}
+
+const char* godec_version(void) {
+  return "libgodec 0.1 (gfx950; GoDec by bilateral random projection)";
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations of libgodec (not part of the public ABI).
+//
+// Device data layout (all inside the caller's workspace):
+//   D      m x ldd working copy of X - S_{t-1} in the panel storage type
+//          (f64 / f32; plus a bf16 copy in the mixed-precision mode).  Rows
+//          are padded to ldd = round_up(n, 16) with zeros so panel kernels
+//          read whole 16-byte vectors without column tails.
+//   panels n_pad x RP and m x RP row-major (RP = r rounded up to a
+//          supported width), compute type TA (double, or float for the f32
+//          and bf16 modes); padding rows/columns are zero.
+//   small  r x r FP64 state of the power chain and the core.
+//   select histogram, plan, candidate list, two sparse lists (S_{t-1},
+//          S_t) as (int64 linear index, value) pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace godec {
+
+constexpr int kMaxRP = 32;
+constexpr int kHistBits0 = 12;        // first radix digit of the key
+constexpr int kHistBits = 11;         // later digits
+constexpr int kHistBins = 1 << kHistBits0;
+constexpr int kBlock = 256;
+
+// Supported padded panel widths.
+inline int round_rp(int r) {
+  const int w[] = {1, 2, 4, 8, 12, 16, 20, 24, 32};
+  for (int x : w)
+    if (r <= x) return x;
+  return -1;
+}
+
+enum DType { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Selection plan, kept in device memory and advanced by the plan kernel.
+enum SelMode : int {
+  SEL_HIST = 0,      // next full-data pass histograms the next digit
+  SEL_COLLECT = 1,   // next full-data pass writes candidates >= bucket low
+  SEL_REFINE = 2,    // candidates hold the bucket; refine digits over them
+  SEL_FINAL = 3,     // threshold resolved, candidates hold everything needed
+  SEL_TIES = 4,      // threshold resolved but ties overflow the candidates
+  SEL_DONE = 5,      // S written by the index-ordered tie scan
+};
+
+struct SelPlan {
+  unsigned long long prefix;   // resolved high bits of the threshold key
+  long long k_rem;             // entries still to take inside the bucket
+  long long count_above;       // entries above the bucket (all taken)
+  long long bucket_count;      // entries inside the bucket
+  long long ncand;             // candidates written
+  long long cap;               // candidate capacity
+  long long nnz;               // entries of S written by compaction
+  int pbits;                   // number of resolved key bits
+  int kbits;                   // key width (31 for f32, 63 for f64)
+  int mode;                    // SelMode
+  int slow;                    // a slow exact path was used
+  int overflow;                // candidate buffer overflowed
+  int pad0;
+  double sum_r2;               // ||X - L||_F^2 (all entries)
+  double sum_sel2;             // sum of R^2 over the selected entries
+  double threshold;            // |R| of the threshold key
+};
+
+// Small FP64 state of one iteration.
+struct SmallState {
+  double R2[kMaxRP * kMaxRP];      // R factor of Y2 = (D^T D)^p A1
+  double T[kMaxRP * kMaxRP];       // B chain: (D^T D)^q Q2 = Y_q T
+  double Rinv[kMaxRP * kMaxRP];    // last Cholesky inverse (FP64)
+  double V[kMaxRP * kMaxRP];       // eigenvectors of B^T B (warm start)
+  double K[kMaxRP * kMaxRP];       // core K' = T K (FP64 copy)
+  double sigma[kMaxRP];            // singular values of B (descending)
+  double sv_c[kMaxRP];             // singular values of Y2 (rank check)
+  int r_eff;                       // current rank (columns of A1 in use)
+  int r_keep;                      // directions kept by this iteration
+  int flags;                       // bit0 non-finite, bit1 rank drop
+  int v_valid;                     // V holds a usable warm start
+  int active[kMaxRP];              // column is active in the chain
+};
+
+struct Launch {
+  hipStream_t stream;
+  int num_cu;
+};
+
+// ---- panel kernels (k_panel.hip) ----
+// W = D Z  (m x RP), D rows of length ldd (padded), Z ldd x RP.
+void launch_apply(const Launch& L, DType td, int rp, const void* D,
+                  int64_t ldd, int64_t m, const void* Z, void* W);
+// Zpart[c] = D[chunk c]^T W[chunk c]  (nchunks x ldd x RP).
+void launch_apply_t(const Launch& L, DType td, int rp, const void* D,
+                    int64_t ldd, int64_t m, const void* W, void* Zpart,
+                    int64_t rows_per_chunk, int64_t nchunks);
+// Zo = sum_c Zpart[c]  (rows x RP).
+void launch_reduce_chunks(const Launch& L, bool f64, int rp,
+                          const void* Zpart, int64_t nchunks, int64_t rows,
+                          void* Zo);
+// Gpart[b] = P^T P over the rows of block b (FP64), nblk blocks.
+void launch_gram(const Launch& L, bool f64, int rp, const void* P,
+                 int64_t rows, double* Gpart, int nblk);
+// Out = P K  (rows x RP), K is RP x RP in the panel type.
+void launch_apply_small(const Launch& L, bool f64, int rp, const void* P,
+                        int64_t rows, const void* K, void* Out);
+// dst (rows_pad x RP) <- src (rows x r, FP64) with columns >= st->r_eff zeroed.
+void launch_copy_panel(const Launch& L, bool f64, int rp, const double* src,
+                       int64_t rows, int64_t rows_pad, int r,
+                       const SmallState* st, void* dst);
+
+// ---- r x r FP64 kernels (k_small.hip) ----
+void launch_chol(const Launch& L, bool f64, int rp, const double* Gpart,
+                 int nparts, SmallState* st, double* acc, void* rinv_panel,
+                 int reset_acc, int normalise);
+void launch_core(const Launch& L, bool f64, int rp, const double* Gpart,
+                 int nparts, SmallState* st, int p, double rank_tol,
+                 int t_identity, void* k_panel);
+void launch_small_init(const Launch& L, SmallState* st, int r);
+
+// ---- selection and sparse state (k_select.hip) ----
+struct SelectArgs {
+  const void* X;        // m x ldx (f64 or f32)
+  int64_t ldx;
+  const void* UL;       // m x RP
+  const void* VL;       // ldd x RP
+  int64_t m, n;
+  int64_t k;
+  SelPlan* plan;
+  unsigned long long* hist;      // kHistBins counters
+  unsigned long long* counters;  // [0] above threshold, [1] ties
+  int64_t* cand_idx;
+  void* cand_val;
+  int64_t cap;
+  int64_t* s_idx;       // output S list (unordered)
+  void* s_val;
+  int64_t* tie_idx;     // scratch for ties (cap entries)
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;  // optional: bracket pass 0
+};
+void launch_select(const Launch& L, bool f64, int rp, const SelectArgs& a);
+// R = X - UL VL^T (dense_l = 0) or L = UL VL^T (dense_l = 1).
+void launch_residual(const Launch& L, bool f64, int rp, const void* X,
+                     int64_t ldx, const void* UL, const void* VL, int64_t m,
+                     int64_t n, void* R, int64_t ldr, int dense_l);
+void launch_init_d(const Launch& L, DType td, bool xf64, void* D,
+                   int64_t ldd, const void* X, int64_t ldx, int64_t m,
+                   int64_t n);
+// D[idx] <- X[idx] - val (val != nullptr) or X[idx] for the plan's nnz entries.
+void launch_update_d(const Launch& L, DType td, bool xf64, void* D,
+                     int64_t ldd, const void* X, int64_t ldx, int64_t n,
+                     const int64_t* idx, const void* val, const SelPlan* plan,
+                     int64_t kmax);
+void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx,
+                       int64_t m, int64_t n, double* out2, int* nonfinite);
+void launch_sort_s(const Launch& L, bool f64, const int64_t* idx,
+                   const void* val, const SelPlan* plan, int64_t mn,
+                   int64_t kmax, uint32_t* bitmap, uint32_t* wpre,
+                   uint32_t* bsum, unsigned long long* boff, int64_t* out_idx,
+                   void* out_val);
+void launch_cast_panel(const Launch& L, bool f64, int rp, const void* src,
+                       int64_t rows, int r, void* dst);
+
+}  // namespace godec

@@ -1,0 +1,67 @@
+// Device helpers shared by the libgodec kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace godec {
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) {
+  return __uint_as_float(h << 16);
+}
+
+// Round-to-nearest-even FP32 -> bfloat16 (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// 4 consecutive elements (16-byte aligned for f32/bf16 pairs, 32-byte for f64).
+__device__ __forceinline__ void load4(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&o)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void load4(const uint16_t* p, float (&o)[4]) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  o[0] = bf16_to_f32(v.x & 0xffffu); o[1] = bf16_to_f32(v.x >> 16);
+  o[2] = bf16_to_f32(v.y & 0xffffu); o[3] = bf16_to_f32(v.y >> 16);
+}
+__device__ __forceinline__ void load2(const float* p, float (&o)[4]) {
+  const float2 v = *reinterpret_cast<const float2*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = 0.f; o[3] = 0.f;
+}
+__device__ __forceinline__ void load2(const double* p, double (&o)[4]) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = 0.0; o[3] = 0.0;
+}
+__device__ __forceinline__ void load2(const uint16_t* p, float (&o)[4]) {
+  const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+  o[0] = bf16_to_f32(v & 0xffffu); o[1] = bf16_to_f32(v >> 16); o[2] = 0.f; o[3] = 0.f;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Monotone integer key of |x|: the IEEE bits with the sign cleared.
+__device__ __forceinline__ unsigned long long abs_key(float x) {
+  return (unsigned long long)(__float_as_uint(x) & 0x7fffffffu);
+}
+__device__ __forceinline__ unsigned long long abs_key(double x) {
+  return (unsigned long long)__double_as_longlong(x) & 0x7fffffffffffffffull;
+}
+
+}  // namespace godec

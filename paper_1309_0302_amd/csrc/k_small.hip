@@ -1,0 +1,495 @@
+// r x r FP64 work of the low-rank step (one workgroup each).
+//
+// Paper background (Sec. 3.1.2, Eq. 6-9; Algorithm 1): the power-scheme BRP
+// needs the QR factors of Y2 = L~^T Y1 and Y1 = L~ Y2, the inverse of the
+// r x r matrix A2^T Y1, a rank check on it, and the (2q+1)-th root of the
+// r x r core.  With A2 = Y1 these are, exactly:
+//   Y2 = (D^T D)^p A1 = Q2 R2        (R2 tracked through the passes below),
+//   A2^T Y1 = R2^T R2                (rank check on the singular values of R2),
+//   core = R factor of B = L~ Q2     (so L = U_B S_B^{1/p} V_B^T Q2^T).
+// The power chain orthonormalises every pass (Cholesky QR with an FP64
+// Gram) and keeps the product of the R factors in FP64, rescaled by exact
+// powers of two.  B is handled through K = V diag(s^{(1-p)/p}) V^T from
+// the eigen-decomposition of B^T B, so that U_L = B K and V_L = Q2.
+#include "godec_internal.h"
+#include "k_common.h"
+
+namespace godec {
+
+// Rescale M (n x n in LDS, row stride ld) by the power of two nearest its
+// largest magnitude; exact in binary floating point.
+__device__ void pow2_normalise(double* M, int n, int ld, double* red) {
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(M[i * ld + j]));
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    red[0] = ldexp(1.0, -e);
+  }
+  __syncthreads();
+  const double s = red[0];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    M[i * ld + j] *= s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky QR step: G = sum Gpart = Z^T Z;  G = R^T R (upper R).
+// A column is inactive when it lies at or past r_eff, is zero, or is
+// numerically dependent on the columns before it: its Cholesky pivot (the
+// squared norm of its component orthogonal to them) is at most
+// tau * G_jj with tau = RP * max(u^2, 2^-53) -- the resolution of a Gram of
+// panel-type data accumulated in FP64.  An inactive column gets a zero row
+// in R (so the tracked factor records a zero singular direction) and a zero
+// column in R^{-1} (so the orthonormalised panel has a zero column, which
+// stays zero in every later product).
+// ---------------------------------------------------------------------------
+template <typename TA, int RP>
+__global__ __launch_bounds__(256) void k_chol(const double* __restrict__ Gpart,
+                                              int nparts, SmallState* st,
+                                              double* acc, TA* rinv_panel,
+                                              int reset_acc, int normalise) {
+  constexpr int LD = RP + 1;
+  __shared__ double G[RP * LD];
+  __shared__ double R[RP * LD];
+  __shared__ double Ri[RP * LD];
+  __shared__ double A[RP * LD];
+  __shared__ double G0[RP];
+  __shared__ double red[4];
+  __shared__ int act[RP];
+  const int tid = threadIdx.x;
+  const int reff = st->r_eff;
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += Gpart[(int64_t)b * RP * RP + e];
+    const int i = e / RP, j = e % RP;
+    G[i * LD + j] = s;
+    R[i * LD + j] = 0.0;
+  }
+  __syncthreads();
+  if (tid < RP) {
+    G0[tid] = G[tid * LD + tid];
+    act[tid] = (tid < reff && G[tid * LD + tid] > 0.0) ? 1 : 0;
+  }
+  __syncthreads();
+  const double u = sizeof(TA) == 8 ? 0x1p-53 : 0x1p-24;
+  const double tau = (double)RP * fmax(u * u, 0x1p-53);
+  for (int j = 0; j < RP; ++j) {
+    if (tid == 0) {
+      if (act[j]) {
+        const double piv = G[j * LD + j];
+        if (piv > tau * G0[j]) {
+          R[j * LD + j] = sqrt(piv);
+        } else {
+          act[j] = 0;
+          R[j * LD + j] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    if (act[j]) {
+      const double rjj = R[j * LD + j];
+      if (tid > j && tid < RP) R[j * LD + tid] = G[j * LD + tid] / rjj;
+      __syncthreads();
+      for (int e = tid; e < RP * RP; e += blockDim.x) {
+        const int a = e / RP, b = e % RP;
+        if (a > j && b > j) G[a * LD + b] -= R[j * LD + a] * R[j * LD + b];
+      }
+    }
+    __syncthreads();
+  }
+  // Inverse of R restricted to the active columns (zero elsewhere).
+  if (tid < RP) {
+    const int c = tid;
+    for (int i = RP - 1; i >= 0; --i) {
+      if (i > c || !act[c] || !act[i]) { Ri[i * LD + c] = 0.0; continue; }
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= c; ++l) s -= R[i * LD + l] * Ri[l * LD + c];
+      Ri[i * LD + c] = s / R[i * LD + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, j = e % RP;
+    rinv_panel[e] = (TA)Ri[i * LD + j];
+    st->Rinv[e] = Ri[i * LD + j];
+  }
+  if (acc != nullptr) {
+    // acc <- R * acc (or R), then an exact power-of-two rescale.
+    for (int e = tid; e < RP * RP; e += blockDim.x) {
+      const int i = e / RP, j = e % RP;
+      double s = 0.0;
+      if (reset_acc) {
+        s = R[i * LD + j];
+      } else {
+        for (int l = i; l < RP; ++l) s += R[i * LD + l] * acc[l * RP + j];
+      }
+      A[i * LD + j] = s;
+    }
+    __syncthreads();
+    // R2 only enters through ratios of its singular values, so it may be
+    // rescaled; T must keep its scale (B = B' T).
+    if (normalise) pow2_normalise(A, RP, LD, red);
+    for (int e = tid; e < RP * RP; e += blockDim.x) acc[e] = A[(e / RP) * LD + (e % RP)];
+  }
+}
+
+// Round-robin pairing (circle method) over N (even) players.
+__device__ __forceinline__ void rr_pair(int round, int k, int N, int& a, int& b) {
+  auto pos = [&](int i) { return i == 0 ? 0 : 1 + ((i - 1 + round) % (N - 1)); };
+  a = pos(k);
+  b = pos(N - 1 - k);
+}
+
+// Two-sided cyclic Jacobi on the symmetric n x n matrix A (LDS, stride LD),
+// accumulating V <- V J.  Parallel over disjoint pairs in each round.
+template <int RP>
+__device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
+  constexpr int LD = RP + 1;
+  const int N = (n + 1) & ~1;
+  const int npairs = N / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) *rot = 0;
+    __syncthreads();
+    for (int round = 0; round < N - 1; ++round) {
+      if (threadIdx.x < npairs) {
+        int p, q;
+        rr_pair(round, threadIdx.x, N, p, q);
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * LD + q];
+          const double app = A[p * LD + p], aqq = A[q * LD + q];
+          if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            atomicAdd(rot, 1);
+          }
+        }
+        cs[4 * threadIdx.x + 0] = c;
+        cs[4 * threadIdx.x + 1] = s;
+        cs[4 * threadIdx.x + 2] = (double)p;
+        cs[4 * threadIdx.x + 3] = (double)q;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
+        const int i = e / npairs, k = e % npairs;
+        const double c = cs[4 * k], s = cs[4 * k + 1];
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+        if (q >= n || s == 0.0) continue;
+        const double aip = A[i * LD + p], aiq = A[i * LD + q];
+        A[i * LD + p] = c * aip - s * aiq;
+        A[i * LD + q] = s * aip + c * aiq;
+        const double vip = V[i * LD + p], viq = V[i * LD + q];
+        V[i * LD + p] = c * vip - s * viq;
+        V[i * LD + q] = s * vip + c * viq;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
+        const int j = e / npairs, k = e % npairs;
+        const double c = cs[4 * k], s = cs[4 * k + 1];
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+        if (q >= n || s == 0.0) continue;
+        const double apj = A[p * LD + j], aqj = A[q * LD + j];
+        A[p * LD + j] = c * apj - s * aqj;
+        A[q * LD + j] = s * apj + c * aqj;
+      }
+      __syncthreads();
+    }
+    if (*rot == 0) break;
+    __syncthreads();
+  }
+}
+
+// One-sided (Hestenes) Jacobi: orthogonalise the columns of M (n x n);
+// afterwards the column norms are the singular values.
+template <int RP>
+__device__ void jacobi_svd_values(double* M, int n, double* out, double* cs, int* rot) {
+  constexpr int LD = RP + 1;
+  const int N = (n + 1) & ~1;
+  const int npairs = N / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) *rot = 0;
+    __syncthreads();
+    for (int round = 0; round < N - 1; ++round) {
+      if (threadIdx.x < npairs) {
+        int p, q;
+        rr_pair(round, threadIdx.x, N, p, q);
+        double c = 1.0, s = 0.0;
+        if (p < n && q < n) {
+          double al = 0, be = 0, ga = 0;
+          for (int i = 0; i < n; ++i) {
+            const double x = M[i * LD + p], y = M[i * LD + q];
+            al += x * x; be += y * y; ga += x * y;
+          }
+          if (ga != 0.0 && fabs(ga) > 1e-17 * sqrt(al * be)) {
+            const double ze = (be - al) / (2.0 * ga);
+            const double t = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = c * t;
+            atomicAdd(rot, 1);
+          }
+        }
+        cs[4 * threadIdx.x + 0] = c;
+        cs[4 * threadIdx.x + 1] = s;
+        cs[4 * threadIdx.x + 2] = (double)p;
+        cs[4 * threadIdx.x + 3] = (double)q;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
+        const int i = e / npairs, k = e % npairs;
+        const double c = cs[4 * k], s = cs[4 * k + 1];
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+        if (p >= n || q >= n || s == 0.0) continue;
+        const double x = M[i * LD + p], y = M[i * LD + q];
+        M[i * LD + p] = c * x - s * y;
+        M[i * LD + q] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+    if (*rot == 0) break;
+    __syncthreads();
+  }
+  if (threadIdx.x < n) {
+    double s = 0;
+    for (int i = 0; i < n; ++i) s += M[i * LD + threadIdx.x] * M[i * LD + threadIdx.x];
+    out[threadIdx.x] = sqrt(s);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Core of the low-rank step.  Inputs: Gpart of B' = D Y_q (so B = B' T),
+// st->T, st->R2.  Output: K' = T K in the panel type, such that
+// U_L = B' K' and L = U_L Q2^T.
+// ---------------------------------------------------------------------------
+template <typename TA, int RP>
+__global__ __launch_bounds__(256) void k_core(const double* __restrict__ Gpart,
+                                              int nparts, SmallState* st, int p,
+                                              double rank_tol, int t_identity,
+                                              TA* k_panel) {
+  constexpr int LD = RP + 1;
+  __shared__ double G[RP * LD];
+  __shared__ double H[RP * LD];
+  __shared__ double T[RP * LD];
+  __shared__ double V[RP * LD];
+  __shared__ double W[RP * LD];
+  __shared__ double cs[4 * 16 + 4];
+  __shared__ double ev[RP];
+  __shared__ double sv[RP];
+  __shared__ int order[RP];
+  __shared__ int rot;
+  __shared__ int sh_keep;
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int n = st->r_eff;             // active leading columns
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += Gpart[(int64_t)b * RP * RP + e];
+    const int i = e / RP, j = e % RP;
+    G[i * LD + j] = s;
+    T[i * LD + j] = t_identity ? (i == j ? 1.0 : 0.0) : st->T[e];
+    W[i * LD + j] = st->R2[e];
+  }
+  __syncthreads();
+
+  // ---- rank check on R2 (A2^T Y1 = R2^T R2) ----
+  // Certificate first: s_min(R2) >= 1/||R2^{-1}||_F and s_max <= ||R2||_F.
+  if (tid == 0) {
+    double fr = 0.0, fi = 0.0;
+    bool ok = n > 0;
+    for (int i = 0; i < n; ++i) {
+      for (int j = i; j < n; ++j) fr += W[i * LD + j] * W[i * LD + j];
+      if (!(W[i * LD + i] != 0.0)) ok = false;
+    }
+    if (ok) {
+      // column c of R2^{-1} by back substitution, accumulate its norm
+      for (int c = 0; c < n && ok; ++c) {
+        double x[RP];
+        for (int i = c; i >= 0; --i) {
+          double s = (i == c) ? 1.0 : 0.0;
+          for (int l = i + 1; l <= c; ++l) s -= W[i * LD + l] * x[l];
+          x[i] = s / W[i * LD + i];
+          fi += x[i] * x[i];
+        }
+      }
+      ok = isfinite(fi) && isfinite(fr) && (1.0 / fi) > rank_tol * fr;
+    }
+    red[0] = ok ? 1.0 : 0.0;
+    sh_keep = n;
+  }
+  __syncthreads();
+  if (red[0] == 0.0 && n > 0) {
+    jacobi_svd_values<RP>(W, n, sv, cs, &rot);
+    if (tid == 0) {
+      double smax = 0.0;
+      for (int i = 0; i < n; ++i) smax = fmax(smax, sv[i]);
+      int keep = 0;
+      for (int i = 0; i < n; ++i)
+        if (smax > 0.0 && sv[i] * sv[i] > rank_tol * smax * smax) ++keep;
+      sh_keep = keep;
+    }
+    __syncthreads();
+  }
+
+  // ---- G_B = T^T G' T on the active block ----
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, j = e % RP;
+    double s = 0.0;
+    for (int l = 0; l <= j; ++l) s += G[i * LD + l] * T[l * LD + j];
+    H[i * LD + j] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, j = e % RP;
+    double s = 0.0;
+    for (int l = 0; l <= i; ++l) s += T[l * LD + i] * H[l * LD + j];
+    W[i * LD + j] = (i < n && j < n) ? s : 0.0;
+  }
+  __syncthreads();
+  // symmetrise and set V (warm start from the previous iteration if valid)
+  const int warm = st->v_valid;
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, j = e % RP;
+    G[i * LD + j] = 0.5 * (W[i * LD + j] + W[j * LD + i]);
+    V[i * LD + j] = warm ? st->V[e] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (warm) {
+    // A = V^T G V
+    for (int e = tid; e < RP * RP; e += blockDim.x) {
+      const int i = e / RP, j = e % RP;
+      double s = 0.0;
+      for (int l = 0; l < n; ++l) s += G[i * LD + l] * V[l * LD + j];
+      H[i * LD + j] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < RP * RP; e += blockDim.x) {
+      const int i = e / RP, j = e % RP;
+      double s = 0.0;
+      for (int l = 0; l < n; ++l) s += V[l * LD + i] * H[l * LD + j];
+      W[i * LD + j] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < RP * RP; e += blockDim.x) {
+      const int i = e / RP, j = e % RP;
+      G[i * LD + j] = 0.5 * (W[i * LD + j] + W[j * LD + i]);
+    }
+    __syncthreads();
+  }
+  jacobi_eig<RP>(G, V, n, cs, &rot);
+  // sort eigenvalues descending
+  if (tid == 0) {
+    for (int i = 0; i < n; ++i) order[i] = i;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j)
+        if (G[order[j] * LD + order[j]] > G[order[i] * LD + order[i]]) {
+          const int t = order[i]; order[i] = order[j]; order[j] = t;
+        }
+    for (int i = 0; i < n; ++i) ev[i] = G[order[i] * LD + order[i]];
+  }
+  __syncthreads();
+  const int keep = sh_keep;
+  // K = sum_{i < keep, ev_i > 0} v_i ev_i^{(1-p)/(2p)} v_i^T
+  const double ex = (1.0 - (double)p) / (2.0 * (double)p);
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int a = e / RP, b = e % RP;
+    double s = 0.0;
+    if (a < n && b < n) {
+      for (int i = 0; i < keep; ++i) {
+        const double lam = ev[i];
+        if (!(lam > 0.0)) continue;
+        const double f = (p == 1) ? 1.0 : pow(lam, ex);
+        s += V[a * LD + order[i]] * f * V[b * LD + order[i]];
+      }
+    }
+    H[a * LD + b] = s;
+  }
+  __syncthreads();
+  // K' = T K ; store eigenvectors (sorted) for the next warm start
+  int bad = 0;
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, j = e % RP;
+    double s = 0.0;
+    for (int l = i; l < RP; ++l) s += T[i * LD + l] * H[l * LD + j];
+    if (!isfinite(s)) bad = 1;
+    st->K[e] = s;
+    k_panel[e] = (TA)s;
+    st->V[e] = (j < n && i < n) ? V[i * LD + order[j]] : (i == j ? 1.0 : 0.0);
+  }
+  if (bad) atomicOr(&st->flags, 1);
+  if (tid < RP) {
+    st->sigma[tid] = (tid < n && ev[tid] > 0.0) ? sqrt(ev[tid]) : 0.0;
+    st->sv_c[tid] = 0.0;
+  }
+  if (tid == 0) {
+    st->r_keep = keep;
+    st->v_valid = (keep == n) ? 1 : 0;
+    if (keep < n) {
+      st->r_eff = keep;
+      atomicOr(&st->flags, 2);
+    }
+  }
+}
+
+__global__ void k_small_init(SmallState* st, int r) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kMaxRP * kMaxRP; e += blockDim.x) {
+    st->R2[e] = 0.0; st->T[e] = 0.0; st->Rinv[e] = 0.0; st->V[e] = 0.0; st->K[e] = 0.0;
+  }
+  if (tid < kMaxRP) { st->sigma[tid] = 0.0; st->sv_c[tid] = 0.0; st->active[tid] = tid < r; }
+  if (tid == 0) { st->r_eff = r; st->r_keep = r; st->flags = 0; st->v_valid = 0; }
+}
+
+#define GODEC_RP_SWITCH(rp, ...)                   \
+  switch (rp) {                                    \
+    case 1: { constexpr int RP = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int RP = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int RP = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int RP = 8; __VA_ARGS__; } break;   \
+    case 12: { constexpr int RP = 12; __VA_ARGS__; } break; \
+    case 16: { constexpr int RP = 16; __VA_ARGS__; } break; \
+    case 20: { constexpr int RP = 20; __VA_ARGS__; } break; \
+    case 24: { constexpr int RP = 24; __VA_ARGS__; } break; \
+    case 32: { constexpr int RP = 32; __VA_ARGS__; } break; \
+    default: break;                                \
+  }
+
+void launch_chol(const Launch& L, bool f64, int rp, const double* Gpart,
+                 int nparts, SmallState* st, double* acc, void* rinv_panel,
+                 int reset_acc, int normalise) {
+  GODEC_RP_SWITCH(rp, {
+    if (f64)
+      hipLaunchKernelGGL((k_chol<double, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
+                         nparts, st, acc, (double*)rinv_panel, reset_acc, normalise);
+    else
+      hipLaunchKernelGGL((k_chol<float, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
+                         nparts, st, acc, (float*)rinv_panel, reset_acc, normalise);
+  });
+}
+
+void launch_core(const Launch& L, bool f64, int rp, const double* Gpart,
+                 int nparts, SmallState* st, int p, double rank_tol,
+                 int t_identity, void* k_panel) {
+  GODEC_RP_SWITCH(rp, {
+    if (f64)
+      hipLaunchKernelGGL((k_core<double, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
+                         nparts, st, p, rank_tol, t_identity, (double*)k_panel);
+    else
+      hipLaunchKernelGGL((k_core<float, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
+                         nparts, st, p, rank_tol, t_identity, (float*)k_panel);
+  });
+}
+
+void launch_small_init(const Launch& L, SmallState* st, int r) {
+  hipLaunchKernelGGL(k_small_init, dim3(1), dim3(256), 0, L.stream, st, r);
+}
+
+}  // namespace godec
