@@ -58,7 +58,7 @@ struct Carver {
 
 struct godec_ctx {
   // problem
-  int64_t m, n, ldx, ldd, k;
+  int64_t m, n, ldx, ldd, mpad, k;
   int r, rp, q, p;
   uint64_t seed;
   godec_dtype dtype;
@@ -73,7 +73,9 @@ struct godec_ctx {
   void* D = nullptr;       // native-precision working copy
   void* D16 = nullptr;     // bf16 working copy (BF16_REFINE)
   double* A1 = nullptr;    // n x r FP64
-  void *P0, *P1, *VL, *W, *Zpart, *Bp, *UL, *Kp, *Rinvp;
+  void *P0, *P1, *VL, *VLt, *W, *Zpart, *Bp, *UL, *Kp, *Rinvp;
+  void *Zt, *Wt;             // 32-row transposed panels for the matrix cores
+  float *Wtpart, *Zpart32;   // partial sums of the two MFMA halves
   double* Gpart;
   SmallState* st;
   SelPlan* plan[2];
@@ -81,16 +83,21 @@ struct godec_ctx {
   unsigned long long* counters;
   int64_t* cand_idx;
   void* cand_val;
+  void* cand_x;
+  unsigned int* seg_count;
   int64_t cap;
   int64_t* tie_idx;
+  SelCarry* carry;
   int64_t* s_idx[2];
   void* s_val[2];
+  void* s_x[2];
   uint32_t *bitmap, *wpre, *bsum;
   unsigned long long* boff;
   double* norm_x2;
   int* nonfinite;
   // schedule
   int64_t nchunks, rows_per_chunk;
+  int64_t kc_a, nct_a, rc_b, nch_b;   // MFMA tiling
   int gram_blocks_n, gram_blocks_m;
   // state
   int64_t iters_done = 0;
@@ -107,22 +114,33 @@ struct godec_ctx {
 namespace {
 
 struct Sizes {
-  int64_t ldd, nchunks, rpc, cap;
+  int64_t ldd, mpad, nchunks, rpc, cap;
+  int64_t kc_a, nct_a, rc_b, nch_b;
   int gbn, gbm;
 };
 
 Sizes plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
   Sizes s;
-  s.ldd = (n + 15) / 16 * 16;
+  s.ldd = (n + 127) / 128 * 128;
+  s.mpad = (m + 63) / 64 * 64;
+  // k_mm_a: 1024-column tiles; k_mm_b: 128-column strips x row chunks
+  s.kc_a = 1024;
+  s.nct_a = (s.ldd + s.kc_a - 1) / s.kc_a;
+  const int64_t strips = s.ldd / 128;
+  int64_t nch = std::max<int64_t>(1, (4LL * num_cu + strips - 1) / strips);
+  nch = std::min<int64_t>(nch, std::max<int64_t>(1, s.mpad / 256));
+  s.rc_b = ((s.mpad + nch - 1) / nch + 63) / 64 * 64;
+  s.nch_b = (s.mpad + s.rc_b - 1) / s.rc_b;
   const int64_t ctiles = (s.ldd + 1023) / 1024;
   int64_t want = std::max<int64_t>(1, (4LL * num_cu + ctiles - 1) / ctiles);
   want = std::min<int64_t>(want, std::max<int64_t>(1, (m + 63) / 64));
   s.rpc = (m + want - 1) / want;
   s.rpc = (s.rpc + 15) / 16 * 16;
   s.nchunks = (m + s.rpc - 1) / s.rpc;
-  s.cap = std::min<int64_t>(m * n, k + std::max<int64_t>(k / 2, 65536));
-  s.gbn = (int)std::min<int64_t>(256, std::max<int64_t>(1, (s.ldd + 63) / 64));
-  s.gbm = (int)std::min<int64_t>(256, std::max<int64_t>(1, (m + 63) / 64));
+  s.cap = std::min<int64_t>(m * n, 2 * k + (1 << 20));
+  // few Gram partials: the one-block r x r kernels sum them serially
+  s.gbn = (int)std::min<int64_t>(32, std::max<int64_t>(1, (s.ldd + 255) / 256));
+  s.gbm = (int)std::min<int64_t>(32, std::max<int64_t>(1, (m + 255) / 256));
   return s;
 }
 
@@ -132,14 +150,25 @@ size_t carve(godec_ctx* c, void* base) {
   const int64_t m = c->m, ldd = c->ldd, rp = c->rp;
   const size_t ta = c->ta;
   const size_t dsz = c->f64 ? 8 : 4;
-  c->D = cv.take((size_t)m * ldd * dsz);
-  c->D16 = (c->prec == GODEC_PREC_BF16_REFINE) ? cv.take((size_t)m * ldd * 2) : nullptr;
+  const int64_t mpad = c->mpad;
+  c->D = cv.take((size_t)mpad * ldd * dsz);
+  c->D16 = (c->prec == GODEC_PREC_BF16_REFINE) ? cv.take((size_t)mpad * ldd * 2) : nullptr;
+  if (!c->f64) {
+    c->Zt = cv.take((size_t)32 * ldd * 4);
+    c->Wt = cv.take((size_t)32 * mpad * 4);
+    c->Wtpart = (float*)cv.take((size_t)c->nct_a * 32 * mpad * 4);
+    c->Zpart32 = (float*)cv.take((size_t)c->nch_b * ldd * 32 * 4);
+  } else {
+    c->Zt = c->Wt = nullptr;
+    c->Wtpart = c->Zpart32 = nullptr;
+  }
   c->A1 = (double*)cv.take((size_t)c->n * c->r * 8);
   c->P0 = cv.take((size_t)ldd * rp * ta);
   c->P1 = cv.take((size_t)ldd * rp * ta);
   c->VL = cv.take((size_t)ldd * rp * ta);
+  c->VLt = cv.take((size_t)ldd * rp * ta);
   c->W = cv.take((size_t)m * rp * ta);
-  c->Zpart = cv.take((size_t)c->nchunks * ldd * rp * ta);
+  c->Zpart = c->f64 ? cv.take((size_t)c->nchunks * ldd * rp * ta) : nullptr;
   c->Bp = cv.take((size_t)m * rp * ta);
   c->UL = cv.take((size_t)m * rp * ta);
   c->Kp = cv.take((size_t)rp * rp * ta);
@@ -148,15 +177,19 @@ size_t carve(godec_ctx* c, void* base) {
   c->st = (SmallState*)cv.take(sizeof(SmallState));
   c->plan[0] = (SelPlan*)cv.take(sizeof(SelPlan));
   c->plan[1] = (SelPlan*)cv.take(sizeof(SelPlan));
-  c->hist = (unsigned long long*)cv.take((size_t)kHistBins * 8);
+  c->hist = (unsigned long long*)cv.take((size_t)kHistReplicas * kHistBins * 8);
   c->counters = (unsigned long long*)cv.take(64);
-  c->cand_idx = (int64_t*)cv.take((size_t)c->cap * 8);
-  c->cand_val = cv.take((size_t)c->cap * ta);
+  c->cand_idx = (int64_t*)cv.take((size_t)c->cap * 2 * 8);
+  c->cand_val = cv.take((size_t)c->cap * 2 * ta);
+  c->cand_x = cv.take((size_t)c->cap * 2 * ta);
+  c->seg_count = (unsigned int*)cv.take((size_t)kMaxSeg * 4);
   c->tie_idx = (int64_t*)cv.take((size_t)c->cap * 8);
+  c->carry = (SelCarry*)cv.take(sizeof(SelCarry));
   const int64_t kk = std::max<int64_t>(c->k, 1);
   for (int b = 0; b < 2; ++b) {
     c->s_idx[b] = (int64_t*)cv.take((size_t)kk * 8);
     c->s_val[b] = cv.take((size_t)kk * ta);
+    c->s_x[b] = cv.take((size_t)kk * ta);
   }
   const int64_t nwords = (m * c->n + 31) / 32;
   const int64_t nb = (nwords + 1023) / 1024;
@@ -200,7 +233,9 @@ void fill_ctx_params(godec_ctx* c, int64_t m, int64_t n, int32_t r, int64_t k,
   c->ta = c->f64 ? 8 : 4;
   c->num_cu = num_cu;
   Sizes s = plan_sizes(m, n, k, num_cu);
-  c->ldd = s.ldd; c->nchunks = s.nchunks; c->rows_per_chunk = s.rpc; c->cap = s.cap;
+  c->ldd = s.ldd; c->mpad = s.mpad; c->nchunks = s.nchunks; c->rows_per_chunk = s.rpc;
+  c->cap = s.cap;
+  c->kc_a = s.kc_a; c->nct_a = s.nct_a; c->rc_b = s.rc_b; c->nch_b = s.nch_b;
   c->gram_blocks_n = s.gbn; c->gram_blocks_m = s.gbm;
 }
 
@@ -232,9 +267,8 @@ Launch launch_of(const godec_ctx* c) { return Launch{c->stream, c->num_cu}; }
 // Kernel classes timed by godec_profile.
 enum ProfClass { PC_APPLY = 0, PC_APPLY_T, PC_APPLY_BF16, PC_APPLY_T_BF16, PC_SEL_PASS,
                  PC_COUNT };
-const char* kProfNames[PC_COUNT] = {"panel_apply(D*Z)", "panel_apply_t(D^T*W)",
-                                    "panel_apply_bf16(D*Z)", "panel_apply_t_bf16(D^T*W)",
-                                    "select_pass(hist)"};
+const char* kProfNames[PC_COUNT] = {"mm_a(D*Z)", "mm_b(W^T*D)", "mm_a_bf16(D*Z)",
+                                    "mm_b_bf16(W^T*D)", "select_pass(hist)"};
 const double kProfElemBytes[PC_COUNT] = {0, 0, 2, 2, 0};   // 0: element size of X
 
 hipEvent_t prof_event(godec_ctx* c) {
@@ -265,8 +299,31 @@ struct ProfScope {
 };
 
 // One Gram pass: out = D^T (D in), through W and the chunk partials.
+// W^T panel of D Y on the matrix cores (f32 / bf16 storage).
+void mfma_apply(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* Wt_out,
+                float* Wrow_out) {
+  const Launch L = launch_of(c);
+  const bool b16 = td == BF16;
+  mfma_to_t(L, b16, in, c->ldd, c->rp, c->Zt);
+  {
+    ProfScope ps(c, b16 ? PC_APPLY_BF16 : PC_APPLY);
+    mfma_mm_a(L, b16, Dsrc, c->ldd, c->mpad, c->Zt, c->Wtpart, c->kc_a);
+  }
+  mfma_reduce_w(L, b16, c->Wtpart, (int)c->nct_a, c->mpad, c->m, c->rp, Wt_out, Wrow_out);
+}
+
 void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* out) {
   const Launch L = launch_of(c);
+  if (td != F64) {
+    const bool b16 = td == BF16;
+    mfma_apply(c, td, Dsrc, in, c->Wt, nullptr);
+    {
+      ProfScope ps(c, b16 ? PC_APPLY_T_BF16 : PC_APPLY_T);
+      mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b);
+    }
+    mfma_reduce_z(L, c->Zpart32, c->nch_b, c->ldd, c->rp, (float*)out);
+    return;
+  }
   {
     ProfScope ps(c, td == BF16 ? PC_APPLY_BF16 : PC_APPLY);
     launch_apply(L, td, c->rp, Dsrc, c->ldd, c->m, in, c->W);
@@ -316,7 +373,10 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
     chol_qr(c, c->P1, c->P0, c->st->T, j == 0);
     in = c->P0;
   }
-  launch_apply(L, tdb, c->rp, Db, c->ldd, c->m, in, c->Bp);
+  if (c->f64)
+    launch_apply(L, tdb, c->rp, Db, c->ldd, c->m, in, c->Bp);
+  else
+    mfma_apply(c, tdb, Db, in, nullptr, (float*)c->Bp);
   // ---- core ----
   launch_gram(L, c->f64, c->rp, c->Bp, c->m, c->Gpart, c->gram_blocks_m);
   launch_core(L, c->f64, c->rp, c->Gpart, c->gram_blocks_m, c->st, c->p, c->rank_tol,
@@ -325,11 +385,16 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   // ---- sparse step ----
   const int prev = c->cur;
   const int nxt = c->cur ^ 1;
+  launch_transpose_panel(L, c->f64, c->VL, c->ldd, c->rp, c->VLt);
   SelectArgs a;
   a.X = c->X; a.ldx = c->ldx; a.UL = c->UL; a.VL = c->VL; a.m = c->m; a.n = c->n; a.k = c->k;
+  a.VLt = c->VLt; a.ldv = c->ldd;
   a.plan = c->plan[nxt]; a.hist = c->hist; a.counters = c->counters;
-  a.cand_idx = c->cand_idx; a.cand_val = c->cand_val; a.cap = c->cap;
-  a.s_idx = c->s_idx[nxt]; a.s_val = c->s_val[nxt]; a.tie_idx = c->tie_idx;
+  a.cand_idx = c->cand_idx; a.cand_val = c->cand_val; a.cand_x = c->cand_x; a.cap = c->cap;
+  a.seg_count = c->seg_count;
+  a.s_idx = c->s_idx[nxt]; a.s_val = c->s_val[nxt]; a.s_x = c->s_x[nxt];
+  a.tie_idx = c->tie_idx;
+  a.carry = c->carry;
   if (c->prof) {
     a.ev_a = prof_event(c);
     a.ev_b = prof_event(c);
@@ -339,17 +404,17 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   // ---- D update ----
   const int64_t kk = std::max<int64_t>(c->k, 1);
   if (c->iters_done > 0) {
-    launch_update_d(L, native, c->f64, c->D, c->ldd, c->X, c->ldx, c->n, c->s_idx[prev],
-                    nullptr, c->plan[prev], kk);
+    launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
+                    c->plan[prev], kk);
     if (mixed)
-      launch_update_d(L, BF16, false, c->D16, c->ldd, c->X, c->ldx, c->n, c->s_idx[prev],
-                      nullptr, c->plan[prev], kk);
+      launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
+                      c->plan[prev], kk);
   }
-  launch_update_d(L, native, c->f64, c->D, c->ldd, c->X, c->ldx, c->n, c->s_idx[nxt],
-                  c->s_val[nxt], c->plan[nxt], kk);
+  launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
+                  c->plan[nxt], kk);
   if (mixed)
-    launch_update_d(L, BF16, false, c->D16, c->ldd, c->X, c->ldx, c->n, c->s_idx[nxt],
-                    c->s_val[nxt], c->plan[nxt], kk);
+    launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
+                    c->plan[nxt], kk);
   c->cur = nxt;
   c->iters_done += 1;
   HIP_TRY(hipGetLastError());
@@ -437,14 +502,15 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   hipError_t e = hipMemcpyAsync(c->A1, c->a1_host.data(), sizeof(double) * n * r,
                                 hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
-  launch_init_d(L, c->f64 ? F64 : F32, c->f64, c->D, c->ldd, X_dev, ldx, m, n);
-  if (c->D16) launch_init_d(L, BF16, false, c->D16, c->ldd, X_dev, ldx, m, n);
+  launch_init_d(L, c->f64 ? F64 : F32, c->f64, c->D, c->ldd, X_dev, ldx, m, n, c->mpad);
+  if (c->D16) launch_init_d(L, BF16, false, c->D16, c->ldd, X_dev, ldx, m, n, c->mpad);
   launch_small_init(L, c->st, r);
   // zero the small scalars, plans and the (unused) panel padding
   e = hipMemsetAsync(c->norm_x2, 0, 8, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->nonfinite, 0, 8, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->plan[0], 0, sizeof(SelPlan), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->plan[1], 0, sizeof(SelPlan), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->carry, 0, sizeof(SelCarry), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->VL, 0, (size_t)c->ldd * c->rp * c->ta, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->UL, 0, (size_t)c->m * c->rp * c->ta, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));

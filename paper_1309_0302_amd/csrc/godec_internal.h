@@ -1,10 +1,10 @@
 // Internal declarations of libgodec (not part of the public ABI).
 //
 // Device data layout (all inside the caller's workspace):
-//   D      m x ldd working copy of X - S_{t-1} in the panel storage type
-//          (f64 / f32; plus a bf16 copy in the mixed-precision mode).  Rows
-//          are padded to ldd = round_up(n, 16) with zeros so panel kernels
-//          read whole 16-byte vectors without column tails.
+//   D      mpad x ldd working copy of X - S_{t-1} in the panel storage type
+//          (f64 / f32; plus a bf16 copy in the mixed-precision mode), zero
+//          padded to mpad = round_up(m, 64) rows and ldd = round_up(n, 128)
+//          columns so panel kernels need no row or column tails.
 //   panels n_pad x RP and m x RP row-major (RP = r rounded up to a
 //          supported width), compute type TA (double, or float for the f32
 //          and bf16 modes); padding rows/columns are zero.
@@ -22,6 +22,8 @@ constexpr int kMaxRP = 32;
 constexpr int kHistBits0 = 12;        // first radix digit of the key
 constexpr int kHistBits = 11;         // later digits
 constexpr int kHistBins = 1 << kHistBits0;
+constexpr int kHistReplicas = 8;      // global histogram copies (contention)
+constexpr int kMaxSeg = 4096;         // most blocks of a full-data selection pass
 constexpr int kBlock = 256;
 
 // Supported padded panel widths.
@@ -40,8 +42,10 @@ enum SelMode : int {
   SEL_COLLECT = 1,   // next full-data pass writes candidates >= bucket low
   SEL_REFINE = 2,    // candidates hold the bucket; refine digits over them
   SEL_FINAL = 3,     // threshold resolved, candidates hold everything needed
-  SEL_TIES = 4,      // threshold resolved but ties overflow the candidates
+  SEL_TIES = 4,      // threshold resolved but ties overflow the candidates:
+                     // the next full pass collects the entries above it
   SEL_DONE = 5,      // S written by the index-ordered tie scan
+  SEL_TSCAN = 6,     // entries above collected; the tie scan comes next
 };
 
 struct SelPlan {
@@ -49,18 +53,26 @@ struct SelPlan {
   long long k_rem;             // entries still to take inside the bucket
   long long count_above;       // entries above the bucket (all taken)
   long long bucket_count;      // entries inside the bucket
-  long long ncand;             // candidates written
-  long long cap;               // candidate capacity
+  long long ncand;             // candidates written to the spill region
+  long long cap;               // capacity of the segments and of the spill
   long long nnz;               // entries of S written by compaction
   int pbits;                   // number of resolved key bits
   int kbits;                   // key width (31 for f32, 63 for f64)
   int mode;                    // SelMode
   int slow;                    // a slow exact path was used
   int overflow;                // candidate buffer overflowed
-  int pad0;
+  int nseg;                    // segments (= blocks of the full passes)
+  int carry_used;              // 1: pass 0 used the carried window
+  int carry_dlo;               // lowest level-0 digit histogrammed/collected
   double sum_r2;               // ||X - L||_F^2 (all entries)
   double sum_sel2;             // sum of R^2 over the selected entries
   double threshold;            // |R| of the threshold key
+};
+
+// Threshold carried between iterations: the level-0 digit window start.
+struct SelCarry {
+  int valid;
+  int dlo;
 };
 
 // Small FP64 state of one iteration.
@@ -122,31 +134,42 @@ struct SelectArgs {
   int64_t ldx;
   const void* UL;       // m x RP
   const void* VL;       // ldd x RP
+  const void* VLt;      // RP x ldv (transpose of VL, for coalesced reads)
+  int64_t ldv;
   int64_t m, n;
   int64_t k;
   SelPlan* plan;
-  unsigned long long* hist;      // kHistBins counters
+  unsigned long long* hist;      // kHistRep x kHistBins counters
   unsigned long long* counters;  // [0] above threshold, [1] ties
+  // candidates: 2*cap entries; [0, cap) is split into one segment per block
+  // of the full-data passes, [cap, 2*cap) is the shared spill region
   int64_t* cand_idx;
   void* cand_val;
+  void* cand_x;         // X at each candidate (so D updates need no X reads)
+  unsigned int* seg_count;  // kMaxSeg entries: fill of each segment
   int64_t cap;
   int64_t* s_idx;       // output S list (unordered)
   void* s_val;
+  void* s_x;
   int64_t* tie_idx;     // scratch for ties (cap entries)
+  SelCarry* carry;      // persists across iterations
   hipEvent_t ev_a = nullptr, ev_b = nullptr;  // optional: bracket pass 0
 };
 void launch_select(const Launch& L, bool f64, int rp, const SelectArgs& a);
+void launch_transpose_panel(const Launch& L, bool f64, const void* VL, int64_t rows, int rp,
+                            void* VLt);
 // R = X - UL VL^T (dense_l = 0) or L = UL VL^T (dense_l = 1).
 void launch_residual(const Launch& L, bool f64, int rp, const void* X,
                      int64_t ldx, const void* UL, const void* VL, int64_t m,
                      int64_t n, void* R, int64_t ldr, int dense_l);
+// D (mpad x ldd) <- X with zero padding rows and columns.
 void launch_init_d(const Launch& L, DType td, bool xf64, void* D,
                    int64_t ldd, const void* X, int64_t ldx, int64_t m,
-                   int64_t n);
-// D[idx] <- X[idx] - val (val != nullptr) or X[idx] for the plan's nnz entries.
-void launch_update_d(const Launch& L, DType td, bool xf64, void* D,
-                     int64_t ldd, const void* X, int64_t ldx, int64_t n,
-                     const int64_t* idx, const void* val, const SelPlan* plan,
+                   int64_t n, int64_t mpad);
+// D[idx] <- x - val (val != nullptr) or x, for the plan's nnz entries, with
+// x the stored value of X at idx.
+void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
+                     const int64_t* idx, const void* val, const void* xv, const SelPlan* plan,
                      int64_t kmax);
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx,
                        int64_t m, int64_t n, double* out2, int* nonfinite);
@@ -155,6 +178,17 @@ void launch_sort_s(const Launch& L, bool f64, const int64_t* idx,
                    int64_t kmax, uint32_t* bitmap, uint32_t* wpre,
                    uint32_t* bsum, unsigned long long* boff, int64_t* out_idx,
                    void* out_val);
+// ---- matrix-core panel products (k_mfma.hip), f32 and bf16 storage ----
+void mfma_to_t(const Launch& L, bool bf16, const void* Z, int64_t ldd, int rp, void* Zt);
+void mfma_mm_a(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
+               const void* Zt, float* Wtpart, int64_t KC);
+void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int64_t mpad,
+                   int64_t m, int rp, void* Wt, float* Wrow);
+void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
+               const void* Wt, float* Zpart, int64_t RC, int64_t nch);
+void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
+                   float* Zo);
+
 void launch_cast_panel(const Launch& L, bool f64, int rp, const void* src,
                        int64_t rows, int r, void* dst);
 

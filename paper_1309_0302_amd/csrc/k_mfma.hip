@@ -1,0 +1,350 @@
+// Panel products of the power chain on the CDNA4 matrix cores.
+//
+// Both halves of a Gram pass stream the working copy D (mpad x ldd,
+// row-major, zero padded to multiples of 64 rows and 128 columns):
+//
+//   k_mm_a:  W^T = (D Z)^T         (32 x mpad)  A = rows of D, B = Z^T
+//   k_mm_b:  Z_out^T = W^T D       (32 x ldd)   A = W^T,      B = D
+//
+// The panel width is padded to 32 (one MFMA tile); padding columns are zero.
+// The contraction index may be permuted freely as long as both operands use
+// the same (lane group, slot) -> k assignment, so each lane reads contiguous
+// runs: along its row of D in k_mm_a, and 16-byte column groups of D rows
+// in k_mm_b (lanes cover consecutive columns, so a wave reads whole rows).
+//
+// Layouts used (v_mfma_f32_32x32x{16_bf16, 2_f32}, lane l, l%32 = index on
+// the lanes, l/32 = group g):  A operand row i = l%32; B operand column
+// j = l%32; accumulator register v holds C[8(v/4) + 4g + v%4][l%32].
+#include "godec_internal.h"
+#include "k_common.h"
+
+namespace godec {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int acc_row(int v, int lane) {
+  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) {
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// k_mm_a: Wtpart[ct] = (D[:, tile ct] Z[tile ct, :])^T.
+// Block = 2 waves, wave w owns rows [blockIdx.y*128 + 64w, +64) as two
+// 32-row MFMA tiles sharing the B operand.  Column tile of KC columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(128) void k_mm_a_bf16(const uint16_t* __restrict__ D,
+                                                   int64_t ldd, int64_t mpad,
+                                                   const uint16_t* __restrict__ Zt,
+                                                   float* __restrict__ Wtpart,
+                                                   int64_t KC) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * 128 + 64 * wave;
+  if (r0 >= mpad) return;
+  const int64_t c0 = (int64_t)blockIdx.x * KC;
+  const int64_t c1 = (c0 + KC) < ldd ? (c0 + KC) : ldd;
+  const int i = lane & 31, g = lane >> 5;
+  const uint16_t* pa0 = D + (r0 + i) * ldd + 32 * g;
+  const uint16_t* pa1 = D + (r0 + 32 + i) * ldd + 32 * g;
+  const uint16_t* pb = Zt + (int64_t)i * ldd + 32 * g;
+  f32x16 acc0 = {}, acc1 = {};
+  for (int64_t kk = c0; kk < c1; kk += 64) {
+    u32x4 a0[4], a1[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a0[s] = *reinterpret_cast<const u32x4*>(pa0 + kk + 8 * s);
+      a1[s] = *reinterpret_cast<const u32x4*>(pa1 + kk + 8 * s);
+      b[s] = *reinterpret_cast<const u32x4*>(pb + kk + 8 * s);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc0 = mfma_bf16(as_bf16x8(a0[s]), as_bf16x8(b[s]), acc0);
+      acc1 = mfma_bf16(as_bf16x8(a1[s]), as_bf16x8(b[s]), acc1);
+    }
+  }
+  float* out = Wtpart + ((int64_t)blockIdx.x * 32 + (lane & 31)) * mpad;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    out[r0 + acc_row(v, lane)] = acc0[v];
+    out[r0 + 32 + acc_row(v, lane)] = acc1[v];
+  }
+}
+
+__global__ __launch_bounds__(128) void k_mm_a_f32(const float* __restrict__ D, int64_t ldd,
+                                                  int64_t mpad, const float* __restrict__ Zt,
+                                                  float* __restrict__ Wtpart, int64_t KC) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * 128 + 64 * wave;
+  if (r0 >= mpad) return;
+  const int64_t c0 = (int64_t)blockIdx.x * KC;
+  const int64_t c1 = (c0 + KC) < ldd ? (c0 + KC) : ldd;
+  const int i = lane & 31, g = lane >> 5;
+  const float* pa0 = D + (r0 + i) * ldd + 8 * g;
+  const float* pa1 = D + (r0 + 32 + i) * ldd + 8 * g;
+  const float* pb = Zt + (int64_t)i * ldd + 8 * g;
+  f32x16 acc0 = {}, acc1 = {};
+  for (int64_t kk = c0; kk < c1; kk += 16) {
+    const float4 a0l = *reinterpret_cast<const float4*>(pa0 + kk);
+    const float4 a0h = *reinterpret_cast<const float4*>(pa0 + kk + 4);
+    const float4 a1l = *reinterpret_cast<const float4*>(pa1 + kk);
+    const float4 a1h = *reinterpret_cast<const float4*>(pa1 + kk + 4);
+    const float4 bl = *reinterpret_cast<const float4*>(pb + kk);
+    const float4 bh = *reinterpret_cast<const float4*>(pb + kk + 4);
+    const float a0[8] = {a0l.x, a0l.y, a0l.z, a0l.w, a0h.x, a0h.y, a0h.z, a0h.w};
+    const float a1[8] = {a1l.x, a1l.y, a1l.z, a1l.w, a1h.x, a1h.y, a1h.z, a1h.w};
+    const float b[8] = {bl.x, bl.y, bl.z, bl.w, bh.x, bh.y, bh.z, bh.w};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      acc0 = mfma_f32(a0[s], b[s], acc0);
+      acc1 = mfma_f32(a1[s], b[s], acc1);
+    }
+  }
+  float* out = Wtpart + ((int64_t)blockIdx.x * 32 + (lane & 31)) * mpad;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    out[r0 + acc_row(v, lane)] = acc0[v];
+    out[r0 + 32 + acc_row(v, lane)] = acc1[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_mm_b: Zpart[ch] (ldd x 32, row = column of D) = (W^T D[rows of ch, :])^T.
+// Block = 4 waves on the same 128-column strip [blockIdx.x*128, +128): lane n
+// holds columns 4n .. 4n+3 of the strip, one per 32-column MFMA tile, so a
+// wave reads each row as one contiguous run.  The waves split the rows of
+// the chunk into four ranges and add their tiles through LDS at the end.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_reduce_store(f32x16 (&acc)[4], float* lds, int wave,
+                                                   int lane, float* __restrict__ Zpart,
+                                                   int64_t row0) {
+  // waves 2,3 -> LDS; waves 0,1 add; wave 1 -> LDS; wave 0 adds and stores
+  float* mine = lds + (int64_t)(wave & 1) * 64 * 64;
+  if (wave >= 2) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mine[(t * 16 + v) * 64 + lane] = acc[t][v];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[t][v] += mine[(t * 16 + v) * 64 + lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) lds[(t * 16 + v) * 64 + lane] = acc[t][v];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int n = lane & 31;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float* out = Zpart + (row0 + 4 * n + t) * 32;
+#pragma unroll
+      for (int v = 0; v < 16; v += 4) {
+        const int i0 = acc_row(v, lane);
+        *reinterpret_cast<float4*>(out + i0) = make_float4(
+            acc[t][v] + lds[(t * 16 + v) * 64 + lane], acc[t][v + 1] + lds[(t * 16 + v + 1) * 64 + lane],
+            acc[t][v + 2] + lds[(t * 16 + v + 2) * 64 + lane], acc[t][v + 3] + lds[(t * 16 + v + 3) * 64 + lane]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mm_b_bf16(const uint16_t* __restrict__ D, int64_t ldd,
+                                                   int64_t mpad,
+                                                   const uint16_t* __restrict__ Wt,
+                                                   float* __restrict__ Zpart, int64_t RC) {
+  __shared__ float lds[2 * 64 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t cw = (int64_t)blockIdx.x * 128;
+  const int64_t kc0 = (int64_t)blockIdx.y * RC;
+  const int64_t kc1 = (kc0 + RC) < mpad ? (kc0 + RC) : mpad;
+  const int64_t q = ((kc1 - kc0) / 4 + 15) / 16 * 16;   // rows per wave, multiple of 16
+  const int64_t k0 = kc0 + q * wave;
+  const int64_t k1 = (k0 + q) < kc1 ? (k0 + q) : kc1;
+  const int n = lane & 31, g = lane >> 5;
+  const uint16_t* pd = D + (8 * g) * ldd + cw + 4 * n;
+  const uint16_t* pw = Wt + (int64_t)n * mpad + 8 * g;
+  f32x16 acc[4] = {};
+  for (int64_t kk = k0; kk < k1; kk += 16) {
+    // A: W^T[n][kk + 8g .. +7]
+    const u32x4 a = *reinterpret_cast<const u32x4*>(pw + kk);
+    // B: 8 rows (kk + 8g + s) x 4 columns
+    uint2 d[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) d[s] = *reinterpret_cast<const uint2*>(pd + (kk + s) * ldd);
+    // repack: tile t gets column 4n + t of the 8 rows (bf16 pairs)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      u32x4 b;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const uint32_t x0 = (t < 2) ? d[2 * h].x : d[2 * h].y;
+        const uint32_t x1 = (t < 2) ? d[2 * h + 1].x : d[2 * h + 1].y;
+        const uint32_t lo = (t & 1) ? (x0 >> 16) : (x0 & 0xffffu);
+        const uint32_t hi = (t & 1) ? (x1 >> 16) : (x1 & 0xffffu);
+        b[h] = lo | (hi << 16);
+      }
+      acc[t] = mfma_bf16(as_bf16x8(a), as_bf16x8(b), acc[t]);
+    }
+  }
+  block_reduce_store(acc, lds, wave, lane, Zpart, (int64_t)blockIdx.y * ldd + cw);
+}
+
+__global__ __launch_bounds__(256) void k_mm_b_f32(const float* __restrict__ D, int64_t ldd,
+                                                  int64_t mpad, const float* __restrict__ Wt,
+                                                  float* __restrict__ Zpart, int64_t RC) {
+  __shared__ float lds[2 * 64 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t cw = (int64_t)blockIdx.x * 128;
+  const int64_t kc0 = (int64_t)blockIdx.y * RC;
+  const int64_t kc1 = (kc0 + RC) < mpad ? (kc0 + RC) : mpad;
+  const int64_t q = ((kc1 - kc0) / 4 + 7) / 8 * 8;      // rows per wave, multiple of 8
+  const int64_t k0 = kc0 + q * wave;
+  const int64_t k1 = (k0 + q) < kc1 ? (k0 + q) : kc1;
+  const int n = lane & 31, g = lane >> 5;
+  const float* pd = D + (4 * g) * ldd + cw + 4 * n;
+  const float* pw = Wt + (int64_t)n * mpad + 4 * g;
+  f32x16 acc[4] = {};
+  for (int64_t kk = k0; kk < k1; kk += 8) {
+    // slot s pairs row kk + 4g + s on both operands
+    const float4 a = *reinterpret_cast<const float4*>(pw + kk);
+    const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float4 d = *reinterpret_cast<const float4*>(pd + (kk + s) * ldd);
+      acc[0] = mfma_f32(av[s], d.x, acc[0]);
+      acc[1] = mfma_f32(av[s], d.y, acc[1]);
+      acc[2] = mfma_f32(av[s], d.z, acc[2]);
+      acc[3] = mfma_f32(av[s], d.w, acc[3]);
+    }
+  }
+  block_reduce_store(acc, lds, wave, lane, Zpart, (int64_t)blockIdx.y * ldd + cw);
+}
+
+// ---------------------------------------------------------------------------
+// Panel conversions around the MFMA kernels.
+// ---------------------------------------------------------------------------
+// Zt (32 x ldd, bf16 or f32) <- Z (ldd x rp, f32), zero rows j >= rp.
+template <typename TT>
+__global__ __launch_bounds__(256) void k_to_t(const float* __restrict__ Z, int64_t rows, int rp,
+                                              TT* __restrict__ Zt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * 32) return;
+  const int64_t j = e / rows, c = e % rows;
+  const float v = (j < rp) ? Z[c * rp + j] : 0.f;
+  if constexpr (sizeof(TT) == 2)
+    Zt[e] = f32_to_bf16(v);
+  else
+    Zt[e] = v;
+}
+
+// Wt = sum_ct Wtpart[ct] (32 x mpad) -> TT (bf16 or f32) transposed panel,
+// and optionally row-major rows x rp f32 (for B' = D Y).
+template <typename TT>
+__global__ __launch_bounds__(256) void k_reduce_w(const float* __restrict__ Wtpart, int nct,
+                                                  int64_t mpad, int64_t m, int rp,
+                                                  TT* __restrict__ Wt, float* __restrict__ Wrow) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= 32 * mpad) return;
+  float s = 0.f;
+  for (int c = 0; c < nct; ++c) s += Wtpart[(int64_t)c * 32 * mpad + e];
+  if (Wt) {
+    if constexpr (sizeof(TT) == 2)
+      Wt[e] = f32_to_bf16(s);
+    else
+      Wt[e] = s;
+  }
+  if (Wrow) {
+    const int64_t j = e / mpad, i = e % mpad;
+    if (j < rp && i < m) Wrow[i * rp + j] = s;
+  }
+}
+
+// Zo (rows x rp, f32) = sum_ch Zpart[ch] (ldd x 32).
+__global__ __launch_bounds__(256) void k_reduce_z(const float* __restrict__ Zpart, int64_t nch,
+                                                  int64_t ldd, int rp, float* __restrict__ Zo) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ldd * rp) return;
+  const int64_t c = e / rp;
+  const int j = (int)(e % rp);
+  float s = 0.f;
+  for (int64_t h = 0; h < nch; ++h) s += Zpart[(h * ldd + c) * 32 + j];
+  Zo[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Host side: one Gram pass Zo = D^T (D Z) and the plain product W = D Y.
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(int64_t work) { return (unsigned)((work + 255) / 256); }
+
+void mfma_to_t(const Launch& L, bool bf16, const void* Z, int64_t ldd, int rp, void* Zt) {
+  if (bf16)
+    hipLaunchKernelGGL(k_to_t<uint16_t>, dim3(blocks_for(ldd * 32)), dim3(256), 0, L.stream,
+                       (const float*)Z, ldd, rp, (uint16_t*)Zt);
+  else
+    hipLaunchKernelGGL(k_to_t<float>, dim3(blocks_for(ldd * 32)), dim3(256), 0, L.stream,
+                       (const float*)Z, ldd, rp, (float*)Zt);
+}
+
+void mfma_mm_a(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
+               const void* Zt, float* Wtpart, int64_t KC) {
+  dim3 grid((unsigned)((ldd + KC - 1) / KC), (unsigned)((mpad + 127) / 128));
+  if (bf16)
+    hipLaunchKernelGGL(k_mm_a_bf16, grid, dim3(128), 0, L.stream, (const uint16_t*)D, ldd, mpad,
+                       (const uint16_t*)Zt, Wtpart, KC);
+  else
+    hipLaunchKernelGGL(k_mm_a_f32, grid, dim3(128), 0, L.stream, (const float*)D, ldd, mpad,
+                       (const float*)Zt, Wtpart, KC);
+}
+
+void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int64_t mpad,
+                   int64_t m, int rp, void* Wt, float* Wrow) {
+  const unsigned b = blocks_for(32 * mpad);
+  if (bf16)
+    hipLaunchKernelGGL(k_reduce_w<uint16_t>, dim3(b), dim3(256), 0, L.stream, Wtpart, nct, mpad,
+                       m, rp, (uint16_t*)Wt, Wrow);
+  else
+    hipLaunchKernelGGL(k_reduce_w<float>, dim3(b), dim3(256), 0, L.stream, Wtpart, nct, mpad, m,
+                       rp, (float*)Wt, Wrow);
+}
+
+void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
+               const void* Wt, float* Zpart, int64_t RC, int64_t nch) {
+  dim3 grid((unsigned)(ldd / 128), (unsigned)nch);
+  if (bf16)
+    hipLaunchKernelGGL(k_mm_b_bf16, grid, dim3(256), 0, L.stream, (const uint16_t*)D, ldd, mpad,
+                       (const uint16_t*)Wt, Zpart, RC);
+  else
+    hipLaunchKernelGGL(k_mm_b_f32, grid, dim3(256), 0, L.stream, (const float*)D, ldd, mpad,
+                       (const float*)Wt, Zpart, RC);
+}
+
+void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
+                   float* Zo) {
+  hipLaunchKernelGGL(k_reduce_z, dim3(blocks_for(ldd * rp)), dim3(256), 0, L.stream, Zpart, nch,
+                     ldd, rp, Zo);
+}
+
+}  // namespace godec

@@ -14,11 +14,13 @@
 #include "godec_internal.h"
 #include "k_common.h"
 
+#include <algorithm>
+
 namespace godec {
 
 template <typename T> struct KeyBits;
-template <> struct KeyBits<float> { static constexpr int value = 31; };
-template <> struct KeyBits<double> { static constexpr int value = 63; };
+template <> struct KeyBits<float> { static constexpr int value = 31; using key_t = uint32_t; };
+template <> struct KeyBits<double> { static constexpr int value = 63; using key_t = uint64_t; };
 
 __device__ __forceinline__ float key_to_val(unsigned long long k, float*) { return __uint_as_float((uint32_t)k); }
 __device__ __forceinline__ double key_to_val(unsigned long long k, double*) { return __longlong_as_double((long long)k); }
@@ -33,8 +35,11 @@ __device__ __forceinline__ T resid(T x, const T* __restrict__ u, const T (&v)[RP
   return x - s;
 }
 
-constexpr int kRowsPerTile = 32;
-constexpr int kCandBuf = 2048;
+constexpr int kRowsPerTile = 64;
+// per-wave candidate staging (entries), sized to keep the pass under 64 KB LDS
+template <typename T>
+constexpr int wave_buf() { return sizeof(T) == 8 ? 256 : 512; }
+constexpr int kHistRep = kHistReplicas;
 
 __device__ __forceinline__ int digit_bits(int pbits, int kbits) {
   if (pbits == 0) return kHistBits0;
@@ -42,134 +47,332 @@ __device__ __forceinline__ int digit_bits(int pbits, int kbits) {
   return rem < kHistBits ? rem : kHistBits;
 }
 
-// ---------------------------------------------------------------------------
-// Full-data pass.  Mode comes from the plan: pass_index == 0 is always the
-// level-0 histogram (plus sum R^2); later passes histogram the next digit
-// inside the bucket (SEL_HIST), collect every entry at or above the bucket
-// (SEL_COLLECT), or collect the entries strictly above the resolved
-// threshold (SEL_TIES).  Any other mode returns at once.
-// ---------------------------------------------------------------------------
 template <typename T, int RP>
-__global__ __launch_bounds__(256) void k_sel_pass(const T* __restrict__ X, int64_t ldx,
-                                                  const T* __restrict__ UL,
-                                                  const T* __restrict__ VL,
-                                                  int64_t m, int64_t n,
-                                                  SelPlan* __restrict__ plan,
-                                                  unsigned long long* __restrict__ hist,
-                                                  int64_t* __restrict__ cand_idx,
-                                                  T* __restrict__ cand_val,
-                                                  int pass_index) {
-  constexpr int KB = KeyBits<T>::value;
-  __shared__ unsigned int lh[kHistBins];
-  __shared__ T us[kRowsPerTile * RP];
-  __shared__ int64_t bidx[kCandBuf];
-  __shared__ T bval[kCandBuf];
-  __shared__ int bcount;
-  __shared__ unsigned long long gbase;
-  __shared__ double red[8];
+constexpr int sel_cpt() {
+  if (sizeof(T) == 8) return RP <= 8 ? 4 : (RP <= 16 ? 2 : 1);
+  return RP <= 24 ? 4 : 2;
+}
 
-  int mode = SEL_HIST;
-  unsigned long long prefix = 0;
-  int pbits = 0;
-  if (pass_index > 0) {
-    mode = plan->mode;
-    if (mode != SEL_HIST && mode != SEL_COLLECT && mode != SEL_TIES) return;
-    prefix = plan->prefix;
-    pbits = plan->pbits;
+// Candidate output of a collecting pass.  Block b owns the segment
+// [b * seg_cap, (b + 1) * seg_cap) of the candidate arrays and appends to it
+// through an LDS counter (one LDS atomic per wave and row, no global
+// atomics); entries beyond a full segment go to the spill region
+// [cap, 2 * cap) through the global counter plan->ncand.  Whenever the total
+// fits in cap, every entry is kept.  The block publishes its segment fill in
+// seg_count[b] at the end of the pass.
+template <typename T>
+struct SegSink {
+  int64_t* idx;             // candidate arrays (2 * cap entries)
+  T* val;
+  T* xv;
+  unsigned int* cnt;        // LDS fill counter of the block
+  long long base;           // first entry of the block's segment
+  unsigned int cap;         // segment capacity
+  unsigned long long* sp_cnt;  // spill fill counter
+  long long sp_cap;         // spill capacity (= cap; the spill starts at cap)
+};
+
+// Called by every lane of the wave (uniform control flow); lanes with
+// `take` append (idx, r, x).  Positions follow lane order within the wave.
+template <typename T>
+__device__ __forceinline__ void seg_push(const SegSink<T>& s, bool take, int64_t idx, T r, T x) {
+  const unsigned long long mask = __ballot(take);
+  if (mask == 0ull) return;
+  const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
+  const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned int b = 0u;
+  if (rank == 0u && take) b = atomicAdd(s.cnt, (unsigned int)__popcll(mask));
+  b = (unsigned int)__builtin_amdgcn_readlane((int)b, leader);
+  if (!take) return;
+  const unsigned int p = b + rank;
+  long long pos;
+  if (p < s.cap) {
+    pos = s.base + p;
+  } else {
+    const unsigned long long q = atomicAdd(s.sp_cnt, 1ull);
+    pos = (long long)q < s.sp_cap ? s.sp_cap + (long long)q : -1;
   }
-  const int dbits = digit_bits(pbits, KB);
-  const bool do_hist = (mode == SEL_HIST);
-  const bool do_coll = (mode == SEL_COLLECT || mode == SEL_TIES);
-  const int tid = threadIdx.x;
-  if (do_hist)
-    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
-  if (tid == 0) bcount = 0;
-  __syncthreads();
+  if (pos >= 0) {
+    s.idx[pos] = idx;
+    s.val[pos] = r;
+    s.xv[pos] = x;
+  }
+}
 
-  const int64_t ctiles = (n + 255) / 256;
+// Range of candidate segment sg (sg == nseg is the spill region).
+__device__ __forceinline__ void seg_range(const SelPlan* plan, const unsigned int* seg_count,
+                                          int sg, long long& base, long long& cnt) {
+  const int nseg = plan->nseg;
+  const long long cap = plan->cap;
+  if (sg < nseg) {
+    base = (long long)sg * (cap / nseg);
+    cnt = (long long)seg_count[sg];
+  } else {
+    base = cap;
+    cnt = plan->ncand < cap ? plan->ncand : cap;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Full-data pass.  A block handles tiles of kRowsPerTile rows x 256*CPT
+// columns; each thread owns CPT consecutive columns (their V_L rows live in
+// registers, read from V_L^T with coalesced loads) and reads the U_L row
+// from LDS as a broadcast.  What a pass does with each residual key is set
+// by three switches, resolved outside the row loop:
+//   HIST  histogram (key >> shift) & mask over the keys in [klo, klo + kspan)
+//   TAKE  append every key >= kmin (kmin >= 1, so zeros are never taken)
+//   S2    sum R^2 over all entries
+// Uses: level-0 histogram (HIST over every key, with S2, in pass 0), deeper
+// digits (HIST inside the bucket), collection (TAKE from the bucket low
+// key, or from the threshold key + 1 when ties are resolved by index), and
+// the carried-window pass 0 (HIST + TAKE + S2 over the window).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PassKeys {
+  typename KeyBits<T>::key_t klo, kspan, kmin, mask;
+  int shift;
+};
+
+template <typename T, int RP, int CPT, bool HIST, bool TAKE, bool S2, bool FULL, bool VEC>
+__device__ __forceinline__ void sel_tile(const T* __restrict__ X, int64_t ldx, int64_t n,
+                                         int64_t i0, int nr, int64_t j0, const T* us,
+                                         const T (&v)[CPT][RP], unsigned int* lh,
+                                         const PassKeys<T>& pk, const SegSink<T>& sink,
+                                         double& s2) {
+  using K = typename KeyBits<T>::key_t;
+  // rows whose X loads are in flight together (fewer when collecting, to
+  // leave registers for the append)
+  constexpr int G = TAKE ? 2 : 4;
+  T xa[G][CPT], xb[G][CPT];
+  auto load_group = [&](T (&xx)[G][CPT], int gi) {
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+      const int64_t i = i0 + gi + a;
+      const bool rok = gi + a < nr;
+      if constexpr (VEC && CPT == 4 && sizeof(T) == 4) {
+        if (rok) {
+          const float4 q = *reinterpret_cast<const float4*>(X + i * ldx + j0);
+          xx[a][0] = q.x; xx[a][1] = q.y; xx[a][2] = q.z; xx[a][3] = q.w;
+        } else {
+#pragma unroll
+          for (int t = 0; t < CPT; ++t) xx[a][t] = T(0);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+          xx[a][t] = (rok && (FULL || j0 + t < n)) ? X[i * ldx + j0 + t] : T(0);
+      }
+    }
+  };
+  load_group(xa, 0);
+  for (int gi = 0; gi < nr; gi += G) {
+    if (gi + G < nr) load_group(xb, gi + G);
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+      const int ii = gi + a;
+      const bool rok = ii < nr;
+      T u[RP];
+#pragma unroll
+      for (int c = 0; c < RP; ++c) u[c] = us[(rok ? ii : 0) * RP + c];
+#pragma unroll
+      for (int t = 0; t < CPT; ++t) {
+        const bool ok = rok && (FULL || j0 + t < n);
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < RP; ++c) acc = fma_t(u[c], v[t][c], acc);
+        const T r = xa[a][t] - acc;
+        const K key = (K)abs_key(r);
+        if constexpr (S2) {
+          if (ok) s2 += (double)r * (double)r;
+        }
+        if constexpr (HIST) {
+          if (ok && (K)(key - pk.klo) < pk.kspan) atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+        }
+        if constexpr (TAKE) seg_push(sink, ok && key >= pk.kmin, (i0 + ii) * n + j0 + t, r, xa[a][t]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+      for (int t = 0; t < CPT; ++t) xa[a][t] = xb[a][t];
+  }
+}
+
+template <typename T, int RP, bool HIST, bool TAKE, bool S2>
+__device__ __forceinline__ void sel_pass_body(const T* __restrict__ X, int64_t ldx,
+                                              const T* __restrict__ UL,
+                                              const T* __restrict__ VLt, int64_t ldv,
+                                              int64_t m, int64_t n, unsigned int* lh, T* us,
+                                              const PassKeys<T>& pk, const SegSink<T>& sink,
+                                              bool vec_ok, double& s2) {
+  constexpr int CPT = sel_cpt<T, RP>();
+  constexpr int TW = 256 * CPT;
+  const int tid = threadIdx.x;
+  const int64_t ctiles = (n + TW - 1) / TW;
   const int64_t rtiles = (m + kRowsPerTile - 1) / kRowsPerTile;
   const int64_t ntiles = ctiles * rtiles;
-  double s2 = 0.0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t ct = tile % ctiles, rt = tile / ctiles;
-    const int64_t j = ct * 256 + tid;
+    const int64_t j0 = ct * TW + (int64_t)tid * CPT;
     const int64_t i0 = rt * kRowsPerTile;
     const int nr = (m - i0) < kRowsPerTile ? (int)(m - i0) : kRowsPerTile;
     __syncthreads();
     for (int e = tid; e < kRowsPerTile * RP; e += 256)
       us[e] = (e < nr * RP) ? UL[i0 * RP + e] : T(0);
     __syncthreads();
-    T v[RP];
+    // V_L^T (RP x ldv): lanes read consecutive columns of each row
+    T v[CPT][RP];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) v[c] = (j < n) ? VL[j * RP + c] : T(0);
-    for (int ii = 0; ii < nr; ++ii) {
-      if (do_coll && (ii & 3) == 0) {
-        // flush the block buffer when another 4 rows could overflow it; the
-        // count is read between two barriers so every thread sees the same
-        // value and takes the same branch
-        __syncthreads();
-        const int bc = bcount;
-        __syncthreads();
-        if (bc > kCandBuf - 4 * 256) {
-          if (tid == 0) {
-            gbase = atomicAdd((unsigned long long*)&plan->ncand, (unsigned long long)bcount);
-          }
-          __syncthreads();
-          const long long cap = plan->cap;
-          for (int e = tid; e < bcount; e += 256) {
-            const long long pos = (long long)gbase + e;
-            if (pos < cap) { cand_idx[pos] = bidx[e]; cand_val[pos] = bval[e]; }
-          }
-          __syncthreads();
-          if (tid == 0) bcount = 0;
-          __syncthreads();
-        }
-      }
-      if (j >= n) continue;
-      const int64_t i = i0 + ii;
-      const T r = resid<T, RP>(X[i * ldx + j], us + ii * RP, v);
-      const unsigned long long key = abs_key(r);
-      if (pass_index == 0) {
-        s2 += (double)r * (double)r;
-        atomicAdd(&lh[key >> (KB - kHistBits0)], 1u);
-      } else if (do_hist) {
-        if ((key >> (KB - pbits)) == prefix)
-          atomicAdd(&lh[(key >> (KB - pbits - dbits)) & ((1ull << dbits) - 1)], 1u);
-      } else {
-        bool take;
-        if (mode == SEL_COLLECT)
-          take = key > 0 && (key >> (KB - pbits)) >= prefix;
-        else
-          take = key > prefix;   // SEL_TIES: prefix holds the full threshold key
-        if (take) {
-          const int slot = atomicAdd(&bcount, 1);
-          bidx[slot] = i * n + j;
-          bval[slot] = r;
-        }
-      }
-    }
+    for (int c = 0; c < RP; ++c)
+#pragma unroll
+      for (int t = 0; t < CPT; ++t) v[t][c] = (j0 + t < n) ? VLt[c * ldv + j0 + t] : T(0);
+    const bool full = (ct + 1) * TW <= n;   // block-uniform
+    if (full && vec_ok)
+      sel_tile<T, RP, CPT, HIST, TAKE, S2, true, true>(X, ldx, n, i0, nr, j0, us, v, lh, pk,
+                                                       sink, s2);
+    else if (full)
+      sel_tile<T, RP, CPT, HIST, TAKE, S2, true, false>(X, ldx, n, i0, nr, j0, us, v, lh, pk,
+                                                        sink, s2);
+    else
+      sel_tile<T, RP, CPT, HIST, TAKE, S2, false, false>(X, ldx, n, i0, nr, j0, us, v, lh, pk,
+                                                         sink, s2);
   }
+}
+
+// Key switches of the level-0 histogram over every key.
+template <typename T>
+__device__ __forceinline__ PassKeys<T> keys_level0() {
+  using K = typename KeyBits<T>::key_t;
+  constexpr int KB = KeyBits<T>::value;
+  PassKeys<T> pk;
+  pk.klo = 0;
+  pk.kspan = (K)(K(1) << KB);
+  pk.kmin = 1;
+  pk.shift = KB - kHistBits0;
+  pk.mask = (K)(kHistBins - 1);
+  return pk;
+}
+
+// Common prologue of the two full-pass kernels.
+#define GODEC_SEL_SHARED                                                      \
+  constexpr int KB = KeyBits<T>::value;                                       \
+  using K = typename KeyBits<T>::key_t;                                       \
+  __shared__ unsigned int lh[kHistBins];                                      \
+  __shared__ T us[kRowsPerTile * RP];                                         \
+  __shared__ unsigned int scount;                                             \
+  __shared__ double red[4];                                                   \
+  const int tid = threadIdx.x;                                                \
+  const int lane = tid & 63, wave = tid >> 6;                                 \
+  (void)KB; (void)lane; (void)wave; (void)red;                                \
+  const long long ccap = plan->cap;                                           \
+  const unsigned int seg_cap = (unsigned int)(ccap / gridDim.x);              \
+  const int64_t sbase = (int64_t)blockIdx.x * seg_cap;                        \
+  const SegSink<T> sink{cand_idx, cand_val, cand_x, &scount, sbase, seg_cap,  \
+                        (unsigned long long*)&plan->ncand, ccap};
+
+// Closing of a collecting pass: publish the block's segment fill.
+#define GODEC_SEL_SEG_CLOSE                                    \
+  if (tid == 0) {                                              \
+    const unsigned int c = scount;                             \
+    seg_count[blockIdx.x] = c < seg_cap ? c : seg_cap;         \
+  }
+
+// Pass 0: the carried-window pass (steady state) or the full level-0
+// histogram (first iteration); both also sum R^2.
+template <typename T, int RP>
+__global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int64_t ldx,
+                                                   const T* __restrict__ UL,
+                                                   const T* __restrict__ VLt, int64_t ldv,
+                                                   int64_t m, int64_t n,
+                                                   SelPlan* __restrict__ plan,
+                                                   unsigned long long* __restrict__ hist,
+                                                   int64_t* __restrict__ cand_idx,
+                                                   T* __restrict__ cand_val,
+                                                   T* __restrict__ cand_x,
+                                                   unsigned int* __restrict__ seg_count) {
+  if (plan->mode != SEL_HIST) return;   // k == 0
+  GODEC_SEL_SHARED
+  const int carry = plan->carry_used;
+  PassKeys<T> pk = keys_level0<T>();
+  if (carry) {
+    // histogram and collect the window [dlo-th level-0 digit, top)
+    const K lo = (K)plan->carry_dlo << (KB - kHistBits0);
+    pk.klo = lo > 0 ? lo : K(1);
+    pk.kspan = (K)((K(1) << KB) - pk.klo);
+    pk.kmin = pk.klo;
+  }
+  for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
+  if (tid == 0) scount = 0u;
+  const bool vec_ok = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
   __syncthreads();
-  if (do_coll && bcount > 0) {
-    if (tid == 0)
-      gbase = atomicAdd((unsigned long long*)&plan->ncand, (unsigned long long)bcount);
-    __syncthreads();
-    const long long cap = plan->cap;
-    for (int e = tid; e < bcount; e += 256) {
-      const long long pos = (long long)gbase + e;
-      if (pos < cap) { cand_idx[pos] = bidx[e]; cand_val[pos] = bval[e]; }
-    }
+  double s2 = 0.0;
+  if (carry)
+    sel_pass_body<T, RP, true, true, true>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
+                                           vec_ok, s2);
+  else
+    sel_pass_body<T, RP, true, false, true>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
+                                            vec_ok, s2);
+  __syncthreads();
+  if (carry) { GODEC_SEL_SEG_CLOSE }
+  unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
+  for (int e = tid; e < kHistBins; e += 256)
+    if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
+  s2 = wave_sum(s2);
+  if (lane == 0) red[wave] = s2;
+  __syncthreads();
+  if (tid == 0) atomicAdd(&plan->sum_r2, red[0] + red[1] + red[2] + red[3]);
+}
+
+// Later passes (first iteration and fall-backs): the level-0 histogram
+// again (after a missed carry), deeper digits, collection from the bucket,
+// or collection above a resolved threshold whose ties overflow the buffer.
+template <typename T, int RP>
+__global__ __launch_bounds__(256) void k_sel_passN(const T* __restrict__ X, int64_t ldx,
+                                                   const T* __restrict__ UL,
+                                                   const T* __restrict__ VLt, int64_t ldv,
+                                                   int64_t m, int64_t n,
+                                                   SelPlan* __restrict__ plan,
+                                                   unsigned long long* __restrict__ hist,
+                                                   int64_t* __restrict__ cand_idx,
+                                                   T* __restrict__ cand_val,
+                                                   T* __restrict__ cand_x,
+                                                   unsigned int* __restrict__ seg_count) {
+  const int mode = plan->mode;
+  if (mode != SEL_HIST && mode != SEL_COLLECT && mode != SEL_TIES) return;
+  GODEC_SEL_SHARED
+  const unsigned long long prefix = plan->prefix;
+  const int pbits = plan->pbits;
+  const int dbits = digit_bits(pbits, KB);
+  const bool do_hist = (mode == SEL_HIST);
+  PassKeys<T> pk = keys_level0<T>();
+  if (pbits > 0) {
+    pk.klo = (K)(prefix << (KB - pbits));
+    pk.kspan = (K)(K(1) << (KB - pbits));
+    pk.shift = KB - pbits - dbits;
+    pk.mask = (K)((K(1) << dbits) - 1);
+    pk.kmin = pk.klo > 0 ? pk.klo : K(1);
   }
+  if (mode == SEL_TIES) pk.kmin = (K)prefix + 1;   // prefix is the full threshold key
+  if (do_hist)
+    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
+  if (tid == 0) scount = 0u;
+  const bool vec_ok = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
+  __syncthreads();
+  double s2 = 0.0;
+  if (do_hist)
+    sel_pass_body<T, RP, true, false, false>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
+                                             vec_ok, s2);
+  else
+    sel_pass_body<T, RP, false, true, false>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
+                                             vec_ok, s2);
+  __syncthreads();
+  if (!do_hist) { GODEC_SEL_SEG_CLOSE }
   if (do_hist) {
     const int bins = 1 << dbits;
+    unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
     for (int e = tid; e < bins; e += 256)
-      if (lh[e]) atomicAdd(&hist[e], (unsigned long long)lh[e]);
-  }
-  if (pass_index == 0) {
-    s2 = wave_sum(s2);
-    if ((tid & 63) == 0) red[tid >> 6] = s2;
-    __syncthreads();
-    if (tid == 0) atomicAdd(&plan->sum_r2, red[0] + red[1] + red[2] + red[3]);
+      if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
   }
 }
 
@@ -177,6 +380,7 @@ __global__ __launch_bounds__(256) void k_sel_pass(const T* __restrict__ X, int64
 template <typename T>
 __global__ __launch_bounds__(256) void k_cand_hist(SelPlan* __restrict__ plan,
                                                    const T* __restrict__ cand_val,
+                                                   const unsigned int* __restrict__ seg_count,
                                                    unsigned long long* __restrict__ hist) {
   constexpr int KB = KeyBits<T>::value;
   __shared__ unsigned int lh[kHistBins];
@@ -184,36 +388,43 @@ __global__ __launch_bounds__(256) void k_cand_hist(SelPlan* __restrict__ plan,
   const unsigned long long prefix = plan->prefix;
   const int pbits = plan->pbits;
   const int dbits = digit_bits(pbits, KB);
-  const long long nc = plan->ncand < plan->cap ? plan->ncand : plan->cap;
   for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
   __syncthreads();
-  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < nc;
-       c += (long long)gridDim.x * 256) {
-    const unsigned long long key = abs_key(cand_val[c]);
-    if ((key >> (KB - pbits)) == prefix)
-      atomicAdd(&lh[(key >> (KB - pbits - dbits)) & ((1ull << dbits) - 1)], 1u);
+  for (int sg = blockIdx.x; sg <= plan->nseg; sg += gridDim.x) {
+    long long base, cnt;
+    seg_range(plan, seg_count, sg, base, cnt);
+    for (long long c = base + threadIdx.x; c < base + cnt; c += 256) {
+      const unsigned long long key = abs_key(cand_val[c]);
+      if ((key >> (KB - pbits)) == prefix)
+        atomicAdd(&lh[(key >> (KB - pbits - dbits)) & ((1ull << dbits) - 1)], 1u);
+    }
   }
   __syncthreads();
+  unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
   for (int e = threadIdx.x; e < (1 << dbits); e += 256)
-    if (lh[e]) atomicAdd(&hist[e], (unsigned long long)lh[e]);
+    if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
 }
 
 // Advance the plan.  One block.  stage 0 follows a full-data pass (which
 // histogrammed in SEL_HIST or collected in SEL_COLLECT); stage 1 follows a
 // candidate histogram (SEL_REFINE).  In any other combination the preceding
-// kernel did nothing and neither does this one.
+// kernel did nothing and neither does this one.  The digit holding the
+// k_rem-th largest key is found with a block-wide suffix scan.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
                                                   unsigned long long* __restrict__ hist,
                                                   int stage) {
   constexpr int KB = KeyBits<T>::value;
+  __shared__ unsigned long long h[kHistBins];
   __shared__ unsigned long long part[256];
+  __shared__ int sel_t;
   const int tid = threadIdx.x;
   const int mode = plan->mode;
-  if (stage == 0 && mode == SEL_COLLECT) {
+  if (stage == 0 && (mode == SEL_COLLECT || mode == SEL_TIES)) {
     if (tid == 0) {
       if (plan->ncand > plan->cap) plan->overflow = 1;
-      plan->mode = (plan->pbits == KB) ? SEL_FINAL : SEL_REFINE;
+      if (mode == SEL_TIES) plan->mode = SEL_TSCAN;
+      else plan->mode = (plan->pbits == KB) ? SEL_FINAL : SEL_REFINE;
     }
     return;
   }
@@ -222,41 +433,80 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
   const int dbits = digit_bits(pbits, KB);
   const int bins = 1 << dbits;
   const int per = (bins + 255) / 256;
-  // thread t owns the digits [bins - (t+1)*per, bins - t*per): top first
+  // sum the replicas (and clear them for the next histogram)
+  for (int e = tid; e < bins; e += 256) {
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int r = 0; r < kHistRep; ++r) {
+      acc += hist[r * kHistBins + e];
+      hist[r * kHistBins + e] = 0ull;
+    }
+    h[e] = acc;
+  }
+  __syncthreads();
+  // thread t owns digits [bins - (t+1)*per, bins - t*per): top digits first
   unsigned long long s = 0;
   for (int u = 0; u < per; ++u) {
     const int d = bins - 1 - (tid * per + u);
-    if (d >= 0) s += hist[d];
+    if (d >= 0) s += h[d];
   }
   part[tid] = s;
+  if (tid == 0) sel_t = -1;
+  __syncthreads();
+  // inclusive scan of part[] (Hillis-Steele)
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned long long add = tid >= off ? part[tid - off] : 0ull;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  const long long k_rem = plan->k_rem;
+  const unsigned long long before = tid > 0 ? part[tid - 1] : 0ull;
+  if (before < (unsigned long long)k_rem && part[tid] >= (unsigned long long)k_rem) sel_t = tid;
   __syncthreads();
   if (tid == 0) {
-    const long long k_rem = plan->k_rem;
-    unsigned long long cum = 0;
     int dsel = -1;
-    for (int t = 0; t < 256 && dsel < 0; ++t) {
-      if (cum + part[t] >= (unsigned long long)k_rem) {
-        for (int u = 0; u < per; ++u) {
-          const int d = bins - 1 - (t * per + u);
-          if (d < 0) break;
-          if (cum + hist[d] >= (unsigned long long)k_rem) { dsel = d; break; }
-          cum += hist[d];
-        }
-      } else {
-        cum += part[t];
+    unsigned long long cum = 0;
+    if (sel_t >= 0) {
+      cum = sel_t > 0 ? part[sel_t - 1] : 0ull;
+      for (int u = 0; u < per; ++u) {
+        const int d = bins - 1 - (sel_t * per + u);
+        if (d < 0) break;
+        if (cum + h[d] >= (unsigned long long)k_rem) { dsel = d; break; }
+        cum += h[d];
       }
+    }
+    if (stage == 0 && pbits == 0 && plan->carry_used == 1) {
+      // pass 0 histogrammed and collected only digits >= carry_dlo: accept
+      // when the k-th key lies there and every candidate was kept;
+      // otherwise fall back to the full level-0 histogram in the next pass
+      if (dsel < 0 || plan->ncand > plan->cap) {
+        plan->carry_used = 0;
+        plan->ncand = 0;
+        plan->slow = 1;
+        plan->mode = SEL_HIST;   // prefix 0, pbits 0, k_rem = k unchanged
+        return;
+      }
+      plan->carry_used = 2;
+      plan->count_above += (long long)cum;
+      plan->k_rem = k_rem - (long long)cum;
+      plan->prefix = (unsigned long long)dsel;
+      plan->pbits = dbits;
+      plan->bucket_count = (long long)h[dsel];
+      plan->mode = (plan->pbits == KB) ? SEL_FINAL : SEL_REFINE;
+      return;
     }
     if (dsel < 0) {
       // fewer keys than k_rem in the bucket: only when the remaining keys
       // are zeros (excluded from the candidates); settle on digit 0
       dsel = 0;
-      cum -= hist[0];
+      cum = part[255] - h[0];
     }
     plan->count_above += (long long)cum;
     plan->k_rem = k_rem - (long long)cum;
     plan->prefix = (plan->prefix << dbits) | (unsigned long long)dsel;
     plan->pbits = pbits + dbits;
-    plan->bucket_count = (long long)hist[dsel];
+    plan->bucket_count = (long long)h[dsel];
     int next;
     if (mode == SEL_HIST) {
       if (plan->count_above + plan->bucket_count <= plan->cap) {
@@ -275,57 +525,118 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
     }
     plan->mode = next;
   }
-  __syncthreads();
-  for (int e = tid; e < bins; e += 256) hist[e] = 0ull;
 }
 
 // FINAL: write S from the candidates.  Entries above the threshold key go
-// straight to S; entries equal to it go to the tie list.
+// straight to S; entries equal to it go to the tie list.  A block takes one
+// candidate segment at a time: it counts its entries, reserves its output
+// range with one atomic per list, then writes in order (ballots + a scan
+// over the four waves).
 template <typename T>
 __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
                                                      const int64_t* __restrict__ cand_idx,
                                                      const T* __restrict__ cand_val,
+                                                     const T* __restrict__ cand_x,
+                                                     const unsigned int* __restrict__ seg_count,
                                                      int64_t* __restrict__ s_idx,
                                                      T* __restrict__ s_val,
+                                                     T* __restrict__ s_x,
                                                      int64_t* __restrict__ tie_idx,
                                                      unsigned long long* __restrict__ counters) {
   __shared__ double red[4];
+  __shared__ unsigned int wa[4], wt[4];
+  __shared__ unsigned long long base_a, base_t;
   if (plan->mode != SEL_FINAL) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long tkey = plan->prefix;
-  const long long nc = plan->ncand < plan->cap ? plan->ncand : plan->cap;
   const unsigned long long kcap = (unsigned long long)(plan->count_above + plan->k_rem);
+  const unsigned long long tcap = (unsigned long long)plan->cap;
+  const unsigned long long below = (1ull << lane) - 1ull;
   double s2 = 0.0;
-  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < nc;
-       c += (long long)gridDim.x * 256) {
-    const T v = cand_val[c];
-    const unsigned long long key = abs_key(v);
-    if (key > tkey) {
-      const unsigned long long pos = atomicAdd(&counters[0], 1ull);
-      if (pos < kcap) {
-        s_idx[pos] = cand_idx[c];
-        s_val[pos] = v;
-        s2 += (double)v * (double)v;
+  for (int sg = blockIdx.x; sg <= plan->nseg; sg += gridDim.x) {
+    long long c0, cnt;
+    seg_range(plan, seg_count, sg, c0, cnt);
+    const long long c1 = c0 + cnt;
+    // phase 1: counts
+    unsigned int na = 0, nt = 0;
+    for (long long c = c0 + tid; c < c1; c += 256) {
+      const unsigned long long key = abs_key(cand_val[c]);
+      na += key > tkey;
+      nt += (key == tkey && tkey > 0);
+    }
+    na = wave_sum(na);
+    nt = wave_sum(nt);
+    __syncthreads();
+    if (lane == 0) { wa[wave] = na; wt[wave] = nt; }
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned int ta = wa[0] + wa[1] + wa[2] + wa[3];
+      const unsigned int tt = wt[0] + wt[1] + wt[2] + wt[3];
+      base_a = ta ? atomicAdd(&counters[0], (unsigned long long)ta) : 0ull;
+      base_t = tt ? atomicAdd(&counters[1], (unsigned long long)tt) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long ba = base_a, bt = base_t;
+    // phase 2: ordered writes, 256 candidates per step
+    for (long long cb = c0; cb < c1; cb += 256) {
+      const long long c = cb + tid;
+      const bool valid = c < c1;
+      const T v = valid ? cand_val[c] : T(0);
+      const unsigned long long key = abs_key(v);
+      const bool above = valid && key > tkey;
+      const bool tie = valid && key == tkey && tkey > 0;
+      const unsigned long long ma = __ballot(above), mt = __ballot(tie);
+      __syncthreads();
+      if (lane == 0) { wa[wave] = (unsigned)__popcll(ma); wt[wave] = (unsigned)__popcll(mt); }
+      __syncthreads();
+      unsigned int oa = 0, ot = 0;
+      for (int w = 0; w < wave; ++w) { oa += wa[w]; ot += wt[w]; }
+      if (above) {
+        const unsigned long long pos = ba + oa + __popcll(ma & below);
+        if (pos < kcap) {
+          s_idx[pos] = cand_idx[c];
+          s_val[pos] = v;
+          s_x[pos] = cand_x[c];
+          s2 += (double)v * (double)v;
+        }
       }
-    } else if (key == tkey && tkey > 0) {
-      const unsigned long long pos = atomicAdd(&counters[1], 1ull);
-      if (pos < (unsigned long long)plan->cap) tie_idx[pos] = cand_idx[c];
+      if (tie) {
+        const unsigned long long pos = bt + ot + __popcll(mt & below);
+        if (pos < tcap) tie_idx[pos] = cand_idx[c];
+      }
+      ba += wa[0] + wa[1] + wa[2] + wa[3];
+      bt += wt[0] + wt[1] + wt[2] + wt[3];
     }
   }
   s2 = wave_sum(s2);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(&plan->sum_sel2, red[0] + red[1] + red[2] + red[3]);
+  if (lane == 0) red[wave] = s2;
+  __syncthreads();
+  if (tid == 0) atomicAdd(&plan->sum_sel2, red[0] + red[1] + red[2] + red[3]);
 }
 
 // Resolve ties: keep the k_rem smallest linear indices among the entries
 // equal to the threshold key (one block; bitonic sort in LDS when they fit,
 // otherwise repeated minimum extraction by a radix select on the index).
+// The next iteration histograms and collects from kCarryWindow level-0
+// digits below this threshold (1/8 octave for f32 keys, which have 16 digits
+// per octave; 1 octave for f64 keys).
+template <typename T>
+__device__ __forceinline__ void carry_update(SelCarry* carry, unsigned long long tkey) {
+  constexpr int KB = KeyBits<T>::value;
+  constexpr int W = sizeof(T) == 4 ? 2 : 2;
+  const int d = (int)(tkey >> (KB - kHistBits0)) - W;
+  carry->dlo = d > 0 ? d : 0;
+  carry->valid = 1;
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_sel_ties(SelPlan* __restrict__ plan,
                                                    int64_t* __restrict__ s_idx,
                                                    T* __restrict__ s_val,
                                                    int64_t* __restrict__ tie_idx,
-                                                   unsigned long long* __restrict__ counters) {
+                                                   unsigned long long* __restrict__ counters,
+                                                   SelCarry* __restrict__ carry) {
   constexpr int KB = KeyBits<T>::value;
   constexpr int NS = 4096;
   __shared__ int64_t sk[NS];
@@ -411,12 +722,13 @@ __global__ __launch_bounds__(1024) void k_sel_ties(SelPlan* __restrict__ plan,
     plan->nnz = nabove + take;
     plan->threshold = (double)tval;
     plan->sum_sel2 += (double)take * (double)tval * (double)tval;
+    carry_update<T>(carry, tkey);
   }
-  (void)KB;
 }
 
-// TIES mode: candidates hold the entries above the threshold; the tied
-// entries are taken in index order by one block scanning all of X.
+// After a TIES collection the candidates hold the entries above the
+// threshold; the tied entries are taken in index order by one block
+// scanning all of X.
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X, int64_t ldx,
                                                          const T* __restrict__ UL,
@@ -425,21 +737,36 @@ __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X
                                                          SelPlan* __restrict__ plan,
                                                          const int64_t* __restrict__ cand_idx,
                                                          const T* __restrict__ cand_val,
+                                                         const T* __restrict__ cand_x,
+                                                         const unsigned int* __restrict__ seg_count,
                                                          int64_t* __restrict__ s_idx,
-                                                         T* __restrict__ s_val) {
+                                                         T* __restrict__ s_val,
+                                                         T* __restrict__ s_x,
+                                                         SelCarry* __restrict__ carry) {
   __shared__ T us[RP];
   __shared__ long long taken;
   __shared__ int flags[256];
-  if (plan->mode != SEL_TIES) return;
+  if (plan->mode != SEL_TSCAN) return;
   const int tid = threadIdx.x;
   const unsigned long long tkey = plan->prefix;
-  long long nabove = plan->ncand < plan->cap ? plan->ncand : plan->cap;
-  if (nabove > plan->count_above) nabove = plan->count_above;
+  // the candidates are exactly the entries above the threshold
+  // (count_above of them, all kept since count_above <= cap)
+  const long long nabove = plan->count_above;
   double s2 = 0.0;
-  for (long long c = tid; c < nabove; c += 256) {
-    s_idx[c] = cand_idx[c];
-    s_val[c] = cand_val[c];
-    s2 += (double)cand_val[c] * (double)cand_val[c];
+  long long out = 0;
+  for (int sg = 0; sg <= plan->nseg; ++sg) {
+    long long base, cnt;
+    seg_range(plan, seg_count, sg, base, cnt);
+    for (long long e = tid; e < cnt; e += 256) {
+      const long long c = base + e;
+      if (out + e < nabove) {
+        s_idx[out + e] = cand_idx[c];
+        s_val[out + e] = cand_val[c];
+        s_x[out + e] = cand_x[c];
+        s2 += (double)cand_val[c] * (double)cand_val[c];
+      }
+    }
+    out += cnt;
   }
   const long long need = (tkey > 0) ? plan->k_rem : 0;
   if (tid == 0) taken = 0;
@@ -479,6 +806,7 @@ __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X
     plan->threshold = (double)tval;
     plan->sum_sel2 = red[0] + red[1] + red[2] + red[3] + (double)taken * (double)tval * (double)tval;
     plan->mode = SEL_DONE;
+    carry_update<T>(carry, tkey);
   }
 }
 
@@ -491,7 +819,8 @@ __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X,
                                                         const SelPlan* __restrict__ plan,
                                                         const unsigned long long* __restrict__ counters,
                                                         int64_t* __restrict__ s_idx,
-                                                        T* __restrict__ s_val) {
+                                                        T* __restrict__ s_val,
+                                                        T* __restrict__ s_x) {
   const long long start = (long long)counters[0];
   const long long nnz = plan->nnz;
   for (long long e = start + (long long)blockIdx.x * 256 + threadIdx.x; e < nnz;
@@ -502,22 +831,41 @@ __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X,
     T u[RP], v[RP];
 #pragma unroll
     for (int c = 0; c < RP; ++c) { u[c] = UL[i * RP + c]; v[c] = VL[j * RP + c]; }
-    s_val[e] = resid<T, RP>(X[i * ldx + j], u, v);
+    const T x = X[i * ldx + j];
+    s_val[e] = resid<T, RP>(x, u, v);
+    s_x[e] = x;
   }
 }
 
 template <typename T>
 __global__ void k_sel_reset(SelPlan* plan, unsigned long long* hist,
-                            unsigned long long* counters, long long k, long long cap) {
+                            unsigned long long* counters, unsigned int* seg_count, long long k,
+                            long long cap, int nseg, const SelCarry* carry) {
   constexpr int KB = KeyBits<T>::value;
-  for (int e = threadIdx.x; e < kHistBins; e += blockDim.x) hist[e] = 0ull;
+  for (int e = threadIdx.x; e < kHistRep * kHistBins; e += blockDim.x) hist[e] = 0ull;
+  // empty segments, so that consumers see no candidates when no collecting
+  // pass runs (k == 0 goes straight to SEL_FINAL)
+  for (int e = threadIdx.x; e < nseg; e += blockDim.x) seg_count[e] = 0u;
   if (threadIdx.x == 0) {
     plan->prefix = 0; plan->k_rem = k; plan->count_above = 0; plan->bucket_count = 0;
     plan->ncand = 0; plan->cap = cap; plan->nnz = 0; plan->pbits = 0; plan->kbits = KB;
     plan->mode = (k > 0) ? SEL_HIST : SEL_FINAL; plan->slow = 0; plan->overflow = 0;
+    plan->nseg = nseg;
     plan->sum_r2 = 0.0; plan->sum_sel2 = 0.0; plan->threshold = 0.0;
+    plan->carry_used = carry->valid ? 1 : 0;
+    plan->carry_dlo = carry->dlo;
     counters[0] = 0; counters[1] = 0;
   }
+}
+
+// VLt (rp x ldv) <- VL (ldv x rp), both in the residual type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_panel(const T* __restrict__ VL, int64_t rows,
+                                                         int rp, T* __restrict__ VLt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * rp) return;
+  const int64_t c = e / rows, j = e % rows;
+  VLt[e] = VL[j * rp + c];
 }
 
 // ---------------------------------------------------------------------------
@@ -559,27 +907,27 @@ template <> __device__ __forceinline__ uint16_t to_store<uint16_t, float>(float 
 template <typename TD, typename TX>
 __global__ __launch_bounds__(256) void k_init_d(TD* __restrict__ D, int64_t ldd,
                                                 const TX* __restrict__ X, int64_t ldx,
-                                                int64_t m, int64_t n) {
-  const int64_t total = m * ldd;
+                                                int64_t m, int64_t n, int64_t mpad) {
+  const int64_t total = mpad * ldd;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / ldd, j = e % ldd;
-    D[e] = (j < n) ? to_store<TD, TX>(X[i * ldx + j]) : TD(0);
+    D[e] = (i < m && j < n) ? to_store<TD, TX>(X[i * ldx + j]) : TD(0);
   }
 }
 
 template <typename TD, typename TX>
-__global__ __launch_bounds__(256) void k_update_d(TD* __restrict__ D, int64_t ldd,
-                                                  const TX* __restrict__ X, int64_t ldx,
-                                                  int64_t n, const int64_t* __restrict__ idx,
+__global__ __launch_bounds__(256) void k_update_d(TD* __restrict__ D, int64_t ldd, int64_t n,
+                                                  const int64_t* __restrict__ idx,
                                                   const TX* __restrict__ val,
+                                                  const TX* __restrict__ xv,
                                                   const SelPlan* __restrict__ plan) {
   const long long cnt = plan->nnz;
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
        e += (long long)gridDim.x * 256) {
     const int64_t id = idx[e];
     const int64_t i = id / n, j = id % n;
-    const TX x = X[i * ldx + j];
+    const TX x = xv[e];
     D[i * ldd + j] = to_store<TD, TX>(val ? (TX)(x - val[e]) : x);
   }
 }
@@ -711,47 +1059,79 @@ static unsigned grid_for(int64_t work, int num_cu, int per_cu) {
   return (unsigned)g;
 }
 
+// Blocks of the full-data passes (one candidate segment each).
+template <typename T>
+static int64_t sel_grid(int rp, int64_t m, int64_t n, int num_cu) {
+  int64_t g = 1;
+  GODEC_RP_SWITCH(rp, {
+    constexpr int TW = 256 * sel_cpt<T, RP>();
+    g = ((n + TW - 1) / TW) * ((m + kRowsPerTile - 1) / kRowsPerTile);
+  });
+  g = std::min<int64_t>(g, (int64_t)num_cu * 2);
+  return std::max<int64_t>(1, std::min<int64_t>(g, kMaxSeg));
+}
+
 template <typename T>
 static void select_t(const Launch& L, int rp, const SelectArgs& a) {
   constexpr int KB = KeyBits<T>::value;
   const int levels = 1 + (KB - kHistBits0 + kHistBits - 1) / kHistBits;
-  const int64_t ctiles = (a.n + 255) / 256;
-  const int64_t rtiles = (a.m + kRowsPerTile - 1) / kRowsPerTile;
-  int64_t g = ctiles * rtiles;
-  if (g > (int64_t)L.num_cu * 4) g = (int64_t)L.num_cu * 4;
-  const unsigned pass_grid = (unsigned)g;
+  const int64_t g = sel_grid<T>(rp, a.m, a.n, L.num_cu);
   hipLaunchKernelGGL(k_sel_reset<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist,
-                     a.counters, (long long)a.k, (long long)a.cap);
+                     a.counters, a.seg_count, (long long)a.k, (long long)a.cap, (int)g, a.carry);
   GODEC_RP_SWITCH(rp, {
-    for (int pass = 0; pass <= levels; ++pass) {
-      if (pass == 0 && a.ev_a) (void)hipEventRecord(a.ev_a, L.stream);
-      hipLaunchKernelGGL((k_sel_pass<T, RP>), dim3(pass_grid), dim3(256), 0, L.stream,
-                         (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL, a.m, a.n,
-                         a.plan, a.hist, a.cand_idx, (T*)a.cand_val, pass);
-      if (pass == 0 && a.ev_b) (void)hipEventRecord(a.ev_b, L.stream);
+    // pass 0 (carried window or full level 0), one spare pass for the
+    // fall-back level-0 histogram, then one per deeper level and the collection
+    for (int pass = 0; pass <= levels + 1; ++pass) {
+      if (pass == 0) {
+        if (a.ev_a) (void)hipEventRecord(a.ev_a, L.stream);
+        hipLaunchKernelGGL((k_sel_pass0<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
+                           (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VLt, a.ldv, a.m,
+                           a.n, a.plan, a.hist, a.cand_idx, (T*)a.cand_val, (T*)a.cand_x,
+                           a.seg_count);
+        if (a.ev_b) (void)hipEventRecord(a.ev_b, L.stream);
+      } else {
+        hipLaunchKernelGGL((k_sel_passN<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
+                           (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VLt, a.ldv, a.m,
+                           a.n, a.plan, a.hist, a.cand_idx, (T*)a.cand_val, (T*)a.cand_x,
+                           a.seg_count);
+      }
       hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 0);
     }
   });
-  const unsigned cg = grid_for(a.cap, L.num_cu, 4);
+  const unsigned cg = (unsigned)(g + 1);   // one block per segment and the spill
   for (int round = 0; round < levels - 1; ++round) {
     hipLaunchKernelGGL(k_cand_hist<T>, dim3(cg), dim3(256), 0, L.stream, a.plan,
-                       (const T*)a.cand_val, a.hist);
+                       (const T*)a.cand_val, (const unsigned int*)a.seg_count, a.hist);
     hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 1);
   }
   GODEC_RP_SWITCH(rp, {
     hipLaunchKernelGGL((k_sel_ties_stream<T, RP>), dim3(1), dim3(256), 0, L.stream,
                        (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL, a.m, a.n, a.plan,
-                       a.cand_idx, (const T*)a.cand_val, a.s_idx, (T*)a.s_val);
+                       a.cand_idx, (const T*)a.cand_val, (const T*)a.cand_x,
+                       (const unsigned int*)a.seg_count, a.s_idx, (T*)a.s_val, (T*)a.s_x,
+                       a.carry);
   });
   hipLaunchKernelGGL(k_sel_compact<T>, dim3(cg), dim3(256), 0, L.stream, a.plan, a.cand_idx,
-                     (const T*)a.cand_val, a.s_idx, (T*)a.s_val, a.tie_idx, a.counters);
+                     (const T*)a.cand_val, (const T*)a.cand_x, (const unsigned int*)a.seg_count,
+                     a.s_idx, (T*)a.s_val, (T*)a.s_x, a.tie_idx, a.counters);
   hipLaunchKernelGGL(k_sel_ties<T>, dim3(1), dim3(1024), 0, L.stream, a.plan, a.s_idx,
-                     (T*)a.s_val, a.tie_idx, a.counters);
+                     (T*)a.s_val, a.tie_idx, a.counters, a.carry);
   GODEC_RP_SWITCH(rp, {
     hipLaunchKernelGGL((k_fix_tie_values<T, RP>), dim3(grid_for(a.k, L.num_cu, 2)), dim3(256),
                        0, L.stream, (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL, a.n,
-                       a.plan, a.counters, a.s_idx, (T*)a.s_val);
+                       a.plan, a.counters, a.s_idx, (T*)a.s_val, (T*)a.s_x);
   });
+}
+
+void launch_transpose_panel(const Launch& L, bool f64, const void* VL, int64_t rows, int rp,
+                            void* VLt) {
+  const unsigned b = (unsigned)((rows * rp + 255) / 256);
+  if (f64)
+    hipLaunchKernelGGL(k_transpose_panel<double>, dim3(b), dim3(256), 0, L.stream,
+                       (const double*)VL, rows, rp, (double*)VLt);
+  else
+    hipLaunchKernelGGL(k_transpose_panel<float>, dim3(b), dim3(256), 0, L.stream,
+                       (const float*)VL, rows, rp, (float*)VLt);
 }
 
 void launch_select(const Launch& L, bool f64, int rp, const SelectArgs& a) {
@@ -776,34 +1156,33 @@ void launch_residual(const Launch& L, bool f64, int rp, const void* X, int64_t l
 }
 
 void launch_init_d(const Launch& L, DType td, bool xf64, void* D, int64_t ldd,
-                   const void* X, int64_t ldx, int64_t m, int64_t n) {
-  dim3 grid(grid_for(m * ldd, L.num_cu, 16));
+                   const void* X, int64_t ldx, int64_t m, int64_t n, int64_t mpad) {
+  dim3 grid(grid_for(mpad * ldd, L.num_cu, 16));
   if (td == F64)
     hipLaunchKernelGGL((k_init_d<double, double>), grid, dim3(256), 0, L.stream, (double*)D,
-                       ldd, (const double*)X, ldx, m, n);
+                       ldd, (const double*)X, ldx, m, n, mpad);
   else if (td == F32)
     hipLaunchKernelGGL((k_init_d<float, float>), grid, dim3(256), 0, L.stream, (float*)D, ldd,
-                       (const float*)X, ldx, m, n);
+                       (const float*)X, ldx, m, n, mpad);
   else
     hipLaunchKernelGGL((k_init_d<uint16_t, float>), grid, dim3(256), 0, L.stream,
-                       (uint16_t*)D, ldd, (const float*)X, ldx, m, n);
+                       (uint16_t*)D, ldd, (const float*)X, ldx, m, n, mpad);
   (void)xf64;
 }
 
-void launch_update_d(const Launch& L, DType td, bool xf64, void* D, int64_t ldd,
-                     const void* X, int64_t ldx, int64_t n, const int64_t* idx,
-                     const void* val, const SelPlan* plan, int64_t kmax) {
+void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
+                     const int64_t* idx, const void* val, const void* xv, const SelPlan* plan,
+                     int64_t kmax) {
   const unsigned g = grid_for(kmax, L.num_cu, 4);
   if (td == F64)
     hipLaunchKernelGGL((k_update_d<double, double>), dim3(g), dim3(256), 0, L.stream,
-                       (double*)D, ldd, (const double*)X, ldx, n, idx, (const double*)val, plan);
+                       (double*)D, ldd, n, idx, (const double*)val, (const double*)xv, plan);
   else if (td == F32)
     hipLaunchKernelGGL((k_update_d<float, float>), dim3(g), dim3(256), 0, L.stream, (float*)D,
-                       ldd, (const float*)X, ldx, n, idx, (const float*)val, plan);
+                       ldd, n, idx, (const float*)val, (const float*)xv, plan);
   else
     hipLaunchKernelGGL((k_update_d<uint16_t, float>), dim3(g), dim3(256), 0, L.stream,
-                       (uint16_t*)D, ldd, (const float*)X, ldx, n, idx, (const float*)val, plan);
-  (void)xf64;
+                       (uint16_t*)D, ldd, n, idx, (const float*)val, (const float*)xv, plan);
 }
 
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx, int64_t m,

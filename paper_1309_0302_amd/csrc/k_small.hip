@@ -16,13 +16,35 @@
 
 namespace godec {
 
+// Sum of entry e over nparts partial matrices of `stride` doubles, with
+// independent accumulators so the loads overlap.
+__device__ __forceinline__ double sum_parts(const double* __restrict__ P, int nparts, int stride,
+                                            int e) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = 0;
+  for (; b + 3 < nparts; b += 4) {
+    a0 += P[(int64_t)(b + 0) * stride + e];
+    a1 += P[(int64_t)(b + 1) * stride + e];
+    a2 += P[(int64_t)(b + 2) * stride + e];
+    a3 += P[(int64_t)(b + 3) * stride + e];
+  }
+  for (; b < nparts; ++b) a0 += P[(int64_t)b * stride + e];
+  return (a0 + a1) + (a2 + a3);
+}
+
 // Rescale M (n x n in LDS, row stride ld) by the power of two nearest its
 // largest magnitude; exact in binary floating point.
 __device__ void pow2_normalise(double* M, int n, int ld, double* red) {
+  // block-wide max |M_ij| (blockDim.x is a multiple of 64, red has >= 4 slots)
+  double mx = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) mx = fmax(mx, fabs(M[(e / n) * ld + (e % n)]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(M[i * ld + j]));
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, red[w]);
     int e = 0;
     if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
     red[0] = ldexp(1.0, -e);
@@ -64,7 +86,7 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ Gpart,
   const int reff = st->r_eff;
   for (int e = tid; e < RP * RP; e += blockDim.x) {
     double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += Gpart[(int64_t)b * RP * RP + e];
+    s = sum_parts(Gpart, nparts, RP * RP, e);
     const int i = e / RP, j = e % RP;
     G[i * LD + j] = s;
     R[i * LD + j] = 0.0;
@@ -101,17 +123,28 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ Gpart,
     }
     __syncthreads();
   }
-  // Inverse of R restricted to the active columns (zero elsewhere).
-  if (tid < RP) {
-    const int c = tid;
-    for (int i = RP - 1; i >= 0; --i) {
-      if (i > c || !act[c] || !act[i]) { Ri[i * LD + c] = 0.0; continue; }
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= c; ++l) s -= R[i * LD + l] * Ri[l * LD + c];
-      Ri[i * LD + c] = s / R[i * LD + i];
-    }
+  // Inverse of R restricted to the active columns (zero elsewhere), by a
+  // right-looking back substitution on [R | I]: step i fixes row i of the
+  // inverse, then removes it from the rows above (parallel over entries).
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, c = e % RP;
+    Ri[i * LD + c] = (i == c && act[c]) ? 1.0 : 0.0;
   }
   __syncthreads();
+  for (int i = RP - 1; i >= 0; --i) {
+    if (act[i]) {
+      const double d = 1.0 / R[i * LD + i];
+      if (tid < RP) Ri[i * LD + tid] *= d;
+      __syncthreads();
+      for (int e = tid; e < i * RP; e += blockDim.x) {
+        const int l = e / RP, c = e % RP;
+        Ri[l * LD + c] -= R[l * LD + i] * Ri[i * LD + c];
+      }
+    } else if (tid < RP) {
+      Ri[i * LD + tid] = 0.0;
+    }
+    __syncthreads();
+  }
   for (int e = tid; e < RP * RP; e += blockDim.x) {
     const int i = e / RP, j = e % RP;
     rinv_panel[e] = (TA)Ri[i * LD + j];
@@ -119,13 +152,16 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ Gpart,
   }
   if (acc != nullptr) {
     // acc <- R * acc (or R), then an exact power-of-two rescale.
+    if (!reset_acc)
+      for (int e = tid; e < RP * RP; e += blockDim.x) G[(e / RP) * LD + (e % RP)] = acc[e];
+    __syncthreads();
     for (int e = tid; e < RP * RP; e += blockDim.x) {
       const int i = e / RP, j = e % RP;
       double s = 0.0;
       if (reset_acc) {
         s = R[i * LD + j];
       } else {
-        for (int l = i; l < RP; ++l) s += R[i * LD + l] * acc[l * RP + j];
+        for (int l = i; l < RP; ++l) s += R[i * LD + l] * G[l * LD + j];
       }
       A[i * LD + j] = s;
     }
@@ -136,6 +172,10 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ Gpart,
     for (int e = tid; e < RP * RP; e += blockDim.x) acc[e] = A[(e / RP) * LD + (e % RP)];
   }
 }
+
+// Rotation threshold of the Jacobi sweeps: an off-diagonal entry below
+// 4 u sqrt(|a_pp a_qq|) (u = 2^-53) is already at rounding level.
+constexpr double kJacobiTol = 4.0 * 0x1p-53;
 
 // Round-robin pairing (circle method) over N (even) players.
 __device__ __forceinline__ void rr_pair(int round, int k, int N, int& a, int& b) {
@@ -163,7 +203,7 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
         if (q < n) {
           const double apq = A[p * LD + q];
           const double app = A[p * LD + p], aqq = A[q * LD + q];
-          if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && apq != 0.0) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -229,7 +269,7 @@ __device__ void jacobi_svd_values(double* M, int n, double* out, double* cs, int
             const double x = M[i * LD + p], y = M[i * LD + q];
             al += x * x; be += y * y; ga += x * y;
           }
-          if (ga != 0.0 && fabs(ga) > 1e-17 * sqrt(al * be)) {
+          if (ga != 0.0 && fabs(ga) > kJacobiTol * sqrt(al * be)) {
             const double ze = (be - al) / (2.0 * ga);
             const double t = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -288,11 +328,12 @@ __global__ __launch_bounds__(256) void k_core(const double* __restrict__ Gpart,
   __shared__ int rot;
   __shared__ int sh_keep;
   __shared__ double red[4];
+  __shared__ double redA[4], redB[4];
   const int tid = threadIdx.x;
   const int n = st->r_eff;             // active leading columns
   for (int e = tid; e < RP * RP; e += blockDim.x) {
     double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += Gpart[(int64_t)b * RP * RP + e];
+    s = sum_parts(Gpart, nparts, RP * RP, e);
     const int i = e / RP, j = e % RP;
     G[i * LD + j] = s;
     T[i * LD + j] = t_identity ? (i == j ? 1.0 : 0.0) : st->T[e];
@@ -302,30 +343,54 @@ __global__ __launch_bounds__(256) void k_core(const double* __restrict__ Gpart,
 
   // ---- rank check on R2 (A2^T Y1 = R2^T R2) ----
   // Certificate first: s_min(R2) >= 1/||R2^{-1}||_F and s_max <= ||R2||_F.
+  // R2^{-1} (upper triangular, active block) by a right-looking back
+  // substitution in H; a zero diagonal fails the certificate.
   if (tid == 0) {
-    double fr = 0.0, fi = 0.0;
-    bool ok = n > 0;
-    for (int i = 0; i < n; ++i) {
-      for (int j = i; j < n; ++j) fr += W[i * LD + j] * W[i * LD + j];
-      if (!(W[i * LD + i] != 0.0)) ok = false;
-    }
-    if (ok) {
-      // column c of R2^{-1} by back substitution, accumulate its norm
-      for (int c = 0; c < n && ok; ++c) {
-        double x[RP];
-        for (int i = c; i >= 0; --i) {
-          double s = (i == c) ? 1.0 : 0.0;
-          for (int l = i + 1; l <= c; ++l) s -= W[i * LD + l] * x[l];
-          x[i] = s / W[i * LD + i];
-          fi += x[i] * x[i];
-        }
-      }
-      ok = isfinite(fi) && isfinite(fr) && (1.0 / fi) > rank_tol * fr;
-    }
-    red[0] = ok ? 1.0 : 0.0;
+    int ok = n > 0;
+    for (int i = 0; i < n; ++i)
+      if (!(W[i * LD + i] != 0.0)) ok = 0;
+    red[1] = ok;
     sh_keep = n;
   }
+  for (int e = tid; e < RP * RP; e += blockDim.x) {
+    const int i = e / RP, c = e % RP;
+    H[i * LD + c] = (i == c) ? 1.0 : 0.0;
+  }
   __syncthreads();
+  if (red[1] != 0.0) {
+    for (int i = n - 1; i >= 0; --i) {
+      const double d = 1.0 / W[i * LD + i];
+      if (tid < n) H[i * LD + tid] *= d;
+      __syncthreads();
+      for (int e = tid; e < i * n; e += blockDim.x) {
+        const int l = e / n, c = e % n;
+        H[l * LD + c] -= W[l * LD + i] * H[i * LD + c];
+      }
+      __syncthreads();
+    }
+  }
+  {
+    double fr = 0.0, fi = 0.0;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = e / n, c = e % n;
+      if (c >= i) {
+        fr += W[i * LD + c] * W[i * LD + c];
+        fi += H[i * LD + c] * H[i * LD + c];
+      }
+    }
+    fr = wave_sum(fr);
+    fi = wave_sum(fi);
+    __syncthreads();
+    if ((tid & 63) == 0) { redA[tid >> 6] = fr; redB[tid >> 6] = fi; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0, b = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += redA[w]; b += redB[w]; }
+      const bool ok = red[1] != 0.0 && isfinite(a) && isfinite(b) && (1.0 / b) > rank_tol * a;
+      red[0] = ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+  }
   if (red[0] == 0.0 && n > 0) {
     jacobi_svd_values<RP>(W, n, sv, cs, &rot);
     if (tid == 0) {
