@@ -23,7 +23,7 @@ constexpr int kHistBits0 = 12;        // first radix digit of the key
 constexpr int kHistBits = 11;         // later digits
 constexpr int kHistBins = 1 << kHistBits0;
 constexpr int kHistReplicas = 8;      // global histogram copies (contention)
-constexpr int kMaxSeg = 4096;         // most blocks of a full-data selection pass
+constexpr int kMaxSeg = 4096;         // most candidate segments (waves of a full pass)
 constexpr int kBlock = 256;
 
 // Supported padded panel widths.

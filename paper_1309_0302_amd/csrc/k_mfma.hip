@@ -8,9 +8,9 @@
 //
 // The panel width is padded to 32 (one MFMA tile); padding columns are zero.
 // The contraction index may be permuted freely as long as both operands use
-// the same (lane group, slot) -> k assignment, so each lane reads contiguous
-// runs: along its row of D in k_mm_a, and 16-byte column groups of D rows
-// in k_mm_b (lanes cover consecutive columns, so a wave reads whole rows).
+// the same (lane group, slot) -> k assignment.  k_mm_a stages D through
+// LDS (coalesced row reads); k_mm_b reads 8-byte column groups of D rows
+// directly (lanes cover consecutive columns, so a wave reads whole rows).
 //
 // Layouts used (v_mfma_f32_32x32x{16_bf16, 2_f32}, lane l, l%32 = index on
 // the lanes, l/32 = group g):  A operand row i = l%32; B operand column
@@ -41,83 +41,124 @@ __device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
 
 // ---------------------------------------------------------------------------
 // k_mm_a: Wtpart[ct] = (D[:, tile ct] Z[tile ct, :])^T.
-// Block = 2 waves, wave w owns rows [blockIdx.y*128 + 64w, +64) as two
-// 32-row MFMA tiles sharing the B operand.  Column tile of KC columns.
+// Block = 4 waves and 128 rows of D; wave w owns the 32-row MFMA tile
+// [32w, 32w + 32).  The block walks its KC-column tile in steps of 128
+// bytes per row: every step, the 128 x 128-byte slab of D and the 32 x
+// 128-byte slab of Z^T are read with coalesced 16-byte loads (eight lanes
+// per row), written to LDS (chunk index XOR-swizzled by the row to spread
+// banks), and read back in the MFMA operand layout.  The loads of step s+1
+// are issued before the products of step s (double-buffered LDS).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void k_mm_a_bf16(const uint16_t* __restrict__ D,
+constexpr int kMmaRows = 128;
+
+template <typename TT>
+__device__ __forceinline__ void mma_gload(const TT* __restrict__ D, int64_t ldd, int64_t mpad,
+                                          const TT* __restrict__ Zt, int64_t rb, int64_t kk,
+                                          int lr, int lc, u32x4 (&st)[4], u32x4& sz) {
+  constexpr int E = 16 / sizeof(TT);   // elements per 16-byte chunk
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int64_t row = rb + lr + 32 * h;
+    st[h] = row < mpad ? *reinterpret_cast<const u32x4*>(D + row * ldd + kk + E * lc)
+                       : u32x4{0u, 0u, 0u, 0u};
+  }
+  sz = *reinterpret_cast<const u32x4*>(Zt + (int64_t)lr * ldd + kk + E * lc);
+}
+
+__device__ __forceinline__ void mma_sstore(u32x4* tD, u32x4* tZ, int lr, int lc,
+                                           const u32x4 (&st)[4], const u32x4& sz) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int row = lr + 32 * h;
+    tD[row * 8 + (lc ^ (row & 7))] = st[h];
+  }
+  tZ[lr * 8 + (lc ^ (lr & 7))] = sz;
+}
+
+__device__ __forceinline__ void mma_store_w(float* __restrict__ Wtpart, int64_t mpad, int64_t r0,
+                                            int lane, const f32x16& acc) {
+  if (r0 >= mpad) return;
+  float* out = Wtpart + ((int64_t)blockIdx.x * 32 + (lane & 31)) * mpad;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) out[r0 + acc_row(v, lane)] = acc[v];
+}
+
+// bf16: a 128-byte step is 64 columns = four 16-wide MFMA slices; lane
+// group g takes chunks 4g .. 4g+3 (the K order is the same on both operands).
+__global__ __launch_bounds__(256) void k_mm_a_bf16(const uint16_t* __restrict__ D,
                                                    int64_t ldd, int64_t mpad,
                                                    const uint16_t* __restrict__ Zt,
                                                    float* __restrict__ Wtpart,
                                                    int64_t KC) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * 128 + 64 * wave;
-  if (r0 >= mpad) return;
+  __shared__ u32x4 tD[2][kMmaRows * 8];
+  __shared__ u32x4 tZ[2][32 * 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, g = lane >> 5;
+  const int lr = tid >> 3, lc = tid & 7;
+  const int64_t rb = (int64_t)blockIdx.y * kMmaRows;
   const int64_t c0 = (int64_t)blockIdx.x * KC;
   const int64_t c1 = (c0 + KC) < ldd ? (c0 + KC) : ldd;
-  const int i = lane & 31, g = lane >> 5;
-  const uint16_t* pa0 = D + (r0 + i) * ldd + 32 * g;
-  const uint16_t* pa1 = D + (r0 + 32 + i) * ldd + 32 * g;
-  const uint16_t* pb = Zt + (int64_t)i * ldd + 32 * g;
-  f32x16 acc0 = {}, acc1 = {};
+  const int row = 32 * wave + i;
+  u32x4 st[4], sz;
+  f32x16 acc = {};
+  mma_gload(D, ldd, mpad, Zt, rb, c0, lr, lc, st, sz);
+  mma_sstore(tD[0], tZ[0], lr, lc, st, sz);
+  __syncthreads();
+  int buf = 0;
   for (int64_t kk = c0; kk < c1; kk += 64) {
-    u32x4 a0[4], a1[4], b[4];
+    const bool more = kk + 64 < c1;
+    if (more) mma_gload(D, ldd, mpad, Zt, rb, kk + 64, lr, lc, st, sz);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      a0[s] = *reinterpret_cast<const u32x4*>(pa0 + kk + 8 * s);
-      a1[s] = *reinterpret_cast<const u32x4*>(pa1 + kk + 8 * s);
-      b[s] = *reinterpret_cast<const u32x4*>(pb + kk + 8 * s);
+      const int ch = 4 * g + s;
+      const u32x4 av = tD[buf][row * 8 + (ch ^ (row & 7))];
+      const u32x4 bv = tZ[buf][i * 8 + (ch ^ (i & 7))];
+      acc = mfma_bf16(as_bf16x8(av), as_bf16x8(bv), acc);
     }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      acc0 = mfma_bf16(as_bf16x8(a0[s]), as_bf16x8(b[s]), acc0);
-      acc1 = mfma_bf16(as_bf16x8(a1[s]), as_bf16x8(b[s]), acc1);
-    }
+    if (more) mma_sstore(tD[buf ^ 1], tZ[buf ^ 1], lr, lc, st, sz);
+    __syncthreads();
+    buf ^= 1;
   }
-  float* out = Wtpart + ((int64_t)blockIdx.x * 32 + (lane & 31)) * mpad;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    out[r0 + acc_row(v, lane)] = acc0[v];
-    out[r0 + 32 + acc_row(v, lane)] = acc1[v];
-  }
+  mma_store_w(Wtpart, mpad, rb + 32 * wave, lane, acc);
 }
 
-__global__ __launch_bounds__(128) void k_mm_a_f32(const float* __restrict__ D, int64_t ldd,
+// f32: a 128-byte step is 32 columns = sixteen 2-wide MFMA slices; slice s
+// of lane group g is element s%4 of chunk 2(s/4) + g.
+__global__ __launch_bounds__(256) void k_mm_a_f32(const float* __restrict__ D, int64_t ldd,
                                                   int64_t mpad, const float* __restrict__ Zt,
                                                   float* __restrict__ Wtpart, int64_t KC) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * 128 + 64 * wave;
-  if (r0 >= mpad) return;
+  __shared__ u32x4 tD[2][kMmaRows * 8];
+  __shared__ u32x4 tZ[2][32 * 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, g = lane >> 5;
+  const int lr = tid >> 3, lc = tid & 7;
+  const int64_t rb = (int64_t)blockIdx.y * kMmaRows;
   const int64_t c0 = (int64_t)blockIdx.x * KC;
   const int64_t c1 = (c0 + KC) < ldd ? (c0 + KC) : ldd;
-  const int i = lane & 31, g = lane >> 5;
-  const float* pa0 = D + (r0 + i) * ldd + 8 * g;
-  const float* pa1 = D + (r0 + 32 + i) * ldd + 8 * g;
-  const float* pb = Zt + (int64_t)i * ldd + 8 * g;
-  f32x16 acc0 = {}, acc1 = {};
-  for (int64_t kk = c0; kk < c1; kk += 16) {
-    const float4 a0l = *reinterpret_cast<const float4*>(pa0 + kk);
-    const float4 a0h = *reinterpret_cast<const float4*>(pa0 + kk + 4);
-    const float4 a1l = *reinterpret_cast<const float4*>(pa1 + kk);
-    const float4 a1h = *reinterpret_cast<const float4*>(pa1 + kk + 4);
-    const float4 bl = *reinterpret_cast<const float4*>(pb + kk);
-    const float4 bh = *reinterpret_cast<const float4*>(pb + kk + 4);
-    const float a0[8] = {a0l.x, a0l.y, a0l.z, a0l.w, a0h.x, a0h.y, a0h.z, a0h.w};
-    const float a1[8] = {a1l.x, a1l.y, a1l.z, a1l.w, a1h.x, a1h.y, a1h.z, a1h.w};
-    const float b[8] = {bl.x, bl.y, bl.z, bl.w, bh.x, bh.y, bh.z, bh.w};
+  const int row = 32 * wave + i;
+  u32x4 st[4], sz;
+  f32x16 acc = {};
+  mma_gload(D, ldd, mpad, Zt, rb, c0, lr, lc, st, sz);
+  mma_sstore(tD[0], tZ[0], lr, lc, st, sz);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kk = c0; kk < c1; kk += 32) {
+    const bool more = kk + 32 < c1;
+    if (more) mma_gload(D, ldd, mpad, Zt, rb, kk + 32, lr, lc, st, sz);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      acc0 = mfma_f32(a0[s], b[s], acc0);
-      acc1 = mfma_f32(a1[s], b[s], acc1);
+    for (int q = 0; q < 4; ++q) {
+      const int ch = 2 * q + g;
+      const u32x4 av = tD[buf][row * 8 + (ch ^ (row & 7))];
+      const u32x4 bv = tZ[buf][i * 8 + (ch ^ (i & 7))];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc = mfma_f32(__uint_as_float(av[e]), __uint_as_float(bv[e]), acc);
     }
+    if (more) mma_sstore(tD[buf ^ 1], tZ[buf ^ 1], lr, lc, st, sz);
+    __syncthreads();
+    buf ^= 1;
   }
-  float* out = Wtpart + ((int64_t)blockIdx.x * 32 + (lane & 31)) * mpad;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    out[r0 + acc_row(v, lane)] = acc0[v];
-    out[r0 + 32 + acc_row(v, lane)] = acc1[v];
-  }
+  mma_store_w(Wtpart, mpad, rb + 32 * wave, lane, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,12 +351,12 @@ void mfma_to_t(const Launch& L, bool bf16, const void* Z, int64_t ldd, int rp, v
 
 void mfma_mm_a(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
                const void* Zt, float* Wtpart, int64_t KC) {
-  dim3 grid((unsigned)((ldd + KC - 1) / KC), (unsigned)((mpad + 127) / 128));
+  dim3 grid((unsigned)((ldd + KC - 1) / KC), (unsigned)((mpad + kMmaRows - 1) / kMmaRows));
   if (bf16)
-    hipLaunchKernelGGL(k_mm_a_bf16, grid, dim3(128), 0, L.stream, (const uint16_t*)D, ldd, mpad,
+    hipLaunchKernelGGL(k_mm_a_bf16, grid, dim3(256), 0, L.stream, (const uint16_t*)D, ldd, mpad,
                        (const uint16_t*)Zt, Wtpart, KC);
   else
-    hipLaunchKernelGGL(k_mm_a_f32, grid, dim3(128), 0, L.stream, (const float*)D, ldd, mpad,
+    hipLaunchKernelGGL(k_mm_a_f32, grid, dim3(256), 0, L.stream, (const float*)D, ldd, mpad,
                        (const float*)Zt, Wtpart, KC);
 }
 

@@ -53,21 +53,24 @@ constexpr int sel_cpt() {
   return RP <= 24 ? 4 : 2;
 }
 
-// Candidate output of a collecting pass.  Block b owns the segment
-// [b * seg_cap, (b + 1) * seg_cap) of the candidate arrays and appends to it
-// through an LDS counter (one LDS atomic per wave and row, no global
-// atomics); entries beyond a full segment go to the spill region
+// Candidate output of a collecting pass.  Wave w of block b owns the
+// segment number b * kSelWaves + w, entries [seg * seg_cap, (seg + 1) *
+// seg_cap) of the candidate arrays.  Its fill is wave-uniform (kept in a
+// scalar register and advanced by ballot counts), so appending needs no
+// atomics; entries beyond a full segment go to the spill region
 // [cap, 2 * cap) through the global counter plan->ncand.  Whenever the total
-// fits in cap, every entry is kept.  The block publishes its segment fill in
-// seg_count[b] at the end of the pass.
+// fits in cap, every entry is kept.  Each wave publishes its segment fill in
+// seg_count[seg] at the end of the pass.
+constexpr int kSelWaves = 4;   // waves per block of the full-data passes
+
 template <typename T>
 struct SegSink {
   int64_t* idx;             // candidate arrays (2 * cap entries)
   T* val;
   T* xv;
-  unsigned int* cnt;        // LDS fill counter of the block
-  long long base;           // first entry of the block's segment
+  long long base;           // first entry of the wave's segment
   unsigned int cap;         // segment capacity
+  unsigned int fill;        // wave-uniform fill
   unsigned long long* sp_cnt;  // spill fill counter
   long long sp_cap;         // spill capacity (= cap; the spill starts at cap)
 };
@@ -75,17 +78,14 @@ struct SegSink {
 // Called by every lane of the wave (uniform control flow); lanes with
 // `take` append (idx, r, x).  Positions follow lane order within the wave.
 template <typename T>
-__device__ __forceinline__ void seg_push(const SegSink<T>& s, bool take, int64_t idx, T r, T x) {
+__device__ __forceinline__ void seg_push(SegSink<T>& s, bool take, int64_t idx, T r, T x) {
   const unsigned long long mask = __ballot(take);
   if (mask == 0ull) return;
   const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
   const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-  const int leader = __ffsll((long long)mask) - 1;
-  unsigned int b = 0u;
-  if (rank == 0u && take) b = atomicAdd(s.cnt, (unsigned int)__popcll(mask));
-  b = (unsigned int)__builtin_amdgcn_readlane((int)b, leader);
+  const unsigned int p = s.fill + rank;
+  s.fill += (unsigned int)__popcll(mask);
   if (!take) return;
-  const unsigned int p = b + rank;
   long long pos;
   if (p < s.cap) {
     pos = s.base + p;
@@ -138,7 +138,7 @@ template <typename T, int RP, int CPT, bool HIST, bool TAKE, bool S2, bool FULL,
 __device__ __forceinline__ void sel_tile(const T* __restrict__ X, int64_t ldx, int64_t n,
                                          int64_t i0, int nr, int64_t j0, const T* us,
                                          const T (&v)[CPT][RP], unsigned int* lh,
-                                         const PassKeys<T>& pk, const SegSink<T>& sink,
+                                         const PassKeys<T>& pk, SegSink<T>& sink,
                                          double& s2) {
   using K = typename KeyBits<T>::key_t;
   // rows whose X loads are in flight together (fewer when collecting, to
@@ -204,7 +204,7 @@ __device__ __forceinline__ void sel_pass_body(const T* __restrict__ X, int64_t l
                                               const T* __restrict__ UL,
                                               const T* __restrict__ VLt, int64_t ldv,
                                               int64_t m, int64_t n, unsigned int* lh, T* us,
-                                              const PassKeys<T>& pk, const SegSink<T>& sink,
+                                              const PassKeys<T>& pk, SegSink<T>& sink,
                                               bool vec_ok, double& s2) {
   constexpr int CPT = sel_cpt<T, RP>();
   constexpr int TW = 256 * CPT;
@@ -260,23 +260,19 @@ __device__ __forceinline__ PassKeys<T> keys_level0() {
   using K = typename KeyBits<T>::key_t;                                       \
   __shared__ unsigned int lh[kHistBins];                                      \
   __shared__ T us[kRowsPerTile * RP];                                         \
-  __shared__ unsigned int scount;                                             \
   __shared__ double red[4];                                                   \
   const int tid = threadIdx.x;                                                \
   const int lane = tid & 63, wave = tid >> 6;                                 \
-  (void)KB; (void)lane; (void)wave; (void)red;                                \
+  (void)KB; (void)red;                                                        \
   const long long ccap = plan->cap;                                           \
-  const unsigned int seg_cap = (unsigned int)(ccap / gridDim.x);              \
-  const int64_t sbase = (int64_t)blockIdx.x * seg_cap;                        \
-  const SegSink<T> sink{cand_idx, cand_val, cand_x, &scount, sbase, seg_cap,  \
-                        (unsigned long long*)&plan->ncand, ccap};
+  const unsigned int seg_cap = (unsigned int)(ccap / ((long long)gridDim.x * kSelWaves)); \
+  const int seg = (int)blockIdx.x * kSelWaves + wave;                         \
+  SegSink<T> sink{cand_idx, cand_val, cand_x, (long long)seg * seg_cap, seg_cap, 0u, \
+                  (unsigned long long*)&plan->ncand, ccap};
 
-// Closing of a collecting pass: publish the block's segment fill.
-#define GODEC_SEL_SEG_CLOSE                                    \
-  if (tid == 0) {                                              \
-    const unsigned int c = scount;                             \
-    seg_count[blockIdx.x] = c < seg_cap ? c : seg_cap;         \
-  }
+// Closing of a collecting pass: publish the wave's segment fill.
+#define GODEC_SEL_SEG_CLOSE                                                   \
+  if (lane == 0) seg_count[seg] = sink.fill < seg_cap ? sink.fill : seg_cap;
 
 // Pass 0: the carried-window pass (steady state) or the full level-0
 // histogram (first iteration); both also sum R^2.
@@ -303,7 +299,6 @@ __global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int6
     pk.kmin = pk.klo;
   }
   for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
-  if (tid == 0) scount = 0u;
   const bool vec_ok = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
   __syncthreads();
   double s2 = 0.0;
@@ -356,7 +351,6 @@ __global__ __launch_bounds__(256) void k_sel_passN(const T* __restrict__ X, int6
   if (mode == SEL_TIES) pk.kmin = (K)prefix + 1;   // prefix is the full threshold key
   if (do_hist)
     for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
-  if (tid == 0) scount = 0u;
   const bool vec_ok = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
   __syncthreads();
   double s2 = 0.0;
@@ -1068,7 +1062,7 @@ static int64_t sel_grid(int rp, int64_t m, int64_t n, int num_cu) {
     g = ((n + TW - 1) / TW) * ((m + kRowsPerTile - 1) / kRowsPerTile);
   });
   g = std::min<int64_t>(g, (int64_t)num_cu * 2);
-  return std::max<int64_t>(1, std::min<int64_t>(g, kMaxSeg));
+  return std::max<int64_t>(1, std::min<int64_t>(g, kMaxSeg / kSelWaves));
 }
 
 template <typename T>
@@ -1076,8 +1070,9 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
   constexpr int KB = KeyBits<T>::value;
   const int levels = 1 + (KB - kHistBits0 + kHistBits - 1) / kHistBits;
   const int64_t g = sel_grid<T>(rp, a.m, a.n, L.num_cu);
+  const int nseg = (int)g * kSelWaves;
   hipLaunchKernelGGL(k_sel_reset<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist,
-                     a.counters, a.seg_count, (long long)a.k, (long long)a.cap, (int)g, a.carry);
+                     a.counters, a.seg_count, (long long)a.k, (long long)a.cap, nseg, a.carry);
   GODEC_RP_SWITCH(rp, {
     // pass 0 (carried window or full level 0), one spare pass for the
     // fall-back level-0 histogram, then one per deeper level and the collection
@@ -1098,7 +1093,7 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
       hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 0);
     }
   });
-  const unsigned cg = (unsigned)(g + 1);   // one block per segment and the spill
+  const unsigned cg = (unsigned)(g + 1);   // segments are taken round-robin by blocks
   for (int round = 0; round < levels - 1; ++round) {
     hipLaunchKernelGGL(k_cand_hist<T>, dim3(cg), dim3(256), 0, L.stream, a.plan,
                        (const T*)a.cand_val, (const unsigned int*)a.seg_count, a.hist);
