@@ -73,10 +73,11 @@ struct godec_ctx {
   void* D = nullptr;       // native-precision working copy
   void* D16 = nullptr;     // bf16 working copy (BF16_REFINE)
   double* A1 = nullptr;    // n x r FP64
-  void *P0, *P1, *VL, *VLt, *W, *Zpart, *Bp, *UL, *Kp, *Rinvp;
+  void *P0, *P1, *VL, *VLt, *W, *Zpart, *Bp, *UL, *Kp;
   void *Zt, *Wt;             // 32-row transposed panels for the matrix cores
   float *Wtpart, *Zpart32;   // partial sums of the two MFMA halves
   double* Gpart;
+  GramCtl* gram_ctl;
   SmallState* st;
   SelPlan* plan[2];
   unsigned long long* hist;
@@ -98,7 +99,6 @@ struct godec_ctx {
   // schedule
   int64_t nchunks, rows_per_chunk;
   int64_t kc_a, nct_a, rc_b, nch_b;   // MFMA tiling
-  int gram_blocks_n, gram_blocks_m;
   // state
   int64_t iters_done = 0;
   int cur = 0;
@@ -116,7 +116,6 @@ namespace {
 struct Sizes {
   int64_t ldd, mpad, nchunks, rpc, cap;
   int64_t kc_a, nct_a, rc_b, nch_b;
-  int gbn, gbm;
 };
 
 Sizes plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
@@ -139,8 +138,6 @@ Sizes plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
   s.nchunks = (m + s.rpc - 1) / s.rpc;
   s.cap = std::min<int64_t>(m * n, 2 * k + (1 << 20));
   // few Gram partials: the one-block r x r kernels sum them serially
-  s.gbn = (int)std::min<int64_t>(32, std::max<int64_t>(1, (s.ldd + 255) / 256));
-  s.gbm = (int)std::min<int64_t>(32, std::max<int64_t>(1, (m + 255) / 256));
   return s;
 }
 
@@ -172,8 +169,8 @@ size_t carve(godec_ctx* c, void* base) {
   c->Bp = cv.take((size_t)m * rp * ta);
   c->UL = cv.take((size_t)m * rp * ta);
   c->Kp = cv.take((size_t)rp * rp * ta);
-  c->Rinvp = cv.take((size_t)rp * rp * ta);
-  c->Gpart = (double*)cv.take((size_t)256 * rp * rp * 8);
+  c->Gpart = (double*)cv.take((size_t)kGramSlots * rp * rp * 8);
+  c->gram_ctl = (GramCtl*)cv.take(sizeof(GramCtl));
   c->st = (SmallState*)cv.take(sizeof(SmallState));
   c->plan[0] = (SelPlan*)cv.take(sizeof(SelPlan));
   c->plan[1] = (SelPlan*)cv.take(sizeof(SelPlan));
@@ -236,7 +233,6 @@ void fill_ctx_params(godec_ctx* c, int64_t m, int64_t n, int32_t r, int64_t k,
   c->ldd = s.ldd; c->mpad = s.mpad; c->nchunks = s.nchunks; c->rows_per_chunk = s.rpc;
   c->cap = s.cap;
   c->kc_a = s.kc_a; c->nct_a = s.nct_a; c->rc_b = s.rc_b; c->nch_b = s.nch_b;
-  c->gram_blocks_n = s.gbn; c->gram_blocks_m = s.gbm;
 }
 
 // Counter-based SplitMix64 (Steele, Lea, Flood 2014): output i of the stream
@@ -298,13 +294,14 @@ struct ProfScope {
   }
 };
 
-// One Gram pass: out = D^T (D in), through W and the chunk partials.
-// W^T panel of D Y on the matrix cores (f32 / bf16 storage).
-void mfma_apply(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* Wt_out,
-                float* Wrow_out) {
+// W^T panel of D Y on the matrix cores (f32 / bf16 storage).  zt_ready:
+// c->Zt already holds Y^T in the type of td (written by the preceding
+// Cholesky QR step).
+void mfma_apply(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt_ready,
+                void* Wt_out, float* Wrow_out) {
   const Launch L = launch_of(c);
   const bool b16 = td == BF16;
-  mfma_to_t(L, b16, in, c->ldd, c->rp, c->Zt);
+  if (!zt_ready) mfma_to_t(L, b16, in, c->ldd, c->rp, c->Zt);
   {
     ProfScope ps(c, b16 ? PC_APPLY_BF16 : PC_APPLY);
     mfma_mm_a(L, b16, Dsrc, c->ldd, c->mpad, c->Zt, c->Wtpart, c->kc_a);
@@ -312,11 +309,13 @@ void mfma_apply(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* 
   mfma_reduce_w(L, b16, c->Wtpart, (int)c->nct_a, c->mpad, c->m, c->rp, Wt_out, Wrow_out);
 }
 
-void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* out) {
+// One Gram pass: out = D^T (D in), through W and the chunk partials.
+void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt_ready,
+               void* out) {
   const Launch L = launch_of(c);
   if (td != F64) {
     const bool b16 = td == BF16;
-    mfma_apply(c, td, Dsrc, in, c->Wt, nullptr);
+    mfma_apply(c, td, Dsrc, in, zt_ready, c->Wt, nullptr);
     {
       ProfScope ps(c, b16 ? PC_APPLY_T_BF16 : PC_APPLY_T);
       mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b);
@@ -325,11 +324,11 @@ void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* o
     return;
   }
   {
-    ProfScope ps(c, td == BF16 ? PC_APPLY_BF16 : PC_APPLY);
+    ProfScope ps(c, PC_APPLY);
     launch_apply(L, td, c->rp, Dsrc, c->ldd, c->m, in, c->W);
   }
   {
-    ProfScope ps(c, td == BF16 ? PC_APPLY_T_BF16 : PC_APPLY_T);
+    ProfScope ps(c, PC_APPLY_T);
     launch_apply_t(L, td, c->rp, Dsrc, c->ldd, c->m, c->W, c->Zpart, c->rows_per_chunk,
                    c->nchunks);
   }
@@ -337,13 +336,16 @@ void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, void* o
 }
 
 // Orthonormalise `in` (ldd x RP) into `out` by one Cholesky QR step,
-// accumulating its R factor into acc (reset when reset != 0).
-void chol_qr(godec_ctx* c, const void* in, void* out, double* acc, int reset) {
+// accumulating its R factor into acc (reset when reset != 0).  next_td:
+// type of the matrix-core pass that reads `out` next (its transpose is
+// written to c->Zt), or F64 when none does.
+void chol_qr(godec_ctx* c, const void* in, void* out, double* acc, int reset, DType next_td) {
   const Launch L = launch_of(c);
-  launch_gram(L, c->f64, c->rp, in, c->ldd, c->Gpart, c->gram_blocks_n);
-  launch_chol(L, c->f64, c->rp, c->Gpart, c->gram_blocks_n, c->st, acc, c->Rinvp, reset,
-              acc == c->st->R2 ? 1 : 0);
-  launch_apply_small(L, c->f64, c->rp, in, c->ldd, c->Rinvp, out);
+  launch_gram_tree(L, c->f64, c->rp, in, c->ldd, c->Gpart, c->gram_ctl, 1, c->st, acc, reset,
+                   acc == c->st->R2 ? 1 : 0);
+  const bool zt = !c->f64 && next_td != F64;
+  launch_apply_rinv(L, c->f64, c->rp, in, c->ldd, c->st, out, next_td, zt ? c->Zt : nullptr,
+                    c->ldd);
 }
 
 godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
@@ -353,34 +355,42 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   const bool refine = mixed && total > 0 && t >= total - c->refine_iters;
   // ---- subspace chain: Q2 = orth((D^T D)^p A1), R2 tracked ----
   launch_copy_panel(L, c->f64, c->rp, c->A1, c->n, c->ldd, c->r, c->st, c->P0);
-  const void* in = c->P0;
-  for (int j = 0; j < c->p; ++j) {
-    const bool low = mixed && !(refine && j == c->p - 1);
-    gram_pass(c, low ? BF16 : native, low ? c->D16 : c->D, in, c->P1);
-    chol_qr(c, c->P1, c->P0, c->st->R2, j == 0);
-    in = c->P0;
-  }
-  // second Cholesky QR round on Q2 (restores orthonormality to working
-  // precision); its R factor joins R2.
-  chol_qr(c, c->P0, c->VL, c->st->R2, 0);
-  // ---- B chain: (D^T D)^q Q2 = Y_q T, then B' = D Y_q ----
+  // type of chain pass j (the refinement redoes the last one in FP32)
+  auto chain_td = [&](int j) {
+    return (mixed && !(refine && j == c->p - 1)) ? BF16 : native;
+  };
   const bool low_b = mixed && !refine;
   const DType tdb = low_b ? BF16 : native;
   const void* Db = low_b ? c->D16 : c->D;
+  const void* in = c->P0;
+  bool zt = false;
+  for (int j = 0; j < c->p; ++j) {
+    const DType td = chain_td(j);
+    gram_pass(c, td, td == BF16 ? c->D16 : c->D, in, zt, c->P1);
+    const bool more = j + 1 < c->p;
+    chol_qr(c, c->P1, c->P0, c->st->R2, j == 0, more ? chain_td(j + 1) : F64);
+    zt = more;
+    in = c->P0;
+  }
+  // second Cholesky QR round on Q2 (restores orthonormality to working
+  // precision); its R factor joins R2.  Its transpose feeds the B chain.
+  chol_qr(c, c->P0, c->VL, c->st->R2, 0, tdb);
+  // ---- B chain: (D^T D)^q Q2 = Y_q T, then B' = D Y_q ----
   in = c->VL;
   for (int j = 0; j < c->q; ++j) {
-    gram_pass(c, tdb, Db, in, c->P1);
-    chol_qr(c, c->P1, c->P0, c->st->T, j == 0);
+    gram_pass(c, tdb, Db, in, true, c->P1);
+    chol_qr(c, c->P1, c->P0, c->st->T, j == 0, tdb);
     in = c->P0;
   }
   if (c->f64)
     launch_apply(L, tdb, c->rp, Db, c->ldd, c->m, in, c->Bp);
   else
-    mfma_apply(c, tdb, Db, in, nullptr, (float*)c->Bp);
+    mfma_apply(c, tdb, Db, in, true, nullptr, (float*)c->Bp);
   // ---- core ----
-  launch_gram(L, c->f64, c->rp, c->Bp, c->m, c->Gpart, c->gram_blocks_m);
-  launch_core(L, c->f64, c->rp, c->Gpart, c->gram_blocks_m, c->st, c->p, c->rank_tol,
-              c->q == 0 ? 1 : 0, c->Kp);
+  launch_gram_tree(L, c->f64, c->rp, c->Bp, c->m, c->Gpart, c->gram_ctl, 0, c->st, nullptr, 0,
+                   0);
+  launch_core(L, c->f64, c->rp, c->Gpart + (size_t)kGramFinal * c->rp * c->rp, 1, c->st, c->p,
+              c->rank_tol, c->q == 0 ? 1 : 0, c->Kp);
   launch_apply_small(L, c->f64, c->rp, c->Bp, c->m, c->Kp, c->UL);
   // ---- sparse step ----
   const int prev = c->cur;
@@ -511,6 +521,7 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   if (e == hipSuccess) e = hipMemsetAsync(c->plan[0], 0, sizeof(SelPlan), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->plan[1], 0, sizeof(SelPlan), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->carry, 0, sizeof(SelCarry), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->gram_ctl, 0, sizeof(GramCtl), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->VL, 0, (size_t)c->ldd * c->rp * c->ta, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->UL, 0, (size_t)c->m * c->rp * c->ta, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));

@@ -79,7 +79,8 @@ struct SelCarry {
 struct SmallState {
   double R2[kMaxRP * kMaxRP];      // R factor of Y2 = (D^T D)^p A1
   double T[kMaxRP * kMaxRP];       // B chain: (D^T D)^q Q2 = Y_q T
-  double Rinv[kMaxRP * kMaxRP];    // last Cholesky inverse (FP64)
+  double Rq[kMaxRP * kMaxRP];      // R factor of the last Cholesky QR step
+  double dinv[kMaxRP];             // 1 / diag(Rq), 0 on inactive columns
   double V[kMaxRP * kMaxRP];       // eigenvectors of B^T B (warm start)
   double K[kMaxRP * kMaxRP];       // core K' = T K (FP64 copy)
   double sigma[kMaxRP];            // singular values of B (descending)
@@ -108,9 +109,33 @@ void launch_apply_t(const Launch& L, DType td, int rp, const void* D,
 void launch_reduce_chunks(const Launch& L, bool f64, int rp,
                           const void* Zpart, int64_t nchunks, int64_t rows,
                           void* Zo);
-// Gpart[b] = P^T P over the rows of block b (FP64), nblk blocks.
-void launch_gram(const Launch& L, bool f64, int rp, const void* P,
-                 int64_t rows, double* Gpart, int nblk);
+// Gram G = P^T P (FP64) of a rows x RP panel in one launch: row blocks
+// write partials, a two-level arrival tree adds them in a fixed order, and
+// the final G lands in Gpart slot kGramFinal.  With `chol` set, the last
+// block then runs the Cholesky step of Cholesky QR (G = R^T R with
+// dependent-column detection) and stores R and 1/diag(R) in st->Rq,
+// st->dinv, and folds R into acc (acc <- R acc, or R when reset_acc),
+// rescaled by a power of two when normalise is set.  ctl must be zero
+// before the first launch; every launch leaves it zero.
+constexpr int kGramRows = 64;        // rows per block
+constexpr int kGramGroup = 16;       // blocks per first-level group
+constexpr int kGramMaxBlocks = 256;
+constexpr int kGramFinal = kGramMaxBlocks + kGramMaxBlocks / kGramGroup;
+constexpr int kGramSlots = kGramFinal + 1;   // partial slots of RP x RP doubles
+struct GramCtl {
+  unsigned int grp[kGramMaxBlocks / kGramGroup];
+  unsigned int top;
+  unsigned int pad[15];
+};
+void launch_gram_tree(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
+                      double* Gpart, GramCtl* ctl, int chol, SmallState* st, double* acc,
+                      int reset_acc, int normalise);
+// Out = P R^{-1} with R = st->Rq (upper triangular; zero rows and dinv = 0 on
+// inactive columns), by forward substitution in FP64, rows x RP in the
+// panel type; when Zt is given, also its transpose (32 x ldz, bf16 or f32,
+// rows >= RP zero) for the next matrix-core pass.
+void launch_apply_rinv(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
+                       const SmallState* st, void* Out, DType zt_type, void* Zt, int64_t ldz);
 // Out = P K  (rows x RP), K is RP x RP in the panel type.
 void launch_apply_small(const Launch& L, bool f64, int rp, const void* P,
                         int64_t rows, const void* K, void* Out);
@@ -118,11 +143,7 @@ void launch_apply_small(const Launch& L, bool f64, int rp, const void* P,
 void launch_copy_panel(const Launch& L, bool f64, int rp, const double* src,
                        int64_t rows, int64_t rows_pad, int r,
                        const SmallState* st, void* dst);
-
 // ---- r x r FP64 kernels (k_small.hip) ----
-void launch_chol(const Launch& L, bool f64, int rp, const double* Gpart,
-                 int nparts, SmallState* st, double* acc, void* rinv_panel,
-                 int reset_acc, int normalise);
 void launch_core(const Launch& L, bool f64, int rp, const double* Gpart,
                  int nparts, SmallState* st, int p, double rank_tol,
                  int t_identity, void* k_panel);

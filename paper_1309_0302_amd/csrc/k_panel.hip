@@ -144,41 +144,41 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const TA* __restrict__ Zp
   Zo[e] = s;
 }
 
-// Gpart[b] = sum over the rows of block b of P[i]^T P[i], in FP64.
-template <typename TA, int RP>
-__global__ __launch_bounds__(256) void k_gram(const TA* __restrict__ P,
-                                              int64_t rows,
-                                              double* __restrict__ Gpart) {
-  constexpr int RB = 64;
-  constexpr int NE = (RP * RP + 255) / 256;
-  __shared__ double ps[RB * RP];
-  double acc[NE];
+// Out = P R^{-1} by forward substitution in FP64 (x R = p row by row, R
+// upper triangular in st->Rq, 1/diag in st->dinv, zero on inactive
+// columns); optionally also the transposed panel Zt (32 x ldz) in bf16 or
+// f32 for the next matrix-core pass, rows >= RP zero.
+template <typename TA, int RP, typename TT>
+__global__ __launch_bounds__(256) void k_apply_rinv(const TA* __restrict__ P, int64_t rows,
+                                                    const SmallState* __restrict__ st,
+                                                    TA* __restrict__ Out, TT* __restrict__ Zt,
+                                                    int64_t ldz) {
+  __shared__ double rs[RP * RP];
+  __shared__ double di[RP];
+  for (int e = threadIdx.x; e < RP * RP; e += 256) rs[e] = st->Rq[e];
+  if (threadIdx.x < RP) di[threadIdx.x] = st->dinv[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows) return;
+  double x[RP];
 #pragma unroll
-  for (int u = 0; u < NE; ++u) acc[u] = 0.0;
-  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = (r0 + per) < rows ? (r0 + per) : rows;
-  for (int64_t i0 = r0; i0 < r1; i0 += RB) {
-    const int nr = (r1 - i0) < RB ? (int)(r1 - i0) : RB;
-    __syncthreads();
-    for (int e = threadIdx.x; e < RB * RP; e += 256)
-      ps[e] = (e < nr * RP) ? (double)P[i0 * RP + e] : 0.0;
-    __syncthreads();
+  for (int j = 0; j < RP; ++j) {
+    double s = (double)P[i * RP + j];
 #pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const int e = threadIdx.x + u * 256;
-      if (e < RP * RP) {
-        const int a = e / RP, b = e % RP;
-        double s = acc[u];
-        for (int ii = 0; ii < nr; ++ii) s = fma(ps[ii * RP + a], ps[ii * RP + b], s);
-        acc[u] = s;
-      }
-    }
+    for (int l = 0; l < j; ++l) s = fma(-x[l], rs[l * RP + j], s);
+    x[j] = s * di[j];
   }
 #pragma unroll
-  for (int u = 0; u < NE; ++u) {
-    const int e = threadIdx.x + u * 256;
-    if (e < RP * RP) Gpart[(int64_t)blockIdx.x * RP * RP + e] = acc[u];
+  for (int j = 0; j < RP; ++j) Out[i * RP + j] = (TA)x[j];
+  if (Zt != nullptr) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const float v = j < RP ? (float)x[j] : 0.f;
+      if constexpr (sizeof(TT) == 2)
+        Zt[(int64_t)j * ldz + i] = f32_to_bf16(v);
+      else
+        Zt[(int64_t)j * ldz + i] = (TT)v;
+    }
   }
 }
 
@@ -297,15 +297,20 @@ void launch_reduce_chunks(const Launch& L, bool f64, int rp, const void* Zpart,
                        (const float*)Zpart, nchunks, nel, (float*)Zo);
 }
 
-void launch_gram(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
-                 double* Gpart, int nblk) {
+void launch_apply_rinv(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
+                       const SmallState* st, void* Out, DType zt_type, void* Zt, int64_t ldz) {
+  const unsigned blocks = (unsigned)((rows + 255) / 256);
   GODEC_RP_SWITCH(rp, {
     if (f64)
-      hipLaunchKernelGGL((k_gram<double, RP>), dim3(nblk), dim3(256), 0, L.stream,
-                         (const double*)P, rows, Gpart);
+      hipLaunchKernelGGL((k_apply_rinv<double, RP, double>), dim3(blocks), dim3(256), 0,
+                         L.stream, (const double*)P, rows, st, (double*)Out, (double*)nullptr,
+                         ldz);
+    else if (Zt != nullptr && zt_type == BF16)
+      hipLaunchKernelGGL((k_apply_rinv<float, RP, uint16_t>), dim3(blocks), dim3(256), 0,
+                         L.stream, (const float*)P, rows, st, (float*)Out, (uint16_t*)Zt, ldz);
     else
-      hipLaunchKernelGGL((k_gram<float, RP>), dim3(nblk), dim3(256), 0, L.stream,
-                         (const float*)P, rows, Gpart);
+      hipLaunchKernelGGL((k_apply_rinv<float, RP, float>), dim3(blocks), dim3(256), 0,
+                         L.stream, (const float*)P, rows, st, (float*)Out, (float*)Zt, ldz);
   });
 }
 

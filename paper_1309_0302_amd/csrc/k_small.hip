@@ -16,6 +16,8 @@
 
 namespace godec {
 
+constexpr int kSmallThreads = 256;
+
 // Sum of entry e over nparts partial matrices of `stride` doubles, with
 // independent accumulators so the loads overlap.
 __device__ __forceinline__ double sum_parts(const double* __restrict__ P, int nparts, int stride,
@@ -32,145 +34,221 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ P, int np
   return (a0 + a1) + (a2 + a3);
 }
 
-// Rescale M (n x n in LDS, row stride ld) by the power of two nearest its
-// largest magnitude; exact in binary floating point.
-__device__ void pow2_normalise(double* M, int n, int ld, double* red) {
-  // block-wide max |M_ij| (blockDim.x is a multiple of 64, red has >= 4 slots)
-  double mx = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) mx = fmax(mx, fabs(M[(e / n) * ld + (e % n)]));
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, red[w]);
-    int e = 0;
-    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
-    red[0] = ldexp(1.0, -e);
-  }
-  __syncthreads();
-  const double s = red[0];
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
-    M[i * ld + j] *= s;
-  }
-  __syncthreads();
+// ---------------------------------------------------------------------------
+// Gram of a panel and the Cholesky step of Cholesky QR.
+//
+// Block b sums P[i]^T P[i] over its kGramRows-row slice into partial b (each
+// thread owns a 2 x 2 tile of G; the rows are split over NG thread groups
+// when the tiles do not fill the block).  The last block of each group of
+// kGramGroup blocks adds the group's partials, and the last group leader
+// adds the group sums: a fixed order, so G is the same bits on every run.
+// Every load of a reduction level is issued at once, so a level costs one
+// memory round trip.
+//
+// Cholesky (one wavefront of the final block, lane j holds column j of G in
+// registers, broadcasts by readlane): G = R^T R, upper R.  A column is
+// inactive when it lies at or past r_eff, is zero, or is numerically
+// dependent on the columns before it: its pivot (the squared norm of its
+// component orthogonal to them) is at most tau * G_jj with
+// tau = RP * max(u^2, 2^-53), the resolution of a Gram of panel-type data
+// accumulated in FP64.  An inactive column gets a zero row in R and
+// dinv = 0, so the orthonormalised panel has a zero column, which stays zero
+// in every later product.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky QR step: G = sum Gpart = Z^T Z;  G = R^T R (upper R).
-// A column is inactive when it lies at or past r_eff, is zero, or is
-// numerically dependent on the columns before it: its Cholesky pivot (the
-// squared norm of its component orthogonal to them) is at most
-// tau * G_jj with tau = RP * max(u^2, 2^-53) -- the resolution of a Gram of
-// panel-type data accumulated in FP64.  An inactive column gets a zero row
-// in R (so the tracked factor records a zero singular direction) and a zero
-// column in R^{-1} (so the orthonormalised panel has a zero column, which
-// stays zero in every later product).
-// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// One wavefront (lanes 0..63); G is RP x RP row-major in LDS.
 template <typename TA, int RP>
-__global__ __launch_bounds__(256) void k_chol(const double* __restrict__ Gpart,
-                                              int nparts, SmallState* st,
-                                              double* acc, TA* rinv_panel,
-                                              int reset_acc, int normalise) {
-  constexpr int LD = RP + 1;
-  __shared__ double G[RP * LD];
-  __shared__ double R[RP * LD];
-  __shared__ double Ri[RP * LD];
-  __shared__ double A[RP * LD];
-  __shared__ double G0[RP];
-  __shared__ double red[4];
-  __shared__ int act[RP];
-  const int tid = threadIdx.x;
+__device__ void wave_chol(const double* G, SmallState* st, double* acc, int reset_acc,
+                          int normalise) {
+  const int lane = threadIdx.x & 63;
+  const bool col = lane < RP;
   const int reff = st->r_eff;
-  for (int e = tid; e < RP * RP; e += blockDim.x) {
-    double s = 0.0;
-    s = sum_parts(Gpart, nparts, RP * RP, e);
-    const int i = e / RP, j = e % RP;
-    G[i * LD + j] = s;
-    R[i * LD + j] = 0.0;
-  }
-  __syncthreads();
-  if (tid < RP) {
-    G0[tid] = G[tid * LD + tid];
-    act[tid] = (tid < reff && G[tid * LD + tid] > 0.0) ? 1 : 0;
-  }
-  __syncthreads();
+  double g[RP];
+#pragma unroll
+  for (int i = 0; i < RP; ++i) g[i] = col ? G[i * RP + lane] : 0.0;
+  const double g0 = col ? G[lane * RP + lane] : 0.0;
   const double u = sizeof(TA) == 8 ? 0x1p-53 : 0x1p-24;
   const double tau = (double)RP * fmax(u * u, 0x1p-53);
-  for (int j = 0; j < RP; ++j) {
-    if (tid == 0) {
-      if (act[j]) {
-        const double piv = G[j * LD + j];
-        if (piv > tau * G0[j]) {
-          R[j * LD + j] = sqrt(piv);
-        } else {
-          act[j] = 0;
-          R[j * LD + j] = 0.0;
-        }
-      }
+  int act = (col && lane < reff && g0 > 0.0) ? 1 : 0;
+  double rcol[RP];   // rcol[k] = R[k][lane]
+  double rdiag = 0.0;
+#pragma unroll
+  for (int k = 0; k < RP; ++k) {
+    const double piv = lane_bcast(g[k], k);
+    const double g0k = lane_bcast(g0, k);
+    const int actk = __builtin_amdgcn_readlane(act, k) && piv > tau * g0k;
+    if (lane == k) act = actk;
+    if (actk) {
+      const double rkk = sqrt(piv);
+      const double inv = 1.0 / rkk;
+      const double rkj = lane > k ? g[k] * inv : (lane == k ? rkk : 0.0);
+      if (lane == k) rdiag = rkk;
+      rcol[k] = rkj;
+#pragma unroll
+      for (int i = k + 1; i < RP; ++i) g[i] -= lane_bcast(rkj, i) * rkj;
+    } else {
+      rcol[k] = 0.0;
     }
-    __syncthreads();
-    if (act[j]) {
-      const double rjj = R[j * LD + j];
-      if (tid > j && tid < RP) R[j * LD + tid] = G[j * LD + tid] / rjj;
-      __syncthreads();
-      for (int e = tid; e < RP * RP; e += blockDim.x) {
-        const int a = e / RP, b = e % RP;
-        if (a > j && b > j) G[a * LD + b] -= R[j * LD + a] * R[j * LD + b];
-      }
-    }
-    __syncthreads();
   }
-  // Inverse of R restricted to the active columns (zero elsewhere), by a
-  // right-looking back substitution on [R | I]: step i fixes row i of the
-  // inverse, then removes it from the rows above (parallel over entries).
-  for (int e = tid; e < RP * RP; e += blockDim.x) {
-    const int i = e / RP, c = e % RP;
-    Ri[i * LD + c] = (i == c && act[c]) ? 1.0 : 0.0;
+  if (col) {
+#pragma unroll
+    for (int k = 0; k < RP; ++k) st->Rq[k * RP + lane] = rcol[k];
+    st->dinv[lane] = act ? 1.0 / rdiag : 0.0;
+  }
+  if (acc == nullptr) return;
+  // acc <- R acc (or R); lane j owns column j
+  double a[RP];
+  if (reset_acc) {
+#pragma unroll
+    for (int i = 0; i < RP; ++i) a[i] = rcol[i];
+  } else {
+    double b[RP];
+#pragma unroll
+    for (int l = 0; l < RP; ++l) b[l] = col ? acc[l * RP + lane] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = i; l < RP; ++l) s += lane_bcast(rcol[i], l) * b[l];
+      a[i] = s;
+    }
+  }
+  // R2 only enters through ratios of its singular values, so it may be
+  // rescaled by a power of two; T must keep its scale (B = B' T).
+  if (normalise) {
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < RP; ++i) mx = fmax(mx, fabs(a[i]));
+    mx = wave_max(mx);
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    const double sc = ldexp(1.0, -e);
+#pragma unroll
+    for (int i = 0; i < RP; ++i) a[i] *= sc;
+  }
+  if (col) {
+#pragma unroll
+    for (int i = 0; i < RP; ++i) acc[i * RP + lane] = a[i];
+  }
+}
+
+template <typename TA, int RP>
+__global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int64_t rows,
+                                                   double* __restrict__ Gpart,
+                                                   GramCtl* __restrict__ ctl, int chol,
+                                                   SmallState* st, double* acc, int reset_acc,
+                                                   int normalise) {
+  constexpr int RH = (RP + 1) / 2;    // tiles per side
+  constexpr int RW = 2 * RH;          // padded width
+  constexpr int NT = RH * RH;         // tiles
+  constexpr int NG = 256 / NT;        // row groups
+  constexpr int CH = kGramRows;
+  constexpr int E = RP * RP;
+  __shared__ double ps[CH * RW];
+  __shared__ double red[NG * NT * 4];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  const int tile = tid % NT, grp = tid / NT;
+  const bool active = grp < NG;
+  const int ta = 2 * (tile / RH), tb = 2 * (tile % RH);
+  // ---- partial of this block's rows ----
+  double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = (r0 + per) < rows ? (r0 + per) : rows;
+  for (int64_t i0 = r0; i0 < r1; i0 += CH) {
+    const int nr = (r1 - i0) < CH ? (int)(r1 - i0) : CH;
+    __syncthreads();
+    for (int e = tid; e < CH * RW; e += 256) {
+      const int row = e / RW, c = e % RW;
+      ps[e] = (row < nr && c < RP) ? (double)P[(i0 + row) * RP + c] : 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      for (int ii = grp; ii < nr; ii += NG) {
+        const double x0 = ps[ii * RW + ta], x1 = ps[ii * RW + ta + 1];
+        const double y0 = ps[ii * RW + tb], y1 = ps[ii * RW + tb + 1];
+        a00 = fma(x0, y0, a00);
+        a01 = fma(x0, y1, a01);
+        a10 = fma(x1, y0, a10);
+        a11 = fma(x1, y1, a11);
+      }
+    }
+  }
+  if (active) {
+    double* q = red + (grp * NT + tile) * 4;
+    q[0] = a00; q[1] = a01; q[2] = a10; q[3] = a11;
   }
   __syncthreads();
-  for (int i = RP - 1; i >= 0; --i) {
-    if (act[i]) {
-      const double d = 1.0 / R[i * LD + i];
-      if (tid < RP) Ri[i * LD + tid] *= d;
-      __syncthreads();
-      for (int e = tid; e < i * RP; e += blockDim.x) {
-        const int l = e / RP, c = e % RP;
-        Ri[l * LD + c] -= R[l * LD + i] * Ri[i * LD + c];
-      }
-    } else if (tid < RP) {
-      Ri[i * LD + tid] = 0.0;
-    }
-    __syncthreads();
+  for (int e = tid; e < E; e += 256) {
+    const int a = e / RP, b = e % RP;
+    const int t = (a / 2) * RH + b / 2, slot = (a & 1) * 2 + (b & 1);
+    double s = 0.0;
+    for (int q = 0; q < NG; ++q) s += red[(q * NT + t) * 4 + slot];
+    Gpart[(int64_t)blockIdx.x * E + e] = s;
   }
-  for (int e = tid; e < RP * RP; e += blockDim.x) {
-    const int i = e / RP, j = e % RP;
-    rinv_panel[e] = (TA)Ri[i * LD + j];
-    st->Rinv[e] = Ri[i * LD + j];
+  // ---- level 1: the last block of the group adds the group's partials ----
+  const int nb = (int)gridDim.x;
+  const int gi = (int)blockIdx.x / kGramGroup;
+  const int g0 = gi * kGramGroup;
+  const int gsz = (nb - g0) < kGramGroup ? (nb - g0) : kGramGroup;
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    flag = atomicAdd(&ctl->grp[gi], 1u) == (unsigned int)(gsz - 1);
   }
-  if (acc != nullptr) {
-    // acc <- R * acc (or R), then an exact power-of-two rescale.
-    if (!reset_acc)
-      for (int e = tid; e < RP * RP; e += blockDim.x) G[(e / RP) * LD + (e % RP)] = acc[e];
-    __syncthreads();
-    for (int e = tid; e < RP * RP; e += blockDim.x) {
-      const int i = e / RP, j = e % RP;
-      double s = 0.0;
-      if (reset_acc) {
-        s = R[i * LD + j];
-      } else {
-        for (int l = i; l < RP; ++l) s += R[i * LD + l] * G[l * LD + j];
-      }
-      A[i * LD + j] = s;
-    }
-    __syncthreads();
-    // R2 only enters through ratios of its singular values, so it may be
-    // rescaled; T must keep its scale (B = B' T).
-    if (normalise) pow2_normalise(A, RP, LD, red);
-    for (int e = tid; e < RP * RP; e += blockDim.x) acc[e] = A[(e / RP) * LD + (e % RP)];
+  __syncthreads();
+  if (!flag) return;
+  __threadfence();
+  for (int e = tid; e < E; e += 256) {
+    double v[kGramGroup];
+#pragma unroll
+    for (int q = 0; q < kGramGroup; ++q) v[q] = q < gsz ? Gpart[(int64_t)(g0 + q) * E + e] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGramGroup; ++q) s += v[q];
+    Gpart[(int64_t)(kGramMaxBlocks + gi) * E + e] = s;
   }
+  // ---- level 2: the last group leader adds the group sums ----
+  const int ngr = (nb + kGramGroup - 1) / kGramGroup;
+  __syncthreads();
+  if (tid == 0) {
+    ctl->grp[gi] = 0u;
+    __threadfence();
+    flag = atomicAdd(&ctl->top, 1u) == (unsigned int)(ngr - 1);
+  }
+  __syncthreads();
+  if (!flag) return;
+  __threadfence();
+  double* Gs = ps;   // E <= 1024 doubles fit in ps
+  for (int e = tid; e < E; e += 256) {
+    double v[kGramMaxBlocks / kGramGroup];
+#pragma unroll
+    for (int q = 0; q < kGramMaxBlocks / kGramGroup; ++q)
+      v[q] = q < ngr ? Gpart[(int64_t)(kGramMaxBlocks + q) * E + e] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGramMaxBlocks / kGramGroup; ++q) s += v[q];
+    Gs[e] = s;
+    Gpart[(int64_t)kGramFinal * E + e] = s;
+  }
+  if (tid == 0) ctl->top = 0u;
+  if (!chol) return;
+  __syncthreads();
+  if (tid >= 64) return;
+  wave_chol<TA, RP>(Gs, st, acc, reset_acc, normalise);
 }
 
 // Rotation threshold of the Jacobi sweeps: an off-diagonal entry below
@@ -311,7 +389,7 @@ __device__ void jacobi_svd_values(double* M, int n, double* out, double* cs, int
 // U_L = B' K' and L = U_L Q2^T.
 // ---------------------------------------------------------------------------
 template <typename TA, int RP>
-__global__ __launch_bounds__(256) void k_core(const double* __restrict__ Gpart,
+__global__ __launch_bounds__(kSmallThreads) void k_core(const double* __restrict__ Gpart,
                                               int nparts, SmallState* st, int p,
                                               double rank_tol, int t_identity,
                                               TA* k_panel) {
@@ -507,9 +585,11 @@ __global__ __launch_bounds__(256) void k_core(const double* __restrict__ Gpart,
 __global__ void k_small_init(SmallState* st, int r) {
   const int tid = threadIdx.x;
   for (int e = tid; e < kMaxRP * kMaxRP; e += blockDim.x) {
-    st->R2[e] = 0.0; st->T[e] = 0.0; st->Rinv[e] = 0.0; st->V[e] = 0.0; st->K[e] = 0.0;
+    st->R2[e] = 0.0; st->T[e] = 0.0; st->Rq[e] = 0.0; st->V[e] = 0.0; st->K[e] = 0.0;
   }
-  if (tid < kMaxRP) { st->sigma[tid] = 0.0; st->sv_c[tid] = 0.0; st->active[tid] = tid < r; }
+  if (tid < kMaxRP) {
+    st->sigma[tid] = 0.0; st->sv_c[tid] = 0.0; st->dinv[tid] = 0.0; st->active[tid] = tid < r;
+  }
   if (tid == 0) { st->r_eff = r; st->r_keep = r; st->flags = 0; st->v_valid = 0; }
 }
 
@@ -527,16 +607,21 @@ __global__ void k_small_init(SmallState* st, int r) {
     default: break;                                \
   }
 
-void launch_chol(const Launch& L, bool f64, int rp, const double* Gpart,
-                 int nparts, SmallState* st, double* acc, void* rinv_panel,
-                 int reset_acc, int normalise) {
+void launch_gram_tree(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
+                      double* Gpart, GramCtl* ctl, int chol, SmallState* st, double* acc,
+                      int reset_acc, int normalise) {
+  int64_t nb = (rows + kGramRows - 1) / kGramRows;
+  if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
+  if (nb < 1) nb = 1;
   GODEC_RP_SWITCH(rp, {
     if (f64)
-      hipLaunchKernelGGL((k_chol<double, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
-                         nparts, st, acc, (double*)rinv_panel, reset_acc, normalise);
+      hipLaunchKernelGGL((k_gram_tree<double, RP>), dim3((unsigned)nb), dim3(256), 0, L.stream,
+                         (const double*)P, rows, Gpart, ctl, chol, st, acc, reset_acc,
+                         normalise);
     else
-      hipLaunchKernelGGL((k_chol<float, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
-                         nparts, st, acc, (float*)rinv_panel, reset_acc, normalise);
+      hipLaunchKernelGGL((k_gram_tree<float, RP>), dim3((unsigned)nb), dim3(256), 0, L.stream,
+                         (const float*)P, rows, Gpart, ctl, chol, st, acc, reset_acc,
+                         normalise);
   });
 }
 
@@ -545,10 +630,10 @@ void launch_core(const Launch& L, bool f64, int rp, const double* Gpart,
                  int t_identity, void* k_panel) {
   GODEC_RP_SWITCH(rp, {
     if (f64)
-      hipLaunchKernelGGL((k_core<double, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
+      hipLaunchKernelGGL((k_core<double, RP>), dim3(1), dim3(kSmallThreads), 0, L.stream, Gpart,
                          nparts, st, p, rank_tol, t_identity, (double*)k_panel);
     else
-      hipLaunchKernelGGL((k_core<float, RP>), dim3(1), dim3(256), 0, L.stream, Gpart,
+      hipLaunchKernelGGL((k_core<float, RP>), dim3(1), dim3(kSmallThreads), 0, L.stream, Gpart,
                          nparts, st, p, rank_tol, t_identity, (float*)k_panel);
   });
 }
