@@ -101,6 +101,10 @@ struct godec_ctx {
   int64_t kc_a, nct_a, rc_b, nch_b;   // MFMA tiling
   // state
   int64_t iters_done = 0;
+  // BF16_REFINE: the FP32 working copy D is only read by the refinement
+  // iterations; it is rebuilt from X and S when one starts and kept in step
+  // from then on.  NATIVE: always in step.
+  bool d_native_valid = true;
   int cur = 0;
   std::vector<double> a1_host;
   // tracing
@@ -355,6 +359,15 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   const bool refine = mixed && total > 0 && t >= total - c->refine_iters;
   // ---- subspace chain: Q2 = orth((D^T D)^p A1), R2 tracked ----
   launch_copy_panel(L, c->f64, c->rp, c->A1, c->n, c->ldd, c->r, c->st, c->P0);
+  const int64_t kk = std::max<int64_t>(c->k, 1);
+  if (refine && !c->d_native_valid) {
+    // D = X - S_{t-1} in FP32 for the refinement passes
+    launch_init_d(L, F32, false, c->D, c->ldd, c->X, c->ldx, c->m, c->n, c->mpad);
+    if (c->iters_done > 0)
+      launch_update_d(L, F32, c->D, c->ldd, c->n, c->s_idx[c->cur], c->s_val[c->cur],
+                      c->s_x[c->cur], c->plan[c->cur], kk);
+    c->d_native_valid = true;
+  }
   // type of chain pass j (the refinement redoes the last one in FP32)
   auto chain_td = [&](int j) {
     return (mixed && !(refine && j == c->p - 1)) ? BF16 : native;
@@ -411,17 +424,19 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
     if (a.ev_a && a.ev_b) c->recs.push_back({PC_SEL_PASS, a.ev_a, a.ev_b});
   }
   launch_select(L, c->f64, c->rp, a);
-  // ---- D update ----
-  const int64_t kk = std::max<int64_t>(c->k, 1);
+  // ---- D update: restore X on the old support, X - S on the new one ----
+  const bool upd_native = c->d_native_valid;
   if (c->iters_done > 0) {
-    launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
-                    c->plan[prev], kk);
+    if (upd_native)
+      launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
+                      c->plan[prev], kk);
     if (mixed)
       launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
                       c->plan[prev], kk);
   }
-  launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
-                  c->plan[nxt], kk);
+  if (upd_native)
+    launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
+                    c->plan[nxt], kk);
   if (mixed)
     launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
                     c->plan[nxt], kk);
@@ -512,8 +527,12 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   hipError_t e = hipMemcpyAsync(c->A1, c->a1_host.data(), sizeof(double) * n * r,
                                 hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
-  launch_init_d(L, c->f64 ? F64 : F32, c->f64, c->D, c->ldd, X_dev, ldx, m, n, c->mpad);
-  if (c->D16) launch_init_d(L, BF16, false, c->D16, c->ldd, X_dev, ldx, m, n, c->mpad);
+  if (c->D16) {
+    launch_init_d(L, BF16, false, c->D16, c->ldd, X_dev, ldx, m, n, c->mpad);
+    c->d_native_valid = false;
+  } else {
+    launch_init_d(L, c->f64 ? F64 : F32, c->f64, c->D, c->ldd, X_dev, ldx, m, n, c->mpad);
+  }
   launch_small_init(L, c->st, r);
   // zero the small scalars, plans and the (unused) panel padding
   e = hipMemsetAsync(c->norm_x2, 0, 8, c->stream);

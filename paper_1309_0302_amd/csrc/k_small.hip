@@ -55,6 +55,25 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ P, int np
 // dinv = 0, so the orthonormalised panel has a zero column, which stays zero
 // in every later product.
 // ---------------------------------------------------------------------------
+// Cross-block hand-off without a device-wide cache write-back: partial
+// results are stored write-through at device (agent) scope and read back
+// with device-scope loads; a block waits for its stores to complete before
+// it signals arrival with a device-scope atomic.
+__device__ __forceinline__ void publish(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void publish_u32(unsigned int* p, unsigned int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double fetch(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned int arrive(unsigned int* p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt left at their maxima)
+__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 __device__ __forceinline__ double lane_bcast(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
@@ -197,54 +216,50 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
     const int t = (a / 2) * RH + b / 2, slot = (a & 1) * 2 + (b & 1);
     double s = 0.0;
     for (int q = 0; q < NG; ++q) s += red[(q * NT + t) * 4 + slot];
-    Gpart[(int64_t)blockIdx.x * E + e] = s;
+    publish(Gpart + (int64_t)blockIdx.x * E + e, s);
   }
   // ---- level 1: the last block of the group adds the group's partials ----
   const int nb = (int)gridDim.x;
   const int gi = (int)blockIdx.x / kGramGroup;
   const int g0 = gi * kGramGroup;
   const int gsz = (nb - g0) < kGramGroup ? (nb - g0) : kGramGroup;
+  stores_done();
   __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    flag = atomicAdd(&ctl->grp[gi], 1u) == (unsigned int)(gsz - 1);
-  }
+  if (tid == 0) flag = arrive(&ctl->grp[gi]) == (unsigned int)(gsz - 1);
   __syncthreads();
   if (!flag) return;
-  __threadfence();
   for (int e = tid; e < E; e += 256) {
     double v[kGramGroup];
 #pragma unroll
-    for (int q = 0; q < kGramGroup; ++q) v[q] = q < gsz ? Gpart[(int64_t)(g0 + q) * E + e] : 0.0;
+    for (int q = 0; q < kGramGroup; ++q) v[q] = q < gsz ? fetch(Gpart + (int64_t)(g0 + q) * E + e) : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < kGramGroup; ++q) s += v[q];
-    Gpart[(int64_t)(kGramMaxBlocks + gi) * E + e] = s;
+    publish(Gpart + (int64_t)(kGramMaxBlocks + gi) * E + e, s);
   }
   // ---- level 2: the last group leader adds the group sums ----
   const int ngr = (nb + kGramGroup - 1) / kGramGroup;
+  stores_done();
   __syncthreads();
   if (tid == 0) {
-    ctl->grp[gi] = 0u;
-    __threadfence();
-    flag = atomicAdd(&ctl->top, 1u) == (unsigned int)(ngr - 1);
+    publish_u32(&ctl->grp[gi], 0u);
+    flag = arrive(&ctl->top) == (unsigned int)(ngr - 1);
   }
   __syncthreads();
   if (!flag) return;
-  __threadfence();
   double* Gs = ps;   // E <= 1024 doubles fit in ps
   for (int e = tid; e < E; e += 256) {
     double v[kGramMaxBlocks / kGramGroup];
 #pragma unroll
     for (int q = 0; q < kGramMaxBlocks / kGramGroup; ++q)
-      v[q] = q < ngr ? Gpart[(int64_t)(kGramMaxBlocks + q) * E + e] : 0.0;
+      v[q] = q < ngr ? fetch(Gpart + (int64_t)(kGramMaxBlocks + q) * E + e) : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < kGramMaxBlocks / kGramGroup; ++q) s += v[q];
     Gs[e] = s;
     Gpart[(int64_t)kGramFinal * E + e] = s;
   }
-  if (tid == 0) ctl->top = 0u;
+  if (tid == 0) publish_u32(&ctl->top, 0u);
   if (!chol) return;
   __syncthreads();
   if (tid >= 64) return;
