@@ -127,6 +127,10 @@ def brp_power(D: np.ndarray, A1: np.ndarray, q: int,
     m, n = D.shape
     p = 2 * q + 1
     r = A1.shape[1]
+    if r == 0:
+        # an earlier rank check left no column (reading R5): L = 0
+        return BrpResult(np.zeros((m, n)), np.zeros((m, 0)), np.zeros((n, 0)), 0,
+                         np.zeros(0), np.zeros(0))
     while True:
         Z, R2 = np.linalg.qr(A1[:, :r])
         for _ in range(p):
@@ -169,6 +173,9 @@ def brp_power_literal(D: np.ndarray, A1: np.ndarray, q: int,
     m, n = D.shape
     p = 2 * q + 1
     r = A1.shape[1]
+    if r == 0:
+        return BrpResult(np.zeros((m, n)), np.zeros((m, 0)), np.zeros((n, 0)), 0,
+                         np.zeros(0), np.zeros(0))
     while True:
         A = A1[:, :r]
         Y1 = ltilde_apply(D, A, q)

@@ -164,3 +164,16 @@ def test_default_rank_rule_is_on_the_scale_of_c():
     assert g.brp_power(X, A1, 2).r_eff == 4
     assert g.brp_power_literal(X, A1, 2).r_eff == 4
     assert g.brp_power(X, A1, 0).r_eff == 5
+
+
+def test_rank_zero_carry_gives_zero_L():
+    """After a rank drop to 0 the next steps run with no column of A1 (reading
+    R5): L = 0, and the loop keeps S = the top-k of X."""
+    D = np.zeros((30, 20))
+    A1 = np.random.default_rng(0).standard_normal((20, 3))
+    res = g.brp_power(D, A1, 1)
+    assert res.r_eff == 0 and not res.L.any()
+    res0 = g.brp_power(D, A1[:, :0], 1)
+    assert res0.r_eff == 0 and res0.L.shape == (30, 20) and not res0.L.any()
+    lit = g.brp_power_literal(D, A1[:, :0], 2)
+    assert lit.r_eff == 0 and not lit.L.any()
