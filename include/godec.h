@@ -193,6 +193,75 @@ godec_status godec_profile(godec_ctx* ctx, int32_t enable);
 godec_status godec_profile_read(godec_ctx* ctx, godec_kernel_stat* out,
                                 int32_t cap, int32_t* count);
 
+/* ---- Batched form: many independent FP32 problems ----------------------
+ * Runs Algorithm 1 (Sec. 3.1.3) on `count` independent problems at once: every
+ * phase of an iteration (the Gram passes of the power scheme, Eq. 6-9; the
+ * Cholesky QR steps; the r x r core; the top-k step of Eq. 4) is one launch
+ * over all problems, and one iteration's launches are captured once into a
+ * HIP graph that godec_batch_step replays.  The same readings as the
+ * single-problem form apply (A1 drawn once per problem from its seed, the
+ * rank check, ties by row-major index, zeros never selected).
+ * Limits: FP32 only; r <= 8; n <= 512 columns (the batched Gram pass keeps a
+ * whole row of the problem in on-chip memory).  Each problem's S list has
+ * capacity k and its candidate buffer m * n entries (all in the workspace).
+ * An autotuner times the Gram pass for several row counts per work item
+ * during godec_batch_init and keeps the fastest (godec_batch_tuning). */
+typedef struct {
+  const void* X_dev;      /* m x n FP32, leading dimension ldx (borrowed) */
+  int64_t m, n, ldx;
+  int32_t r;              /* 1 <= r <= min(8, m, n) */
+  int32_t reserved;
+  int64_t k;              /* 0 <= k <= m * n */
+  uint64_t seed;          /* seed of this problem's A1 (godec_draw_a1) */
+} godec_problem;
+
+typedef struct godec_batch godec_batch;
+
+/* Workspace bytes for the batch.  Errors as godec_workspace_size, plus
+ * GODEC_E_UNSUPPORTED for r > 8 or n > 512, GODEC_E_INVAL for count < 1. */
+godec_status godec_batch_workspace_size(const godec_problem* probs, int32_t count, int32_t q,
+                                        const godec_opts* opts, size_t* bytes);
+
+/* Set up the batch (FP32 X only; opts->prec must be NATIVE; opts->a1_host is
+ * ignored).  Draws every A1, copies X to the working copies, checks X for
+ * NaN/Inf (GODEC_E_NUMERIC), runs the autotuner and captures the iteration
+ * graph.  Synchronises the stream.  opts->stream must not be NULL (a graph
+ * cannot be captured on the legacy default stream); NULL gives E_INVAL. */
+godec_status godec_batch_init(godec_batch** out, const godec_problem* probs, int32_t count,
+                              int32_t q, void* workspace_dev, size_t workspace_bytes,
+                              const godec_opts* opts);
+
+/* Run `iters` iterations on every problem (graph replays; asynchronous). */
+godec_status godec_batch_step(godec_batch* b, int32_t iters);
+
+/* The same iterations enqueued as ordinary launches instead of graph
+ * replays (test hook: graph and eager runs must agree bit for bit). */
+godec_status godec_batch_step_eager(godec_batch* b, int32_t iters);
+
+/* Problem i: L = UL * VL^T (UL_dev m x r, VL_dev n x r, FP32, row-major;
+ * columns past rank_eff are zero).  Asynchronous. */
+godec_status godec_batch_get_factors(godec_batch* b, int32_t i, void* UL_dev, void* VL_dev);
+
+/* Problem i: S as ascending linear indices and values (capacity k each).
+ * Synchronous; *nnz_host receives the count. */
+godec_status godec_batch_get_S(godec_batch* b, int32_t i, int64_t* idx_dev, void* val_dev,
+                               int64_t* nnz_host);
+
+/* Problem i: the residual X - L the last selection used (m x n, ldr).  Async. */
+godec_status godec_batch_get_residual(godec_batch* b, int32_t i, void* R_dev, int64_t ldr);
+
+/* Problem i: its A1 (n x r, FP64) on the host.  Synchronous. */
+godec_status godec_batch_get_A1(godec_batch* b, int32_t i, double* a1_host);
+
+/* Problem i: state after the last iteration.  Synchronous. */
+godec_status godec_batch_get_info(godec_batch* b, int32_t i, godec_info* info);
+
+/* Rows per work item the autotuner chose and the number of work items. */
+godec_status godec_batch_tuning(godec_batch* b, int32_t* rows_per_item, int32_t* items);
+
+/* Release the handle and its graphs (the workspace stays the caller's). */
+godec_status godec_batch_destroy(godec_batch* b);
+
 /* Build information string (static storage). */
 const char* godec_version(void);
 

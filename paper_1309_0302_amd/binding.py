@@ -47,6 +47,13 @@ class godec_kernel_stat(ctypes.Structure):
                 ("bytes_per_launch", ctypes.c_double)]
 
 
+class godec_problem(ctypes.Structure):
+    _fields_ = [("X_dev", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("ldx", ctypes.c_int64),
+                ("r", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("k", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
 class GodecError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -83,6 +90,20 @@ _SIG = {
     "godec_profile": (_I32, [_P, _I32]),
     "godec_profile_read": (_I32, [_P, ctypes.POINTER(godec_kernel_stat), _I32,
                                   ctypes.POINTER(_I32)]),
+    "godec_batch_workspace_size": (_I32, [ctypes.POINTER(godec_problem), _I32, _I32,
+                                          ctypes.POINTER(godec_opts),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "godec_batch_init": (_I32, [ctypes.POINTER(_P), ctypes.POINTER(godec_problem), _I32,
+                                _I32, _P, ctypes.c_size_t, ctypes.POINTER(godec_opts)]),
+    "godec_batch_step": (_I32, [_P, _I32]),
+    "godec_batch_step_eager": (_I32, [_P, _I32]),
+    "godec_batch_get_factors": (_I32, [_P, _I32, _P, _P]),
+    "godec_batch_get_S": (_I32, [_P, _I32, _P, _P, ctypes.POINTER(_I64)]),
+    "godec_batch_get_residual": (_I32, [_P, _I32, _P, _I64]),
+    "godec_batch_get_A1": (_I32, [_P, _I32, _P]),
+    "godec_batch_get_info": (_I32, [_P, _I32, ctypes.POINTER(godec_info)]),
+    "godec_batch_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "godec_batch_destroy": (_I32, [_P]),
 }
 
 
@@ -311,6 +332,164 @@ class GoDec:
         if getattr(self, "ctx", None) is not None:
             godec_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batched form -------------------------------------------------------------
+
+def _problems(specs):
+    arr = (godec_problem * len(specs))()
+    for i, (X, r, k, seed) in enumerate(specs):
+        arr[i].X_dev = X.data_ptr()
+        arr[i].m, arr[i].n = X.shape
+        arr[i].ldx = X.stride(0)
+        arr[i].r = r
+        arr[i].reserved = 0
+        arr[i].k = k
+        arr[i].seed = seed
+    return arr
+
+
+def godec_batch_workspace_size(probs, q, opts=None):
+    out = ctypes.c_size_t(0)
+    _check(load().godec_batch_workspace_size(probs, len(probs), q,
+                                             ctypes.byref(opts) if opts else None,
+                                             ctypes.byref(out)))
+    return out.value
+
+
+def godec_batch_init(probs, q, ws_ptr, ws_bytes, opts):
+    b = ctypes.c_void_p()
+    _check(load().godec_batch_init(ctypes.byref(b), probs, len(probs), q, ws_ptr,
+                                   ws_bytes, ctypes.byref(opts)))
+    return b
+
+
+def godec_batch_step(b, iters):
+    _check(load().godec_batch_step(b, iters))
+
+
+def godec_batch_step_eager(b, iters):
+    _check(load().godec_batch_step_eager(b, iters))
+
+
+def godec_batch_get_factors(b, i, ul_ptr, vl_ptr):
+    _check(load().godec_batch_get_factors(b, i, ul_ptr, vl_ptr))
+
+
+def godec_batch_get_S(b, i, idx_ptr, val_ptr):
+    nnz = _I64(0)
+    _check(load().godec_batch_get_S(b, i, idx_ptr, val_ptr, ctypes.byref(nnz)))
+    return nnz.value
+
+
+def godec_batch_get_residual(b, i, r_ptr, ldr):
+    _check(load().godec_batch_get_residual(b, i, r_ptr, ldr))
+
+
+def godec_batch_get_A1(b, i, n, r):
+    out = np.empty((n, r), dtype=np.float64)
+    _check(load().godec_batch_get_A1(b, i, out.ctypes.data))
+    return out
+
+
+def godec_batch_get_info(b, i):
+    info = godec_info()
+    _check(load().godec_batch_get_info(b, i, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def godec_batch_tuning(b):
+    rows, items = _I32(0), _I32(0)
+    _check(load().godec_batch_tuning(b, ctypes.byref(rows), ctypes.byref(items)))
+    return rows.value, items.value
+
+
+def godec_batch_destroy(b):
+    _check(load().godec_batch_destroy(b))
+
+
+class GoDecBatch:
+    """Many independent FP32 decompositions advanced together.
+
+    specs: list of (X, r, k, seed) with X a float32 device tensor.  The batch
+    runs on its own stream (a captured graph cannot use the default stream);
+    getters synchronise it before returning.
+    """
+
+    def __init__(self, specs, q, rank_tol=0.0, stream=None):
+        import torch
+        self.specs = specs
+        self.q = q
+        for X, _, _, _ in specs:
+            if not X.is_cuda or X.dtype != torch.float32 or X.stride(1) != 1:
+                raise ValueError("every X must be a row-major float32 device tensor")
+        dev = specs[0][0].device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self.opts, _ = make_opts(rank_tol=rank_tol, stream=self.stream.cuda_stream)
+        self.probs = _problems(specs)
+        self.ws_bytes = godec_batch_workspace_size(self.probs, q, self.opts)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        base = (self.ws.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(dev)
+        self.b = godec_batch_init(self.probs, q, base, self.ws_bytes, self.opts)
+
+    def step(self, iters=1, eager=False):
+        (godec_batch_step_eager if eager else godec_batch_step)(self.b, iters)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def factors(self, i):
+        import torch
+        X, r = self.specs[i][0], self.specs[i][1]
+        m, n = X.shape
+        UL = torch.empty((m, r), dtype=torch.float32, device=X.device)
+        VL = torch.empty((n, r), dtype=torch.float32, device=X.device)
+        self.synchronize()
+        godec_batch_get_factors(self.b, i, UL.data_ptr(), VL.data_ptr())
+        self.synchronize()
+        return UL, VL
+
+    def S(self, i):
+        import torch
+        X, k = self.specs[i][0], self.specs[i][2]
+        kk = max(k, 1)
+        idx = torch.empty(kk, dtype=torch.int64, device=X.device)
+        val = torch.empty(kk, dtype=torch.float32, device=X.device)
+        self.synchronize()
+        nnz = godec_batch_get_S(self.b, i, idx.data_ptr(), val.data_ptr())
+        return idx[:nnz], val[:nnz]
+
+    def residual(self, i):
+        import torch
+        X = self.specs[i][0]
+        m, n = X.shape
+        R = torch.empty((m, n), dtype=torch.float32, device=X.device)
+        self.synchronize()
+        godec_batch_get_residual(self.b, i, R.data_ptr(), n)
+        self.synchronize()
+        return R
+
+    def A1(self, i):
+        X, r = self.specs[i][0], self.specs[i][1]
+        return godec_batch_get_A1(self.b, i, X.shape[1], r)
+
+    def info(self, i):
+        return godec_batch_get_info(self.b, i)
+
+    def tuning(self):
+        return godec_batch_tuning(self.b)
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            godec_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

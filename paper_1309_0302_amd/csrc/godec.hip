@@ -21,40 +21,14 @@
 
 #include "../../include/godec.h"
 #include "godec_internal.h"
+#include "host_common.h"
 
 using namespace godec;
+using namespace godec_host;
 
-namespace {
-
+namespace godec_host {
 thread_local std::string g_last_error;
-
-godec_status fail(godec_status s, const std::string& msg) {
-  g_last_error = msg;
-  return s;
-}
-
-#define HIP_TRY(expr)                                                        \
-  do {                                                                       \
-    hipError_t _e = (expr);                                                  \
-    if (_e != hipSuccess)                                                    \
-      return fail(GODEC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
-  } while (0)
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-// Bump allocator over the workspace (base == nullptr only measures).
-struct Carver {
-  char* base;
-  size_t off = 0;
-  void* take(size_t bytes) {
-    off = align_up(off, 256);
-    void* p = base ? base + off : nullptr;
-    off += bytes;
-    return p;
-  }
-};
-
-}  // namespace
+}  // namespace godec_host
 
 struct godec_ctx {
   // problem
@@ -468,7 +442,9 @@ godec_status godec_draw_a1(uint64_t seed, int64_t n, int32_t r, double* a1_host)
   return GODEC_OK;
 }
 
-static int device_cu_count() {
+}  // extern "C" (reopened below)
+
+int godec_host::device_cu_count() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
   int cu = 0;
@@ -476,6 +452,8 @@ static int device_cu_count() {
     return 256;
   return cu;
 }
+
+extern "C" {
 
 godec_status godec_workspace_size(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
                                   godec_dtype dtype, const godec_opts* opts, size_t* bytes) {

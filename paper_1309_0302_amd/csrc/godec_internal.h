@@ -213,4 +213,99 @@ void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd
 void launch_cast_panel(const Launch& L, bool f64, int rp, const void* src,
                        int64_t rows, int r, void* dst);
 
+
+// ---- batched form: many independent FP32 problems (k_batch.hip, k_small.hip) ----
+// Every phase of an iteration is one launch over all problems.  Streaming
+// phases walk a flat list of work items (a problem and a row range); the r x r
+// phases run one workgroup per problem.  Panels are kBatchRP = 8 columns
+// wide for every problem (columns at or past the problem's rank are zero).
+constexpr int kBatchRP = 8;
+constexpr int kBatchSub = 16;          // rows of D staged per step of a work item
+constexpr int kBatchMaxN = 512;        // widest problem (columns) a work item handles
+
+enum BSelMode : int { BS_COLLECT = 0, BS_REFINE = 1, BS_FINAL = 2, BS_NONE = 3 };
+
+struct BSel {                          // per-problem selection state
+  unsigned long long prefix;           // resolved high bits of the threshold key
+  long long k_rem;                     // entries still to take inside the bucket
+  long long count_above;               // entries above the bucket
+  unsigned long long ncand;            // candidates written (atomic)
+  unsigned long long nabove;           // S entries above the threshold (atomic)
+  unsigned long long nties;            // tied entries collected (atomic)
+  long long nnz;                       // entries of S_t
+  long long nnz_list[2];               // entries of each S list
+  int pbits;                           // resolved key bits
+  int mode;                            // BSelMode
+  double sum_r2;                       // ||X - L||_F^2
+  double sum_sel2;                     // sum of S_t^2
+  double threshold;                    // |R| of the k-th entry
+  double rel_err_sq;                   // (sum_r2 - sum_sel2) / ||X||_F^2
+  double norm_x2;                      // ||X||_F^2
+  int nonfinite;                       // NaN/Inf seen in X
+  int pad;
+};
+
+struct BProb {                         // device view of one problem
+  int64_t m, n, ldx, ldd, k;
+  double rank_tol;                     // rank check tolerance (r * 2^-52 by default)
+  int32_t r, item0;                    // rank bound; first work item of the problem
+  int32_t nitems, pad;                 // work items of the problem
+  const float* X;                      // m x ldx (caller's)
+  float* D;                            // m x ldd working copy of X - S
+  float* P0;                           // n x 8 panels
+  float* P1;
+  float* VL;                           // V_L = Q2
+  float* Bp;                           // m x 8: B' = D Y_q
+  float* UL;                           // m x 8: U_L = B' K'
+  float* Kp;                           // 8 x 8: K' = T K (FP32 copy)
+  const double* A1;                    // n x r
+  SmallState* st;
+  BSel* sel;
+  unsigned int* hist;                  // 4096 bins
+  int64_t* cand_idx;                   // cap = m n candidates
+  float* cand_val;
+  float* cand_x;
+  int64_t* tie_idx;                    // cap entries
+  int64_t* s_idx[2];                   // S lists (k entries each)
+  float* s_val[2];
+  float* s_x[2];
+};
+
+struct BItem {                         // one work item: rows [i0, i1) of a problem
+  int32_t prob, pad;
+  int64_t i0, i1;
+  int64_t zoff;                        // offset of its n x 8 partial in the slot array
+};
+
+struct BatchArgs {
+  const BProb* probs;
+  int nprob;
+  const BItem* items;
+  int nitems;
+  float* zslots;                       // Gram-pass partials (n x 8 per item)
+  double* gslots;                      // FP64 Gram partials of B' (8 x 8 per item)
+  int* iter;                           // device iteration counter
+  int q, p;
+};
+
+// chain
+void bl_copy_a1(const Launch& L, const BatchArgs& a, int64_t max_n);
+// in: panel pointer selector (0 = P0, 1 = P1, 2 = VL); mode 0 = Gram pass
+// (partials into zslots), 1 = W = D Y into Bp
+void bl_pass(const Launch& L, const BatchArgs& a, int in, int mode);
+// one workgroup per problem: out = orth(sum of the problem's partials) (or
+// of panel `in` when from_slots == 0), R folded into R2 (acc 0) or T (acc 1)
+void bl_chol(const Launch& L, const BatchArgs& a, int from_slots, int in, int out, int acc,
+             int reset);
+void bl_core(const Launch& L, const BatchArgs& a, int t_identity);
+void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m);
+// sparse step
+void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
+// (bl_update_d also advances the device iteration counter)
+void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
+void bl_init(const Launch& L, const BatchArgs& a);   // D = X, norms, state
+void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, float* R,
+                 int64_t ldr);
+void bl_small_init(const Launch& L, const BatchArgs& a);
+
 }  // namespace godec

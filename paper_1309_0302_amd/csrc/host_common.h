@@ -1,0 +1,44 @@
+// Host-side helpers shared by the single-problem and batched ABI files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/godec.h"
+
+namespace godec_host {
+
+// Message of the calling thread's last failure (godec_last_error).
+extern thread_local std::string g_last_error;
+
+inline godec_status fail(godec_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the workspace (base == nullptr only measures).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  void* take(size_t bytes) {
+    off = align_up(off, 256);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+int device_cu_count();
+
+}  // namespace godec_host
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess)                                                    \
+      return godec_host::fail(GODEC_E_DEVICE,                                \
+                              std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)

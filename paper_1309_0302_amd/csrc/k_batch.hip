@@ -1,0 +1,699 @@
+// Batched GoDec: many independent FP32 problems X_i (m_i x n_i, n_i small),
+// every phase of Algorithm 1 in one launch over all of them.
+//
+// Streaming phases walk a flat list of work items, each a problem and a
+// range of its rows; the problems' r x r work runs one workgroup per problem
+// (k_small.hip).  Panels are kBatchRP = 8 columns wide for every problem;
+// columns at or past a problem's rank stay zero.
+//
+// Gram pass (Algorithm 1's products with L~ and L~^T, Sec. 3.1.3): because
+// n_i is small, one work item holds a 16-row slab of D in LDS together with
+// the whole n x 8 panel Z, forms W = D_slab Z and immediately accumulates
+// D_slab^T W, so each pass reads D once (the single-problem path reads it
+// twice, since its panel is too long for LDS).
+//
+// Sparse step (Eq. 4): a level-0 histogram pass over every problem, a
+// collection pass of the entries at or above each problem's bucket, and the
+// remaining radix digits resolved over the candidates; ties at the threshold
+// are taken by row-major index, smallest first, and exact zeros are never
+// selected.
+#include "godec_internal.h"
+#include "k_common.h"
+
+#include <algorithm>
+
+namespace godec {
+
+constexpr int RP8 = kBatchRP;
+
+__device__ __forceinline__ const float* bpanel(const BProb& b, int which) {
+  return which == 0 ? b.P0 : (which == 1 ? b.P1 : b.VL);
+}
+
+// Residual entry with a fixed multiply-add order (selection, compaction and
+// the residual getter all use it).
+__device__ __forceinline__ float bresid(float x, const float* u, const float* v) {
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < RP8; ++c) s = fmaf(u[c], v[c], s);
+  return x - s;
+}
+
+__device__ __forceinline__ uint32_t fkey(float r) { return __float_as_uint(r) & 0x7fffffffu; }
+
+// ---------------------------------------------------------------------------
+// Chain kernels.
+// ---------------------------------------------------------------------------
+
+// P0 <- A1 (columns at or past r_eff zero).
+__global__ __launch_bounds__(256) void kb_copy_a1(const BProb* __restrict__ probs) {
+  const BProb& b = probs[blockIdx.y];
+  const int reff = b.st->r_eff;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= b.n * RP8) return;
+  const int64_t j = e / RP8;
+  const int c = (int)(e % RP8);
+  b.P0[e] = (c < reff && c < b.r) ? (float)b.A1[j * b.r + c] : 0.f;
+}
+
+// Gram pass (MODE 0): zslots[item] = D_rows^T (D_rows Z); apply (MODE 1):
+// Bp[rows] = D_rows Z and the FP64 Gram of those Bp rows into gslots[item].
+template <int MODE>
+__global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
+                                               const BItem* __restrict__ items, int in,
+                                               float* __restrict__ zslots,
+                                               double* __restrict__ gslots) {
+  constexpr int LDT = kBatchMaxN + 4;          // LDS row stride of the D slab
+  __shared__ float zt[RP8][kBatchMaxN];        // Z^T
+  __shared__ float dt[kBatchSub * LDT];        // D slab
+  __shared__ float w[kBatchSub][RP8];
+  const int tid = threadIdx.x;
+  const BItem it = items[blockIdx.x];
+  const BProb& b = probs[it.prob];
+  const int n = (int)b.n;
+  const int64_t ldd = b.ldd;
+  const int n4 = (int)((n + 3) / 4) * 4;
+  const float* Z = bpanel(b, in);
+  for (int e = tid; e < RP8 * kBatchMaxN; e += 256) {
+    const int c = e / kBatchMaxN, j = e % kBatchMaxN;
+    zt[c][j] = j < n ? Z[(int64_t)j * RP8 + c] : 0.f;
+  }
+  // Zout columns owned by this thread: j = tid and tid + 256
+  float acc[2][RP8];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int c = 0; c < RP8; ++c) acc[u][c] = 0.f;
+  double g = 0.0;                              // MODE 1: Gram entry tid < 64
+  const int ga = tid / RP8, gb = tid % RP8;
+  // phase (a) mapping: row i, column c, half h of the j range
+  const int ai = tid / 16, ac = (tid / 2) % RP8, ah = tid % 2;
+  const int q4 = (int)(ldd / 4);               // float4 per row
+  for (int64_t i0 = it.i0; i0 < it.i1; i0 += kBatchSub) {
+    const int nr = (it.i1 - i0) < kBatchSub ? (int)(it.i1 - i0) : kBatchSub;
+    __syncthreads();
+    for (int e = tid; e < kBatchSub * q4; e += 256) {
+      const int row = e / q4, c4 = e % q4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < nr) v = *reinterpret_cast<const float4*>(b.D + (i0 + row) * ldd + 4 * c4);
+      *reinterpret_cast<float4*>(&dt[row * LDT + 4 * c4]) = v;
+    }
+    __syncthreads();
+    // (a) W = D_slab Z
+    {
+      float s = 0.f;
+      for (int j = 4 * ah; j < n4; j += 8) {
+        const float4 d = *reinterpret_cast<const float4*>(&dt[ai * LDT + j]);
+        const float4 z = *reinterpret_cast<const float4*>(&zt[ac][j]);
+        s = fmaf(d.x, z.x, s);
+        s = fmaf(d.y, z.y, s);
+        s = fmaf(d.z, z.z, s);
+        s = fmaf(d.w, z.w, s);
+      }
+      s += __shfl_xor(s, 1, 64);
+      if (ah == 0) w[ai][ac] = s;
+    }
+    __syncthreads();
+    if constexpr (MODE == 0) {
+      // (b) Zout += D_slab^T W
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int j = tid + 256 * u;
+        if (j < n) {
+          for (int i = 0; i < nr; ++i) {
+            const float d = dt[i * LDT + j];
+            const float4 w0 = *reinterpret_cast<const float4*>(&w[i][0]);
+            const float4 w1 = *reinterpret_cast<const float4*>(&w[i][4]);
+            acc[u][0] = fmaf(d, w0.x, acc[u][0]);
+            acc[u][1] = fmaf(d, w0.y, acc[u][1]);
+            acc[u][2] = fmaf(d, w0.z, acc[u][2]);
+            acc[u][3] = fmaf(d, w0.w, acc[u][3]);
+            acc[u][4] = fmaf(d, w1.x, acc[u][4]);
+            acc[u][5] = fmaf(d, w1.y, acc[u][5]);
+            acc[u][6] = fmaf(d, w1.z, acc[u][6]);
+            acc[u][7] = fmaf(d, w1.w, acc[u][7]);
+          }
+        }
+      }
+    } else {
+      if (tid < nr * RP8) b.Bp[(i0 + tid / RP8) * RP8 + tid % RP8] = w[tid / RP8][tid % RP8];
+      if (tid < RP8 * RP8)
+        for (int i = 0; i < nr; ++i) g = fma((double)w[i][ga], (double)w[i][gb], g);
+    }
+  }
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = tid + 256 * u;
+      if (j < n)
+#pragma unroll
+        for (int c = 0; c < RP8; ++c) zslots[it.zoff + (int64_t)j * RP8 + c] = acc[u][c];
+    }
+  } else {
+    if (tid < RP8 * RP8) gslots[(int64_t)blockIdx.x * RP8 * RP8 + tid] = g;
+  }
+}
+
+// U_L = B' K' (m x 8).
+__global__ __launch_bounds__(256) void kb_apply_k(const BProb* __restrict__ probs) {
+  const BProb& b = probs[blockIdx.y];
+  __shared__ float ks[RP8 * RP8];
+  if (threadIdx.x < RP8 * RP8) ks[threadIdx.x] = b.Kp[threadIdx.x];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= b.m * RP8) return;
+  const int64_t i = e / RP8;
+  const int c = (int)(e % RP8);
+  float s = 0.f;
+#pragma unroll
+  for (int l = 0; l < RP8; ++l) s = fmaf(b.Bp[i * RP8 + l], ks[l * RP8 + c], s);
+  b.UL[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Full-data passes of the sparse step.  Threads own columns (their V_L rows
+// in registers); a block covers `rg` rows at once when the row is short.
+// ---------------------------------------------------------------------------
+struct ColMap {
+  int lanes;   // threads per row (multiple of 64, >= n unless two columns each)
+  int rg;      // rows processed together
+  int cpt;     // columns per thread (1 or 2)
+};
+
+__device__ __forceinline__ ColMap colmap(int n) {
+  ColMap cm;
+  const int r64 = ((n + 63) / 64) * 64;
+  if (r64 <= 256) {
+    cm.lanes = r64;
+    cm.rg = 256 / r64;
+    cm.cpt = 1;
+  } else {
+    cm.lanes = 256;
+    cm.rg = 1;
+    cm.cpt = 2;
+  }
+  return cm;
+}
+
+// KIND 0: level-0 histogram + sum of R^2 + NaN check; KIND 1: collect the
+// entries with key >= klo (klo >= 1) of problems in BS_COLLECT mode.
+template <int KIND>
+__global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
+                                                   const BItem* __restrict__ items) {
+  __shared__ unsigned int lh[kHistBins];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const BItem it = items[blockIdx.x];
+  const BProb& b = probs[it.prob];
+  BSel* sel = b.sel;
+  if (KIND == 1 && sel->mode == BS_NONE) return;
+  const int n = (int)b.n;
+  const ColMap cm = colmap(n);
+  const int rsub = tid / cm.lanes;
+  const int col0 = tid % cm.lanes;
+  uint32_t klo = 1u;
+  if (KIND == 1) {
+    const int pb = sel->pbits;
+    klo = (uint32_t)(sel->prefix << (31 - pb));
+    if (klo < 1u) klo = 1u;
+  } else {
+    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
+    __syncthreads();
+  }
+  float v[2][RP8];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = col0 + 256 * u;
+#pragma unroll
+    for (int c = 0; c < RP8; ++c) v[u][c] = (u < cm.cpt && j < n) ? b.VL[(int64_t)j * RP8 + c] : 0.f;
+  }
+  double s2 = 0.0;
+  int bad = 0;
+  for (int64_t i = it.i0 + rsub; i < it.i1 + rsub; i += cm.rg) {
+    // every thread runs the same number of trips so the ballots stay uniform
+    const bool rok = i < it.i1 && rsub < cm.rg;
+    float uu[RP8];
+#pragma unroll
+    for (int c = 0; c < RP8; ++c) uu[c] = rok ? b.UL[i * RP8 + c] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = col0 + 256 * u;
+      const bool ok = rok && u < cm.cpt && j < n;
+      const float x = ok ? b.X[i * b.ldx + j] : 0.f;
+      const float r = bresid(x, uu, v[u]);
+      const uint32_t key = fkey(r);
+      if (KIND == 0) {
+        if (ok) {
+          s2 += (double)r * (double)r;
+          atomicAdd(&lh[key >> (31 - kHistBits0)], 1u);
+          if (!isfinite(x)) bad = 1;
+        }
+      } else {
+        const bool take = ok && key >= klo;
+        const unsigned long long mask = __ballot(take);
+        if (mask) {
+          const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
+          const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+          const int leader = __ffsll((long long)mask) - 1;
+          unsigned long long base = 0;
+          if (take && rank == 0u) base = atomicAdd(&sel->ncand, (unsigned long long)__popcll(mask));
+          const unsigned int blo = __builtin_amdgcn_readlane((unsigned int)base, leader);
+          const unsigned int bhi = __builtin_amdgcn_readlane((unsigned int)(base >> 32), leader);
+          base = ((unsigned long long)bhi << 32) | blo;
+          if (take) {
+            const unsigned long long pos = base + rank;
+            b.cand_idx[pos] = i * (int64_t)n + j;
+            b.cand_val[pos] = r;
+            b.cand_x[pos] = x;
+          }
+        }
+      }
+    }
+  }
+  if (KIND == 0) {
+    __syncthreads();
+    for (int e = tid; e < kHistBins; e += 256)
+      if (lh[e]) atomicAdd(&b.hist[e], lh[e]);
+    s2 = wave_sum(s2);
+    if (lane == 0) red[wave] = s2;
+    if (bad) atomicOr(&sel->nonfinite, 1);
+    __syncthreads();
+    if (tid == 0) atomicAdd(&sel->sum_r2, red[0] + red[1] + red[2] + red[3]);
+  }
+}
+
+// Reset of the per-problem selection state (one workgroup per problem).
+__global__ __launch_bounds__(256) void kb_sel_reset(const BProb* __restrict__ probs) {
+  const BProb& b = probs[blockIdx.x];
+  for (int e = threadIdx.x; e < kHistBins; e += 256) b.hist[e] = 0u;
+  if (threadIdx.x == 0) {
+    BSel* s = b.sel;
+    s->prefix = 0; s->k_rem = b.k; s->count_above = 0; s->ncand = 0; s->nabove = 0;
+    s->nties = 0; s->nnz = 0; s->pbits = 0; s->mode = b.k > 0 ? BS_COLLECT : BS_NONE;
+    s->sum_r2 = 0.0; s->sum_sel2 = 0.0; s->threshold = 0.0;
+  }
+}
+
+// Digit selection over a histogram of `bins` counts (one workgroup per
+// problem): the digit holding the k_rem-th largest key, by a suffix scan.
+// level 0 follows the full-data histogram; later levels the candidates'.
+__global__ __launch_bounds__(256) void kb_sel_plan(const BProb* __restrict__ probs, int level) {
+  __shared__ unsigned long long h[kHistBins];
+  __shared__ unsigned long long part[256];
+  __shared__ int sel_t;
+  const BProb& b = probs[blockIdx.x];
+  BSel* s = b.sel;
+  const int tid = threadIdx.x;
+  if (s->mode == BS_NONE || (level > 0 && s->mode != BS_REFINE)) return;
+  const int pbits = s->pbits;
+  const int dbits = level == 0 ? kHistBits0 : (31 - pbits < kHistBits ? 31 - pbits : kHistBits);
+  const int bins = 1 << dbits;
+  const int per = (bins + 255) / 256;
+  for (int e = tid; e < bins; e += 256) {
+    h[e] = b.hist[e];
+    b.hist[e] = 0u;
+  }
+  __syncthreads();
+  unsigned long long acc = 0;
+  for (int u = 0; u < per; ++u) {
+    const int d = bins - 1 - (tid * per + u);
+    if (d >= 0) acc += h[d];
+  }
+  part[tid] = acc;
+  if (tid == 0) sel_t = -1;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned long long add = tid >= off ? part[tid - off] : 0ull;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  const long long k_rem = s->k_rem;
+  const unsigned long long before = tid > 0 ? part[tid - 1] : 0ull;
+  if (before < (unsigned long long)k_rem && part[tid] >= (unsigned long long)k_rem) sel_t = tid;
+  __syncthreads();
+  if (tid != 0) return;
+  int dsel = -1;
+  unsigned long long cum = 0;
+  if (sel_t >= 0) {
+    cum = sel_t > 0 ? part[sel_t - 1] : 0ull;
+    for (int u = 0; u < per; ++u) {
+      const int d = bins - 1 - (sel_t * per + u);
+      if (d < 0) break;
+      if (cum + h[d] >= (unsigned long long)k_rem) { dsel = d; break; }
+      cum += h[d];
+    }
+  }
+  if (dsel < 0) {
+    // fewer nonzero keys than k_rem: settle on digit 0 (zeros are excluded
+    // from the candidates)
+    dsel = 0;
+    cum = part[255] - h[0];
+  }
+  s->count_above += (long long)cum;
+  s->k_rem = k_rem - (long long)cum;
+  s->prefix = (s->prefix << dbits) | (unsigned long long)dsel;
+  s->pbits = pbits + dbits;
+  if (level == 0) s->mode = BS_COLLECT;
+  else s->mode = s->pbits == 31 ? BS_FINAL : BS_REFINE;
+}
+
+// After the collection pass: move to candidate refinement.
+__global__ __launch_bounds__(64) void kb_sel_to_refine(const BProb* __restrict__ probs,
+                                                       int nprob) {
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  if (p >= nprob) return;
+  BSel* s = probs[p].sel;
+  if (s->mode == BS_COLLECT) s->mode = s->pbits == 31 ? BS_FINAL : BS_REFINE;
+}
+
+// Histogram of the next digit over the candidates inside the bucket.
+__global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ probs) {
+  __shared__ unsigned int lh[1 << kHistBits];
+  const BProb& b = probs[blockIdx.y];
+  const BSel* s = b.sel;
+  if (s->mode != BS_REFINE) return;
+  const int pbits = s->pbits;
+  const int dbits = 31 - pbits < kHistBits ? 31 - pbits : kHistBits;
+  const unsigned long long prefix = s->prefix;
+  for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
+  __syncthreads();
+  const long long nc = (long long)s->ncand;
+  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < nc;
+       c += (long long)gridDim.x * 256) {
+    const uint32_t key = fkey(b.cand_val[c]);
+    if ((key >> (31 - pbits)) == prefix)
+      atomicAdd(&lh[(key >> (31 - pbits - dbits)) & ((1u << dbits) - 1)], 1u);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < (1 << dbits); e += 256)
+    if (lh[e]) atomicAdd(&b.hist[e], lh[e]);
+}
+
+// FINAL: entries above the threshold key go to S; entries equal to it go to
+// the tie list (as candidate positions).
+__global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ probs, int cur) {
+  __shared__ double red[4];
+  const BProb& b = probs[blockIdx.y];
+  BSel* s = b.sel;
+  if (s->mode != BS_FINAL) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tkey = (uint32_t)s->prefix;
+  const long long nc = (long long)s->ncand;
+  const long long kcap = s->count_above;
+  double s2 = 0.0;
+  const long long span = (nc + gridDim.x - 1) / gridDim.x;
+  const long long c0 = (long long)blockIdx.x * span;
+  const long long c1 = (c0 + span) < nc ? (c0 + span) : nc;
+  for (long long cb = c0; cb < c1; cb += 256) {
+    const long long c = cb + tid;
+    const bool valid = c < c1;
+    const float v = valid ? b.cand_val[c] : 0.f;
+    const uint32_t key = fkey(v);
+    const bool above = valid && key > tkey;
+    const bool tie = valid && key == tkey && tkey > 0;
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+      const bool take = kind == 0 ? above : tie;
+      const unsigned long long mask = __ballot(take);
+      if (!mask) continue;
+      const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
+      const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+      const int leader = __ffsll((long long)mask) - 1;
+      unsigned long long base = 0;
+      if (take && rank == 0u)
+        base = atomicAdd(kind == 0 ? &s->nabove : &s->nties, (unsigned long long)__popcll(mask));
+      const unsigned int blo = __builtin_amdgcn_readlane((unsigned int)base, leader);
+      const unsigned int bhi = __builtin_amdgcn_readlane((unsigned int)(base >> 32), leader);
+      base = ((unsigned long long)bhi << 32) | blo;
+      if (take) {
+        const unsigned long long pos = base + rank;
+        if (kind == 0) {
+          if ((long long)pos < kcap) {
+            b.s_idx[cur][pos] = b.cand_idx[c];
+            b.s_val[cur][pos] = v;
+            b.s_x[cur][pos] = b.cand_x[c];
+            s2 += (double)v * (double)v;
+          }
+        } else {
+          b.tie_idx[pos] = c;
+        }
+      }
+    }
+  }
+  s2 = wave_sum(s2);
+  if (lane == 0) red[wave] = s2;
+  __syncthreads();
+  if (tid == 0) atomicAdd(&s->sum_sel2, red[0] + red[1] + red[2] + red[3]);
+}
+
+// Ties: keep the k_rem smallest linear indices among the candidates equal to
+// the threshold (bitonic sort in LDS when they fit, else a radix select on
+// the index).  One workgroup per problem.  Also sets nnz, the threshold and
+// the objective.
+__global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs, int cur) {
+  constexpr int NS = 4096;
+  __shared__ unsigned long long sk[NS];     // linear indices
+  __shared__ int sp[NS];                    // their tie-list slots
+  __shared__ unsigned int cnt[256];
+  __shared__ unsigned long long sh_pref;
+  __shared__ long long sh_need;
+  __shared__ unsigned int wpos;
+  const BProb& b = probs[blockIdx.x];
+  BSel* s = b.sel;
+  const int tid = threadIdx.x;
+  if (s->mode == BS_NONE) {
+    if (tid == 0) {
+      s->nnz = 0;
+      s->nnz_list[cur] = 0;
+      s->threshold = 0.0;
+      s->rel_err_sq = s->norm_x2 > 0.0 ? s->sum_r2 / s->norm_x2 : 0.0;
+    }
+    return;
+  }
+  if (s->mode != BS_FINAL) return;
+  const uint32_t tkey = (uint32_t)s->prefix;
+  const long long nabove = s->count_above;
+  const long long nties = (long long)s->nties;
+  long long take = tkey > 0 ? s->k_rem : 0;
+  if (take > nties) take = nties;
+  const float tval = __uint_as_float(tkey);
+  if (take == nties) {
+    for (long long e = tid; e < take; e += blockDim.x) {
+      const long long c = b.tie_idx[e];
+      b.s_idx[cur][nabove + e] = b.cand_idx[c];
+      b.s_val[cur][nabove + e] = b.cand_val[c];
+      b.s_x[cur][nabove + e] = b.cand_x[c];
+    }
+  } else if (nties <= NS) {
+    for (int e = tid; e < NS; e += blockDim.x) {
+      if (e < nties) {
+        const long long c = b.tie_idx[e];
+        sk[e] = (unsigned long long)b.cand_idx[c];
+        sp[e] = (int)e;
+      } else {
+        sk[e] = ~0ull;
+        sp[e] = -1;
+      }
+    }
+    __syncthreads();
+    for (int size = 2; size <= NS; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int e = tid; e < NS; e += blockDim.x) {
+          const int o = e ^ stride;
+          if (o > e) {
+            const bool up = (e & size) == 0;
+            const unsigned long long a = sk[e], c = sk[o];
+            if ((a > c) == up) {
+              sk[e] = c; sk[o] = a;
+              const int t = sp[e]; sp[e] = sp[o]; sp[o] = t;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (long long e = tid; e < take; e += blockDim.x) {
+      const long long c = b.tie_idx[sp[e]];
+      b.s_idx[cur][nabove + e] = b.cand_idx[c];
+      b.s_val[cur][nabove + e] = b.cand_val[c];
+      b.s_x[cur][nabove + e] = b.cand_x[c];
+    }
+  } else {
+    // radix select of the take-th smallest linear index, 8 bits at a time
+    if (tid == 0) { sh_pref = 0; sh_need = take; }
+    __syncthreads();
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      if (tid < 256) cnt[tid] = 0u;
+      __syncthreads();
+      const unsigned long long pref = sh_pref;
+      for (long long e = tid; e < nties; e += blockDim.x) {
+        const unsigned long long x = (unsigned long long)b.cand_idx[b.tie_idx[e]];
+        if (shift == 56 || (x >> (shift + 8)) == pref) atomicAdd(&cnt[(x >> shift) & 255], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const long long need = sh_need;
+        unsigned long long cum = 0;
+        int d = 0;
+        for (; d < 256; ++d) {
+          if ((long long)(cum + cnt[d]) >= need) break;
+          cum += cnt[d];
+        }
+        sh_need = need - (long long)cum;
+        sh_pref = (pref << 8) | (unsigned long long)d;
+      }
+      __syncthreads();
+    }
+    const unsigned long long lim = sh_pref;
+    if (tid == 0) wpos = 0u;
+    __syncthreads();
+    for (long long e = tid; e < nties; e += blockDim.x) {
+      const long long c = b.tie_idx[e];
+      const unsigned long long x = (unsigned long long)b.cand_idx[c];
+      if (x <= lim) {
+        const unsigned int p = atomicAdd(&wpos, 1u);
+        b.s_idx[cur][nabove + p] = (int64_t)x;
+        b.s_val[cur][nabove + p] = b.cand_val[c];
+        b.s_x[cur][nabove + p] = b.cand_x[c];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s->nnz = nabove + take;
+    s->nnz_list[cur] = nabove + take;
+    s->threshold = (double)tval;
+    s->sum_sel2 += (double)take * (double)tval * (double)tval;
+    s->rel_err_sq = s->norm_x2 > 0.0 ? (s->sum_r2 - s->sum_sel2) / s->norm_x2 : 0.0;
+  }
+}
+
+// D <- X on the old support (restore) or X - S on the new one.
+__global__ __launch_bounds__(256) void kb_update_d(const BProb* __restrict__ probs,
+                                                   const int* __restrict__ iter, int list,
+                                                   int restore) {
+  const BProb& b = probs[blockIdx.y];
+  if (restore && *iter == 0) return;
+  const long long nnz = b.sel->nnz_list[list];
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nnz;
+       e += (long long)gridDim.x * 256) {
+    const int64_t idx = b.s_idx[list][e];
+    const int64_t i = idx / b.n, j = idx % b.n;
+    const float x = b.s_x[list][e];
+    b.D[i * b.ldd + j] = restore ? x : x - b.s_val[list][e];
+  }
+}
+
+// D = X (rows of the item), ||X||_F^2 and the NaN/Inf check.
+__global__ __launch_bounds__(256) void kb_init_d(const BProb* __restrict__ probs,
+                                                 const BItem* __restrict__ items) {
+  __shared__ double red[4];
+  const BItem it = items[blockIdx.x];
+  const BProb& b = probs[it.prob];
+  const int tid = threadIdx.x;
+  double s2 = 0.0;
+  int bad = 0;
+  const int64_t rows = it.i1 - it.i0;
+  for (int64_t e = tid; e < rows * b.ldd; e += 256) {
+    const int64_t i = it.i0 + e / b.ldd, j = e % b.ldd;
+    float x = 0.f;
+    if (j < b.n) {
+      x = b.X[i * b.ldx + j];
+      s2 += (double)x * (double)x;
+      if (!isfinite(x)) bad = 1;
+    }
+    b.D[i * b.ldd + j] = x;
+  }
+  s2 = wave_sum(s2);
+  if ((tid & 63) == 0) red[tid >> 6] = s2;
+  if (bad) atomicOr(&b.sel->nonfinite, 1);
+  __syncthreads();
+  if (tid == 0) atomicAdd(&b.sel->norm_x2, red[0] + red[1] + red[2] + red[3]);
+}
+
+// Residual R = X - U_L V_L^T of one problem (getter).
+__global__ __launch_bounds__(256) void kb_residual(const BProb* __restrict__ prob, float* R,
+                                                   int64_t ldr) {
+  const BProb& b = *prob;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= b.m * b.n) return;
+  const int64_t i = e / b.n, j = e % b.n;
+  float u[RP8], v[RP8];
+#pragma unroll
+  for (int c = 0; c < RP8; ++c) { u[c] = b.UL[i * RP8 + c]; v[c] = b.VL[j * RP8 + c]; }
+  R[i * ldr + j] = bresid(b.X[i * b.ldx + j], u, v);
+}
+
+__global__ void kb_iter_inc(int* iter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *iter += 1;
+}
+
+}  // namespace godec
+
+namespace godec {
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+void bl_copy_a1(const Launch& L, const BatchArgs& a, int64_t max_n) {
+  dim3 grid((unsigned)((max_n * kBatchRP + 255) / 256), (unsigned)a.nprob);
+  hipLaunchKernelGGL(kb_copy_a1, grid, dim3(256), 0, L.stream, a.probs);
+}
+
+void bl_pass(const Launch& L, const BatchArgs& a, int in, int mode) {
+  if (mode == 0)
+    hipLaunchKernelGGL(kb_pass<0>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+                       a.items, in, a.zslots, a.gslots);
+  else
+    hipLaunchKernelGGL(kb_pass<1>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+                       a.items, in, a.zslots, a.gslots);
+}
+
+void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m) {
+  dim3 grid((unsigned)((max_m * kBatchRP + 255) / 256), (unsigned)a.nprob);
+  hipLaunchKernelGGL(kb_apply_k, grid, dim3(256), 0, L.stream, a.probs);
+}
+
+// Sparse step into S list `cur`, then the D update (restore list cur ^ 1,
+// write list cur).
+void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
+  const unsigned np = (unsigned)a.nprob;
+  hipLaunchKernelGGL(kb_sel_reset, dim3(np), dim3(256), 0, L.stream, a.probs);
+  hipLaunchKernelGGL(kb_sel_pass<0>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+                     a.items);
+  hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, 0);
+  hipLaunchKernelGGL(kb_sel_pass<1>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+                     a.items);
+  hipLaunchKernelGGL(kb_sel_to_refine, dim3((np + 63) / 64), dim3(64), 0, L.stream, a.probs,
+                     a.nprob);
+  // candidate blocks per problem: enough for the largest candidate list
+  unsigned cb = (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, (2 * max_k + 65535) / 65536));
+  for (int level = 1; level <= 2; ++level) {
+    hipLaunchKernelGGL(kb_cand_hist, dim3(cb, np), dim3(256), 0, L.stream, a.probs);
+    hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, level);
+  }
+  hipLaunchKernelGGL(kb_compact, dim3(cb, np), dim3(256), 0, L.stream, a.probs, cur);
+  hipLaunchKernelGGL(kb_ties, dim3(np), dim3(1024), 0, L.stream, a.probs, cur);
+}
+
+void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
+  const unsigned g = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, (max_k + 255) / 256));
+  hipLaunchKernelGGL(kb_update_d, dim3(g, (unsigned)a.nprob), dim3(256), 0, L.stream, a.probs,
+                     a.iter, cur ^ 1, 1);
+  hipLaunchKernelGGL(kb_update_d, dim3(g, (unsigned)a.nprob), dim3(256), 0, L.stream, a.probs,
+                     a.iter, cur, 0);
+  hipLaunchKernelGGL(kb_iter_inc, dim3(1), dim3(64), 0, L.stream, a.iter);
+}
+
+void bl_init(const Launch& L, const BatchArgs& a) {
+  hipLaunchKernelGGL(kb_init_d, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+                     a.items);
+}
+
+void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, float* R,
+                 int64_t ldr) {
+  const unsigned g = (unsigned)((m * n + 255) / 256);
+  hipLaunchKernelGGL(kb_residual, dim3(g), dim3(256), 0, L.stream, prob_dev, R, ldr);
+}
+
+}  // namespace godec

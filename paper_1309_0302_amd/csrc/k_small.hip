@@ -404,10 +404,8 @@ __device__ void jacobi_svd_values(double* M, int n, double* out, double* cs, int
 // U_L = B' K' and L = U_L Q2^T.
 // ---------------------------------------------------------------------------
 template <typename TA, int RP>
-__global__ __launch_bounds__(kSmallThreads) void k_core(const double* __restrict__ Gpart,
-                                              int nparts, SmallState* st, int p,
-                                              double rank_tol, int t_identity,
-                                              TA* k_panel) {
+__device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallState* st, int p,
+                          double rank_tol, int t_identity, TA* k_panel) {
   constexpr int LD = RP + 1;
   __shared__ double G[RP * LD];
   __shared__ double H[RP * LD];
@@ -597,6 +595,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_core(const double* __restrict
   }
 }
 
+template <typename TA, int RP>
+__global__ __launch_bounds__(kSmallThreads) void k_core(const double* __restrict__ Gpart,
+                                                        int nparts, SmallState* st, int p,
+                                                        double rank_tol, int t_identity,
+                                                        TA* k_panel) {
+  core_body<TA, RP>(Gpart, nparts, st, p, rank_tol, t_identity, k_panel);
+}
+
 __global__ void k_small_init(SmallState* st, int r) {
   const int tid = threadIdx.x;
   for (int e = tid; e < kMaxRP * kMaxRP; e += blockDim.x) {
@@ -655,6 +661,118 @@ void launch_core(const Launch& L, bool f64, int rp, const double* Gpart,
 
 void launch_small_init(const Launch& L, SmallState* st, int r) {
   hipLaunchKernelGGL(k_small_init, dim3(1), dim3(256), 0, L.stream, st, r);
+}
+
+}  // namespace godec
+
+namespace godec {
+
+// ---------------------------------------------------------------------------
+// Batched r x r work: one workgroup per problem, 8-column panels.
+// ---------------------------------------------------------------------------
+constexpr int RB = kBatchRP;
+
+__device__ __forceinline__ float* bpanel_rw(const BProb& b, int which) {
+  return which == 0 ? b.P0 : (which == 1 ? b.P1 : b.VL);
+}
+
+// out = orth(Z) by one Cholesky QR step with an FP64 Gram, Z = the sum of the
+// problem's Gram-pass partials (fixed order) or panel `in`; R folded into
+// R2 (acc 0, rescaled by powers of two) or T (acc 1).
+__global__ __launch_bounds__(256) void kb_chol(const BProb* __restrict__ probs,
+                                               const BItem* __restrict__ items,
+                                               const float* __restrict__ zslots, int from_slots,
+                                               int in, int out, int acc_sel, int reset) {
+  __shared__ float zs[kBatchMaxN * RB];
+  __shared__ double gp[4][RB * RB];
+  __shared__ double G[RB * RB];
+  __shared__ double rq[RB * RB];
+  __shared__ double di[RB];
+  const BProb& b = probs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = (int)b.n;
+  const int ne = n * RB;
+  if (from_slots) {
+    for (int e = tid; e < ne; e += 256) {
+      float s = 0.f;
+      for (int it = 0; it < b.nitems; ++it) s += zslots[items[b.item0 + it].zoff + e];
+      zs[e] = s;
+    }
+  } else {
+    const float* P = bpanel_rw(b, in);
+    for (int e = tid; e < ne; e += 256) zs[e] = P[e];
+  }
+  __syncthreads();
+  {
+    const int e = tid % (RB * RB), h = tid / (RB * RB);
+    const int a = e / RB, c = e % RB;
+    double s = 0.0;
+    for (int j = h; j < n; j += 4) s = fma((double)zs[j * RB + a], (double)zs[j * RB + c], s);
+    gp[h][e] = s;
+  }
+  __syncthreads();
+  if (tid < RB * RB) G[tid] = (gp[0][tid] + gp[1][tid]) + (gp[2][tid] + gp[3][tid]);
+  __syncthreads();
+  if (tid < 64) {
+    double* acc = acc_sel == 0 ? b.st->R2 : b.st->T;
+    wave_chol<float, RB>(G, b.st, acc, reset, acc_sel == 0 ? 1 : 0);
+  }
+  __syncthreads();
+  if (tid < RB * RB) rq[tid] = b.st->Rq[tid];
+  if (tid < RB) di[tid] = b.st->dinv[tid];
+  __syncthreads();
+  float* O = bpanel_rw(b, out);
+  for (int j = tid; j < n; j += 256) {
+    double x[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) {
+      double s = (double)zs[j * RB + c];
+#pragma unroll
+      for (int l = 0; l < c; ++l) s = fma(-x[l], rq[l * RB + c], s);
+      x[c] = s * di[c];
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c) O[j * RB + c] = (float)x[c];
+  }
+}
+
+// Core of the low-rank step per problem: the Gram of B' from the apply
+// pass's partials, then the shared FP64 core (rank certificate, Jacobi
+// eigen-solver, K' = T K into Kp).
+__global__ __launch_bounds__(kSmallThreads) void kb_core(const BProb* __restrict__ probs,
+                                                         const double* __restrict__ gslots,
+                                                         int p, int t_identity) {
+  const BProb& b = probs[blockIdx.x];
+  core_body<float, RB>(gslots + (int64_t)b.item0 * RB * RB, b.nitems, b.st, p, b.rank_tol,
+                       t_identity, b.Kp);
+}
+
+__global__ void kb_small_init(const BProb* __restrict__ probs) {
+  const BProb& b = probs[blockIdx.x];
+  SmallState* st = b.st;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kMaxRP * kMaxRP; e += blockDim.x) {
+    st->R2[e] = 0.0; st->T[e] = 0.0; st->Rq[e] = 0.0; st->V[e] = 0.0; st->K[e] = 0.0;
+  }
+  if (tid < kMaxRP) {
+    st->sigma[tid] = 0.0; st->sv_c[tid] = 0.0; st->dinv[tid] = 0.0; st->active[tid] = tid < b.r;
+  }
+  if (tid == 0) { st->r_eff = b.r; st->r_keep = b.r; st->flags = 0; st->v_valid = 0; }
+}
+
+void bl_chol(const Launch& L, const BatchArgs& a, int from_slots, int in, int out, int acc,
+             int reset) {
+  hipLaunchKernelGGL(kb_chol, dim3((unsigned)a.nprob), dim3(256), 0, L.stream, a.probs, a.items,
+                     a.zslots, from_slots, in, out, acc, reset);
+}
+
+void bl_core(const Launch& L, const BatchArgs& a, int t_identity) {
+  hipLaunchKernelGGL(kb_core, dim3((unsigned)a.nprob), dim3(kSmallThreads), 0, L.stream, a.probs,
+                     a.gslots, a.p, t_identity);
+}
+
+void bl_small_init(const Launch& L, const BatchArgs& a) {
+  hipLaunchKernelGGL(kb_small_init, dim3((unsigned)a.nprob), dim3(256), 0, L.stream, a.probs);
 }
 
 }  // namespace godec

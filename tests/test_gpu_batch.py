@@ -1,0 +1,183 @@
+"""GPU parity of the batched form against the FP64 oracle, through the C ABI.
+
+Each problem of a batch is checked like the single-problem form: before an
+iteration the batch's own S_{t-1} of that problem is read back, the oracle runs
+the low-rank step of Algorithm 1 on D = X - S_{t-1} with the problem's A1, and
+the batch's L_t must match (relative Frobenius, non-squared, 1e-5 in FP32).
+The support of S_t must equal, bit for bit, the hard threshold (Eq. 4, ties by
+row-major index, zeros excluded) of the batch's own residual of that problem.
+"""
+import numpy as np
+import pytest
+
+from oracle import godec_ref as g
+from paper_1309_0302_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).cuda()
+
+
+def batch_of(works, q, seeds=None):
+    from paper_1309_0302_amd.binding import GoDecBatch
+    specs = []
+    for i, w in enumerate(works):
+        seed = seeds[i] if seeds is not None else 100 + i
+        specs.append((dev(w.X), w.r, w.k, seed))
+    print(f"\n[batch] {len(specs)} problems, q={q}: "
+          + ", ".join(f"{w.X.shape[0]}x{w.X.shape[1]} r{w.r} k{w.k}" for w in works[:8])
+          + (" ..." if len(works) > 8 else ""), flush=True)
+    return GoDecBatch(specs, q)
+
+
+def S_dense(gb, i, shape):
+    idx, val = gb.S(i)
+    S = np.zeros(int(np.prod(shape)))
+    S[idx.cpu().numpy()] = val.cpu().numpy().astype(np.float64)
+    return S.reshape(shape)
+
+
+def check_problem(gb, i, w, q, S_prev, r_eff, tol=1e-5):
+    A1 = gb.A1(i)
+    ref = g.brp_power(w.X.astype(np.float64) - S_prev, A1[:, :r_eff], q, w.r * 2.0 ** -52)
+    UL, VL = gb.factors(i)
+    err = g.rel_fro_factors(UL.cpu().numpy().astype(np.float64),
+                            VL.cpu().numpy().astype(np.float64), ref.left, ref.right)
+    assert err <= tol, (i, err)
+    assert gb.info(i)["rank_eff"] == ref.r_eff, i
+    R = gb.residual(i).cpu().numpy()
+    ridx, rval = g.hard_threshold(R, w.k)
+    sidx, sval = gb.S(i)
+    sidx = sidx.cpu().numpy()
+    sval = sval.cpu().numpy()
+    assert np.array_equal(sidx, ridx), (i, sidx.size, ridx.size)
+    assert np.array_equal(sval.view(np.uint32), rval.astype(np.float32).view(np.uint32)), i
+    return err
+
+
+def per_step_batch(works, q, iters, check=None):
+    gb = batch_of(works, q)
+    check = range(len(works)) if check is None else check
+    worst = 0.0
+    for t in range(iters):
+        prev = {i: S_dense(gb, i, works[i].X.shape) for i in check}
+        reff = {i: gb.info(i)["rank_eff"] for i in check}
+        gb.step(1)
+        gb.synchronize()
+        for i in check:
+            worst = max(worst, check_problem(gb, i, works[i], q, prev[i], reff[i]))
+        print(f"[batch] iteration {t}: worst rel L err {worst:.2e}", flush=True)
+    return gb, worst
+
+
+def mixed_works(seed=11):
+    rng = np.random.default_rng(seed)
+    shapes = [(300, 40, 3), (517, 100, 8), (1200, 257, 5), (2049, 37, 1),
+              (640, 512, 8), (999, 129, 2), (333, 64, 4), (1500, 300, 6)]
+    works = []
+    for j, (m, n, r) in enumerate(shapes):
+        rho = float(rng.uniform(0.03, 0.10))
+        works.append(wl.tiny(m, n, r, rho=rho, seed=int(rng.integers(1 << 30)),
+                             dtype=np.float32, noise_std=0.03,
+                             factor_std=(1.0 / np.sqrt(r)) ** 0.5))
+    return works
+
+
+def test_batch_mixed_shapes_per_step():
+    per_step_batch(mixed_works(), 1, 3)
+
+
+def test_batch_q0_and_q2():
+    works = mixed_works(seed=12)[:4]
+    per_step_batch(works, 0, 2)
+    per_step_batch(works, 2, 2)
+
+
+def test_batch_graph_replays_match_eager():
+    """Graph replays (with eager work and synchronisations between them) give
+    the same bits as the same iterations launched one by one."""
+    works = mixed_works(seed=13)[:5]
+    ga = batch_of(works, 1)
+    gb = batch_of(works, 1)
+    for t in range(5):
+        ga.step(1)
+        gb.step(1, eager=True)
+        ga.synchronize()
+        gb.synchronize()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work
+    for i in range(len(works)):
+        ua, va = ga.factors(i)
+        ub, vb = gb.factors(i)
+        assert torch.equal(ua, ub) and torch.equal(va, vb), i
+        ia, sa = ga.S(i)
+        ib, sb = gb.S(i)
+        assert torch.equal(ia, ib) and torch.equal(sa, sb), i
+
+
+def test_batch_edge_cases():
+    rng = np.random.default_rng(5)
+    works = []
+    w = wl.tiny(200, 50, 3, seed=1, dtype=np.float32)
+    works.append(wl.Workload("k0", w.X, 3, 0, 1, 3, 1))                 # k = 0
+    w = wl.tiny(120, 40, 2, seed=2, dtype=np.float32)
+    works.append(wl.Workload("kmn", w.X, 2, 120 * 40, 1, 3, 2))         # k = mn
+    Xi = rng.integers(-3, 4, size=(256, 64)).astype(np.float32)          # ties
+    works.append(wl.Workload("ties", Xi, 2, 1000, 1, 3, 3))
+    U = rng.standard_normal((300, 2))
+    V = rng.standard_normal((80, 2))
+    works.append(wl.Workload("rankdef", (U @ V.T).astype(np.float32), 4, 50, 1, 3, 4))
+    works.append(wl.Workload("zeros", np.zeros((100, 30), np.float32), 2, 40, 1, 3, 5))
+    per_step_batch(works, 1, 3)
+
+
+def test_batch_single_problem():
+    per_step_batch(mixed_works(seed=14)[2:3], 1, 2)
+
+
+def test_batch_rejects_bad_problems():
+    from paper_1309_0302_amd.binding import GodecError
+    w = wl.tiny(100, 600, 2, seed=1, dtype=np.float32)
+    with pytest.raises(GodecError):
+        batch_of([w], 1)                         # n > 512
+    w = wl.tiny(100, 60, 9, seed=1, dtype=np.float32)
+    with pytest.raises(GodecError):
+        batch_of([w], 1)                         # r > 8
+    w = wl.tiny(100, 60, 2, seed=1, dtype=np.float32)
+    X = w.X.copy()
+    X[3, 4] = np.nan
+    with pytest.raises(GodecError):
+        batch_of([wl.Workload("nan", X, 2, 10, 1, 3, 1)], 1)
+
+
+def test_batch_w4_full_configuration_sampled():
+    """The 64-problem workload in the configuration the benchmark times; every
+    8th problem is checked per step for two iterations."""
+    works = wl.w4()
+    per_step_batch(works, 1, 2, check=range(0, 64, 8))
+
+
+def test_batch_trajectory_against_oracle():
+    """25 iterations of two W4-shaped problems against the oracle's own run."""
+    works = [w for w in wl.w4(count=12) if w.X.shape[0] <= 6000][:2]
+    gb = batch_of(works, 1)
+    gb.step(25)
+    gb.synchronize()
+    for i, w in enumerate(works):
+        ref = g.godec_brp(w.X.astype(np.float64), w.r, w.k, 1, gb.A1(i), 25,
+                          rank_tol=w.r * 2.0 ** -52)
+        UL, VL = gb.factors(i)
+        errL = g.rel_fro_factors(UL.cpu().numpy().astype(np.float64),
+                                 VL.cpu().numpy().astype(np.float64), ref.left, ref.right)
+        S = S_dense(gb, i, w.X.shape)
+        common = (S != 0) & (ref.S != 0)
+        errS = np.linalg.norm((S - ref.S)[common]) / np.linalg.norm(ref.S[common])
+        swaps = int(np.sum((S != 0) != (ref.S != 0)))
+        print(f"[batch] trajectory problem {i}: L {errL:.2e} S(common) {errS:.2e} "
+              f"swaps {swaps}", flush=True)
+        assert errL < 1e-5 and errS < 1e-5
+        assert swaps <= max(2, int(1e-4 * w.k))
