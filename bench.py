@@ -95,6 +95,52 @@ def roofline_of(stats):
             "launches": dom["launches"]}
 
 
+def run_batched(iters, warmup, seed=1004):
+    """The 64-problem workload (uneven shapes, q = 1) in the batched form:
+    `iters` graph-replayed iterations from S_0 = 0, timed on the batch's
+    stream with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GoDecBatch
+    works = workloads.w4(seed=seed)
+    specs = [(torch.from_numpy(w.X).cuda(), w.r, w.k, 100 + i) for i, w in enumerate(works)]
+    torch.cuda.synchronize()
+    if warmup > 0:
+        gb = GoDecBatch(specs, 1)
+        gb.step(warmup)
+        gb.synchronize()
+        gb.close()
+    gb = GoDecBatch(specs, 1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    gb.synchronize()
+    e0.record(gb.stream)
+    gb.step(iters)
+    e1.record(gb.stream)
+    gb.synchronize()
+    ms = e0.elapsed_time(e1)
+    rows, items = gb.tuning()
+    mn = sum(int(w.X.shape[0]) * int(w.X.shape[1]) for w in works)
+    # algorithmic bytes of one batch iteration: 2q+1 + q Gram passes, the
+    # B' pass and two selection passes, each reading every X or D once
+    passes = (2 * 1 + 1) + 1 + 1 + 2
+    bytes_iter = passes * mn * 4
+    rel = [gb.info(i)["rel_err_sq"] for i in range(len(works))]
+    gb.close()
+    ms_iter = ms / iters
+    achieved = bytes_iter / (ms_iter * 1e-3) / 1e9
+    return {"workload": f"w4_{len(works)}_problems_q1", "problems": len(works),
+            "sum_mn": mn, "iterations": iters,
+            "ms_per_iteration": round(ms_iter, 4),
+            "problem_iterations_per_s": round(len(works) * iters / (ms * 1e-3), 1),
+            "rows_per_item": rows, "work_items": items,
+            "algorithmic_bytes_per_iteration": bytes_iter,
+            "achieved_GBps": round(achieved, 1),
+            "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
+            "median_final_rel_err_sq": float(np.median(rel))}
+
+
 def cpu_baseline(w, iters):
     """The FP64 oracle on the host cores, `iters` iterations of the same X."""
     import numpy as np
@@ -126,6 +172,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-iters", type=int, default=25)
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
     args = ap.parse_args()
@@ -182,6 +230,10 @@ def main():
         out["rel_diff_L_bf16_refine_vs_fp32"] = rel_diff_factors(
             bf["UL"], bf["VL"], fp["UL"], fp["VL"])
     out["kernels"] = bf["stats"]
+    if not args.skip_batch:
+        log("[bench] batched form: 64 problems")
+        out["batched"] = run_batched(args.batch_iters, min(args.warmup, 3))
+        log(f"[bench] batched {out['batched']['ms_per_iteration']} ms/iteration")
     if not args.skip_cpu:
         log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)

@@ -53,6 +53,8 @@ struct godec_batch {
   int rows_per_item = 0;
   float* zslots = nullptr;
   double* gslots = nullptr;
+  unsigned int* seg_count = nullptr;
+  int max_items = 1;
   int* iter = nullptr;
   int64_t max_m = 0, max_n = 0, max_k = 0;
   hipGraph_t graph[2] = {nullptr, nullptr};
@@ -99,6 +101,7 @@ size_t carve_batch(godec_batch* b, void* base) {
   b->ditems = (BItem*)cv.take(sizeof(BItem) * items);
   b->zslots = (float*)cv.take(sizeof(float) * zfl);
   b->gslots = (double*)cv.take(sizeof(double) * items * kBatchRP * kBatchRP);
+  b->seg_count = (unsigned int*)cv.take(sizeof(unsigned int) * items);
   b->iter = (int*)cv.take(sizeof(int));
   b->tab.assign(b->count, BProb{});
   for (int i = 0; i < b->count; ++i) {
@@ -162,6 +165,8 @@ BatchArgs args_of(const godec_batch* b) {
   a.nitems = b->nitems;
   a.zslots = b->zslots;
   a.gslots = b->gslots;
+  a.seg_count = b->seg_count;
+  a.max_items = b->max_items;
   a.iter = b->iter;
   a.q = b->q;
   a.p = b->p;
@@ -174,6 +179,7 @@ godec_status set_items(godec_batch* b, int64_t rows) {
   HIP_TRY(hipStreamSynchronize(b->stream));   // earlier copies from b->items are done
   std::vector<BItem>& items = b->items;
   items.clear();
+  b->max_items = 1;
   int64_t zoff = 0;
   for (int i = 0; i < b->count; ++i) {
     const HostProb& h = b->hp[i];
@@ -189,6 +195,7 @@ godec_status set_items(godec_batch* b, int64_t rows) {
       items.push_back(it);
     }
     b->tab[i].nitems = (int32_t)(items.size() - b->tab[i].item0);
+    b->max_items = std::max(b->max_items, (int)b->tab[i].nitems);
   }
   if ((int64_t)items.size() > b->items_cap) return fail(GODEC_E_STATE, "work item overflow");
   b->nitems = (int)items.size();
@@ -206,13 +213,15 @@ void enqueue_iteration(godec_batch* b, int cur) {
   bl_copy_a1(L, a, b->max_n);
   for (int j = 0; j < b->p; ++j) {
     bl_pass(L, a, 0, 0);
-    bl_chol(L, a, 1, 0, 0, 0, j == 0);
+    bl_reduce_slots(L, a, b->max_n);
+    bl_chol(L, a, 0, 1, 0, 0, j == 0);
   }
   bl_chol(L, a, 0, 0, 2, 0, 0);   // second round: P0 -> V_L, R joins R2
   int in = 2;
   for (int j = 0; j < b->q; ++j) {
     bl_pass(L, a, in, 0);
-    bl_chol(L, a, 1, in, 0, 1, j == 0);
+    bl_reduce_slots(L, a, b->max_n);
+    bl_chol(L, a, 0, 1, 0, 1, j == 0);
     in = 0;
   }
   bl_pass(L, a, in, 1);
@@ -237,7 +246,10 @@ godec_status autotune(godec_batch* b) {
     const BatchArgs a = args_of(b);
     bl_pass(L, a, 0, 0);   // warm-up
     HIP_TRY(hipEventRecord(e0, b->stream));
-    for (int rep = 0; rep < 3; ++rep) bl_pass(L, a, 0, 0);
+    for (int rep = 0; rep < 3; ++rep) {
+      bl_pass(L, a, 0, 0);
+      bl_reduce_slots(L, a, b->max_n);
+    }
     HIP_TRY(hipEventRecord(e1, b->stream));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;

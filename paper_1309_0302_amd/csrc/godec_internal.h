@@ -282,6 +282,8 @@ struct BatchArgs {
   int nprob;
   const BItem* items;
   int nitems;
+  int max_items;                       // most work items of one problem
+  unsigned int* seg_count;             // candidates written per work item
   float* zslots;                       // Gram-pass partials (n x 8 per item)
   double* gslots;                      // FP64 Gram partials of B' (8 x 8 per item)
   int* iter;                           // device iteration counter
@@ -299,6 +301,8 @@ void bl_chol(const Launch& L, const BatchArgs& a, int from_slots, int in, int ou
              int reset);
 void bl_core(const Launch& L, const BatchArgs& a, int t_identity);
 void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m);
+// P1 = sum of each problem's Gram-pass partials
+void bl_reduce_slots(const Launch& L, const BatchArgs& a, int64_t max_n);
 // sparse step
 void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 // (bl_update_d also advances the device iteration counter)

@@ -58,100 +58,170 @@ __global__ __launch_bounds__(256) void kb_copy_a1(const BProb* __restrict__ prob
 
 // Gram pass (MODE 0): zslots[item] = D_rows^T (D_rows Z); apply (MODE 1):
 // Bp[rows] = D_rows Z and the FP64 Gram of those Bp rows into gslots[item].
+//
+// On the matrix cores, v_mfma_f32_16x16x4f32 (lane l: A row l%16 and B
+// column l%16 at k = l/16; accumulator register v holds C[4(l/16)+v][l%16]).
+// Per 16-row slab of D (in LDS):
+//   (a) W = D_slab Z (16 x 8): the 4 waves split the contraction over n in
+//       16-wide steps; a lane reads 4 consecutive k with one 16-byte load and
+//       feeds them to 4 MFMAs (same k order on both operands); the 4 partial
+//       W go through LDS.
+//   (b) Zout^T += W^T D_slab (8 x n): wave w owns column tiles w, w+4, ...
+//       of 16 columns, whose accumulators live across the whole work item.
+// The next slab is loaded into registers while the current one is used.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
                                                const BItem* __restrict__ items, int in,
                                                float* __restrict__ zslots,
                                                double* __restrict__ gslots) {
   constexpr int LDT = kBatchMaxN + 4;          // LDS row stride of the D slab
-  __shared__ float zt[RP8][kBatchMaxN];        // Z^T
-  __shared__ float dt[kBatchSub * LDT];        // D slab
-  __shared__ float w[kBatchSub][RP8];
-  const int tid = threadIdx.x;
+  constexpr int PF = kBatchSub * (kBatchMaxN / 4) / 256;   // prefetch float4 per thread
+  constexpr int MAXT = kBatchMaxN / 16 / 4;    // column tiles per wave
+  __shared__ float zt[RP8][kBatchMaxN];        // Z^T (zero past n)
+  __shared__ float dt[kBatchSub * LDT];        // D slab (zero past ldd)
+  __shared__ float wp[4][kBatchSub][RP8];      // per-wave partial W
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kg = lane >> 4;
   const BItem it = items[blockIdx.x];
   const BProb& b = probs[it.prob];
   const int n = (int)b.n;
   const int64_t ldd = b.ldd;
-  const int n4 = (int)((n + 3) / 4) * 4;
+  const int n16 = (n + 15) & ~15;
+  const int q4 = (int)(ldd / 4);
   const float* Z = bpanel(b, in);
   for (int e = tid; e < RP8 * kBatchMaxN; e += 256) {
     const int c = e / kBatchMaxN, j = e % kBatchMaxN;
     zt[c][j] = j < n ? Z[(int64_t)j * RP8 + c] : 0.f;
   }
-  // Zout columns owned by this thread: j = tid and tid + 256
-  float acc[2][RP8];
+  // columns [ldd, n16) of the slab are never loaded: zero them once
+  for (int e = tid; e < kBatchSub * 16; e += 256) {
+    const int row = e / 16, c = (int)ldd + e % 16;
+    if (c < n16) dt[row * LDT + c] = 0.f;
+  }
+  f32x4 acc[MAXT];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int c = 0; c < RP8; ++c) acc[u][c] = 0.f;
+  for (int t = 0; t < MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   double g = 0.0;                              // MODE 1: Gram entry tid < 64
   const int ga = tid / RP8, gb = tid % RP8;
-  // phase (a) mapping: row i, column c, half h of the j range
-  const int ai = tid / 16, ac = (tid / 2) % RP8, ah = tid % 2;
-  const int q4 = (int)(ldd / 4);               // float4 per row
-  for (int64_t i0 = it.i0; i0 < it.i1; i0 += kBatchSub) {
-    const int nr = (it.i1 - i0) < kBatchSub ? (int)(it.i1 - i0) : kBatchSub;
-    __syncthreads();
-    for (int e = tid; e < kBatchSub * q4; e += 256) {
+  float4 pf[PF];
+  auto prefetch = [&](int64_t i0, int nr) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + 256 * u;
       const int row = e / q4, c4 = e % q4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (row < nr) v = *reinterpret_cast<const float4*>(b.D + (i0 + row) * ldd + 4 * c4);
-      *reinterpret_cast<float4*>(&dt[row * LDT + 4 * c4]) = v;
+      pf[u] = v;
+    }
+  };
+  int nr = (it.i1 - it.i0) < kBatchSub ? (int)(it.i1 - it.i0) : kBatchSub;
+  prefetch(it.i0, nr);
+  for (int64_t i0 = it.i0; i0 < it.i1; i0 += kBatchSub) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + 256 * u;
+      if (e < kBatchSub * q4) {
+        const int row = e / q4, c4 = e % q4;
+        *reinterpret_cast<float4*>(&dt[row * LDT + 4 * c4]) = pf[u];
+      }
     }
     __syncthreads();
-    // (a) W = D_slab Z
-    {
-      float s = 0.f;
-      for (int j = 4 * ah; j < n4; j += 8) {
-        const float4 d = *reinterpret_cast<const float4*>(&dt[ai * LDT + j]);
-        const float4 z = *reinterpret_cast<const float4*>(&zt[ac][j]);
-        s = fmaf(d.x, z.x, s);
-        s = fmaf(d.y, z.y, s);
-        s = fmaf(d.z, z.z, s);
-        s = fmaf(d.w, z.w, s);
-      }
-      s += __shfl_xor(s, 1, 64);
-      if (ah == 0) w[ai][ac] = s;
+    const int cur_nr = nr;
+    const int64_t nx = i0 + kBatchSub;
+    if (nx < it.i1) {
+      nr = (it.i1 - nx) < kBatchSub ? (int)(it.i1 - nx) : kBatchSub;
+      prefetch(nx, nr);
+    }
+    // (a) partial W of this wave's k steps
+    f32x4 wa = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 16 * wave; k0 < n16; k0 += 64) {
+      const float4 av = *reinterpret_cast<const float4*>(&dt[li * LDT + k0 + 4 * kg]);
+      float4 bv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (li < RP8) bv = *reinterpret_cast<const float4*>(&zt[li][k0 + 4 * kg]);
+      wa = mfma16(av.x, bv.x, wa);
+      wa = mfma16(av.y, bv.y, wa);
+      wa = mfma16(av.z, bv.z, wa);
+      wa = mfma16(av.w, bv.w, wa);
+    }
+    if (li < RP8) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) wp[wave][4 * kg + v][li] = wa[v];
     }
     __syncthreads();
     if constexpr (MODE == 0) {
-      // (b) Zout += D_slab^T W
+      // (b) this lane's W^T operand: W[4 kg + s][li] for s = 0..3 (li < 8)
+      float wt[4];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int j = tid + 256 * u;
-        if (j < n) {
-          for (int i = 0; i < nr; ++i) {
-            const float d = dt[i * LDT + j];
-            const float4 w0 = *reinterpret_cast<const float4*>(&w[i][0]);
-            const float4 w1 = *reinterpret_cast<const float4*>(&w[i][4]);
-            acc[u][0] = fmaf(d, w0.x, acc[u][0]);
-            acc[u][1] = fmaf(d, w0.y, acc[u][1]);
-            acc[u][2] = fmaf(d, w0.z, acc[u][2]);
-            acc[u][3] = fmaf(d, w0.w, acc[u][3]);
-            acc[u][4] = fmaf(d, w1.x, acc[u][4]);
-            acc[u][5] = fmaf(d, w1.y, acc[u][5]);
-            acc[u][6] = fmaf(d, w1.z, acc[u][6]);
-            acc[u][7] = fmaf(d, w1.w, acc[u][7]);
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int i = 4 * kg + s2;
+        wt[s2] = (li < RP8 && i < cur_nr)
+                     ? (wp[0][i][li] + wp[1][i][li]) + (wp[2][i][li] + wp[3][i][li])
+                     : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        const int j0 = 16 * (wave + 4 * t);
+        if (j0 < n16) {
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) {
+            const int i = 4 * kg + s2;
+            acc[t] = mfma16(wt[s2], dt[i * LDT + j0 + li], acc[t]);
           }
         }
       }
     } else {
-      if (tid < nr * RP8) b.Bp[(i0 + tid / RP8) * RP8 + tid % RP8] = w[tid / RP8][tid % RP8];
-      if (tid < RP8 * RP8)
-        for (int i = 0; i < nr; ++i) g = fma((double)w[i][ga], (double)w[i][gb], g);
+      if (tid < cur_nr * RP8) {
+        const int i = tid / RP8, c = tid % RP8;
+        b.Bp[(i0 + i) * RP8 + c] = (wp[0][i][c] + wp[1][i][c]) + (wp[2][i][c] + wp[3][i][c]);
+      }
+      if (tid < RP8 * RP8) {
+        for (int i = 0; i < cur_nr; ++i) {
+          const float wa_ = (wp[0][i][ga] + wp[1][i][ga]) + (wp[2][i][ga] + wp[3][i][ga]);
+          const float wb_ = (wp[0][i][gb] + wp[1][i][gb]) + (wp[2][i][gb] + wp[3][i][gb]);
+          g = fma((double)wa_, (double)wb_, g);
+        }
+      }
     }
   }
   if constexpr (MODE == 0) {
+    // lane holds Zout^T[4 kg + v][j0 + li]; rows 0..7 are the panel columns
+    if (kg < 2) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int j = tid + 256 * u;
-      if (j < n)
+      for (int t = 0; t < MAXT; ++t) {
+        const int j = 16 * (wave + 4 * t) + li;
+        if (j < n) {
 #pragma unroll
-        for (int c = 0; c < RP8; ++c) zslots[it.zoff + (int64_t)j * RP8 + c] = acc[u][c];
+          for (int v = 0; v < 4; ++v) zslots[it.zoff + (int64_t)j * RP8 + 4 * kg + v] = acc[t][v];
+        }
+      }
     }
   } else {
     if (tid < RP8 * RP8) gslots[(int64_t)blockIdx.x * RP8 * RP8 + tid] = g;
   }
+}
+
+// P1 = sum of the problem's Gram-pass partials, in item order.
+__global__ __launch_bounds__(256) void kb_reduce_slots(const BProb* __restrict__ probs,
+                                                       const BItem* __restrict__ items,
+                                                       const float* __restrict__ zslots) {
+  const BProb& b = probs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= b.n * RP8) return;
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int it = 0;
+  for (; it + 7 < b.nitems; it += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += zslots[items[b.item0 + it + u].zoff + e];
+  }
+  for (; it < b.nitems; ++it) a[0] += zslots[items[b.item0 + it].zoff + e];
+  b.P1[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // U_L = B' K' (m x 8).
@@ -199,9 +269,11 @@ __device__ __forceinline__ ColMap colmap(int n) {
 // entries with key >= klo (klo >= 1) of problems in BS_COLLECT mode.
 template <int KIND>
 __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
-                                                   const BItem* __restrict__ items) {
+                                                   const BItem* __restrict__ items,
+                                                   unsigned int* __restrict__ seg_count) {
   __shared__ unsigned int lh[kHistBins];
   __shared__ double red[4];
+  __shared__ unsigned int scount;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const BItem it = items[blockIdx.x];
   const BProb& b = probs[it.prob];
@@ -216,10 +288,15 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
     const int pb = sel->pbits;
     klo = (uint32_t)(sel->prefix << (31 - pb));
     if (klo < 1u) klo = 1u;
+    if (tid == 0) scount = 0u;
+    __syncthreads();
   } else {
     for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
     __syncthreads();
   }
+  // candidates of this item go to its own segment [i0 n, i1 n) of the
+  // problem's candidate arrays (it cannot hold more), through an LDS counter
+  const int64_t seg0 = it.i0 * (int64_t)n;
   float v[2][RP8];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -255,13 +332,11 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
           const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
           const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
           const int leader = __ffsll((long long)mask) - 1;
-          unsigned long long base = 0;
-          if (take && rank == 0u) base = atomicAdd(&sel->ncand, (unsigned long long)__popcll(mask));
-          const unsigned int blo = __builtin_amdgcn_readlane((unsigned int)base, leader);
-          const unsigned int bhi = __builtin_amdgcn_readlane((unsigned int)(base >> 32), leader);
-          base = ((unsigned long long)bhi << 32) | blo;
+          unsigned int base = 0u;
+          if (take && rank == 0u) base = atomicAdd(&scount, (unsigned int)__popcll(mask));
+          base = __builtin_amdgcn_readlane(base, leader);
           if (take) {
-            const unsigned long long pos = base + rank;
+            const int64_t pos = seg0 + base + rank;
             b.cand_idx[pos] = i * (int64_t)n + j;
             b.cand_val[pos] = r;
             b.cand_x[pos] = x;
@@ -269,6 +344,10 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
         }
       }
     }
+  }
+  if (KIND == 1) {
+    __syncthreads();
+    if (tid == 0) seg_count[blockIdx.x] = scount;
   }
   if (KIND == 0) {
     __syncthreads();
@@ -367,8 +446,11 @@ __global__ __launch_bounds__(64) void kb_sel_to_refine(const BProb* __restrict__
   if (s->mode == BS_COLLECT) s->mode = s->pbits == 31 ? BS_FINAL : BS_REFINE;
 }
 
-// Histogram of the next digit over the candidates inside the bucket.
-__global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ probs) {
+// Histogram of the next digit over the candidates inside the bucket.  The
+// blocks of a problem take its work items' candidate segments in turn.
+__global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ probs,
+                                                    const BItem* __restrict__ items,
+                                                    const unsigned int* __restrict__ seg_count) {
   __shared__ unsigned int lh[1 << kHistBits];
   const BProb& b = probs[blockIdx.y];
   const BSel* s = b.sel;
@@ -378,12 +460,15 @@ __global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ pr
   const unsigned long long prefix = s->prefix;
   for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
   __syncthreads();
-  const long long nc = (long long)s->ncand;
-  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < nc;
-       c += (long long)gridDim.x * 256) {
-    const uint32_t key = fkey(b.cand_val[c]);
-    if ((key >> (31 - pbits)) == prefix)
-      atomicAdd(&lh[(key >> (31 - pbits - dbits)) & ((1u << dbits) - 1)], 1u);
+  for (int itn = blockIdx.x; itn < b.nitems; itn += gridDim.x) {
+    const int item = b.item0 + itn;
+    const int64_t c0 = items[item].i0 * b.n;
+    const int64_t c1 = c0 + seg_count[item];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) {
+      const uint32_t key = fkey(b.cand_val[c]);
+      if ((key >> (31 - pbits)) == prefix)
+        atomicAdd(&lh[(key >> (31 - pbits - dbits)) & ((1u << dbits) - 1)], 1u);
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < (1 << dbits); e += 256)
@@ -392,51 +477,55 @@ __global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ pr
 
 // FINAL: entries above the threshold key go to S; entries equal to it go to
 // the tie list (as candidate positions).
-__global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ probs, int cur) {
+__global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ probs,
+                                                  const BItem* __restrict__ items,
+                                                  const unsigned int* __restrict__ seg_count,
+                                                  int cur) {
   __shared__ double red[4];
   const BProb& b = probs[blockIdx.y];
   BSel* s = b.sel;
   if (s->mode != BS_FINAL) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tkey = (uint32_t)s->prefix;
-  const long long nc = (long long)s->ncand;
   const long long kcap = s->count_above;
   double s2 = 0.0;
-  const long long span = (nc + gridDim.x - 1) / gridDim.x;
-  const long long c0 = (long long)blockIdx.x * span;
-  const long long c1 = (c0 + span) < nc ? (c0 + span) : nc;
-  for (long long cb = c0; cb < c1; cb += 256) {
-    const long long c = cb + tid;
-    const bool valid = c < c1;
-    const float v = valid ? b.cand_val[c] : 0.f;
-    const uint32_t key = fkey(v);
-    const bool above = valid && key > tkey;
-    const bool tie = valid && key == tkey && tkey > 0;
+  for (int itn = blockIdx.x; itn < b.nitems; itn += gridDim.x) {
+    const int item = b.item0 + itn;
+    const int64_t c0 = items[item].i0 * b.n;
+    const int64_t c1 = c0 + seg_count[item];
+    for (int64_t cb = c0; cb < c1; cb += 256) {
+      const int64_t c = cb + tid;
+      const bool valid = c < c1;
+      const float v = valid ? b.cand_val[c] : 0.f;
+      const uint32_t key = fkey(v);
+      const bool above = valid && key > tkey;
+      const bool tie = valid && key == tkey && tkey > 0;
 #pragma unroll
-    for (int kind = 0; kind < 2; ++kind) {
-      const bool take = kind == 0 ? above : tie;
-      const unsigned long long mask = __ballot(take);
-      if (!mask) continue;
-      const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
-      const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-      const int leader = __ffsll((long long)mask) - 1;
-      unsigned long long base = 0;
-      if (take && rank == 0u)
-        base = atomicAdd(kind == 0 ? &s->nabove : &s->nties, (unsigned long long)__popcll(mask));
-      const unsigned int blo = __builtin_amdgcn_readlane((unsigned int)base, leader);
-      const unsigned int bhi = __builtin_amdgcn_readlane((unsigned int)(base >> 32), leader);
-      base = ((unsigned long long)bhi << 32) | blo;
-      if (take) {
-        const unsigned long long pos = base + rank;
-        if (kind == 0) {
-          if ((long long)pos < kcap) {
-            b.s_idx[cur][pos] = b.cand_idx[c];
-            b.s_val[cur][pos] = v;
-            b.s_x[cur][pos] = b.cand_x[c];
-            s2 += (double)v * (double)v;
+      for (int kind = 0; kind < 2; ++kind) {
+        const bool take = kind == 0 ? above : tie;
+        const unsigned long long mask = __ballot(take);
+        if (!mask) continue;
+        const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
+        const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned long long base = 0;
+        if (take && rank == 0u)
+          base = atomicAdd(kind == 0 ? &s->nabove : &s->nties, (unsigned long long)__popcll(mask));
+        const unsigned int blo = __builtin_amdgcn_readlane((unsigned int)base, leader);
+        const unsigned int bhi = __builtin_amdgcn_readlane((unsigned int)(base >> 32), leader);
+        base = ((unsigned long long)bhi << 32) | blo;
+        if (take) {
+          const unsigned long long pos = base + rank;
+          if (kind == 0) {
+            if ((long long)pos < kcap) {
+              b.s_idx[cur][pos] = b.cand_idx[c];
+              b.s_val[cur][pos] = v;
+              b.s_x[cur][pos] = b.cand_x[c];
+              s2 += (double)v * (double)v;
+            }
+          } else {
+            b.tie_idx[pos] = c;
           }
-        } else {
-          b.tie_idx[pos] = c;
         }
       }
     }
@@ -649,6 +738,11 @@ void bl_pass(const Launch& L, const BatchArgs& a, int in, int mode) {
                        a.items, in, a.zslots, a.gslots);
 }
 
+void bl_reduce_slots(const Launch& L, const BatchArgs& a, int64_t max_n) {
+  dim3 grid((unsigned)((max_n * kBatchRP + 255) / 256), (unsigned)a.nprob);
+  hipLaunchKernelGGL(kb_reduce_slots, grid, dim3(256), 0, L.stream, a.probs, a.items, a.zslots);
+}
+
 void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m) {
   dim3 grid((unsigned)((max_m * kBatchRP + 255) / 256), (unsigned)a.nprob);
   hipLaunchKernelGGL(kb_apply_k, grid, dim3(256), 0, L.stream, a.probs);
@@ -660,19 +754,22 @@ void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
   const unsigned np = (unsigned)a.nprob;
   hipLaunchKernelGGL(kb_sel_reset, dim3(np), dim3(256), 0, L.stream, a.probs);
   hipLaunchKernelGGL(kb_sel_pass<0>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
-                     a.items);
+                     a.items, a.seg_count);
   hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, 0);
   hipLaunchKernelGGL(kb_sel_pass<1>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
-                     a.items);
+                     a.items, a.seg_count);
   hipLaunchKernelGGL(kb_sel_to_refine, dim3((np + 63) / 64), dim3(64), 0, L.stream, a.probs,
                      a.nprob);
-  // candidate blocks per problem: enough for the largest candidate list
-  unsigned cb = (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, (2 * max_k + 65535) / 65536));
+  // blocks per problem over its candidate segments
+  const unsigned cb = (unsigned)std::max(1, std::min(64, a.max_items));
+  (void)max_k;
   for (int level = 1; level <= 2; ++level) {
-    hipLaunchKernelGGL(kb_cand_hist, dim3(cb, np), dim3(256), 0, L.stream, a.probs);
+    hipLaunchKernelGGL(kb_cand_hist, dim3(cb, np), dim3(256), 0, L.stream, a.probs, a.items,
+                       a.seg_count);
     hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, level);
   }
-  hipLaunchKernelGGL(kb_compact, dim3(cb, np), dim3(256), 0, L.stream, a.probs, cur);
+  hipLaunchKernelGGL(kb_compact, dim3(cb, np), dim3(256), 0, L.stream, a.probs, a.items,
+                     a.seg_count, cur);
   hipLaunchKernelGGL(kb_ties, dim3(np), dim3(1024), 0, L.stream, a.probs, cur);
 }
 
