@@ -26,7 +26,7 @@ using namespace godec_host;
 namespace {
 
 constexpr int64_t kMinRowsPerItem = 64;
-const int kTuneRows[] = {64, 128, 256, 512, 1024};
+const int kTuneRows[] = {64, 128, 256, 512, kBatchMaxRows};
 
 struct HostProb {
   int64_t m, n, ldx, ldd, k;
@@ -101,7 +101,7 @@ size_t carve_batch(godec_batch* b, void* base) {
   b->ditems = (BItem*)cv.take(sizeof(BItem) * items);
   b->zslots = (float*)cv.take(sizeof(float) * zfl);
   b->gslots = (double*)cv.take(sizeof(double) * items * kBatchRP * kBatchRP);
-  b->seg_count = (unsigned int*)cv.take(sizeof(unsigned int) * items);
+  b->seg_count = (unsigned int*)cv.take(sizeof(unsigned int) * items * 4);
   b->iter = (int*)cv.take(sizeof(int));
   b->tab.assign(b->count, BProb{});
   for (int i = 0; i < b->count; ++i) {
@@ -122,11 +122,16 @@ size_t carve_batch(godec_batch* b, void* base) {
     t.st = (SmallState*)cv.take(sizeof(SmallState));
     t.sel = (BSel*)cv.take(sizeof(BSel));
     t.hist = (unsigned int*)cv.take(sizeof(unsigned int) * kHistBins);
-    const int64_t mn = h.m * h.n;
-    t.cand_idx = (int64_t*)cv.take(sizeof(int64_t) * mn);
-    t.cand_val = (float*)cv.take(sizeof(float) * mn);
-    t.cand_x = (float*)cv.take(sizeof(float) * mn);
-    t.tie_idx = (int64_t*)cv.take(sizeof(int64_t) * mn);
+    // candidate slots: every (row, thread column) position of the selection
+    // pass's thread map (at least n per row), plus 3 rows of slack for a last
+    // work item whose row count is not a multiple of the rows per block step
+    const int64_t r64 = (h.n + 63) / 64 * 64;
+    t.rowcap = r64 <= 256 ? 256 / (256 / r64) : 512;
+    const int64_t cap = (h.m + 3) * t.rowcap;
+    t.cand_idx = (int32_t*)cv.take(sizeof(int32_t) * cap);
+    t.cand_val = (float*)cv.take(sizeof(float) * cap);
+    t.cand_x = (float*)cv.take(sizeof(float) * cap);
+    t.tie_idx = (int32_t*)cv.take(sizeof(int32_t) * cap);
     const int64_t kk = std::max<int64_t>(h.k, 1);
     for (int l = 0; l < 2; ++l) {
       t.s_idx[l] = (int64_t*)cv.take(sizeof(int64_t) * kk);

@@ -222,8 +222,14 @@ void launch_cast_panel(const Launch& L, bool f64, int rp, const void* src,
 constexpr int kBatchRP = 8;
 constexpr int kBatchSub = 16;          // rows of D staged per step of a work item
 constexpr int kBatchMaxN = 512;        // widest problem (columns) a work item handles
+constexpr int kBatchMaxRows = 1024;    // most rows of one work item
 
-enum BSelMode : int { BS_COLLECT = 0, BS_REFINE = 1, BS_FINAL = 2, BS_NONE = 3 };
+// BS_CARRY: one pass histograms and collects the carried window of level-0
+// digits below the previous threshold; BS_HIST: full level-0 histogram
+// (first iteration, or the window missed); BS_COLLECT: collect the bucket.
+enum BSelMode : int {
+  BS_COLLECT = 0, BS_REFINE = 1, BS_FINAL = 2, BS_NONE = 3, BS_HIST = 4, BS_CARRY = 5
+};
 
 struct BSel {                          // per-problem selection state
   unsigned long long prefix;           // resolved high bits of the threshold key
@@ -242,7 +248,9 @@ struct BSel {                          // per-problem selection state
   double rel_err_sq;                   // (sum_r2 - sum_sel2) / ||X||_F^2
   double norm_x2;                      // ||X||_F^2
   int nonfinite;                       // NaN/Inf seen in X
-  int pad;
+  int s2_done;                         // sum_r2 already taken this iteration
+  int carry_valid;                     // carry_dlo holds a window (persists)
+  int carry_dlo;                       // lowest level-0 digit of the window
 };
 
 struct BProb {                         // device view of one problem
@@ -262,10 +270,11 @@ struct BProb {                         // device view of one problem
   SmallState* st;
   BSel* sel;
   unsigned int* hist;                  // 4096 bins
-  int64_t* cand_idx;                   // cap = m n candidates
-  float* cand_val;
-  float* cand_x;
-  int64_t* tie_idx;                    // cap entries
+  int64_t rowcap;                      // candidate slots per row of X
+  int32_t* cand_idx;                   // (m + 3) rowcap candidates: linear index
+  float* cand_val;                     //   residual
+  float* cand_x;                       //   X
+  int32_t* tie_idx;                    // candidate positions of the tied entries
   int64_t* s_idx[2];                   // S lists (k entries each)
   float* s_val[2];
   float* s_x[2];
@@ -283,7 +292,7 @@ struct BatchArgs {
   const BItem* items;
   int nitems;
   int max_items;                       // most work items of one problem
-  unsigned int* seg_count;             // candidates written per work item
+  unsigned int* seg_count;             // candidates written per (work item, wave)
   float* zslots;                       // Gram-pass partials (n x 8 per item)
   double* gslots;                      // FP64 Gram partials of B' (8 x 8 per item)
   int* iter;                           // device iteration counter

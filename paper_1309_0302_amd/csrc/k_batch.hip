@@ -265,20 +265,32 @@ __device__ __forceinline__ ColMap colmap(int n) {
   return cm;
 }
 
-// KIND 0: level-0 histogram + sum of R^2 + NaN check; KIND 1: collect the
-// entries with key >= klo (klo >= 1) of problems in BS_COLLECT mode.
+// Candidate segment of wave w of a work item of R rows: the wave's thread
+// map covers ceil(R / rg) rows of 64 * cpt positions, so it cannot write more.
+__device__ __forceinline__ int64_t wave_seg_cap(int R, const ColMap& cm) {
+  return (int64_t)((R + cm.rg - 1) / cm.rg) * 64 * cm.cpt;
+}
+
+// KIND 0 (problems in BS_HIST): level-0 histogram, sum of R^2, NaN check.
+// KIND 1 (BS_COLLECT): collect the entries at or above the bucket.
+// KIND 2 (BS_CARRY): sum of R^2 and NaN check; histogram and collect the
+// entries whose level-0 digit lies in the carried window.
+// The item's U_L rows are staged in LDS; each wave appends to its own
+// candidate segment with a wave-uniform fill counter (no atomics).
 template <int KIND>
 __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
                                                    const BItem* __restrict__ items,
                                                    unsigned int* __restrict__ seg_count) {
   __shared__ unsigned int lh[kHistBins];
+  __shared__ float us[kBatchMaxRows * RP8];
   __shared__ double red[4];
-  __shared__ unsigned int scount;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const BItem it = items[blockIdx.x];
   const BProb& b = probs[it.prob];
   BSel* sel = b.sel;
-  if (KIND == 1 && sel->mode == BS_NONE) return;
+  const int want = KIND == 0 ? BS_HIST : (KIND == 1 ? BS_COLLECT : BS_CARRY);
+  if (sel->mode != want) return;
+  const bool add_s2 = KIND == 2 || (KIND == 0 && !sel->s2_done);
   const int n = (int)b.n;
   const ColMap cm = colmap(n);
   const int rsub = tid / cm.lanes;
@@ -287,16 +299,15 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
   if (KIND == 1) {
     const int pb = sel->pbits;
     klo = (uint32_t)(sel->prefix << (31 - pb));
-    if (klo < 1u) klo = 1u;
-    if (tid == 0) scount = 0u;
-    __syncthreads();
-  } else {
-    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
-    __syncthreads();
+  } else if (KIND == 2) {
+    klo = (uint32_t)sel->carry_dlo << (31 - kHistBits0);
   }
-  // candidates of this item go to its own segment [i0 n, i1 n) of the
-  // problem's candidate arrays (it cannot hold more), through an LDS counter
-  const int64_t seg0 = it.i0 * (int64_t)n;
+  if (klo < 1u) klo = 1u;
+  if (KIND != 1)
+    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
+  const int R = (int)(it.i1 - it.i0);
+  for (int e = tid; e < R * RP8; e += 256) us[e] = b.UL[it.i0 * RP8 + e];
+  __syncthreads();
   float v[2][RP8];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -304,52 +315,72 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
 #pragma unroll
     for (int c = 0; c < RP8; ++c) v[u][c] = (u < cm.cpt && j < n) ? b.VL[(int64_t)j * RP8 + c] : 0.f;
   }
+  const int rows_w = (R + cm.rg - 1) / cm.rg;   // same trip count for every thread
+  const int64_t segw = it.i0 * b.rowcap + (int64_t)wave * wave_seg_cap(R, cm);
+  unsigned int fill = 0u;                        // wave-uniform
   double s2 = 0.0;
   int bad = 0;
-  for (int64_t i = it.i0 + rsub; i < it.i1 + rsub; i += cm.rg) {
-    // every thread runs the same number of trips so the ballots stay uniform
-    const bool rok = i < it.i1 && rsub < cm.rg;
-    float uu[RP8];
+  constexpr int G = 8;                           // rows whose X loads are in flight together
+  for (int t0 = 0; t0 < rows_w; t0 += G) {
+    float x[G][2];
 #pragma unroll
-    for (int c = 0; c < RP8; ++c) uu[c] = rok ? b.UL[i * RP8 + c] : 0.f;
+    for (int g = 0; g < G; ++g) {
+      const int ir = rsub + cm.rg * (t0 + g);
+      const bool rok = rsub < cm.rg && t0 + g < rows_w && ir < R;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int j = col0 + 256 * u;
-      const bool ok = rok && u < cm.cpt && j < n;
-      const float x = ok ? b.X[i * b.ldx + j] : 0.f;
-      const float r = bresid(x, uu, v[u]);
-      const uint32_t key = fkey(r);
-      if (KIND == 0) {
-        if (ok) {
-          s2 += (double)r * (double)r;
-          atomicAdd(&lh[key >> (31 - kHistBits0)], 1u);
-          if (!isfinite(x)) bad = 1;
-        }
-      } else {
-        const bool take = ok && key >= klo;
-        const unsigned long long mask = __ballot(take);
-        if (mask) {
-          const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
-          const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-          const int leader = __ffsll((long long)mask) - 1;
-          unsigned int base = 0u;
-          if (take && rank == 0u) base = atomicAdd(&scount, (unsigned int)__popcll(mask));
-          base = __builtin_amdgcn_readlane(base, leader);
-          if (take) {
-            const int64_t pos = seg0 + base + rank;
-            b.cand_idx[pos] = i * (int64_t)n + j;
-            b.cand_val[pos] = r;
-            b.cand_x[pos] = x;
+      for (int u = 0; u < 2; ++u) {
+        const int j = col0 + 256 * u;
+        x[g][u] = (rok && u < cm.cpt && j < n) ? b.X[(it.i0 + ir) * b.ldx + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (t0 + g >= rows_w) break;               // uniform
+      const int ir = rsub + cm.rg * (t0 + g);
+      const bool rok = rsub < cm.rg && ir < R;
+      float uu[RP8];
+#pragma unroll
+      for (int c = 0; c < RP8; ++c) uu[c] = rok ? us[ir * RP8 + c] : 0.f;
+      const int64_t i = it.i0 + ir;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int j = col0 + 256 * u;
+        const bool ok = rok && u < cm.cpt && j < n;
+        const float r = bresid(x[g][u], uu, v[u]);
+        const uint32_t key = fkey(r);
+        if (KIND == 0) {
+          if (ok) {
+            if (add_s2) s2 += (double)r * (double)r;
+            atomicAdd(&lh[key >> (31 - kHistBits0)], 1u);
+            if (!isfinite(x[g][u])) bad = 1;
+          }
+        } else {
+          const bool take = ok && key >= klo;
+          if (KIND == 2 && ok) {
+            s2 += (double)r * (double)r;
+            if (!isfinite(x[g][u])) bad = 1;
+            if (take) atomicAdd(&lh[key >> (31 - kHistBits0)], 1u);
+          }
+          if (u < cm.cpt) {
+            const unsigned long long mask = __ballot(take);
+            if (mask) {
+              const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
+              const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+              if (take) {
+                const int64_t pos = segw + fill + rank;
+                b.cand_idx[pos] = (int32_t)(i * n + j);
+                b.cand_val[pos] = r;
+                b.cand_x[pos] = x[g][u];
+              }
+              fill += (unsigned int)__popcll(mask);
+            }
           }
         }
       }
     }
   }
-  if (KIND == 1) {
-    __syncthreads();
-    if (tid == 0) seg_count[blockIdx.x] = scount;
-  }
-  if (KIND == 0) {
+  if (KIND != 0 && lane == 0) seg_count[(int64_t)blockIdx.x * 4 + wave] = fill;
+  if (KIND != 1) {
     __syncthreads();
     for (int e = tid; e < kHistBins; e += 256)
       if (lh[e]) atomicAdd(&b.hist[e], lh[e]);
@@ -357,7 +388,7 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
     if (lane == 0) red[wave] = s2;
     if (bad) atomicOr(&sel->nonfinite, 1);
     __syncthreads();
-    if (tid == 0) atomicAdd(&sel->sum_r2, red[0] + red[1] + red[2] + red[3]);
+    if (tid == 0 && add_s2) atomicAdd(&sel->sum_r2, red[0] + red[1] + red[2] + red[3]);
   }
 }
 
@@ -368,14 +399,19 @@ __global__ __launch_bounds__(256) void kb_sel_reset(const BProb* __restrict__ pr
   if (threadIdx.x == 0) {
     BSel* s = b.sel;
     s->prefix = 0; s->k_rem = b.k; s->count_above = 0; s->ncand = 0; s->nabove = 0;
-    s->nties = 0; s->nnz = 0; s->pbits = 0; s->mode = b.k > 0 ? BS_COLLECT : BS_NONE;
+    s->nties = 0; s->nnz = 0; s->pbits = 0; s->s2_done = 0;
+    s->mode = b.k > 0 ? (s->carry_valid ? BS_CARRY : BS_HIST) : BS_NONE;
     s->sum_r2 = 0.0; s->sum_sel2 = 0.0; s->threshold = 0.0;
   }
 }
 
 // Digit selection over a histogram of `bins` counts (one workgroup per
 // problem): the digit holding the k_rem-th largest key, by a suffix scan.
-// level 0 follows the full-data histogram; later levels the candidates'.
+// level 0 follows the full-data histogram (BS_HIST), level -1 the carried
+// window (BS_CARRY), later levels the candidates' histograms (BS_REFINE).
+// A carried window is accepted when the k-th key's digit lies inside it (all
+// keys at or above that digit were collected); otherwise the problem falls
+// back to the full histogram pass.
 __global__ __launch_bounds__(256) void kb_sel_plan(const BProb* __restrict__ probs, int level) {
   __shared__ unsigned long long h[kHistBins];
   __shared__ unsigned long long part[256];
@@ -383,9 +419,10 @@ __global__ __launch_bounds__(256) void kb_sel_plan(const BProb* __restrict__ pro
   const BProb& b = probs[blockIdx.x];
   BSel* s = b.sel;
   const int tid = threadIdx.x;
-  if (s->mode == BS_NONE || (level > 0 && s->mode != BS_REFINE)) return;
+  const int want = level < 0 ? BS_CARRY : (level == 0 ? BS_HIST : BS_REFINE);
+  if (s->mode != want) return;
   const int pbits = s->pbits;
-  const int dbits = level == 0 ? kHistBits0 : (31 - pbits < kHistBits ? 31 - pbits : kHistBits);
+  const int dbits = level <= 0 ? kHistBits0 : (31 - pbits < kHistBits ? 31 - pbits : kHistBits);
   const int bins = 1 << dbits;
   const int per = (bins + 255) / 256;
   for (int e = tid; e < bins; e += 256) {
@@ -422,6 +459,20 @@ __global__ __launch_bounds__(256) void kb_sel_plan(const BProb* __restrict__ pro
       if (cum + h[d] >= (unsigned long long)k_rem) { dsel = d; break; }
       cum += h[d];
     }
+  }
+  if (level < 0) {
+    if (dsel < 0 || dsel < s->carry_dlo) {
+      // window missed the k-th key: full histogram pass (R^2 already summed)
+      s->s2_done = 1;
+      s->mode = BS_HIST;
+      return;
+    }
+    s->count_above = (long long)cum;
+    s->k_rem = k_rem - (long long)cum;
+    s->prefix = (unsigned long long)dsel;
+    s->pbits = dbits;
+    s->mode = BS_REFINE;
+    return;
   }
   if (dsel < 0) {
     // fewer nonzero keys than k_rem: settle on digit 0 (zeros are excluded
@@ -460,10 +511,12 @@ __global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ pr
   const unsigned long long prefix = s->prefix;
   for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
   __syncthreads();
-  for (int itn = blockIdx.x; itn < b.nitems; itn += gridDim.x) {
-    const int item = b.item0 + itn;
-    const int64_t c0 = items[item].i0 * b.n;
-    const int64_t c1 = c0 + seg_count[item];
+  const ColMap cm = colmap((int)b.n);
+  for (int sg = blockIdx.x; sg < b.nitems * 4; sg += gridDim.x) {
+    const int item = b.item0 + sg / 4, w = sg % 4;
+    const BItem itm = items[item];
+    const int64_t c0 = itm.i0 * b.rowcap + (int64_t)w * wave_seg_cap((int)(itm.i1 - itm.i0), cm);
+    const int64_t c1 = c0 + seg_count[(int64_t)item * 4 + w];
     for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) {
       const uint32_t key = fkey(b.cand_val[c]);
       if ((key >> (31 - pbits)) == prefix)
@@ -489,10 +542,12 @@ __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ prob
   const uint32_t tkey = (uint32_t)s->prefix;
   const long long kcap = s->count_above;
   double s2 = 0.0;
-  for (int itn = blockIdx.x; itn < b.nitems; itn += gridDim.x) {
-    const int item = b.item0 + itn;
-    const int64_t c0 = items[item].i0 * b.n;
-    const int64_t c1 = c0 + seg_count[item];
+  const ColMap cm = colmap((int)b.n);
+  for (int sg = blockIdx.x; sg < b.nitems * 4; sg += gridDim.x) {
+    const int item = b.item0 + sg / 4, w = sg % 4;
+    const BItem itm = items[item];
+    const int64_t c0 = itm.i0 * b.rowcap + (int64_t)w * wave_seg_cap((int)(itm.i1 - itm.i0), cm);
+    const int64_t c1 = c0 + seg_count[(int64_t)item * 4 + w];
     for (int64_t cb = c0; cb < c1; cb += 256) {
       const int64_t c = cb + tid;
       const bool valid = c < c1;
@@ -518,13 +573,13 @@ __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ prob
           const unsigned long long pos = base + rank;
           if (kind == 0) {
             if ((long long)pos < kcap) {
-              b.s_idx[cur][pos] = b.cand_idx[c];
+              b.s_idx[cur][pos] = (int64_t)b.cand_idx[c];
               b.s_val[cur][pos] = v;
               b.s_x[cur][pos] = b.cand_x[c];
               s2 += (double)v * (double)v;
             }
           } else {
-            b.tie_idx[pos] = c;
+            b.tie_idx[pos] = (int32_t)c;
           }
         }
       }
@@ -553,6 +608,7 @@ __global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs,
   const int tid = threadIdx.x;
   if (s->mode == BS_NONE) {
     if (tid == 0) {
+      s->carry_valid = 0;
       s->nnz = 0;
       s->nnz_list[cur] = 0;
       s->threshold = 0.0;
@@ -570,7 +626,7 @@ __global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs,
   if (take == nties) {
     for (long long e = tid; e < take; e += blockDim.x) {
       const long long c = b.tie_idx[e];
-      b.s_idx[cur][nabove + e] = b.cand_idx[c];
+      b.s_idx[cur][nabove + e] = (int64_t)b.cand_idx[c];
       b.s_val[cur][nabove + e] = b.cand_val[c];
       b.s_x[cur][nabove + e] = b.cand_x[c];
     }
@@ -603,7 +659,7 @@ __global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs,
       }
     for (long long e = tid; e < take; e += blockDim.x) {
       const long long c = b.tie_idx[sp[e]];
-      b.s_idx[cur][nabove + e] = b.cand_idx[c];
+      b.s_idx[cur][nabove + e] = (int64_t)b.cand_idx[c];
       b.s_val[cur][nabove + e] = b.cand_val[c];
       b.s_x[cur][nabove + e] = b.cand_x[c];
     }
@@ -649,6 +705,11 @@ __global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs,
   }
   __syncthreads();
   if (tid == 0) {
+    // next iteration: histogram and collect from two level-0 digits (a
+    // quarter octave) below this threshold's digit
+    const int d0 = (int)(tkey >> (31 - kHistBits0));
+    s->carry_dlo = d0 > 2 ? d0 - 2 : 0;
+    s->carry_valid = tkey > 0 ? 1 : 0;
     s->nnz = nabove + take;
     s->nnz_list[cur] = nabove + take;
     s->threshold = (double)tval;
@@ -753,6 +814,9 @@ void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m) {
 void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
   const unsigned np = (unsigned)a.nprob;
   hipLaunchKernelGGL(kb_sel_reset, dim3(np), dim3(256), 0, L.stream, a.probs);
+  hipLaunchKernelGGL(kb_sel_pass<2>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+                     a.items, a.seg_count);
+  hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, -1);
   hipLaunchKernelGGL(kb_sel_pass<0>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
                      a.items, a.seg_count);
   hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, 0);
