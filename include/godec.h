@@ -262,6 +262,60 @@ godec_status godec_batch_tuning(godec_batch* b, int32_t* rows_per_item, int32_t*
 /* Release the handle and its graphs (the workspace stays the caller's). */
 godec_status godec_batch_destroy(godec_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Differentiable layer: T unrolled iterations of Algorithm 1 (Sec. 3.1.3) on
+ * a batch of equally shaped problems, with a backward pass.
+ *
+ * The forward pass runs T iterations on each problem b (X_b = X_dev + b*m*n,
+ * row-major, leading dimension n; A1 drawn from seed + b) and keeps the
+ * support and values of every S_t.  The backward pass differentiates the
+ * unrolled map with the supports M_t held fixed:
+ *   S_0 = 0,  L_t = f(X - S_{t-1}),  S_t = M_t * (X - L_t),
+ * where f is the power-scheme low-rank update (Eq. 6-9), written exactly as
+ * f(D) = D A^q Q (Q^T A^p Q)^a Q^T with A = D^T D, p = 2q + 1,
+ * Q = orth(A^p A1), a = -(p - 1) / (2p) (the range of Q is that of Y2 and
+ * the core's power gives the (2q+1)-th root of Eq. 9).  Selection is
+ * piecewise constant in X, so its derivative is zero almost everywhere.
+ * The adjoints are hand-written (eigen-function derivative of the r x r core,
+ * orthonormal-range derivative, power-chain terms) and run in the dtype of X
+ * with the r x r algebra in FP64.  Limits: r <= 8; the sketch must keep full
+ * rank r in every iteration (else GODEC_E_UNSUPPORTED from the forward).
+ * ------------------------------------------------------------------------ */
+typedef struct godec_layer godec_layer;
+
+/* Workspace bytes for a layer (batch problems of m x n, T iterations). */
+godec_status godec_layer_workspace_size(int32_t batch, int64_t m, int64_t n, int32_t r,
+                                        int64_t k, int32_t q, int32_t T, godec_dtype dtype,
+                                        size_t* bytes);
+
+/* Forward pass.  X_dev: batch x m x n (dtype), borrowed until destroy.
+ * L_dev, S_dev (optional, batch x m x n dense, dtype of X) receive L_T and
+ * S_T.  opts may be NULL; opts->prec must be NATIVE and opts->a1_host NULL;
+ * opts->rank_tol and opts->stream are used.  Synchronous. */
+godec_status godec_layer_forward(godec_layer** out, const void* X_dev, godec_dtype dtype,
+                                 int32_t batch, int64_t m, int64_t n, int32_t r, int64_t k,
+                                 int32_t q, int32_t T, uint64_t seed, void* workspace_dev,
+                                 size_t workspace_bytes, const godec_opts* opts, void* L_dev,
+                                 void* S_dev);
+
+/* Backward pass: dX_dev = d/dX of <dL, L_T> + <dS, S_T> (all batch x m x n
+ * dense, dtype of X; dX is overwritten).  May be called several times.
+ * GODEC_E_NUMERIC when a Cholesky pivot or core eigenvalue is not positive.
+ * Synchronous. */
+godec_status godec_layer_backward(godec_layer* l, const void* dL_dev, const void* dS_dev,
+                                  void* dX_dev);
+
+/* Support of S_t (1 <= t <= T) of problem b: ascending linear indices into
+ * idx_host (capacity k; may be NULL to query the count), count in *nnz_host. */
+godec_status godec_layer_get_mask(godec_layer* l, int32_t b, int32_t t, int64_t* idx_host,
+                                  int64_t* nnz_host);
+
+/* A1 (n x r, FP64, row-major) of problem b. */
+godec_status godec_layer_get_A1(godec_layer* l, int32_t b, double* a1_host);
+
+/* Release the layer (the workspace stays the caller's). */
+godec_status godec_layer_destroy(godec_layer* l);
+
 /* Build information string (static storage). */
 const char* godec_version(void);
 

@@ -104,6 +104,15 @@ _SIG = {
     "godec_batch_get_info": (_I32, [_P, _I32, ctypes.POINTER(godec_info)]),
     "godec_batch_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "godec_batch_destroy": (_I32, [_P]),
+    "godec_layer_workspace_size": (_I32, [_I32, _I64, _I64, _I32, _I64, _I32, _I32, _I32,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "godec_layer_forward": (_I32, [ctypes.POINTER(_P), _P, _I32, _I32, _I64, _I64, _I32, _I64,
+                                   _I32, _I32, ctypes.c_uint64, _P, ctypes.c_size_t,
+                                   ctypes.POINTER(godec_opts), _P, _P]),
+    "godec_layer_backward": (_I32, [_P, _P, _P, _P]),
+    "godec_layer_get_mask": (_I32, [_P, _I32, _I32, _P, ctypes.POINTER(_I64)]),
+    "godec_layer_get_A1": (_I32, [_P, _I32, _P]),
+    "godec_layer_destroy": (_I32, [_P]),
 }
 
 
@@ -496,3 +505,130 @@ class GoDecBatch:
             self.close()
         except Exception:
             pass
+
+
+# ---- differentiable layer -----------------------------------------------------
+
+def godec_layer_workspace_size(batch, m, n, r, k, q, T, dtype):
+    out = ctypes.c_size_t(0)
+    _check(load().godec_layer_workspace_size(batch, m, n, r, k, q, T, dtype,
+                                             ctypes.byref(out)))
+    return out.value
+
+
+def godec_layer_forward(X_ptr, dtype, batch, m, n, r, k, q, T, seed, ws_ptr, ws_bytes,
+                        opts, L_ptr, S_ptr):
+    h = _P()
+    _check(load().godec_layer_forward(ctypes.byref(h), X_ptr, dtype, batch, m, n, r, k, q, T,
+                                      seed, ws_ptr, ws_bytes,
+                                      ctypes.byref(opts) if opts is not None else None,
+                                      L_ptr, S_ptr))
+    return h
+
+
+def godec_layer_backward(h, dL_ptr, dS_ptr, dX_ptr):
+    _check(load().godec_layer_backward(h, dL_ptr, dS_ptr, dX_ptr))
+
+
+def godec_layer_get_mask(h, b, t, k):
+    nnz = _I64(0)
+    out = np.empty(max(k, 1), dtype=np.int64)
+    _check(load().godec_layer_get_mask(h, b, t, out.ctypes.data, ctypes.byref(nnz)))
+    return out[:nnz.value].copy()
+
+
+def godec_layer_get_A1(h, b, n, r):
+    out = np.empty((n, r), dtype=np.float64)
+    _check(load().godec_layer_get_A1(h, b, out.ctypes.data))
+    return out
+
+
+def godec_layer_destroy(h):
+    _check(load().godec_layer_destroy(h))
+
+
+class GoDecLayer:
+    """T unrolled GoDec iterations on a batch of equally shaped problems
+    (X: batch x m x n device tensor, float32 or float64) with a backward pass
+    through the frozen supports.  forward() runs the iterations and returns
+    (L_T, S_T); backward(dL, dS) returns dX."""
+
+    def __init__(self, r, k, q, T, seed=0, rank_tol=0.0, stream=None):
+        self.r, self.k, self.q, self.T, self.seed = r, k, q, T, seed
+        self.rank_tol = rank_tol
+        self.stream = stream
+        self.h = None
+
+    def forward(self, X):
+        import torch
+        if X.dim() == 2:
+            X = X.unsqueeze(0)
+        if not X.is_cuda or not X.is_contiguous():
+            raise ValueError("X must be a contiguous device tensor (batch x m x n)")
+        self.close()
+        self.X = X
+        self.nb, self.m, self.n = X.shape
+        self.dtype = _dtype_code(X)
+        stream = self.stream
+        if stream is None:
+            stream = torch.cuda.current_stream(X.device).cuda_stream
+        self.opts, _ = make_opts(rank_tol=self.rank_tol, stream=stream)
+        self.ws_bytes = godec_layer_workspace_size(self.nb, self.m, self.n, self.r, self.k,
+                                                   self.q, self.T, self.dtype)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=X.device)
+        base = (self.ws.data_ptr() + 255) // 256 * 256
+        L = torch.empty_like(X)
+        S = torch.empty_like(X)
+        self.h = godec_layer_forward(X.data_ptr(), self.dtype, self.nb, self.m, self.n,
+                                     self.r, self.k, self.q, self.T, self.seed, base,
+                                     self.ws_bytes, self.opts, L.data_ptr(), S.data_ptr())
+        return L, S
+
+    def backward(self, dL, dS):
+        import torch
+        dL = dL.reshape(self.X.shape).contiguous()
+        dS = dS.reshape(self.X.shape).contiguous()
+        if dL.dtype != self.X.dtype or dS.dtype != self.X.dtype:
+            raise ValueError("dL and dS must have the dtype of X")
+        dX = torch.empty_like(self.X)
+        godec_layer_backward(self.h, dL.data_ptr(), dS.data_ptr(), dX.data_ptr())
+        return dX
+
+    def mask(self, b, t):
+        return godec_layer_get_mask(self.h, b, t, self.k)
+
+    def A1(self, b):
+        return godec_layer_get_A1(self.h, b, self.n, self.r)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            godec_layer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def godec_layer_fn(X, r, k, q, T, seed=0):
+    """(L_T, S_T) = GoDec layer of X (batch x m x n) as a torch autograd
+    function whose backward calls the library's hand-written adjoints."""
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, Xin):
+            layer = GoDecLayer(r, k, q, T, seed)
+            L, S = layer.forward(Xin.detach().contiguous())
+            ctx.layer = layer
+            return L, S
+
+        @staticmethod
+        def backward(ctx, dL, dS):
+            dL = torch.zeros_like(ctx.layer.X) if dL is None else dL
+            dS = torch.zeros_like(ctx.layer.X) if dS is None else dS
+            return ctx.layer.backward(dL, dS).reshape(X.shape)
+
+    return _Fn.apply(X)

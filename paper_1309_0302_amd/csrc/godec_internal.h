@@ -321,4 +321,40 @@ void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, f
                  int64_t ldr);
 void bl_small_init(const Launch& L, const BatchArgs& a);
 
+
+// ---- differentiable layer (k_layer.hip) ----
+constexpr int kLayerMaxRank = 8;   // r x r algebra held in registers
+// Batched row-major GEMM C = alpha op(A) op(B) + beta C over nb problems
+// (batch strides sA, sB, sC); ta / tb: A stored K x M / B stored N x K.
+// Splits long K ranges over `part` (part_cap elements) when the output is small.
+void lk_gemm(const Launch& L, bool f64, int nb, int M, int N, int K, const void* A, int64_t lda,
+             int64_t sA, int ta, const void* B, int64_t ldb, int64_t sB, int tb, double alpha,
+             double beta, void* C, int64_t ldc, int64_t sC, void* part, int64_t part_cap);
+void lk_fill(const Launch& L, bool f64, int nb, void* P, int64_t count, int64_t stride, double v);
+void lk_copy(const Launch& L, bool f64, int nb, const void* S, void* D, int64_t count,
+             int64_t stride);
+void lk_axpy(const Launch& L, bool f64, int nb, const void* X, void* Y, int64_t count,
+             int64_t stride);
+void lk_scatter(const Launch& L, bool f64, int nb, void* P, int64_t stride, const int64_t* idx,
+                const void* v, int64_t kstride, int64_t kmax, const int64_t* nnz, int mode,
+                double s);
+void lk_gather(const Launch& L, bool f64, int nb, const void* G, int64_t stride,
+               const int64_t* idx, int64_t kstride, int64_t kmax, const int64_t* nnz, void* out);
+void lk_lowrank_at(const Launch& L, bool f64, int nb, const void* U, int64_t sU, const void* V,
+                   int64_t sV, int w, int64_t n, const int64_t* idx, int64_t kstride,
+                   int64_t kmax, const int64_t* nnz, void* out);
+void lk_put_cols(const Launch& L, bool f64, int nb, const void* P, int64_t sP, int r, void* O,
+                 int64_t sO, int w, int c0, int64_t rows);
+void lk_cast_a1(const Launch& L, bool f64, int nb, const double* A1, int64_t sA, void* P,
+                int64_t sP, int64_t count);
+void lk_chol(const Launch& L, bool f64, int nb, int r, const void* gram, const double* rin,
+             void* rinv, double* rout, void* rout_t, int* flag);
+void lk_eig(const Launch& L, bool f64, int nb, int r, const void* c, double a, void* calpha,
+            double* v, double* f, int* flag);
+void lk_dk(const Launch& L, bool f64, int nb, int r, const void* cbar_a, const double* v,
+           const double* f, void* s2);
+void lk_rrel(const Launch& L, bool f64, int nb, int r, const double* rc, const double* rtot,
+             void* out);
+void lk_identity(const Launch& L, int nb, int r, double* out);
+
 }  // namespace godec

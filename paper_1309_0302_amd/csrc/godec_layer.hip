@@ -1,0 +1,461 @@
+// libgodec host side of the differentiable GoDec layer (godec_layer_*).
+//
+// Forward: every problem of the batch runs T iterations of Algorithm 1
+// (Sec. 3.1.3) through the single-problem path, and the support and values of
+// S_t are checkpointed after each iteration.
+//
+// Backward: with the supports frozen, S_t = M_t * (X - L_t) and
+// L_t = f(X - S_{t-1}); for t = T .. 1 the library rebuilds D_t = X - S_{t-1}
+// from X and the checkpoint, recomputes the forward panels of f at D_t, and
+// applies the adjoint of f (k_layer.hip states f and its factorisation) to
+// L^bar_t.  The result D^bar_t is kept as low-rank factors U V^T; it is added
+// to X^bar, and its values on M_{t-1} become L^bar_{t-1} and leave X^bar,
+// since S_{t-1} = M_{t-1} * (X - L_{t-1}) and D_t = X - S_{t-1}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/godec.h"
+#include "godec_internal.h"
+#include "host_common.h"
+
+using namespace godec;
+using namespace godec_host;
+
+struct godec_layer {
+  int nb = 0;
+  int64_t m = 0, n = 0, k = 0;
+  int r = 0, q = 0, p = 1, T = 0, w = 0;
+  bool f64 = false;
+  size_t ts = 4;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  const void* X = nullptr;
+  std::vector<godec_ctx*> ctx;
+  // Checkpoints of S_t, t = 1..T: slot (t - 1) * nb + b, capacity max(k, 1).
+  int64_t* ck_idx = nullptr;
+  void* ck_val = nullptr;
+  int64_t* ck_nnz = nullptr;
+  std::vector<int64_t> ck_nnz_host;
+  double* A1 = nullptr;  // nb x n x r
+  std::vector<double> a1_host;
+  // Backward buffers.  Chains with several members are stored member-major
+  // (member j of every problem contiguous) so that one batched launch covers
+  // all problems with a single stride.
+  void *D = nullptr, *Lbar = nullptr;
+  void* Z = nullptr;     // (p + 1) x nb panels n x r: orthonormalised A^j A1
+  double* Rc = nullptr;  // (p + 2) x nb r x r: accumulated Cholesky factors
+  void* Qs = nullptr;    // (q + 1) x nb panels n x r: A^i Q (member 0 is Q)
+  void *Rinv = nullptr, *Gm = nullptr, *Cm = nullptr, *Ca = nullptr, *CbarA = nullptr;
+  void *S2 = nullptr, *T1 = nullptr, *Rrel = nullptr;
+  double *Vv = nullptr, *F = nullptr;
+  void *Wm = nullptr, *Wm2 = nullptr, *B = nullptr, *LQ = nullptr, *Bbar = nullptr;
+  void *Vn = nullptr, *LtB = nullptr, *Qbar = nullptr, *Cur = nullptr, *Tn = nullptr;
+  void *Uf = nullptr, *Vf = nullptr;  // nb x m x w, nb x n x w
+  void* vals = nullptr;               // nb x max(k, 1)
+  void* part = nullptr;               // split-K partial products
+  int64_t part_cap = 0;
+  int* flag = nullptr;
+};
+
+namespace {
+
+inline void* at(void* p, size_t ts, int64_t off) { return (char*)p + ts * off; }
+
+// Carve the workspace (base == nullptr only measures).
+size_t carve_layer(godec_layer* l, void* base, size_t ctx_ws, std::vector<void*>* ctx_ptr) {
+  Carver cv{(char*)base};
+  const int nb = l->nb, r = l->r, p = l->p, q = l->q;
+  const int64_t m = l->m, n = l->n, kk = std::max<int64_t>(l->k, 1);
+  const int64_t mn = m * n, nr = n * r, mr = m * r, E = (int64_t)r * r;
+  const size_t ts = l->ts;
+  l->w = r + 2 * r * (p + q);
+  if (ctx_ptr) ctx_ptr->clear();
+  for (int b = 0; b < nb; ++b) {
+    void* w = cv.take(ctx_ws);
+    if (ctx_ptr) ctx_ptr->push_back(w);
+  }
+  l->ck_idx = (int64_t*)cv.take(sizeof(int64_t) * l->T * nb * kk);
+  l->ck_val = cv.take(ts * l->T * nb * kk);
+  l->ck_nnz = (int64_t*)cv.take(sizeof(int64_t) * l->T * nb);
+  l->A1 = (double*)cv.take(sizeof(double) * nb * nr);
+  l->D = cv.take(ts * nb * mn);
+  l->Lbar = cv.take(ts * nb * mn);
+  l->Z = cv.take(ts * (p + 1) * nb * nr);
+  l->Rc = (double*)cv.take(sizeof(double) * (p + 2) * nb * E);
+  l->Qs = cv.take(ts * (q + 1) * nb * nr);
+  void** small[] = {&l->Rinv, &l->Gm, &l->Cm, &l->Ca, &l->CbarA, &l->S2, &l->T1, &l->Rrel};
+  for (void** s : small) *s = cv.take(ts * nb * E);
+  l->Vv = (double*)cv.take(sizeof(double) * nb * E);
+  l->F = (double*)cv.take(sizeof(double) * nb * E);
+  void** mpan[] = {&l->Wm, &l->Wm2, &l->B, &l->LQ, &l->Bbar};
+  for (void** s : mpan) *s = cv.take(ts * nb * mr);
+  void** npan[] = {&l->Vn, &l->LtB, &l->Qbar, &l->Cur, &l->Tn};
+  for (void** s : npan) *s = cv.take(ts * nb * nr);
+  l->Uf = cv.take(ts * nb * m * l->w);
+  l->Vf = cv.take(ts * nb * n * l->w);
+  l->vals = cv.take(ts * nb * kk);
+  // Largest split-K product: n x r or r x r outputs, at most 64 chunks.
+  l->part_cap = (int64_t)nb * 64 * std::max<int64_t>(nr, E);
+  l->part = cv.take(ts * l->part_cap);
+  l->flag = (int*)cv.take(sizeof(int) * 4);
+  return cv.off;
+}
+
+// Batched panel algebra of one layer (all problems per launch).
+struct Ops {
+  godec_layer* l;
+  Launch L;
+  // C = alpha op(A) op(B) + beta C with per-problem strides sA, sB, sC.
+  void gemm(int M, int N, int K, const void* A, int64_t lda, int64_t sA, int ta, const void* B,
+            int64_t ldb, int64_t sB, int tb, double alpha, double beta, void* C, int64_t ldc,
+            int64_t sC) {
+    lk_gemm(L, l->f64, l->nb, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, alpha, beta, C, ldc, sC,
+            l->part, l->part_cap);
+  }
+  // out (m x r) = D P, P n x r
+  void dmul(const void* P, void* out) {
+    const int64_t m = l->m, n = l->n;
+    const int r = l->r;
+    gemm((int)m, r, (int)n, l->D, n, m * n, 0, P, r, n * r, 0, 1.0, 0.0, out, r, m * r);
+  }
+  // out (n x r) = D^T W, W m x r
+  void dtmul(const void* W, void* out) {
+    const int64_t m = l->m, n = l->n;
+    const int r = l->r;
+    gemm((int)n, r, (int)m, l->D, n, m * n, 1, W, r, m * r, 0, 1.0, 0.0, out, r, n * r);
+  }
+  // out = A P = D^T (D P)
+  void amul(const void* P, void* out) {
+    dmul(P, l->Wm2);
+    dtmul(l->Wm2, out);
+  }
+  // r x r: G = P^T P2 for panels with `rows` rows
+  void inner(const void* P, const void* P2, int64_t rows, void* G) {
+    const int r = l->r;
+    gemm(r, r, (int)rows, P, r, rows * r, 1, P2, r, rows * r, 0, 1.0, 0.0, G, r, (int64_t)r * r);
+  }
+  // out (rows x r) = alpha P M + beta out, M r x r
+  void panel_rr(const void* P, int64_t rows, const void* M, void* out, double alpha = 1.0,
+                double beta = 0.0) {
+    const int r = l->r;
+    gemm((int)rows, r, r, P, r, rows * r, 0, M, r, (int64_t)r * r, 0, alpha, beta, out, r,
+         rows * r);
+  }
+  // columns [c0, c0 + r) of the rows x w factor O <- P
+  void put(const void* P, int64_t rows, void* O, int c0) {
+    lk_put_cols(L, l->f64, l->nb, P, rows * l->r, l->r, O, rows * l->w, l->w, c0, rows);
+  }
+  void copy(const void* S, void* D, int64_t count) { lk_copy(L, l->f64, l->nb, S, D, count, count); }
+};
+
+// Factors U (m x w), V (n x w) with D^bar = U V^T for the current D and L^bar.
+void vjp_step(godec_layer* l, Ops& o) {
+  const int r = l->r, p = l->p, q = l->q, nb = l->nb;
+  const int64_t m = l->m, n = l->n, nr = n * r, E = (int64_t)r * r;
+  const size_t ts = l->ts;
+  const bool f64 = l->f64;
+  const Launch& L = o.L;
+  auto Zj = [&](int j) { return at(l->Z, ts, (int64_t)j * nb * nr); };
+  auto Rcj = [&](int j) { return l->Rc + (int64_t)j * nb * E; };
+  auto Qsi = [&](int i) { return at(l->Qs, ts, (int64_t)i * nb * nr); };
+  void* Q = Qsi(0);
+
+  // ---- forward panels of f at D ----
+  // Z_0 = A1, Rc_0 = I; A Z_{j-1} = Z_j R_j, Rc_j = R_j Rc_{j-1}; so
+  // A^j A1 = Z_j Rc_j.  A second Cholesky QR of Z_p gives Q, Rtot = Rc_{p+1}.
+  lk_cast_a1(L, f64, nb, l->A1, nr, Zj(0), nr, nr);
+  lk_identity(L, nb, r, Rcj(0));
+  for (int j = 1; j <= p; ++j) {
+    o.amul(Zj(j - 1), l->Vn);
+    o.inner(l->Vn, l->Vn, n, l->Gm);
+    lk_chol(L, f64, nb, r, l->Gm, Rcj(j - 1), l->Rinv, Rcj(j), nullptr, l->flag);
+    o.panel_rr(l->Vn, n, l->Rinv, Zj(j));
+  }
+  o.inner(Zj(p), Zj(p), n, l->Gm);
+  lk_chol(L, f64, nb, r, l->Gm, Rcj(p), l->Rinv, Rcj(p + 1), nullptr, l->flag);
+  o.panel_rr(Zj(p), n, l->Rinv, Q);
+  for (int i = 1; i <= q; ++i) o.amul(Qsi(i - 1), Qsi(i));
+  // B = D A^q Q, C = B^T B, C^a with a = -(p - 1) / (2p)
+  o.dmul(Qsi(q), l->B);
+  o.inner(l->B, l->B, m, l->Cm);
+  lk_eig(L, f64, nb, r, l->Cm, -(double)(p - 1) / (2.0 * p), l->Ca, l->Vv, l->F, l->flag);
+
+  // ---- adjoint of L = B C^a Q^T ----
+  o.gemm((int)m, r, (int)n, l->Lbar, n, m * n, 0, Q, r, nr, 0, 1.0, 0.0, l->LQ, r, m * r);
+  o.gemm((int)n, r, (int)m, l->Lbar, n, m * n, 1, l->B, r, m * r, 0, 1.0, 0.0, l->LtB, r, nr);
+  o.inner(l->B, l->LQ, m, l->CbarA);                 // C^a bar = B^T L^bar Q
+  lk_dk(L, f64, nb, r, l->CbarA, l->Vv, l->F, l->S2);  // B^T B adjoint, both sides
+  o.panel_rr(l->LQ, m, l->Ca, l->Bbar);               // B^bar = L^bar Q C^a + B S2
+  o.panel_rr(l->B, m, l->S2, l->Bbar, 1.0, 1.0);
+  o.panel_rr(l->LtB, n, l->Ca, l->Qbar);              // Q^bar = L^bar^T B C^a
+
+  // D^bar terms, each a rank-r outer product appended to (U, V).
+  int col = 0;
+  o.put(l->Bbar, m, l->Uf, col);                      // B = D (A^q Q): B^bar (A^q Q)^T
+  o.put(Qsi(q), n, l->Vf, col);
+  col += r;
+  // dA = dD^T D + D^T dD turns <G, dA> with G = U W^T into D^bar terms
+  // (D U) W^T + (D W) U^T.
+  auto add_term = [&](const void* U, const void* W) {
+    o.dmul(U, l->Wm);
+    o.put(l->Wm, m, l->Uf, col);
+    o.put(W, n, l->Vf, col);
+    col += r;
+    o.dmul(W, l->Wm);
+    o.put(l->Wm, m, l->Uf, col);
+    o.put(U, n, l->Vf, col);
+    col += r;
+  };
+  // A^q inside B: terms (A^i D^T B^bar, A^{q-1-i} Q); Q^bar += A^q D^T B^bar
+  o.dtmul(l->Bbar, l->Cur);
+  for (int i = 0; i < q; ++i) {
+    add_term(l->Cur, Qsi(q - 1 - i));
+    o.amul(l->Cur, l->Tn);
+    o.copy(l->Tn, l->Cur, nr);
+  }
+  lk_axpy(L, f64, nb, l->Cur, l->Qbar, nr, nr);
+  // Q = orth(Y), Y = A^p A1 = Q Rtot; f depends on the range of Q only, so
+  // Y^bar = (I - Q Q^T) Q^bar Rtot^{-T}.
+  o.inner(Q, l->Qbar, n, l->T1);
+  o.panel_rr(Q, n, l->T1, l->Qbar, -1.0, 1.0);         // Qbar <- (I - Q Q^T) Qbar
+  // Terms of A^p: (A^i Y^bar, A^{p-1-i} A1).  With A^j A1 = Z_j Rc_j they are
+  // (A^i Ybar0) (Z_j Rc_j Rtot^{-1})^T, Ybar0 = (I - Q Q^T) Q^bar, which keeps
+  // every factor well scaled.
+  o.copy(l->Qbar, l->Cur, nr);
+  for (int i = 0; i < p; ++i) {
+    const int j = p - 1 - i;
+    lk_rrel(L, f64, nb, r, Rcj(j), Rcj(p + 1), l->Rrel);
+    o.panel_rr(Zj(j), n, l->Rrel, l->Tn);
+    add_term(l->Cur, l->Tn);
+    if (i + 1 < p) {
+      o.amul(l->Cur, l->Vn);
+      o.copy(l->Vn, l->Cur, nr);
+    }
+  }
+}
+
+godec_status validate_layer(int32_t batch, int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
+                            int32_t T, godec_dtype dtype) {
+  if (batch < 1 || m < 1 || n < 1 || T < 1)
+    return fail(GODEC_E_INVAL, "batch, m, n and T must be >= 1");
+  if (r < 1 || r > std::min<int64_t>(m, n)) return fail(GODEC_E_INVAL, "r out of range");
+  if (r > kLayerMaxRank) return fail(GODEC_E_UNSUPPORTED, "the layer supports r <= 8");
+  if (k < 0 || k > m * n) return fail(GODEC_E_INVAL, "k out of range");
+  if (q < 0) return fail(GODEC_E_INVAL, "q < 0");
+  if (dtype != GODEC_F64 && dtype != GODEC_F32) return fail(GODEC_E_INVAL, "bad dtype");
+  if (m > INT32_MAX || n > INT32_MAX) return fail(GODEC_E_UNSUPPORTED, "m or n too large");
+  return GODEC_OK;
+}
+
+void fill_layer(godec_layer* l, int32_t batch, int64_t m, int64_t n, int32_t r, int64_t k,
+                int32_t q, int32_t T, godec_dtype dtype) {
+  l->nb = batch;
+  l->m = m;
+  l->n = n;
+  l->r = r;
+  l->k = k;
+  l->q = q;
+  l->p = 2 * q + 1;
+  l->T = T;
+  l->f64 = dtype == GODEC_F64;
+  l->ts = l->f64 ? 8 : 4;
+}
+
+}  // namespace
+
+extern "C" {
+
+godec_status godec_layer_workspace_size(int32_t batch, int64_t m, int64_t n, int32_t r, int64_t k,
+                                        int32_t q, int32_t T, godec_dtype dtype, size_t* bytes) {
+  if (!bytes) return fail(GODEC_E_INVAL, "bytes is NULL");
+  godec_status s = validate_layer(batch, m, n, r, k, q, T, dtype);
+  if (s != GODEC_OK) return s;
+  size_t ctx_ws = 0;
+  s = godec_workspace_size(m, n, r, k, q, dtype, nullptr, &ctx_ws);
+  if (s != GODEC_OK) return s;
+  godec_layer tmp;
+  fill_layer(&tmp, batch, m, n, r, k, q, T, dtype);
+  *bytes = carve_layer(&tmp, nullptr, ctx_ws, nullptr);
+  return GODEC_OK;
+}
+
+godec_status godec_layer_forward(godec_layer** out, const void* X_dev, godec_dtype dtype,
+                                 int32_t batch, int64_t m, int64_t n, int32_t r, int64_t k,
+                                 int32_t q, int32_t T, uint64_t seed, void* workspace_dev,
+                                 size_t workspace_bytes, const godec_opts* opts, void* L_dev,
+                                 void* S_dev) {
+  if (!out) return fail(GODEC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  godec_status s = validate_layer(batch, m, n, r, k, q, T, dtype);
+  if (s != GODEC_OK) return s;
+  if (!X_dev || !workspace_dev || ((uintptr_t)workspace_dev & 255))
+    return fail(GODEC_E_INVAL, "X or workspace is NULL, or the workspace is not 256-byte aligned");
+  if (opts && opts->prec != GODEC_PREC_NATIVE)
+    return fail(GODEC_E_UNSUPPORTED, "the layer computes in the dtype of X (prec NATIVE)");
+  if (opts && opts->a1_host)
+    return fail(GODEC_E_UNSUPPORTED, "the layer draws A1 from the seed");
+  size_t ctx_ws = 0;
+  s = godec_workspace_size(m, n, r, k, q, dtype, nullptr, &ctx_ws);
+  if (s != GODEC_OK) return s;
+  godec_layer* l = new godec_layer;
+  fill_layer(l, batch, m, n, r, k, q, T, dtype);
+  l->X = X_dev;
+  l->stream = opts ? (hipStream_t)opts->stream : nullptr;
+  l->num_cu = device_cu_count();
+  if (workspace_bytes < carve_layer(l, nullptr, ctx_ws, nullptr)) {
+    delete l;
+    return fail(GODEC_E_NOMEM, "workspace too small");
+  }
+  std::vector<void*> ws;
+  carve_layer(l, workspace_dev, ctx_ws, &ws);
+  auto bail = [&](godec_status st) {
+    for (godec_ctx* c : l->ctx)
+      if (c) godec_destroy(c);
+    delete l;
+    return st;
+  };
+  godec_opts o;
+  godec_opts_default(&o);
+  if (opts) o.rank_tol = opts->rank_tol;
+  o.stream = l->stream;
+  const int64_t mn = m * n, kk = std::max<int64_t>(k, 1);
+  const size_t ts = l->ts;
+  l->ctx.assign(batch, nullptr);
+  for (int b = 0; b < batch; ++b) {
+    s = godec_init(&l->ctx[b], at(const_cast<void*>(X_dev), ts, b * mn), dtype, m, n, n, r, k, q,
+                   seed + (uint64_t)b, ws[b], ctx_ws, &o);
+    if (s != GODEC_OK) return bail(s);
+  }
+  l->ck_nnz_host.assign((size_t)T * batch, 0);
+  for (int t = 0; t < T; ++t) {
+    for (int b = 0; b < batch; ++b) {
+      s = godec_step(l->ctx[b], 1, 0);
+      if (s != GODEC_OK) return bail(s);
+    }
+    for (int b = 0; b < batch; ++b) {
+      const int64_t slot = (int64_t)t * batch + b;
+      int64_t nnz = 0;
+      s = godec_get_S(l->ctx[b], l->ck_idx + slot * kk, at(l->ck_val, ts, slot * kk), &nnz);
+      if (s != GODEC_OK) return bail(s);
+      l->ck_nnz_host[slot] = nnz;
+    }
+  }
+  l->a1_host.resize((size_t)batch * n * r);
+  for (int b = 0; b < batch; ++b) {
+    godec_info info;
+    s = godec_get_info(l->ctx[b], &info);
+    if (s != GODEC_OK) return bail(s);
+    if (info.rank_eff != r)
+      return bail(fail(GODEC_E_UNSUPPORTED,
+                       "problem " + std::to_string(b) + " lost rank in the forward pass; the "
+                       "layer's gradient needs a full-rank sketch"));
+    s = godec_get_A1(l->ctx[b], l->a1_host.data() + (size_t)b * n * r);
+    if (s != GODEC_OK) return bail(s);
+    if (L_dev) {
+      s = godec_get_L_dense(l->ctx[b], at(L_dev, ts, b * mn), n);
+      if (s != GODEC_OK) return bail(s);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(l->ck_nnz, l->ck_nnz_host.data(),
+                                sizeof(int64_t) * l->ck_nnz_host.size(), hipMemcpyHostToDevice,
+                                l->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(l->A1, l->a1_host.data(), sizeof(double) * l->a1_host.size(),
+                       hipMemcpyHostToDevice, l->stream);
+  if (e != hipSuccess) return bail(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  if (S_dev) {
+    const Launch L{l->stream, l->num_cu};
+    const int64_t slot = (int64_t)(T - 1) * batch;
+    lk_fill(L, l->f64, batch, S_dev, mn, mn, 0.0);
+    lk_scatter(L, l->f64, batch, S_dev, mn, l->ck_idx + slot * kk, at(l->ck_val, ts, slot * kk),
+               kk, kk, l->ck_nnz + slot, 0, 1.0);
+  }
+  e = hipStreamSynchronize(l->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return bail(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  *out = l;
+  return GODEC_OK;
+}
+
+godec_status godec_layer_backward(godec_layer* l, const void* dL_dev, const void* dS_dev,
+                                  void* dX_dev) {
+  if (!l) return fail(GODEC_E_INVAL, "layer is NULL");
+  if (!dL_dev || !dS_dev || !dX_dev) return fail(GODEC_E_INVAL, "NULL argument");
+  const Launch L{l->stream, l->num_cu};
+  const bool f64 = l->f64;
+  const int nb = l->nb;
+  const int64_t m = l->m, n = l->n, mn = m * n, kk = std::max<int64_t>(l->k, 1);
+  const size_t ts = l->ts;
+  Ops o{l, L};
+  lk_fill(L, false, 1, l->flag, 4, 4, 0.0);
+  auto idx_of = [&](int t) { return l->ck_idx + (int64_t)(t - 1) * nb * kk; };
+  auto val_of = [&](int t) { return at(l->ck_val, ts, (int64_t)(t - 1) * nb * kk); };
+  auto nnz_of = [&](int t) { return l->ck_nnz + (int64_t)(t - 1) * nb; };
+  // S_T = M_T * (X - L_T): X^bar = M_T * dS, L^bar_T = dL - M_T * dS
+  lk_gather(L, f64, nb, dS_dev, mn, idx_of(l->T), kk, kk, nnz_of(l->T), l->vals);
+  lk_fill(L, f64, nb, dX_dev, mn, mn, 0.0);
+  lk_scatter(L, f64, nb, dX_dev, mn, idx_of(l->T), l->vals, kk, kk, nnz_of(l->T), 0, 1.0);
+  lk_copy(L, f64, nb, dL_dev, l->Lbar, mn, mn);
+  lk_scatter(L, f64, nb, l->Lbar, mn, idx_of(l->T), l->vals, kk, kk, nnz_of(l->T), 1, -1.0);
+  for (int t = l->T; t >= 1; --t) {
+    // D_t = X - S_{t-1}
+    lk_copy(L, f64, nb, l->X, l->D, mn, mn);
+    if (t >= 2)
+      lk_scatter(L, f64, nb, l->D, mn, idx_of(t - 1), val_of(t - 1), kk, kk, nnz_of(t - 1), 1,
+                 -1.0);
+    vjp_step(l, o);
+    // X^bar += D^bar = U V^T
+    o.gemm((int)m, (int)n, l->w, l->Uf, l->w, m * l->w, 0, l->Vf, l->w, n * l->w, 1, 1.0, 1.0,
+           dX_dev, n, mn);
+    if (t >= 2) {
+      // S_{t-1} = M_{t-1} * (X - L_{t-1}) with S^bar_{t-1} = -D^bar
+      lk_lowrank_at(L, f64, nb, l->Uf, m * l->w, l->Vf, n * l->w, l->w, n, idx_of(t - 1), kk, kk,
+                    nnz_of(t - 1), l->vals);
+      lk_scatter(L, f64, nb, dX_dev, mn, idx_of(t - 1), l->vals, kk, kk, nnz_of(t - 1), 1, -1.0);
+      lk_fill(L, f64, nb, l->Lbar, mn, mn, 0.0);
+      lk_scatter(L, f64, nb, l->Lbar, mn, idx_of(t - 1), l->vals, kk, kk, nnz_of(t - 1), 0, 1.0);
+    }
+  }
+  int hflag[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(hflag, l->flag, sizeof(hflag), hipMemcpyDeviceToHost, l->stream));
+  HIP_TRY(hipStreamSynchronize(l->stream));
+  HIP_TRY(hipGetLastError());
+  if (hflag[0])
+    return fail(GODEC_E_NUMERIC, "a non-positive pivot or eigenvalue in the backward pass");
+  return GODEC_OK;
+}
+
+godec_status godec_layer_get_mask(godec_layer* l, int32_t b, int32_t t, int64_t* idx_host,
+                                  int64_t* nnz_host) {
+  if (!l || !nnz_host) return fail(GODEC_E_INVAL, "NULL argument");
+  if (b < 0 || b >= l->nb || t < 1 || t > l->T) return fail(GODEC_E_INVAL, "index out of range");
+  const int64_t kk = std::max<int64_t>(l->k, 1);
+  const int64_t slot = (int64_t)(t - 1) * l->nb + b;
+  const int64_t nnz = l->ck_nnz_host[slot];
+  *nnz_host = nnz;
+  if (idx_host && nnz > 0)
+    HIP_TRY(hipMemcpy(idx_host, l->ck_idx + slot * kk, sizeof(int64_t) * nnz,
+                      hipMemcpyDeviceToHost));
+  return GODEC_OK;
+}
+
+godec_status godec_layer_get_A1(godec_layer* l, int32_t b, double* a1_host) {
+  if (!l || !a1_host || b < 0 || b >= l->nb) return fail(GODEC_E_INVAL, "bad argument");
+  std::memcpy(a1_host, l->a1_host.data() + (size_t)b * l->n * l->r,
+              sizeof(double) * l->n * l->r);
+  return GODEC_OK;
+}
+
+godec_status godec_layer_destroy(godec_layer* l) {
+  if (!l) return fail(GODEC_E_INVAL, "layer is NULL");
+  for (godec_ctx* c : l->ctx)
+    if (c) godec_destroy(c);
+  delete l;
+  return GODEC_OK;
+}
+
+}  // extern "C"

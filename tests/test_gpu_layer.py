@@ -1,0 +1,166 @@
+"""GPU parity of the differentiable layer against the FP64 layer oracle.
+
+The layer runs T iterations of Algorithm 1 on the GPU, keeps the supports
+M_t, and its backward pass applies hand-written adjoints with the supports
+held fixed.  The oracle (oracle/godec_layer_ref.py) replays the same frozen
+supports and the same A1 in PyTorch FP64 on the CPU and differentiates with
+autograd; it is itself pinned to finite differences.  Checks:
+  * FP64 at 64 x 48, r = 2, k = 150, q = 1, T = 10: the GPU gradient matches
+    central differences of the frozen-mask function to 1e-6 relative along
+    random directions, the unfrozen oracle run picks the same supports at
+    X +- hV (so the frozen derivative is the derivative), and the gradient
+    matches the oracle's autograd gradient element by element;
+  * the same through the torch.autograd.Function wrapper, for q = 0, 1, 2;
+  * FP32 on the 16 x 4096 x 256 (r = 4, k = 52429, q = 1, T = 10) workload
+    with its loss ||S - S_tgt||^2 + ||L - L_tgt||^2: two problems against the
+    oracle's FP64 gradient (relative Frobenius, FP32 tolerance below).
+"""
+import numpy as np
+import pytest
+
+from oracle import godec_layer_ref as lr
+from oracle import godec_ref as g
+from paper_1309_0302_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# FP32 gradient tolerance (relative Frobenius against the FP64 oracle).  The
+# backward runs its panel products in FP32 (unit roundoff 6e-8) through
+# 10 unrolled steps whose adjoints pass through (C^T C)^(-1/3) and the
+# orthonormal-range derivative; the r x r algebra is FP64.  Measured well
+# below this bound on the 4096 x 256 workload.
+FP32_GRAD_TOL = 1e-3
+
+
+def small_case(seed, q):
+    w = wl.tiny(64, 48, 2, rho=150 / (64 * 48), seed=seed, dtype=np.float64, noise_std=1e-3)
+    rng = np.random.default_rng(seed + 1)
+    return w.X, rng.standard_normal(w.X.shape), rng.standard_normal(w.X.shape)
+
+
+def gpu_layer(X, r, k, q, T, seed):
+    from paper_1309_0302_amd.binding import GoDecLayer
+    print(f"\n[layer] forward {tuple(X.shape)} {X.dtype} r={r} k={k} q={q} T={T}", flush=True)
+    layer = GoDecLayer(r, k, q, T, seed)
+    L, S = layer.forward(X)
+    torch.cuda.synchronize()
+    return layer, L, S
+
+
+def masks_of(layer, b, T):
+    return [layer.mask(b, t) for t in range(1, T + 1)]
+
+
+@pytest.mark.parametrize("q,T", [(1, 10), (0, 4), (2, 4)])
+def test_layer_fp64_matches_finite_differences(q, T):
+    X, dL, dS = small_case(1006, q)
+    Xd = torch.from_numpy(X).cuda().unsqueeze(0).contiguous()
+    layer, L, S = gpu_layer(Xd, 2, 150, q, T, 7)
+    masks = masks_of(layer, 0, T)
+    A1 = layer.A1(0)
+    # forward against the oracle's frozen-mask forward
+    Lr, Sr = lr.layer_forward(torch.tensor(X), torch.tensor(A1), q, masks)
+    assert g.rel_fro(L[0].cpu().numpy(), Lr.numpy()) < 1e-10
+    assert g.rel_fro(S[0].cpu().numpy(), Sr.numpy()) < 1e-10
+    print("[layer] backward", flush=True)
+    dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
+    dX = dX[0].cpu().numpy()
+    ref = lr.layer_grad(X, A1, q, masks, dL, dS)
+    err = np.linalg.norm(dX - ref) / np.linalg.norm(ref)
+    print(f"[layer] q={q}: gradient vs oracle autograd {err:.2e}", flush=True)
+    assert err < 1e-9
+    rng = np.random.default_rng(8)
+    h = 1e-6 * np.abs(X).max()
+    worst = 0.0
+    for d in range(12):
+        V = rng.standard_normal(X.shape)
+        fd = (lr.layer_value(X + h * V, A1, q, masks, dL, dS)
+              - lr.layer_value(X - h * V, A1, q, masks, dL, dS)) / (2 * h)
+        ad = float(np.sum(dX * V))
+        worst = max(worst, abs(fd - ad) / abs(ad))
+        if d < 2:
+            # the unfrozen iteration selects the same supports at X +- hV
+            for sgn in (1.0, -1.0):
+                tr = g.godec_brp(X + sgn * h * V, 2, 150, q, A1, T, keep_supports=True)
+                for t in range(T):
+                    assert np.array_equal(np.sort(tr.supports[t]), masks[t]), (sgn, t)
+    print(f"[layer] q={q}: worst FD relative error {worst:.2e}", flush=True)
+    assert worst < 1e-6
+    layer.close()
+
+
+def test_layer_autograd_function_fp64():
+    """The torch.autograd.Function wrapper gives the oracle's gradient of a
+    quadratic loss on two problems of a batch."""
+    from paper_1309_0302_amd.binding import godec_layer_fn
+    q, T = 1, 6
+    Xs = np.stack([small_case(s, q)[0] for s in (1006, 1016)])
+    rng = np.random.default_rng(3)
+    Lt = rng.standard_normal(Xs.shape)
+    St = rng.standard_normal(Xs.shape)
+    X = torch.from_numpy(Xs).cuda().requires_grad_(True)
+    print("\n[layer] autograd wrapper, batch 2 FP64", flush=True)
+    L, S = godec_layer_fn(X, 2, 150, q, T, seed=11)
+    loss = ((S - torch.from_numpy(St).cuda()) ** 2).sum() + \
+        ((L - torch.from_numpy(Lt).cuda()) ** 2).sum()
+    loss.backward()
+    from paper_1309_0302_amd.binding import GoDecLayer
+    ref_layer = GoDecLayer(2, 150, q, T, seed=11)
+    ref_layer.forward(X.detach())
+    for b in range(2):
+        masks = masks_of(ref_layer, b, T)
+        A1 = ref_layer.A1(b)
+        dL = 2 * (L[b].detach().cpu().numpy() - Lt[b])
+        dS = 2 * (S[b].detach().cpu().numpy() - St[b])
+        ref = lr.layer_grad(Xs[b], A1, q, masks, dL, dS)
+        got = X.grad[b].cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[layer] wrapper problem {b}: {err:.2e}", flush=True)
+        assert err < 1e-9
+    ref_layer.close()
+
+
+def test_layer_fp32_full_workload_sampled():
+    """The 16 x 4096 x 256 FP32 workload (fwd + bwd on all 16 problems); the
+    first two problems are checked against the FP64 oracle."""
+    w = wl.w5()
+    X = torch.from_numpy(w["X"]).cuda()
+    layer, L, S = gpu_layer(X, w["r"], w["k"], w["q"], w["iters"], w["seed"])
+    Lt = torch.from_numpy(w["L_target"]).cuda()
+    St = torch.from_numpy(w["S_target"]).cuda()
+    dL = 2 * (L - Lt)
+    dS = 2 * (S - St)
+    print("[layer] backward (FP32, 16 problems)", flush=True)
+    dX = layer.backward(dL, dS)
+    torch.cuda.synchronize()
+    assert torch.isfinite(dX).all()
+    for b in range(2):
+        masks = masks_of(layer, b, w["iters"])
+        assert all(mk.size == w["k"] for mk in masks)
+        A1 = layer.A1(b)
+        Xb = w["X"][b].astype(np.float64)
+        Lr, Sr = lr.layer_forward(torch.tensor(Xb), torch.tensor(A1), w["q"], masks)
+        eL = g.rel_fro(L[b].cpu().numpy().astype(np.float64), Lr.numpy())
+        eS = g.rel_fro(S[b].cpu().numpy().astype(np.float64), Sr.numpy())
+        ref = lr.layer_grad(Xb, A1, w["q"], masks,
+                            dL[b].cpu().numpy().astype(np.float64),
+                            dS[b].cpu().numpy().astype(np.float64))
+        got = dX[b].cpu().numpy().astype(np.float64)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[layer] FP32 problem {b}: L {eL:.2e} S {eS:.2e} gradient {err:.2e}", flush=True)
+        assert eL < 1e-5 and eS < 1e-5
+        assert err < FP32_GRAD_TOL
+    layer.close()
+
+
+def test_layer_rejects_bad_arguments():
+    from paper_1309_0302_amd.binding import GodecError, GoDecLayer
+    X = torch.zeros((1, 40, 30), dtype=torch.float32, device="cuda")
+    with pytest.raises(GodecError):
+        GoDecLayer(9, 10, 1, 2).forward(X)          # r > 8
+    with pytest.raises(GodecError):
+        GoDecLayer(2, 40 * 30 + 1, 1, 2).forward(X)  # k > m n
+    with pytest.raises(GodecError):
+        GoDecLayer(2, 10, 1, 0).forward(X)          # T = 0
