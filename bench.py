@@ -141,6 +141,52 @@ def run_batched(iters, warmup, seed=1004):
             "median_final_rel_err_sq": float(np.median(rel))}
 
 
+def run_layer(warmup, seed=1005):
+    """The differentiable layer on its 16 x 4096 x 256 FP32 workload (r = 4,
+    k = 5 %, q = 1, T = 10): forward, then the hand-written backward of the
+    loss ||S - S_tgt||^2 + ||L - L_tgt||^2, each timed on the host around a
+    synchronised call."""
+    import torch
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GoDecLayer
+    w = workloads.w5(seed=seed)
+    X = torch.from_numpy(w["X"]).cuda()
+    Lt = torch.from_numpy(w["L_target"]).cuda()
+    St = torch.from_numpy(w["S_target"]).cuda()
+    nb, m, n = X.shape
+    fwd, bwd = [], []
+    for it in range(warmup + 1):
+        layer = GoDecLayer(w["r"], w["k"], w["q"], w["iters"], seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, S = layer.forward(X)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dL = 2 * (L - Lt)
+        dS = 2 * (S - St)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        dX = layer.backward(dL, dS)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        layer.close()
+        fwd.append((t1 - t0) * 1e3)
+        bwd.append((t3 - t2) * 1e3)
+    assert bool(torch.isfinite(dX).all())
+    p, q, T = 2 * w["q"] + 1, w["q"], w["iters"]
+    # algorithmic bytes of the backward: per unrolled step the forward panels
+    # of f read D 2p + 2q + 1 times, the adjoint reads L^bar twice and D
+    # 1 + 4q + 2p + 2(p - 1) times; D = X - S is written once and X^bar
+    # read and written once
+    reads = (2 * p + 2 * q + 1) + 2 + (1 + 4 * q + 2 * p + 2 * (p - 1))
+    bytes_bwd = T * (reads + 1 + 1 + 2) * nb * m * n * 4
+    return {"workload": f"w5_{nb}x{m}x{n}_r{w['r']}_T{T}_f32", "batch": nb,
+            "forward_ms": round(fwd[-1], 3), "backward_ms": round(bwd[-1], 3),
+            "fwd_bwd_ms": round(fwd[-1] + bwd[-1], 3),
+            "backward_algorithmic_bytes": bytes_bwd,
+            "backward_achieved_GBps": round(bytes_bwd / (bwd[-1] * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(w, iters):
     """The FP64 oracle on the host cores, `iters` iterations of the same X."""
     import numpy as np
@@ -174,6 +220,7 @@ def main():
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=25)
+    ap.add_argument("--skip-layer", action="store_true")
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
     args = ap.parse_args()
@@ -234,6 +281,11 @@ def main():
         log("[bench] batched form: 64 problems")
         out["batched"] = run_batched(args.batch_iters, min(args.warmup, 3))
         log(f"[bench] batched {out['batched']['ms_per_iteration']} ms/iteration")
+    if not args.skip_layer:
+        log("[bench] differentiable layer: 16 x 4096 x 256, T = 10")
+        out["layer"] = run_layer(min(args.warmup, 1))
+        log(f"[bench] layer fwd {out['layer']['forward_ms']} ms, "
+            f"bwd {out['layer']['backward_ms']} ms")
     if not args.skip_cpu:
         log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)

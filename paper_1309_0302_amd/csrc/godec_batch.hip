@@ -298,6 +298,20 @@ godec_status check_index(godec_batch* b, int32_t i) {
 
 }  // namespace
 
+namespace godec_host {
+
+godec_status batch_snapshot_S(godec_batch* b, int64_t* idx_dev, float* val_dev, int64_t kstride,
+                              int64_t* nnz_dev) {
+  if (!b || b->iters_done == 0) return fail(GODEC_E_STATE, "no iteration has run");
+  const Launch L{b->stream, b->num_cu};
+  bl_copy_lists(L, b->dprobs, b->count, (int)((b->iters_done - 1) & 1), b->max_k, idx_dev, val_dev,
+                kstride, nnz_dev);
+  HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
+}  // namespace godec_host
+
 extern "C" {
 
 godec_status godec_batch_workspace_size(const godec_problem* probs, int32_t count, int32_t q,

@@ -317,6 +317,8 @@ void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 // (bl_update_d also advances the device iteration counter)
 void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 void bl_init(const Launch& L, const BatchArgs& a);   // D = X, norms, state
+void bl_copy_lists(const Launch& L, const BProb* probs_dev, int nprob, int list, int64_t kmax,
+                   int64_t* idx_out, float* val_out, int64_t kstride, int64_t* nnz_out);
 void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, float* R,
                  int64_t ldr);
 void bl_small_init(const Launch& L, const BatchArgs& a);

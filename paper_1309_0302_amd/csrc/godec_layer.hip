@@ -1,8 +1,11 @@
 // libgodec host side of the differentiable GoDec layer (godec_layer_*).
 //
 // Forward: every problem of the batch runs T iterations of Algorithm 1
-// (Sec. 3.1.3) through the single-problem path, and the support and values of
-// S_t are checkpointed after each iteration.
+// (Sec. 3.1.3), and the support and values of S_t are checkpointed after each
+// iteration.  FP32 problems within the batched form's limits (n <= 512,
+// r <= 8) run as one batched decomposition (graph-replayed iterations, one
+// snapshot launch per iteration); the others run one single-problem context
+// per batch member.
 //
 // Backward: with the supports frozen, S_t = M_t * (X - L_t) and
 // L_t = f(X - S_{t-1}); for t = T .. 1 the library rebuilds D_t = X - S_{t-1}
@@ -34,7 +37,8 @@ struct godec_layer {
   hipStream_t stream = nullptr;
   int num_cu = 256;
   const void* X = nullptr;
-  std::vector<godec_ctx*> ctx;
+  bool use_batch = false;  // forward through the batched form
+  size_t sub_ws = 0;       // workspace of one context, or of the whole batch
   // Checkpoints of S_t, t = 1..T: slot (t - 1) * nb + b, capacity max(k, 1).
   int64_t* ck_idx = nullptr;
   void* ck_val = nullptr;
@@ -65,7 +69,9 @@ namespace {
 
 inline void* at(void* p, size_t ts, int64_t off) { return (char*)p + ts * off; }
 
-// Carve the workspace (base == nullptr only measures).
+// Carve the workspace (base == nullptr only measures).  The forward's own
+// workspace comes first: nb single-problem workspaces of ctx_ws bytes, or one
+// batch workspace of ctx_ws bytes.
 size_t carve_layer(godec_layer* l, void* base, size_t ctx_ws, std::vector<void*>* ctx_ptr) {
   Carver cv{(char*)base};
   const int nb = l->nb, r = l->r, p = l->p, q = l->q;
@@ -74,7 +80,7 @@ size_t carve_layer(godec_layer* l, void* base, size_t ctx_ws, std::vector<void*>
   const size_t ts = l->ts;
   l->w = r + 2 * r * (p + q);
   if (ctx_ptr) ctx_ptr->clear();
-  for (int b = 0; b < nb; ++b) {
+  for (int b = 0; b < (l->use_batch ? 1 : nb); ++b) {
     void* w = cv.take(ctx_ws);
     if (ctx_ptr) ctx_ptr->push_back(w);
   }
@@ -263,6 +269,146 @@ void fill_layer(godec_layer* l, int32_t batch, int64_t m, int64_t n, int32_t r, 
   l->T = T;
   l->f64 = dtype == GODEC_F64;
   l->ts = l->f64 ? 8 : 4;
+  l->use_batch = !l->f64 && n <= kBatchMaxN && r <= kBatchRP;
+}
+
+std::vector<godec_problem> layer_problems(const godec_layer* l, const void* X_dev, uint64_t seed) {
+  std::vector<godec_problem> pr(l->nb);
+  for (int b = 0; b < l->nb; ++b) {
+    godec_problem& g = pr[b];
+    std::memset(&g, 0, sizeof(g));
+    g.X_dev = X_dev ? (const char*)X_dev + l->ts * b * l->m * l->n : nullptr;
+    g.m = l->m;
+    g.n = l->n;
+    g.ldx = l->n;
+    g.r = l->r;
+    g.k = l->k;
+    g.seed = seed + (uint64_t)b;
+  }
+  return pr;
+}
+
+// Bytes of the forward's own workspace (per context, or for the batch).
+godec_status sub_workspace(godec_layer* l, size_t* bytes) {
+  if (!l->use_batch)
+    return godec_workspace_size(l->m, l->n, l->r, l->k, l->q, l->f64 ? GODEC_F64 : GODEC_F32,
+                                nullptr, bytes);
+  const std::vector<godec_problem> pr = layer_problems(l, nullptr, 0);
+  return godec_batch_workspace_size(pr.data(), l->nb, l->q, nullptr, bytes);
+}
+
+
+godec_status rank_error(int b) {
+  return fail(GODEC_E_UNSUPPORTED, "problem " + std::to_string(b) +
+                                       " lost rank in the forward pass; the layer's gradient "
+                                       "needs a full-rank sketch");
+}
+
+// Forward through one single-problem context per batch member.
+godec_status forward_single(godec_layer* l, const void* X_dev, uint64_t seed,
+                            const std::vector<void*>& ws, const godec_opts& o, void* L_dev) {
+  const int nb = l->nb, T = l->T;
+  const int64_t m = l->m, n = l->n, mn = m * n, kk = std::max<int64_t>(l->k, 1);
+  const size_t ts = l->ts;
+  const godec_dtype dt = l->f64 ? GODEC_F64 : GODEC_F32;
+  std::vector<godec_ctx*> ctx(nb, nullptr);
+  auto done = [&](godec_status st) {
+    for (godec_ctx* c : ctx)
+      if (c) godec_destroy(c);
+    return st;
+  };
+  godec_status s;
+  for (int b = 0; b < nb; ++b) {
+    s = godec_init(&ctx[b], at(const_cast<void*>(X_dev), ts, b * mn), dt, m, n, n, l->r, l->k,
+                   l->q, seed + (uint64_t)b, ws[b], l->sub_ws, &o);
+    if (s != GODEC_OK) return done(s);
+  }
+  for (int t = 0; t < T; ++t) {
+    for (int b = 0; b < nb; ++b) {
+      s = godec_step(ctx[b], 1, 0);
+      if (s != GODEC_OK) return done(s);
+    }
+    for (int b = 0; b < nb; ++b) {
+      const int64_t slot = (int64_t)t * nb + b;
+      int64_t nnz = 0;
+      s = godec_get_S(ctx[b], l->ck_idx + slot * kk, at(l->ck_val, ts, slot * kk), &nnz);
+      if (s != GODEC_OK) return done(s);
+      l->ck_nnz_host[slot] = nnz;
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    godec_info info;
+    s = godec_get_info(ctx[b], &info);
+    if (s != GODEC_OK) return done(s);
+    if (info.rank_eff != l->r) return done(rank_error(b));
+    s = godec_get_A1(ctx[b], l->a1_host.data() + (size_t)b * n * l->r);
+    if (s != GODEC_OK) return done(s);
+    if (L_dev) {
+      s = godec_get_L_dense(ctx[b], at(L_dev, ts, b * mn), n);
+      if (s != GODEC_OK) return done(s);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(l->ck_nnz, l->ck_nnz_host.data(),
+                                sizeof(int64_t) * l->ck_nnz_host.size(), hipMemcpyHostToDevice,
+                                l->stream);
+  if (e != hipSuccess) return done(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  return done(GODEC_OK);
+}
+
+// Forward through one batched decomposition of all members (FP32).  The
+// batch runs on a stream of its own (its iterations are graph replays, which
+// need a capturable stream) after the caller's stream has drained.
+godec_status forward_batched(godec_layer* l, const void* X_dev, uint64_t seed, void* ws,
+                             const godec_opts& o, void* L_dev) {
+  const int nb = l->nb, T = l->T, r = l->r;
+  const int64_t m = l->m, n = l->n, mn = m * n, kk = std::max<int64_t>(l->k, 1);
+  HIP_TRY(hipStreamSynchronize(l->stream));
+  hipStream_t bs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+  godec_batch* gb = nullptr;
+  auto done = [&](godec_status st) {
+    if (gb) godec_batch_destroy(gb);
+    (void)hipStreamSynchronize(bs);
+    (void)hipStreamDestroy(bs);
+    return st;
+  };
+  godec_opts bo = o;
+  bo.stream = bs;
+  const std::vector<godec_problem> pr = layer_problems(l, X_dev, seed);
+  godec_status s = godec_batch_init(&gb, pr.data(), nb, l->q, ws, l->sub_ws, &bo);
+  if (s != GODEC_OK) return done(s);
+  for (int t = 0; t < T; ++t) {
+    s = godec_batch_step(gb, 1);
+    if (s != GODEC_OK) return done(s);
+    const int64_t slot = (int64_t)t * nb;
+    s = batch_snapshot_S(gb, l->ck_idx + slot * kk, (float*)l->ck_val + slot * kk, kk,
+                         l->ck_nnz + slot);
+    if (s != GODEC_OK) return done(s);
+  }
+  hipError_t e = hipMemcpyAsync(l->ck_nnz_host.data(), l->ck_nnz,
+                                sizeof(int64_t) * l->ck_nnz_host.size(), hipMemcpyDeviceToHost, bs);
+  if (e != hipSuccess) return done(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  for (int b = 0; b < nb; ++b) {
+    godec_info info;
+    s = godec_batch_get_info(gb, b, &info);   // synchronises bs
+    if (s != GODEC_OK) return done(s);
+    if (info.rank_eff != r) return done(rank_error(b));
+    s = godec_batch_get_A1(gb, b, l->a1_host.data() + (size_t)b * n * r);
+    if (s != GODEC_OK) return done(s);
+    if (L_dev) {
+      s = godec_batch_get_factors(gb, b, (float*)l->Uf + b * m * r, (float*)l->Vf + b * n * r);
+      if (s != GODEC_OK) return done(s);
+    }
+  }
+  if (L_dev) {
+    const Launch L{bs, l->num_cu};
+    lk_gemm(L, false, nb, (int)m, (int)n, r, l->Uf, r, m * r, 0, l->Vf, r, n * r, 1, 1.0, 0.0,
+            L_dev, n, mn, l->part, l->part_cap);
+  }
+  e = hipStreamSynchronize(bs);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return done(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  return done(GODEC_OK);
 }
 
 }  // namespace
@@ -274,12 +420,12 @@ godec_status godec_layer_workspace_size(int32_t batch, int64_t m, int64_t n, int
   if (!bytes) return fail(GODEC_E_INVAL, "bytes is NULL");
   godec_status s = validate_layer(batch, m, n, r, k, q, T, dtype);
   if (s != GODEC_OK) return s;
-  size_t ctx_ws = 0;
-  s = godec_workspace_size(m, n, r, k, q, dtype, nullptr, &ctx_ws);
-  if (s != GODEC_OK) return s;
   godec_layer tmp;
   fill_layer(&tmp, batch, m, n, r, k, q, T, dtype);
-  *bytes = carve_layer(&tmp, nullptr, ctx_ws, nullptr);
+  size_t sub = 0;
+  s = sub_workspace(&tmp, &sub);
+  if (s != GODEC_OK) return s;
+  *bytes = carve_layer(&tmp, nullptr, sub, nullptr);
   return GODEC_OK;
 }
 
@@ -294,89 +440,59 @@ godec_status godec_layer_forward(godec_layer** out, const void* X_dev, godec_dty
   if (s != GODEC_OK) return s;
   if (!X_dev || !workspace_dev || ((uintptr_t)workspace_dev & 255))
     return fail(GODEC_E_INVAL, "X or workspace is NULL, or the workspace is not 256-byte aligned");
+  if (opts && opts->size != sizeof(godec_opts)) return fail(GODEC_E_INVAL, "opts->size mismatch");
   if (opts && opts->prec != GODEC_PREC_NATIVE)
     return fail(GODEC_E_UNSUPPORTED, "the layer computes in the dtype of X (prec NATIVE)");
   if (opts && opts->a1_host)
     return fail(GODEC_E_UNSUPPORTED, "the layer draws A1 from the seed");
-  size_t ctx_ws = 0;
-  s = godec_workspace_size(m, n, r, k, q, dtype, nullptr, &ctx_ws);
-  if (s != GODEC_OK) return s;
   godec_layer* l = new godec_layer;
   fill_layer(l, batch, m, n, r, k, q, T, dtype);
+  s = sub_workspace(l, &l->sub_ws);
+  if (s != GODEC_OK) {
+    delete l;
+    return s;
+  }
   l->X = X_dev;
   l->stream = opts ? (hipStream_t)opts->stream : nullptr;
   l->num_cu = device_cu_count();
-  if (workspace_bytes < carve_layer(l, nullptr, ctx_ws, nullptr)) {
+  if (workspace_bytes < carve_layer(l, nullptr, l->sub_ws, nullptr)) {
     delete l;
     return fail(GODEC_E_NOMEM, "workspace too small");
   }
   std::vector<void*> ws;
-  carve_layer(l, workspace_dev, ctx_ws, &ws);
-  auto bail = [&](godec_status st) {
-    for (godec_ctx* c : l->ctx)
-      if (c) godec_destroy(c);
-    delete l;
-    return st;
-  };
+  carve_layer(l, workspace_dev, l->sub_ws, &ws);
   godec_opts o;
   godec_opts_default(&o);
   if (opts) o.rank_tol = opts->rank_tol;
   o.stream = l->stream;
-  const int64_t mn = m * n, kk = std::max<int64_t>(k, 1);
-  const size_t ts = l->ts;
-  l->ctx.assign(batch, nullptr);
-  for (int b = 0; b < batch; ++b) {
-    s = godec_init(&l->ctx[b], at(const_cast<void*>(X_dev), ts, b * mn), dtype, m, n, n, r, k, q,
-                   seed + (uint64_t)b, ws[b], ctx_ws, &o);
-    if (s != GODEC_OK) return bail(s);
-  }
   l->ck_nnz_host.assign((size_t)T * batch, 0);
-  for (int t = 0; t < T; ++t) {
-    for (int b = 0; b < batch; ++b) {
-      s = godec_step(l->ctx[b], 1, 0);
-      if (s != GODEC_OK) return bail(s);
-    }
-    for (int b = 0; b < batch; ++b) {
-      const int64_t slot = (int64_t)t * batch + b;
-      int64_t nnz = 0;
-      s = godec_get_S(l->ctx[b], l->ck_idx + slot * kk, at(l->ck_val, ts, slot * kk), &nnz);
-      if (s != GODEC_OK) return bail(s);
-      l->ck_nnz_host[slot] = nnz;
-    }
-  }
   l->a1_host.resize((size_t)batch * n * r);
-  for (int b = 0; b < batch; ++b) {
-    godec_info info;
-    s = godec_get_info(l->ctx[b], &info);
-    if (s != GODEC_OK) return bail(s);
-    if (info.rank_eff != r)
-      return bail(fail(GODEC_E_UNSUPPORTED,
-                       "problem " + std::to_string(b) + " lost rank in the forward pass; the "
-                       "layer's gradient needs a full-rank sketch"));
-    s = godec_get_A1(l->ctx[b], l->a1_host.data() + (size_t)b * n * r);
-    if (s != GODEC_OK) return bail(s);
-    if (L_dev) {
-      s = godec_get_L_dense(l->ctx[b], at(L_dev, ts, b * mn), n);
-      if (s != GODEC_OK) return bail(s);
-    }
+  s = l->use_batch ? forward_batched(l, X_dev, seed, ws[0], o, L_dev)
+                   : forward_single(l, X_dev, seed, ws, o, L_dev);
+  if (s != GODEC_OK) {
+    delete l;
+    return s;
   }
-  hipError_t e = hipMemcpyAsync(l->ck_nnz, l->ck_nnz_host.data(),
-                                sizeof(int64_t) * l->ck_nnz_host.size(), hipMemcpyHostToDevice,
-                                l->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(l->A1, l->a1_host.data(), sizeof(double) * l->a1_host.size(),
-                       hipMemcpyHostToDevice, l->stream);
-  if (e != hipSuccess) return bail(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  const int64_t mn = m * n, kk = std::max<int64_t>(k, 1);
+  hipError_t e = hipMemcpyAsync(l->A1, l->a1_host.data(), sizeof(double) * l->a1_host.size(),
+                                hipMemcpyHostToDevice, l->stream);
+  if (e != hipSuccess) {
+    delete l;
+    return fail(GODEC_E_DEVICE, hipGetErrorString(e));
+  }
   if (S_dev) {
     const Launch L{l->stream, l->num_cu};
     const int64_t slot = (int64_t)(T - 1) * batch;
     lk_fill(L, l->f64, batch, S_dev, mn, mn, 0.0);
-    lk_scatter(L, l->f64, batch, S_dev, mn, l->ck_idx + slot * kk, at(l->ck_val, ts, slot * kk),
+    lk_scatter(L, l->f64, batch, S_dev, mn, l->ck_idx + slot * kk, at(l->ck_val, l->ts, slot * kk),
                kk, kk, l->ck_nnz + slot, 0, 1.0);
   }
   e = hipStreamSynchronize(l->stream);
   if (e == hipSuccess) e = hipGetLastError();
-  if (e != hipSuccess) return bail(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  if (e != hipSuccess) {
+    delete l;
+    return fail(GODEC_E_DEVICE, hipGetErrorString(e));
+  }
   *out = l;
   return GODEC_OK;
 }
@@ -437,9 +553,11 @@ godec_status godec_layer_get_mask(godec_layer* l, int32_t b, int32_t t, int64_t*
   const int64_t slot = (int64_t)(t - 1) * l->nb + b;
   const int64_t nnz = l->ck_nnz_host[slot];
   *nnz_host = nnz;
-  if (idx_host && nnz > 0)
+  if (idx_host && nnz > 0) {
     HIP_TRY(hipMemcpy(idx_host, l->ck_idx + slot * kk, sizeof(int64_t) * nnz,
                       hipMemcpyDeviceToHost));
+    std::sort(idx_host, idx_host + nnz);
+  }
   return GODEC_OK;
 }
 
@@ -452,8 +570,6 @@ godec_status godec_layer_get_A1(godec_layer* l, int32_t b, double* a1_host) {
 
 godec_status godec_layer_destroy(godec_layer* l) {
   if (!l) return fail(GODEC_E_INVAL, "layer is NULL");
-  for (godec_ctx* c : l->ctx)
-    if (c) godec_destroy(c);
   delete l;
   return GODEC_OK;
 }

@@ -33,6 +33,12 @@ struct Carver {
 
 int device_cu_count();
 
+// Enqueue (on the batch's stream) a copy of every problem's current S list:
+// problem i's entries, in selection order, to idx_dev/val_dev + i * kstride,
+// and its length to nnz_dev[i].
+godec_status batch_snapshot_S(godec_batch* b, int64_t* idx_dev, float* val_dev, int64_t kstride,
+                              int64_t* nnz_dev);
+
 }  // namespace godec_host
 
 #define HIP_TRY(expr)                                                        \

@@ -774,6 +774,22 @@ __global__ __launch_bounds__(256) void kb_residual(const BProb* __restrict__ pro
   R[i * ldr + j] = bresid(b.X[i * b.ldx + j], u, v);
 }
 
+// Snapshot of every problem's current S list (entries in selection order)
+// and its length: problem blockIdx.y, list `list`.
+__global__ __launch_bounds__(256) void kb_copy_lists(const BProb* __restrict__ probs, int list,
+                                                     int64_t* __restrict__ idx_out,
+                                                     float* __restrict__ val_out,
+                                                     int64_t kstride,
+                                                     int64_t* __restrict__ nnz_out) {
+  const BProb& P = probs[blockIdx.y];
+  const int64_t nnz = P.sel->nnz_list[list];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) nnz_out[blockIdx.y] = nnz;
+  if (e >= nnz) return;
+  idx_out[(int64_t)blockIdx.y * kstride + e] = P.s_idx[list][e];
+  val_out[(int64_t)blockIdx.y * kstride + e] = P.s_val[list][e];
+}
+
 __global__ void kb_iter_inc(int* iter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *iter += 1;
 }
@@ -855,6 +871,13 @@ void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, f
                  int64_t ldr) {
   const unsigned g = (unsigned)((m * n + 255) / 256);
   hipLaunchKernelGGL(kb_residual, dim3(g), dim3(256), 0, L.stream, prob_dev, R, ldr);
+}
+
+void bl_copy_lists(const Launch& L, const BProb* probs_dev, int nprob, int list, int64_t kmax,
+                   int64_t* idx_out, float* val_out, int64_t kstride, int64_t* nnz_out) {
+  const dim3 g((unsigned)((std::max<int64_t>(kmax, 1) + 255) / 256), (unsigned)nprob);
+  hipLaunchKernelGGL(kb_copy_lists, g, dim3(256), 0, L.stream, probs_dev, list, idx_out, val_out,
+                     kstride, nnz_out);
 }
 
 }  // namespace godec
