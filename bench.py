@@ -13,8 +13,10 @@ is the FP32 refinement.  The same K iterations are also timed in plain FP32.
 
 Prints one JSON line with the headline value (iterations/s of the bf16 +
 refinement form), the FP32 plain figure beside it, the roofline of the
-dominant streaming kernel (HIP events on the library's stream), and the FP64
-oracle timed on the host cores on a bounded sample.
+dominant streaming kernel (its launches stamped with their own start and end
+on the library's stream), its HBM traffic from the committed counter record,
+and the FP64 oracle timed on the host cores on a bounded sample.  Secondary
+legs: the 64-problem batched form and the differentiable layer.
 """
 
 import argparse
@@ -83,13 +85,41 @@ def run_form(X, w, prec, steps, warmup, seed):
     return dict(ms=ev_ms, wall_s=wall, info=info, UL=UL, VL=VL, stats=stats)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "godec_w3_mm_a_bf16_hbm_counters.md")
+TRAFFIC_KERNEL = "mm_a_bf16(D*Z)"
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record (scaled by a plain copy), or
+    None when there is no record or the kernel's source file has changed
+    since the counters were taken."""
+    import hashlib
+    if kernel_name != TRAFFIC_KERNEL or not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = None
+    for line in open(COUNTERS_FILE):
+        line = line.strip()
+        if line.startswith("{") and '"hbm_bytes_per_launch"' in line:
+            rec = json.loads(line)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def roofline_of(stats):
     dom = max(stats, key=lambda s: s["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
     achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom["name"]),
             "avg_launch_us": round(avg_ms * 1e3, 2),
             "bytes_per_launch": dom["bytes_per_launch"],
             "launches": dom["launches"]}
@@ -187,6 +217,23 @@ def run_layer(warmup, seed=1005):
             "backward_achieved_GBps": round(bytes_bwd / (bwd[-1] * 1e-3) / 1e9, 1)}
 
 
+def run_copy(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of a known size: the reference against
+    which the HBM byte counters of the other kernels are scaled."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+            "ms_per_copy": round(dt * 1e3, 4),
+            "GBps_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}
+
+
 def cpu_baseline(w, iters):
     """The FP64 oracle on the host cores, `iters` iterations of the same X."""
     import numpy as np
@@ -221,6 +268,8 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=25)
     ap.add_argument("--skip-layer", action="store_true")
+    ap.add_argument("--only", choices=["batch", "layer", "copy"],
+                    help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
     args = ap.parse_args()
@@ -233,6 +282,16 @@ def main():
     import torch
     from paper_1309_0302_amd import workloads
     from paper_1309_0302_amd.binding import GODEC_PREC_BF16_REFINE, GODEC_PREC_NATIVE
+
+    if args.only == "batch":
+        print(json.dumps(run_batched(args.batch_iters, min(args.warmup, 3))), flush=True)
+        return
+    if args.only == "layer":
+        print(json.dumps(run_layer(min(args.warmup, 1))), flush=True)
+        return
+    if args.only == "copy":
+        print(json.dumps(run_copy()), flush=True)
+        return
 
     log(f"[bench] generating workload {args.size}x{args.size}")
     w = workloads.w3(seed=args.seed, m=args.size, n=args.size)

@@ -254,20 +254,24 @@ hipEvent_t prof_event(godec_ctx* c) {
   return c->pool[c->pool_used++];
 }
 
-// Scoped pair of events around one launch (no-op unless profiling).
+// Pair of events timing one launch (no-op unless profiling).  With
+// ext = true the launch itself stamps the events with the kernel's start and
+// end (extended launch); otherwise they are recorded on the stream around it.
 struct ProfScope {
   godec_ctx* c;
   int cls;
+  bool ext;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(godec_ctx* ctx, int k) : c(ctx), cls(k) {
+  ProfScope(godec_ctx* ctx, int k, bool ext_launch = false) : c(ctx), cls(k), ext(ext_launch) {
     if (!c->prof) return;
     a = prof_event(c);
     b = prof_event(c);
-    if (a && b) (void)hipEventRecord(a, c->stream);
+    if (!a || !b) a = b = nullptr;
+    if (a && !ext) (void)hipEventRecord(a, c->stream);
   }
   ~ProfScope() {
-    if (!c->prof || !a || !b) return;
-    (void)hipEventRecord(b, c->stream);
+    if (!c->prof || !a) return;
+    if (!ext) (void)hipEventRecord(b, c->stream);
     c->recs.push_back({cls, a, b});
   }
 };
@@ -281,8 +285,8 @@ void mfma_apply(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool z
   const bool b16 = td == BF16;
   if (!zt_ready) mfma_to_t(L, b16, in, c->ldd, c->rp, c->Zt);
   {
-    ProfScope ps(c, b16 ? PC_APPLY_BF16 : PC_APPLY);
-    mfma_mm_a(L, b16, Dsrc, c->ldd, c->mpad, c->Zt, c->Wtpart, c->kc_a);
+    ProfScope ps(c, b16 ? PC_APPLY_BF16 : PC_APPLY, true);
+    mfma_mm_a(L, b16, Dsrc, c->ldd, c->mpad, c->Zt, c->Wtpart, c->kc_a, ps.a, ps.b);
   }
   mfma_reduce_w(L, b16, c->Wtpart, (int)c->nct_a, c->mpad, c->m, c->rp, Wt_out, Wrow_out);
 }
@@ -295,8 +299,8 @@ void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt
     const bool b16 = td == BF16;
     mfma_apply(c, td, Dsrc, in, zt_ready, c->Wt, nullptr);
     {
-      ProfScope ps(c, b16 ? PC_APPLY_T_BF16 : PC_APPLY_T);
-      mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b);
+      ProfScope ps(c, b16 ? PC_APPLY_T_BF16 : PC_APPLY_T, true);
+      mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b, ps.a, ps.b);
     }
     mfma_reduce_z(L, c->Zpart32, c->nch_b, c->ldd, c->rp, (float*)out);
     return;

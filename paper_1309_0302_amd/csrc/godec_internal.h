@@ -201,12 +201,15 @@ void launch_sort_s(const Launch& L, bool f64, const int64_t* idx,
                    void* out_val);
 // ---- matrix-core panel products (k_mfma.hip), f32 and bf16 storage ----
 void mfma_to_t(const Launch& L, bool bf16, const void* Z, int64_t ldd, int rp, void* Zt);
+// ev_a/ev_b (optional) receive the kernel's own start and end timestamps.
 void mfma_mm_a(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
-               const void* Zt, float* Wtpart, int64_t KC);
+               const void* Zt, float* Wtpart, int64_t KC, hipEvent_t ev_a = nullptr,
+               hipEvent_t ev_b = nullptr);
 void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int64_t mpad,
                    int64_t m, int rp, void* Wt, float* Wrow);
 void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
-               const void* Wt, float* Zpart, int64_t RC, int64_t nch);
+               const void* Wt, float* Zpart, int64_t RC, int64_t nch, hipEvent_t ev_a = nullptr,
+               hipEvent_t ev_b = nullptr);
 void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
                    float* Zo);
 

@@ -15,6 +15,8 @@
 // Layouts used (v_mfma_f32_32x32x{16_bf16, 2_f32}, lane l, l%32 = index on
 // the lanes, l/32 = group g):  A operand row i = l%32; B operand column
 // j = l%32; accumulator register v holds C[8(v/4) + 4g + v%4][l%32].
+#include <hip/hip_ext.h>
+
 #include "godec_internal.h"
 #include "k_common.h"
 
@@ -349,15 +351,17 @@ void mfma_to_t(const Launch& L, bool bf16, const void* Z, int64_t ldd, int rp, v
                        (const float*)Z, ldd, rp, (float*)Zt);
 }
 
+// ev_a/ev_b (optional): events that receive the kernel's own start and end
+// timestamps (timing mode).
 void mfma_mm_a(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
-               const void* Zt, float* Wtpart, int64_t KC) {
+               const void* Zt, float* Wtpart, int64_t KC, hipEvent_t ev_a, hipEvent_t ev_b) {
   dim3 grid((unsigned)((ldd + KC - 1) / KC), (unsigned)((mpad + kMmaRows - 1) / kMmaRows));
   if (bf16)
-    hipLaunchKernelGGL(k_mm_a_bf16, grid, dim3(256), 0, L.stream, (const uint16_t*)D, ldd, mpad,
-                       (const uint16_t*)Zt, Wtpart, KC);
+    hipExtLaunchKernelGGL(k_mm_a_bf16, grid, dim3(256), 0, L.stream, ev_a, ev_b, 0,
+                          (const uint16_t*)D, ldd, mpad, (const uint16_t*)Zt, Wtpart, KC);
   else
-    hipLaunchKernelGGL(k_mm_a_f32, grid, dim3(256), 0, L.stream, (const float*)D, ldd, mpad,
-                       (const float*)Zt, Wtpart, KC);
+    hipExtLaunchKernelGGL(k_mm_a_f32, grid, dim3(256), 0, L.stream, ev_a, ev_b, 0,
+                          (const float*)D, ldd, mpad, (const float*)Zt, Wtpart, KC);
 }
 
 void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int64_t mpad,
@@ -372,14 +376,15 @@ void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int
 }
 
 void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
-               const void* Wt, float* Zpart, int64_t RC, int64_t nch) {
+               const void* Wt, float* Zpart, int64_t RC, int64_t nch, hipEvent_t ev_a,
+               hipEvent_t ev_b) {
   dim3 grid((unsigned)(ldd / 128), (unsigned)nch);
   if (bf16)
-    hipLaunchKernelGGL(k_mm_b_bf16, grid, dim3(256), 0, L.stream, (const uint16_t*)D, ldd, mpad,
-                       (const uint16_t*)Wt, Zpart, RC);
+    hipExtLaunchKernelGGL(k_mm_b_bf16, grid, dim3(256), 0, L.stream, ev_a, ev_b, 0,
+                          (const uint16_t*)D, ldd, mpad, (const uint16_t*)Wt, Zpart, RC);
   else
-    hipLaunchKernelGGL(k_mm_b_f32, grid, dim3(256), 0, L.stream, (const float*)D, ldd, mpad,
-                       (const float*)Wt, Zpart, RC);
+    hipExtLaunchKernelGGL(k_mm_b_f32, grid, dim3(256), 0, L.stream, ev_a, ev_b, 0,
+                          (const float*)D, ldd, mpad, (const float*)Wt, Zpart, RC);
 }
 
 void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
