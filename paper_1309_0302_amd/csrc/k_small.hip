@@ -269,6 +269,10 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
 // Rotation threshold of the Jacobi sweeps: an off-diagonal entry below
 // 4 u sqrt(|a_pp a_qq|) (u = 2^-53) is already at rounding level.
 constexpr double kJacobiTol = 4.0 * 0x1p-53;
+// A sweep whose rotations all had |a_pq| <= 2^-34 sqrt(a_pp a_qq) leaves the
+// off-diagonal at about the square of that (quadratic convergence of cyclic
+// Jacobi), far below kJacobiTol, so the confirming sweep is skipped.
+constexpr double kJacobiQuad = 0x1p-34;
 
 // Round-robin pairing (circle method) over N (even) players.
 __device__ __forceinline__ void rr_pair(int round, int k, int N, int& a, int& b) {
@@ -278,14 +282,20 @@ __device__ __forceinline__ void rr_pair(int round, int k, int N, int& a, int& b)
 }
 
 // Two-sided cyclic Jacobi on the symmetric n x n matrix A (LDS, stride LD),
-// accumulating V <- V J.  Parallel over disjoint pairs in each round.
+// accumulating V <- V J.  Parallel over disjoint pairs in each round: the
+// rotations of a round are computed first, then one pass applies them, a
+// thread per 2 x 2 block of A (the column rotation of the block's column
+// pair, then the row rotation of its row pair) and a thread per (row, pair)
+// of V.
 template <int RP>
 __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
   constexpr int LD = RP + 1;
   const int N = (n + 1) & ~1;
   const int npairs = N / 2;
+  const int nblk = npairs * npairs;
+  int* big = rot + 1;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (threadIdx.x == 0) *rot = 0;
+    if (threadIdx.x == 0) { rot[0] = 0; big[0] = 0; }
     __syncthreads();
     for (int round = 0; round < N - 1; ++round) {
       if (threadIdx.x < npairs) {
@@ -296,12 +306,26 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
         if (q < n) {
           const double apq = A[p * LD + q];
           const double app = A[p * LD + p], aqq = A[q * LD + q];
-          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && apq != 0.0) {
-            const double th = (aqq - app) / (2.0 * apq);
-            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
+          const double scale = sqrt(fabs(app * aqq));
+          if (fabs(apq) > kJacobiTol * scale && apq != 0.0) {
+            // tan of the rotation t = sgn(d) h / (|d| + r), d = a_qq - a_pp,
+            // h = 2 a_pq, r = hypot(d, h); with w = sqrt(2 r (r + |d|)):
+            // c = (r + |d|) / w, s = sgn(d) h / w.
+            const double d = aqq - app, h = 2.0 * apq;
+            const double mx = fmax(fabs(d), fabs(h));
+            if (mx > 0x1p-450 && mx < 0x1p450) {
+              const double r = sqrt(d * d + h * h);
+              const double iw = 1.0 / sqrt(2.0 * r * (r + fabs(d)));
+              c = (r + fabs(d)) * iw;
+              s = (d >= 0.0 ? h : -h) * iw;
+            } else {
+              const double th = d / h;
+              const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+              c = 1.0 / sqrt(t * t + 1.0);
+              s = t * c;
+            }
             atomicAdd(rot, 1);
+            if (fabs(apq) > kJacobiQuad * scale) atomicAdd(big, 1);
           }
         }
         cs[4 * threadIdx.x + 0] = c;
@@ -310,33 +334,49 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
         cs[4 * threadIdx.x + 3] = (double)q;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
-        const int i = e / npairs, k = e % npairs;
-        const double c = cs[4 * k], s = cs[4 * k + 1];
-        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
-        if (q >= n || s == 0.0) continue;
-        const double aip = A[i * LD + p], aiq = A[i * LD + q];
-        A[i * LD + p] = c * aip - s * aiq;
-        A[i * LD + q] = s * aip + c * aiq;
-        const double vip = V[i * LD + p], viq = V[i * LD + q];
-        V[i * LD + p] = c * vip - s * viq;
-        V[i * LD + q] = s * vip + c * viq;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
-        const int j = e / npairs, k = e % npairs;
-        const double c = cs[4 * k], s = cs[4 * k + 1];
-        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
-        if (q >= n || s == 0.0) continue;
-        const double apj = A[p * LD + j], aqj = A[q * LD + j];
-        A[p * LD + j] = c * apj - s * aqj;
-        A[q * LD + j] = s * apj + c * aqj;
+      for (int e = threadIdx.x; e < nblk + n * npairs; e += blockDim.x) {
+        if (e < nblk) {
+          // A <- J^T A J on the block (row pair k1) x (column pair k2)
+          const int k1 = e / npairs, k2 = e % npairs;
+          const double c1 = cs[4 * k1], s1 = cs[4 * k1 + 1];
+          const double c2 = cs[4 * k2], s2 = cs[4 * k2 + 1];
+          if (s1 == 0.0 && s2 == 0.0) continue;
+          const int p1 = (int)cs[4 * k1 + 2], q1 = (int)cs[4 * k1 + 3];
+          const int p2 = (int)cs[4 * k2 + 2], q2 = (int)cs[4 * k2 + 3];
+          const bool rq = q1 < n, cq = q2 < n;   // the partner may be the padding index
+          double a = A[p1 * LD + p2];
+          double b = cq ? A[p1 * LD + q2] : 0.0;
+          double cc = rq ? A[q1 * LD + p2] : 0.0;
+          double d = (rq && cq) ? A[q1 * LD + q2] : 0.0;
+          if (s2 != 0.0) {
+            const double a2 = c2 * a - s2 * b, b2 = s2 * a + c2 * b;
+            const double c3 = c2 * cc - s2 * d, d2 = s2 * cc + c2 * d;
+            a = a2; b = b2; cc = c3; d = d2;
+          }
+          if (s1 != 0.0) {
+            const double a2 = c1 * a - s1 * cc, c3 = s1 * a + c1 * cc;
+            const double b2 = c1 * b - s1 * d, d2 = s1 * b + c1 * d;
+            a = a2; cc = c3; b = b2; d = d2;
+          }
+          A[p1 * LD + p2] = a;
+          if (cq) A[p1 * LD + q2] = b;
+          if (rq) A[q1 * LD + p2] = cc;
+          if (rq && cq) A[q1 * LD + q2] = d;
+        } else {
+          // V <- V J
+          const int f = e - nblk;
+          const int i = f / npairs, k = f % npairs;
+          const double c = cs[4 * k], s = cs[4 * k + 1];
+          const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+          if (q >= n || s == 0.0) continue;
+          const double vip = V[i * LD + p], viq = V[i * LD + q];
+          V[i * LD + p] = c * vip - s * viq;
+          V[i * LD + q] = s * vip + c * viq;
+        }
       }
       __syncthreads();
     }
-    if (*rot == 0) break;
+    if (rot[0] == 0 || big[0] == 0) break;
     __syncthreads();
   }
 }
@@ -414,9 +454,10 @@ __device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallSta
   __shared__ double W[RP * LD];
   __shared__ double cs[4 * 16 + 4];
   __shared__ double ev[RP];
+  __shared__ double fk[RP];
   __shared__ double sv[RP];
   __shared__ int order[RP];
-  __shared__ int rot;
+  __shared__ int rot[2];
   __shared__ int sh_keep;
   __shared__ double red[4];
   __shared__ double redA[4], redB[4];
@@ -434,8 +475,8 @@ __device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallSta
 
   // ---- rank check on R2 (A2^T Y1 = R2^T R2) ----
   // Certificate first: s_min(R2) >= 1/||R2^{-1}||_F and s_max <= ||R2||_F.
-  // R2^{-1} (upper triangular, active block) by a right-looking back
-  // substitution in H; a zero diagonal fails the certificate.
+  // R2^{-1} (upper triangular, active block) by back substitution, one lane
+  // per column in registers, into H; a zero diagonal fails the certificate.
   if (tid == 0) {
     int ok = n > 0;
     for (int i = 0; i < n; ++i)
@@ -448,18 +489,25 @@ __device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallSta
     H[i * LD + c] = (i == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (red[1] != 0.0) {
-    for (int i = n - 1; i >= 0; --i) {
-      const double d = 1.0 / W[i * LD + i];
-      if (tid < n) H[i * LD + tid] *= d;
-      __syncthreads();
-      for (int e = tid; e < i * n; e += blockDim.x) {
-        const int l = e / n, c = e % n;
-        H[l * LD + c] -= W[l * LD + i] * H[i * LD + c];
+  if (tid < n) fk[tid] = 1.0 / W[tid * LD + tid];
+  __syncthreads();
+  if (red[1] != 0.0 && tid < n) {
+    // column tid of R2^{-1}: each lane substitutes its own column in registers
+    double h[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) h[i] = (i == tid) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = RP - 1; i >= 0; --i) {
+      if (i < n) {
+        h[i] *= fk[i];
+#pragma unroll
+        for (int l = 0; l < i; ++l) h[l] -= W[l * LD + i] * h[i];
       }
-      __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < RP; ++i) H[i * LD + tid] = h[i];
   }
+  __syncthreads();
   {
     double fr = 0.0, fi = 0.0;
     for (int e = tid; e < n * n; e += blockDim.x) {
@@ -483,7 +531,7 @@ __device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallSta
     __syncthreads();
   }
   if (red[0] == 0.0 && n > 0) {
-    jacobi_svd_values<RP>(W, n, sv, cs, &rot);
+    jacobi_svd_values<RP>(W, n, sv, cs, rot);
     if (tid == 0) {
       double smax = 0.0;
       for (int i = 0; i < n; ++i) smax = fmax(smax, sv[i]);
@@ -540,30 +588,34 @@ __device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallSta
     }
     __syncthreads();
   }
-  jacobi_eig<RP>(G, V, n, cs, &rot);
-  // sort eigenvalues descending
-  if (tid == 0) {
-    for (int i = 0; i < n; ++i) order[i] = i;
-    for (int i = 0; i < n; ++i)
-      for (int j = i + 1; j < n; ++j)
-        if (G[order[j] * LD + order[j]] > G[order[i] * LD + order[i]]) {
-          const int t = order[i]; order[i] = order[j]; order[j] = t;
-        }
-    for (int i = 0; i < n; ++i) ev[i] = G[order[i] * LD + order[i]];
+  jacobi_eig<RP>(G, V, n, cs, rot);
+  // sort eigenvalues descending (rank of each by counting; ties by index)
+  if (tid < n) {
+    const double mine = G[tid * LD + tid];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double o = G[j * LD + j];
+      rank += (o > mine || (o == mine && j < tid)) ? 1 : 0;
+    }
+    order[rank] = tid;
+    ev[rank] = mine;
   }
   __syncthreads();
   const int keep = sh_keep;
   // K = sum_{i < keep, ev_i > 0} v_i ev_i^{(1-p)/(2p)} v_i^T
   const double ex = (1.0 - (double)p) / (2.0 * (double)p);
+  if (tid < n) {
+    const double lam = ev[tid];
+    fk[tid] = (tid < keep && lam > 0.0) ? ((p == 1) ? 1.0 : pow(lam, ex)) : 0.0;
+  }
+  __syncthreads();
   for (int e = tid; e < RP * RP; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
     double s = 0.0;
     if (a < n && b < n) {
       for (int i = 0; i < keep; ++i) {
-        const double lam = ev[i];
-        if (!(lam > 0.0)) continue;
-        const double f = (p == 1) ? 1.0 : pow(lam, ex);
-        s += V[a * LD + order[i]] * f * V[b * LD + order[i]];
+        if (!(ev[i] > 0.0)) continue;
+        s += V[a * LD + order[i]] * fk[i] * V[b * LD + order[i]];
       }
     }
     H[a * LD + b] = s;
