@@ -11,6 +11,11 @@
 // over the candidates only; otherwise further full passes histogram the
 // next digits.  Degenerate inputs (more exact ties at the threshold than the
 // candidate buffer holds) fall back to an index-ordered scan.
+//
+// FP32 residuals are evaluated on the matrix cores in aligned 16 x 16 tiles
+// (res_tile); every FP32 consumer (selection passes, tie scan, tie values,
+// the dense residual and L) computes an entry inside the same aligned tile,
+// so all of them see the same bits.  FP64 residuals use the FMA chain resid().
 #include "godec_internal.h"
 #include "k_common.h"
 
@@ -33,6 +38,78 @@ __device__ __forceinline__ T resid(T x, const T* __restrict__ u, const T (&v)[RP
 #pragma unroll
   for (int c = 0; c < RP; ++c) s = fma_t(u[c], v[c], s);
   return x - s;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 residual tiles: L = U_L V_L^T over rows [r0, r0 + 16) and columns
+// [c0, c0 + 16) (r0, c0 multiples of 16) by one wavefront with
+// v_mfma_f32_16x16x4f32, k-steps of four rank columns in ascending order.
+// Lane l supplies U_L[r0 + l%16][4s + l/16] and V_L[c0 + l%16][4s + l/16]
+// (zero past m, n or RP) and receives L at column c0 + l%16 and rows
+// r0 + res_row(v, l), v < 4.
+// ---------------------------------------------------------------------------
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <int RP>
+struct ResK { static constexpr int KS = (RP + 3) / 4; };
+
+__device__ __forceinline__ int res_row(int v, int lane) { return 4 * (lane >> 4) + v; }
+
+template <int RP>
+__device__ __forceinline__ void res_load_u(const float* __restrict__ UL, int64_t m, int64_t r0,
+                                           int lane, float (&a)[ResK<RP>::KS]) {
+  const int64_t row = r0 + (lane & 15);
+  const int g = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < ResK<RP>::KS; ++s) {
+    const int k = 4 * s + g;
+    a[s] = (k < RP && row < m) ? UL[row * RP + k] : 0.f;
+  }
+}
+
+// V operand from V_L^T (RP x ldv).
+template <int RP>
+__device__ __forceinline__ void res_load_vt(const float* __restrict__ VLt, int64_t ldv,
+                                            int64_t n, int64_t c0, int lane,
+                                            float (&b)[ResK<RP>::KS]) {
+  const int64_t col = c0 + (lane & 15);
+  const int g = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < ResK<RP>::KS; ++s) {
+    const int k = 4 * s + g;
+    b[s] = (k < RP && col < n) ? VLt[k * ldv + col] : 0.f;
+  }
+}
+
+// V operand from V_L (n x RP, row-major): the same values.
+template <int RP>
+__device__ __forceinline__ void res_load_v(const float* __restrict__ VL, int64_t n, int64_t c0,
+                                           int lane, float (&b)[ResK<RP>::KS]) {
+  const int64_t col = c0 + (lane & 15);
+  const int g = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < ResK<RP>::KS; ++s) {
+    const int k = 4 * s + g;
+    b[s] = (k < RP && col < n) ? VL[col * RP + k] : 0.f;
+  }
+}
+
+template <int RP>
+__device__ __forceinline__ f32x4_t res_tile(const float (&a)[ResK<RP>::KS],
+                                            const float (&b)[ResK<RP>::KS]) {
+  f32x4_t acc = {};
+#pragma unroll
+  for (int s = 0; s < ResK<RP>::KS; ++s)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ __forceinline__ float res_pick(const f32x4_t& L, int v) {
+  float out = L[0];
+  out = (v == 1) ? L[1] : out;
+  out = (v == 2) ? L[2] : out;
+  out = (v == 3) ? L[3] : out;
+  return out;
 }
 
 constexpr int kRowsPerTile = 64;
@@ -199,6 +276,73 @@ __device__ __forceinline__ void sel_tile(const T* __restrict__ X, int64_t ldx, i
   }
 }
 
+// FP32 full-data pass on the matrix cores.  Work unit = a band of 16 rows x
+// 1024 columns; wave w takes the 256 columns [256 w, 256 w + 256) of the
+// unit as 16 tiles, left to right, so the candidates it appends lie in one
+// 16 x 256 region (row-local order for the later scattered updates of D).
+// The U_L operand stays in registers for the unit; the V_L operand and the X
+// entries of the next tile are loaded before the current tile is processed.
+constexpr int kResUnitCols = 1024;
+
+template <int RP, bool HIST, bool TAKE, bool S2>
+__device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64_t ldx,
+                                              const float* __restrict__ UL,
+                                              const float* __restrict__ VLt, int64_t ldv,
+                                              int64_t m, int64_t n, unsigned int* lh,
+                                              const PassKeys<float>& pk, SegSink<float>& sink,
+                                              double& s2) {
+  using K = uint32_t;
+  constexpr int KS = ResK<RP>::KS;
+  constexpr int WT = kResUnitCols / 4 / 16;   // tiles per wave per unit
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ncs = (n + kResUnitCols - 1) / kResUnitCols;
+  const int64_t nrb = (m + 15) / 16;
+  const int64_t units = ncs * nrb;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t cs = u % ncs, rb = u / ncs;
+    const int64_t r0 = rb * 16;
+    const int64_t cw = cs * kResUnitCols + (int64_t)(kResUnitCols / 4) * wave;
+    if (cw >= n) continue;   // wave-uniform
+    float a[KS];
+    res_load_u<RP>(UL, m, r0, lane, a);
+    float b[KS], x[4];
+    auto load_tile = [&](int t) {
+      const int64_t c0 = cw + 16 * t;
+      const int64_t col = c0 + (lane & 15);
+      res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + res_row(v, lane);
+        x[v] = (col < n && row < m) ? X[row * ldx + col] : 0.f;
+      }
+    };
+    const int nt = (int)(((n - cw) + 15) / 16 < WT ? ((n - cw) + 15) / 16 : WT);
+    load_tile(0);
+    for (int t = 0; t < nt; ++t) {
+      const int64_t col = cw + 16 * t + (lane & 15);
+      const f32x4_t L = res_tile<RP>(a, b);
+      float xc[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xc[v] = x[v];
+      if (t + 1 < nt) load_tile(t + 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + res_row(v, lane);
+        const bool ok = col < n && row < m;
+        const float r = xc[v] - L[v];
+        const K key = (K)abs_key(r);
+        if constexpr (S2) {
+          if (ok) s2 += (double)r * (double)r;
+        }
+        if constexpr (HIST) {
+          if (ok && (K)(key - pk.klo) < pk.kspan) atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+        }
+        if constexpr (TAKE) seg_push(sink, ok && key >= pk.kmin, row * n + col, r, xc[v]);
+      }
+    }
+  }
+}
+
 template <typename T, int RP, bool HIST, bool TAKE, bool S2>
 __device__ __forceinline__ void sel_pass_body(const T* __restrict__ X, int64_t ldx,
                                               const T* __restrict__ UL,
@@ -206,6 +350,9 @@ __device__ __forceinline__ void sel_pass_body(const T* __restrict__ X, int64_t l
                                               int64_t m, int64_t n, unsigned int* lh, T* us,
                                               const PassKeys<T>& pk, SegSink<T>& sink,
                                               bool vec_ok, double& s2) {
+  if constexpr (sizeof(T) == 4) {
+    sel_pass_mfma<RP, HIST, TAKE, S2>(X, ldx, UL, VLt, ldv, m, n, lh, pk, sink, s2);
+  } else {
   constexpr int CPT = sel_cpt<T, RP>();
   constexpr int TW = 256 * CPT;
   const int tid = threadIdx.x;
@@ -237,6 +384,7 @@ __device__ __forceinline__ void sel_pass_body(const T* __restrict__ X, int64_t l
     else
       sel_tile<T, RP, CPT, HIST, TAKE, S2, false, false>(X, ldx, n, i0, nr, j0, us, v, lh, pk,
                                                          sink, s2);
+  }
   }
 }
 
@@ -522,10 +670,11 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
 }
 
 // FINAL: write S from the candidates.  Entries above the threshold key go
-// straight to S; entries equal to it go to the tie list.  A block takes one
-// candidate segment at a time: it counts its entries, reserves its output
-// range with one atomic per list, then writes in order (ballots + a scan
-// over the four waves).
+// straight to S; entries equal to it go to the tie list.  Wave w of block b
+// takes the candidate segments 4 b + w, 4 b + w + 4 gridDim.x, ...: the
+// waves count their entries, the block reserves its output range with one
+// atomic per list, and each wave then writes its entries in order (ballots
+// only, no block barrier), 256 candidates per step.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
                                                      const int64_t* __restrict__ cand_idx,
@@ -546,64 +695,73 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
   const unsigned long long kcap = (unsigned long long)(plan->count_above + plan->k_rem);
   const unsigned long long tcap = (unsigned long long)plan->cap;
   const unsigned long long below = (1ull << lane) - 1ull;
-  double s2 = 0.0;
-  for (int sg = blockIdx.x; sg <= plan->nseg; sg += gridDim.x) {
+  const int nseg = plan->nseg;
+  const int wstride = 4 * (int)gridDim.x;
+  const int w0 = 4 * (int)blockIdx.x + wave;
+  // phase 1: per-wave counts, one reservation per block and list
+  unsigned int na = 0, nt = 0;
+  for (int sg = w0; sg <= nseg; sg += wstride) {
     long long c0, cnt;
     seg_range(plan, seg_count, sg, c0, cnt);
-    const long long c1 = c0 + cnt;
-    // phase 1: counts
-    unsigned int na = 0, nt = 0;
-    for (long long c = c0 + tid; c < c1; c += 256) {
+    for (long long c = c0 + lane; c < c0 + cnt; c += 64) {
       const unsigned long long key = abs_key(cand_val[c]);
       na += key > tkey;
       nt += (key == tkey && tkey > 0);
     }
-    na = wave_sum(na);
-    nt = wave_sum(nt);
-    __syncthreads();
-    if (lane == 0) { wa[wave] = na; wt[wave] = nt; }
-    __syncthreads();
-    if (tid == 0) {
-      const unsigned int ta = wa[0] + wa[1] + wa[2] + wa[3];
-      const unsigned int tt = wt[0] + wt[1] + wt[2] + wt[3];
-      base_a = ta ? atomicAdd(&counters[0], (unsigned long long)ta) : 0ull;
-      base_t = tt ? atomicAdd(&counters[1], (unsigned long long)tt) : 0ull;
-    }
-    __syncthreads();
-    unsigned long long ba = base_a, bt = base_t;
-    // phase 2: ordered writes, 256 candidates per step
+  }
+  na = wave_sum(na);
+  nt = wave_sum(nt);
+  if (lane == 0) { wa[wave] = na; wt[wave] = nt; }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned int ta = wa[0] + wa[1] + wa[2] + wa[3];
+    const unsigned int tt = wt[0] + wt[1] + wt[2] + wt[3];
+    base_a = ta ? atomicAdd(&counters[0], (unsigned long long)ta) : 0ull;
+    base_t = tt ? atomicAdd(&counters[1], (unsigned long long)tt) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long ba = base_a, bt = base_t;
+  for (int w = 0; w < wave; ++w) { ba += wa[w]; bt += wt[w]; }
+  // phase 2: each wave writes its segments in order, four loads in flight
+  double s2 = 0.0;
+  for (int sg = w0; sg <= nseg; sg += wstride) {
+    long long c0, cnt;
+    seg_range(plan, seg_count, sg, c0, cnt);
+    const long long c1 = c0 + cnt;
     for (long long cb = c0; cb < c1; cb += 256) {
-      const long long c = cb + tid;
-      const bool valid = c < c1;
-      const T v = valid ? cand_val[c] : T(0);
-      const unsigned long long key = abs_key(v);
-      const bool above = valid && key > tkey;
-      const bool tie = valid && key == tkey && tkey > 0;
-      const unsigned long long ma = __ballot(above), mt = __ballot(tie);
-      __syncthreads();
-      if (lane == 0) { wa[wave] = (unsigned)__popcll(ma); wt[wave] = (unsigned)__popcll(mt); }
-      __syncthreads();
-      unsigned int oa = 0, ot = 0;
-      for (int w = 0; w < wave; ++w) { oa += wa[w]; ot += wt[w]; }
-      if (above) {
-        const unsigned long long pos = ba + oa + __popcll(ma & below);
-        if (pos < kcap) {
-          s_idx[pos] = cand_idx[c];
-          s_val[pos] = v;
-          s_x[pos] = cand_x[c];
-          s2 += (double)v * (double)v;
+      T v[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const long long c = cb + 64 * h + lane;
+        v[h] = c < c1 ? cand_val[c] : T(0);
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const long long c = cb + 64 * h + lane;
+        const bool valid = c < c1;
+        const unsigned long long key = abs_key(v[h]);
+        const bool above = valid && key > tkey;
+        const bool tie = valid && key == tkey && tkey > 0;
+        const unsigned long long ma = __ballot(above), mt = __ballot(tie);
+        if (above) {
+          const unsigned long long pos = ba + __popcll(ma & below);
+          if (pos < kcap) {
+            s_idx[pos] = cand_idx[c];
+            s_val[pos] = v[h];
+            s_x[pos] = cand_x[c];
+            s2 += (double)v[h] * (double)v[h];
+          }
         }
+        if (tie) {
+          const unsigned long long pos = bt + __popcll(mt & below);
+          if (pos < tcap) tie_idx[pos] = cand_idx[c];
+        }
+        ba += __popcll(ma);
+        bt += __popcll(mt);
       }
-      if (tie) {
-        const unsigned long long pos = bt + ot + __popcll(mt & below);
-        if (pos < tcap) tie_idx[pos] = cand_idx[c];
-      }
-      ba += wa[0] + wa[1] + wa[2] + wa[3];
-      bt += wt[0] + wt[1] + wt[2] + wt[3];
     }
   }
   s2 = wave_sum(s2);
-  __syncthreads();
   if (lane == 0) red[wave] = s2;
   __syncthreads();
   if (tid == 0) atomicAdd(&plan->sum_sel2, red[0] + red[1] + red[2] + red[3]);
@@ -723,10 +881,120 @@ __global__ __launch_bounds__(1024) void k_sel_ties(SelPlan* __restrict__ plan,
 // After a TIES collection the candidates hold the entries above the
 // threshold; the tied entries are taken in index order by one block
 // scanning all of X.
+// FP32 form of the index-ordered tie scan: bands of 16 rows; the hits of
+// each band are counted per row, the rows that fit are taken whole and the
+// first row that does not fit is taken in column order by one wavefront.
+// Returns the number of tied entries written at s_idx[base ..].
+template <int RP>
+__device__ long long ties_scan_mfma(const float* __restrict__ X, int64_t ldx,
+                                    const float* __restrict__ UL,
+                                    const float* __restrict__ VLt, int64_t ldv, int64_t m,
+                                    int64_t n, uint32_t tkey, long long need, long long base,
+                                    int64_t* __restrict__ s_idx, float* __restrict__ s_val) {
+  constexpr int KS = ResK<RP>::KS;
+  __shared__ unsigned int rowcnt[16];
+  __shared__ unsigned int wpos, full_cnt, cut_q;
+  __shared__ int cut_row;
+  __shared__ long long done;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) done = 0;
+  __syncthreads();
+  for (int64_t r0 = 0; r0 < m; r0 += 16) {
+    if (done >= need) break;
+    if (tid < 16) rowcnt[tid] = 0u;
+    if (tid == 0) wpos = 0u;
+    __syncthreads();
+    float a[KS];
+    res_load_u<RP>(UL, m, r0, lane, a);
+    // hits per row of the band
+    for (int64_t c0 = 16 * wave; c0 < n; c0 += 64) {
+      float b[KS];
+      res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
+      const f32x4_t L = res_tile<RP>(a, b);
+      const int64_t col = c0 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = res_row(v, lane);
+        const int64_t row = r0 + lr;
+        if (col < n && row < m && (uint32_t)abs_key(X[row * ldx + col] - L[v]) == tkey)
+          atomicAdd(&rowcnt[lr], 1u);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const long long rem = need - done;
+      long long acc = 0;
+      int cut = 16;
+      long long q = 0;
+      for (int rr = 0; rr < 16; ++rr) {
+        if (acc + (long long)rowcnt[rr] > rem) { cut = rr; q = rem - acc; break; }
+        acc += rowcnt[rr];
+      }
+      cut_row = cut;
+      cut_q = (unsigned int)q;
+      full_cnt = (unsigned int)acc;
+    }
+    __syncthreads();
+    const int cut = cut_row;
+    const long long at = base + done;
+    // rows before the cut: every hit (order within S does not matter)
+    if (full_cnt > 0u) {
+      for (int64_t c0 = 16 * wave; c0 < n; c0 += 64) {
+        float b[KS];
+        res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
+        const f32x4_t L = res_tile<RP>(a, b);
+        const int64_t col = c0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int lr = res_row(v, lane);
+          const int64_t row = r0 + lr;
+          if (lr < cut && col < n && row < m &&
+              (uint32_t)abs_key(X[row * ldx + col] - L[v]) == tkey) {
+            const unsigned int p = atomicAdd(&wpos, 1u);
+            s_idx[at + p] = row * n + col;
+            s_val[at + p] = 0.f;
+          }
+        }
+      }
+    }
+    // the cut row: its first cut_q hits in column order (lanes 16 gcut ..
+    // 16 gcut + 15 hold its 16 columns of a tile, in order)
+    if (cut < 16 && wave == 0) {
+      const unsigned int q = cut_q;
+      const int gcut = cut >> 2, vcut = cut & 3;
+      const int64_t row = r0 + cut;
+      unsigned int got = 0;
+      for (int64_t c0 = 0; c0 < n && got < q; c0 += 16) {
+        float b[KS];
+        res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
+        const f32x4_t L = res_tile<RP>(a, b);
+        const int64_t col = c0 + (lane & 15);
+        bool hit = false;
+        if ((lane >> 4) == gcut && col < n && row < m)
+          hit = (uint32_t)abs_key(X[row * ldx + col] - res_pick(L, vcut)) == tkey;
+        const unsigned long long mask = __ballot(hit);
+        const unsigned int rank = __builtin_amdgcn_mbcnt_hi(
+            (unsigned int)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)mask, 0u));
+        if (hit && got + rank < q) {
+          s_idx[at + full_cnt + got + rank] = row * n + col;
+          s_val[at + full_cnt + got + rank] = 0.f;
+        }
+        const unsigned int c = (unsigned int)__popcll(mask);
+        got = (got + c < q) ? got + c : q;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) done += (long long)full_cnt + (cut < 16 ? (long long)cut_q : 0ll);
+    __syncthreads();
+  }
+  return done;
+}
+
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X, int64_t ldx,
                                                          const T* __restrict__ UL,
                                                          const T* __restrict__ VL,
+                                                         const T* __restrict__ VLt, int64_t ldv,
                                                          int64_t m, int64_t n,
                                                          SelPlan* __restrict__ plan,
                                                          const int64_t* __restrict__ cand_idx,
@@ -765,6 +1033,12 @@ __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X
   const long long need = (tkey > 0) ? plan->k_rem : 0;
   if (tid == 0) taken = 0;
   __syncthreads();
+  if constexpr (sizeof(T) == 4) {
+    const long long got = ties_scan_mfma<RP>(X, ldx, UL, VLt, ldv, m, n, (uint32_t)tkey, need,
+                                             nabove, s_idx, s_val);
+    if (tid == 0) taken = got;
+    __syncthreads();
+  } else {
   for (int64_t i = 0; i < m && taken < need; ++i) {
     __syncthreads();
     if (tid < RP) us[tid] = UL[i * RP + tid];
@@ -790,6 +1064,7 @@ __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X
       __syncthreads();
     }
   }
+  }
   s2 = wave_sum(s2);
   __shared__ double red[4];
   if ((tid & 63) == 0) red[tid >> 6] = s2;
@@ -806,10 +1081,13 @@ __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X
 
 // Restore the sign of tied entries: their stored value is the residual,
 // recomputed here from X and the factors (same arithmetic as selection).
+// FP32: one wavefront per entry, which evaluates the entry's aligned tile.
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X, int64_t ldx,
                                                         const T* __restrict__ UL,
-                                                        const T* __restrict__ VL, int64_t n,
+                                                        const T* __restrict__ VL,
+                                                        const T* __restrict__ VLt, int64_t ldv,
+                                                        int64_t m, int64_t n,
                                                         const SelPlan* __restrict__ plan,
                                                         const unsigned long long* __restrict__ counters,
                                                         int64_t* __restrict__ s_idx,
@@ -817,6 +1095,29 @@ __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X,
                                                         T* __restrict__ s_x) {
   const long long start = (long long)counters[0];
   const long long nnz = plan->nnz;
+  if constexpr (sizeof(T) == 4) {
+    constexpr int KS = ResK<RP>::KS;
+    const int lane = threadIdx.x & 63;
+    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long e = start + (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+         e < nnz; e += nw) {
+      if (s_val[e] != 0.f) continue;   // the whole wavefront reads the same entry
+      const int64_t idx = s_idx[e];
+      const int64_t i = idx / n, j = idx % n;
+      const int64_t r0 = i - i % 16, c0 = j - j % 16;
+      float a[KS], b[KS];
+      res_load_u<RP>(UL, m, r0, lane, a);
+      res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
+      const f32x4_t L = res_tile<RP>(a, b);
+      const int li = (int)(i - r0), lj = (int)(j - c0);
+      if (lane == lj + 16 * (li >> 2)) {
+        const float x = X[i * ldx + j];
+        s_val[e] = x - res_pick(L, li & 3);
+        s_x[e] = x;
+      }
+    }
+    return;
+  }
   for (long long e = start + (long long)blockIdx.x * 256 + threadIdx.x; e < nnz;
        e += (long long)gridDim.x * 256) {
     if (s_val[e] != T(0)) continue;
@@ -865,6 +1166,32 @@ __global__ __launch_bounds__(256) void k_transpose_panel(const T* __restrict__ V
 // ---------------------------------------------------------------------------
 // Dense helpers.
 // ---------------------------------------------------------------------------
+// FP32 dense residual (or L) by aligned tiles: block (x, y) covers rows
+// [16 y, 16 y + 16) and columns [64 x, 64 x + 64), one tile per wavefront.
+template <int RP>
+__global__ __launch_bounds__(256) void k_residual_f32(const float* __restrict__ X, int64_t ldx,
+                                                      const float* __restrict__ UL,
+                                                      const float* __restrict__ VL, int64_t m,
+                                                      int64_t n, float* __restrict__ R,
+                                                      int64_t ldr, int dense_l) {
+  constexpr int KS = ResK<RP>::KS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * 16;
+  const int64_t c0 = (int64_t)blockIdx.x * 64 + 16 * wave;
+  float a[KS], b[KS];
+  res_load_u<RP>(UL, m, r0, lane, a);
+  res_load_v<RP>(VL, n, c0, lane, b);
+  const f32x4_t L = res_tile<RP>(a, b);
+  const int64_t col = c0 + (lane & 15);
+  if (col >= n) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = r0 + res_row(v, lane);
+    if (row >= m) continue;
+    R[row * ldr + col] = dense_l ? 0.f - (0.f - L[v]) : X[row * ldx + col] - L[v];
+  }
+}
+
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ X, int64_t ldx,
                                                   const T* __restrict__ UL,
@@ -1054,14 +1381,21 @@ static unsigned grid_for(int64_t work, int num_cu, int per_cu) {
 }
 
 // Blocks of the full-data passes (one candidate segment each).
+// FP32 passes (matrix-core tiles, four blocks per CU fit) take up to four
+// blocks per CU; FP64 passes two.
 template <typename T>
 static int64_t sel_grid(int rp, int64_t m, int64_t n, int num_cu) {
   int64_t g = 1;
-  GODEC_RP_SWITCH(rp, {
-    constexpr int TW = 256 * sel_cpt<T, RP>();
-    g = ((n + TW - 1) / TW) * ((m + kRowsPerTile - 1) / kRowsPerTile);
-  });
-  g = std::min<int64_t>(g, (int64_t)num_cu * 2);
+  if (sizeof(T) == 4) {
+    g = ((n + kResUnitCols - 1) / kResUnitCols) * ((m + 15) / 16);
+    g = std::min<int64_t>(g, (int64_t)num_cu * 4);
+  } else {
+    GODEC_RP_SWITCH(rp, {
+      constexpr int TW = 256 * sel_cpt<T, RP>();
+      g = ((n + TW - 1) / TW) * ((m + kRowsPerTile - 1) / kRowsPerTile);
+    });
+    g = std::min<int64_t>(g, (int64_t)num_cu * 2);
+  }
   return std::max<int64_t>(1, std::min<int64_t>(g, kMaxSeg / kSelWaves));
 }
 
@@ -1101,7 +1435,8 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
   }
   GODEC_RP_SWITCH(rp, {
     hipLaunchKernelGGL((k_sel_ties_stream<T, RP>), dim3(1), dim3(256), 0, L.stream,
-                       (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL, a.m, a.n, a.plan,
+                       (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL, (const T*)a.VLt,
+                       a.ldv, a.m, a.n, a.plan,
                        a.cand_idx, (const T*)a.cand_val, (const T*)a.cand_x,
                        (const unsigned int*)a.seg_count, a.s_idx, (T*)a.s_val, (T*)a.s_x,
                        a.carry);
@@ -1113,8 +1448,9 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
                      (T*)a.s_val, a.tie_idx, a.counters, a.carry);
   GODEC_RP_SWITCH(rp, {
     hipLaunchKernelGGL((k_fix_tie_values<T, RP>), dim3(grid_for(a.k, L.num_cu, 2)), dim3(256),
-                       0, L.stream, (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL, a.n,
-                       a.plan, a.counters, a.s_idx, (T*)a.s_val, (T*)a.s_x);
+                       0, L.stream, (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL,
+                       (const T*)a.VLt, a.ldv, a.m, a.n, a.plan, a.counters, a.s_idx,
+                       (T*)a.s_val, (T*)a.s_x);
   });
 }
 
@@ -1138,13 +1474,14 @@ void launch_residual(const Launch& L, bool f64, int rp, const void* X, int64_t l
                      const void* UL, const void* VL, int64_t m, int64_t n, void* R,
                      int64_t ldr, int dense_l) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + kRowsPerTile - 1) / kRowsPerTile));
+  dim3 grid16((unsigned)((n + 63) / 64), (unsigned)((m + 15) / 16));
   GODEC_RP_SWITCH(rp, {
     if (f64)
       hipLaunchKernelGGL((k_residual<double, RP>), grid, dim3(256), 0, L.stream,
                          (const double*)X, ldx, (const double*)UL, (const double*)VL, m, n,
                          (double*)R, ldr, dense_l);
     else
-      hipLaunchKernelGGL((k_residual<float, RP>), grid, dim3(256), 0, L.stream,
+      hipLaunchKernelGGL((k_residual_f32<RP>), grid16, dim3(256), 0, L.stream,
                          (const float*)X, ldx, (const float*)UL, (const float*)VL, m, n,
                          (float*)R, ldr, dense_l);
   });
