@@ -294,9 +294,11 @@ void mfma_apply(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool z
   mfma_reduce_w(L, b16, c->Wtpart, (int)c->nct_a, c->mpad, c->m, c->rp, Wt_out, Wrow_out);
 }
 
-// One Gram pass: out = D^T (D in), through W and the chunk partials.
+// One Gram pass: out = D^T (D in), through W and the chunk partials.  With
+// defer_sum (matrix-core passes only) the chunk partials are left in
+// c->Zpart32 for the Gram step to add up (gram_chol).
 void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt_ready,
-               void* out) {
+               void* out, bool defer_sum = false) {
   const Launch L = launch_of(c);
   if (td != F64) {
     const bool b16 = td == BF16;
@@ -305,7 +307,7 @@ void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt
       ProfScope ps(c, b16 ? PC_APPLY_T_BF16 : PC_APPLY_T, true);
       mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b, ps.a, ps.b);
     }
-    mfma_reduce_z(L, c->Zpart32, c->nch_b, c->ldd, c->rp, (float*)out);
+    if (!defer_sum) mfma_reduce_z(L, c->Zpart32, c->nch_b, c->ldd, c->rp, (float*)out);
     return;
   }
   {
@@ -324,13 +326,25 @@ void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt
 // accumulating its R factor into acc (reset when reset != 0).  next_td:
 // type of the matrix-core pass that reads `out` next (its transpose is
 // written to c->Zt), or F64 when none does.
-void chol_qr(godec_ctx* c, const void* in, void* out, double* acc, int reset, DType next_td) {
+void chol_qr(godec_ctx* c, const void* in, void* out, double* acc, int reset, DType next_td,
+             bool from_parts = false) {
   const Launch L = launch_of(c);
   launch_gram_tree(L, c->f64, c->rp, in, c->ldd, c->Gpart, c->gram_ctl, 1, c->st, acc, reset,
-                   acc == c->st->R2 ? 1 : 0);
+                   acc == c->st->R2 ? 1 : 0, from_parts ? c->Zpart32 : nullptr,
+                   from_parts ? (int)c->nch_b : 0);
   const bool zt = !c->f64 && next_td != F64;
   launch_apply_rinv(L, c->f64, c->rp, in, c->ldd, c->st, out, next_td, zt ? c->Zt : nullptr,
                     c->ldd);
+}
+
+// A Gram pass and one Cholesky QR step: out = orth(D^T (D in)) via tmp, its
+// R factor folded into acc.  For matrix-core passes the Gram kernel adds up
+// the pass's row-chunk partials itself (and stores tmp).
+void gram_chol(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt_ready,
+               void* tmp, void* out, double* acc, int reset, DType next_td) {
+  const bool parts = td != F64 && c->nch_b <= kGramMaxChunks;
+  gram_pass(c, td, Dsrc, in, zt_ready, tmp, parts);
+  chol_qr(c, tmp, out, acc, reset, next_td, parts);
 }
 
 godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
@@ -360,9 +374,9 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   bool zt = false;
   for (int j = 0; j < c->p; ++j) {
     const DType td = chain_td(j);
-    gram_pass(c, td, td == BF16 ? c->D16 : c->D, in, zt, c->P1);
     const bool more = j + 1 < c->p;
-    chol_qr(c, c->P1, c->P0, c->st->R2, j == 0, more ? chain_td(j + 1) : F64);
+    gram_chol(c, td, td == BF16 ? c->D16 : c->D, in, zt, c->P1, c->P0, c->st->R2, j == 0,
+              more ? chain_td(j + 1) : F64);
     zt = more;
     in = c->P0;
   }
@@ -372,8 +386,7 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   // ---- B chain: (D^T D)^q Q2 = Y_q T, then B' = D Y_q ----
   in = c->VL;
   for (int j = 0; j < c->q; ++j) {
-    gram_pass(c, tdb, Db, in, true, c->P1);
-    chol_qr(c, c->P1, c->P0, c->st->T, j == 0, tdb);
+    gram_chol(c, tdb, Db, in, true, c->P1, c->P0, c->st->T, j == 0, tdb);
     in = c->P0;
   }
   if (c->f64)

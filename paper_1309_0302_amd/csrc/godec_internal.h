@@ -122,14 +122,19 @@ constexpr int kGramGroup = 16;       // blocks per first-level group
 constexpr int kGramMaxBlocks = 256;
 constexpr int kGramFinal = kGramMaxBlocks + kGramMaxBlocks / kGramGroup;
 constexpr int kGramSlots = kGramFinal + 1;   // partial slots of RP x RP doubles
+constexpr int kGramMaxChunks = 16;   // row-chunk partials k_gram_tree can add up
 struct GramCtl {
   unsigned int grp[kGramMaxBlocks / kGramGroup];
   unsigned int top;
   unsigned int pad[15];
 };
+// Zpart (optional, FP32 only): form P first as the sum of nch (<= 16)
+// row-chunk partials Zpart (nch x rows x 32, chunk-ascending order) and store
+// it, instead of reading it.
 void launch_gram_tree(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
                       double* Gpart, GramCtl* ctl, int chol, SmallState* st, double* acc,
-                      int reset_acc, int normalise);
+                      int reset_acc, int normalise, const float* Zpart = nullptr,
+                      int nch = 0);
 // Out = P R^{-1} with R = st->Rq (upper triangular; zero rows and dinv = 0 on
 // inactive columns), by forward substitution in FP64, rows x RP in the
 // panel type; when Zt is given, also its transpose (32 x ldz, bf16 or f32,

@@ -163,12 +163,18 @@ __device__ void wave_chol(const double* G, SmallState* st, double* acc, int rese
   }
 }
 
+// With Zpart (FP32 panels only), the panel is first formed here: row i,
+// column c of P is the sum over h < nch of Zpart[(h rows + i) 32 + c] in
+// ascending h (the row-chunk partials of a matrix-core Gram pass), and is
+// also stored to P.
+
 template <typename TA, int RP>
 __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int64_t rows,
                                                    double* __restrict__ Gpart,
                                                    GramCtl* __restrict__ ctl, int chol,
                                                    SmallState* st, double* acc, int reset_acc,
-                                                   int normalise) {
+                                                   int normalise,
+                                                   const float* __restrict__ Zpart, int nch) {
   constexpr int RH = (RP + 1) / 2;    // tiles per side
   constexpr int RW = 2 * RH;          // padded width
   constexpr int NT = RH * RH;         // tiles
@@ -190,9 +196,29 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
   for (int64_t i0 = r0; i0 < r1; i0 += CH) {
     const int nr = (r1 - i0) < CH ? (int)(r1 - i0) : CH;
     __syncthreads();
-    for (int e = tid; e < CH * RW; e += 256) {
-      const int row = e / RW, c = e % RW;
-      ps[e] = (row < nr && c < RP) ? (double)P[(i0 + row) * RP + c] : 0.0;
+    if (Zpart != nullptr) {
+      for (int e = tid; e < CH * RW; e += 256) {
+        const int row = e / RW, c = e % RW;
+        double val = 0.0;
+        if (row < nr && c < RP) {
+          float v[kGramMaxChunks];
+#pragma unroll
+          for (int h = 0; h < kGramMaxChunks; ++h)
+            v[h] = h < nch ? Zpart[((int64_t)h * rows + i0 + row) * 32 + c] : 0.f;
+          float z = 0.f;
+#pragma unroll
+          for (int h = 0; h < kGramMaxChunks; ++h)
+            if (h < nch) z += v[h];
+          const_cast<TA*>(P)[(i0 + row) * RP + c] = (TA)z;
+          val = (double)z;
+        }
+        ps[e] = val;
+      }
+    } else {
+      for (int e = tid; e < CH * RW; e += 256) {
+        const int row = e / RW, c = e % RW;
+        ps[e] = (row < nr && c < RP) ? (double)P[(i0 + row) * RP + c] : 0.0;
+      }
     }
     __syncthreads();
     if (active) {
@@ -682,7 +708,7 @@ __global__ void k_small_init(SmallState* st, int r) {
 
 void launch_gram_tree(const Launch& L, bool f64, int rp, const void* P, int64_t rows,
                       double* Gpart, GramCtl* ctl, int chol, SmallState* st, double* acc,
-                      int reset_acc, int normalise) {
+                      int reset_acc, int normalise, const float* Zpart, int nch) {
   int64_t nb = (rows + kGramRows - 1) / kGramRows;
   if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
   if (nb < 1) nb = 1;
@@ -690,11 +716,11 @@ void launch_gram_tree(const Launch& L, bool f64, int rp, const void* P, int64_t 
     if (f64)
       hipLaunchKernelGGL((k_gram_tree<double, RP>), dim3((unsigned)nb), dim3(256), 0, L.stream,
                          (const double*)P, rows, Gpart, ctl, chol, st, acc, reset_acc,
-                         normalise);
+                         normalise, nullptr, 0);
     else
       hipLaunchKernelGGL((k_gram_tree<float, RP>), dim3((unsigned)nb), dim3(256), 0, L.stream,
                          (const float*)P, rows, Gpart, ctl, chol, st, acc, reset_acc,
-                         normalise);
+                         normalise, Zpart, nch);
   });
 }
 
