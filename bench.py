@@ -268,6 +268,7 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=25)
     ap.add_argument("--skip-layer", action="store_true")
+    ap.add_argument("--skip-copy", action="store_true")
     ap.add_argument("--only", choices=["batch", "layer", "copy"],
                     help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
@@ -336,6 +337,15 @@ def main():
         out["rel_diff_L_bf16_refine_vs_fp32"] = rel_diff_factors(
             bf["UL"], bf["VL"], fp["UL"], fp["VL"])
     out["kernels"] = bf["stats"]
+    # whole-iteration view: every timed streaming launch's algorithmic bytes
+    # (panel passes and the selection pass) over the whole timed solve
+    it_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in bf["stats"]) / args.steps
+    out["iteration_roofline"] = {
+        "streaming_bytes_per_iteration": round(it_bytes),
+        "achieved_GBps": round(it_bytes / (bf["ms"] / args.steps * 1e-3) / 1e9, 1),
+        "frac": round(it_bytes / (bf["ms"] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not args.skip_copy:
+        out["measured_copy"] = run_copy(1 << 30, 5)
     if not args.skip_batch:
         log("[bench] batched form: 64 problems")
         out["batched"] = run_batched(args.batch_iters, min(args.warmup, 3))

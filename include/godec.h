@@ -137,6 +137,23 @@ godec_status godec_solve(const void* X_dev, godec_dtype dtype, int64_t m,
                          int64_t* S_idx_dev, void* S_val_dev,
                          godec_info* info);
 
+/* As godec_solve, but iterating until the loop test of Algorithm 1 holds:
+ * after each iteration ||X - L - S||_F^2 / ||X||_F^2 (godec_info.rel_err_sq,
+ * Sec. 5 measure) is compared with eps, and the loop stops at the first
+ * iteration where it is <= eps, or after max_iters iterations.  In
+ * BF16_REFINE mode the tested iterations use the BF16 panels and
+ * opts->refine_iters FP32 refinement iterations follow the last one (they
+ * count toward max_iters).  Synchronises the stream once per iteration.
+ * info->iters reports the iterations run.  Errors as godec_solve, plus
+ * GODEC_E_INVAL for max_iters < 1 or eps < 0. */
+godec_status godec_solve_tol(const void* X_dev, godec_dtype dtype, int64_t m,
+                             int64_t n, int64_t ldx, int32_t r, int64_t k,
+                             int32_t q, uint64_t seed, int32_t max_iters, double eps,
+                             void* workspace_dev, size_t workspace_bytes,
+                             const godec_opts* opts, void* UL_dev, void* VL_dev,
+                             int64_t* S_idx_dev, void* S_val_dev,
+                             godec_info* info);
+
 /* L = UL * VL^T: UL_dev m x r, VL_dev n x r, row-major, dtype of X.
  * Columns past rank_eff are zero.  Asynchronous. */
 godec_status godec_get_factors(godec_ctx* ctx, void* UL_dev, void* VL_dev);

@@ -77,6 +77,10 @@ _SIG = {
                            ctypes.c_uint64, _I32, _P, ctypes.c_size_t,
                            ctypes.POINTER(godec_opts), _P, _P, _P, _P,
                            ctypes.POINTER(godec_info)]),
+    "godec_solve_tol": (_I32, [_P, _I32, _I64, _I64, _I64, _I32, _I64, _I32,
+                               ctypes.c_uint64, _I32, ctypes.c_double, _P, ctypes.c_size_t,
+                               ctypes.POINTER(godec_opts), _P, _P, _P, _P,
+                               ctypes.POINTER(godec_info)]),
     "godec_get_factors": (_I32, [_P, _P, _P]),
     "godec_get_L_dense": (_I32, [_P, _P, _I64]),
     "godec_get_S": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
@@ -262,6 +266,29 @@ def godec_solve(X, r, k, q, seed, iters, opts=None):
                               seed, iters, base, ws_bytes, ctypes.byref(opts),
                               UL.data_ptr(), VL.data_ptr(), sidx.data_ptr(),
                               sval.data_ptr(), ctypes.byref(info)))
+    nnz = info.nnz
+    return UL, VL, sidx[:nnz], sval[:nnz], info.as_dict()
+
+
+def godec_solve_tol(X, r, k, q, seed, max_iters, eps, opts=None):
+    """Iterate until rel_err_sq <= eps (loop test of Algorithm 1) or max_iters;
+    returns (UL, VL, S_idx, S_val, info)."""
+    import torch
+    m, n = X.shape
+    dt = _dtype_code(X)
+    opts = opts if opts is not None else make_opts()[0]
+    ws_bytes = godec_workspace_size(m, n, r, k, q, dt, opts)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    UL = torch.zeros((m, r), dtype=X.dtype, device=X.device)
+    VL = torch.zeros((n, r), dtype=X.dtype, device=X.device)
+    sidx = torch.zeros(max(k, 1), dtype=torch.int64, device=X.device)
+    sval = torch.zeros(max(k, 1), dtype=X.dtype, device=X.device)
+    info = godec_info()
+    _check(load().godec_solve_tol(X.data_ptr(), dt, m, n, X.stride(0), r, k, q,
+                                  seed, max_iters, eps, base, ws_bytes, ctypes.byref(opts),
+                                  UL.data_ptr(), VL.data_ptr(), sidx.data_ptr(),
+                                  sval.data_ptr(), ctypes.byref(info)))
     nnz = info.nnz
     return UL, VL, sidx[:nnz], sval[:nnz], info.as_dict()
 

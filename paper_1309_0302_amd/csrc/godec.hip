@@ -712,6 +712,43 @@ godec_status godec_solve(const void* X_dev, godec_dtype dtype, int64_t m, int64_
   return s;
 }
 
+godec_status godec_solve_tol(const void* X_dev, godec_dtype dtype, int64_t m, int64_t n,
+                             int64_t ldx, int32_t r, int64_t k, int32_t q, uint64_t seed,
+                             int32_t max_iters, double eps, void* ws, size_t ws_bytes,
+                             const godec_opts* opts, void* UL_dev, void* VL_dev,
+                             int64_t* S_idx_dev, void* S_val_dev, godec_info* info) {
+  if (max_iters < 1) return fail(GODEC_E_INVAL, "max_iters < 1");
+  if (!(eps >= 0.0)) return fail(GODEC_E_INVAL, "eps must be >= 0");
+  godec_ctx* c = nullptr;
+  godec_status s = godec_init(&c, X_dev, dtype, m, n, ldx, r, k, q, seed, ws, ws_bytes, opts);
+  if (s != GODEC_OK) return s;
+  const int32_t nref =
+      c->prec == GODEC_PREC_BF16_REFINE ? std::min<int32_t>(c->refine_iters, max_iters) : 0;
+  const int32_t budget = max_iters - nref;
+  int32_t done = 0;
+  godec_info cur;
+  // the loop test of Algorithm 1 after each iteration (the FP32 refinement
+  // iterations, when asked for, follow the last tested one)
+  while (s == GODEC_OK && done < budget) {
+    s = godec_step(c, 1, max_iters);
+    if (s != GODEC_OK) break;
+    ++done;
+    s = godec_get_info(c, &cur);
+    if (s == GODEC_OK && cur.rel_err_sq <= eps) break;
+  }
+  if (s == GODEC_OK && nref > 0) s = godec_step(c, nref, done + nref);
+  if (s == GODEC_OK && UL_dev && VL_dev) s = godec_get_factors(c, UL_dev, VL_dev);
+  int64_t nnz = 0;
+  if (s == GODEC_OK && S_idx_dev && S_val_dev) s = godec_get_S(c, S_idx_dev, S_val_dev, &nnz);
+  if (s == GODEC_OK && info) s = godec_get_info(c, info);
+  if (s == GODEC_OK) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = fail(GODEC_E_DEVICE, hipGetErrorString(e));
+  }
+  godec_destroy(c);
+  return s;
+}
+
 const char* godec_version(void) {
   return "libgodec 0.1 (gfx950; GoDec by bilateral random projection)";
 }

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   constexpr int LDT = kBatchMaxN + 4;          // LDS row stride of the D slab
   constexpr int PF = kBatchSub * (kBatchMaxN / 4) / 256;   // prefetch float4 per thread
   constexpr int MAXT = kBatchMaxN / 16 / 4;    // column tiles per wave
-  __shared__ float zt[RP8][kBatchMaxN];        // Z^T (zero past n)
+  __shared__ float zt[RP8][kBatchMaxN + 4];    // Z^T (zero past n); padded rows: no bank conflicts
   __shared__ float dt[kBatchSub * LDT];        // D slab (zero past ldd)
   __shared__ float wp[4][kBatchSub][RP8];      // per-wave partial W
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -110,13 +110,21 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   double g = 0.0;                              // MODE 1: Gram entry tid < 64
   const int ga = tid / RP8, gb = tid % RP8;
   float4 pf[PF];
+  // slab position of this thread's float4 number u (row, 4-column group),
+  // fixed for the whole work item
+  int prow[PF], poff[PF];
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int e = tid + 256 * u;
+    prow[u] = e / q4;
+    poff[u] = 4 * (e % q4);
+  }
   auto prefetch = [&](int64_t i0, int nr) {
+    const float* base = b.D + i0 * ldd;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int e = tid + 256 * u;
-      const int row = e / q4, c4 = e % q4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < nr) v = *reinterpret_cast<const float4*>(b.D + (i0 + row) * ldd + 4 * c4);
+      if (prow[u] < nr) v = *reinterpret_cast<const float4*>(base + (int64_t)prow[u] * ldd + poff[u]);
       pf[u] = v;
     }
   };
@@ -125,13 +133,8 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   for (int64_t i0 = it.i0; i0 < it.i1; i0 += kBatchSub) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + 256 * u;
-      if (e < kBatchSub * q4) {
-        const int row = e / q4, c4 = e % q4;
-        *reinterpret_cast<float4*>(&dt[row * LDT + 4 * c4]) = pf[u];
-      }
-    }
+    for (int u = 0; u < PF; ++u)
+      if (prow[u] < kBatchSub) *reinterpret_cast<float4*>(&dt[prow[u] * LDT + poff[u]]) = pf[u];
     __syncthreads();
     const int cur_nr = nr;
     const int64_t nx = i0 + kBatchSub;

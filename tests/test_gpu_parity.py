@@ -244,6 +244,36 @@ def test_solve_entry_point_matches_step_path():
     assert info["iters"] == 4
 
 
+def test_solve_tol_stops_at_the_loop_test():
+    """godec_solve_tol stops after the first iteration whose relative error is
+    <= eps (Algorithm 1's loop test), with the same result as that many
+    plain steps; the oracle's error sequence says where that is."""
+    from paper_1309_0302_amd import binding as b
+    from oracle.rng_ref import a1_gaussian
+    w = wl.tiny(300, 200, 5, seed=22, dtype=np.float64)
+    A1 = a1_gaussian(99, 200, 5)
+    tr = g.godec_brp(w.X, 5, w.k, 1, A1, 12)
+    errs = np.asarray(tr.rel_err_sq)
+    assert errs[2] > 1.01 * errs[3]                # a clear step to stop at
+    eps = float(np.sqrt(errs[2] * errs[3]))       # between the 3rd and 4th errors
+    expect = int(np.argmax(errs <= eps)) + 1
+    print(f"\n[solve_tol] errors {errs[:6]}, eps {eps:.3e}, expect {expect}", flush=True)
+    UL, VL, sidx, sval, info = b.godec_solve_tol(dev(w.X), 5, w.k, 1, 99, 12, eps)
+    assert info["iters"] == expect
+    assert info["rel_err_sq"] <= eps
+    gd = b.GoDec(dev(w.X), 5, w.k, 1, seed=99)
+    gd.step(expect)
+    U2, V2 = gd.factors()
+    assert np.array_equal(UL.cpu().numpy(), U2.cpu().numpy())
+    # eps = 0 runs all max_iters; bf16 + refinement ends with the refinement
+    _, _, _, _, info0 = b.godec_solve_tol(dev(w.X), 5, w.k, 1, 99, 5, 0.0)
+    assert info0["iters"] == 5
+    wf = wl.tiny(600, 400, 4, seed=23, dtype=np.float32)
+    opts, _ = b.make_opts(prec=1, refine_iters=1)
+    _, _, _, _, inf1 = b.godec_solve_tol(dev(wf.X), 4, wf.k, 1, 7, 6, 1e30, opts)
+    assert inf1["iters"] == 2                      # one tested iteration + one refinement
+
+
 # ---------------------------------------------------------------------------
 # Mixed precision: bf16 panels with FP32 accumulation and FP32 refinement
 # ---------------------------------------------------------------------------
