@@ -376,12 +376,121 @@ __global__ void ks_identity(int nb, int r, double* __restrict__ out) {
 }
 
 // ---------------------------------------------------------------------------
+// Tall-skinny products (the panel passes of the backward).
+//
+// kl_ts_nn: C[b] = alpha A[b] B[b] + beta C[b] with A M x K (row-major, one
+// thread per row) and B K x NC (NC <= 8, K <= kTsMaxK) staged in LDS.
+// kl_ts_tn: the K-chunk partials of A[b]^T B[b] with A stored K x M (one
+// thread per column of A, rows of the chunk read coalesced) and B K x NC;
+// kl_ts_reduce adds the chunks in order.
+// ---------------------------------------------------------------------------
+constexpr int kTsMaxK = 512;
+constexpr int kTsChunk = 256;
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void kl_ts_nn(int M, int K, const T* __restrict__ A,
+                                                int64_t lda, int64_t sA, const T* __restrict__ B,
+                                                int64_t sB, T alpha, T beta, T* __restrict__ C,
+                                                int64_t ldc, int64_t sC) {
+  __shared__ T bs[kTsMaxK * NC];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const T* Bb = B + (int64_t)b * sB;
+  for (int e = tid; e < K * NC; e += 256) bs[e] = Bb[e];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + tid;
+  if (i >= M) return;
+  const T* a = A + (int64_t)b * sA + (int64_t)i * lda;
+  T acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = T(0);
+  for (int k = 0; k < K; ++k) {
+    const T x = a[k];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j] += x * bs[k * NC + j];
+  }
+  T* c = C + (int64_t)b * sC + (int64_t)i * ldc;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) c[j] = alpha * acc[j] + (beta != T(0) ? beta * c[j] : T(0));
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void kl_ts_tn(int M, int K, const T* __restrict__ A,
+                                                int64_t lda, int64_t sA, const T* __restrict__ B,
+                                                int64_t sB, T* __restrict__ part) {
+  __shared__ T bs[kTsChunk * NC];
+  const int b = blockIdx.z, ch = blockIdx.y, tid = threadIdx.x;
+  const int k0 = ch * kTsChunk;
+  const int kn = (K - k0) < kTsChunk ? (K - k0) : kTsChunk;
+  const T* Bb = B + (int64_t)b * sB + (int64_t)k0 * NC;
+  for (int e = tid; e < kn * NC; e += 256) bs[e] = Bb[e];
+  __syncthreads();
+  const int c = blockIdx.x * 256 + tid;
+  if (c >= M) return;
+  const T* a = A + (int64_t)b * sA + (int64_t)k0 * lda + c;
+  T acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = T(0);
+  for (int k = 0; k < kn; ++k) {
+    const T x = a[(int64_t)k * lda];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j] += x * bs[k * NC + j];
+  }
+  T* o = part + (((int64_t)b * gridDim.y + ch) * M + c) * NC;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) o[j] = acc[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kl_ts_reduce(int M, int NC, int nch,
+                                                    const T* __restrict__ part, T alpha, T beta,
+                                                    T* __restrict__ C, int64_t ldc, int64_t sC) {
+  const int b = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M * NC) return;
+  T s = T(0);
+  for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)b * nch + ch) * M * NC + e];
+  const int64_t i = e / NC, j = e % NC;
+  T* c = C + (int64_t)b * sC + i * ldc + j;
+  *c = alpha * s + (beta != T(0) ? beta * *c : T(0));
+}
+
+#define GODEC_NC_SWITCH(nc, ...)                              \
+  switch (nc) {                                               \
+    case 1: { constexpr int NC = 1; __VA_ARGS__; } break;     \
+    case 2: { constexpr int NC = 2; __VA_ARGS__; } break;     \
+    case 3: { constexpr int NC = 3; __VA_ARGS__; } break;     \
+    case 4: { constexpr int NC = 4; __VA_ARGS__; } break;     \
+    case 5: { constexpr int NC = 5; __VA_ARGS__; } break;     \
+    case 6: { constexpr int NC = 6; __VA_ARGS__; } break;     \
+    case 7: { constexpr int NC = 7; __VA_ARGS__; } break;     \
+    case 8: { constexpr int NC = 8; __VA_ARGS__; } break;     \
+    default: break;                                           \
+  }
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
 template <typename T>
 void lk_gemm_t(const Launch& L, int nb, int M, int N, int K, const T* A, int64_t lda,
                int64_t sA, int ta, const T* B, int64_t ldb, int64_t sB, int tb, T alpha, T beta,
                T* C, int64_t ldc, int64_t sC, T* part, int64_t part_cap) {
+  // tall-skinny cases: a long panel times a small N-column one
+  if (!ta && !tb && N <= 8 && K <= kTsMaxK && ldb == N && M >= 256) {
+    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)nb);
+    GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_ts_nn<T, NC>), grid, dim3(256), 0, L.stream, M, K,
+                                          A, lda, sA, B, sB, alpha, beta, C, ldc, sC));
+    return;
+  }
+  const int nch_ts = (K + kTsChunk - 1) / kTsChunk;
+  if (ta && !tb && N <= 8 && ldb == N && M >= 64 && (int64_t)nb * nch_ts * M * N <= part_cap) {
+    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)nch_ts, (unsigned)nb);
+    GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_ts_tn<T, NC>), grid, dim3(256), 0, L.stream, M, K,
+                                          A, lda, sA, B, sB, part));
+    const dim3 g2((unsigned)(((int64_t)M * N + 255) / 256), (unsigned)nb);
+    hipLaunchKernelGGL(kl_ts_reduce<T>, g2, dim3(256), 0, L.stream, M, N, nch_ts, (const T*)part,
+                       alpha, beta, C, ldc, sC);
+    return;
+  }
   const int tiles = ((M + 15) / 16) * ((N + 15) / 16) * nb;
   int nsplit = 1;
   if (tiles < 1024 && K > 512) {

@@ -192,3 +192,26 @@ def test_layer_fp32_wide_problems_single_path():
         print(f"[layer] FP32 wide problem {b}: gradient {err:.2e}", flush=True)
         assert err < FP32_GRAD_TOL
     layer.close()
+
+
+def test_layer_fp64_tall_panels():
+    """FP64 problems tall enough for the tall-skinny panel products of the
+    backward (m >= 256 rows, n >= 64 columns): gradient against the oracle's
+    autograd gradient on both problems of a batch."""
+    works = [wl.tiny(520, 96, 3, rho=0.05, seed=s, dtype=np.float64, noise_std=1e-3)
+             for s in (41, 42)]
+    Xs = np.stack([w.X for w in works])
+    X = torch.from_numpy(Xs).cuda()
+    layer, L, S = gpu_layer(X, 3, works[0].k, 1, 3, 5)
+    rng = np.random.default_rng(6)
+    dL = rng.standard_normal(Xs.shape)
+    dS = rng.standard_normal(Xs.shape)
+    dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
+    for b in range(2):
+        masks = masks_of(layer, b, 3)
+        ref = lr.layer_grad(Xs[b], layer.A1(b), 1, masks, dL[b], dS[b])
+        got = dX[b].cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[layer] FP64 tall problem {b}: gradient {err:.2e}", flush=True)
+        assert err < 1e-9
+    layer.close()
