@@ -222,7 +222,10 @@ godec_status godec_profile_read(godec_ctx* ctx, godec_kernel_stat* out,
  * whole row of the problem in on-chip memory).  Each problem's S list has
  * capacity k and its candidate buffer m * n entries (all in the workspace).
  * An autotuner times the Gram pass for several row counts per work item
- * during godec_batch_init and keeps the fastest (godec_batch_tuning). */
+ * during godec_batch_init and keeps the fastest (godec_batch_tuning); the
+ * choice is remembered for the life of the process per device and batch
+ * shape (q and every problem's m and n), and later batches of that shape
+ * reuse it without timing. */
 typedef struct {
   const void* X_dev;      /* m x n FP32, leading dimension ldx (borrowed) */
   int64_t m, n, ldx;

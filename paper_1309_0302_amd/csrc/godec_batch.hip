@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -56,6 +58,7 @@ struct godec_batch {
   unsigned int* seg_count = nullptr;
   int max_items = 1;
   int* iter = nullptr;
+  int* state = nullptr;        // 2 ints per problem: non-finite flag, current rank
   int64_t max_m = 0, max_n = 0, max_k = 0;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -103,6 +106,7 @@ size_t carve_batch(godec_batch* b, void* base) {
   b->gslots = (double*)cv.take(sizeof(double) * items * kBatchRP * kBatchRP);
   b->seg_count = (unsigned int*)cv.take(sizeof(unsigned int) * items * 4);
   b->iter = (int*)cv.take(sizeof(int));
+  b->state = (int*)cv.take(sizeof(int) * 2 * b->count);
   b->tab.assign(b->count, BProb{});
   for (int i = 0; i < b->count; ++i) {
     const HostProb& h = b->hp[i];
@@ -237,7 +241,30 @@ void enqueue_iteration(godec_batch* b, int cur) {
 }
 
 // Time the Gram pass for each candidate row count; keep the fastest.
+// Tuned rows per work item, kept for the life of the process per device and
+// batch shape (q and every problem's m, n): later batches of the same shape
+// (a layer's forward on each call, say) skip the timing runs.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int64_t> g_tune_cache;
+
+std::vector<int64_t> tune_key(const godec_batch* b) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::vector<int64_t> key{dev, b->q, b->count};
+  for (const HostProb& h : b->hp) {
+    key.push_back(h.m);
+    key.push_back(h.n);
+  }
+  return key;
+}
+
 godec_status autotune(godec_batch* b) {
+  const std::vector<int64_t> key = tune_key(b);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return set_items(b, it->second);
+  }
   const Launch L{b->stream, b->num_cu};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -266,6 +293,10 @@ godec_status autotune(godec_batch* b) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best_rows;
+  }
   return set_items(b, best_rows);
 }
 
@@ -307,6 +338,19 @@ godec_status batch_snapshot_S(godec_batch* b, int64_t* idx_dev, float* val_dev, 
   bl_copy_lists(L, b->dprobs, b->count, (int)((b->iters_done - 1) & 1), b->max_k, idx_dev, val_dev,
                 kstride, nnz_dev);
   HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
+godec_status batch_ranks(godec_batch* b, int* rank_host) {
+  if (!b || !rank_host) return fail(GODEC_E_INVAL, "NULL argument");
+  const Launch L{b->stream, b->num_cu};
+  bl_gather_state(L, b->dprobs, b->count, b->state);
+  std::vector<int> st(2 * (size_t)b->count);
+  HIP_TRY(hipMemcpyAsync(st.data(), b->state, sizeof(int) * st.size(), hipMemcpyDeviceToHost,
+                         b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipGetLastError());
+  for (int i = 0; i < b->count; ++i) rank_host[i] = st[2 * i + 1];
   return GODEC_OK;
 }
 
@@ -371,15 +415,15 @@ godec_status godec_batch_init(godec_batch** out, const godec_problem* probs, int
   bl_init(L, a);
   bl_small_init(L, a);
   bl_copy_a1(L, a, b->max_n);
-  if (hipStreamSynchronize(b->stream) != hipSuccess || hipGetLastError() != hipSuccess)
+  bl_gather_state(L, b->dprobs, count, b->state);
+  std::vector<int> st(2 * (size_t)count);
+  if (hipMemcpyAsync(st.data(), b->state, sizeof(int) * st.size(), hipMemcpyDeviceToHost,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess || hipGetLastError() != hipSuccess)
     return bail(fail(GODEC_E_DEVICE, "batch init kernels failed"));
-  for (int i = 0; i < count; ++i) {
-    BSel hs;
-    if (hipMemcpy(&hs, b->tab[i].sel, sizeof(BSel), hipMemcpyDeviceToHost) != hipSuccess)
-      return bail(fail(GODEC_E_DEVICE, "copy"));
-    if (hs.nonfinite)
+  for (int i = 0; i < count; ++i)
+    if (st[2 * i])
       return bail(fail(GODEC_E_NUMERIC, "X of problem " + std::to_string(i) + " has NaN/Inf"));
-  }
   s = autotune(b);
   if (s != GODEC_OK) return bail(s);
   s = capture(b);

@@ -327,6 +327,8 @@ void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 void bl_init(const Launch& L, const BatchArgs& a);   // D = X, norms, state
 void bl_copy_lists(const Launch& L, const BProb* probs_dev, int nprob, int list, int64_t kmax,
                    int64_t* idx_out, float* val_out, int64_t kstride, int64_t* nnz_out);
+// out[2i], out[2i + 1] = problem i's non-finite flag and current rank
+void bl_gather_state(const Launch& L, const BProb* probs_dev, int nprob, int* out);
 void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, float* R,
                  int64_t ldr);
 void bl_small_init(const Launch& L, const BatchArgs& a);
@@ -350,11 +352,39 @@ void lk_scatter(const Launch& L, bool f64, int nb, void* P, int64_t stride, cons
                 double s);
 void lk_gather(const Launch& L, bool f64, int nb, const void* G, int64_t stride,
                const int64_t* idx, int64_t kstride, int64_t kmax, const int64_t* nnz, void* out);
-void lk_lowrank_at(const Launch& L, bool f64, int nb, const void* U, int64_t sU, const void* V,
-                   int64_t sV, int w, int64_t n, const int64_t* idx, int64_t kstride,
-                   int64_t kmax, const int64_t* nnz, void* out);
-void lk_put_cols(const Launch& L, bool f64, int nb, const void* P, int64_t sP, int r, void* O,
-                 int64_t sO, int w, int c0, int64_t rows);
+// D = X per problem (count entries); zeroes the bitmap words when bits != nullptr.
+void lk_rebuild_d(const Launch& L, bool f64, int nb, const void* X, void* D, int64_t count,
+                  uint32_t* bits, int64_t words);
+// D[idx] -= v over each problem's list, and the list's bits set in the bitmap.
+void lk_sub_mark(const Launch& L, bool f64, int nb, void* D, int64_t stride, const int64_t* idx,
+                 const void* v, int64_t kstride, int64_t kmax, const int64_t* nnz,
+                 uint32_t* bits, int64_t words);
+// Row-pass products over a dense m x n matrix D (row stride n; n <= 512 in
+// FP32, <= 128 in FP64; r <= 8), each problem in one read of D (k_dpass.hip):
+//   Y = D P'  (m x ny, row stride ldy) when Y is given, and
+//   Z = D^T Y[:, :r]  (n x r, row stride r) when Z is given (Y may then be
+//   nullptr unless pair),
+// with P n x r (pair false) or n x 2r (pair true: P' = P with its two r-column
+// halves swapped, ny = 2r), row stride ldp.  False when the shape is outside
+// the kernel's range (nothing launched).
+bool lk_dpass(const Launch& L, bool f64, int nb, int m, int n, int r, const void* D, bool pair,
+              const void* P, int64_t ldp, int64_t sP, void* Y, int64_t ldy, int64_t sY, void* Z,
+              void* part, int64_t part_cap);
+// C = A B' with B' column j = column (j + rot) mod N of B (B K x N, row stride
+// ldb), for a long A (M >= 256 rows, K <= 512, N <= 8); false when the shape is
+// outside that range (nothing launched).
+bool lk_dmul_rot(const Launch& L, bool f64, int nb, int M, int N, int K, const void* A,
+                 int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB, int rot,
+                 void* C, int64_t ldc, int64_t sC);
+// X += U V^T off the support and Lbar = U V^T on it (0 off it); bits ==
+// nullptr: X += U V^T everywhere (X = U V^T when accumulate is 0).  U m x w,
+// V n x w, row stride w.
+void lk_uvt_update(const Launch& L, bool f64, int nb, int m, int n, int w, const void* U,
+                   int64_t sU, const void* V, int64_t sV, void* X, int64_t ldx, int64_t sX,
+                   int accumulate, const uint32_t* bits, int64_t wstride, void* Lbar,
+                   int64_t sL);
+void lk_put_cols(const Launch& L, bool f64, int nb, const void* P0, const void* P1, int64_t sP,
+                 int r, void* O, int64_t sO, int w, int c0, int64_t rows);
 void lk_cast_a1(const Launch& L, bool f64, int nb, const double* A1, int64_t sA, void* P,
                 int64_t sP, int64_t count);
 void lk_chol(const Launch& L, bool f64, int nb, int r, const void* gram, const double* rin,

@@ -56,10 +56,12 @@ struct godec_layer {
   void *Rinv = nullptr, *Gm = nullptr, *Cm = nullptr, *Ca = nullptr, *CbarA = nullptr;
   void *S2 = nullptr, *T1 = nullptr, *Rrel = nullptr;
   double *Vv = nullptr, *F = nullptr;
-  void *Wm = nullptr, *Wm2 = nullptr, *B = nullptr, *LQ = nullptr, *Bbar = nullptr;
+  void *Wm2 = nullptr, *B = nullptr, *LQ = nullptr, *Bbar = nullptr;
   void *Vn = nullptr, *LtB = nullptr, *Qbar = nullptr, *Cur = nullptr, *Tn = nullptr;
   void *Uf = nullptr, *Vf = nullptr;  // nb x m x w, nb x n x w
   void* vals = nullptr;               // nb x max(k, 1)
+  uint32_t* bits = nullptr;           // nb x words: support bitmap of one M_t
+  int64_t words = 0;
   void* part = nullptr;               // split-K partial products
   int64_t part_cap = 0;
   int* flag = nullptr;
@@ -97,13 +99,15 @@ size_t carve_layer(godec_layer* l, void* base, size_t ctx_ws, std::vector<void*>
   for (void** s : small) *s = cv.take(ts * nb * E);
   l->Vv = (double*)cv.take(sizeof(double) * nb * E);
   l->F = (double*)cv.take(sizeof(double) * nb * E);
-  void** mpan[] = {&l->Wm, &l->Wm2, &l->B, &l->LQ, &l->Bbar};
+  void** mpan[] = {&l->Wm2, &l->B, &l->LQ, &l->Bbar};
   for (void** s : mpan) *s = cv.take(ts * nb * mr);
   void** npan[] = {&l->Vn, &l->LtB, &l->Qbar, &l->Cur, &l->Tn};
   for (void** s : npan) *s = cv.take(ts * nb * nr);
   l->Uf = cv.take(ts * nb * m * l->w);
   l->Vf = cv.take(ts * nb * n * l->w);
   l->vals = cv.take(ts * nb * kk);
+  l->words = (mn + 31) / 32;
+  l->bits = (uint32_t*)cv.take(sizeof(uint32_t) * nb * l->words);
   // Largest split-K product: n x r or r x r outputs, at most 64 chunks.
   l->part_cap = (int64_t)nb * 64 * std::max<int64_t>(nr, E);
   l->part = cv.take(ts * l->part_cap);
@@ -122,11 +126,18 @@ struct Ops {
     lk_gemm(L, l->f64, l->nb, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, alpha, beta, C, ldc, sC,
             l->part, l->part_cap);
   }
-  // out (m x r) = D P, P n x r
-  void dmul(const void* P, void* out) {
+  // out (m x r, row stride ldo, problem stride so) = D P, P n x r
+  void dmul(const void* P, void* out, int64_t ldo = 0, int64_t so = 0) {
     const int64_t m = l->m, n = l->n;
     const int r = l->r;
-    gemm((int)m, r, (int)n, l->D, n, m * n, 0, P, r, n * r, 0, 1.0, 0.0, out, r, m * r);
+    if (!ldo) {
+      ldo = r;
+      so = m * r;
+    }
+    if (lk_dpass(L, l->f64, l->nb, (int)m, (int)n, r, l->D, false, P, r, n * r, out, ldo, so,
+                 nullptr, l->part, l->part_cap))
+      return;
+    gemm((int)m, r, (int)n, l->D, n, m * n, 0, P, r, n * r, 0, 1.0, 0.0, out, ldo, so);
   }
   // out (n x r) = D^T W, W m x r
   void dtmul(const void* W, void* out) {
@@ -136,6 +147,9 @@ struct Ops {
   }
   // out = A P = D^T (D P)
   void amul(const void* P, void* out) {
+    if (lk_dpass(L, l->f64, l->nb, (int)l->m, (int)l->n, l->r, l->D, false, P, l->r,
+                 l->n * l->r, nullptr, 0, 0, out, l->part, l->part_cap))
+      return;
     dmul(P, l->Wm2);
     dtmul(l->Wm2, out);
   }
@@ -151,9 +165,10 @@ struct Ops {
     gemm((int)rows, r, r, P, r, rows * r, 0, M, r, (int64_t)r * r, 0, alpha, beta, out, r,
          rows * r);
   }
-  // columns [c0, c0 + r) of the rows x w factor O <- P
-  void put(const void* P, int64_t rows, void* O, int c0) {
-    lk_put_cols(L, l->f64, l->nb, P, rows * l->r, l->r, O, rows * l->w, l->w, c0, rows);
+  // columns [c0, c0 + r) of the rows x w factor O <- P0, and
+  // [c0 + r, c0 + 2r) <- P1 when given
+  void put(const void* P0, const void* P1, int64_t rows, void* O, int c0) {
+    lk_put_cols(L, l->f64, l->nb, P0, P1, rows * l->r, l->r, O, rows * l->w, l->w, c0, rows);
   }
   void copy(const void* S, void* D, int64_t count) { lk_copy(L, l->f64, l->nb, S, D, count, count); }
 };
@@ -191,7 +206,9 @@ void vjp_step(godec_layer* l, Ops& o) {
   lk_eig(L, f64, nb, r, l->Cm, -(double)(p - 1) / (2.0 * p), l->Ca, l->Vv, l->F, l->flag);
 
   // ---- adjoint of L = B C^a Q^T ----
-  o.gemm((int)m, r, (int)n, l->Lbar, n, m * n, 0, Q, r, nr, 0, 1.0, 0.0, l->LQ, r, m * r);
+  if (!lk_dpass(L, f64, nb, (int)m, (int)n, r, l->Lbar, false, Q, r, nr, l->LQ, r, m * r, nullptr,
+                l->part, l->part_cap))
+    o.gemm((int)m, r, (int)n, l->Lbar, n, m * n, 0, Q, r, nr, 0, 1.0, 0.0, l->LQ, r, m * r);
   o.gemm((int)n, r, (int)m, l->Lbar, n, m * n, 1, l->B, r, m * r, 0, 1.0, 0.0, l->LtB, r, nr);
   o.inner(l->B, l->LQ, m, l->CbarA);                 // C^a bar = B^T L^bar Q
   lk_dk(L, f64, nb, r, l->CbarA, l->Vv, l->F, l->S2);  // B^T B adjoint, both sides
@@ -201,29 +218,38 @@ void vjp_step(godec_layer* l, Ops& o) {
 
   // D^bar terms, each a rank-r outer product appended to (U, V).
   int col = 0;
-  o.put(l->Bbar, m, l->Uf, col);                      // B = D (A^q Q): B^bar (A^q Q)^T
-  o.put(Qsi(q), n, l->Vf, col);
+  o.put(l->Bbar, nullptr, m, l->Uf, col);             // B = D (A^q Q): B^bar (A^q Q)^T
+  o.put(Qsi(q), nullptr, n, l->Vf, col);
   col += r;
   // dA = dD^T D + D^T dD turns <G, dA> with G = U W^T into D^bar terms
   // (D U) W^T + (D W) U^T.
-  auto add_term = [&](const void* U, const void* W) {
-    o.dmul(U, l->Wm);
-    o.put(l->Wm, m, l->Uf, col);
-    o.put(W, n, l->Vf, col);
-    col += r;
-    o.dmul(W, l->Wm);
-    o.put(l->Wm, m, l->Uf, col);
-    o.put(U, n, l->Vf, col);
-    col += r;
+  // The pair takes columns [col, col + 2r) of both factors: V gets (W, U) and
+  // U gets (D U, D W), which is D times V's block with its halves swapped
+  // (one pass over D when the panel kernel takes it).
+  const int64_t w = l->w;
+  // With AU given, the same pass over D also forms AU = A U.
+  auto add_term = [&](const void* U, const void* W, void* AU) {
+    o.put(W, U, n, l->Vf, col);
+    if (!lk_dpass(L, f64, nb, (int)m, (int)n, r, l->D, true, at(l->Vf, ts, col), w, n * w,
+                  at(l->Uf, ts, col), w, m * w, AU, l->part, l->part_cap)) {
+      if (!lk_dmul_rot(L, f64, nb, (int)m, 2 * r, (int)n, l->D, n, m * n, at(l->Vf, ts, col), w,
+                       n * w, r, at(l->Uf, ts, col), w, m * w)) {
+        o.dmul(U, at(l->Uf, ts, col), w, m * w);
+        o.dmul(W, at(l->Uf, ts, col + r), w, m * w);
+      }
+      if (AU) o.amul(U, AU);
+    }
+    col += 2 * r;
   };
   // A^q inside B: terms (A^i D^T B^bar, A^{q-1-i} Q); Q^bar += A^q D^T B^bar
-  o.dtmul(l->Bbar, l->Cur);
+  void* cur = l->Cur;
+  void* spare = l->Tn;
+  o.dtmul(l->Bbar, cur);
   for (int i = 0; i < q; ++i) {
-    add_term(l->Cur, Qsi(q - 1 - i));
-    o.amul(l->Cur, l->Tn);
-    o.copy(l->Tn, l->Cur, nr);
+    add_term(cur, Qsi(q - 1 - i), spare);
+    std::swap(cur, spare);
   }
-  lk_axpy(L, f64, nb, l->Cur, l->Qbar, nr, nr);
+  lk_axpy(L, f64, nb, cur, l->Qbar, nr, nr);
   // Q = orth(Y), Y = A^p A1 = Q Rtot; f depends on the range of Q only, so
   // Y^bar = (I - Q Q^T) Q^bar Rtot^{-T}.
   o.inner(Q, l->Qbar, n, l->T1);
@@ -231,16 +257,15 @@ void vjp_step(godec_layer* l, Ops& o) {
   // Terms of A^p: (A^i Y^bar, A^{p-1-i} A1).  With A^j A1 = Z_j Rc_j they are
   // (A^i Ybar0) (Z_j Rc_j Rtot^{-1})^T, Ybar0 = (I - Q Q^T) Q^bar, which keeps
   // every factor well scaled.
-  o.copy(l->Qbar, l->Cur, nr);
+  cur = l->Qbar;
+  spare = l->Vn;
   for (int i = 0; i < p; ++i) {
     const int j = p - 1 - i;
     lk_rrel(L, f64, nb, r, Rcj(j), Rcj(p + 1), l->Rrel);
     o.panel_rr(Zj(j), n, l->Rrel, l->Tn);
-    add_term(l->Cur, l->Tn);
-    if (i + 1 < p) {
-      o.amul(l->Cur, l->Vn);
-      o.copy(l->Vn, l->Cur, nr);
-    }
+    const bool more = i + 1 < p;
+    add_term(cur, l->Tn, more ? spare : nullptr);
+    if (more) std::swap(cur, spare);
   }
 }
 
@@ -388,11 +413,11 @@ godec_status forward_batched(godec_layer* l, const void* X_dev, uint64_t seed, v
   hipError_t e = hipMemcpyAsync(l->ck_nnz_host.data(), l->ck_nnz,
                                 sizeof(int64_t) * l->ck_nnz_host.size(), hipMemcpyDeviceToHost, bs);
   if (e != hipSuccess) return done(fail(GODEC_E_DEVICE, hipGetErrorString(e)));
+  std::vector<int> rank(nb);
+  s = batch_ranks(gb, rank.data());   // synchronises bs
+  if (s != GODEC_OK) return done(s);
   for (int b = 0; b < nb; ++b) {
-    godec_info info;
-    s = godec_batch_get_info(gb, b, &info);   // synchronises bs
-    if (s != GODEC_OK) return done(s);
-    if (info.rank_eff != r) return done(rank_error(b));
+    if (rank[b] != r) return done(rank_error(b));
     s = godec_batch_get_A1(gb, b, l->a1_host.data() + (size_t)b * n * r);
     if (s != GODEC_OK) return done(s);
     if (L_dev) {
@@ -402,8 +427,8 @@ godec_status forward_batched(godec_layer* l, const void* X_dev, uint64_t seed, v
   }
   if (L_dev) {
     const Launch L{bs, l->num_cu};
-    lk_gemm(L, false, nb, (int)m, (int)n, r, l->Uf, r, m * r, 0, l->Vf, r, n * r, 1, 1.0, 0.0,
-            L_dev, n, mn, l->part, l->part_cap);
+    lk_uvt_update(L, false, nb, (int)m, (int)n, r, l->Uf, m * r, l->Vf, n * r, L_dev, n, mn, 0,
+                  nullptr, 0, nullptr, 0);
   }
   e = hipStreamSynchronize(bs);
   if (e == hipSuccess) e = hipGetLastError();
@@ -518,22 +543,21 @@ godec_status godec_layer_backward(godec_layer* l, const void* dL_dev, const void
   lk_copy(L, f64, nb, dL_dev, l->Lbar, mn, mn);
   lk_scatter(L, f64, nb, l->Lbar, mn, idx_of(l->T), l->vals, kk, kk, nnz_of(l->T), 1, -1.0);
   for (int t = l->T; t >= 1; --t) {
-    // D_t = X - S_{t-1}
-    lk_copy(L, f64, nb, l->X, l->D, mn, mn);
+    // D_t = X - S_{t-1}, and the bitmap of M_{t-1}
+    lk_rebuild_d(L, f64, nb, l->X, l->D, mn, t >= 2 ? l->bits : nullptr, l->words);
     if (t >= 2)
-      lk_scatter(L, f64, nb, l->D, mn, idx_of(t - 1), val_of(t - 1), kk, kk, nnz_of(t - 1), 1,
-                 -1.0);
+      lk_sub_mark(L, f64, nb, l->D, mn, idx_of(t - 1), val_of(t - 1), kk, kk, nnz_of(t - 1),
+                  l->bits, l->words);
     vjp_step(l, o);
-    // X^bar += D^bar = U V^T
-    o.gemm((int)m, (int)n, l->w, l->Uf, l->w, m * l->w, 0, l->Vf, l->w, n * l->w, 1, 1.0, 1.0,
-           dX_dev, n, mn);
+    // X^bar += D^bar = U V^T.  For t >= 2, S_{t-1} = M_{t-1} * (X - L_{t-1})
+    // with S^bar_{t-1} = -D^bar: on M_{t-1} the two contributions to X^bar
+    // cancel and D^bar becomes L^bar_{t-1}, which is zero off M_{t-1}.
     if (t >= 2) {
-      // S_{t-1} = M_{t-1} * (X - L_{t-1}) with S^bar_{t-1} = -D^bar
-      lk_lowrank_at(L, f64, nb, l->Uf, m * l->w, l->Vf, n * l->w, l->w, n, idx_of(t - 1), kk, kk,
-                    nnz_of(t - 1), l->vals);
-      lk_scatter(L, f64, nb, dX_dev, mn, idx_of(t - 1), l->vals, kk, kk, nnz_of(t - 1), 1, -1.0);
-      lk_fill(L, f64, nb, l->Lbar, mn, mn, 0.0);
-      lk_scatter(L, f64, nb, l->Lbar, mn, idx_of(t - 1), l->vals, kk, kk, nnz_of(t - 1), 0, 1.0);
+      lk_uvt_update(L, f64, nb, (int)m, (int)n, l->w, l->Uf, m * l->w, l->Vf, n * l->w, dX_dev, n,
+                    mn, 1, l->bits, l->words, l->Lbar, mn);
+    } else {
+      lk_uvt_update(L, f64, nb, (int)m, (int)n, l->w, l->Uf, m * l->w, l->Vf, n * l->w, dX_dev, n,
+                    mn, 1, nullptr, 0, nullptr, 0);
     }
   }
   int hflag[4] = {0, 0, 0, 0};

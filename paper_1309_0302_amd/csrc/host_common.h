@@ -39,6 +39,10 @@ int device_cu_count();
 godec_status batch_snapshot_S(godec_batch* b, int64_t* idx_dev, float* val_dev, int64_t kstride,
                               int64_t* nnz_dev);
 
+// Current rank of every problem of the batch (one copy, synchronises the
+// batch's stream).
+godec_status batch_ranks(godec_batch* b, int* rank_host);
+
 }  // namespace godec_host
 
 #define HIP_TRY(expr)                                                        \

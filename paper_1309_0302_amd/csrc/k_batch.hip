@@ -876,6 +876,20 @@ void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, f
   hipLaunchKernelGGL(kb_residual, dim3(g), dim3(256), 0, L.stream, prob_dev, R, ldr);
 }
 
+// out[2i] = problem i's non-finite flag, out[2i + 1] = its current rank
+__global__ __launch_bounds__(256) void kb_gather_state(const BProb* __restrict__ probs, int nprob,
+                                                       int* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nprob) return;
+  out[2 * i] = probs[i].sel->nonfinite;
+  out[2 * i + 1] = probs[i].st->r_eff;
+}
+
+void bl_gather_state(const Launch& L, const BProb* probs_dev, int nprob, int* out) {
+  hipLaunchKernelGGL(kb_gather_state, dim3((unsigned)((nprob + 255) / 256)), dim3(256), 0,
+                     L.stream, probs_dev, nprob, out);
+}
+
 void bl_copy_lists(const Launch& L, const BProb* probs_dev, int nprob, int list, int64_t kmax,
                    int64_t* idx_out, float* val_out, int64_t kstride, int64_t* nnz_out) {
   const dim3 g((unsigned)((std::max<int64_t>(kmax, 1) + 255) / 256), (unsigned)nprob);

@@ -16,6 +16,7 @@
 #include "k_common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace godec {
 
@@ -138,30 +139,229 @@ __global__ __launch_bounds__(256) void kl_gather(const T* __restrict__ G, int64_
   out[(int64_t)b * kstride + e] = G[(int64_t)b * stride + idx[(int64_t)b * kstride + e]];
 }
 
-// out[e] = sum_c U[i][c] V[j][c] at the list entries (i, j) = divmod(idx, n)
-template <typename T>
-__global__ __launch_bounds__(256) void kl_lowrank_at(const T* __restrict__ U, int64_t sU,
+// Low-rank update split by a support (one block: RB rows x 256 columns).
+//   P = U V^T  (U m x w, V n x w, both with row stride w)
+//   X += P off the support,  Lbar = P on the support and 0 off it;
+// without a bitmap: X += P everywhere, or X = P when accumulate is 0 (Lbar
+// untouched).  Entry (i, j) of the
+// support is bit i n + j of the problem's bitmap.  Chunks of CW columns of w
+// pass through LDS: V's rows for the block's columns (one per thread, odd
+// row stride) and U's rows for the block's rows, transposed so that a thread
+// reads four of its RB row values per broadcast.  Each thread owns one column
+// and keeps RB sums, added in the order of w.
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void kl_uvt_update(int m, int n, int w,
+                                                     const T* __restrict__ U, int64_t sU,
                                                      const T* __restrict__ V, int64_t sV,
-                                                     int w, int64_t n,
-                                                     const int64_t* __restrict__ idx,
-                                                     int64_t kstride,
-                                                     const int64_t* __restrict__ nnz,
-                                                     T* __restrict__ out) {
+                                                     T* __restrict__ X, int64_t ldx, int64_t sX,
+                                                     int accumulate,
+                                                     const uint32_t* __restrict__ bits,
+                                                     int64_t wstride, T* __restrict__ Lbar,
+                                                     int64_t sL) {
+  constexpr int CW = sizeof(T) == 8 ? 16 : 32;
+  __shared__ T vs[256][CW + 1];
+  __shared__ __align__(16) T ut[CW][RB];
+  const int b = blockIdx.z, tid = threadIdx.x;
+  const int j0 = blockIdx.x * 256, i0 = blockIdx.y * RB;
+  const T* Ub = U + (int64_t)b * sU;
+  const T* Vb = V + (int64_t)b * sV;
+  T acc[RB];
+#pragma unroll
+  for (int ii = 0; ii < RB; ++ii) acc[ii] = T(0);
+  for (int c0 = 0; c0 < w; c0 += CW) {
+    const int cw = (w - c0) < CW ? (w - c0) : CW;
+    __syncthreads();
+#pragma unroll 4
+    for (int e = tid; e < 256 * CW; e += 256) {
+      const int jj = e / CW, cc = e % CW;
+      vs[jj][cc] = (cc < cw && j0 + jj < n) ? Vb[(int64_t)(j0 + jj) * w + c0 + cc] : T(0);
+    }
+    for (int e = tid; e < RB * CW; e += 256) {
+      const int ii = e / CW, cc = e % CW;
+      ut[cc][ii] = (cc < cw && i0 + ii < m) ? Ub[(int64_t)(i0 + ii) * w + c0 + cc] : T(0);
+    }
+    __syncthreads();
+    for (int cc = 0; cc < cw; ++cc) {
+      const T v = vs[tid][cc];
+#pragma unroll
+      for (int ii = 0; ii < RB; ++ii) acc[ii] += ut[cc][ii] * v;
+    }
+  }
+  const int j = j0 + tid;
+  if (j >= n) return;
+  T* Xb = X + (int64_t)b * sX;
+#pragma unroll
+  for (int ii = 0; ii < RB; ++ii) {
+    const int i = i0 + ii;
+    if (i < m) {
+      T* x = Xb + (int64_t)i * ldx + j;
+      if (bits) {
+        const int64_t e = (int64_t)i * n + j;
+        const bool on = (bits[(int64_t)b * wstride + (e >> 5)] >> (unsigned)(e & 31)) & 1u;
+        if (!on) *x += acc[ii];
+        Lbar[(int64_t)b * sL + e] = on ? acc[ii] : T(0);
+      } else {
+        *x = accumulate ? *x + acc[ii] : acc[ii];
+      }
+    }
+  }
+}
+
+// FP32 form of kl_uvt_update on the matrix cores: a block covers 64 rows x
+// 256 columns, each wave one 16-row tile against the 16 column tiles, with
+// v_mfma_f32_16x16x4f32 over chunks of 32 columns of w.  In k-step s of a
+// chunk, lane l (row or column l%16, g = l/16) supplies column 8g + s of the
+// chunk, so that each lane reads eight consecutive values of its U or V row
+// (two 16-byte loads when VEC: w a multiple of four).  Lane l receives the
+// product at column l%16 and rows 4g + v, v < 4, of its tile.
+typedef float kl_f32x4 __attribute__((ext_vector_type(4)));
+
+template <bool VEC>
+__device__ __forceinline__ void uvt_row8(const float* __restrict__ row, bool ok, int c, int w,
+                                         float (&v)[8]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v[s] = 0.f;
+  if (!ok) return;
+  if (VEC) {
+    if (c + 8 <= w) {
+      const float4 x = *reinterpret_cast<const float4*>(row + c);
+      const float4 y = *reinterpret_cast<const float4*>(row + c + 4);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    } else if (c + 4 <= w) {
+      const float4 x = *reinterpret_cast<const float4*>(row + c);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      if (c + s < w) v[s] = row[c + s];
+  }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void kl_uvt_mfma(int m, int n, int w,
+                                                   const float* __restrict__ U, int64_t sU,
+                                                   const float* __restrict__ V, int64_t sV,
+                                                   float* __restrict__ X, int64_t ldx,
+                                                   int64_t sX, int accumulate,
+                                                   const uint32_t* __restrict__ bits,
+                                                   int64_t wstride, float* __restrict__ Lbar,
+                                                   int64_t sL) {
+  const int b = blockIdx.z, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.y * 64 + wave * 16;
+  const int j0 = blockIdx.x * 256;
+  const float* Ub = U + (int64_t)b * sU;
+  const float* Vb = V + (int64_t)b * sV;
+  kl_f32x4 acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = kl_f32x4{0.f, 0.f, 0.f, 0.f};
+  const int urow = r0 + li;
+  for (int c0 = 0; c0 < w; c0 += 32) {
+    const int ks = (w - c0) < 8 ? (w - c0) : 8;  // k-steps with a valid column
+    float a[8];
+    uvt_row8<VEC>(Ub + (int64_t)urow * w, urow < m, c0 + 8 * g, w, a);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int vrow = j0 + 16 * t + li;
+      float bv[8];
+      uvt_row8<VEC>(Vb + (int64_t)vrow * w, vrow < n, c0 + 8 * g, w, bv);
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (s < ks) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[s], acc[t], 0, 0, 0);
+    }
+  }
+  // Epilogue in batches of four tiles; the next batch's loads are issued
+  // before this batch's stores so that waiting for them does not wait for
+  // the stores.
+  float* Xb = X + (int64_t)b * sX;
+  const uint32_t* Bb = bits ? bits + (int64_t)b * wstride : nullptr;
+  float xv[2][4][4];
+  uint32_t wv[2][4][4];
+  auto load_batch = [&](int t0, float (&xs)[4][4], uint32_t (&ws)[4][4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 16 * (t0 + u) + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = r0 + 4 * g + v;
+        const bool ok = i < m && j < n;
+        const int64_t e = (int64_t)i * n + j;
+        xs[u][v] = (ok && (accumulate || Bb)) ? Xb[(int64_t)i * ldx + j] : 0.f;
+        ws[u][v] = (ok && Bb) ? Bb[e >> 5] : 0u;
+      }
+    }
+  };
+  load_batch(0, xv[0], wv[0]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k + 1 < 4) load_batch(4 * (k + 1), xv[(k + 1) & 1], wv[(k + 1) & 1]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = 4 * k + u;
+      const int j = j0 + 16 * t + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = r0 + 4 * g + v;
+        if (i < m && j < n) {
+          float* x = Xb + (int64_t)i * ldx + j;
+          const float val = acc[t][v];
+          const float old = xv[k & 1][u][v];
+          if (Bb) {
+            const int64_t e = (int64_t)i * n + j;
+            const bool on = (wv[k & 1][u][v] >> (unsigned)(e & 31)) & 1u;
+            if (!on) *x = old + val;
+            Lbar[(int64_t)b * sL + e] = on ? val : 0.f;
+          } else {
+            *x = accumulate ? old + val : val;
+          }
+        }
+      }
+    }
+  }
+}
+
+// D = X (count entries per problem; 16-byte vectors when vec is set) and,
+// when bits is given, zero the problem's bitmap words.
+template <typename T>
+__global__ __launch_bounds__(256) void kl_rebuild_d(const T* __restrict__ X, T* __restrict__ D,
+                                                    int64_t count, int vec,
+                                                    uint32_t* __restrict__ bits, int64_t words) {
+  constexpr int VW = 16 / sizeof(T);
+  using V4 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  const int b = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (bits && e < words) bits[(int64_t)b * words + e] = 0u;
+  if (vec) {
+    if (e < count / VW)
+      reinterpret_cast<V4*>(D + (int64_t)b * count)[e] =
+          reinterpret_cast<const V4*>(X + (int64_t)b * count)[e];
+  } else if (e < count) {
+    D[(int64_t)b * count + e] = X[(int64_t)b * count + e];
+  }
+}
+
+// D[idx[e]] -= v[e] over the list of problem b and set the entry's bit.
+template <typename T>
+__global__ __launch_bounds__(256) void kl_sub_mark(T* __restrict__ D, int64_t stride,
+                                                   const int64_t* __restrict__ idx,
+                                                   const T* __restrict__ v, int64_t kstride,
+                                                   const int64_t* __restrict__ nnz,
+                                                   uint32_t* __restrict__ bits, int64_t words) {
   const int b = blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nnz[b]) return;
   const int64_t at = idx[(int64_t)b * kstride + e];
-  const int64_t i = at / n, j = at % n;
-  const T* u = U + (int64_t)b * sU + i * w;
-  const T* v = V + (int64_t)b * sV + j * w;
-  T s = T(0);
-  for (int c = 0; c < w; ++c) s += u[c] * v[c];
-  out[(int64_t)b * kstride + e] = s;
+  D[(int64_t)b * stride + at] -= v[(int64_t)b * kstride + e];
+  atomicOr(&bits[(int64_t)b * words + (at >> 5)], 1u << (unsigned)(at & 31));
 }
 
-// Copy a panel (rows x r, ld r) into columns [c0, c0 + r) of a rows x w panel.
+// Copy panel P0 (rows x r, ld r) into columns [c0, c0 + r) of a rows x w
+// panel, and P1 (when given) into columns [c0 + r, c0 + 2r).
 template <typename T>
-__global__ __launch_bounds__(256) void kl_put_cols(const T* __restrict__ P, int64_t sP, int r,
+__global__ __launch_bounds__(256) void kl_put_cols(const T* __restrict__ P0,
+                                                   const T* __restrict__ P1, int64_t sP, int r,
                                                    T* __restrict__ O, int64_t sO, int w, int c0,
                                                    int64_t rows) {
   const int b = blockIdx.y;
@@ -169,7 +369,9 @@ __global__ __launch_bounds__(256) void kl_put_cols(const T* __restrict__ P, int6
   if (e >= rows * r) return;
   const int64_t i = e / r;
   const int c = (int)(e % r);
-  O[(int64_t)b * sO + i * w + c0 + c] = P[(int64_t)b * sP + e];
+  T* o = O + (int64_t)b * sO + i * w + c0 + c;
+  o[0] = P0[(int64_t)b * sP + e];
+  if (P1) o[r] = P1[(int64_t)b * sP + e];
 }
 
 // Y += X (count entries per problem).
@@ -190,87 +392,111 @@ __global__ __launch_bounds__(256) void kl_cast_a1(const double* __restrict__ A1,
 }
 
 // ---------------------------------------------------------------------------
-// r x r FP64 algebra, one thread per problem (r <= 8).
+// r x r FP64 algebra, one thread per problem (r <= 8).  The rank R is a
+// template argument so that every loop unrolls and the matrices stay in
+// registers.
 // ---------------------------------------------------------------------------
-constexpr int LR = 8;
 
 // Cholesky QR factor: Gram = R^T R; Rinv (T), and Rcum_out = R Rcum_in (FP64;
 // also as T when rout_t is given).  flag set when a pivot is not positive.
-template <typename T>
-__global__ void ks_chol(int nb, int r, const T* __restrict__ gram, const double* __restrict__ rin,
+template <typename T, int R>
+__global__ __launch_bounds__(64) void ks_chol(int nb, const T* __restrict__ gram, const double* __restrict__ rin,
                         T* __restrict__ rinv, double* __restrict__ rout, T* __restrict__ rout_t,
                         int* __restrict__ flag) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  const int E = r * r;
-  double G[LR][LR], R[LR][LR], Ri[LR][LR];
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
-      G[i][j] = 0.5 * ((double)gram[b * E + i * r + j] + (double)gram[b * E + j * r + i]);
-      R[i][j] = 0.0;
-      Ri[i][j] = 0.0;
+  constexpr int E = R * R;
+  double G[R][R], U[R][R], Ui[R][R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      G[i][j] = 0.5 * ((double)gram[b * E + i * R + j] + (double)gram[b * E + j * R + i]);
+      U[i][j] = 0.0;
+      Ui[i][j] = 0.0;
     }
-  for (int j = 0; j < r; ++j) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
     double d = G[j][j];
-    for (int l = 0; l < j; ++l) d -= R[l][j] * R[l][j];
+#pragma unroll
+    for (int l = 0; l < j; ++l) d -= U[l][j] * U[l][j];
     if (!(d > 0.0)) { atomicOr(flag, 1); d = 1e-300; }
-    R[j][j] = sqrt(d);
-    for (int c = j + 1; c < r; ++c) {
+    U[j][j] = sqrt(d);
+#pragma unroll
+    for (int c = j + 1; c < R; ++c) {
       double s = G[j][c];
-      for (int l = 0; l < j; ++l) s -= R[l][j] * R[l][c];
-      R[j][c] = s / R[j][j];
+#pragma unroll
+      for (int l = 0; l < j; ++l) s -= U[l][j] * U[l][c];
+      U[j][c] = s / U[j][j];
     }
   }
   // upper-triangular inverse
-  for (int j = r - 1; j >= 0; --j) {
-    Ri[j][j] = 1.0 / R[j][j];
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {
+    Ui[j][j] = 1.0 / U[j][j];
+#pragma unroll
     for (int i = j - 1; i >= 0; --i) {
       double s = 0.0;
-      for (int l = i + 1; l <= j; ++l) s += R[i][l] * Ri[l][j];
-      Ri[i][j] = -s / R[i][i];
+#pragma unroll
+      for (int l = i + 1; l <= j; ++l) s += U[i][l] * Ui[l][j];
+      Ui[i][j] = -s / U[i][i];
     }
   }
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
-      rinv[b * E + i * r + j] = (T)Ri[i][j];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      rinv[b * E + i * R + j] = (T)Ui[i][j];
       double s = 0.0;
-      for (int l = 0; l < r; ++l) s += R[i][l] * rin[b * E + l * r + j];
-      rout[b * E + i * r + j] = s;
-      if (rout_t) rout_t[b * E + i * r + j] = (T)s;
+#pragma unroll
+      for (int l = 0; l < R; ++l) s += U[i][l] * rin[b * E + l * R + j];
+      rout[b * E + i * R + j] = s;
+      if (rout_t) rout_t[b * E + i * R + j] = (T)s;
     }
 }
 
-__device__ void jacobi_sym(double (&A)[LR][LR], double (&V)[LR][LR], int r) {
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+template <int R>
+__device__ void jacobi_sym(double (&A)[R][R], double (&V)[R][R]) {
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) V[i][j] = i == j ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int i = 0; i < r; ++i) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
       dia += A[i][i] * A[i][i];
-      for (int j = i + 1; j < r; ++j) off += A[i][j] * A[i][j];
+#pragma unroll
+      for (int j = i + 1; j < R; ++j) off += A[i][j] * A[i][j];
     }
     if (off <= 1e-32 * dia) break;
-    for (int p = 0; p < r; ++p)
-      for (int q = p + 1; q < r; ++q) {
+#pragma unroll
+    for (int p = 0; p < R; ++p)
+#pragma unroll
+      for (int q = p + 1; q < R; ++q) {
         const double apq = A[p][q];
-        if (apq == 0.0) continue;
-        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < r; ++k) {
-          const double akp = A[k][p], akq = A[k][q];
-          A[k][p] = c * akp - s * akq;
-          A[k][q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < r; ++k) {
-          const double apk = A[p][k], aqk = A[q][k];
-          A[p][k] = c * apk - s * aqk;
-          A[q][k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < r; ++k) {
-          const double vkp = V[k][p], vkq = V[k][q];
-          V[k][p] = c * vkp - s * vkq;
-          V[k][q] = s * vkp + c * vkq;
+        if (apq != 0.0) {
+          const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double akp = A[k][p], akq = A[k][q];
+            A[k][p] = c * akp - s * akq;
+            A[k][q] = s * akp + c * akq;
+          }
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double apk = A[p][k], aqk = A[q][k];
+            A[p][k] = c * apk - s * aqk;
+            A[q][k] = s * apk + c * aqk;
+          }
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double vkp = V[k][p], vkq = V[k][q];
+            V[k][p] = c * vkp - s * vkq;
+            V[k][q] = s * vkp + c * vkq;
+          }
         }
       }
   }
@@ -278,93 +504,119 @@ __device__ void jacobi_sym(double (&A)[LR][LR], double (&V)[LR][LR], int r) {
 
 // C = V diag(lam) V^T:  C^a (T), and the Daleckii-Krein weights
 // F_ij = (lam_i^a - lam_j^a) / (lam_i - lam_j)  (a lam^(a-1) when equal).
-template <typename T>
-__global__ void ks_eig(int nb, int r, const T* __restrict__ cmat, double a,
-                       T* __restrict__ calpha, double* __restrict__ vout,
-                       double* __restrict__ fout, int* __restrict__ flag) {
+template <typename T, int R>
+__global__ __launch_bounds__(64) void ks_eig(int nb, const T* __restrict__ cmat, double a, T* __restrict__ calpha,
+                       double* __restrict__ vout, double* __restrict__ fout,
+                       int* __restrict__ flag) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  const int E = r * r;
-  double A[LR][LR], V[LR][LR];
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j)
-      A[i][j] = 0.5 * ((double)cmat[b * E + i * r + j] + (double)cmat[b * E + j * r + i]);
-  jacobi_sym(A, V, r);
-  double lam[LR], la[LR];
-  for (int i = 0; i < r; ++i) {
+  constexpr int E = R * R;
+  double A[R][R], V[R][R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      A[i][j] = 0.5 * ((double)cmat[b * E + i * R + j] + (double)cmat[b * E + j * R + i]);
+  jacobi_sym<R>(A, V);
+  double lam[R], la[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
     lam[i] = A[i][i];
     if (!(lam[i] > 0.0)) { atomicOr(flag, 2); lam[i] = 1e-300; }
     la[i] = pow(lam[i], a);
   }
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
       double s = 0.0;
-      for (int l = 0; l < r; ++l) s += V[i][l] * la[l] * V[j][l];
-      calpha[b * E + i * r + j] = (T)s;
-      vout[b * E + i * r + j] = V[i][j];
+#pragma unroll
+      for (int l = 0; l < R; ++l) s += V[i][l] * la[l] * V[j][l];
+      calpha[b * E + i * R + j] = (T)s;
+      vout[b * E + i * R + j] = V[i][j];
       const double d = lam[i] - lam[j];
-      fout[b * E + i * r + j] =
+      fout[b * E + i * R + j] =
           fabs(d) > 1e-12 * fmax(lam[i], lam[j]) ? (la[i] - la[j]) / d
                                                   : a * pow(0.5 * (lam[i] + lam[j]), a - 1.0);
     }
 }
 
 // S2 = 2 Cbar with Cbar = V (F o (V^T sym(Cbar_a) V)) V^T  (Daleckii-Krein).
-template <typename T>
-__global__ void ks_dk(int nb, int r, const T* __restrict__ cbar_a, const double* __restrict__ vin,
+template <typename T, int R>
+__global__ __launch_bounds__(64) void ks_dk(int nb, const T* __restrict__ cbar_a, const double* __restrict__ vin,
                       const double* __restrict__ fin, T* __restrict__ s2) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  const int E = r * r;
-  double S[LR][LR], V[LR][LR], M[LR][LR], N[LR][LR];
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
-      S[i][j] = 0.5 * ((double)cbar_a[b * E + i * r + j] + (double)cbar_a[b * E + j * r + i]);
-      V[i][j] = vin[b * E + i * r + j];
+  constexpr int E = R * R;
+  double S[R][R], V[R][R], M[R][R], N[R][R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      S[i][j] = 0.5 * ((double)cbar_a[b * E + i * R + j] + (double)cbar_a[b * E + j * R + i]);
+      V[i][j] = vin[b * E + i * R + j];
     }
-  for (int i = 0; i < r; ++i)           // M = V^T S V
-    for (int j = 0; j < r; ++j) {
+#pragma unroll
+  for (int i = 0; i < R; ++i)           // M = V^T S V
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
       double s = 0.0;
-      for (int k = 0; k < r; ++k)
-        for (int l = 0; l < r; ++l) s += V[k][i] * S[k][l] * V[l][j];
-      M[i][j] = s * fin[b * E + i * r + j];
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int l = 0; l < R; ++l) s += V[k][i] * S[k][l] * V[l][j];
+      M[i][j] = s * fin[b * E + i * R + j];
     }
-  for (int i = 0; i < r; ++i)           // N = V M V^T
-    for (int j = 0; j < r; ++j) {
+#pragma unroll
+  for (int i = 0; i < R; ++i)           // N = V M V^T
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
       double s = 0.0;
-      for (int k = 0; k < r; ++k)
-        for (int l = 0; l < r; ++l) s += V[i][k] * M[k][l] * V[j][l];
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int l = 0; l < R; ++l) s += V[i][k] * M[k][l] * V[j][l];
       N[i][j] = s;
     }
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) s2[b * E + i * r + j] = (T)(N[i][j] + N[j][i]);
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) s2[b * E + i * R + j] = (T)(N[i][j] + N[j][i]);
 }
 
 // out = Rc Rtot^{-1} for upper-triangular FP64 Rc, Rtot (T output).  Both
 // are accumulated products of Cholesky factors, so their ratio stays well
 // scaled where each alone grows with powers of the spectrum.
-template <typename T>
-__global__ void ks_rrel(int nb, int r, const double* __restrict__ rc,
-                        const double* __restrict__ rtot, T* __restrict__ out) {
+template <typename T, int R>
+__global__ __launch_bounds__(64) void ks_rrel(int nb, const double* __restrict__ rc, const double* __restrict__ rtot,
+                        T* __restrict__ out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  const int E = r * r;
-  double R[LR][LR], Ri[LR][LR];
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) { R[i][j] = rtot[b * E + i * r + j]; Ri[i][j] = 0.0; }
-  for (int j = r - 1; j >= 0; --j) {
-    Ri[j][j] = 1.0 / R[j][j];
+  constexpr int E = R * R;
+  double U[R][R], Ui[R][R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) { U[i][j] = rtot[b * E + i * R + j]; Ui[i][j] = 0.0; }
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {
+    Ui[j][j] = 1.0 / U[j][j];
+#pragma unroll
     for (int i = j - 1; i >= 0; --i) {
       double s = 0.0;
-      for (int l = i + 1; l <= j; ++l) s += R[i][l] * Ri[l][j];
-      Ri[i][j] = -s / R[i][i];
+#pragma unroll
+      for (int l = i + 1; l <= j; ++l) s += U[i][l] * Ui[l][j];
+      Ui[i][j] = -s / U[i][i];
     }
   }
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
       double s = 0.0;
-      for (int l = 0; l < r; ++l) s += rc[b * E + i * r + l] * Ri[l][j];
-      out[b * E + i * r + j] = (T)s;
+#pragma unroll
+      for (int l = 0; l < R; ++l) s += rc[b * E + i * R + l] * Ui[l][j];
+      out[b * E + i * R + j] = (T)s;
     }
 }
 
@@ -379,7 +631,8 @@ __global__ void ks_identity(int nb, int r, double* __restrict__ out) {
 // Tall-skinny products (the panel passes of the backward).
 //
 // kl_ts_nn: C[b] = alpha A[b] B[b] + beta C[b] with A M x K (row-major, one
-// thread per row) and B K x NC (NC <= 8, K <= kTsMaxK) staged in LDS.
+// thread per row) and B K x NC (NC <= 8, K <= kTsMaxK, row stride ldb) staged
+// in LDS; column j of the product uses column (j + rot) mod NC of B.
 // kl_ts_tn: the K-chunk partials of A[b]^T B[b] with A stored K x M (one
 // thread per column of A, rows of the chunk read coalesced) and B K x NC;
 // kl_ts_reduce adds the chunks in order.
@@ -390,12 +643,16 @@ constexpr int kTsChunk = 256;
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void kl_ts_nn(int M, int K, const T* __restrict__ A,
                                                 int64_t lda, int64_t sA, const T* __restrict__ B,
-                                                int64_t sB, T alpha, T beta, T* __restrict__ C,
-                                                int64_t ldc, int64_t sC) {
+                                                int64_t ldb, int64_t sB, int rot, T alpha,
+                                                T beta, T* __restrict__ C, int64_t ldc,
+                                                int64_t sC) {
   __shared__ T bs[kTsMaxK * NC];
   const int b = blockIdx.y, tid = threadIdx.x;
   const T* Bb = B + (int64_t)b * sB;
-  for (int e = tid; e < K * NC; e += 256) bs[e] = Bb[e];
+  for (int e = tid; e < K * NC; e += 256) {
+    const int k = e / NC, j = e % NC;
+    bs[e] = Bb[(int64_t)k * ldb + (j + rot) % NC];
+  }
   __syncthreads();
   const int i = blockIdx.x * 256 + tid;
   if (i >= M) return;
@@ -414,13 +671,13 @@ __global__ __launch_bounds__(256) void kl_ts_nn(int M, int K, const T* __restric
 }
 
 template <typename T, int NC>
-__global__ __launch_bounds__(256) void kl_ts_tn(int M, int K, const T* __restrict__ A,
+__global__ __launch_bounds__(256) void kl_ts_tn(int M, int K, int chunk, const T* __restrict__ A,
                                                 int64_t lda, int64_t sA, const T* __restrict__ B,
                                                 int64_t sB, T* __restrict__ part) {
   __shared__ T bs[kTsChunk * NC];
   const int b = blockIdx.z, ch = blockIdx.y, tid = threadIdx.x;
-  const int k0 = ch * kTsChunk;
-  const int kn = (K - k0) < kTsChunk ? (K - k0) : kTsChunk;
+  const int k0 = ch * chunk;
+  const int kn = (K - k0) < chunk ? (K - k0) : chunk;
   const T* Bb = B + (int64_t)b * sB + (int64_t)k0 * NC;
   for (int e = tid; e < kn * NC; e += 256) bs[e] = Bb[e];
   __syncthreads();
@@ -448,10 +705,83 @@ __global__ __launch_bounds__(256) void kl_ts_reduce(int M, int NC, int nch,
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)M * NC) return;
   T s = T(0);
-  for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)b * nch + ch) * M * NC + e];
+  const T* pe = part + (int64_t)b * nch * M * NC + e;
+  const int64_t st = (int64_t)M * NC;
+  int ch = 0;
+  for (; ch + 8 <= nch; ch += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pe[(ch + u) * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; ch < nch; ++ch) s += pe[ch * st];
   const int64_t i = e / NC, j = e % NC;
   T* c = C + (int64_t)b * sC + i * ldc + j;
   *c = alpha * s + (beta != T(0) ? beta * *c : T(0));
+}
+
+// kl_inner: C[b] = alpha P[b]^T P2[b] for two NC-column panels of `rows` rows
+// (ld NC), one block per chunk of kInnerRows rows; each thread sums its rows,
+// the wave sums go through fixed-order lane exchanges, then the four waves
+// add in order.  With one chunk the block writes C; otherwise it writes its
+// chunk's partial for kl_ts_reduce.
+constexpr int kInnerRows = 4096;
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void kl_inner(int rows, const T* __restrict__ P,
+                                                int64_t sP, const T* __restrict__ P2,
+                                                int64_t sP2, T alpha, T beta,
+                                                T* __restrict__ C, int64_t ldc, int64_t sC,
+                                                T* __restrict__ part) {
+  __shared__ T red[4][NC * NC];
+  const int b = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+  const int r0 = ch * kInnerRows;
+  const int r1 = (rows - r0) < kInnerRows ? rows : r0 + kInnerRows;
+  const T* pb = P + (int64_t)b * sP;
+  const T* qb = P2 + (int64_t)b * sP2;
+  T acc[NC][NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[i][j] = T(0);
+  for (int row = r0 + tid; row < r1; row += 256) {
+    T x[NC], y[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      x[i] = pb[(int64_t)row * NC + i];
+      y[i] = qb[(int64_t)row * NC + i];
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[i][j] += x[i] * y[j];
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      T v = acc[i][j];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[i][j] = v;
+    }
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) red[wave][i * NC + j] = acc[i][j];
+  }
+  __syncthreads();
+  if (tid >= NC * NC) return;
+  const T s = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+  if (gridDim.x == 1) {
+    T* c = C + (int64_t)b * sC + (tid / NC) * ldc + tid % NC;
+    *c = alpha * s + (beta != T(0) ? beta * *c : T(0));
+  } else {
+    part[((int64_t)b * gridDim.x + ch) * NC * NC + tid] = s;
+  }
 }
 
 #define GODEC_NC_SWITCH(nc, ...)                              \
@@ -474,18 +804,41 @@ template <typename T>
 void lk_gemm_t(const Launch& L, int nb, int M, int N, int K, const T* A, int64_t lda,
                int64_t sA, int ta, const T* B, int64_t ldb, int64_t sB, int tb, T alpha, T beta,
                T* C, int64_t ldc, int64_t sC, T* part, int64_t part_cap) {
+  // r x r inner products of two panels
+  if (ta && !tb && M <= 8 && N == M && lda == M && ldb == N) {
+    const int nch = (K + kInnerRows - 1) / kInnerRows;
+    if (nch == 1 || (int64_t)nb * nch * M * N <= part_cap) {
+      const dim3 grid((unsigned)std::max(nch, 1), (unsigned)nb);
+      GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_inner<T, NC>), grid, dim3(256), 0, L.stream, K,
+                                            A, sA, B, sB, alpha, beta, C, ldc, sC, part));
+      if (nch > 1) {
+        const dim3 g2((unsigned)((M * N + 255) / 256), (unsigned)nb);
+        hipLaunchKernelGGL(kl_ts_reduce<T>, g2, dim3(256), 0, L.stream, M, N, nch,
+                           (const T*)part, alpha, beta, C, ldc, sC);
+      }
+      return;
+    }
+  }
   // tall-skinny cases: a long panel times a small N-column one
   if (!ta && !tb && N <= 8 && K <= kTsMaxK && ldb == N && M >= 256) {
     const dim3 grid((unsigned)((M + 255) / 256), (unsigned)nb);
     GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_ts_nn<T, NC>), grid, dim3(256), 0, L.stream, M, K,
-                                          A, lda, sA, B, sB, alpha, beta, C, ldc, sC));
+                                          A, lda, sA, B, ldb, sB, 0, alpha, beta, C, ldc, sC));
     return;
   }
-  const int nch_ts = (K + kTsChunk - 1) / kTsChunk;
+  // K chunks of kTsChunk rows, halved (down to 32) while the launch has
+  // fewer than four blocks per compute unit and the partials fit
+  int chunk = kTsChunk;
+  const int64_t mb = (M + 255) / 256;
+  auto nch_of = [&](int c) { return (K + c - 1) / c; };
+  while (chunk > 32 && nb * mb * nch_of(chunk) < 4 * (int64_t)L.num_cu &&
+         (int64_t)nb * nch_of(chunk / 2) * M * N <= part_cap)
+    chunk /= 2;
+  const int nch_ts = nch_of(chunk);
   if (ta && !tb && N <= 8 && ldb == N && M >= 64 && (int64_t)nb * nch_ts * M * N <= part_cap) {
-    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)nch_ts, (unsigned)nb);
+    const dim3 grid((unsigned)mb, (unsigned)nch_ts, (unsigned)nb);
     GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_ts_tn<T, NC>), grid, dim3(256), 0, L.stream, M, K,
-                                          A, lda, sA, B, sB, part));
+                                          chunk, A, lda, sA, B, sB, part));
     const dim3 g2((unsigned)(((int64_t)M * N + 255) / 256), (unsigned)nb);
     hipLaunchKernelGGL(kl_ts_reduce<T>, g2, dim3(256), 0, L.stream, M, N, nch_ts, (const T*)part,
                        alpha, beta, C, ldc, sC);
@@ -556,25 +909,80 @@ void lk_gather(const Launch& L, bool f64, int nb, const void* G, int64_t stride,
                        idx, kstride, nnz, (float*)out);
 }
 
-void lk_lowrank_at(const Launch& L, bool f64, int nb, const void* U, int64_t sU, const void* V,
-                   int64_t sV, int w, int64_t n, const int64_t* idx, int64_t kstride, int64_t kmax,
-                   const int64_t* nnz, void* out) {
+void lk_rebuild_d(const Launch& L, bool f64, int nb, const void* X, void* D, int64_t count,
+                  uint32_t* bits, int64_t words) {
+  const int64_t vw = f64 ? 2 : 4;
+  const bool vec = count % vw == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)D % 16 == 0;
+  const int64_t th = std::max<int64_t>(vec ? count / vw : count, bits ? words : 0);
   if (f64)
-    hipLaunchKernelGGL(kl_lowrank_at<double>, g1(kmax, nb), dim3(256), 0, L.stream, (const double*)U, sU,
-                       (const double*)V, sV, w, n, idx, kstride, nnz, (double*)out);
+    hipLaunchKernelGGL(kl_rebuild_d<double>, g1(th, nb), dim3(256), 0, L.stream,
+                       (const double*)X, (double*)D, count, (int)vec, bits, words);
   else
-    hipLaunchKernelGGL(kl_lowrank_at<float>, g1(kmax, nb), dim3(256), 0, L.stream, (const float*)U, sU,
-                       (const float*)V, sV, w, n, idx, kstride, nnz, (float*)out);
+    hipLaunchKernelGGL(kl_rebuild_d<float>, g1(th, nb), dim3(256), 0, L.stream, (const float*)X,
+                       (float*)D, count, (int)vec, bits, words);
 }
 
-void lk_put_cols(const Launch& L, bool f64, int nb, const void* P, int64_t sP, int r, void* O,
-                 int64_t sO, int w, int c0, int64_t rows) {
+void lk_sub_mark(const Launch& L, bool f64, int nb, void* D, int64_t stride, const int64_t* idx,
+                 const void* v, int64_t kstride, int64_t kmax, const int64_t* nnz,
+                 uint32_t* bits, int64_t words) {
   if (f64)
-    hipLaunchKernelGGL(kl_put_cols<double>, g1(rows * r, nb), dim3(256), 0, L.stream, (const double*)P, sP,
-                       r, (double*)O, sO, w, c0, rows);
+    hipLaunchKernelGGL(kl_sub_mark<double>, g1(kmax, nb), dim3(256), 0, L.stream, (double*)D,
+                       stride, idx, (const double*)v, kstride, nnz, bits, words);
   else
-    hipLaunchKernelGGL(kl_put_cols<float>, g1(rows * r, nb), dim3(256), 0, L.stream, (const float*)P, sP,
-                       r, (float*)O, sO, w, c0, rows);
+    hipLaunchKernelGGL(kl_sub_mark<float>, g1(kmax, nb), dim3(256), 0, L.stream, (float*)D,
+                       stride, idx, (const float*)v, kstride, nnz, bits, words);
+}
+
+bool lk_dmul_rot(const Launch& L, bool f64, int nb, int M, int N, int K, const void* A,
+                 int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB, int rot,
+                 void* C, int64_t ldc, int64_t sC) {
+  if (N > 8 || K > kTsMaxK || M < 256) return false;
+  const dim3 grid((unsigned)((M + 255) / 256), (unsigned)nb);
+  if (f64) {
+    GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_ts_nn<double, NC>), grid, dim3(256), 0, L.stream,
+                                          M, K, (const double*)A, lda, sA, (const double*)B, ldb,
+                                          sB, rot, 1.0, 0.0, (double*)C, ldc, sC));
+  } else {
+    GODEC_NC_SWITCH(N, hipLaunchKernelGGL((kl_ts_nn<float, NC>), grid, dim3(256), 0, L.stream, M,
+                                          K, (const float*)A, lda, sA, (const float*)B, ldb, sB,
+                                          rot, 1.0f, 0.0f, (float*)C, ldc, sC));
+  }
+  return true;
+}
+
+void lk_uvt_update(const Launch& L, bool f64, int nb, int m, int n, int w, const void* U,
+                   int64_t sU, const void* V, int64_t sV, void* X, int64_t ldx, int64_t sX,
+                   int accumulate, const uint32_t* bits, int64_t wstride, void* Lbar,
+                   int64_t sL) {
+  constexpr int RB = 32;
+  if (f64) {
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + RB - 1) / RB), (unsigned)nb);
+    hipLaunchKernelGGL((kl_uvt_update<double, RB>), grid, dim3(256), 0, L.stream, m, n, w,
+                       (const double*)U, sU, (const double*)V, sV, (double*)X, ldx, sX,
+                       accumulate, bits, wstride, (double*)Lbar, sL);
+    return;
+  }
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + 63) / 64), (unsigned)nb);
+  const bool vec = w % 4 == 0 && (uintptr_t)U % 16 == 0 && (uintptr_t)V % 16 == 0 &&
+                   sU % 4 == 0 && sV % 4 == 0;
+  if (vec)
+    hipLaunchKernelGGL(kl_uvt_mfma<true>, grid, dim3(256), 0, L.stream, m, n, w, (const float*)U,
+                       sU, (const float*)V, sV, (float*)X, ldx, sX, accumulate, bits, wstride,
+                       (float*)Lbar, sL);
+  else
+    hipLaunchKernelGGL(kl_uvt_mfma<false>, grid, dim3(256), 0, L.stream, m, n, w,
+                       (const float*)U, sU, (const float*)V, sV, (float*)X, ldx, sX,
+                       accumulate, bits, wstride, (float*)Lbar, sL);
+}
+
+void lk_put_cols(const Launch& L, bool f64, int nb, const void* P0, const void* P1, int64_t sP,
+                 int r, void* O, int64_t sO, int w, int c0, int64_t rows) {
+  if (f64)
+    hipLaunchKernelGGL(kl_put_cols<double>, g1(rows * r, nb), dim3(256), 0, L.stream,
+                       (const double*)P0, (const double*)P1, sP, r, (double*)O, sO, w, c0, rows);
+  else
+    hipLaunchKernelGGL(kl_put_cols<float>, g1(rows * r, nb), dim3(256), 0, L.stream,
+                       (const float*)P0, (const float*)P1, sP, r, (float*)O, sO, w, c0, rows);
 }
 
 void lk_cast_a1(const Launch& L, bool f64, int nb, const double* A1, int64_t sA, void* P,
@@ -588,43 +996,51 @@ void lk_cast_a1(const Launch& L, bool f64, int nb, const double* A1, int64_t sA,
 void lk_chol(const Launch& L, bool f64, int nb, int r, const void* gram, const double* rin,
              void* rinv, double* rout, void* rout_t, int* flag) {
   const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64)
-    hipLaunchKernelGGL(ks_chol<double>, dim3(g), dim3(64), 0, L.stream, nb, r, (const double*)gram, rin,
-                       (double*)rinv, rout, (double*)rout_t, flag);
-  else
-    hipLaunchKernelGGL(ks_chol<float>, dim3(g), dim3(64), 0, L.stream, nb, r, (const float*)gram, rin,
-                       (float*)rinv, rout, (float*)rout_t, flag);
+  if (f64) {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_chol<double, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, (const double*)gram, rin, (double*)rinv, rout,
+                                          (double*)rout_t, flag));
+  } else {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_chol<float, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, (const float*)gram, rin, (float*)rinv, rout,
+                                          (float*)rout_t, flag));
+  }
 }
 
 void lk_eig(const Launch& L, bool f64, int nb, int r, const void* c, double a, void* calpha,
             double* v, double* f, int* flag) {
   const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64)
-    hipLaunchKernelGGL(ks_eig<double>, dim3(g), dim3(64), 0, L.stream, nb, r, (const double*)c, a,
-                       (double*)calpha, v, f, flag);
-  else
-    hipLaunchKernelGGL(ks_eig<float>, dim3(g), dim3(64), 0, L.stream, nb, r, (const float*)c, a,
-                       (float*)calpha, v, f, flag);
+  if (f64) {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_eig<double, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, (const double*)c, a, (double*)calpha, v, f, flag));
+  } else {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_eig<float, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, (const float*)c, a, (float*)calpha, v, f, flag));
+  }
 }
 
 void lk_dk(const Launch& L, bool f64, int nb, int r, const void* cbar_a, const double* v,
            const double* f, void* s2) {
   const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64)
-    hipLaunchKernelGGL(ks_dk<double>, dim3(g), dim3(64), 0, L.stream, nb, r, (const double*)cbar_a, v, f,
-                       (double*)s2);
-  else
-    hipLaunchKernelGGL(ks_dk<float>, dim3(g), dim3(64), 0, L.stream, nb, r, (const float*)cbar_a, v, f,
-                       (float*)s2);
+  if (f64) {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_dk<double, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, (const double*)cbar_a, v, f, (double*)s2));
+  } else {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_dk<float, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, (const float*)cbar_a, v, f, (float*)s2));
+  }
 }
 
 void lk_rrel(const Launch& L, bool f64, int nb, int r, const double* rc, const double* rtot,
              void* out) {
   const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64)
-    hipLaunchKernelGGL(ks_rrel<double>, dim3(g), dim3(64), 0, L.stream, nb, r, rc, rtot, (double*)out);
-  else
-    hipLaunchKernelGGL(ks_rrel<float>, dim3(g), dim3(64), 0, L.stream, nb, r, rc, rtot, (float*)out);
+  if (f64) {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_rrel<double, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, rc, rtot, (double*)out));
+  } else {
+    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_rrel<float, NC>), dim3(g), dim3(64), 0, L.stream,
+                                          nb, rc, rtot, (float*)out));
+  }
 }
 
 void lk_identity(const Launch& L, int nb, int r, double* out) {
