@@ -345,8 +345,6 @@ void lk_gemm(const Launch& L, bool f64, int nb, int M, int N, int K, const void*
 void lk_fill(const Launch& L, bool f64, int nb, void* P, int64_t count, int64_t stride, double v);
 void lk_copy(const Launch& L, bool f64, int nb, const void* S, void* D, int64_t count,
              int64_t stride);
-void lk_axpy(const Launch& L, bool f64, int nb, const void* X, void* Y, int64_t count,
-             int64_t stride);
 void lk_scatter(const Launch& L, bool f64, int nb, void* P, int64_t stride, const int64_t* idx,
                 const void* v, int64_t kstride, int64_t kmax, const int64_t* nnz, int mode,
                 double s);
@@ -385,16 +383,25 @@ void lk_uvt_update(const Launch& L, bool f64, int nb, int m, int n, int w, const
                    int64_t sL);
 void lk_put_cols(const Launch& L, bool f64, int nb, const void* P0, const void* P1, int64_t sP,
                  int r, void* O, int64_t sO, int w, int c0, int64_t rows);
-void lk_cast_a1(const Launch& L, bool f64, int nb, const double* A1, int64_t sA, void* P,
-                int64_t sP, int64_t count);
-void lk_chol(const Launch& L, bool f64, int nb, int r, const void* gram, const double* rin,
-             void* rinv, double* rout, void* rout_t, int* flag);
-void lk_eig(const Launch& L, bool f64, int nb, int r, const void* c, double a, void* calpha,
-            double* v, double* f, int* flag);
-void lk_dk(const Launch& L, bool f64, int nb, int r, const void* cbar_a, const double* v,
-           const double* f, void* s2);
-void lk_rrel(const Launch& L, bool f64, int nb, int r, const double* rc, const double* rtot,
-             void* out);
-void lk_identity(const Launch& L, int nb, int r, double* out);
+// Fused steps of the backward, one block per problem (k_lfuse.hip; r <= 8,
+// r-column panels row-major unless a row stride w is given):
+// Z_0 = A1, Rc_0 = I
+void lf_chain_init(const Launch& L, bool f64, int nb, int n, int r, const double* A1, void* Z0,
+                   double* rc0);
+// P^T P = U^T U, Z = P U^{-1}, rc_out = U rc_in; flag |= 1 on a bad pivot
+void lf_cholqr(const Launch& L, bool f64, int nb, int rows, int r, const void* P,
+               const double* rc_in, double* rc_out, void* Z, int* flag);
+// B^T B = V diag(lam) V^T: C^a, V and divided differences F; flag |= 2 if lam <= 0
+void lf_gram_eig(const Launch& L, bool f64, int nb, int rows, int r, const void* B, double a,
+                 void* calpha, double* v, double* f, int* flag);
+// Bbar = LQ C^a + B S2 (S2 from B^T LQ by Daleckii-Krein), also into Uf[:, 0:r]
+void lf_bbar(const Launch& L, bool f64, int nb, int m, int r, const void* B, const void* LQ,
+             const void* Ca, const double* v, const double* f, void* Bbar, void* Uf, int w);
+// Qbar = (LtB C^a + cur) projected off the range of Q
+void lf_qbar(const Launch& L, bool f64, int nb, int n, int r, const void* LtB, const void* Ca,
+             const void* cur, const void* Q, void* Qbar);
+// Vf[:, col:col+r] = Zj Rc Rtot^{-1}, Vf[:, col+r:col+2r] = cur
+void lf_pterm(const Launch& L, bool f64, int nb, int n, int r, const void* Zj, const double* rc,
+              const double* rtot, const void* cur, void* Vf, int w, int col);
 
 }  // namespace godec

@@ -53,8 +53,7 @@ struct godec_layer {
   void* Z = nullptr;     // (p + 1) x nb panels n x r: orthonormalised A^j A1
   double* Rc = nullptr;  // (p + 2) x nb r x r: accumulated Cholesky factors
   void* Qs = nullptr;    // (q + 1) x nb panels n x r: A^i Q (member 0 is Q)
-  void *Rinv = nullptr, *Gm = nullptr, *Cm = nullptr, *Ca = nullptr, *CbarA = nullptr;
-  void *S2 = nullptr, *T1 = nullptr, *Rrel = nullptr;
+  void* Ca = nullptr;  // nb x r x r: C^a
   double *Vv = nullptr, *F = nullptr;
   void *Wm2 = nullptr, *B = nullptr, *LQ = nullptr, *Bbar = nullptr;
   void *Vn = nullptr, *LtB = nullptr, *Qbar = nullptr, *Cur = nullptr, *Tn = nullptr;
@@ -95,8 +94,7 @@ size_t carve_layer(godec_layer* l, void* base, size_t ctx_ws, std::vector<void*>
   l->Z = cv.take(ts * (p + 1) * nb * nr);
   l->Rc = (double*)cv.take(sizeof(double) * (p + 2) * nb * E);
   l->Qs = cv.take(ts * (q + 1) * nb * nr);
-  void** small[] = {&l->Rinv, &l->Gm, &l->Cm, &l->Ca, &l->CbarA, &l->S2, &l->T1, &l->Rrel};
-  for (void** s : small) *s = cv.take(ts * nb * E);
+  l->Ca = cv.take(ts * nb * E);
   l->Vv = (double*)cv.take(sizeof(double) * nb * E);
   l->F = (double*)cv.take(sizeof(double) * nb * E);
   void** mpan[] = {&l->Wm2, &l->B, &l->LQ, &l->Bbar};
@@ -153,24 +151,11 @@ struct Ops {
     dmul(P, l->Wm2);
     dtmul(l->Wm2, out);
   }
-  // r x r: G = P^T P2 for panels with `rows` rows
-  void inner(const void* P, const void* P2, int64_t rows, void* G) {
-    const int r = l->r;
-    gemm(r, r, (int)rows, P, r, rows * r, 1, P2, r, rows * r, 0, 1.0, 0.0, G, r, (int64_t)r * r);
-  }
-  // out (rows x r) = alpha P M + beta out, M r x r
-  void panel_rr(const void* P, int64_t rows, const void* M, void* out, double alpha = 1.0,
-                double beta = 0.0) {
-    const int r = l->r;
-    gemm((int)rows, r, r, P, r, rows * r, 0, M, r, (int64_t)r * r, 0, alpha, beta, out, r,
-         rows * r);
-  }
   // columns [c0, c0 + r) of the rows x w factor O <- P0, and
   // [c0 + r, c0 + 2r) <- P1 when given
   void put(const void* P0, const void* P1, int64_t rows, void* O, int c0) {
     lk_put_cols(L, l->f64, l->nb, P0, P1, rows * l->r, l->r, O, rows * l->w, l->w, c0, rows);
   }
-  void copy(const void* S, void* D, int64_t count) { lk_copy(L, l->f64, l->nb, S, D, count, count); }
 };
 
 // Factors U (m x w), V (n x w) with D^bar = U V^T for the current D and L^bar.
@@ -188,54 +173,44 @@ void vjp_step(godec_layer* l, Ops& o) {
   // ---- forward panels of f at D ----
   // Z_0 = A1, Rc_0 = I; A Z_{j-1} = Z_j R_j, Rc_j = R_j Rc_{j-1}; so
   // A^j A1 = Z_j Rc_j.  A second Cholesky QR of Z_p gives Q, Rtot = Rc_{p+1}.
-  lk_cast_a1(L, f64, nb, l->A1, nr, Zj(0), nr, nr);
-  lk_identity(L, nb, r, Rcj(0));
+  lf_chain_init(L, f64, nb, (int)n, r, l->A1, Zj(0), Rcj(0));
   for (int j = 1; j <= p; ++j) {
     o.amul(Zj(j - 1), l->Vn);
-    o.inner(l->Vn, l->Vn, n, l->Gm);
-    lk_chol(L, f64, nb, r, l->Gm, Rcj(j - 1), l->Rinv, Rcj(j), nullptr, l->flag);
-    o.panel_rr(l->Vn, n, l->Rinv, Zj(j));
+    lf_cholqr(L, f64, nb, (int)n, r, l->Vn, Rcj(j - 1), Rcj(j), Zj(j), l->flag);
   }
-  o.inner(Zj(p), Zj(p), n, l->Gm);
-  lk_chol(L, f64, nb, r, l->Gm, Rcj(p), l->Rinv, Rcj(p + 1), nullptr, l->flag);
-  o.panel_rr(Zj(p), n, l->Rinv, Q);
+  lf_cholqr(L, f64, nb, (int)n, r, Zj(p), Rcj(p), Rcj(p + 1), Q, l->flag);
   for (int i = 1; i <= q; ++i) o.amul(Qsi(i - 1), Qsi(i));
   // B = D A^q Q, C = B^T B, C^a with a = -(p - 1) / (2p)
   o.dmul(Qsi(q), l->B);
-  o.inner(l->B, l->B, m, l->Cm);
-  lk_eig(L, f64, nb, r, l->Cm, -(double)(p - 1) / (2.0 * p), l->Ca, l->Vv, l->F, l->flag);
+  lf_gram_eig(L, f64, nb, (int)m, r, l->B, -(double)(p - 1) / (2.0 * p), l->Ca, l->Vv, l->F,
+              l->flag);
 
   // ---- adjoint of L = B C^a Q^T ----
   if (!lk_dpass(L, f64, nb, (int)m, (int)n, r, l->Lbar, false, Q, r, nr, l->LQ, r, m * r, nullptr,
                 l->part, l->part_cap))
     o.gemm((int)m, r, (int)n, l->Lbar, n, m * n, 0, Q, r, nr, 0, 1.0, 0.0, l->LQ, r, m * r);
   o.gemm((int)n, r, (int)m, l->Lbar, n, m * n, 1, l->B, r, m * r, 0, 1.0, 0.0, l->LtB, r, nr);
-  o.inner(l->B, l->LQ, m, l->CbarA);                 // C^a bar = B^T L^bar Q
-  lk_dk(L, f64, nb, r, l->CbarA, l->Vv, l->F, l->S2);  // B^T B adjoint, both sides
-  o.panel_rr(l->LQ, m, l->Ca, l->Bbar);               // B^bar = L^bar Q C^a + B S2
-  o.panel_rr(l->B, m, l->S2, l->Bbar, 1.0, 1.0);
-  o.panel_rr(l->LtB, n, l->Ca, l->Qbar);              // Q^bar = L^bar^T B C^a
-
-  // D^bar terms, each a rank-r outer product appended to (U, V).
+  // B^bar = L^bar Q C^a + B S2 (S2 from C^a bar = B^T L^bar Q), stored also as
+  // the first rank term: B = D (A^q Q) gives B^bar (A^q Q)^T.
+  const int64_t w = l->w;
+  lf_bbar(L, f64, nb, (int)m, r, l->B, l->LQ, l->Ca, l->Vv, l->F, l->Bbar, l->Uf, (int)w);
   int col = 0;
-  o.put(l->Bbar, nullptr, m, l->Uf, col);             // B = D (A^q Q): B^bar (A^q Q)^T
   o.put(Qsi(q), nullptr, n, l->Vf, col);
   col += r;
   // dA = dD^T D + D^T dD turns <G, dA> with G = U W^T into D^bar terms
-  // (D U) W^T + (D W) U^T.
-  // The pair takes columns [col, col + 2r) of both factors: V gets (W, U) and
-  // U gets (D U, D W), which is D times V's block with its halves swapped
-  // (one pass over D when the panel kernel takes it).
-  const int64_t w = l->w;
-  // With AU given, the same pass over D also forms AU = A U.
-  auto add_term = [&](const void* U, const void* W, void* AU) {
-    o.put(W, U, n, l->Vf, col);
+  // (D U) W^T + (D W) U^T.  A pair takes columns [col, col + 2r) of both
+  // factors: V holds (W, U) (written before the call) and U gets (D U, D W),
+  // which is D times V's block with its halves swapped; with AU given the
+  // same pass over D also forms AU = A U.
+  auto add_term = [&](const void* U, void* AU) {
     if (!lk_dpass(L, f64, nb, (int)m, (int)n, r, l->D, true, at(l->Vf, ts, col), w, n * w,
                   at(l->Uf, ts, col), w, m * w, AU, l->part, l->part_cap)) {
       if (!lk_dmul_rot(L, f64, nb, (int)m, 2 * r, (int)n, l->D, n, m * n, at(l->Vf, ts, col), w,
                        n * w, r, at(l->Uf, ts, col), w, m * w)) {
-        o.dmul(U, at(l->Uf, ts, col), w, m * w);
-        o.dmul(W, at(l->Uf, ts, col + r), w, m * w);
+        o.gemm((int)m, r, (int)n, l->D, n, m * n, 0, at(l->Vf, ts, col + r), w, n * w, 0, 1.0,
+               0.0, at(l->Uf, ts, col), w, m * w);
+        o.gemm((int)m, r, (int)n, l->D, n, m * n, 0, at(l->Vf, ts, col), w, n * w, 0, 1.0, 0.0,
+               at(l->Uf, ts, col + r), w, m * w);
       }
       if (AU) o.amul(U, AU);
     }
@@ -246,14 +221,13 @@ void vjp_step(godec_layer* l, Ops& o) {
   void* spare = l->Tn;
   o.dtmul(l->Bbar, cur);
   for (int i = 0; i < q; ++i) {
-    add_term(cur, Qsi(q - 1 - i), spare);
+    o.put(Qsi(q - 1 - i), cur, n, l->Vf, col);
+    add_term(cur, spare);
     std::swap(cur, spare);
   }
-  lk_axpy(L, f64, nb, cur, l->Qbar, nr, nr);
-  // Q = orth(Y), Y = A^p A1 = Q Rtot; f depends on the range of Q only, so
-  // Y^bar = (I - Q Q^T) Q^bar Rtot^{-T}.
-  o.inner(Q, l->Qbar, n, l->T1);
-  o.panel_rr(Q, n, l->T1, l->Qbar, -1.0, 1.0);         // Qbar <- (I - Q Q^T) Qbar
+  // Q^bar = L^bar^T B C^a + A^q D^T B^bar.  Q = orth(Y), Y = A^p A1 = Q Rtot;
+  // f depends on the range of Q only, so Y^bar = (I - Q Q^T) Q^bar Rtot^{-T}.
+  lf_qbar(L, f64, nb, (int)n, r, l->LtB, l->Ca, cur, Q, l->Qbar);
   // Terms of A^p: (A^i Y^bar, A^{p-1-i} A1).  With A^j A1 = Z_j Rc_j they are
   // (A^i Ybar0) (Z_j Rc_j Rtot^{-1})^T, Ybar0 = (I - Q Q^T) Q^bar, which keeps
   // every factor well scaled.
@@ -261,10 +235,9 @@ void vjp_step(godec_layer* l, Ops& o) {
   spare = l->Vn;
   for (int i = 0; i < p; ++i) {
     const int j = p - 1 - i;
-    lk_rrel(L, f64, nb, r, Rcj(j), Rcj(p + 1), l->Rrel);
-    o.panel_rr(Zj(j), n, l->Rrel, l->Tn);
+    lf_pterm(L, f64, nb, (int)n, r, Zj(j), Rcj(j), Rcj(p + 1), cur, l->Vf, (int)w, col);
     const bool more = i + 1 < p;
-    add_term(cur, l->Tn, more ? spare : nullptr);
+    add_term(cur, more ? spare : nullptr);
     if (more) std::swap(cur, spare);
   }
 }

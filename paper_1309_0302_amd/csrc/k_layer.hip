@@ -374,258 +374,6 @@ __global__ __launch_bounds__(256) void kl_put_cols(const T* __restrict__ P0,
   if (P1) o[r] = P1[(int64_t)b * sP + e];
 }
 
-// Y += X (count entries per problem).
-template <typename T>
-__global__ __launch_bounds__(256) void kl_axpy(const T* __restrict__ X, T* __restrict__ Y,
-                                               int64_t count, int64_t stride) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < count) Y[(int64_t)blockIdx.y * stride + e] += X[(int64_t)blockIdx.y * stride + e];
-}
-
-// A1 (FP64, n x r) -> panel of type T.
-template <typename T>
-__global__ __launch_bounds__(256) void kl_cast_a1(const double* __restrict__ A1, int64_t sA,
-                                                  T* __restrict__ P, int64_t sP, int64_t count) {
-  const int b = blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < count) P[(int64_t)b * sP + e] = (T)A1[(int64_t)b * sA + e];
-}
-
-// ---------------------------------------------------------------------------
-// r x r FP64 algebra, one thread per problem (r <= 8).  The rank R is a
-// template argument so that every loop unrolls and the matrices stay in
-// registers.
-// ---------------------------------------------------------------------------
-
-// Cholesky QR factor: Gram = R^T R; Rinv (T), and Rcum_out = R Rcum_in (FP64;
-// also as T when rout_t is given).  flag set when a pivot is not positive.
-template <typename T, int R>
-__global__ __launch_bounds__(64) void ks_chol(int nb, const T* __restrict__ gram, const double* __restrict__ rin,
-                        T* __restrict__ rinv, double* __restrict__ rout, T* __restrict__ rout_t,
-                        int* __restrict__ flag) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  constexpr int E = R * R;
-  double G[R][R], U[R][R], Ui[R][R];
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      G[i][j] = 0.5 * ((double)gram[b * E + i * R + j] + (double)gram[b * E + j * R + i]);
-      U[i][j] = 0.0;
-      Ui[i][j] = 0.0;
-    }
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    double d = G[j][j];
-#pragma unroll
-    for (int l = 0; l < j; ++l) d -= U[l][j] * U[l][j];
-    if (!(d > 0.0)) { atomicOr(flag, 1); d = 1e-300; }
-    U[j][j] = sqrt(d);
-#pragma unroll
-    for (int c = j + 1; c < R; ++c) {
-      double s = G[j][c];
-#pragma unroll
-      for (int l = 0; l < j; ++l) s -= U[l][j] * U[l][c];
-      U[j][c] = s / U[j][j];
-    }
-  }
-  // upper-triangular inverse
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j) {
-    Ui[j][j] = 1.0 / U[j][j];
-#pragma unroll
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-#pragma unroll
-      for (int l = i + 1; l <= j; ++l) s += U[i][l] * Ui[l][j];
-      Ui[i][j] = -s / U[i][i];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      rinv[b * E + i * R + j] = (T)Ui[i][j];
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < R; ++l) s += U[i][l] * rin[b * E + l * R + j];
-      rout[b * E + i * R + j] = s;
-      if (rout_t) rout_t[b * E + i * R + j] = (T)s;
-    }
-}
-
-template <int R>
-__device__ void jacobi_sym(double (&A)[R][R], double (&V)[R][R]) {
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) V[i][j] = i == j ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      dia += A[i][i] * A[i][i];
-#pragma unroll
-      for (int j = i + 1; j < R; ++j) off += A[i][j] * A[i][j];
-    }
-    if (off <= 1e-32 * dia) break;
-#pragma unroll
-    for (int p = 0; p < R; ++p)
-#pragma unroll
-      for (int q = p + 1; q < R; ++q) {
-        const double apq = A[p][q];
-        if (apq != 0.0) {
-          const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            const double akp = A[k][p], akq = A[k][q];
-            A[k][p] = c * akp - s * akq;
-            A[k][q] = s * akp + c * akq;
-          }
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            const double apk = A[p][k], aqk = A[q][k];
-            A[p][k] = c * apk - s * aqk;
-            A[q][k] = s * apk + c * aqk;
-          }
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            const double vkp = V[k][p], vkq = V[k][q];
-            V[k][p] = c * vkp - s * vkq;
-            V[k][q] = s * vkp + c * vkq;
-          }
-        }
-      }
-  }
-}
-
-// C = V diag(lam) V^T:  C^a (T), and the Daleckii-Krein weights
-// F_ij = (lam_i^a - lam_j^a) / (lam_i - lam_j)  (a lam^(a-1) when equal).
-template <typename T, int R>
-__global__ __launch_bounds__(64) void ks_eig(int nb, const T* __restrict__ cmat, double a, T* __restrict__ calpha,
-                       double* __restrict__ vout, double* __restrict__ fout,
-                       int* __restrict__ flag) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  constexpr int E = R * R;
-  double A[R][R], V[R][R];
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-      A[i][j] = 0.5 * ((double)cmat[b * E + i * R + j] + (double)cmat[b * E + j * R + i]);
-  jacobi_sym<R>(A, V);
-  double lam[R], la[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    lam[i] = A[i][i];
-    if (!(lam[i] > 0.0)) { atomicOr(flag, 2); lam[i] = 1e-300; }
-    la[i] = pow(lam[i], a);
-  }
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < R; ++l) s += V[i][l] * la[l] * V[j][l];
-      calpha[b * E + i * R + j] = (T)s;
-      vout[b * E + i * R + j] = V[i][j];
-      const double d = lam[i] - lam[j];
-      fout[b * E + i * R + j] =
-          fabs(d) > 1e-12 * fmax(lam[i], lam[j]) ? (la[i] - la[j]) / d
-                                                  : a * pow(0.5 * (lam[i] + lam[j]), a - 1.0);
-    }
-}
-
-// S2 = 2 Cbar with Cbar = V (F o (V^T sym(Cbar_a) V)) V^T  (Daleckii-Krein).
-template <typename T, int R>
-__global__ __launch_bounds__(64) void ks_dk(int nb, const T* __restrict__ cbar_a, const double* __restrict__ vin,
-                      const double* __restrict__ fin, T* __restrict__ s2) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  constexpr int E = R * R;
-  double S[R][R], V[R][R], M[R][R], N[R][R];
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      S[i][j] = 0.5 * ((double)cbar_a[b * E + i * R + j] + (double)cbar_a[b * E + j * R + i]);
-      V[i][j] = vin[b * E + i * R + j];
-    }
-#pragma unroll
-  for (int i = 0; i < R; ++i)           // M = V^T S V
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < R; ++k)
-#pragma unroll
-        for (int l = 0; l < R; ++l) s += V[k][i] * S[k][l] * V[l][j];
-      M[i][j] = s * fin[b * E + i * R + j];
-    }
-#pragma unroll
-  for (int i = 0; i < R; ++i)           // N = V M V^T
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < R; ++k)
-#pragma unroll
-        for (int l = 0; l < R; ++l) s += V[i][k] * M[k][l] * V[j][l];
-      N[i][j] = s;
-    }
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) s2[b * E + i * R + j] = (T)(N[i][j] + N[j][i]);
-}
-
-// out = Rc Rtot^{-1} for upper-triangular FP64 Rc, Rtot (T output).  Both
-// are accumulated products of Cholesky factors, so their ratio stays well
-// scaled where each alone grows with powers of the spectrum.
-template <typename T, int R>
-__global__ __launch_bounds__(64) void ks_rrel(int nb, const double* __restrict__ rc, const double* __restrict__ rtot,
-                        T* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  constexpr int E = R * R;
-  double U[R][R], Ui[R][R];
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) { U[i][j] = rtot[b * E + i * R + j]; Ui[i][j] = 0.0; }
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j) {
-    Ui[j][j] = 1.0 / U[j][j];
-#pragma unroll
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-#pragma unroll
-      for (int l = i + 1; l <= j; ++l) s += U[i][l] * Ui[l][j];
-      Ui[i][j] = -s / U[i][i];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < R; ++l) s += rc[b * E + i * R + l] * Ui[l][j];
-      out[b * E + i * R + j] = (T)s;
-    }
-}
-
-__global__ void ks_identity(int nb, int r, double* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) out[b * r * r + i * r + j] = i == j ? 1.0 : 0.0;
-}
 
 // ---------------------------------------------------------------------------
 // Tall-skinny products (the panel passes of the backward).
@@ -883,11 +631,6 @@ void lk_copy(const Launch& L, bool f64, int nb, const void* S, void* D, int64_t 
   else hipLaunchKernelGGL(kl_copy<float>, g1(count, nb), dim3(256), 0, L.stream, (const float*)S, (float*)D, count, stride);
 }
 
-void lk_axpy(const Launch& L, bool f64, int nb, const void* X, void* Y, int64_t count, int64_t stride) {
-  if (f64) hipLaunchKernelGGL(kl_axpy<double>, g1(count, nb), dim3(256), 0, L.stream, (const double*)X, (double*)Y, count, stride);
-  else hipLaunchKernelGGL(kl_axpy<float>, g1(count, nb), dim3(256), 0, L.stream, (const float*)X, (float*)Y, count, stride);
-}
-
 void lk_scatter(const Launch& L, bool f64, int nb, void* P, int64_t stride, const int64_t* idx,
                 const void* v, int64_t kstride, int64_t kmax, const int64_t* nnz, int mode,
                 double s) {
@@ -983,68 +726,6 @@ void lk_put_cols(const Launch& L, bool f64, int nb, const void* P0, const void* 
   else
     hipLaunchKernelGGL(kl_put_cols<float>, g1(rows * r, nb), dim3(256), 0, L.stream,
                        (const float*)P0, (const float*)P1, sP, r, (float*)O, sO, w, c0, rows);
-}
-
-void lk_cast_a1(const Launch& L, bool f64, int nb, const double* A1, int64_t sA, void* P,
-                int64_t sP, int64_t count) {
-  if (f64)
-    hipLaunchKernelGGL(kl_cast_a1<double>, g1(count, nb), dim3(256), 0, L.stream, A1, sA, (double*)P, sP, count);
-  else
-    hipLaunchKernelGGL(kl_cast_a1<float>, g1(count, nb), dim3(256), 0, L.stream, A1, sA, (float*)P, sP, count);
-}
-
-void lk_chol(const Launch& L, bool f64, int nb, int r, const void* gram, const double* rin,
-             void* rinv, double* rout, void* rout_t, int* flag) {
-  const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64) {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_chol<double, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, (const double*)gram, rin, (double*)rinv, rout,
-                                          (double*)rout_t, flag));
-  } else {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_chol<float, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, (const float*)gram, rin, (float*)rinv, rout,
-                                          (float*)rout_t, flag));
-  }
-}
-
-void lk_eig(const Launch& L, bool f64, int nb, int r, const void* c, double a, void* calpha,
-            double* v, double* f, int* flag) {
-  const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64) {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_eig<double, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, (const double*)c, a, (double*)calpha, v, f, flag));
-  } else {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_eig<float, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, (const float*)c, a, (float*)calpha, v, f, flag));
-  }
-}
-
-void lk_dk(const Launch& L, bool f64, int nb, int r, const void* cbar_a, const double* v,
-           const double* f, void* s2) {
-  const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64) {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_dk<double, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, (const double*)cbar_a, v, f, (double*)s2));
-  } else {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_dk<float, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, (const float*)cbar_a, v, f, (float*)s2));
-  }
-}
-
-void lk_rrel(const Launch& L, bool f64, int nb, int r, const double* rc, const double* rtot,
-             void* out) {
-  const unsigned g = (unsigned)((nb + 63) / 64);
-  if (f64) {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_rrel<double, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, rc, rtot, (double*)out));
-  } else {
-    GODEC_NC_SWITCH(r, hipLaunchKernelGGL((ks_rrel<float, NC>), dim3(g), dim3(64), 0, L.stream,
-                                          nb, rc, rtot, (float*)out));
-  }
-}
-
-void lk_identity(const Launch& L, int nb, int r, double* out) {
-  hipLaunchKernelGGL(ks_identity, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0, L.stream, nb, r, out);
 }
 
 }  // namespace godec
