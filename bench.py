@@ -205,11 +205,12 @@ def run_layer(warmup, seed=1005):
     assert bool(torch.isfinite(dX).all())
     p, q, T = 2 * w["q"] + 1, w["q"], w["iters"]
     # algorithmic bytes of the backward: per unrolled step the forward panels
-    # of f read D 2p + 2q + 1 times, the adjoint reads L^bar twice and D
-    # 1 + 4q + 2p + 2(p - 1) times; D = X - S is written once and X^bar
-    # read and written once
-    reads = (2 * p + 2 * q + 1) + 2 + (1 + 4 * q + 2 * p + 2 * (p - 1))
-    bytes_bwd = T * (reads + 1 + 1 + 2) * nb * m * n * 4
+    # of f read D p + q + 1 times (each A P = D^T (D P) in one read), the
+    # adjoint reads L^bar twice and D 1 + q + p times (each pair of rank terms
+    # together with the next power of A in one read); D = X - S reads X and
+    # writes D; X^bar is read and written and L^bar written once
+    reads = (p + q + 1) + 2 + (1 + q + p)
+    bytes_bwd = T * (reads + 2 + 3) * nb * m * n * 4
     return {"workload": f"w5_{nb}x{m}x{n}_r{w['r']}_T{T}_f32", "batch": nb,
             "forward_ms": round(fwd[-1], 3), "backward_ms": round(bwd[-1], 3),
             "fwd_bwd_ms": round(fwd[-1] + bwd[-1], 3),
