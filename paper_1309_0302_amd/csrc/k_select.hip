@@ -283,6 +283,7 @@ __device__ __forceinline__ void sel_tile(const T* __restrict__ X, int64_t ldx, i
 // The U_L operand stays in registers for the unit; the V_L operand and the X
 // entries of the next tile are loaded before the current tile is processed.
 constexpr int kResUnitCols = 1024;
+constexpr int kResSlots = 4;   // tiles of a wave's X and V_L operands in registers
 
 template <int RP, bool HIST, bool TAKE, bool S2>
 __device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64_t ldx,
@@ -305,39 +306,51 @@ __device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64
     if (cw >= n) continue;   // wave-uniform
     float a[KS];
     res_load_u<RP>(UL, m, r0, lane, a);
-    float b[KS], x[4];
-    auto load_tile = [&](int t) {
+    // Tiles cycle through kResSlots register slots: the loads of tiles
+    // t + 1 .. t + kResSlots - 1 are in flight while tile t is processed
+    // (slot indices are compile-time; the tile loop is unrolled by the slot
+    // count).
+    float b[kResSlots][KS], x[kResSlots][4];
+    auto load_tile = [&](int t, float (&bb)[KS], float (&xx)[4]) {
       const int64_t c0 = cw + 16 * t;
       const int64_t col = c0 + (lane & 15);
-      res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
+      res_load_vt<RP>(VLt, ldv, n, c0, lane, bb);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = r0 + res_row(v, lane);
-        x[v] = (col < n && row < m) ? X[row * ldx + col] : 0.f;
+        xx[v] = (col < n && row < m) ? X[row * ldx + col] : 0.f;
       }
     };
     const int nt = (int)(((n - cw) + 15) / 16 < WT ? ((n - cw) + 15) / 16 : WT);
-    load_tile(0);
-    for (int t = 0; t < nt; ++t) {
-      const int64_t col = cw + 16 * t + (lane & 15);
-      const f32x4_t L = res_tile<RP>(a, b);
-      float xc[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xc[v] = x[v];
-      if (t + 1 < nt) load_tile(t + 1);
+    for (int u = 0; u < kResSlots - 1; ++u)
+      if (u < nt) load_tile(u, b[u], x[u]);
+    for (int t0 = 0; t0 < nt; t0 += kResSlots) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + res_row(v, lane);
-        const bool ok = col < n && row < m;
-        const float r = xc[v] - L[v];
-        const K key = (K)abs_key(r);
-        if constexpr (S2) {
-          if (ok) s2 += (double)r * (double)r;
+      for (int u = 0; u < kResSlots; ++u) {
+        const int t = t0 + u;
+        if (t < nt) {
+          // the slot freed by the previous tile takes tile t + kResSlots - 1
+          const int up = (u + kResSlots - 1) % kResSlots;
+          if (t + kResSlots - 1 < nt) load_tile(t + kResSlots - 1, b[up], x[up]);
+          const int64_t col = cw + 16 * t + (lane & 15);
+          const f32x4_t L = res_tile<RP>(a, b[u]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + res_row(v, lane);
+            const bool ok = col < n && row < m;
+            const float r = x[u][v] - L[v];
+            const K key = (K)abs_key(r);
+            if constexpr (S2) {
+              if (ok) s2 += (double)r * (double)r;
+            }
+            if constexpr (HIST) {
+              if (ok && (K)(key - pk.klo) < pk.kspan)
+                atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+            }
+            if constexpr (TAKE) seg_push(sink, ok && key >= pk.kmin, row * n + col, r, x[u][v]);
+          }
         }
-        if constexpr (HIST) {
-          if (ok && (K)(key - pk.klo) < pk.kspan) atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
-        }
-        if constexpr (TAKE) seg_push(sink, ok && key >= pk.kmin, row * n + col, r, xc[v]);
       }
     }
   }
