@@ -15,7 +15,10 @@ autograd; it is itself pinned to finite differences.  Checks:
     with its loss ||S - S_tgt||^2 + ||L - L_tgt||^2 (batched forward): two
     problems against the oracle's FP64 gradient (relative Frobenius, FP32
     tolerance below), and FP32 problems with n > 512 (single-problem
-    forward) the same way.
+    forward) the same way;
+  * FP32 at r = 8 on 512-column problems (the widest one-pass row products,
+    pairs of 16 columns) and FP64 problems wider than the FP64 row pass takes
+    (the separate-product fallback), against the oracle's gradient.
 """
 import numpy as np
 import pytest
@@ -32,8 +35,9 @@ torch = pytest.importorskip("torch")
 # backward runs its panel products in FP32 (unit roundoff 6e-8, sums of up to
 # 4096 terms) through 10 unrolled steps whose adjoints pass through
 # (B^T B)^(-1/3) and the orthonormal-range derivative; the r x r algebra is
-# FP64.  Measured 1.2e-5 and 1.4e-5 on two problems of the 4096 x 256
-# workload and below 3e-6 on the 300 x 520 case.
+# FP64.  Measured 2.1e-6 and 2.6e-6 on two problems of the 4096 x 256
+# workload, below 1e-6 on the 300 x 520 case and up to 5.5e-6 on the
+# 700 x 512, r = 8 case.
 FP32_GRAD_TOL = 1e-4
 
 
@@ -213,5 +217,52 @@ def test_layer_fp64_tall_panels():
         got = dX[b].cpu().numpy()
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"[layer] FP64 tall problem {b}: gradient {err:.2e}", flush=True)
+        assert err < 1e-9
+    layer.close()
+
+
+def test_layer_fp32_rank8_widest_batched():
+    """FP32, r = 8 on 512-column problems (the widest the batched forward and
+    the one-pass row products take) with a row count that is not a multiple of
+    any block size: gradient against the oracle on every problem."""
+    works = [wl.tiny(700, 512, 8, rho=0.04, seed=s, dtype=np.float32, noise_std=0.02)
+             for s in (51, 52, 53)]
+    Xs = np.stack([w.X for w in works])
+    X = torch.from_numpy(Xs).cuda()
+    layer, L, S = gpu_layer(X, 8, works[0].k, 1, 3, 9)
+    rng = np.random.default_rng(12)
+    dL = rng.standard_normal(Xs.shape).astype(np.float32)
+    dS = rng.standard_normal(Xs.shape).astype(np.float32)
+    dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
+    for b in range(3):
+        masks = masks_of(layer, b, 3)
+        ref = lr.layer_grad(Xs[b].astype(np.float64), layer.A1(b), 1, masks,
+                            dL[b].astype(np.float64), dS[b].astype(np.float64))
+        got = dX[b].cpu().numpy().astype(np.float64)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[layer] FP32 r=8 n=512 problem {b}: gradient {err:.2e}", flush=True)
+        assert err < FP32_GRAD_TOL
+    layer.close()
+
+
+def test_layer_fp64_wider_than_row_pass():
+    """FP64 problems wider than the FP64 one-pass row products take (n > 128):
+    the backward falls back to separate panel products; gradient against the
+    oracle's autograd gradient."""
+    works = [wl.tiny(300, 160, 2, rho=0.05, seed=s, dtype=np.float64, noise_std=1e-3)
+             for s in (61, 62)]
+    Xs = np.stack([w.X for w in works])
+    X = torch.from_numpy(Xs).cuda()
+    layer, L, S = gpu_layer(X, 2, works[0].k, 1, 2, 3)
+    rng = np.random.default_rng(13)
+    dL = rng.standard_normal(Xs.shape)
+    dS = rng.standard_normal(Xs.shape)
+    dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
+    for b in range(2):
+        masks = masks_of(layer, b, 2)
+        ref = lr.layer_grad(Xs[b], layer.A1(b), 1, masks, dL[b], dS[b])
+        got = dX[b].cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[layer] FP64 n=160 problem {b}: gradient {err:.2e}", flush=True)
         assert err < 1e-9
     layer.close()
