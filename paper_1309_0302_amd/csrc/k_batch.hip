@@ -95,9 +95,17 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   const int n16 = (n + 15) & ~15;
   const int q4 = (int)(ldd / 4);
   const float* Z = bpanel(b, in);
-  for (int e = tid; e < RP8 * kBatchMaxN; e += 256) {
-    const int c = e / kBatchMaxN, j = e % kBatchMaxN;
-    zt[c][j] = j < n ? Z[(int64_t)j * RP8 + c] : 0.f;
+  // Z^T over the columns the products read (j < n16): one row of Z (two
+  // 16-byte loads) per thread
+  static_assert(RP8 == 8, "the panel rows are two float4");
+  for (int j = tid; j < n16; j += 256) {
+    float4 z0 = make_float4(0.f, 0.f, 0.f, 0.f), z1 = z0;
+    if (j < n) {
+      z0 = *reinterpret_cast<const float4*>(Z + (int64_t)j * RP8);
+      z1 = *reinterpret_cast<const float4*>(Z + (int64_t)j * RP8 + 4);
+    }
+    zt[0][j] = z0.x; zt[1][j] = z0.y; zt[2][j] = z0.z; zt[3][j] = z0.w;
+    zt[4][j] = z1.x; zt[5][j] = z1.y; zt[6][j] = z1.z; zt[7][j] = z1.w;
   }
   // columns [ldd, n16) of the slab are never loaded: zero them once
   for (int e = tid; e < kBatchSub * 16; e += 256) {
@@ -113,11 +121,15 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   // slab position of this thread's float4 number u (row, 4-column group),
   // fixed for the whole work item
   int prow[PF], poff[PF];
+  // e / q4 as (e Rq) >> 20 with Rq = ceil(2^20 / q4): exact for e < 2^11 and
+  // q4 <= 2^7 (the rounding adds less than 2^-9, below the 1/q4 gap)
+  static_assert(kBatchSub * (kBatchMaxN / 4) <= 2048 && kBatchMaxN / 4 <= 128, "range of Rq");
+  const uint32_t Rq = ((1u << 20) + (uint32_t)q4 - 1u) / (uint32_t)q4;
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
     const int e = tid + 256 * u;
-    prow[u] = e / q4;
-    poff[u] = 4 * (e % q4);
+    prow[u] = (int)(((uint32_t)e * Rq) >> 20);
+    poff[u] = 4 * (e - prow[u] * q4);
   }
   auto prefetch = [&](int64_t i0, int nr) {
     const float* base = b.D + i0 * ldd;
