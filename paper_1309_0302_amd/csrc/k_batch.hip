@@ -291,61 +291,37 @@ __device__ __forceinline__ int64_t wave_seg_cap(int R, const ColMap& cm) {
 // KIND 2 (BS_CARRY): sum of R^2 and NaN check; histogram and collect the
 // entries whose level-0 digit lies in the carried window.
 // The item's U_L rows are staged in LDS; each wave appends to its own
-// candidate segment with a wave-uniform fill counter (no atomics).
-template <int KIND>
-__global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
-                                                   const BItem* __restrict__ items,
-                                                   unsigned int* __restrict__ seg_count) {
-  __shared__ unsigned int lh[kHistBins];
-  __shared__ float us[kBatchMaxRows * RP8];
-  __shared__ double red[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const BItem it = items[blockIdx.x];
-  const BProb& b = probs[it.prob];
-  BSel* sel = b.sel;
-  const int want = KIND == 0 ? BS_HIST : (KIND == 1 ? BS_COLLECT : BS_CARRY);
-  if (sel->mode != want) return;
-  const bool add_s2 = KIND == 2 || (KIND == 0 && !sel->s2_done);
-  const int n = (int)b.n;
-  const ColMap cm = colmap(n);
-  const int rsub = tid / cm.lanes;
-  const int col0 = tid % cm.lanes;
-  uint32_t klo = 1u;
-  if (KIND == 1) {
-    const int pb = sel->pbits;
-    klo = (uint32_t)(sel->prefix << (31 - pb));
-  } else if (KIND == 2) {
-    klo = (uint32_t)sel->carry_dlo << (31 - kHistBits0);
-  }
-  if (klo < 1u) klo = 1u;
-  if (KIND != 1)
-    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
-  const int R = (int)(it.i1 - it.i0);
-  for (int e = tid; e < R * RP8; e += 256) us[e] = b.UL[it.i0 * RP8 + e];
-  __syncthreads();
-  float v[2][RP8];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int j = col0 + 256 * u;
-#pragma unroll
-    for (int c = 0; c < RP8; ++c) v[u][c] = (u < cm.cpt && j < n) ? b.VL[(int64_t)j * RP8 + c] : 0.f;
-  }
+// candidate segment with a wave-uniform fill counter (no atomics).  The
+// problem's fields are read once into registers, and the row loop is
+// compiled for one or two columns per thread (a block-uniform choice).
+struct SelArgs {
+  const float* X;
+  int64_t ldx, n, i0, segw;
+  int32_t* cand_idx;
+  float* cand_val;
+  float* cand_x;
+  uint32_t klo;
+  bool add_s2;
+};
+
+template <int KIND, int CPT>
+__device__ __forceinline__ void sel_rows(const SelArgs& A, const ColMap& cm, int R, int rsub,
+                                         int col0, const float* us, const float (&v)[2][RP8],
+                                         unsigned int* lh, unsigned int& fill, double& s2,
+                                         int& bad) {
   const int rows_w = (R + cm.rg - 1) / cm.rg;   // same trip count for every thread
-  const int64_t segw = it.i0 * b.rowcap + (int64_t)wave * wave_seg_cap(R, cm);
-  unsigned int fill = 0u;                        // wave-uniform
-  double s2 = 0.0;
-  int bad = 0;
+  const int n = (int)A.n;
   constexpr int G = 8;                           // rows whose X loads are in flight together
   for (int t0 = 0; t0 < rows_w; t0 += G) {
-    float x[G][2];
+    float x[G][CPT];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int ir = rsub + cm.rg * (t0 + g);
       const bool rok = rsub < cm.rg && t0 + g < rows_w && ir < R;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < CPT; ++u) {
         const int j = col0 + 256 * u;
-        x[g][u] = (rok && u < cm.cpt && j < n) ? b.X[(it.i0 + ir) * b.ldx + j] : 0.f;
+        x[g][u] = (rok && j < n) ? A.X[(A.i0 + ir) * A.ldx + j] : 0.f;
       }
     }
 #pragma unroll
@@ -354,46 +330,107 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
       const int ir = rsub + cm.rg * (t0 + g);
       const bool rok = rsub < cm.rg && ir < R;
       float uu[RP8];
+      {
+        const int ro = rok ? ir : 0;
+        const float4 u0 = *reinterpret_cast<const float4*>(&us[ro * RP8]);
+        const float4 u1 = *reinterpret_cast<const float4*>(&us[ro * RP8 + 4]);
+        uu[0] = u0.x; uu[1] = u0.y; uu[2] = u0.z; uu[3] = u0.w;
+        uu[4] = u1.x; uu[5] = u1.y; uu[6] = u1.z; uu[7] = u1.w;
+      }
+      const int64_t i = A.i0 + ir;
 #pragma unroll
-      for (int c = 0; c < RP8; ++c) uu[c] = rok ? us[ir * RP8 + c] : 0.f;
-      const int64_t i = it.i0 + ir;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < CPT; ++u) {
         const int j = col0 + 256 * u;
-        const bool ok = rok && u < cm.cpt && j < n;
+        const bool ok = rok && j < n;
         const float r = bresid(x[g][u], uu, v[u]);
         const uint32_t key = fkey(r);
         if (KIND == 0) {
           if (ok) {
-            if (add_s2) s2 += (double)r * (double)r;
+            if (A.add_s2) s2 += (double)r * (double)r;
             atomicAdd(&lh[key >> (31 - kHistBits0)], 1u);
             if (!isfinite(x[g][u])) bad = 1;
           }
         } else {
-          const bool take = ok && key >= klo;
+          const bool take = ok && key >= A.klo;
           if (KIND == 2 && ok) {
             s2 += (double)r * (double)r;
             if (!isfinite(x[g][u])) bad = 1;
             if (take) atomicAdd(&lh[key >> (31 - kHistBits0)], 1u);
           }
-          if (u < cm.cpt) {
-            const unsigned long long mask = __ballot(take);
-            if (mask) {
-              const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
-              const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-              if (take) {
-                const int64_t pos = segw + fill + rank;
-                b.cand_idx[pos] = (int32_t)(i * n + j);
-                b.cand_val[pos] = r;
-                b.cand_x[pos] = x[g][u];
-              }
-              fill += (unsigned int)__popcll(mask);
+          const unsigned long long mask = __ballot(take);
+          if (mask) {
+            const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
+            const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            if (take) {
+              const int64_t pos = A.segw + fill + rank;
+              A.cand_idx[pos] = (int32_t)(i * n + j);
+              A.cand_val[pos] = r;
+              A.cand_x[pos] = x[g][u];
             }
+            fill += (unsigned int)__popcll(mask);
           }
         }
       }
     }
   }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
+                                                   const BItem* __restrict__ items,
+                                                   unsigned int* __restrict__ seg_count) {
+  __shared__ unsigned int lh[kHistBins];
+  __shared__ __align__(16) float us[kBatchMaxRows * RP8];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const BItem it = items[blockIdx.x];
+  const BProb& b = probs[it.prob];
+  BSel* sel = b.sel;
+  const int want = KIND == 0 ? BS_HIST : (KIND == 1 ? BS_COLLECT : BS_CARRY);
+  if (sel->mode != want) return;
+  const int n = (int)b.n;
+  const ColMap cm = colmap(n);
+  const int rsub = tid / cm.lanes;
+  const int col0 = tid % cm.lanes;
+  SelArgs A;
+  A.X = b.X;
+  A.ldx = b.ldx;
+  A.n = b.n;
+  A.i0 = it.i0;
+  A.cand_idx = b.cand_idx;
+  A.cand_val = b.cand_val;
+  A.cand_x = b.cand_x;
+  A.add_s2 = KIND == 2 || (KIND == 0 && !sel->s2_done);
+  uint32_t klo = 1u;
+  if (KIND == 1) {
+    const int pb = sel->pbits;
+    klo = (uint32_t)(sel->prefix << (31 - pb));
+  } else if (KIND == 2) {
+    klo = (uint32_t)sel->carry_dlo << (31 - kHistBits0);
+  }
+  A.klo = klo < 1u ? 1u : klo;
+  if (KIND != 1)
+    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
+  const int R = (int)(it.i1 - it.i0);
+  const float* ULb = b.UL + it.i0 * RP8;
+  for (int e = tid; e < R * RP8; e += 256) us[e] = ULb[e];
+  __syncthreads();
+  float v[2][RP8];
+  const float* VLb = b.VL;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = col0 + 256 * u;
+#pragma unroll
+    for (int c = 0; c < RP8; ++c) v[u][c] = (u < cm.cpt && j < n) ? VLb[(int64_t)j * RP8 + c] : 0.f;
+  }
+  A.segw = it.i0 * b.rowcap + (int64_t)wave * wave_seg_cap(R, cm);
+  unsigned int fill = 0u;                        // wave-uniform
+  double s2 = 0.0;
+  int bad = 0;
+  if (cm.cpt == 1)
+    sel_rows<KIND, 1>(A, cm, R, rsub, col0, us, v, lh, fill, s2, bad);
+  else
+    sel_rows<KIND, 2>(A, cm, R, rsub, col0, us, v, lh, fill, s2, bad);
   if (KIND != 0 && lane == 0) seg_count[(int64_t)blockIdx.x * 4 + wave] = fill;
   if (KIND != 1) {
     __syncthreads();
@@ -403,7 +440,7 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
     if (lane == 0) red[wave] = s2;
     if (bad) atomicOr(&sel->nonfinite, 1);
     __syncthreads();
-    if (tid == 0 && add_s2) atomicAdd(&sel->sum_r2, red[0] + red[1] + red[2] + red[3]);
+    if (tid == 0 && A.add_s2) atomicAdd(&sel->sum_r2, red[0] + red[1] + red[2] + red[3]);
   }
 }
 
