@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void kl_uvt_update(int m, int n, int w,
 }
 
 // FP32 form of kl_uvt_update on the matrix cores: a block covers 64 rows x
-// 256 columns, each wave one 16-row tile against the 16 column tiles, with
+// 128 columns, each wave one 16-row tile against the 8 column tiles, with
 // v_mfma_f32_16x16x4f32 over chunks of 32 columns of w.  In k-step s of a
 // chunk, lane l (row or column l%16, g = l/16) supplies column 8g + s of the
 // chunk, so that each lane reads eight consecutive values of its U or V row
@@ -239,8 +239,11 @@ __device__ __forceinline__ void uvt_row8(const float* __restrict__ row, bool ok,
   }
 }
 
+constexpr int kUvtTiles = 8;   // 16-column tiles per wave (a block: 64 rows x 128 columns)
+
 template <bool VEC>
-__global__ __launch_bounds__(256) void kl_uvt_mfma(int m, int n, int w,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kl_uvt_mfma(
+    int m, int n, int w,
                                                    const float* __restrict__ U, int64_t sU,
                                                    const float* __restrict__ V, int64_t sV,
                                                    float* __restrict__ X, int64_t ldx,
@@ -248,40 +251,24 @@ __global__ __launch_bounds__(256) void kl_uvt_mfma(int m, int n, int w,
                                                    const uint32_t* __restrict__ bits,
                                                    int64_t wstride, float* __restrict__ Lbar,
                                                    int64_t sL) {
+  constexpr int NT = kUvtTiles;
   const int b = blockIdx.z, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, g = lane >> 4;
   const int r0 = blockIdx.y * 64 + wave * 16;
-  const int j0 = blockIdx.x * 256;
+  const int j0 = blockIdx.x * (16 * NT);
   const float* Ub = U + (int64_t)b * sU;
   const float* Vb = V + (int64_t)b * sV;
-  kl_f32x4 acc[16];
-#pragma unroll
-  for (int t = 0; t < 16; ++t) acc[t] = kl_f32x4{0.f, 0.f, 0.f, 0.f};
-  const int urow = r0 + li;
-  for (int c0 = 0; c0 < w; c0 += 32) {
-    const int ks = (w - c0) < 8 ? (w - c0) : 8;  // k-steps with a valid column
-    float a[8];
-    uvt_row8<VEC>(Ub + (int64_t)urow * w, urow < m, c0 + 8 * g, w, a);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int vrow = j0 + 16 * t + li;
-      float bv[8];
-      uvt_row8<VEC>(Vb + (int64_t)vrow * w, vrow < n, c0 + 8 * g, w, bv);
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        if (s < ks) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[s], acc[t], 0, 0, 0);
-    }
-  }
-  // Epilogue in batches of four tiles; the next batch's loads are issued
-  // before this batch's stores so that waiting for them does not wait for
-  // the stores.
   float* Xb = X + (int64_t)b * sX;
   const uint32_t* Bb = bits ? bits + (int64_t)b * wstride : nullptr;
-  float xv[2][4][4];
-  uint32_t wv[2][4][4];
-  auto load_batch = [&](int t0, float (&xs)[4][4], uint32_t (&ws)[4][4]) {
+  // Epilogue operands in batches of EB tiles; each next batch's loads are
+  // issued before the current batch's stores (so that waiting for loads never
+  // waits for stores).
+  constexpr int EB = 2;
+  float xv[2][EB][4];
+  uint32_t wv[2][EB][4];
+  auto load_batch = [&](int t0, float (&xs)[EB][4], uint32_t (&ws)[EB][4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < EB; ++u) {
       const int j = j0 + 16 * (t0 + u) + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -293,13 +280,31 @@ __global__ __launch_bounds__(256) void kl_uvt_mfma(int m, int n, int w,
       }
     }
   };
+  kl_f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = kl_f32x4{0.f, 0.f, 0.f, 0.f};
+  const int urow = r0 + li;
+  for (int c0 = 0; c0 < w; c0 += 32) {
+    const int ks = (w - c0) < 8 ? (w - c0) : 8;  // k-steps with a valid column
+    float a[8];
+    uvt_row8<VEC>(Ub + (int64_t)urow * w, urow < m, c0 + 8 * g, w, a);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int vrow = j0 + 16 * t + li;
+      float bv[8];
+      uvt_row8<VEC>(Vb + (int64_t)vrow * w, vrow < n, c0 + 8 * g, w, bv);
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (s < ks) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[s], acc[t], 0, 0, 0);
+    }
+  }
   load_batch(0, xv[0], wv[0]);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k + 1 < 4) load_batch(4 * (k + 1), xv[(k + 1) & 1], wv[(k + 1) & 1]);
+  for (int k = 0; k < NT / EB; ++k) {
+    if (k + 1 < NT / EB) load_batch(EB * (k + 1), xv[(k + 1) & 1], wv[(k + 1) & 1]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = 4 * k + u;
+    for (int u = 0; u < EB; ++u) {
+      const int t = EB * k + u;
       const int j = j0 + 16 * t + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -705,7 +710,8 @@ void lk_uvt_update(const Launch& L, bool f64, int nb, int m, int n, int w, const
                        accumulate, bits, wstride, (double*)Lbar, sL);
     return;
   }
-  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((m + 63) / 64), (unsigned)nb);
+  const dim3 grid((unsigned)((n + 16 * kUvtTiles - 1) / (16 * kUvtTiles)),
+                  (unsigned)((m + 63) / 64), (unsigned)nb);
   const bool vec = w % 4 == 0 && (uintptr_t)U % 16 == 0 && (uintptr_t)V % 16 == 0 &&
                    sU % 4 == 0 && sV % 4 == 0;
   if (vec)
