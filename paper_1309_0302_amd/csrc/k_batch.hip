@@ -76,7 +76,7 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_pass(const BProb* __restrict__ probs,
                                                const BItem* __restrict__ items, int in,
                                                float* __restrict__ zslots,
                                                double* __restrict__ gslots) {
@@ -118,25 +118,25 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   double g = 0.0;                              // MODE 1: Gram entry tid < 64
   const int ga = tid / RP8, gb = tid % RP8;
   float4 pf[PF];
-  // slab position of this thread's float4 number u (row, 4-column group),
-  // fixed for the whole work item
-  int prow[PF], poff[PF];
-  // e / q4 as (e Rq) >> 20 with Rq = ceil(2^20 / q4): exact for e < 2^11 and
-  // q4 <= 2^7 (the rounding adds less than 2^-9, below the 1/q4 gap)
+  // thread's float4 number u of a slab: e = tid + 256 u, row e / q4 and
+  // column group e % q4; e / q4 = (e Rq) >> 20 with Rq = ceil(2^20 / q4), exact
+  // for e < 2^11 and q4 <= 2^7 (the rounding adds less than 2^-9, below the
+  // 1/q4 gap).  Recomputed where used rather than kept in registers.
   static_assert(kBatchSub * (kBatchMaxN / 4) <= 2048 && kBatchMaxN / 4 <= 128, "range of Rq");
   const uint32_t Rq = ((1u << 20) + (uint32_t)q4 - 1u) / (uint32_t)q4;
-#pragma unroll
-  for (int u = 0; u < PF; ++u) {
+  auto slab_pos = [&](int u, int& row, int& off) {
     const int e = tid + 256 * u;
-    prow[u] = (int)(((uint32_t)e * Rq) >> 20);
-    poff[u] = 4 * (e - prow[u] * q4);
-  }
+    row = (int)(((uint32_t)e * Rq) >> 20);
+    off = 4 * (e - row * q4);
+  };
   auto prefetch = [&](int64_t i0, int nr) {
     const float* base = b.D + i0 * ldd;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
+      int row, off;
+      slab_pos(u, row, off);
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (prow[u] < nr) v = *reinterpret_cast<const float4*>(base + (int64_t)prow[u] * ldd + poff[u]);
+      if (row < nr) v = *reinterpret_cast<const float4*>(base + (int64_t)row * ldd + off);
       pf[u] = v;
     }
   };
@@ -145,8 +145,11 @@ __global__ __launch_bounds__(256) void kb_pass(const BProb* __restrict__ probs,
   for (int64_t i0 = it.i0; i0 < it.i1; i0 += kBatchSub) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PF; ++u)
-      if (prow[u] < kBatchSub) *reinterpret_cast<float4*>(&dt[prow[u] * LDT + poff[u]]) = pf[u];
+    for (int u = 0; u < PF; ++u) {
+      int row, off;
+      slab_pos(u, row, off);
+      if (row < kBatchSub) *reinterpret_cast<float4*>(&dt[row * LDT + off]) = pf[u];
+    }
     __syncthreads();
     const int cur_nr = nr;
     const int64_t nx = i0 + kBatchSub;
