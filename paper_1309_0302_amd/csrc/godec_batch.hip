@@ -179,6 +179,7 @@ BatchArgs args_of(const godec_batch* b) {
   a.iter = b->iter;
   a.q = b->q;
   a.p = b->p;
+  a.rows_per_item = b->rows_per_item;
   return a;
 }
 

@@ -305,6 +305,7 @@ struct BatchArgs {
   double* gslots;                      // FP64 Gram partials of B' (8 x 8 per item)
   int* iter;                           // device iteration counter
   int q, p;
+  int rows_per_item;                   // most rows of a work item
 };
 
 // chain

@@ -378,12 +378,15 @@ __device__ __forceinline__ void sel_rows(const SelArgs& A, const ColMap& cm, int
   }
 }
 
+// LDS: the histogram, then the item's U_L rows (dynamic size: kHistBins
+// words plus the most rows of a work item times 8 floats).
 template <int KIND>
 __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
                                                    const BItem* __restrict__ items,
                                                    unsigned int* __restrict__ seg_count) {
-  __shared__ unsigned int lh[kHistBins];
-  __shared__ __align__(16) float us[kBatchMaxRows * RP8];
+  extern __shared__ __align__(16) unsigned char sel_lds[];
+  unsigned int* lh = reinterpret_cast<unsigned int*>(sel_lds);
+  float* us = reinterpret_cast<float*>(sel_lds + sizeof(unsigned int) * kHistBins);
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const BItem it = items[blockIdx.x];
@@ -884,14 +887,16 @@ void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m) {
 // write list cur).
 void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
   const unsigned np = (unsigned)a.nprob;
+  const size_t lds = sizeof(unsigned int) * kHistBins +
+                     sizeof(float) * RP8 * (size_t)std::min(a.rows_per_item, kBatchMaxRows);
   hipLaunchKernelGGL(kb_sel_reset, dim3(np), dim3(256), 0, L.stream, a.probs);
-  hipLaunchKernelGGL(kb_sel_pass<2>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+  hipLaunchKernelGGL(kb_sel_pass<2>, dim3((unsigned)a.nitems), dim3(256), lds, L.stream, a.probs,
                      a.items, a.seg_count);
   hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, -1);
-  hipLaunchKernelGGL(kb_sel_pass<0>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+  hipLaunchKernelGGL(kb_sel_pass<0>, dim3((unsigned)a.nitems), dim3(256), lds, L.stream, a.probs,
                      a.items, a.seg_count);
   hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, 0);
-  hipLaunchKernelGGL(kb_sel_pass<1>, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
+  hipLaunchKernelGGL(kb_sel_pass<1>, dim3((unsigned)a.nitems), dim3(256), lds, L.stream, a.probs,
                      a.items, a.seg_count);
   hipLaunchKernelGGL(kb_sel_to_refine, dim3((np + 63) / 64), dim3(64), 0, L.stream, a.probs,
                      a.nprob);
