@@ -586,60 +586,106 @@ __global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ pr
     if (lh[e]) atomicAdd(&b.hist[e], lh[e]);
 }
 
-// FINAL: entries above the threshold key go to S; entries equal to it go to
-// the tie list (as candidate positions).
+// S lists of the problems in BS_FINAL: the candidates above the threshold
+// key (at most count_above) and the tied ones (their candidate positions).
+// Each block counts its segments' entries first, reserves its output ranges
+// with one atomic per kind, and then writes them wave by wave in segment
+// order (a second read of the candidate values).
 __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ probs,
                                                   const BItem* __restrict__ items,
                                                   const unsigned int* __restrict__ seg_count,
                                                   int cur) {
   __shared__ double red[4];
+  __shared__ unsigned long long wcnt[2][4];
+  __shared__ unsigned long long wbase[2][4];
   const BProb& b = probs[blockIdx.y];
   BSel* s = b.sel;
   if (s->mode != BS_FINAL) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tkey = (uint32_t)s->prefix;
   const long long kcap = s->count_above;
-  double s2 = 0.0;
   const ColMap cm = colmap((int)b.n);
-  for (int sg = blockIdx.x; sg < b.nitems * 4; sg += gridDim.x) {
-    const int item = b.item0 + sg / 4, w = sg % 4;
+  const int nseg = b.nitems * 4;
+  const int item0 = b.item0;
+  const int64_t rowcap = b.rowcap;
+  const float* cval = b.cand_val;
+  const int32_t* cidx = b.cand_idx;
+  const float* cxv = b.cand_x;
+  auto seg_range = [&](int sg, int64_t& c0, int64_t& c1) {
+    const int item = item0 + sg / 4, w = sg % 4;
     const BItem itm = items[item];
-    const int64_t c0 = itm.i0 * b.rowcap + (int64_t)w * wave_seg_cap((int)(itm.i1 - itm.i0), cm);
-    const int64_t c1 = c0 + seg_count[(int64_t)item * 4 + w];
+    c0 = itm.i0 * rowcap + (int64_t)w * wave_seg_cap((int)(itm.i1 - itm.i0), cm);
+    c1 = c0 + seg_count[(int64_t)item * 4 + w];
+  };
+  // counts of this block's segments, per wave
+  unsigned long long na = 0ull, nt = 0ull;   // wave-uniform
+  for (int sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    int64_t c0, c1;
+    seg_range(sg, c0, c1);
     for (int64_t cb = c0; cb < c1; cb += 256) {
       const int64_t c = cb + tid;
       const bool valid = c < c1;
-      const float v = valid ? b.cand_val[c] : 0.f;
+      const uint32_t key = fkey(valid ? cval[c] : 0.f);
+      na += (unsigned long long)__popcll(__ballot(valid && key > tkey));
+      nt += (unsigned long long)__popcll(__ballot(valid && key == tkey && tkey > 0));
+    }
+  }
+  if (lane == 0) {
+    wcnt[0][wave] = na;
+    wcnt[1][wave] = nt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+      const unsigned long long tot = wcnt[kind][0] + wcnt[kind][1] + wcnt[kind][2] + wcnt[kind][3];
+      unsigned long long base = 0ull;
+      if (tot) base = atomicAdd(kind == 0 ? &s->nabove : &s->nties, tot);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        wbase[kind][w] = base;
+        base += wcnt[kind][w];
+      }
+    }
+  }
+  __syncthreads();
+  unsigned long long pa = wbase[0][wave], pt = wbase[1][wave];   // wave-uniform
+  int64_t* sidx = b.s_idx[cur];
+  float* sval = b.s_val[cur];
+  float* sx = b.s_x[cur];
+  int32_t* tie = b.tie_idx;
+  double s2 = 0.0;
+  for (int sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    int64_t c0, c1;
+    seg_range(sg, c0, c1);
+    for (int64_t cb = c0; cb < c1; cb += 256) {
+      const int64_t c = cb + tid;
+      const bool valid = c < c1;
+      const float v = valid ? cval[c] : 0.f;
       const uint32_t key = fkey(v);
       const bool above = valid && key > tkey;
-      const bool tie = valid && key == tkey && tkey > 0;
-#pragma unroll
-      for (int kind = 0; kind < 2; ++kind) {
-        const bool take = kind == 0 ? above : tie;
-        const unsigned long long mask = __ballot(take);
-        if (!mask) continue;
-        const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
-        const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned long long base = 0;
-        if (take && rank == 0u)
-          base = atomicAdd(kind == 0 ? &s->nabove : &s->nties, (unsigned long long)__popcll(mask));
-        const unsigned int blo = __builtin_amdgcn_readlane((unsigned int)base, leader);
-        const unsigned int bhi = __builtin_amdgcn_readlane((unsigned int)(base >> 32), leader);
-        base = ((unsigned long long)bhi << 32) | blo;
-        if (take) {
-          const unsigned long long pos = base + rank;
-          if (kind == 0) {
-            if ((long long)pos < kcap) {
-              b.s_idx[cur][pos] = (int64_t)b.cand_idx[c];
-              b.s_val[cur][pos] = v;
-              b.s_x[cur][pos] = b.cand_x[c];
-              s2 += (double)v * (double)v;
-            }
-          } else {
-            b.tie_idx[pos] = (int32_t)c;
+      const bool istie = valid && key == tkey && tkey > 0;
+      const unsigned long long ma = __ballot(above);
+      if (ma) {
+        const unsigned int rank = __builtin_amdgcn_mbcnt_hi(
+            (unsigned int)(ma >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)ma, 0u));
+        if (above) {
+          const unsigned long long pos = pa + rank;
+          if ((long long)pos < kcap) {
+            sidx[pos] = (int64_t)cidx[c];
+            sval[pos] = v;
+            sx[pos] = cxv[c];
+            s2 += (double)v * (double)v;
           }
         }
+        pa += (unsigned long long)__popcll(ma);
+      }
+      const unsigned long long mt = __ballot(istie);
+      if (mt) {
+        const unsigned int rank = __builtin_amdgcn_mbcnt_hi(
+            (unsigned int)(mt >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)mt, 0u));
+        if (istie) tie[pt + rank] = (int32_t)c;
+        pt += (unsigned long long)__popcll(mt);
       }
     }
   }
