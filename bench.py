@@ -92,8 +92,8 @@ TRAFFIC_KERNEL = "mm_a_bf16(D*Z)"
 def measured_traffic(kernel_name):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE record (scaled by a plain copy), or
-    None when there is no record or the kernel's source file has changed
-    since the counters were taken."""
+    None when there is no record or the kernel's source file (or the file
+    that sets its launch shape) has changed since the counters were taken."""
     import hashlib
     if kernel_name != TRAFFIC_KERNEL or not os.path.exists(COUNTERS_FILE):
         return None
@@ -104,11 +104,15 @@ def measured_traffic(kernel_name):
             rec = json.loads(line)
     if rec is None:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src):
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
+    # the kernel's source and the source that sets its launch shape
+    for key in ("source", "launch_source"):
+        if key not in rec:
+            continue
+        src = os.path.join(ROOT, rec[key])
+        if not os.path.exists(src):
+            return None
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec[key + "_sha256"]:
+            return None
     return rec["hbm_bytes_per_launch"]
 
 
