@@ -342,6 +342,16 @@ godec_status batch_snapshot_S(godec_batch* b, int64_t* idx_dev, float* val_dev, 
   return GODEC_OK;
 }
 
+godec_status batch_factors(godec_batch* b, float* U_dev, int64_t sU, float* V_dev, int64_t sV) {
+  if (!b || !U_dev || !V_dev) return fail(GODEC_E_INVAL, "NULL argument");
+  int64_t most = 0;
+  for (const HostProb& h : b->hp) most = std::max<int64_t>(most, (h.m + h.n) * h.r);
+  const Launch L{b->stream, b->num_cu};
+  bl_copy_factors(L, b->dprobs, b->count, most, U_dev, sU, V_dev, sV);
+  HIP_TRY(hipGetLastError());
+  return GODEC_OK;
+}
+
 godec_status batch_ranks(godec_batch* b, int* rank_host) {
   if (!b || !rank_host) return fail(GODEC_E_INVAL, "NULL argument");
   const Launch L{b->stream, b->num_cu};

@@ -328,6 +328,9 @@ void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 void bl_init(const Launch& L, const BatchArgs& a);   // D = X, norms, state
 void bl_copy_lists(const Launch& L, const BProb* probs_dev, int nprob, int list, int64_t kmax,
                    int64_t* idx_out, float* val_out, int64_t kstride, int64_t* nnz_out);
+// every problem's U_L (m x r) and V_L (n x r) into dense panels at U + b sU, V + b sV
+void bl_copy_factors(const Launch& L, const BProb* probs_dev, int nprob, int64_t max_elems,
+                     float* U, int64_t sU, float* V, int64_t sV);
 // out[2i], out[2i + 1] = problem i's non-finite flag and current rank
 void bl_gather_state(const Launch& L, const BProb* probs_dev, int nprob, int* out);
 void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, float* R,

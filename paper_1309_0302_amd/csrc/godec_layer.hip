@@ -393,12 +393,10 @@ godec_status forward_batched(godec_layer* l, const void* X_dev, uint64_t seed, v
     if (rank[b] != r) return done(rank_error(b));
     s = godec_batch_get_A1(gb, b, l->a1_host.data() + (size_t)b * n * r);
     if (s != GODEC_OK) return done(s);
-    if (L_dev) {
-      s = godec_batch_get_factors(gb, b, (float*)l->Uf + b * m * r, (float*)l->Vf + b * n * r);
-      if (s != GODEC_OK) return done(s);
-    }
   }
   if (L_dev) {
+    s = batch_factors(gb, (float*)l->Uf, m * r, (float*)l->Vf, n * r);
+    if (s != GODEC_OK) return done(s);
     const Launch L{bs, l->num_cu};
     lk_uvt_update(L, false, nb, (int)m, (int)n, r, l->Uf, m * r, l->Vf, n * r, L_dev, n, mn, 0,
                   nullptr, 0, nullptr, 0);

@@ -43,6 +43,10 @@ godec_status batch_snapshot_S(godec_batch* b, int64_t* idx_dev, float* val_dev, 
 // batch's stream).
 godec_status batch_ranks(godec_batch* b, int* rank_host);
 
+// Enqueue a copy of every problem's factors U_L (m x r) and V_L (n x r) to
+// U_dev + i sU and V_dev + i sV (one launch on the batch's stream).
+godec_status batch_factors(godec_batch* b, float* U_dev, int64_t sU, float* V_dev, int64_t sV);
+
 }  // namespace godec_host
 
 #define HIP_TRY(expr)                                                        \

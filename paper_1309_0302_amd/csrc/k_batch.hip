@@ -979,6 +979,34 @@ void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, f
   hipLaunchKernelGGL(kb_residual, dim3(g), dim3(256), 0, L.stream, prob_dev, R, ldr);
 }
 
+// U_L (m x 8) and V_L (n x 8) of every problem into dense m x r and n x r
+// panels (problem b at U + b sU, V + b sV).
+__global__ __launch_bounds__(256) void kb_copy_factors(const BProb* __restrict__ probs,
+                                                       float* __restrict__ U, int64_t sU,
+                                                       float* __restrict__ V, int64_t sV) {
+  const BProb& b = probs[blockIdx.y];
+  const int r = b.r;
+  const int64_t nu = b.m * r, nv = b.n * r;
+  const float* UL = b.UL;
+  const float* VL = b.VL;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nu + nv;
+       e += (int64_t)gridDim.x * 256) {
+    if (e < nu) {
+      U[(int64_t)blockIdx.y * sU + e] = UL[(e / r) * RP8 + e % r];
+    } else {
+      const int64_t f = e - nu;
+      V[(int64_t)blockIdx.y * sV + f] = VL[(f / r) * RP8 + f % r];
+    }
+  }
+}
+
+void bl_copy_factors(const Launch& L, const BProb* probs_dev, int nprob, int64_t max_elems,
+                     float* U, int64_t sU, float* V, int64_t sV) {
+  const unsigned g = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (max_elems + 255) / 256));
+  hipLaunchKernelGGL(kb_copy_factors, dim3(g, (unsigned)nprob), dim3(256), 0, L.stream, probs_dev,
+                     U, sU, V, sV);
+}
+
 // out[2i] = problem i's non-finite flag, out[2i + 1] = its current rank
 __global__ __launch_bounds__(256) void kb_gather_state(const BProb* __restrict__ probs, int nprob,
                                                        int* __restrict__ out) {
