@@ -25,6 +25,17 @@ W4  64 independent FP32 problems: m ~ U{2000..20000}, n ~ U{100..400},
     noise std sqrt(1e-3); q = 1, T = 25.
 W5  16 FP32 problems of 4096 x 256, r = 4, 5% support, q = 1, T = 10,
     with Gaussian targets for a loss on (L, S).
+
+GreBsmo (Sec. 3.2.1) workloads, with the parameters a GreBsmo run takes
+(rank bound r, rows per stage dr, inner iterations K, soft threshold lam,
+power steps) in ``GreBsmoWorkload``:
+G1  500 x 500 FP64 planted problem (the shape of the phase-diagram
+    experiment of Sec. 5.4): U, V iid N(0, var 1/sqrt(r)) with r = 5,
+    5% support of values +-5 (random signs), no noise; r = 5, dr = 1,
+    K = 30, lam = 0.1, power = 2.
+G2  25 344 x 500 FP32 video-shaped matrix (144 x 176 pixels x 500 frames,
+    the shape of the Hall sequence of Sec. 5.5) from the W2 recipe with 500
+    frames; r = 4, dr = 1, K = 10, lam = 0.125, power = 2.
 """
 
 from dataclasses import dataclass, field
@@ -196,3 +207,44 @@ def tiny(m: int, n: int, r: int, *, rho: float = 0.05, amp: float = 5.0,
                                  keep_parts=True)
     return Workload(f"tiny_{m}x{n}_r{r}", X, r, support, 1, 5, seed, {}, L0,
                     sidx)
+
+
+@dataclass
+class GreBsmoWorkload:
+    name: str
+    X: np.ndarray
+    r: int
+    dr: int
+    K: int
+    lam: float
+    power: int
+    seed: int
+    recipe: dict = field(default_factory=dict)
+    L0: np.ndarray | None = None
+
+
+def planted_pm(m: int, n: int, r: int, *, rho: float, amp: float, seed: int,
+               dtype=np.float64):
+    """X = U V^T + S0, S0 = +-amp on a Bernoulli(rho) support (no noise)."""
+    rng = np.random.default_rng(seed)
+    std = (1.0 / np.sqrt(r)) ** 0.5
+    U = rng.standard_normal((m, r)) * std
+    V = rng.standard_normal((n, r)) * std
+    L0 = U @ V.T
+    u = rng.uniform(size=(m, n))
+    S0 = np.where(u < rho / 2, amp, np.where(u < rho, -amp, 0.0))
+    return (L0 + S0).astype(dtype), L0, S0
+
+
+def g1(seed: int = 1006) -> GreBsmoWorkload:
+    X, L0, _ = planted_pm(500, 500, 5, rho=0.05, amp=5.0, seed=seed)
+    return GreBsmoWorkload("g1_planted_500x500_f64", X, 5, 1, 30, 0.1, 2, seed,
+                           dict(rho=0.05, amp=5.0, dtype="f64"), L0)
+
+
+def g2(seed: int = 1007, frames: int = 500) -> GreBsmoWorkload:
+    X, B, mask = video_background_blocks(seed, frames=frames)
+    return GreBsmoWorkload(f"g2_video_25344x{frames}_f32", X.astype(np.float32), 4, 1, 10,
+                           0.125, 2, seed,
+                           dict(frames=frames, support_fraction=float(mask.mean()),
+                                dtype="f32"), B)
