@@ -222,6 +222,79 @@ def run_layer(warmup, seed=1005):
             "backward_achieved_GBps": round(bytes_bwd / (bwd[-1] * 1e-3) / 1e9, 1)}
 
 
+def grebsmo_bytes(m, n, r, dr, K, power, elem=4):
+    """Algorithmic bytes of one GreBsmo solve: per stage the greedy step's
+    power Gram passes (two reads of R each), per inner iteration the two
+    panel passes (reads of D) and the soft pass (read X, write D), and the R
+    write of every stage but the last."""
+    stages = -(-r // dr)
+    mn = m * n * elem
+    return stages * (2 * power + 4 * K) * mn + (stages - 1) * mn
+
+
+def run_grebsmo(warmup, seed=1007):
+    """GreBsmo on the 25 344 x 500 FP32 video-shaped workload (r = 4, dr = 1,
+    K = 10, lambda = 0.125, power = 2): whole solves, timed on the stream with
+    HIP events; the FP64 oracle's solve on the host beside it."""
+    import numpy as np
+    import torch
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GreBsmo
+    w = workloads.g2(seed=seed)
+    X = torch.from_numpy(w.X).cuda()
+    m, n = w.X.shape
+    ms = []
+    for it in range(warmup + 3):
+        gb = GreBsmo(X, w.r, dr=w.dr, power=w.power, lam=w.lam, seed=w.seed)
+        stream = torch.cuda.ExternalStream(gb.stream) if gb.stream else \
+            torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        gb.solve(w.K, 0.0, want_info=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            ms.append(e0.elapsed_time(e1))
+        info = gb.info()
+        gb.close()
+    t = float(np.median(ms))
+    nbytes = grebsmo_bytes(m, n, w.r, w.dr, w.K, w.power)
+    return {"workload": w.name, "m": m, "n": n, "r": w.r, "dr": w.dr, "K": w.K,
+            "lambda": w.lam, "power": w.power, "ms_per_solve": round(t, 4),
+            "solves_per_s": round(1e3 / t, 2),
+            "inner_iterations": int(info.inner_iters),
+            "algorithmic_bytes_per_solve": nbytes,
+            "achieved_GBps": round(nbytes / (t * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "rel_err_sq": info.rel_err_sq, "nnz": int(info.nnz)}
+
+
+def grebsmo_cpu_baseline(seed=1007):
+    """The FP64 GreBsmo oracle on the host cores: one whole solve of the same
+    workload."""
+    import numpy as np
+    from oracle import grebsmo_ref as g
+    from oracle.rng_ref import a1_gaussian
+    from paper_1309_0302_amd import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(i.get("num_threads", 1) for i in threadpool_info()) or 1
+    except Exception:
+        threads = os.cpu_count() or 1
+    w = workloads.g2(seed=seed)
+    Om = a1_gaussian(w.seed, w.X.shape[1], w.r)
+    X = w.X.astype(np.float64)
+    t0 = time.perf_counter()
+    g.grebsmo(X, w.r, w.dr, w.K, w.lam, w.power, Om)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one FP64 oracle solve of the full {w.X.shape[0]}x{w.X.shape[1]} "
+                      f"GreBsmo workload (numpy/OpenBLAS), {dt:.1f} s"}
+
+
 def run_copy(nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of a known size: the reference against
     which the HBM byte counters of the other kernels are scaled."""
@@ -274,7 +347,8 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=25)
     ap.add_argument("--skip-layer", action="store_true")
     ap.add_argument("--skip-copy", action="store_true")
-    ap.add_argument("--only", choices=["batch", "layer", "copy"],
+    ap.add_argument("--skip-grebsmo", action="store_true")
+    ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo"],
                     help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
@@ -297,6 +371,12 @@ def main():
         return
     if args.only == "copy":
         print(json.dumps(run_copy()), flush=True)
+        return
+    if args.only == "grebsmo":
+        out = run_grebsmo(min(args.warmup, 2))
+        if not args.skip_cpu:
+            out["cpu_baseline"] = grebsmo_cpu_baseline()
+        print(json.dumps(out), flush=True)
         return
 
     log(f"[bench] generating workload {args.size}x{args.size}")
@@ -360,7 +440,14 @@ def main():
         out["layer"] = run_layer(min(args.warmup, 1))
         log(f"[bench] layer fwd {out['layer']['forward_ms']} ms, "
             f"bwd {out['layer']['backward_ms']} ms")
+    if not args.skip_grebsmo:
+        log("[bench] GreBsmo: 25344 x 500 video-shaped, r = 4")
+        out["grebsmo"] = run_grebsmo(min(args.warmup, 2))
+        log(f"[bench] grebsmo {out['grebsmo']['ms_per_solve']} ms/solve")
     if not args.skip_cpu:
+        if "grebsmo" in out:
+            log("[bench] grebsmo cpu baseline: one oracle solve")
+            out["grebsmo"]["cpu_baseline"] = grebsmo_cpu_baseline()
         log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -336,6 +336,76 @@ godec_status godec_layer_get_A1(godec_layer* l, int32_t b, double* a1_host);
 /* Release the layer (the workspace stays the caller's). */
 godec_status godec_layer_destroy(godec_layer* l);
 
+/* ------------------------------------------------------------------------
+ * GreBsmo: greedy bilateral smoothing (Sec. 3.2.1 within the greedy bilateral
+ * paradigm of Algorithm 2).  X (m x n) = U V + S + noise is fitted by
+ * minimising 1/2 ||X - U V - S||_F^2 + lambda ||S||_1 with rank(U V) <= r
+ * (Eq. 10).  Each rank stage appends rows to V, then runs K inner iterations
+ * of Eq. 13:
+ *   U = Q with (X - S) V^T = Q R,   V = Q^T (X - S),   S = S_lambda(X - U V)
+ * (S_lambda: element-wise soft thresholding, Eq. 12).  The appended rows are
+ * an orthonormal basis of (R^T R)^power Omega_s, the random-projection
+ * estimate of the top right singular vectors of R = X - U V - S (Eq. 14),
+ * with Omega_s = columns [s*dr, min((s+1)*dr, r)) of an n x r standard
+ * Gaussian matrix drawn from seed (the generator of godec_draw_a1).  V
+ * starts empty, so stage 0 uses R = X.
+ *
+ * Storage: U (m x r) and V^T (n x r) are kept as zero-padded panels in the
+ * dtype of X; D = X - S and R are dense m x n copies in the workspace.  The
+ * orthonormal bases come from two Cholesky QR rounds with an FP64 Gram
+ * matrix; a direction that is numerically dependent on the others comes out
+ * as a zero column (the rank reported stays the number of rows appended).
+ * ------------------------------------------------------------------------ */
+typedef struct godec_grebsmo godec_grebsmo;
+
+typedef struct {
+  int32_t rank;          /* rows of V appended so far */
+  int32_t stages;        /* rank stages completed */
+  int64_t inner_iters;   /* Eq. 13 iterations completed (all stages) */
+  int64_t nnz;           /* nonzeros of S after the last S update */
+  double rel_err_sq;     /* ||X - U V - S||_F^2 / ||X||_F^2 after it */
+  double l1;             /* ||S||_1 after it */
+} godec_grebsmo_info;
+
+/* Workspace bytes for an m x n problem of rank bound r (1 <= r <= 32). */
+godec_status godec_grebsmo_workspace_size(int64_t m, int64_t n, int32_t r, godec_dtype dtype,
+                                          size_t* bytes);
+
+/* Set up a decomposition of X_dev (m x n, leading dimension ldx, borrowed
+ * until destroy).  dr >= 1 rows per stage, power >= 1, lambda >= 0 finite.
+ * omega_host (n x r FP64 row-major) replaces the seeded draw when not NULL.
+ * The workspace must be 256-byte aligned.  stream: a hipStream_t or NULL.
+ * Synchronous (checks X for NaN / Inf: GODEC_E_NUMERIC). */
+godec_status godec_grebsmo_init(godec_grebsmo** out, const void* X_dev, godec_dtype dtype,
+                                int64_t m, int64_t n, int64_t ldx, int32_t r, int32_t dr,
+                                int32_t power, double lambda, uint64_t seed,
+                                const double* omega_host, void* workspace_dev,
+                                size_t workspace_bytes, void* stream);
+
+/* One rank stage: the greedy step, then K >= 1 inner iterations.
+ * GODEC_E_STATE once the rank has reached r.  Asynchronous. */
+godec_status godec_grebsmo_stage(godec_grebsmo* g, int32_t K);
+
+/* Stages of K inner iterations until the rank reaches r or, when tau > 0,
+ * until the relative error is <= tau (read back after each stage, which
+ * synchronises).  info may be NULL; when given it is filled (synchronises). */
+godec_status godec_grebsmo_solve(godec_grebsmo* g, int32_t K, double tau,
+                                 godec_grebsmo_info* info);
+
+/* U (m x rank, row-major) and V^T (n x rank, row-major), so L = U (V^T)^T;
+ * dtype of X.  Asynchronous. */
+godec_status godec_grebsmo_get_factors(godec_grebsmo* g, void* U_dev, void* Vt_dev);
+
+/* Dense S (m x n, leading dimension lds >= n, dtype of X), recomputed from
+ * X, U and V exactly as the last S update computed it.  Asynchronous. */
+godec_status godec_grebsmo_get_S(godec_grebsmo* g, void* S_dev, int64_t lds);
+
+/* Counters and objective terms of the last S update.  Synchronises. */
+godec_status godec_grebsmo_get_info(godec_grebsmo* g, godec_grebsmo_info* info);
+
+/* Release the handle (the workspace stays the caller's). */
+godec_status godec_grebsmo_destroy(godec_grebsmo* g);
+
 /* Build information string (static storage). */
 const char* godec_version(void);
 

@@ -46,6 +46,7 @@ Pinning status (the tests under tests/test_oracle_grebsmo.py):
                        F non-increasing)
     greedy_directions  pinned (LAPACK SVD's top right singular vectors on an
                        input with a spectral gap)
+    grebsmo_stage,
     grebsmo            pinned (F non-increasing across stages; truncated SVD
                        when lambda is so large that S stays 0; recovery of a
                        planted low-rank + sparse X, the success criterion of
@@ -124,6 +125,21 @@ def stage_columns(stage: int, dr: int, r: int) -> tuple[int, int]:
     return c0, min(c0 + dr, r)
 
 
+def grebsmo_stage(X, U, V, S, Omega_s, K, lam, power, objective_log=None):
+    """One rank stage of Algorithm 2 from the state (U, V, S): append the
+    greedy rows for dF/dV = X - U V - S (Eq. 14; readings G2, G3), then K
+    inner iterations of Eq. 13 (G5).  Returns (U, V, S, Z) with Z the rows
+    appended."""
+    R = X - U @ V - S
+    Z = greedy_directions(R, Omega_s, power)
+    V = np.vstack([V, Z])
+    for _ in range(K):
+        U, V, S = inner_step(X, S, V, lam)
+        if objective_log is not None:
+            objective_log.append(objective(X, U @ V, S, lam))
+    return U, V, S, Z
+
+
 def grebsmo(X: np.ndarray, r: int, dr: int, K: int, lam: float, power: int,
             Omega: np.ndarray, tau: float = 0.0, stages: int | None = None,
             track: bool = False) -> GreBsmoResult:
@@ -146,13 +162,8 @@ def grebsmo(X: np.ndarray, r: int, dr: int, K: int, lam: float, power: int,
     stage = 0
     while True:
         c0, c1 = stage_columns(stage, dr, r)
-        R = X - U @ V - S
-        Z = greedy_directions(R, Omega[:, c0:c1], power)
-        V = np.vstack([V, Z])
-        for _ in range(K):
-            U, V, S = inner_step(X, S, V, lam)
-            if track:
-                res.objective.append(objective(X, U @ V, S, lam))
+        U, V, S, Z = grebsmo_stage(X, U, V, S, Omega[:, c0:c1], K, lam, power,
+                                   res.objective if track else None)
         E = X - U @ V - S
         res.rel_err.append(float(np.sum(E * E)) / normx2)
         res.ranks.append(V.shape[0])

@@ -54,6 +54,12 @@ class godec_problem(ctypes.Structure):
                 ("k", ctypes.c_int64), ("seed", ctypes.c_uint64)]
 
 
+class godec_grebsmo_info(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("stages", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rel_err_sq", ctypes.c_double), ("l1", ctypes.c_double)]
+
+
 class GodecError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -117,6 +123,18 @@ _SIG = {
     "godec_layer_get_mask": (_I32, [_P, _I32, _I32, _P, ctypes.POINTER(_I64)]),
     "godec_layer_get_A1": (_I32, [_P, _I32, _P]),
     "godec_layer_destroy": (_I32, [_P]),
+    "godec_grebsmo_workspace_size": (_I32, [_I64, _I64, _I32, _I32,
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "godec_grebsmo_init": (_I32, [ctypes.POINTER(_P), _P, _I32, _I64, _I64, _I64, _I32, _I32,
+                                  _I32, ctypes.c_double, ctypes.c_uint64, _P, _P,
+                                  ctypes.c_size_t, _P]),
+    "godec_grebsmo_stage": (_I32, [_P, _I32]),
+    "godec_grebsmo_solve": (_I32, [_P, _I32, ctypes.c_double,
+                                   ctypes.POINTER(godec_grebsmo_info)]),
+    "godec_grebsmo_get_factors": (_I32, [_P, _P, _P]),
+    "godec_grebsmo_get_S": (_I32, [_P, _P, _I64]),
+    "godec_grebsmo_get_info": (_I32, [_P, ctypes.POINTER(godec_grebsmo_info)]),
+    "godec_grebsmo_destroy": (_I32, [_P]),
 }
 
 
@@ -659,3 +677,114 @@ def godec_layer_fn(X, r, k, q, T, seed=0):
             return ctx.layer.backward(dL, dS).reshape(X.shape)
 
     return _Fn.apply(X)
+
+
+# ---- GreBsmo ------------------------------------------------------------------
+
+def godec_grebsmo_workspace_size(m, n, r, dtype):
+    out = ctypes.c_size_t(0)
+    _check(load().godec_grebsmo_workspace_size(m, n, r, dtype, ctypes.byref(out)))
+    return out.value
+
+
+def godec_grebsmo_init(X_ptr, dtype, m, n, ldx, r, dr, power, lam, seed, omega, ws_ptr,
+                       ws_bytes, stream):
+    h = _P()
+    om = None
+    if omega is not None:
+        omega = np.ascontiguousarray(omega, dtype=np.float64)
+        if omega.shape != (n, r):
+            raise ValueError("omega must be n x r")
+        om = omega.ctypes.data
+    _check(load().godec_grebsmo_init(ctypes.byref(h), X_ptr, dtype, m, n, ldx, r, dr, power,
+                                     lam, seed, om, ws_ptr, ws_bytes, stream))
+    return h
+
+
+def godec_grebsmo_stage(h, K):
+    _check(load().godec_grebsmo_stage(h, K))
+
+
+def godec_grebsmo_solve(h, K, tau=0.0, want_info=True):
+    """Run stages until the rank bound (or tau); with want_info=False and
+    tau = 0 the call only enqueues work and returns None."""
+    info = godec_grebsmo_info() if want_info else None
+    _check(load().godec_grebsmo_solve(h, K, tau, ctypes.byref(info) if want_info else None))
+    return info
+
+
+def godec_grebsmo_get_factors(h, u_ptr, vt_ptr):
+    _check(load().godec_grebsmo_get_factors(h, u_ptr, vt_ptr))
+
+
+def godec_grebsmo_get_S(h, s_ptr, lds):
+    _check(load().godec_grebsmo_get_S(h, s_ptr, lds))
+
+
+def godec_grebsmo_get_info(h):
+    info = godec_grebsmo_info()
+    _check(load().godec_grebsmo_get_info(h, ctypes.byref(info)))
+    return info
+
+
+def godec_grebsmo_destroy(h):
+    _check(load().godec_grebsmo_destroy(h))
+
+
+class GreBsmo:
+    """GreBsmo (greedy bilateral smoothing) of one dense device matrix X
+    (m x n, float32 or float64): rank stages of dr appended rows, K inner
+    iterations each, soft threshold lam, power steps per greedy direction."""
+
+    def __init__(self, X, r, dr=1, power=2, lam=0.1, seed=0, omega=None, stream=None):
+        import torch
+        if X.dim() != 2 or not X.is_cuda or X.stride(1) != 1:
+            raise ValueError("X must be a 2-D device tensor with unit column stride")
+        self.X = X
+        self.m, self.n = X.shape
+        self.r = r
+        self.dtype = _dtype_code(X)
+        if stream is None:
+            stream = torch.cuda.current_stream(X.device).cuda_stream
+        self.stream = stream
+        self.ws_bytes = godec_grebsmo_workspace_size(self.m, self.n, r, self.dtype)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=X.device)
+        base = (self.ws.data_ptr() + 255) // 256 * 256
+        self.h = None
+        self.h = godec_grebsmo_init(X.data_ptr(), self.dtype, self.m, self.n, X.stride(0), r,
+                                    dr, power, lam, seed, omega, base, self.ws_bytes, stream)
+
+    def stage(self, K):
+        godec_grebsmo_stage(self.h, K)
+
+    def solve(self, K, tau=0.0, want_info=True):
+        return godec_grebsmo_solve(self.h, K, tau, want_info)
+
+    def info(self):
+        return godec_grebsmo_get_info(self.h)
+
+    def factors(self):
+        """(U m x rank, Vt n x rank) device tensors, L = U Vt^T."""
+        import torch
+        rank = self.info().rank
+        U = torch.empty((self.m, rank), dtype=self.X.dtype, device=self.X.device)
+        Vt = torch.empty((self.n, rank), dtype=self.X.dtype, device=self.X.device)
+        godec_grebsmo_get_factors(self.h, U.data_ptr(), Vt.data_ptr())
+        return U, Vt
+
+    def S(self):
+        import torch
+        S = torch.empty((self.m, self.n), dtype=self.X.dtype, device=self.X.device)
+        godec_grebsmo_get_S(self.h, S.data_ptr(), self.n)
+        return S
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            godec_grebsmo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

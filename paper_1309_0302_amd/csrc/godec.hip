@@ -89,15 +89,8 @@ struct godec_ctx {
   size_t pool_used = 0;
 };
 
-namespace {
-
-struct Sizes {
-  int64_t ldd, mpad, nchunks, rpc, cap;
-  int64_t kc_a, nct_a, rc_b, nch_b;
-};
-
-Sizes plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
-  Sizes s;
+PanelPlan godec_host::plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
+  PanelPlan s;
   s.ldd = (n + 127) / 128 * 128;
   s.mpad = (m + 63) / 64 * 64;
   // k_mm_a: 1152-column tiles (the fastest of 640 ... 2048 in steps of 64
@@ -123,6 +116,8 @@ Sizes plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
   // few Gram partials: the one-block r x r kernels sum them serially
   return s;
 }
+
+namespace {
 
 // Carve every buffer; returns the total size.  ctx may be a measuring dummy.
 size_t carve(godec_ctx* c, void* base) {
@@ -212,7 +207,7 @@ void fill_ctx_params(godec_ctx* c, int64_t m, int64_t n, int32_t r, int64_t k,
   c->f64 = dtype == GODEC_F64;
   c->ta = c->f64 ? 8 : 4;
   c->num_cu = num_cu;
-  Sizes s = plan_sizes(m, n, k, num_cu);
+  PanelPlan s = plan_sizes(m, n, k, num_cu);
   c->ldd = s.ldd; c->mpad = s.mpad; c->nchunks = s.nchunks; c->rows_per_chunk = s.rpc;
   c->cap = s.cap;
   c->kc_a = s.kc_a; c->nct_a = s.nct_a; c->rc_b = s.rc_b; c->nch_b = s.nch_b;

@@ -408,4 +408,20 @@ void lf_qbar(const Launch& L, bool f64, int nb, int n, int r, const void* LtB, c
 void lf_pterm(const Launch& L, bool f64, int nb, int n, int r, const void* Zj, const double* rc,
               const double* rtot, const void* cur, void* Vf, int w, int col);
 
+// ---- GreBsmo (k_grebsmo.hip) ----
+// Blocks of the soft pass (= partial triples it writes).
+int64_t gb_soft_blocks(int64_t m, int64_t n);
+// Soft-thresholding pass of Eq. 12 with L = U V (U m x RP, Vt = V^T ldd x RP
+// panels): D <- X - S, optionally R <- X - U V - S (padded layout, ld ldd),
+// stats[0..2] <- sum e^2, sum |s|, nnz(S) (deterministic order, through part).
+void gb_soft(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, const void* U,
+             const void* Vt, int64_t m, int64_t n, double lam, void* D, int64_t ldd, void* R,
+             double* part, double* stats);
+// The same S written densely to S (ld lds).
+void gb_soft_s(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, const void* U,
+               const void* Vt, int64_t m, int64_t n, double lam, void* S, int64_t lds);
+// Vt[:, c0 + c] <- P[:, c], c < cnt (rows x RP panels).
+void gb_put_cols(const Launch& L, bool f64, int rp, const void* P, int64_t rows, int c0,
+                 int cnt, void* Vt);
+
 }  // namespace godec

@@ -33,6 +33,14 @@ struct Carver {
 
 int device_cu_count();
 
+// Padded shapes and tilings of the panel passes over an m x n matrix (k: the
+// cardinality bound, which sizes the candidate buffer of the sparse step).
+struct PanelPlan {
+  int64_t ldd, mpad, nchunks, rpc, cap;
+  int64_t kc_a, nct_a, rc_b, nch_b;   // matrix-core tilings
+};
+PanelPlan plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu);
+
 // Enqueue (on the batch's stream) a copy of every problem's current S list:
 // problem i's entries, in selection order, to idx_dev/val_dev + i * kstride,
 // and its length to nnz_dev[i].

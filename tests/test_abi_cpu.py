@@ -115,6 +115,46 @@ def test_init_rejects_null_pointers_without_touching_the_gpu(lib):
     assert st == 1                       # workspace misaligned
 
 
+@pytest.mark.parametrize("args,code", [
+    ((0, 10, 1), 1), ((10, 0, 1), 1), ((10, 10, 0), 1), ((10, 8, 9), 1),
+    ((100, 100, 33), 6),
+])
+def test_grebsmo_workspace_size_rejects_bad_arguments(lib, args, code):
+    with pytest.raises(b.GodecError) as ei:
+        b.godec_grebsmo_workspace_size(*args, b.GODEC_F32)
+    assert ei.value.status == code
+
+
+def test_grebsmo_workspace_size_grows(lib):
+    a = b.godec_grebsmo_workspace_size(100, 80, 4, b.GODEC_F32)
+    c = b.godec_grebsmo_workspace_size(1000, 800, 4, b.GODEC_F32)
+    assert 0 < a < c
+    # D and R, both m x round_up(n, 128) in the dtype of X
+    assert c >= 2 * 1000 * 896 * 4
+    assert b.godec_grebsmo_workspace_size(1000, 800, 4, b.GODEC_F64) > c
+
+
+@pytest.mark.parametrize("dr,power,lam", [(0, 2, 0.1), (1, 0, 0.1), (1, 2, -1.0),
+                                          (1, 2, float("nan")), (1, 2, float("inf"))])
+def test_grebsmo_init_rejects_bad_parameters_without_touching_the_gpu(lib, dr, power, lam):
+    h = ctypes.c_void_p()
+    st = lib.godec_grebsmo_init(ctypes.byref(h), 4096, 1, 10, 10, 10, 2, dr, power, lam, 0,
+                                None, 4096, 1 << 20, None)
+    assert st == 1 and not h.value
+
+
+def test_grebsmo_init_rejects_null_and_misaligned(lib):
+    h = ctypes.c_void_p()
+    assert lib.godec_grebsmo_init(ctypes.byref(h), None, 1, 10, 10, 10, 2, 1, 2, 0.1, 0,
+                                  None, 4096, 1 << 20, None) == 1
+    assert lib.godec_grebsmo_init(ctypes.byref(h), 4096, 1, 10, 10, 9, 2, 1, 2, 0.1, 0,
+                                  None, 4096, 1 << 20, None) == 1       # ldx < n
+    assert lib.godec_grebsmo_init(ctypes.byref(h), 4096, 1, 10, 10, 10, 2, 1, 2, 0.1, 0,
+                                  None, 4096 + 16, 1 << 20, None) == 1  # workspace misaligned
+    assert lib.godec_grebsmo_init(ctypes.byref(h), 4096, 1, 10, 10, 10, 2, 1, 2, 0.1, 0,
+                                  None, 4096, 64, None) == 2            # workspace too small
+
+
 def test_product_path_has_no_oracle_dependency():
     """The package never imports the oracle (it is test infrastructure)."""
     pkg = os.path.join(ROOT, "paper_1309_0302_amd")

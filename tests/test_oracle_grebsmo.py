@@ -234,7 +234,7 @@ def test_unmutated_oracle_passes_the_pins():
     (g.inner_step, "V = U.T @ D", "V = U.T @ X"),                     # dropped S
     (g.inner_step, "X - U @ V, lam", "X - S - U @ V, lam"),           # S counted twice
     (g.greedy_directions, "orth(R.T @ (R @ Z))", "orth(R.T @ Z[:R.shape[0]])"),
-    (g.grebsmo, "R = X - U @ V - S", "R = X - U @ V"),                 # dropped S in dF/dV
+    (g.grebsmo_stage, "R = X - U @ V - S", "R = X - U @ V"),           # dropped S in dF/dV
 ])
 def test_planted_mistake_is_caught(func, old, new):
     ns = _mutant(func, old, new)
