@@ -100,6 +100,14 @@ PanelPlan godec_host::plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
   // strips x chunks within one round of 2 * num_cu resident blocks, so no
   // block of a pass waits for a second round.
   s.kc_a = 1152;
+  // Narrow matrices: with 128-row blocks one column tile can leave CUs idle,
+  // so the tile narrows (512, then 256 columns) until the pass has at least
+  // 1.5 blocks per CU (25 344 x 500: 198 -> 396 blocks, measured 5% faster).
+  const int64_t rblocks = (s.mpad + 127) / 128;
+  for (int64_t kc : {512, 256}) {
+    if (2 * rblocks * ((s.ldd + s.kc_a - 1) / s.kc_a) >= 3LL * num_cu) break;
+    s.kc_a = kc;
+  }
   s.nct_a = (s.ldd + s.kc_a - 1) / s.kc_a;
   const int64_t strips = s.ldd / 128;
   int64_t nch = std::max<int64_t>(1, (2LL * num_cu) / strips);

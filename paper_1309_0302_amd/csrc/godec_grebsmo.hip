@@ -145,8 +145,10 @@ void greedy_step(godec_grebsmo* g) {
   launch_small_init(L, g->st, c1);
 }
 
-// One inner iteration of Eq. 13; with_r: also write R for the next stage.
-void inner_step(godec_grebsmo* g, bool with_r) {
+// One inner iteration of Eq. 13.  last: the stage's last one, which also
+// writes R (when another stage may follow) and the statistics.
+void inner_step(godec_grebsmo* g, bool last) {
+  const bool with_r = last && g->rank < g->r;
   const Launch L = launch_of(g);
   const int64_t ldd = g->pl.ldd, mpad = g->pl.mpad, m = g->m;
   // W = D V^T
@@ -175,7 +177,7 @@ void inner_step(godec_grebsmo* g, bool with_r) {
   }
   // S = S_lambda(X - U V), D = X - S (and R = X - U V - S)
   gb_soft(L, g->f64, g->rp, g->X, g->ldx, g->U, g->Vt, m, g->n, g->lambda, g->D, ldd,
-          with_r ? g->R : nullptr, g->part, g->stats);
+          with_r ? g->R : nullptr, last ? g->part : nullptr, last ? g->stats : nullptr);
   g->inner += 1;
 }
 
@@ -183,8 +185,7 @@ godec_status run_stage(godec_grebsmo* g, int32_t K) {
   if (K < 1) return fail(GODEC_E_INVAL, "K must be >= 1");
   if (g->rank >= g->r) return fail(GODEC_E_STATE, "rank bound reached");
   greedy_step(g);
-  const bool more = g->rank < g->r;
-  for (int k = 0; k < K; ++k) inner_step(g, more && k == K - 1);
+  for (int k = 0; k < K; ++k) inner_step(g, k == K - 1);
   g->stages += 1;
   HIP_TRY(hipGetLastError());
   return GODEC_OK;

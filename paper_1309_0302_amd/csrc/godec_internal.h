@@ -413,7 +413,8 @@ void lf_pterm(const Launch& L, bool f64, int nb, int n, int r, const void* Zj, c
 int64_t gb_soft_blocks(int64_t m, int64_t n);
 // Soft-thresholding pass of Eq. 12 with L = U V (U m x RP, Vt = V^T ldd x RP
 // panels): D <- X - S, optionally R <- X - U V - S (padded layout, ld ldd),
-// stats[0..2] <- sum e^2, sum |s|, nnz(S) (deterministic order, through part).
+// stats[0..2] <- sum e^2, sum |s|, nnz(S) (deterministic order, through part;
+// both null: no statistics).
 void gb_soft(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, const void* U,
              const void* Vt, int64_t m, int64_t n, double lam, void* D, int64_t ldd, void* R,
              double* part, double* stats);

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(kSoftCols) void kg_soft(const TA* __restrict__ X, i
     }
   }
   if constexpr (MODE == 0) {
+    if (part == nullptr) return;   // uniform: no statistics wanted
     __shared__ double red[3][kSoftCols / 64];
     e2 = wave_sum(e2);
     l1 = wave_sum(l1);
@@ -154,8 +155,9 @@ void gb_soft(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, cons
                          (float)lam, (float*)D, ldd, (float*)R, (float*)nullptr, (int64_t)0,
                          part);
   });
-  hipLaunchKernelGGL(kg_stats_reduce, dim3(1), dim3(256), 0, L.stream, part,
-                     gb_soft_blocks(m, n), stats);
+  if (stats != nullptr)
+    hipLaunchKernelGGL(kg_stats_reduce, dim3(1), dim3(256), 0, L.stream, part,
+                       gb_soft_blocks(m, n), stats);
 }
 
 void gb_soft_s(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, const void* U,

@@ -325,16 +325,45 @@ __global__ __launch_bounds__(256) void k_reduce_w(const float* __restrict__ Wtpa
   }
 }
 
-// Zo (rows x rp, f32) = sum_ch Zpart[ch] (ldd x 32).
+// Zo (ldd x rp, f32) = sum_ch Zpart[ch] (ldd x 32).  One block per 16
+// consecutive outputs e = c * rp + j: each of 16 chunk lanes adds every 16th
+// chunk (ascending), then the lane sums are added in lane order, so the
+// result does not depend on scheduling.  Many short chains instead of one
+// long one per output keep enough loads in flight when there are many
+// chunks and few outputs (narrow matrices).
+constexpr int kRzVals = 16;
+constexpr int kRzLanes = 16;
 __global__ __launch_bounds__(256) void k_reduce_z(const float* __restrict__ Zpart, int64_t nch,
                                                   int64_t ldd, int rp, float* __restrict__ Zo) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= ldd * rp) return;
-  const int64_t c = e / rp;
-  const int j = (int)(e % rp);
+  __shared__ float red[kRzLanes][kRzVals];
+  const int v = threadIdx.x % kRzVals, hl = threadIdx.x / kRzVals;
+  const int64_t e = (int64_t)blockIdx.x * kRzVals + v;
+  const bool live = e < ldd * rp;
   float s = 0.f;
-  for (int64_t h = 0; h < nch; ++h) s += Zpart[(h * ldd + c) * 32 + j];
-  Zo[e] = s;
+  if (live) {
+    const float* p = Zpart + (e / rp) * 32 + (e % rp);
+    const int64_t step = ldd * 32;
+    int64_t h = hl;
+    for (; h + 3 * kRzLanes < nch; h += 4 * kRzLanes) {
+      const float a0 = p[h * step];
+      const float a1 = p[(h + kRzLanes) * step];
+      const float a2 = p[(h + 2 * kRzLanes) * step];
+      const float a3 = p[(h + 3 * kRzLanes) * step];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; h < nch; h += kRzLanes) s += p[h * step];
+  }
+  red[hl][v] = s;
+  __syncthreads();
+  if (hl == 0 && live) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kRzLanes; ++q) t += red[q][v];
+    Zo[e] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -389,8 +418,8 @@ void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t m
 
 void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
                    float* Zo) {
-  hipLaunchKernelGGL(k_reduce_z, dim3(blocks_for(ldd * rp)), dim3(256), 0, L.stream, Zpart, nch,
-                     ldd, rp, Zo);
+  const unsigned b = (unsigned)((ldd * rp + kRzVals - 1) / kRzVals);
+  hipLaunchKernelGGL(k_reduce_z, dim3(b), dim3(256), 0, L.stream, Zpart, nch, ldd, rp, Zo);
 }
 
 }  // namespace godec
