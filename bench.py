@@ -224,12 +224,13 @@ def run_layer(warmup, seed=1005):
 
 def grebsmo_bytes(m, n, r, dr, K, power, elem=4):
     """Algorithmic bytes of one GreBsmo solve: per stage the greedy step's
-    power Gram passes (two reads of R each), per inner iteration the two
-    panel passes (reads of D) and the soft pass (read X, write D), and the R
+    power Gram passes (two reads of R each), one read of D for the stage's
+    first D V^T, and per inner iteration the transposed pass (read D) and the
+    soft pass (read X, write D; it also forms the next D V^T), plus the R
     write of every stage but the last."""
     stages = -(-r // dr)
     mn = m * n * elem
-    return stages * (2 * power + 4 * K) * mn + (stages - 1) * mn
+    return stages * (2 * power + 1 + 3 * K) * mn + (stages - 1) * mn
 
 
 def run_grebsmo(warmup, seed=1007):

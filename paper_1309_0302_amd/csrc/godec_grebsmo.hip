@@ -38,6 +38,7 @@ struct godec_grebsmo {
   PanelPlan pl;
   // workspace
   void *D, *R;                 // mpad x ldd, zero padded
+  float* Xp;                   // FP32: X zero padded to mpad x ldd (fused soft pass)
   double* Om;                  // stage-ordered Gaussian blocks (n x cnt_s each)
   void *Vt, *U, *W, *P0, *P1;  // panels (ldd or mpad rows x RP)
   void* Zpart;                 // FP64 row-chunk partials of D^T U
@@ -53,6 +54,7 @@ struct godec_grebsmo {
   int rank = 0;
   int stages = 0;
   int64_t inner = 0;
+  bool w_ready = false;        // Wtpart holds D V^T of the current D and V
 };
 
 namespace {
@@ -83,10 +85,12 @@ size_t carve(godec_grebsmo* g, void* base) {
   g->W = cv.take((size_t)mpad * rp * ta);
   if (g->f64) {
     g->Zpart = cv.take((size_t)g->pl.nchunks * ldd * rp * ta);
+    g->Xp = nullptr;
     g->Zt = g->Wt = nullptr;
     g->Wtpart = g->Zpart32 = nullptr;
   } else {
     g->Zpart = nullptr;
+    g->Xp = (float*)cv.take((size_t)mpad * ldd * 4);
     g->Zt = cv.take((size_t)32 * ldd * 4);
     g->Wt = cv.take((size_t)32 * mpad * 4);
     g->Wtpart = (float*)cv.take((size_t)g->pl.nct_a * 32 * mpad * 4);
@@ -146,7 +150,9 @@ void greedy_step(godec_grebsmo* g) {
 }
 
 // One inner iteration of Eq. 13.  last: the stage's last one, which also
-// writes R (when another stage may follow) and the statistics.
+// writes R (when another stage may follow) and the statistics.  In FP32 with
+// r <= 8 the soft pass of every other step also forms the next step's
+// D V^T partials (mfma_soft_mm_a), so that step starts at their reduction.
 void inner_step(godec_grebsmo* g, bool last) {
   const bool with_r = last && g->rank < g->r;
   const Launch L = launch_of(g);
@@ -155,10 +161,13 @@ void inner_step(godec_grebsmo* g, bool last) {
   if (g->f64) {
     launch_apply(L, F64, g->rp, g->D, ldd, m, g->Vt, g->W);
   } else {
-    mfma_to_t(L, false, g->Vt, ldd, g->rp, g->Zt);
-    mfma_mm_a(L, false, g->D, ldd, mpad, g->Zt, g->Wtpart, g->pl.kc_a);
+    if (!g->w_ready) {
+      mfma_to_t(L, false, g->Vt, ldd, g->rp, g->Zt);
+      mfma_mm_a(L, false, g->D, ldd, mpad, g->Zt, g->Wtpart, g->pl.kc_a);
+    }
     mfma_reduce_w(L, false, g->Wtpart, (int)g->pl.nct_a, mpad, m, g->rp, nullptr, (float*)g->W);
   }
+  g->w_ready = false;
   // U = orth(W): two Cholesky QR rounds; the second also writes U^T for the
   // matrix-core pass
   launch_gram_tree(L, g->f64, g->rp, g->W, m, g->Gpart, g->gram_ctl, 1, g->st, nullptr, 0, 0);
@@ -176,8 +185,15 @@ void inner_step(godec_grebsmo* g, bool last) {
     mfma_reduce_z(L, g->Zpart32, g->pl.nch_b, ldd, g->rp, (float*)g->Vt);
   }
   // S = S_lambda(X - U V), D = X - S (and R = X - U V - S)
-  gb_soft(L, g->f64, g->rp, g->X, g->ldx, g->U, g->Vt, m, g->n, g->lambda, g->D, ldd,
-          with_r ? g->R : nullptr, last ? g->part : nullptr, last ? g->stats : nullptr);
+  if (!last && !g->f64) {
+    mfma_to_t(L, false, g->Vt, ldd, g->rp, g->Zt);
+    g->w_ready = mfma_soft_mm_a(L, g->rp, g->Xp, ldd, mpad, (const float*)g->U,
+                                (const float*)g->Vt, (float)g->lambda, (float*)g->D,
+                                (const float*)g->Zt, g->Wtpart, g->pl.kc_a);
+  }
+  if (!g->w_ready)
+    gb_soft(L, g->f64, g->rp, g->X, g->ldx, g->U, g->Vt, m, g->n, g->lambda, g->D, ldd,
+            with_r ? g->R : nullptr, last ? g->part : nullptr, last ? g->stats : nullptr);
   g->inner += 1;
 }
 
@@ -270,6 +286,7 @@ godec_status godec_grebsmo_init(godec_grebsmo** out, const void* X_dev, godec_dt
   if (e == hipSuccess) e = hipMemsetAsync(g->nonfinite, 0, 8, g->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
   launch_init_d(L, g->f64 ? F64 : F32, g->f64, g->D, ldd, X_dev, ldx, m, n, mpad);
+  if (g->Xp) launch_init_d(L, F32, false, g->Xp, ldd, X_dev, ldx, m, n, mpad);
   launch_small_init(L, g->st, 1);
   launch_norm_check(L, g->f64, X_dev, ldx, m, n, g->stats + 3, g->nonfinite);
   e = hipGetLastError();

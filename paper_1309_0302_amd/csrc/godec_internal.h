@@ -217,6 +217,13 @@ void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t m
                hipEvent_t ev_b = nullptr);
 void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
                    float* Zo);
+// GreBsmo: D <- Xp - S_lambda(Xp - U V) (Xp: X zero padded to mpad x ldd, U
+// mpad x RP, Vt = V^T ldd x RP) and, in the same pass, the column-tile
+// partials Wtpart of (D V^T)^T with Zt = (V^T)^T.  Returns false (nothing
+// launched) when rp > 8.
+bool mfma_soft_mm_a(const Launch& L, int rp, const float* Xp, int64_t ldd, int64_t mpad,
+                    const float* U, const float* Vt, float lam, float* D, const float* Zt,
+                    float* Wtpart, int64_t KC);
 
 void launch_cast_panel(const Launch& L, bool f64, int rp, const void* src,
                        int64_t rows, int r, void* dst);

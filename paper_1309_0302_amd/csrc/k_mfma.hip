@@ -164,6 +164,110 @@ __global__ __launch_bounds__(256) void k_mm_a_f32(const float* __restrict__ D, i
 }
 
 // ---------------------------------------------------------------------------
+// k_soft_mm_a_f32 (GreBsmo, Sec. 3.2.1): the soft-thresholding pass of Eq. 12
+// fused with the next inner iteration's D V^T (Eq. 13).  Same tiling as
+// k_mm_a_f32, but the slab read from HBM is the zero-padded copy Xp of X:
+// every 16-byte chunk (four columns of one row) is turned into
+//   d = x - S_lambda(x - u_i . v_j)
+// in registers (u_i: the thread's four rows of U, kept in registers; v_j:
+// rows of V^T read from the panel), written to D, and staged in LDS as the
+// A operand of W^T = (D V^T)^T.  Zt holds V^T transposed (the same V), so
+// one read of X replaces the soft pass plus one read of D.  Padding rows and
+// columns stay zero (U and V^T are zero there).  RP <= 8.
+// ---------------------------------------------------------------------------
+template <int RP>
+__device__ __forceinline__ void soft_load_v(const float* __restrict__ Vt, int64_t col0,
+                                            float (&v)[4][RP]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < RP; ++c) v[e][c] = Vt[(col0 + e) * RP + c];
+}
+
+template <int RP>
+__device__ __forceinline__ void soft_chunks(u32x4 (&st)[4], const float (&u)[4][RP],
+                                            const float (&v)[4][RP], float lam,
+                                            float* __restrict__ D, int64_t ldd, int64_t mpad,
+                                            int64_t row0, int64_t col0) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int64_t row = row0 + 32 * h;
+    float d[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float l = 0.f;
+#pragma unroll
+      for (int c = 0; c < RP; ++c) l = fma_t(u[h][c], v[e][c], l);
+      const float x = __uint_as_float(st[h][e]);
+      const float res = x - l;
+      const float a = fabsf(res) - lam;
+      const float sv = a > 0.f ? copysignf(a, res) : 0.f;
+      d[e] = x - sv;
+      st[h][e] = __float_as_uint(d[e]);
+    }
+    if (row < mpad)
+      *reinterpret_cast<float4*>(D + row * ldd + col0) = make_float4(d[0], d[1], d[2], d[3]);
+  }
+}
+
+template <int RP>
+__global__ __launch_bounds__(256) void k_soft_mm_a_f32(const float* __restrict__ Xp,
+                                                       int64_t ldd, int64_t mpad,
+                                                       const float* __restrict__ U,
+                                                       const float* __restrict__ Vt,
+                                                       float lam, float* __restrict__ D,
+                                                       const float* __restrict__ Zt,
+                                                       float* __restrict__ Wtpart, int64_t KC) {
+  __shared__ u32x4 tD[2][kMmaRows * 8];
+  __shared__ u32x4 tZ[2][32 * 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, g = lane >> 5;
+  const int lr = tid >> 3, lc = tid & 7;
+  const int64_t rb = (int64_t)blockIdx.y * kMmaRows;
+  const int64_t c0 = (int64_t)blockIdx.x * KC;
+  const int64_t c1 = (c0 + KC) < ldd ? (c0 + KC) : ldd;
+  const int row = 32 * wave + i;
+  float u[4][RP], v[4][RP];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int64_t r = rb + lr + 32 * h;
+#pragma unroll
+    for (int c = 0; c < RP; ++c) u[h][c] = r < mpad ? U[r * RP + c] : 0.f;
+  }
+  u32x4 st[4], sz;
+  f32x16 acc = {};
+  mma_gload(Xp, ldd, mpad, Zt, rb, c0, lr, lc, st, sz);
+  soft_load_v<RP>(Vt, c0 + 4 * lc, v);
+  soft_chunks<RP>(st, u, v, lam, D, ldd, mpad, rb + lr, c0 + 4 * lc);
+  mma_sstore(tD[0], tZ[0], lr, lc, st, sz);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kk = c0; kk < c1; kk += 32) {
+    const bool more = kk + 32 < c1;
+    if (more) {
+      mma_gload(Xp, ldd, mpad, Zt, rb, kk + 32, lr, lc, st, sz);
+      soft_load_v<RP>(Vt, kk + 32 + 4 * lc, v);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = 2 * q + g;
+      const u32x4 av = tD[buf][row * 8 + (ch ^ (row & 7))];
+      const u32x4 bv = tZ[buf][i * 8 + (ch ^ (i & 7))];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc = mfma_f32(__uint_as_float(av[e]), __uint_as_float(bv[e]), acc);
+    }
+    if (more) {
+      soft_chunks<RP>(st, u, v, lam, D, ldd, mpad, rb + lr, kk + 32 + 4 * lc);
+      mma_sstore(tD[buf ^ 1], tZ[buf ^ 1], lr, lc, st, sz);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  mma_store_w(Wtpart, mpad, rb + 32 * wave, lane, acc);
+}
+
+// ---------------------------------------------------------------------------
 // k_mm_b: Zpart[ch] (ldd x 32, row = column of D) = (W^T D[rows of ch, :])^T.
 // Block = 4 waves on the same 128-column strip [blockIdx.x*128, +128): lane n
 // holds columns 4n .. 4n+3 of the strip, one per 32-column MFMA tile, so a
@@ -420,6 +524,26 @@ void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd
                    float* Zo) {
   const unsigned b = (unsigned)((ldd * rp + kRzVals - 1) / kRzVals);
   hipLaunchKernelGGL(k_reduce_z, dim3(b), dim3(256), 0, L.stream, Zpart, nch, ldd, rp, Zo);
+}
+
+bool mfma_soft_mm_a(const Launch& L, int rp, const float* Xp, int64_t ldd, int64_t mpad,
+                    const float* U, const float* Vt, float lam, float* D, const float* Zt,
+                    float* Wtpart, int64_t KC) {
+  dim3 grid((unsigned)((ldd + KC - 1) / KC), (unsigned)((mpad + kMmaRows - 1) / kMmaRows));
+  switch (rp) {
+#define GB_SOFT_CASE(R)                                                                      \
+  case R:                                                                                    \
+    hipLaunchKernelGGL(k_soft_mm_a_f32<R>, grid, dim3(256), 0, L.stream, Xp, ldd, mpad, U, Vt, \
+                       lam, D, Zt, Wtpart, KC);                                              \
+    return true;
+    GB_SOFT_CASE(1)
+    GB_SOFT_CASE(2)
+    GB_SOFT_CASE(4)
+    GB_SOFT_CASE(8)
+#undef GB_SOFT_CASE
+    default:
+      return false;
+  }
 }
 
 }  // namespace godec
