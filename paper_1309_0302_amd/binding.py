@@ -326,6 +326,7 @@ class GoDec:
         self.X = X
         self.m, self.n = X.shape
         self.r, self.k, self.q = r, k, q
+        self.seed, self.a1 = seed, a1
         self.dtype = _dtype_code(X)
         if stream is None:
             stream = torch.cuda.current_stream(X.device).cuda_stream

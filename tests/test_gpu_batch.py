@@ -9,6 +9,7 @@ row-major index, zeros excluded) of the batch's own residual of that problem.
 """
 import numpy as np
 import pytest
+from conftest import oracle_a1
 
 from oracle import godec_ref as g
 from paper_1309_0302_amd import workloads as wl
@@ -42,7 +43,7 @@ def S_dense(gb, i, shape):
 
 
 def check_problem(gb, i, w, q, S_prev, r_eff, tol=1e-5):
-    A1 = gb.A1(i)
+    A1 = oracle_a1(gb, i)
     ref = g.brp_power(w.X.astype(np.float64) - S_prev, A1[:, :r_eff], q, w.r * 2.0 ** -52)
     UL, VL = gb.factors(i)
     err = g.rel_fro_factors(UL.cpu().numpy().astype(np.float64),
@@ -168,7 +169,7 @@ def test_batch_trajectory_against_oracle():
     gb.step(25)
     gb.synchronize()
     for i, w in enumerate(works):
-        ref = g.godec_brp(w.X.astype(np.float64), w.r, w.k, 1, gb.A1(i), 25,
+        ref = g.godec_brp(w.X.astype(np.float64), w.r, w.k, 1, oracle_a1(gb, i), 25,
                           rank_tol=w.r * 2.0 ** -52)
         UL, VL = gb.factors(i)
         errL = g.rel_fro_factors(UL.cpu().numpy().astype(np.float64),

@@ -11,6 +11,7 @@ residual's.
 """
 import numpy as np
 import pytest
+from conftest import oracle_a1
 
 from oracle import godec_ref as g
 from paper_1309_0302_amd import workloads as wl
@@ -26,12 +27,11 @@ def w3():
     return wl.w3()
 
 
-def _step_and_check(gd, X64, q, k, tol, total):
+def _step_and_check(gd, X64, q, k, tol, total, A1):
     idx, val = gd.S()
     S = np.zeros(X64.size)
     S[idx.cpu().numpy()] = val.cpu().numpy().astype(np.float64)
     r_eff = gd.info()["rank_eff"]
-    A1 = gd.A1()
     gd.step(1, total)
     torch.cuda.synchronize()
     D = X64 - S.reshape(X64.shape)
@@ -63,10 +63,11 @@ def test_w3_bf16_refine_per_step(w3):
     gd = GoDec(X, w3.r, w3.k, w3.q, seed=w3.seed, prec=GODEC_PREC_BF16_REFINE,
                refine_iters=1)
     X64 = w3.X.astype(np.float64)
+    A1 = oracle_a1(gd)
     total = 3
     for t, tol in enumerate((2e-3, 2e-3, 1e-5)):
         print(f"[fullsize] bf16+refine iteration {t} of {total}", flush=True)
-        _step_and_check(gd, X64, w3.q, w3.k, tol, total)
+        _step_and_check(gd, X64, w3.q, w3.k, tol, total, A1)
     gd.close()
 
 
@@ -75,7 +76,8 @@ def test_w3_fp32_plain_per_step(w3):
     X = torch.from_numpy(w3.X).cuda()
     gd = GoDec(X, w3.r, w3.k, w3.q, seed=w3.seed)
     X64 = w3.X.astype(np.float64)
+    A1 = oracle_a1(gd)
     for t in range(2):
         print(f"[fullsize] fp32 iteration {t}", flush=True)
-        _step_and_check(gd, X64, w3.q, w3.k, 1e-5, 0)
+        _step_and_check(gd, X64, w3.q, w3.k, 1e-5, 0, A1)
     gd.close()

@@ -22,6 +22,7 @@ autograd; it is itself pinned to finite differences.  Checks:
 """
 import numpy as np
 import pytest
+from conftest import oracle_a1
 
 from oracle import godec_layer_ref as lr
 from oracle import godec_ref as g
@@ -66,7 +67,7 @@ def test_layer_fp64_matches_finite_differences(q, T):
     Xd = torch.from_numpy(X).cuda().unsqueeze(0).contiguous()
     layer, L, S = gpu_layer(Xd, 2, 150, q, T, 7)
     masks = masks_of(layer, 0, T)
-    A1 = layer.A1(0)
+    A1 = oracle_a1(layer, 0)
     # forward against the oracle's frozen-mask forward
     Lr, Sr = lr.layer_forward(torch.tensor(X), torch.tensor(A1), q, masks)
     assert g.rel_fro(L[0].cpu().numpy(), Lr.numpy()) < 1e-10
@@ -118,7 +119,7 @@ def test_layer_autograd_function_fp64():
     ref_layer.forward(X.detach())
     for b in range(2):
         masks = masks_of(ref_layer, b, T)
-        A1 = ref_layer.A1(b)
+        A1 = oracle_a1(ref_layer, b)
         dL = 2 * (L[b].detach().cpu().numpy() - Lt[b])
         dS = 2 * (S[b].detach().cpu().numpy() - St[b])
         ref = lr.layer_grad(Xs[b], A1, q, masks, dL, dS)
@@ -146,7 +147,7 @@ def test_layer_fp32_full_workload_sampled():
     for b in range(2):
         masks = masks_of(layer, b, w["iters"])
         assert all(mk.size == w["k"] for mk in masks)
-        A1 = layer.A1(b)
+        A1 = oracle_a1(layer, b)
         Xb = w["X"][b].astype(np.float64)
         Lr, Sr = lr.layer_forward(torch.tensor(Xb), torch.tensor(A1), w["q"], masks)
         eL = g.rel_fro(L[b].cpu().numpy().astype(np.float64), Lr.numpy())
@@ -187,7 +188,7 @@ def test_layer_fp32_wide_problems_single_path():
     dX = layer.backward(dL, dS)
     for b in range(2):
         masks = masks_of(layer, b, 5)
-        A1 = layer.A1(b)
+        A1 = oracle_a1(layer, b)
         ref = lr.layer_grad(Xs[b].astype(np.float64), A1, 1, masks,
                             dL[b].cpu().numpy().astype(np.float64),
                             dS[b].cpu().numpy().astype(np.float64))
@@ -213,7 +214,7 @@ def test_layer_fp64_tall_panels():
     dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
     for b in range(2):
         masks = masks_of(layer, b, 3)
-        ref = lr.layer_grad(Xs[b], layer.A1(b), 1, masks, dL[b], dS[b])
+        ref = lr.layer_grad(Xs[b], oracle_a1(layer, b), 1, masks, dL[b], dS[b])
         got = dX[b].cpu().numpy()
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"[layer] FP64 tall problem {b}: gradient {err:.2e}", flush=True)
@@ -236,7 +237,7 @@ def test_layer_fp32_rank8_widest_batched():
     dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
     for b in range(3):
         masks = masks_of(layer, b, 3)
-        ref = lr.layer_grad(Xs[b].astype(np.float64), layer.A1(b), 1, masks,
+        ref = lr.layer_grad(Xs[b].astype(np.float64), oracle_a1(layer, b), 1, masks,
                             dL[b].astype(np.float64), dS[b].astype(np.float64))
         got = dX[b].cpu().numpy().astype(np.float64)
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
@@ -260,7 +261,7 @@ def test_layer_fp64_wider_than_row_pass():
     dX = layer.backward(torch.from_numpy(dL).cuda(), torch.from_numpy(dS).cuda())
     for b in range(2):
         masks = masks_of(layer, b, 2)
-        ref = lr.layer_grad(Xs[b], layer.A1(b), 1, masks, dL[b], dS[b])
+        ref = lr.layer_grad(Xs[b], oracle_a1(layer, b), 1, masks, dL[b], dS[b])
         got = dX[b].cpu().numpy()
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"[layer] FP64 n=160 problem {b}: gradient {err:.2e}", flush=True)

@@ -10,6 +10,7 @@ the GPU's precision on both sides), and the values must be the residual's.
 """
 import numpy as np
 import pytest
+from conftest import oracle_a1
 
 from oracle import godec_ref as g
 from paper_1309_0302_amd import workloads as wl
@@ -49,7 +50,7 @@ def per_step(X, r, k, q, iters, tol, *, seed=7, prec=0, refine_iters=1,
           f"iters={iters} prec={prec}", flush=True)
     gd = GoDec(dev(X), r, k, q, seed=seed, prec=prec, refine_iters=refine_iters,
                rank_tol=rank_tol or 0.0)
-    A1 = gd.A1()
+    A1 = oracle_a1(gd)
     X64 = X.astype(np.float64)
     errs = []
     try:
@@ -87,7 +88,7 @@ def test_f64_w1_trajectory_20_iterations():
     w = wl.w1()
     gd = GoDec(dev(w.X), w.r, w.k, w.q, seed=w.seed)
     gd.step(w.iters)
-    ref = g.godec_brp(w.X, w.r, w.k, w.q, gd.A1(), w.iters)
+    ref = g.godec_brp(w.X, w.r, w.k, w.q, oracle_a1(gd), w.iters)
     L = gd.L_dense().cpu().numpy()
     S = gpu_S(gd, w.X.shape)
     assert g.rel_fro(L, ref.L) < 1e-10
@@ -129,7 +130,7 @@ def test_f32_w2_video_trajectory():
     w = wl.w2()
     gd = GoDec(dev(w.X), w.r, w.k, w.q, seed=w.seed)
     gd.step(w.iters)
-    ref = g.godec_brp(w.X.astype(np.float64), w.r, w.k, w.q, gd.A1(), w.iters)
+    ref = g.godec_brp(w.X.astype(np.float64), w.r, w.k, w.q, oracle_a1(gd), w.iters)
     L = gd.L_dense().cpu().numpy().astype(np.float64)
     S = gpu_S(gd, w.X.shape)
     errL = g.rel_fro(L, ref.L)
