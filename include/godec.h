@@ -78,6 +78,17 @@ typedef struct {
   const double* a1_host;  /* optional n x r row-major A1 replacing the seeded
                              draw (test hook); copied during godec_init */
   void* stream;           /* hipStream_t, NULL = default stream */
+  /* Matrix completion (Sec. 2: the cardinality constraint replaced by a fixed
+   * support set).  When support_nnz > 0 or support_dev != NULL, the S update
+   * is S_t = P_support(X - L_t) on the support_nnz row-major linear indices
+   * i*n + j at support_dev (device memory, strictly ascending, in [0, m*n),
+   * borrowed and unmodified until destroy; checked during godec_init).  The
+   * support is the set of unobserved entries: D = X - S_t then holds X on
+   * the observed entries and L_t on the others.  Requires k == support_nnz
+   * and prec NATIVE.  info.rel_err_sq is the squared error on the observed
+   * entries over ||X||_F^2; info.threshold is 0. */
+  const int64_t* support_dev;
+  int64_t support_nnz;
 } godec_opts;
 
 typedef struct {

@@ -28,7 +28,8 @@ class godec_opts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("prec", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("rank_tol", ctypes.c_double), ("a1_host", ctypes.c_void_p),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("support_dev", ctypes.c_void_p),
+                ("support_nnz", ctypes.c_int64)]
 
 
 class godec_info(ctypes.Structure):
@@ -172,7 +173,9 @@ def _dtype_code(t):
 
 
 def make_opts(prec=GODEC_PREC_NATIVE, refine_iters=1, rank_tol=0.0, a1=None,
-              stream=None):
+              stream=None, support=None):
+    """support: optional int64 device tensor of strictly ascending linear
+    indices (matrix completion: the fixed support of S)."""
     o = godec_opts()
     load().godec_opts_default(ctypes.byref(o))
     o.prec = prec
@@ -183,6 +186,12 @@ def make_opts(prec=GODEC_PREC_NATIVE, refine_iters=1, rank_tol=0.0, a1=None,
         keep = np.ascontiguousarray(a1, dtype=np.float64)
         o.a1_host = keep.ctypes.data
     o.stream = stream
+    if support is not None:
+        import torch
+        if not support.is_cuda or support.dtype != torch.int64 or not support.is_contiguous():
+            raise ValueError("support must be a contiguous int64 device tensor")
+        o.support_dev = support.data_ptr() if support.numel() else None
+        o.support_nnz = support.numel()
     return o, keep
 
 
@@ -317,7 +326,7 @@ class GoDec:
     """One decomposition of a CUDA/HIP tensor X (float32 or float64)."""
 
     def __init__(self, X, r, k, q, seed=0, prec=GODEC_PREC_NATIVE,
-                 refine_iters=1, rank_tol=0.0, a1=None, stream=None):
+                 refine_iters=1, rank_tol=0.0, a1=None, stream=None, support=None):
         import torch
         if not X.is_cuda:
             raise ValueError("X must be a device tensor")
@@ -330,8 +339,9 @@ class GoDec:
         self.dtype = _dtype_code(X)
         if stream is None:
             stream = torch.cuda.current_stream(X.device).cuda_stream
+        self.support = support
         self.opts, self._a1_keep = make_opts(prec, refine_iters, rank_tol, a1,
-                                             stream)
+                                             stream, support)
         self.ws_bytes = godec_workspace_size(self.m, self.n, r, k, q,
                                              self.dtype, self.opts)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,

@@ -41,6 +41,9 @@ struct godec_ctx {
   const void* X;
   hipStream_t stream;
   int num_cu;
+  const int64_t* support = nullptr;   // completion: fixed support of S
+  int64_t support_nnz = 0;
+  bool completion = false;
   bool f64;            // panel / residual type is double
   size_t ta;           // sizeof panel type
   // workspace
@@ -200,6 +203,15 @@ godec_status validate(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
     if (o->prec == GODEC_PREC_BF16_REFINE && dtype != GODEC_F32)
       return fail(GODEC_E_INVAL, "BF16_REFINE needs an FP32 X");
     if (o->refine_iters < 0) return fail(GODEC_E_INVAL, "refine_iters < 0");
+    if (o->support_dev != nullptr || o->support_nnz != 0) {
+      if (o->support_nnz < 0 || o->support_nnz > m * n)
+        return fail(GODEC_E_INVAL, "need 0 <= support_nnz <= m*n");
+      if (o->support_nnz > 0 && o->support_dev == nullptr)
+        return fail(GODEC_E_INVAL, "support_dev is NULL");
+      if (o->support_nnz != k) return fail(GODEC_E_INVAL, "completion needs k == support_nnz");
+      if (o->prec != GODEC_PREC_NATIVE)
+        return fail(GODEC_E_UNSUPPORTED, "completion runs in the NATIVE precision form");
+    }
   }
   return GODEC_OK;
 }
@@ -422,7 +434,12 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
     a.ev_b = prof_event(c);
     if (a.ev_a && a.ev_b) c->recs.push_back({PC_SEL_PASS, a.ev_a, a.ev_b});
   }
-  launch_select(L, c->f64, c->rp, a);
+  if (c->completion)
+    launch_fixed_support(L, c->f64, c->rp, c->X, c->ldx, c->UL, c->VL, c->m, c->n, c->support,
+                         c->support_nnz, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
+                         c->plan[nxt], (double*)c->hist);
+  else
+    launch_select(L, c->f64, c->rp, a);
   // ---- D update: restore X on the old support, X - S on the new one ----
   const bool upd_native = c->d_native_valid;
   if (c->iters_done > 0) {
@@ -517,6 +534,26 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   }
   c->num_cu = device_cu_count();
   carve(c, ws);
+  if (opts && (opts->support_dev != nullptr || opts->support_nnz != 0)) {
+    // the fixed support must be strictly ascending and inside the matrix
+    c->completion = true;
+    c->support = opts->support_dev;
+    c->support_nnz = opts->support_nnz;
+    if (c->support_nnz > 0) {
+      std::vector<int64_t> h((size_t)c->support_nnz);
+      hipError_t e = hipMemcpy(h.data(), c->support, sizeof(int64_t) * h.size(),
+                               hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        delete c;
+        return fail(GODEC_E_DEVICE, hipGetErrorString(e));
+      }
+      for (size_t q = 0; q < h.size(); ++q)
+        if (h[q] < 0 || h[q] >= m * n || (q > 0 && h[q] <= h[q - 1])) {
+          delete c;
+          return fail(GODEC_E_INVAL, "support must be strictly ascending in [0, m*n)");
+        }
+    }
+  }
   c->a1_host.resize((size_t)n * r);
   if (opts && opts->a1_host)
     std::memcpy(c->a1_host.data(), opts->a1_host, sizeof(double) * n * r);

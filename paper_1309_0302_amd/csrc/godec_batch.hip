@@ -74,6 +74,8 @@ godec_status validate_batch(const godec_problem* probs, int32_t count, int32_t q
   if (opts && opts->size != sizeof(godec_opts)) return fail(GODEC_E_INVAL, "opts->size mismatch");
   if (opts && opts->prec != GODEC_PREC_NATIVE)
     return fail(GODEC_E_UNSUPPORTED, "the batched form runs FP32 only (prec NATIVE)");
+  if (opts && (opts->support_dev || opts->support_nnz))
+    return fail(GODEC_E_UNSUPPORTED, "the batched form has no fixed-support (completion) form");
   for (int i = 0; i < count; ++i) {
     const godec_problem& P = probs[i];
     const std::string at = " (problem " + std::to_string(i) + ")";

@@ -415,6 +415,16 @@ void lf_qbar(const Launch& L, bool f64, int nb, int n, int r, const void* LtB, c
 void lf_pterm(const Launch& L, bool f64, int nb, int n, int r, const void* Zj, const double* rc,
               const double* rtot, const void* cur, void* Vf, int w, int col);
 
+// ---- matrix completion (k_complete.hip) ----
+// S update on a fixed support: lists s_idx / s_val / s_x and plan (nnz,
+// sum_r2, sum_sel2) as the selection would leave them.  scratch: at least
+// fixed_support_scratch_doubles() doubles.
+void launch_fixed_support(const Launch& L, bool f64, int rp, const void* X, int64_t ldx,
+                          const void* UL, const void* VL, int64_t m, int64_t n,
+                          const int64_t* support, int64_t nnz, int64_t* s_idx, void* s_val,
+                          void* s_x, SelPlan* plan, double* scratch);
+int64_t fixed_support_scratch_doubles();
+
 // ---- GreBsmo (k_grebsmo.hip) ----
 // Blocks of the soft pass (= partial triples it writes).
 int64_t gb_soft_blocks(int64_t m, int64_t n);

@@ -1,0 +1,143 @@
+"""GPU parity of GoDec matrix completion (Sec. 2: the S update on a fixed
+support set) against the FP64 oracle, through the C ABI.
+
+Per step: the GPU's own S_{t-1} is fed to the oracle's L update with the
+oracle's A1, and L_t must match within 1e-10 (FP64) / 1e-5 (FP32), the
+relative Frobenius bars of the BRP path.  The S list must be the given
+support, bit for bit, and its values the GPU's own residual at those
+entries, bit for bit.  Trajectories: a rank-3 matrix with 30 % of its entries
+missing is completed to 1e-10 by both the GPU and the oracle.
+"""
+import numpy as np
+import pytest
+from conftest import oracle_a1
+
+from oracle import completion_ref as cr
+from oracle import godec_ref as g
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).cuda()
+
+
+def case(m, n, r, frac, seed, dtype=np.float64, noise=0.0):
+    rng = np.random.default_rng(seed)
+    X0 = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    X0 += noise * rng.standard_normal((m, n))
+    miss = np.sort(rng.choice(m * n, size=int(round(frac * m * n)), replace=False))
+    X = X0.copy()
+    X.flat[miss] = 0.0
+    return X0.astype(dtype), X.astype(dtype), miss
+
+
+def make(X, r, q, miss, seed):
+    from paper_1309_0302_amd.binding import GoDec
+    sup = torch.from_numpy(miss.astype(np.int64)).cuda()
+    return GoDec(dev(X), r, int(miss.size), q, seed=seed, support=sup)
+
+
+def per_step(X, r, q, miss, iters, tol, seed=3):
+    print(f"\n[completion] shape={X.shape} dtype={X.dtype} r={r} q={q} missing={miss.size} "
+          f"iters={iters}", flush=True)
+    gd = make(X, r, q, miss, seed)
+    A1 = oracle_a1(gd)
+    X64 = X.astype(np.float64)
+    S = np.zeros_like(X64)
+    errs = []
+    for t in range(iters):
+        r_eff = gd.info()["rank_eff"]
+        gd.step(1)
+        torch.cuda.synchronize()
+        ref = g.brp_power(X64 - S, A1[:, :r_eff], q)
+        L = gd.L_dense().cpu().numpy().astype(np.float64)
+        errs.append(g.rel_fro(L, ref.L))
+        idx, val = gd.S()
+        idx = idx.cpu().numpy()
+        val = val.cpu().numpy()
+        assert np.array_equal(idx, miss), t
+        R = gd.residual().cpu().numpy()
+        assert np.array_equal(val.view(np.uint8), R.flat[miss].view(np.uint8)), t
+        S = np.zeros_like(X64)
+        S.flat[idx] = val.astype(np.float64)
+    print(f"  per-step L errors: max {max(errs):.2e}", flush=True)
+    assert max(errs) <= tol
+    gd.close()
+
+
+@pytest.mark.parametrize("m,n,r,q", [(120, 100, 3, 1), (333, 257, 5, 2), (150, 400, 4, 0)])
+def test_f64_per_step(m, n, r, q):
+    _, X, miss = case(m, n, r, 0.3, seed=m + n)
+    per_step(X, r, q, miss, 4, 1e-10)
+
+
+@pytest.mark.parametrize("m,n,r,q", [(1000, 700, 8, 1), (2001, 1503, 20, 2)])
+def test_f32_per_step(m, n, r, q):
+    _, X, miss = case(m, n, r, 0.2, seed=m + n, dtype=np.float32, noise=1e-3)
+    per_step(X, r, q, miss, 3, 1e-5)
+
+
+def test_f64_completes_like_the_oracle():
+    X0, X, miss = case(120, 100, 3, 0.3, seed=3)
+    gd = make(X, 3, 1, miss, 9)
+    gd.step(100)
+    L = gd.L_dense().cpu().numpy()
+    info = gd.info()
+    ref = cr.godec_completion(X, 3, 1, oracle_a1(gd), miss, 100)
+    eL = np.linalg.norm(L - X0) / np.linalg.norm(X0)
+    print(f"\n[completion] 100 iterations: L vs truth {eL:.2e}, vs oracle "
+          f"{np.linalg.norm(L - ref.L) / np.linalg.norm(ref.L):.2e}, rel err "
+          f"{info['rel_err_sq']:.2e} (oracle {ref.rel_err_sq[-1]:.2e})", flush=True)
+    assert eL <= 1e-10
+    assert np.linalg.norm(L - ref.L) <= 1e-10 * np.linalg.norm(ref.L)
+    assert info["rel_err_sq"] <= 1e-20 and info["nnz"] == miss.size
+    gd.close()
+
+
+def g_a1(seed, n, r):
+    from oracle.rng_ref import a1_gaussian
+    return a1_gaussian(seed, n, r)
+
+
+def test_solve_tol_stops_like_the_oracle():
+    from paper_1309_0302_amd.binding import godec_solve_tol, make_opts
+    X0, X, miss = case(120, 100, 3, 0.3, seed=4)
+    sup = torch.from_numpy(miss).cuda()
+    opts, _ = make_opts(support=sup)
+    out = godec_solve_tol(dev(X), 3, int(miss.size), 1, 11, 200, 1e-12, opts)
+    info = out[-1]
+    ref = cr.godec_completion(X, 3, 1, g_a1(11, 100, 3), miss, 200, eps=1e-12)
+    assert info["iters"] == len(ref.rel_err_sq)
+    assert info["rel_err_sq"] <= 1e-12
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "duplicate", "range", "k"])
+def test_bad_support_rejected(bad):
+    from paper_1309_0302_amd.binding import GoDec, GodecError
+    _, X, miss = case(60, 50, 2, 0.2, seed=5)
+    k = miss.size
+    if bad == "unsorted":
+        miss = miss[::-1].copy()
+    elif bad == "duplicate":
+        miss = np.concatenate([miss[:1], miss[:-1]])
+    elif bad == "range":
+        miss = miss.copy()
+        miss[-1] = 60 * 50
+    else:
+        k = k - 1
+    sup = torch.from_numpy(miss.astype(np.int64)).cuda()
+    with pytest.raises(GodecError) as ei:
+        GoDec(dev(X), 2, k, 1, support=sup)
+    assert ei.value.status == 1
+
+
+def test_bf16_form_unsupported():
+    from paper_1309_0302_amd.binding import GODEC_PREC_BF16_REFINE, GoDec, GodecError
+    _, X, miss = case(60, 50, 2, 0.2, seed=6, dtype=np.float32)
+    sup = torch.from_numpy(miss).cuda()
+    with pytest.raises(GodecError) as ei:
+        GoDec(dev(X), 2, miss.size, 1, support=sup, prec=GODEC_PREC_BF16_REFINE)
+    assert ei.value.status == 6
