@@ -296,6 +296,38 @@ def grebsmo_cpu_baseline(seed=1007):
                       f"GreBsmo workload (numpy/OpenBLAS), {dt:.1f} s"}
 
 
+def run_completion(X, w, iters, warmup, frac=0.1, seed=1008):
+    """Matrix completion (fixed support) on the 10 000 x 10 000 FP32 matrix
+    with a seeded 10 % of its entries unobserved: `iters` iterations from
+    S_0 = 0, timed on the stream with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GoDec
+    m, n = X.shape
+    sup = torch.from_numpy(workloads.missing_support(m, n, frac, seed)).cuda()
+    gd = GoDec(X, w.r, int(sup.numel()), w.q, seed=w.seed, support=sup)
+    gd.step(warmup)
+    torch.cuda.synchronize()
+    gd.close()
+    gd = GoDec(X, w.r, int(sup.numel()), w.q, seed=w.seed, support=sup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    gd.step(iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    info = gd.info()
+    gd.close()
+    return {"workload": f"m1_{m}x{n}_r{w.r}_q{w.q}_missing{frac:g}_f32",
+            "unobserved": int(sup.numel()), "iterations": iters,
+            "ms_per_iteration": round(ms / iters, 4),
+            "iter_per_s": round(iters * 1e3 / ms, 2),
+            "rel_err_sq_observed": info["rel_err_sq"]}
+
+
 def run_copy(nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of a known size: the reference against
     which the HBM byte counters of the other kernels are scaled."""
@@ -349,7 +381,8 @@ def main():
     ap.add_argument("--skip-layer", action="store_true")
     ap.add_argument("--skip-copy", action="store_true")
     ap.add_argument("--skip-grebsmo", action="store_true")
-    ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo"],
+    ap.add_argument("--skip-completion", action="store_true")
+    ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo", "completion"],
                     help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
@@ -384,6 +417,9 @@ def main():
     w = workloads.w3(seed=args.seed, m=args.size, n=args.size)
     X = torch.from_numpy(w.X).cuda()
     torch.cuda.synchronize()
+    if args.only == "completion":
+        print(json.dumps(run_completion(X, w, 10, 2)), flush=True)
+        return
     log("[bench] bf16 + refinement form")
     bf = run_form(X, w, GODEC_PREC_BF16_REFINE, args.steps, args.warmup, args.seed)
     log(f"[bench] bf16+refine {args.steps / (bf['ms'] * 1e-3):.1f} iter/s")
@@ -441,6 +477,10 @@ def main():
         out["layer"] = run_layer(min(args.warmup, 1))
         log(f"[bench] layer fwd {out['layer']['forward_ms']} ms, "
             f"bwd {out['layer']['backward_ms']} ms")
+    if not args.skip_completion:
+        log("[bench] matrix completion: 10000 x 10000, 10 % unobserved")
+        out["completion"] = run_completion(X, w, 10, 2)
+        log(f"[bench] completion {out['completion']['iter_per_s']} iter/s")
     if not args.skip_grebsmo:
         log("[bench] GreBsmo: 25344 x 500 video-shaped, r = 4")
         out["grebsmo"] = run_grebsmo(min(args.warmup, 2))

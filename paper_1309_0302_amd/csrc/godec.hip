@@ -442,7 +442,8 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
     launch_select(L, c->f64, c->rp, a);
   // ---- D update: restore X on the old support, X - S on the new one ----
   const bool upd_native = c->d_native_valid;
-  if (c->iters_done > 0) {
+  // a fixed support is rewritten in place: no restore of the old one
+  if (c->iters_done > 0 && !c->completion) {
     if (upd_native)
       launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
                       c->plan[prev], kk);
@@ -536,6 +537,10 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   carve(c, ws);
   if (opts && (opts->support_dev != nullptr || opts->support_nnz != 0)) {
     // the fixed support must be strictly ascending and inside the matrix
+    if (fixed_support_scratch_doubles() > (int64_t)kHistReplicas * kHistBins) {
+      delete c;
+      return fail(GODEC_E_UNSUPPORTED, "completion scratch exceeds the histogram buffer");
+    }
     c->completion = true;
     c->support = opts->support_dev;
     c->support_nnz = opts->support_nnz;

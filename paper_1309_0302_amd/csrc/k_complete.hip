@@ -11,7 +11,8 @@ namespace godec {
 
 namespace {
 
-constexpr int kCompBlocks = 2048;   // most blocks (= partial sums) per pass
+constexpr int kCompBlocks = 2048;   // most blocks (= partial sums) of the gather
+constexpr int kNormBlocks = 16384;  // most blocks of the residual-norm pass
 
 template <typename T>
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -31,6 +32,7 @@ template <typename T, int RP>
 __global__ __launch_bounds__(256) void kc_gather(const T* __restrict__ X, int64_t ldx,
                                                  const T* __restrict__ UL,
                                                  const T* __restrict__ VL, int64_t n,
+                                                 bool small,
                                                  const int64_t* __restrict__ support,
                                                  int64_t nnz, int64_t* __restrict__ s_idx,
                                                  T* __restrict__ s_val, T* __restrict__ s_x,
@@ -40,10 +42,32 @@ __global__ __launch_bounds__(256) void kc_gather(const T* __restrict__ X, int64_
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * 256) {
     const int64_t id = support[e];
-    const int64_t i = id / n, j = id % n;
+    int64_t i, j;
+    if (small) {   // m n < 2^32: 32-bit division (uniform branch)
+      const uint32_t q = (uint32_t)id / (uint32_t)n;
+      i = q;
+      j = (int64_t)((uint32_t)id - q * (uint32_t)n);
+    } else {
+      i = id / n;
+      j = id % n;
+    }
     T l = T(0);
+    if constexpr (sizeof(T) == 4 && RP % 4 == 0) {
+      // rows of the panels as 16-byte loads (RP * 4 bytes, 16-byte aligned)
+      const float4* u4 = reinterpret_cast<const float4*>(UL + i * RP);
+      const float4* v4 = reinterpret_cast<const float4*>(VL + j * RP);
 #pragma unroll
-    for (int c = 0; c < RP; ++c) l = fma_t(UL[i * RP + c], VL[j * RP + c], l);
+      for (int c = 0; c < RP / 4; ++c) {
+        const float4 a = u4[c], b = v4[c];
+        l = fma_t(a.x, b.x, l);
+        l = fma_t(a.y, b.y, l);
+        l = fma_t(a.z, b.z, l);
+        l = fma_t(a.w, b.w, l);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < RP; ++c) l = fma_t(UL[i * RP + c], VL[j * RP + c], l);
+    }
     const T x = X[i * ldx + j];
     const T r = x - l;
     s_idx[e] = id;
@@ -55,40 +79,64 @@ __global__ __launch_bounds__(256) void kc_gather(const T* __restrict__ X, int64_
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// part[block] = sum over the block's entries of (X - U_L V_L^T)^2.
+// part[block] = sum of (X - U_L V_L^T)^2 over the block's tiles of 64 rows
+// x 256 columns (tile t: row block t % nrb, column block t / nrb).  A thread
+// owns one column and keeps its row of V_L in registers; the row of U_L is
+// the same for the whole block, so each entry costs RP FMAs and one load.
+constexpr int kNormRows = 64;
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void kc_res_norm(const T* __restrict__ X, int64_t ldx,
                                                    const T* __restrict__ UL,
                                                    const T* __restrict__ VL, int64_t m,
-                                                   int64_t n, double* __restrict__ part) {
+                                                   int64_t n, int64_t nrb, int64_t ntiles,
+                                                   double* __restrict__ part) {
   __shared__ double red[4];
   double acc = 0.0;
-  const int64_t total = m * n;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * 256) {
-    const int64_t i = e / n, j = e % n;
-    T l = T(0);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t i0 = (t % nrb) * kNormRows;
+    const int64_t j = (t / nrb) * 256 + threadIdx.x;
+    if (j >= n) continue;
+    T v[RP];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) l = fma_t(UL[i * RP + c], VL[j * RP + c], l);
-    const double r = (double)(X[i * ldx + j] - l);
-    acc = fma(r, r, acc);
+    for (int c = 0; c < RP; ++c) v[c] = VL[j * RP + c];
+    const int64_t i1 = (i0 + kNormRows) < m ? (i0 + kNormRows) : m;
+    for (int64_t i = i0; i < i1; ++i) {
+      const T* u = UL + i * RP;
+      T l = T(0);
+#pragma unroll
+      for (int c = 0; c < RP; ++c) l = fma_t(u[c], v[c], l);
+      const double r = (double)(X[i * ldx + j] - l);
+      acc = fma(r, r, acc);
+    }
   }
-  const double t = block_sum<T>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  const double tot = block_sum<T>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // The plan of a fixed-support step: nnz, sum_sel2 = sum of the gather
-// partials, sum_r2 = sum of the norm partials (both in block order).
-__global__ __launch_bounds__(64) void kc_finish(const double* __restrict__ psel, int nsel,
-                                                const double* __restrict__ pall, int nall,
-                                                int64_t nnz, SelPlan* __restrict__ plan) {
-  if (threadIdx.x != 0) return;
+// partials, sum_r2 = sum of the norm partials (strided per thread, then a
+// tree in LDS: a fixed order).
+__global__ __launch_bounds__(256) void kc_finish(const double* __restrict__ psel, int nsel,
+                                                 const double* __restrict__ pall, int nall,
+                                                 int64_t nnz, SelPlan* __restrict__ plan) {
+  __shared__ double ra[256], rb[256];
   double a = 0.0, b = 0.0;
-  for (int q = 0; q < nsel; ++q) a += psel[q];
-  for (int q = 0; q < nall; ++q) b += pall[q];
+  for (int q = threadIdx.x; q < nsel; q += 256) a += psel[q];
+  for (int q = threadIdx.x; q < nall; q += 256) b += pall[q];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      ra[threadIdx.x] += ra[threadIdx.x + h];
+      rb[threadIdx.x] += rb[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   plan->nnz = nnz;
-  plan->sum_sel2 = a;
-  plan->sum_r2 = b;
+  plan->sum_sel2 = ra[0];
+  plan->sum_r2 = rb[0];
   plan->threshold = 0.0;
   plan->slow = 0;
   plan->overflow = 0;
@@ -122,29 +170,34 @@ void launch_fixed_support(const Launch& L, bool f64, int rp, const void* X, int6
                           const void* UL, const void* VL, int64_t m, int64_t n,
                           const int64_t* support, int64_t nnz, int64_t* s_idx, void* s_val,
                           void* s_x, SelPlan* plan, double* scratch) {
-  const unsigned gs = blocks_of(nnz), ga = blocks_of(m * n);
+  const unsigned gs = blocks_of(nnz);
+  const bool small = m * n <= (int64_t)0xffffffffLL;
+  const int64_t nrb = (m + kNormRows - 1) / kNormRows;
+  const int64_t ntiles = nrb * ((n + 255) / 256);
+  const unsigned ga = (unsigned)(ntiles < kNormBlocks ? ntiles : kNormBlocks);
   double* psel = scratch;
   double* pall = scratch + kCompBlocks;
   GC_RP_SWITCH(rp, {
     if (f64) {
       hipLaunchKernelGGL((kc_gather<double, RP>), dim3(gs), dim3(256), 0, L.stream,
-                         (const double*)X, ldx, (const double*)UL, (const double*)VL, n, support,
-                         nnz, s_idx, (double*)s_val, (double*)s_x, psel);
+                         (const double*)X, ldx, (const double*)UL, (const double*)VL, n, small,
+                         support, nnz, s_idx, (double*)s_val, (double*)s_x, psel);
       hipLaunchKernelGGL((kc_res_norm<double, RP>), dim3(ga), dim3(256), 0, L.stream,
                          (const double*)X, ldx, (const double*)UL, (const double*)VL, m, n,
-                         pall);
+                         nrb, ntiles, pall);
     } else {
       hipLaunchKernelGGL((kc_gather<float, RP>), dim3(gs), dim3(256), 0, L.stream,
-                         (const float*)X, ldx, (const float*)UL, (const float*)VL, n, support,
-                         nnz, s_idx, (float*)s_val, (float*)s_x, psel);
+                         (const float*)X, ldx, (const float*)UL, (const float*)VL, n, small,
+                         support, nnz, s_idx, (float*)s_val, (float*)s_x, psel);
       hipLaunchKernelGGL((kc_res_norm<float, RP>), dim3(ga), dim3(256), 0, L.stream,
-                         (const float*)X, ldx, (const float*)UL, (const float*)VL, m, n, pall);
+                         (const float*)X, ldx, (const float*)UL, (const float*)VL, m, n, nrb,
+                         ntiles, pall);
     }
   });
-  hipLaunchKernelGGL(kc_finish, dim3(1), dim3(64), 0, L.stream, psel, (int)gs, pall, (int)ga,
+  hipLaunchKernelGGL(kc_finish, dim3(1), dim3(256), 0, L.stream, psel, (int)gs, pall, (int)ga,
                      nnz, plan);
 }
 
-int64_t fixed_support_scratch_doubles() { return 2 * (int64_t)kCompBlocks; }
+int64_t fixed_support_scratch_doubles() { return (int64_t)kCompBlocks + kNormBlocks; }
 
 }  // namespace godec

@@ -33,6 +33,10 @@ G1  500 x 500 FP64 planted problem (the shape of the phase-diagram
     experiment of Sec. 5.4): U, V iid N(0, var 1/sqrt(r)) with r = 5,
     5% support of values +-5 (random signs), no noise; r = 5, dr = 1,
     K = 30, lam = 0.1, power = 2.
+Matrix completion (Sec. 2, fixed support) workload:
+M1  the W3 matrix (10 000 x 10 000 FP32, r = 20, q = 2) with a seeded 10 %
+    of its entries unobserved (``missing_support``).
+
 G2  25 344 x 500 FP32 video-shaped matrix (144 x 176 pixels x 500 frames,
     the shape of the Hall sequence of Sec. 5.5) from the W2 recipe with 500
     frames; r = 4, dr = 1, K = 10, lam = 0.125, power = 2.
@@ -248,3 +252,16 @@ def g2(seed: int = 1007, frames: int = 500) -> GreBsmoWorkload:
                            0.125, 2, seed,
                            dict(frames=frames, support_fraction=float(mask.mean()),
                                 dtype="f32"), B)
+
+
+def missing_support(m: int, n: int, frac: float, seed: int,
+                    chunk: int = 1 << 24) -> np.ndarray:
+    """Ascending linear indices of a Bernoulli(frac) set of unobserved
+    entries of an m x n matrix, drawn chunk by chunk (bounded memory)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    total = m * n
+    for c0 in range(0, total, chunk):
+        c1 = min(c0 + chunk, total)
+        out.append(np.flatnonzero(rng.random(c1 - c0) < frac).astype(np.int64) + c0)
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
