@@ -154,6 +154,27 @@ def brp_power(D: np.ndarray, A1: np.ndarray, q: int,
     return BrpResult(left @ right.T, left, right, r, s_c, s)
 
 
+def brp_projection(D: np.ndarray, A1: np.ndarray, q: int) -> BrpResult:
+    """The projection form of the power-scheme low-rank step: L = D P_{Y2},
+    the projection of the rows of D onto range(Y2) with
+    Y2 = L~^T L~ A1 = (D^T D)^p A1 — the approximation that the power-scheme
+    bound of App. II (Thm. 4) analyses.  Y2 is built as p products with
+    D^T D, each followed by a Householder QR (the span is unchanged), so
+    L = (D Q2) Q2^T with Q2 the last Q.  At q = 0 it equals the root form
+    (Eq. 5).  No rank check: it needs no inverse.
+
+    Pinned by: the Thm. 4 deterministic bound on every draw for q = 1, 2;
+    equality with brp_power at q = 0; exact reproduction of rank-r inputs
+    (tests/test_oracle_brp.py).
+    """
+    p = 2 * q + 1
+    Z, _ = np.linalg.qr(A1)
+    for _ in range(p):
+        Z, _ = np.linalg.qr(D.T @ (D @ Z))
+    left = D @ Z
+    return BrpResult(left @ Z.T, left, Z, A1.shape[1], np.zeros(0), np.zeros(0))
+
+
 def _rank_from_r2(R2: np.ndarray, rank_tol: float | None):
     r = R2.shape[1]
     s_c = np.linalg.svd(R2, compute_uv=False) ** 2     # singular values of C
@@ -266,8 +287,11 @@ class GoDecTrace:
 def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
               iters: int, eps: float | None = None,
               rank_tol: float | None = None,
-              keep_supports: bool = False) -> GoDecTrace:
+              keep_supports: bool = False, lstep: str = "root") -> GoDecTrace:
     """Algorithm 1 (GoDec by BRP), FP64, readings R1-R7.
+
+    lstep = "proj" takes the projection form of the L step (brp_projection)
+    instead of the root form of Algorithm 1.
 
     Pinned by: on the 500 x 500 workload its trajectory equals that of the
     naive SVD GoDec (Eq. 4); the S-step half of Theorem 1 (monotone
@@ -282,7 +306,7 @@ def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
     tr = GoDecTrace(L=X.copy(), S=S, left=None, right=None, r_eff=r)
     for _ in range(iters):
         D = X - S
-        res = brp_power(D, A, q, rank_tol)
+        res = brp_projection(D, A, q) if lstep == "proj" else brp_power(D, A, q, rank_tol)
         A = A[:, :res.r_eff]
         L = res.L
         tr.e1.append(float(np.sum((X - L - S) ** 2)))

@@ -177,3 +177,68 @@ def test_rank_zero_carry_gives_zero_L():
     assert res0.r_eff == 0 and res0.L.shape == (30, 20) and not res0.L.any()
     lit = g.brp_power_literal(D, A1[:, :0], 2)
     assert lit.r_eff == 0 and not lit.L.any()
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_theorem4_bound_projection_form_every_draw(q):
+    """App. II, Thm. 4: for the power scheme, ||X - L||^2 <=
+    (||L2^{2p} (V2^T A1)(V1^T A1)^+ L1^{-p}||^2 + ||L2^p||^2)^{1/p}, p = 2q+1,
+    for every draw of A1, with L = X P_{Y2} (spectral norm).  The bound is
+    tight on these inputs (ratios up to 0.9999), so a wrong power, a
+    transposed operand or a missing re-orthonormalisation breaks it."""
+    rng = np.random.default_rng(5 + q)
+    p = 2 * q + 1
+    worst = 0.0
+    for _ in range(100):
+        m, n, r = 50, 30, 3
+        X = rng.standard_normal((m, n)) @ np.diag(0.75 ** np.arange(n)) \
+            @ rng.standard_normal((n, n))
+        U, lam, Vt = np.linalg.svd(X, full_matrices=False)
+        V = Vt.T
+        A1 = rng.standard_normal((n, r))
+        L = g.brp_projection(X, A1, q).L
+        err = np.linalg.norm(X - L, 2) ** 2
+        L1, L2 = np.diag(lam[:r]), np.diag(lam[r:])
+        V1, V2 = V[:, :r], V[:, r:]
+        t1 = np.linalg.norm(np.linalg.matrix_power(L2, 2 * p) @ (V2.T @ A1)
+                            @ np.linalg.pinv(V1.T @ A1)
+                            @ np.linalg.matrix_power(np.linalg.inv(L1), p), 2) ** 2
+        t2 = np.linalg.norm(np.linalg.matrix_power(L2, p), 2) ** 2
+        bound = (t1 + t2) ** (1.0 / p)
+        assert err <= bound * (1 + 1e-10)
+        worst = max(worst, err / bound)
+    assert worst > 0.5          # the bound is not vacuous here
+
+
+def test_projection_equals_root_form_at_q0():
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((40, 30)) @ np.diag(0.8 ** np.arange(30)) @ rng.standard_normal((30, 30))
+    A1 = rng.standard_normal((30, 4))
+    a = g.brp_projection(X, A1, 0).L
+    b = g.brp_power(X, A1, 0).L
+    assert g.rel_fro(a, b) < 1e-12
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_projection_reproduces_rank_r(q):
+    rng = np.random.default_rng(12 + q)
+    X = rng.standard_normal((60, 4)) @ rng.standard_normal((4, 45))
+    L = g.brp_projection(X, rng.standard_normal((45, 4)), q).L
+    assert g.rel_fro(L, X) < 1e-12
+
+
+def test_projection_loop_recovers_w1_like_problem():
+    """GoDec with the projection L step on a planted low-rank + sparse X
+    recovers the low-rank part (the same fixed point as the root form)."""
+    rng = np.random.default_rng(13)
+    m, n, r, k = 200, 150, 4, 1500
+    L0 = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    X = L0.copy()
+    idx = rng.choice(m * n, size=k, replace=False)
+    X.flat[idx] += rng.uniform(-10, 10, size=k)
+    A1 = rng.standard_normal((n, r))
+    tr = g.godec_brp(X, r, k, 1, A1, 30, lstep="proj")
+    assert g.rel_fro(tr.L, L0) < 1e-8
+    ref = g.godec_brp(X, r, k, 1, A1, 30)
+    assert g.rel_fro(tr.L, ref.L) < 1e-8
+
