@@ -51,17 +51,18 @@ def rel_diff_factors(a_l, a_r, b_l, b_r):
     return max(aa - 2 * ab + bb, 0.0) ** 0.5 / bb ** 0.5
 
 
-def run_form(X, w, prec, steps, warmup, seed):
-    """Time `steps` iterations (one solve); returns timing, stats, factors."""
+def run_form(X, w, prec, steps, warmup, seed, lstep=0):
+    """Time `steps` iterations (one solve); returns timing, stats, factors.
+    lstep = 1 takes the projection form of the L update."""
     import torch
     from paper_1309_0302_amd.binding import GoDec
     stream = torch.cuda.current_stream()
     if warmup > 0:
-        g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1)
+        g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1, lstep=lstep)
         g.step(warmup, warmup)
         g.info()
         g.close()
-    g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1)
+    g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1, lstep=lstep)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -76,7 +77,7 @@ def run_form(X, w, prec, steps, warmup, seed):
     UL, VL = g.factors()
     g.close()
     # the same solve again with per-kernel event timing switched on
-    g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1)
+    g = GoDec(X, w.r, w.k, w.q, seed=seed, prec=prec, refine_iters=1, lstep=lstep)
     g.profile(True)
     g.step(steps, steps)
     stats = g.profile_read()
@@ -382,6 +383,7 @@ def main():
     ap.add_argument("--skip-copy", action="store_true")
     ap.add_argument("--skip-grebsmo", action="store_true")
     ap.add_argument("--skip-completion", action="store_true")
+    ap.add_argument("--skip-projection", action="store_true")
     ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo", "completion"],
                     help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
@@ -477,6 +479,15 @@ def main():
         out["layer"] = run_layer(min(args.warmup, 1))
         log(f"[bench] layer fwd {out['layer']['forward_ms']} ms, "
             f"bwd {out['layer']['backward_ms']} ms")
+    if not args.skip_projection:
+        log("[bench] projection-form L update, bf16 + refinement")
+        pj = run_form(X, w, GODEC_PREC_BF16_REFINE, args.steps, args.warmup, args.seed, lstep=1)
+        out["projection_form"] = {
+            "value": round(args.steps / (pj["ms"] * 1e-3), 2), "unit": "iter/s",
+            "ms_per_step": round(pj["ms"] / args.steps, 4),
+            "final_rel_err_sq": pj["info"]["rel_err_sq"],
+            "rel_diff_L_vs_root_form": rel_diff_factors(pj["UL"], pj["VL"], bf["UL"], bf["VL"])}
+        log(f"[bench] projection form {out['projection_form']['value']} iter/s")
     if not args.skip_completion:
         log("[bench] matrix completion: 10000 x 10000, 10 % unobserved")
         out["completion"] = run_completion(X, w, 10, 2)

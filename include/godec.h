@@ -73,7 +73,11 @@ typedef struct {
   uint32_t size;          /* sizeof(godec_opts); set by godec_opts_default */
   int32_t prec;           /* godec_prec */
   int32_t refine_iters;   /* BF16_REFINE only: trailing FP32 iterations (>= 0) */
-  int32_t reserved0;
+  int32_t lstep;          /* L update: 0 = the root form of Algorithm 1 (Eq. 9);
+                             1 = the projection form L = (X - S) P_{Y2} that
+                             App. II (Thm. 4) bounds: U_L = (X - S) Q2,
+                             V_L = Q2, no B chain, core or rank check
+                             (dependent directions come out as zero columns) */
   double rank_tol;        /* <= 0: default r * 2^-52 (see above) */
   const double* a1_host;  /* optional n x r row-major A1 replacing the seeded
                              draw (test hook); copied during godec_init */

@@ -41,6 +41,7 @@ struct godec_ctx {
   const void* X;
   hipStream_t stream;
   int num_cu;
+  int lstep = 0;                      // 1: projection form of the L update
   const int64_t* support = nullptr;   // completion: fixed support of S
   int64_t support_nnz = 0;
   bool completion = false;
@@ -203,6 +204,7 @@ godec_status validate(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
     if (o->prec == GODEC_PREC_BF16_REFINE && dtype != GODEC_F32)
       return fail(GODEC_E_INVAL, "BF16_REFINE needs an FP32 X");
     if (o->refine_iters < 0) return fail(GODEC_E_INVAL, "refine_iters < 0");
+    if (o->lstep != 0 && o->lstep != 1) return fail(GODEC_E_INVAL, "opts.lstep must be 0 or 1");
     if (o->support_dev != nullptr || o->support_nnz != 0) {
       if (o->support_nnz < 0 || o->support_nnz > m * n)
         return fail(GODEC_E_INVAL, "need 0 <= support_nnz <= m*n");
@@ -400,6 +402,13 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   // second Cholesky QR round on Q2 (restores orthonormality to working
   // precision); its R factor joins R2.  Its transpose feeds the B chain.
   chol_qr(c, c->P0, c->VL, c->st->R2, 0, tdb);
+  if (c->lstep == 1) {
+    // projection form: L = D Q2 Q2^T, i.e. U_L = D Q2 and V_L = Q2
+    if (c->f64)
+      launch_apply(L, tdb, c->rp, Db, c->ldd, c->m, c->VL, c->UL);
+    else
+      mfma_apply(c, tdb, Db, c->VL, true, nullptr, (float*)c->UL);
+  } else {
   // ---- B chain: (D^T D)^q Q2 = Y_q T, then B' = D Y_q ----
   in = c->VL;
   for (int j = 0; j < c->q; ++j) {
@@ -416,6 +425,7 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   launch_core(L, c->f64, c->rp, c->Gpart + (size_t)kGramFinal * c->rp * c->rp, 1, c->st, c->p,
               c->rank_tol, c->q == 0 ? 1 : 0, c->Kp);
   launch_apply_small(L, c->f64, c->rp, c->Bp, c->m, c->Kp, c->UL);
+  }
   // ---- sparse step ----
   const int prev = c->cur;
   const int nxt = c->cur ^ 1;
@@ -527,6 +537,7 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   c->ldx = ldx;
   c->seed = seed;
   c->X = X_dev;
+  c->lstep = opts ? opts->lstep : 0;
   c->stream = opts ? (hipStream_t)opts->stream : nullptr;
   const size_t need = carve(c, nullptr);
   if (ws_bytes < need) {

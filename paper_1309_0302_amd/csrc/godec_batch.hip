@@ -76,6 +76,8 @@ godec_status validate_batch(const godec_problem* probs, int32_t count, int32_t q
     return fail(GODEC_E_UNSUPPORTED, "the batched form runs FP32 only (prec NATIVE)");
   if (opts && (opts->support_dev || opts->support_nnz))
     return fail(GODEC_E_UNSUPPORTED, "the batched form has no fixed-support (completion) form");
+  if (opts && opts->lstep != 0)
+    return fail(GODEC_E_UNSUPPORTED, "the batched form runs the root-form L update");
   for (int i = 0; i < count; ++i) {
     const godec_problem& P = probs[i];
     const std::string at = " (problem " + std::to_string(i) + ")";

@@ -443,6 +443,8 @@ godec_status godec_layer_forward(godec_layer** out, const void* X_dev, godec_dty
     return fail(GODEC_E_UNSUPPORTED, "the layer draws A1 from the seed");
   if (opts && (opts->support_dev || opts->support_nnz))
     return fail(GODEC_E_UNSUPPORTED, "the layer has no fixed-support (completion) form");
+  if (opts && opts->lstep != 0)
+    return fail(GODEC_E_UNSUPPORTED, "the layer differentiates the root-form L update");
   godec_layer* l = new godec_layer;
   fill_layer(l, batch, m, n, r, k, q, T, dtype);
   s = sub_workspace(l, &l->sub_ws);

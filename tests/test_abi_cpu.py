@@ -97,6 +97,15 @@ def test_opts_size_checked(lib):
         _ws(100, 100, 4, 10, 1, opts=o)
 
 
+def test_lstep_checked(lib):
+    o, _ = b.make_opts(lstep=1)
+    assert _ws(100, 100, 4, 10, 1, opts=o) == _ws(100, 100, 4, 10, 1)
+    o, _ = b.make_opts(lstep=2)
+    with pytest.raises(b.GodecError) as ei:
+        _ws(100, 100, 4, 10, 1, opts=o)
+    assert ei.value.status == 1
+
+
 def test_k_extremes_accepted(lib):
     assert _ws(20, 10, 2, 0, 0) > 0
     assert _ws(20, 10, 2, 200, 0) > 0
