@@ -93,6 +93,12 @@ typedef struct {
    * entries over ||X||_F^2; info.threshold is 0. */
   const int64_t* support_dev;
   int64_t support_nnz;
+  /* 1: every power chain after the first starts from the previous
+   * iteration's Q2 (whose span is that of Y2) instead of A1 -- a variant
+   * outside the paper that lets a smaller q reach the same fixed point;
+   * 0 (default): A1 every iteration, as Algorithm 1. */
+  int32_t warm_start;
+  int32_t reserved1;
 } godec_opts;
 
 typedef struct {

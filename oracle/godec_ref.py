@@ -287,11 +287,16 @@ class GoDecTrace:
 def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
               iters: int, eps: float | None = None,
               rank_tol: float | None = None,
-              keep_supports: bool = False, lstep: str = "root") -> GoDecTrace:
+              keep_supports: bool = False, lstep: str = "root",
+              warm: bool = False) -> GoDecTrace:
     """Algorithm 1 (GoDec by BRP), FP64, readings R1-R7.
 
     lstep = "proj" takes the projection form of the L step (brp_projection)
-    instead of the root form of Algorithm 1.
+    instead of the root form of Algorithm 1.  warm = True starts every power
+    chain after the first from the previous iteration's right factor (whose
+    span is that of Q2) instead of A1: a variant outside the paper (Q2 of
+    the last step in the role of A1 of Sec. 3.1.1), pinned by its fixed
+    point.
 
     Pinned by: on the 500 x 500 workload its trajectory equals that of the
     naive SVD GoDec (Eq. 4); the S-step half of Theorem 1 (monotone
@@ -307,7 +312,7 @@ def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
     for _ in range(iters):
         D = X - S
         res = brp_projection(D, A, q) if lstep == "proj" else brp_power(D, A, q, rank_tol)
-        A = A[:, :res.r_eff]
+        A = res.right if warm else A[:, :res.r_eff]
         L = res.L
         tr.e1.append(float(np.sum((X - L - S) ** 2)))
         R = X - L

@@ -29,7 +29,8 @@ class godec_opts(ctypes.Structure):
                 ("refine_iters", ctypes.c_int32), ("lstep", ctypes.c_int32),
                 ("rank_tol", ctypes.c_double), ("a1_host", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("support_dev", ctypes.c_void_p),
-                ("support_nnz", ctypes.c_int64)]
+                ("support_nnz", ctypes.c_int64), ("warm_start", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
 
 
 class godec_info(ctypes.Structure):
@@ -173,13 +174,14 @@ def _dtype_code(t):
 
 
 def make_opts(prec=GODEC_PREC_NATIVE, refine_iters=1, rank_tol=0.0, a1=None,
-              stream=None, support=None, lstep=0):
+              stream=None, support=None, lstep=0, warm_start=0):
     """support: optional int64 device tensor of strictly ascending linear
     indices (matrix completion: the fixed support of S)."""
     o = godec_opts()
     load().godec_opts_default(ctypes.byref(o))
     o.prec = prec
     o.lstep = lstep
+    o.warm_start = warm_start
     o.refine_iters = refine_iters
     o.rank_tol = rank_tol
     keep = None
@@ -328,7 +330,7 @@ class GoDec:
 
     def __init__(self, X, r, k, q, seed=0, prec=GODEC_PREC_NATIVE,
                  refine_iters=1, rank_tol=0.0, a1=None, stream=None, support=None,
-                 lstep=0):
+                 lstep=0, warm_start=0):
         import torch
         if not X.is_cuda:
             raise ValueError("X must be a device tensor")
@@ -343,7 +345,7 @@ class GoDec:
             stream = torch.cuda.current_stream(X.device).cuda_stream
         self.support = support
         self.opts, self._a1_keep = make_opts(prec, refine_iters, rank_tol, a1,
-                                             stream, support, lstep)
+                                             stream, support, lstep, warm_start)
         self.ws_bytes = godec_workspace_size(self.m, self.n, r, k, q,
                                              self.dtype, self.opts)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,

@@ -42,6 +42,7 @@ struct godec_ctx {
   hipStream_t stream;
   int num_cu;
   int lstep = 0;                      // 1: projection form of the L update
+  bool warm = false;                  // chains start from the previous Q2
   const int64_t* support = nullptr;   // completion: fixed support of S
   int64_t support_nnz = 0;
   bool completion = false;
@@ -205,6 +206,8 @@ godec_status validate(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
       return fail(GODEC_E_INVAL, "BF16_REFINE needs an FP32 X");
     if (o->refine_iters < 0) return fail(GODEC_E_INVAL, "refine_iters < 0");
     if (o->lstep != 0 && o->lstep != 1) return fail(GODEC_E_INVAL, "opts.lstep must be 0 or 1");
+    if (o->warm_start != 0 && o->warm_start != 1)
+      return fail(GODEC_E_INVAL, "opts.warm_start must be 0 or 1");
     if (o->support_dev != nullptr || o->support_nnz != 0) {
       if (o->support_nnz < 0 || o->support_nnz > m * n)
         return fail(GODEC_E_INVAL, "need 0 <= support_nnz <= m*n");
@@ -372,7 +375,11 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   const bool mixed = c->prec == GODEC_PREC_BF16_REFINE;
   const bool refine = mixed && total > 0 && t >= total - c->refine_iters;
   // ---- subspace chain: Q2 = orth((D^T D)^p A1), R2 tracked ----
-  launch_copy_panel(L, c->f64, c->rp, c->A1, c->n, c->ldd, c->r, c->st, c->P0);
+  if (c->warm && c->iters_done > 0)
+    HIP_TRY(hipMemcpyAsync(c->P0, c->VL, (size_t)c->ldd * c->rp * c->ta, hipMemcpyDeviceToDevice,
+                           c->stream));   // Q2 of the last iteration (zero past r_eff)
+  else
+    launch_copy_panel(L, c->f64, c->rp, c->A1, c->n, c->ldd, c->r, c->st, c->P0);
   const int64_t kk = std::max<int64_t>(c->k, 1);
   if (refine && !c->d_native_valid) {
     // D = X - S_{t-1} in FP32 for the refinement passes
@@ -538,6 +545,7 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   c->seed = seed;
   c->X = X_dev;
   c->lstep = opts ? opts->lstep : 0;
+  c->warm = opts && opts->warm_start;
   c->stream = opts ? (hipStream_t)opts->stream : nullptr;
   const size_t need = carve(c, nullptr);
   if (ws_bytes < need) {

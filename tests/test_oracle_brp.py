@@ -242,3 +242,30 @@ def test_projection_loop_recovers_w1_like_problem():
     ref = g.godec_brp(X, r, k, 1, A1, 30)
     assert g.rel_fro(tr.L, ref.L) < 1e-8
 
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_warm_start_reaches_the_same_fixed_point(q):
+    """Warm-started chains (the previous right factor in place of A1) reach
+    the planted low-rank part, as the cold-started loop does, and never
+    fewer digits of it."""
+    rng = np.random.default_rng(21 + q)
+    m, n, r, k = 200, 150, 4, 1500
+    L0 = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    X = L0.copy()
+    idx = rng.choice(m * n, size=k, replace=False)
+    X.flat[idx] += rng.uniform(-10, 10, size=k)
+    A1 = rng.standard_normal((n, r))
+    warm = g.godec_brp(X, r, k, q, A1, 40, warm=True)
+    cold = g.godec_brp(X, r, k, q, A1, 40)
+    assert g.rel_fro(warm.L, L0) < 1e-8
+    assert g.rel_fro(warm.L, L0) <= max(10 * g.rel_fro(cold.L, L0), 1e-12)
+
+
+def test_warm_start_first_iteration_is_the_cold_one():
+    rng = np.random.default_rng(23)
+    X = rng.standard_normal((80, 60))
+    A1 = rng.standard_normal((60, 3))
+    a = g.godec_brp(X, 3, 100, 1, A1, 1, warm=True)
+    b = g.godec_brp(X, 3, 100, 1, A1, 1)
+    assert np.array_equal(a.L, b.L)
+
