@@ -106,6 +106,15 @@ def test_lstep_checked(lib):
     assert ei.value.status == 1
 
 
+def test_warm_start_checked(lib):
+    o, _ = b.make_opts(warm_start=1)
+    assert _ws(100, 100, 4, 10, 1, opts=o) > 0
+    o, _ = b.make_opts(warm_start=3)
+    with pytest.raises(b.GodecError) as ei:
+        _ws(100, 100, 4, 10, 1, opts=o)
+    assert ei.value.status == 1
+
+
 def test_k_extremes_accepted(lib):
     assert _ws(20, 10, 2, 0, 0) > 0
     assert _ws(20, 10, 2, 200, 0) > 0
