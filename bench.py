@@ -397,7 +397,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
-              "supported (the multi-GPU row sharding is described in DESIGN.md)",
+              "supported (the row-block sharding across GPUs is designed, not built)",
               file=sys.stderr)
         sys.exit(2)
 
