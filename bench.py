@@ -396,7 +396,7 @@ def main():
                     help="square size (default: the 10000 x 10000 workload)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not "
               "supported (the row-block sharding across GPUs is designed, not built)",
               file=sys.stderr)
         sys.exit(2)

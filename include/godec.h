@@ -55,7 +55,7 @@ typedef enum {
   GODEC_E_DEVICE = 3,      /* a HIP runtime call failed */
   GODEC_E_NUMERIC = 4,     /* NaN/Inf in X, or a non-finite r x r core */
   GODEC_E_STATE = 5,       /* call not valid in the context's state */
-  GODEC_E_UNSUPPORTED = 6  /* valid request outside this build's limits */
+  GODEC_E_UNSUPPORTED = 6  /* valid request outside the library's limits */
 } godec_status;
 
 typedef enum { GODEC_F64 = 0, GODEC_F32 = 1 } godec_dtype;
@@ -67,7 +67,7 @@ typedef enum { GODEC_F64 = 0, GODEC_F32 = 1 } godec_dtype;
  * residual in FP32.  The r x r core is FP64 in every mode. */
 typedef enum { GODEC_PREC_NATIVE = 0, GODEC_PREC_BF16_REFINE = 1 } godec_prec;
 
-#define GODEC_MAX_RANK 32   /* largest r this build supports */
+#define GODEC_MAX_RANK 32   /* largest r the library supports */
 
 typedef struct {
   uint32_t size;          /* sizeof(godec_opts); set by godec_opts_default */
