@@ -150,6 +150,9 @@ def per_stage_f32(X, r, dr, K, lam, power, seed, tol=1e-5):
     (333, 257, 5, 1, 3, 0.25),
     (150, 400, 4, 3, 3, 0.1),
     (1000, 300, 8, 2, 5, 0.125),
+    (700, 400, 12, 4, 3, 0.1),      # r > 8: the unfused soft pass + D V^T pass
+    (500, 260, 1, 1, 4, 0.1),       # one-column panels
+    (500, 260, 2, 2, 3, 0.1),
 ])
 def test_f32_per_stage_parity(m, n, r, dr, K, lam):
     X, _ = problem(m, n, r, seed=m + n, dtype=np.float32)
