@@ -45,6 +45,7 @@ struct godec_ctx {
   bool warm = false;                  // chains start from the previous Q2
   const int64_t* support = nullptr;   // completion: fixed support of S
   int64_t support_nnz = 0;
+  int64_t* row_ptr = nullptr;         // completion: m x (ncb + 1) run starts (see init)
   bool completion = false;
   bool f64;            // panel / residual type is double
   size_t ta;           // sizeof panel type
@@ -187,6 +188,10 @@ size_t carve(godec_ctx* c, void* base) {
   c->boff = (unsigned long long*)cv.take((size_t)nb * 8);
   c->norm_x2 = (double*)cv.take(8);
   c->nonfinite = (int*)cv.take(8);
+  // completion: start of each (row, 256-column block) run of the support
+  c->row_ptr = c->completion
+                   ? (int64_t*)cv.take((size_t)m * ((c->n + 255) / 256 + 1) * 8)
+                   : nullptr;
   return align_up(cv.off, 256);
 }
 
@@ -236,6 +241,7 @@ void fill_ctx_params(godec_ctx* c, int64_t m, int64_t n, int32_t r, int64_t k,
   c->ldd = s.ldd; c->mpad = s.mpad; c->nchunks = s.nchunks; c->rows_per_chunk = s.rpc;
   c->cap = s.cap;
   c->kc_a = s.kc_a; c->nct_a = s.nct_a; c->rc_b = s.rc_b; c->nch_b = s.nch_b;
+  c->completion = o && (o->support_dev != nullptr || o->support_nnz != 0);
 }
 
 // Counter-based SplitMix64 (Steele, Lea, Flood 2014): output i of the stream
@@ -453,8 +459,8 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   }
   if (c->completion)
     launch_fixed_support(L, c->f64, c->rp, c->X, c->ldx, c->UL, c->VL, c->m, c->n, c->support,
-                         c->support_nnz, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
-                         c->plan[nxt], (double*)c->hist);
+                         c->row_ptr, c->support_nnz, c->s_idx[nxt], c->s_val[nxt],
+                         c->s_x[nxt], c->plan[nxt], (double*)c->hist);
   else
     launch_select(L, c->f64, c->rp, a);
   // ---- D update: restore X on the old support, X - S on the new one ----
@@ -577,6 +583,35 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
           return fail(GODEC_E_INVAL, "support must be strictly ascending in [0, m*n)");
         }
     }
+    // run starts of the sorted support: entry (i, cb) is the first support
+    // entry at or after (row i, column 256 cb); entry (i, ncb) is the first
+    // entry of row i + 1 (blocked CSR, ncb = ceil(n / 256))
+    const int64_t ncb = (n + 255) / 256;
+    std::vector<int64_t> rp((size_t)(m * (ncb + 1)), 0);
+    {
+      std::vector<int64_t> h((size_t)c->support_nnz);
+      if (!h.empty()) {
+        hipError_t e = hipMemcpy(h.data(), c->support, sizeof(int64_t) * h.size(),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+          delete c;
+          return fail(GODEC_E_DEVICE, hipGetErrorString(e));
+        }
+      }
+      size_t pos = 0;
+      for (int64_t i = 0; i < m; ++i)
+        for (int64_t cb = 0; cb <= ncb; ++cb) {
+          const int64_t key = cb < ncb ? i * n + cb * 256 : (i + 1) * n;
+          while (pos < h.size() && h[pos] < key) ++pos;
+          rp[(size_t)(i * (ncb + 1) + cb)] = (int64_t)pos;
+        }
+    }
+    hipError_t e = hipMemcpy(c->row_ptr, rp.data(), sizeof(int64_t) * rp.size(),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(GODEC_E_DEVICE, hipGetErrorString(e));
+    }
   }
   c->a1_host.resize((size_t)n * r);
   if (opts && opts->a1_host)
@@ -698,7 +733,10 @@ godec_status godec_get_info(godec_ctx* c, godec_info* info) {
   info->flags = (flags & 1) | (flags & 2) | (hp.slow ? 4 : 0) | (hp.overflow ? 8 : 0);
   info->sum_r2 = hp.sum_r2;
   info->norm_x2 = nx2;
-  info->rel_err_sq = nx2 > 0 ? (hp.sum_r2 - hp.sum_sel2) / nx2 : 0.0;
+  // with a fixed support the error off the support is summed directly (the
+  // difference of the two sums would lose it to cancellation)
+  const double off = c->completion ? hp.sum_obs2 : hp.sum_r2 - hp.sum_sel2;
+  info->rel_err_sq = nx2 > 0 ? off / nx2 : 0.0;
   if (info->rel_err_sq < 0) info->rel_err_sq = 0.0;
   info->threshold = hp.threshold;
   if (flags & 1) return fail(GODEC_E_NUMERIC, "non-finite value in the r x r core");

@@ -67,6 +67,7 @@ struct SelPlan {
   double sum_r2;               // ||X - L||_F^2 (all entries)
   double sum_sel2;             // sum of R^2 over the selected entries
   double threshold;            // |R| of the threshold key
+  double sum_obs2;             // fixed support only: sum of R^2 off the support
 };
 
 // Threshold carried between iterations: the level-0 digit window start.
@@ -416,13 +417,16 @@ void lf_pterm(const Launch& L, bool f64, int nb, int n, int r, const void* Zj, c
               const double* rtot, const void* cur, void* Vf, int w, int col);
 
 // ---- matrix completion (k_complete.hip) ----
-// S update on a fixed support: lists s_idx / s_val / s_x and plan (nnz,
-// sum_r2, sum_sel2) as the selection would leave them.  scratch: at least
+// S update on a fixed support (ascending; row_ptr: m x (ceil(n/256) + 1)
+// starts of its runs per row and 256-column block): lists
+// s_idx / s_val / s_x and plan (nnz, sum_r2, sum_sel2) as the selection
+// would leave them, in one pass over X.  scratch: at least
 // fixed_support_scratch_doubles() doubles.
 void launch_fixed_support(const Launch& L, bool f64, int rp, const void* X, int64_t ldx,
                           const void* UL, const void* VL, int64_t m, int64_t n,
-                          const int64_t* support, int64_t nnz, int64_t* s_idx, void* s_val,
-                          void* s_x, SelPlan* plan, double* scratch);
+                          const int64_t* support, const int64_t* row_ptr, int64_t nnz,
+                          int64_t* s_idx, void* s_val, void* s_x, SelPlan* plan,
+                          double* scratch);
 int64_t fixed_support_scratch_doubles();
 
 // ---- GreBsmo (k_grebsmo.hip) ----

@@ -11,8 +11,7 @@ namespace godec {
 
 namespace {
 
-constexpr int kCompBlocks = 2048;   // most blocks (= partial sums) of the gather
-constexpr int kNormBlocks = 16384;  // most blocks of the residual-norm pass
+constexpr int kNormBlocks = 16384;  // most blocks (= partial sums) of the pass
 
 template <typename T>
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -25,97 +24,85 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-// For every support entry e (ascending linear index id = i n + j):
-// r = X_ij - (U_L V_L^T)_ij, s_idx[e] = id, s_val[e] = r, s_x[e] = X_ij;
-// part[block] = sum of r^2 over the block's entries.
-template <typename T, int RP>
-__global__ __launch_bounds__(256) void kc_gather(const T* __restrict__ X, int64_t ldx,
-                                                 const T* __restrict__ UL,
-                                                 const T* __restrict__ VL, int64_t n,
-                                                 bool small,
-                                                 const int64_t* __restrict__ support,
-                                                 int64_t nnz, int64_t* __restrict__ s_idx,
-                                                 T* __restrict__ s_val, T* __restrict__ s_x,
-                                                 double* __restrict__ part) {
-  __shared__ double red[4];
-  double acc = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz;
-       e += (int64_t)gridDim.x * 256) {
-    const int64_t id = support[e];
-    int64_t i, j;
-    if (small) {   // m n < 2^32: 32-bit division (uniform branch)
-      const uint32_t q = (uint32_t)id / (uint32_t)n;
-      i = q;
-      j = (int64_t)((uint32_t)id - q * (uint32_t)n);
-    } else {
-      i = id / n;
-      j = id % n;
-    }
-    T l = T(0);
-    if constexpr (sizeof(T) == 4 && RP % 4 == 0) {
-      // rows of the panels as 16-byte loads (RP * 4 bytes, 16-byte aligned)
-      const float4* u4 = reinterpret_cast<const float4*>(UL + i * RP);
-      const float4* v4 = reinterpret_cast<const float4*>(VL + j * RP);
-#pragma unroll
-      for (int c = 0; c < RP / 4; ++c) {
-        const float4 a = u4[c], b = v4[c];
-        l = fma_t(a.x, b.x, l);
-        l = fma_t(a.y, b.y, l);
-        l = fma_t(a.z, b.z, l);
-        l = fma_t(a.w, b.w, l);
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < RP; ++c) l = fma_t(UL[i * RP + c], VL[j * RP + c], l);
-    }
-    const T x = X[i * ldx + j];
-    const T r = x - l;
-    s_idx[e] = id;
-    s_val[e] = r;
-    s_x[e] = x;
-    acc = fma((double)r, (double)r, acc);
-  }
-  const double t = block_sum<T>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-// part[block] = sum of (X - U_L V_L^T)^2 over the block's tiles of 64 rows
-// x 256 columns (tile t: row block t % nrb, column block t / nrb).  A thread
-// owns one column and keeps its row of V_L in registers; the row of U_L is
-// the same for the whole block, so each entry costs RP FMAs and one load.
+// One pass over X for the whole fixed-support step.  Tiles of 64 rows x 256
+// columns (tile t: row block t % nrb, column block t / nrb) are walked
+// grid-stride; a thread owns one column and keeps its row of V_L in
+// registers (the row of U_L is the same for the whole block).  For every
+// row of a tile the residuals r = X - (U_L V_L^T) go to LDS; the support
+// entries of that row inside the tile's columns -- the contiguous run
+// [row_ptr[i][cb], row_ptr[i][cb + 1]) of the ascending list -- then take
+// theirs: s_idx, s_val = r, s_x = X, and mark their columns so that the
+// block partials pall / psel sum r^2 off / on the support separately.
 constexpr int kNormRows = 64;
+
 template <typename T, int RP>
-__global__ __launch_bounds__(256) void kc_res_norm(const T* __restrict__ X, int64_t ldx,
-                                                   const T* __restrict__ UL,
-                                                   const T* __restrict__ VL, int64_t m,
-                                                   int64_t n, int64_t nrb, int64_t ntiles,
-                                                   double* __restrict__ part) {
+__global__ __launch_bounds__(256) void kc_pass(const T* __restrict__ X, int64_t ldx,
+                                               const T* __restrict__ UL,
+                                               const T* __restrict__ VL, int64_t m, int64_t n,
+                                               int64_t nrb, int64_t ntiles, int64_t ncb,
+                                               const int64_t* __restrict__ support,
+                                               const int64_t* __restrict__ row_ptr,
+                                               int64_t* __restrict__ s_idx,
+                                               T* __restrict__ s_val, T* __restrict__ s_x,
+                                               double* __restrict__ pall,
+                                               double* __restrict__ psel) {
+  __shared__ T rs[256], xs[256];
+  __shared__ int mk[256];
   __shared__ double red[4];
-  double acc = 0.0;
+  double acc = 0.0, accs = 0.0;   // sums of r^2 off and on the support
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t i0 = (t % nrb) * kNormRows;
-    const int64_t j = (t / nrb) * 256 + threadIdx.x;
-    if (j >= n) continue;
+    const int64_t cb = t / nrb;
+    const int64_t j0 = cb * 256;
+    const int64_t j = j0 + threadIdx.x;
+    const bool live = j < n;
     T v[RP];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) v[c] = VL[j * RP + c];
+    for (int c = 0; c < RP; ++c) v[c] = live ? VL[j * RP + c] : T(0);
     const int64_t i1 = (i0 + kNormRows) < m ? (i0 + kNormRows) : m;
     for (int64_t i = i0; i < i1; ++i) {
       const T* u = UL + i * RP;
       T l = T(0);
 #pragma unroll
       for (int c = 0; c < RP; ++c) l = fma_t(u[c], v[c], l);
-      const double r = (double)(X[i * ldx + j] - l);
-      acc = fma(r, r, acc);
+      const T x = live ? X[i * ldx + j] : T(0);
+      const T r = x - l;
+      const int64_t* run = row_ptr + i * (ncb + 1) + cb;
+      const int64_t a = run[0], b = run[1];
+      if (a == b) {   // uniform: no support entry in this row and block
+        if (live) acc = fma((double)r, (double)r, acc);
+        continue;
+      }
+      rs[threadIdx.x] = r;
+      xs[threadIdx.x] = x;
+      mk[threadIdx.x] = 0;
+      __syncthreads();
+      const int64_t base = i * n;
+      if ((int64_t)threadIdx.x < b - a) {
+        const int64_t e = a + threadIdx.x;
+        const int64_t id = support[e];
+        const int q = (int)(id - base - j0);
+        const T rv = rs[q];
+        s_idx[e] = id;
+        s_val[e] = rv;
+        s_x[e] = xs[q];
+        mk[q] = 1;
+        accs = fma((double)rv, (double)rv, accs);
+      }
+      __syncthreads();
+      if (live && !mk[threadIdx.x]) acc = fma((double)r, (double)r, acc);
     }
   }
-  const double tot = block_sum<T>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  double tot = block_sum<T>(acc, red);
+  if (threadIdx.x == 0) pall[blockIdx.x] = tot;
+  __syncthreads();
+  tot = block_sum<T>(accs, red);
+  if (threadIdx.x == 0) psel[blockIdx.x] = tot;
 }
 
-// The plan of a fixed-support step: nnz, sum_sel2 = sum of the gather
-// partials, sum_r2 = sum of the norm partials (strided per thread, then a
-// tree in LDS: a fixed order).
+// The plan of a fixed-support step: nnz, sum_sel2 = sum of the support
+// partials, sum_obs2 = sum of the off-support partials, sum_r2 = both
+// (strided per thread, then a tree in LDS: a fixed order).
 __global__ __launch_bounds__(256) void kc_finish(const double* __restrict__ psel, int nsel,
                                                  const double* __restrict__ pall, int nall,
                                                  int64_t nnz, SelPlan* __restrict__ plan) {
@@ -136,19 +123,14 @@ __global__ __launch_bounds__(256) void kc_finish(const double* __restrict__ psel
   if (threadIdx.x != 0) return;
   plan->nnz = nnz;
   plan->sum_sel2 = ra[0];
-  plan->sum_r2 = rb[0];
+  plan->sum_obs2 = rb[0];
+  plan->sum_r2 = rb[0] + ra[0];
   plan->threshold = 0.0;
   plan->slow = 0;
   plan->overflow = 0;
   plan->mode = SEL_DONE;
 }
 
-unsigned blocks_of(int64_t work) {
-  int64_t g = (work + 255) / 256;
-  if (g > kCompBlocks) g = kCompBlocks;
-  if (g < 1) g = 1;
-  return (unsigned)g;
-}
 
 }  // namespace
 
@@ -168,36 +150,32 @@ unsigned blocks_of(int64_t work) {
 
 void launch_fixed_support(const Launch& L, bool f64, int rp, const void* X, int64_t ldx,
                           const void* UL, const void* VL, int64_t m, int64_t n,
-                          const int64_t* support, int64_t nnz, int64_t* s_idx, void* s_val,
-                          void* s_x, SelPlan* plan, double* scratch) {
-  const unsigned gs = blocks_of(nnz);
-  const bool small = m * n <= (int64_t)0xffffffffLL;
+                          const int64_t* support, const int64_t* row_ptr, int64_t nnz,
+                          int64_t* s_idx, void* s_val, void* s_x, SelPlan* plan,
+                          double* scratch) {
   const int64_t nrb = (m + kNormRows - 1) / kNormRows;
   const int64_t ntiles = nrb * ((n + 255) / 256);
   const unsigned ga = (unsigned)(ntiles < kNormBlocks ? ntiles : kNormBlocks);
   double* psel = scratch;
-  double* pall = scratch + kCompBlocks;
+  double* pall = scratch + kNormBlocks;
   GC_RP_SWITCH(rp, {
-    if (f64) {
-      hipLaunchKernelGGL((kc_gather<double, RP>), dim3(gs), dim3(256), 0, L.stream,
-                         (const double*)X, ldx, (const double*)UL, (const double*)VL, n, small,
-                         support, nnz, s_idx, (double*)s_val, (double*)s_x, psel);
-      hipLaunchKernelGGL((kc_res_norm<double, RP>), dim3(ga), dim3(256), 0, L.stream,
-                         (const double*)X, ldx, (const double*)UL, (const double*)VL, m, n,
-                         nrb, ntiles, pall);
-    } else {
-      hipLaunchKernelGGL((kc_gather<float, RP>), dim3(gs), dim3(256), 0, L.stream,
-                         (const float*)X, ldx, (const float*)UL, (const float*)VL, n, small,
-                         support, nnz, s_idx, (float*)s_val, (float*)s_x, psel);
-      hipLaunchKernelGGL((kc_res_norm<float, RP>), dim3(ga), dim3(256), 0, L.stream,
+    if (f64)
+      hipLaunchKernelGGL((kc_pass<double, RP>), dim3(ga), dim3(256), 0, L.stream,
+                         (const double*)X, ldx, (const double*)UL, (const double*)VL, m, n, nrb,
+                         ntiles, (n + 255) / 256, support, row_ptr, s_idx, (double*)s_val,
+                         (double*)s_x, pall,
+                         psel);
+    else
+      hipLaunchKernelGGL((kc_pass<float, RP>), dim3(ga), dim3(256), 0, L.stream,
                          (const float*)X, ldx, (const float*)UL, (const float*)VL, m, n, nrb,
-                         ntiles, pall);
-    }
+                         ntiles, (n + 255) / 256, support, row_ptr, s_idx, (float*)s_val,
+                         (float*)s_x, pall,
+                         psel);
   });
-  hipLaunchKernelGGL(kc_finish, dim3(1), dim3(256), 0, L.stream, psel, (int)gs, pall, (int)ga,
+  hipLaunchKernelGGL(kc_finish, dim3(1), dim3(256), 0, L.stream, psel, (int)ga, pall, (int)ga,
                      nnz, plan);
 }
 
-int64_t fixed_support_scratch_doubles() { return (int64_t)kCompBlocks + kNormBlocks; }
+int64_t fixed_support_scratch_doubles() { return 2 * (int64_t)kNormBlocks; }
 
 }  // namespace godec
