@@ -74,7 +74,7 @@ def test_f64_per_step(m, n, r, q):
     per_step(X, r, q, miss, 4, 1e-10)
 
 
-@pytest.mark.parametrize("m,n,r,q", [(1000, 700, 8, 1), (2001, 1503, 20, 2)])
+@pytest.mark.parametrize("m,n,r,q", [(1000, 700, 8, 1), (2001, 1503, 20, 2), (30, 20, 2, 1)])
 def test_f32_per_step(m, n, r, q):
     _, X, miss = case(m, n, r, 0.2, seed=m + n, dtype=np.float32, noise=1e-3)
     per_step(X, r, q, miss, 3, 1e-5)

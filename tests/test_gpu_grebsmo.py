@@ -153,6 +153,7 @@ def per_stage_f32(X, r, dr, K, lam, power, seed, tol=1e-5):
     (700, 400, 12, 4, 3, 0.1),      # r > 8: the unfused soft pass + D V^T pass
     (500, 260, 1, 1, 4, 0.1),       # one-column panels
     (500, 260, 2, 2, 3, 0.1),
+    (20, 10, 2, 1, 3, 0.05),        # smaller than one tile in both directions
 ])
 def test_f32_per_stage_parity(m, n, r, dr, K, lam):
     X, _ = problem(m, n, r, seed=m + n, dtype=np.float32)
