@@ -155,6 +155,8 @@ void greedy_step(godec_grebsmo* g) {
 // D V^T partials (mfma_soft_mm_a), so that step starts at their reduction.
 void inner_step(godec_grebsmo* g, bool last) {
   const bool with_r = last && g->rank < g->r;
+  // fused soft pass + next D V^T (FP32, r <= 8, not the stage's last step)
+  const bool fuse = !last && !g->f64 && g->rp <= 8;
   const Launch L = launch_of(g);
   const int64_t ldd = g->pl.ldd, mpad = g->pl.mpad, m = g->m;
   // W = D V^T
@@ -182,15 +184,16 @@ void inner_step(godec_grebsmo* g, bool last) {
     launch_reduce_chunks(L, true, g->rp, g->Zpart, g->pl.nchunks, ldd, g->Vt);
   } else {
     mfma_mm_b(L, false, g->D, ldd, mpad, g->Wt, g->Zpart32, g->pl.rc_b, g->pl.nch_b);
-    mfma_reduce_z(L, g->Zpart32, g->pl.nch_b, ldd, g->rp, (float*)g->Vt);
+    if (fuse)   // the fused soft pass below reads V^T transposed
+      gb_reduce_zt(L, g->Zpart32, g->pl.nch_b, ldd, g->rp, (float*)g->Vt, (float*)g->Zt);
+    else
+      mfma_reduce_z(L, g->Zpart32, g->pl.nch_b, ldd, g->rp, (float*)g->Vt);
   }
   // S = S_lambda(X - U V), D = X - S (and R = X - U V - S)
-  if (!last && !g->f64) {
-    mfma_to_t(L, false, g->Vt, ldd, g->rp, g->Zt);
+  if (fuse)
     g->w_ready = mfma_soft_mm_a(L, g->rp, g->Xp, ldd, mpad, (const float*)g->U,
                                 (const float*)g->Vt, (float)g->lambda, (float*)g->D,
                                 (const float*)g->Zt, g->Wtpart, g->pl.kc_a);
-  }
   if (!g->w_ready)
     gb_soft(L, g->f64, g->rp, g->X, g->ldx, g->U, g->Vt, m, g->n, g->lambda, g->D, ldd,
             with_r ? g->R : nullptr, last ? g->part : nullptr, last ? g->stats : nullptr);

@@ -442,6 +442,10 @@ void gb_soft(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, cons
 // The same S written densely to S (ld lds).
 void gb_soft_s(const Launch& L, bool f64, int rp, const void* X, int64_t ldx, const void* U,
                const void* Vt, int64_t m, int64_t n, double lam, void* S, int64_t lds);
+// V^T = sum of the row-chunk partials Zpart (nch x ldd x 32) into Vt
+// (ldd x rp) and into rows j < rp of Zt (32 x ldd).
+void gb_reduce_zt(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
+                  float* Vt, float* Zt);
 // Vt[:, c0 + c] <- P[:, c], c < cnt (rows x RP panels).
 void gb_put_cols(const Launch& L, bool f64, int rp, const void* P, int64_t rows, int c0,
                  int cnt, void* Vt);

@@ -118,7 +118,46 @@ __global__ __launch_bounds__(256) void kg_put_cols(const TA* __restrict__ P, int
   Vt[i * RP + c0 + c] = P[i * RP + c];
 }
 
+// V^T (ldd x rp) = sum_ch Zpart[ch] (ldd x 32), and its transpose into rows
+// j < rp of Zt (32 x ldd, the B operand of the next matrix-core pass).  One
+// block per 16 consecutive outputs e = c * rp + j; each of 16 chunk lanes
+// adds every 16th chunk (ascending), then the lane sums are added in lane
+// order (a fixed order).
+constexpr int kZtVals = 16;
+constexpr int kZtLanes = 16;
+__global__ __launch_bounds__(256) void kg_reduce_zt(const float* __restrict__ Zpart,
+                                                    int64_t nch, int64_t ldd, int rp,
+                                                    float* __restrict__ Vt,
+                                                    float* __restrict__ Zt) {
+  __shared__ float red[kZtLanes][kZtVals];
+  const int v = threadIdx.x % kZtVals, hl = threadIdx.x / kZtVals;
+  const int64_t e = (int64_t)blockIdx.x * kZtVals + v;
+  const bool live = e < ldd * rp;
+  float s = 0.f;
+  if (live) {
+    const float* p = Zpart + (e / rp) * 32 + (e % rp);
+    const int64_t step = ldd * 32;
+    for (int64_t h = hl; h < nch; h += kZtLanes) s += p[h * step];
+  }
+  red[hl][v] = s;
+  __syncthreads();
+  if (hl == 0 && live) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kZtLanes; ++q) t += red[q][v];
+    Vt[e] = t;
+    Zt[(e % rp) * ldd + e / rp] = t;
+  }
+}
+
 }  // namespace
+
+void gb_reduce_zt(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
+                  float* Vt, float* Zt) {
+  const unsigned b = (unsigned)((ldd * rp + kZtVals - 1) / kZtVals);
+  hipLaunchKernelGGL(kg_reduce_zt, dim3(b), dim3(256), 0, L.stream, Zpart, nch, ldd, rp, Vt,
+                     Zt);
+}
 
 #define GB_RP_SWITCH(rp, ...)                                \
   switch (rp) {                                              \
