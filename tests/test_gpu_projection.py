@@ -87,3 +87,20 @@ def test_f64_w1_trajectory():
     assert eL < 1e-10 and eS < 1e-10
     assert abs(gd.info()["rel_err_sq"] - ref.rel_err_sq[-1]) <= 1e-9 * ref.rel_err_sq[-1]
     gd.close()
+
+
+def test_f64_rank_deficient_x():
+    """X of rank 2 with r = 4: the dependent directions of Q2 come out as zero
+    columns on the GPU, and L = X exactly, as the oracle's projection gives."""
+    from paper_1309_0302_amd.binding import GoDec
+    rng = np.random.default_rng(51)
+    X = rng.standard_normal((120, 2)) @ rng.standard_normal((2, 90))
+    print("\n[proj] rank-2 120 x 90 FP64 with r = 4", flush=True)
+    gd = GoDec(dev(X), 4, 0, 1, seed=3, lstep=1)
+    gd.step(2)
+    L = gd.L_dense().cpu().numpy()
+    ref = g.brp_projection(X, oracle_a1(gd), 1)
+    print(f"  L vs X {g.rel_fro(L, X):.2e}, vs oracle {g.rel_fro(L, ref.L):.2e}", flush=True)
+    assert g.rel_fro(L, X) < 1e-12 and g.rel_fro(L, ref.L) < 1e-12
+    assert np.all(np.isfinite(L))
+    gd.close()

@@ -70,3 +70,23 @@ def test_warm_first_step_equals_cold():
     assert torch.equal(a.L_dense(), b.L_dense())
     a.close()
     b.close()
+
+
+def test_f64_warm_start_after_a_rank_drop():
+    """X of rank 3 with r = 5: the first iteration drops the rank (the root
+    form's rank check) and the warm chains continue on the kept directions,
+    as the oracle's warm run does."""
+    from paper_1309_0302_amd.binding import GoDec
+    rng = np.random.default_rng(52)
+    X = rng.standard_normal((150, 3)) @ rng.standard_normal((3, 110))
+    print("\n[warm] rank-3 150 x 110 FP64 with r = 5, 4 iterations", flush=True)
+    gd = GoDec(dev(X), 5, 0, 1, seed=4, warm_start=1)
+    gd.step(4)
+    ref = g.godec_brp(X, 5, 0, 1, oracle_a1(gd), 4, warm=True)
+    L = gd.L_dense().cpu().numpy()
+    info = gd.info()
+    print(f"  rank_eff {info['rank_eff']} (oracle {ref.r_eff}), L vs oracle "
+          f"{g.rel_fro(L, ref.L):.2e}", flush=True)
+    assert info["rank_eff"] == ref.r_eff == 3
+    assert g.rel_fro(L, ref.L) < 1e-10 and g.rel_fro(L, X) < 1e-10
+    gd.close()
