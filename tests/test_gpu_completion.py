@@ -141,3 +141,19 @@ def test_bf16_form_unsupported():
     with pytest.raises(GodecError) as ei:
         GoDec(dev(X), 2, miss.size, 1, support=sup, prec=GODEC_PREC_BF16_REFINE)
     assert ei.value.status == 6
+
+
+@pytest.mark.parametrize("lstep,warm", [(1, 0), (0, 1), (1, 1)])
+def test_completion_with_other_l_updates(lstep, warm):
+    """The fixed-support S update combines with the projection form and the
+    warm-started chains: the rank-3 matrix is still completed."""
+    from paper_1309_0302_amd.binding import GoDec
+    X0, X, miss = case(120, 100, 3, 0.3, seed=3)
+    sup = torch.from_numpy(miss).cuda()
+    gd = GoDec(dev(X), 3, int(miss.size), 1, seed=9, support=sup, lstep=lstep, warm_start=warm)
+    gd.step(100)
+    L = gd.L_dense().cpu().numpy()
+    eL = np.linalg.norm(L - X0) / np.linalg.norm(X0)
+    print(f"\n[completion] lstep={lstep} warm={warm}: L vs truth {eL:.2e}", flush=True)
+    assert eL <= 1e-10
+    gd.close()
