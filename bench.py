@@ -11,12 +11,24 @@ already resident in device memory.  `--steps K` iterations are timed as one
 solve from S_0 = 0; in the headline mixed-precision form the last iteration
 is the FP32 refinement.  The same K iterations are also timed in plain FP32.
 
-Prints one JSON line with the headline value (iterations/s of the bf16 +
-refinement form), the FP32 plain figure beside it, the roofline of the
-dominant streaming kernel (its launches stamped with their own start and end
-on the library's stream), its HBM traffic from the committed counter record,
-and the FP64 oracle timed on the host cores on a bounded sample.  Secondary
-legs: the 64-problem batched form and the differentiable layer.
+Prints one JSON line with:
+- the headline value (iterations/s of the bf16 + refinement form) and the
+  FP32 plain figure beside it;
+- `roofline`: the per-iteration fraction of the HBM roofline, i.e. the
+  algorithmic bytes of one iteration (one read of D per panel pass, one read
+  of X for the residual and selection, the S corrections and the S write;
+  `iteration_bytes`) over the measured time per iteration, against 8 TB/s;
+  the dominant kernel's own figure (its launches stamped with their start
+  and end on the library's stream) is reported inside it;
+- `precision_vs_oracle`: the relative errors of L, S and the objective of
+  both forms after K iterations against the FP64 oracle's own K-iteration run
+  on the same X and A1 (common-support S error and boundary swaps counted
+  separately);
+- `cpu_baseline`: the FP64 oracle on the host cores, on the same workload
+  (its per-iteration median) and on the 500 x 500 FP64 and 25344 x 200 FP32
+  workloads, with all threads and with one;
+- GPU legs on those two small workloads, and the secondary forms (batched,
+  differentiable layer, projection form, warm start, completion, GreBsmo).
 """
 
 import argparse
@@ -79,6 +91,7 @@ def run_form(X, w, prec, steps, warmup, seed, lstep=0, warm_start=0, q=None):
     ev_ms = e0.elapsed_time(e1)
     info = g.info()
     UL, VL = g.factors()
+    s_idx, s_val = g.S()
     g.close()
     # the same solve again with per-kernel event timing switched on
     g = GoDec(X, w.r, w.k, q, seed=seed, prec=prec, refine_iters=1, lstep=lstep,
@@ -88,51 +101,147 @@ def run_form(X, w, prec, steps, warmup, seed, lstep=0, warm_start=0, q=None):
     stats = g.profile_read()
     g.profile(False)
     g.close()
-    return dict(ms=ev_ms, wall_s=wall, info=info, UL=UL, VL=VL, stats=stats)
+    return dict(ms=ev_ms, wall_s=wall, info=info, UL=UL, VL=VL, s_idx=s_idx, s_val=s_val,
+                stats=stats)
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "godec_w3_mm_a_bf16_hbm_counters.md")
-TRAFFIC_KERNEL = "mm_a_bf16(D*Z)"
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "godec_w3_iteration_hbm_counters.md")
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE record (scaled by a plain copy), or
-    None when there is no record or the kernel's source file (or the file
-    that sets its launch shape) has changed since the counters were taken."""
+def measured_traffic(mixed):
+    """HBM bytes per iteration of the timed form from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record (each scaled by what the counter
+    reads for a plain copy of known size), or None when there is no record
+    for this form or any kernel source has changed since the counters were
+    taken (the record carries the SHA-256 of every source file)."""
     import hashlib
-    if kernel_name != TRAFFIC_KERNEL or not os.path.exists(COUNTERS_FILE):
+    if not os.path.exists(COUNTERS_FILE):
         return None
-    rec = None
+    recs = []
     for line in open(COUNTERS_FILE):
         line = line.strip()
-        if line.startswith("{") and '"hbm_bytes_per_launch"' in line:
-            rec = json.loads(line)
+        if line.startswith("{") and '"hbm_bytes_per_iteration"' in line:
+            recs.append(json.loads(line))
+    want = "bf16_refine" if mixed else "fp32"
+    rec = next((r for r in recs if r.get("form") == want), None)
     if rec is None:
         return None
-    # the kernel's source and the source that sets its launch shape
-    for key in ("source", "launch_source"):
-        if key not in rec:
-            continue
-        src = os.path.join(ROOT, rec[key])
-        if not os.path.exists(src):
+    for path, sha in rec.get("sources", {}).items():
+        src = os.path.join(ROOT, path)
+        if not os.path.exists(src) or \
+                hashlib.sha256(open(src, "rb").read()).hexdigest() != sha:
             return None
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec[key + "_sha256"]:
-            return None
-    return rec["hbm_bytes_per_launch"]
+    return rec["hbm_bytes_per_iteration"]
 
 
-def roofline_of(stats):
-    dom = max(stats, key=lambda s: s["total_ms"])
+def iteration_bytes(m, n, k, q, panel_elem, res_elem=4, refine=False):
+    """Algorithmic HBM bytes of one GoDec iteration of the restated
+    Algorithm 1 (Sec. 3.1.3): 3q + 2 panel passes that each stream D = X - S
+    once (2q + 1 Gram passes of the subspace chain, q of the B chain and the
+    plain B' = D Y pass), one residual / selection read of X, 8 bytes of S
+    correction per entry of S for every panel pass, and 20 bytes per entry
+    of S for the S write and the selection candidates.  In the refinement
+    iteration of the mixed form the last subspace pass and the whole B chain
+    read FP32 (4-byte) D instead of the bf16 copy."""
+    mn = m * n
+    passes = 3 * q + 2
+    if refine:
+        panel = (2 * q) * 2 * mn + (q + 2) * 4 * mn
+    else:
+        panel = passes * panel_elem * mn
+    return panel + res_elem * mn + passes * 8 * k + 20 * k
+
+
+def roofline_of(stats, m, n, k, q, steps, ms, mixed, refine_iters=1, elem=4):
+    """Per-iteration HBM roofline fraction of a timed solve of `steps`
+    iterations taking `ms`: the average algorithmic bytes of its iterations
+    over the measured time per iteration, against the 8 TB/s peak.  The
+    dominant kernel's own bandwidth is reported inside."""
+    if mixed:
+        nref = min(refine_iters, steps)
+        b_avg = ((steps - nref) * iteration_bytes(m, n, k, q, 2)
+                 + nref * iteration_bytes(m, n, k, q, 2, refine=True)) / steps
+    else:
+        b_avg = iteration_bytes(m, n, k, q, elem, res_elem=elem)
+    t_iter = ms / steps * 1e-3
+    achieved = b_avg / t_iter / 1e9
+    dom = max(stats, key=lambda st: st["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
-    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom["name"]),
-            "avg_launch_us": round(avg_ms * 1e3, 2),
-            "bytes_per_launch": dom["bytes_per_launch"],
-            "launches": dom["launches"]}
+    dom_gbs = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    streamed = sum(st["bytes_per_launch"] * st["launches"] for st in stats) / steps
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(mixed),
+            "algorithmic_bytes_per_iteration": round(b_avg),
+            "ms_per_iteration": round(ms / steps, 4),
+            "streamed_bytes_per_iteration": round(streamed),
+            "streamed_over_algorithmic": round(streamed / b_avg, 3),
+            "dominant_kernel": {"name": dom["name"], "launches": dom["launches"],
+                                "avg_launch_us": round(avg_ms * 1e3, 2),
+                                "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
+                                "achieved_GBps": round(dom_gbs, 1),
+                                "frac": round(dom_gbs / HBM_PEAK_GBS, 4)}}
+
+
+def trajectory_errors(X, UL, VL, s_idx, s_val, thr, L_o, S_o, thr_o):
+    """Errors of a GPU run (factors UL, VL; S as sorted linear indices and
+    values; threshold thr) against the oracle's own run (dense L_o, S_o and
+    its threshold) on the same X, all in FP64 on the host:
+    rel_L = ||L - L_o||_F / ||L_o||_F; rel_obj = |e - e_o| / e_o with
+    e = ||X - L - S||_F^2 / ||X||_F^2 computed from the arrays; the S error on
+    the common support and over everything; and the boundary swaps (entries
+    in one support only).  A swap is within the band when its oracle
+    residual lies within 2 max|L - L_o| + |thr - thr_o| of the oracle's
+    threshold."""
+    import numpy as np
+    X = np.asarray(X, dtype=np.float64)
+    L = np.asarray(UL, np.float64) @ np.asarray(VL, np.float64).T
+    nl = np.linalg.norm(L_o)
+    dL = L - L_o
+    rel_L = float(np.linalg.norm(dL) / nl)
+    band_L = float(np.max(np.abs(dL)))
+    del dL
+    idx = np.asarray(s_idx, np.int64)
+    val = np.asarray(s_val, np.float64)
+    Sf = S_o.ravel()
+    idx_o = np.flatnonzero(Sf)
+    common, ia, ib = np.intersect1d(idx, idx_o, assume_unique=True, return_indices=True)
+    vo = Sf[idx_o]
+    rel_S_common = float(np.linalg.norm(val[ia] - vo[ib]) / max(np.linalg.norm(vo[ib]), 1e-300))
+    only_g = np.setdiff1d(idx, idx_o, assume_unique=True)
+    only_o = np.setdiff1d(idx_o, idx, assume_unique=True)
+    # ||S - S_o||^2 over the union: common part plus each side's own entries
+    ga = np.ones(idx.size, bool)
+    ga[ia] = False
+    ob = np.ones(idx_o.size, bool)
+    ob[ib] = False
+    d2 = (np.sum((val[ia] - vo[ib]) ** 2) + np.sum(val[ga] ** 2) + np.sum(vo[ob] ** 2))
+    rel_S = float(np.sqrt(d2) / max(np.linalg.norm(vo), 1e-300))
+    xx = float(np.sum(X * X))
+    E = X - L
+    Ef = E.ravel()
+    Ef[idx] -= val
+    e = float(np.sum(E * E)) / xx
+    del E, Ef
+    E_o = X - L_o - S_o
+    e_o = float(np.sum(E_o * E_o)) / xx
+    del E_o
+    swaps = np.concatenate([only_g, only_o])
+    Xf = X.ravel()
+    band = 2.0 * band_L + abs(thr - thr_o)
+    if swaps.size:
+        r_o = np.abs(Xf[swaps] - L_o.ravel()[swaps])
+        dist = np.abs(r_o - thr_o)
+        worst = float(np.max(dist))
+    else:
+        worst = 0.0
+    return {"rel_L": rel_L, "rel_obj": abs(e - e_o) / e_o if e_o > 0 else abs(e - e_o),
+            "obj": e, "obj_oracle": e_o,
+            "rel_S_common": rel_S_common, "rel_S": rel_S,
+            "common": int(common.size), "swaps": int(swaps.size),
+            "swaps_gpu_only": int(only_g.size), "swaps_oracle_only": int(only_o.size),
+            "swap_band": band, "swap_worst_dist": worst,
+            "swaps_within_band": bool(worst <= band), "max_abs_dL": band_L}
 
 
 def run_batched(iters, warmup, seed=1004):
@@ -351,26 +460,108 @@ def run_copy(nbytes=1 << 30, reps=5):
             "GBps_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}
 
 
-def cpu_baseline(w, iters):
-    """The FP64 oracle on the host cores, `iters` iterations of the same X."""
+def blas_info():
+    """BLAS library and thread count numpy uses (threadpoolctl)."""
+    try:
+        from threadpoolctl import threadpool_info
+        infos = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if infos:
+            i = infos[0]
+            return {"vendor": i.get("internal_api"), "threads": i.get("num_threads"),
+                    "version": i.get("version")}
+    except Exception:
+        pass
+    return {"vendor": None, "threads": None, "version": None}
+
+
+def oracle_run(w, iters, threads=None):
+    """The FP64 oracle's own `iters`-iteration run of workload w (A1 from the
+    workload's seed), on `threads` BLAS threads (None: all)."""
     import numpy as np
     from oracle import godec_ref as g
     from oracle.rng_ref import a1_gaussian
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max(i.get("num_threads", 1) for i in threadpool_info()) or 1
-    except Exception:
-        threads = os.cpu_count() or 1
     A1 = a1_gaussian(w.seed, w.X.shape[1], w.r)
     X = w.X.astype(np.float64)
-    t0 = time.perf_counter()
-    g.godec_brp(X, w.r, w.k, w.q, A1, iters)
-    dt = time.perf_counter() - t0
-    return {"value": round(iters / dt, 4), "unit": "iter/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{iters} FP64 oracle iterations of the full "
-                      f"{w.X.shape[0]}x{w.X.shape[1]} workload (numpy/OpenBLAS), "
-                      f"{dt:.1f} s"}
+    if threads is None:
+        return g.godec_brp(X, w.r, w.k, w.q, A1, iters)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=threads, user_api="blas"):
+        return g.godec_brp(X, w.r, w.k, w.q, A1, iters)
+
+
+def oracle_rate(tr):
+    import numpy as np
+    med = float(np.median(tr.seconds))
+    return {"iter_per_s": round(1.0 / med, 4), "median_s_per_iter": round(med, 5),
+            "iters": len(tr.seconds), "total_s": round(float(np.sum(tr.seconds)), 3)}
+
+
+def run_small_leg(w, prec, reps=5):
+    """GPU leg on a small workload (its own T iterations per solve, FP64 or
+    FP32 native): the median over `reps` timed solves, each timed on the
+    stream with HIP events; returns the rate and the last solve's results."""
+    import numpy as np
+    import torch
+    from paper_1309_0302_amd.binding import GoDec
+    X = torch.from_numpy(w.X).cuda()
+    stream = torch.cuda.current_stream()
+    ms = []
+    for it in range(reps + 1):
+        g = GoDec(X, w.r, w.k, w.q, seed=w.seed, prec=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(w.iters, w.iters)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            ms.append(e0.elapsed_time(e1))
+        if it < reps:
+            g.close()
+    info = g.info()
+    UL, VL = g.factors()
+    idx, val = g.S()
+    out = dict(UL=UL.double().cpu().numpy(), VL=VL.double().cpu().numpy(),
+               idx=idx.cpu().numpy(), val=val.double().cpu().numpy(), info=info)
+    g.close()
+    t = float(np.median(ms))
+    return t, out
+
+
+def host_errors(X, form, tr):
+    """trajectory_errors of a timed GPU form against the oracle's run."""
+    return trajectory_errors(X, form["UL"].double().cpu().numpy(),
+                             form["VL"].double().cpu().numpy(),
+                             form["s_idx"].cpu().numpy(), form["s_val"].double().cpu().numpy(),
+                             form["info"]["threshold"], tr.L, tr.S, tr.thresholds[-1])
+
+
+def small_legs(skip_cpu):
+    """GPU legs on the 500 x 500 FP64 (T = 20) and 25 344 x 200 FP32 (T = 50)
+    workloads, each against the oracle's own run (all host threads), with the
+    oracle's rate on all threads and on one."""
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GODEC_PREC_NATIVE
+    legs = {}
+    for w in (workloads.w1(), workloads.w2()):
+        m, n = w.X.shape
+        name = f"{w.name}_{m}x{n}_{'f64' if w.X.dtype.itemsize == 8 else 'f32'}"
+        log(f"[bench] small leg {name}: {w.iters} iterations")
+        t, res = run_small_leg(w, GODEC_PREC_NATIVE)
+        leg = {"m": m, "n": n, "r": w.r, "k": w.k, "q": w.q, "iterations_per_solve": w.iters,
+               "ms_per_solve": round(t, 4), "iter_per_s": round(w.iters / (t * 1e-3), 1),
+               "algorithmic_bytes_per_iteration": iteration_bytes(
+                   m, n, w.k, w.q, w.X.dtype.itemsize, res_elem=w.X.dtype.itemsize)}
+        if not skip_cpu:
+            tr = oracle_run(w, w.iters)
+            leg["vs_oracle"] = trajectory_errors(w.X, res["UL"], res["VL"], res["idx"],
+                                                 res["val"], res["info"]["threshold"],
+                                                 tr.L, tr.S, tr.thresholds[-1])
+            tr1 = oracle_run(w, w.iters, threads=1)
+            leg["cpu_baseline"] = {"all_threads": oracle_rate(tr), "one_thread": oracle_rate(tr1)}
+        legs[name] = leg
+    return legs
 
 
 def main():
@@ -379,9 +570,9 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=1003)
-    ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=25)
     ap.add_argument("--skip-layer", action="store_true")
@@ -390,7 +581,8 @@ def main():
     ap.add_argument("--skip-completion", action="store_true")
     ap.add_argument("--skip-projection", action="store_true")
     ap.add_argument("--skip-warm", action="store_true")
-    ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo", "completion"],
+    ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo", "completion",
+                                       "small"],
                     help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
@@ -401,6 +593,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_1309_0302_amd import workloads
     from paper_1309_0302_amd.binding import GODEC_PREC_BF16_REFINE, GODEC_PREC_NATIVE
@@ -414,6 +607,9 @@ def main():
     if args.only == "copy":
         print(json.dumps(run_copy()), flush=True)
         return
+    if args.only == "small":
+        print(json.dumps(small_legs(args.skip_cpu)), flush=True)
+        return
     if args.only == "grebsmo":
         out = run_grebsmo(min(args.warmup, 2))
         if not args.skip_cpu:
@@ -425,6 +621,7 @@ def main():
     w = workloads.w3(seed=args.seed, m=args.size, n=args.size)
     X = torch.from_numpy(w.X).cuda()
     torch.cuda.synchronize()
+    m, n = w.X.shape
     if args.only == "completion":
         print(json.dumps(run_completion(X, w, 10, 2)), flush=True)
         return
@@ -450,32 +647,27 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": w.name + "_f32", "m": int(w.X.shape[0]),
-                   "n": int(w.X.shape[1]), "r": w.r, "k": w.k, "q": w.q,
+        "config": {"workload": w.name + "_f32", "m": m, "n": n, "r": w.r, "k": w.k, "q": w.q,
                    "iterations_per_solve": args.steps, "refine_iters": 1,
                    "form": "bf16 panels (fp32 accumulate) + fp32 refinement, "
                            "fp64 r x r core"},
-        "roofline": roofline_of(bf["stats"]),
+        "roofline": roofline_of(bf["stats"], m, n, w.k, w.q, args.steps, bf["ms"], True),
         "final_rel_err_sq": bf["info"]["rel_err_sq"],
     }
     if fp is not None:
         out["fp32_plain"] = {"value": round(args.steps / (fp["ms"] * 1e-3), 2),
                              "ms_per_step": round(fp["ms"] / args.steps, 4),
-                             "roofline": roofline_of(fp["stats"]),
+                             "roofline": roofline_of(fp["stats"], m, n, w.k, w.q, args.steps,
+                                                     fp["ms"], False),
                              "final_rel_err_sq": fp["info"]["rel_err_sq"]}
         out["speedup_vs_fp32_plain"] = round(value / out["fp32_plain"]["value"], 3)
         out["rel_diff_L_bf16_refine_vs_fp32"] = rel_diff_factors(
             bf["UL"], bf["VL"], fp["UL"], fp["VL"])
     out["kernels"] = bf["stats"]
-    # whole-iteration view: every timed streaming launch's algorithmic bytes
-    # (panel passes and the selection pass) over the whole timed solve
-    it_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in bf["stats"]) / args.steps
-    out["iteration_roofline"] = {
-        "streaming_bytes_per_iteration": round(it_bytes),
-        "achieved_GBps": round(it_bytes / (bf["ms"] / args.steps * 1e-3) / 1e9, 1),
-        "frac": round(it_bytes / (bf["ms"] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.skip_copy:
         out["measured_copy"] = run_copy(1 << 30, 5)
+    if not args.skip_small:
+        out["small_workloads"] = small_legs(args.skip_cpu)
     if not args.skip_batch:
         log("[bench] batched form: 64 problems")
         out["batched"] = run_batched(args.batch_iters, min(args.warmup, 3))
@@ -512,12 +704,35 @@ def main():
         log("[bench] GreBsmo: 25344 x 500 video-shaped, r = 4")
         out["grebsmo"] = run_grebsmo(min(args.warmup, 2))
         log(f"[bench] grebsmo {out['grebsmo']['ms_per_solve']} ms/solve")
+    del X
+    torch.cuda.empty_cache()
     if not args.skip_cpu:
         if "grebsmo" in out:
             log("[bench] grebsmo cpu baseline: one oracle solve")
             out["grebsmo"]["cpu_baseline"] = grebsmo_cpu_baseline()
-        log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+        # the oracle's own run of the timed solve's iterations on the same X
+        # and A1: the per-iteration CPU baseline, and the reference for the
+        # errors of both GPU forms (skipped beyond 30 iterations, ~1 s each)
+        iters = min(args.steps, 30)
+        log(f"[bench] cpu baseline: {iters} oracle iterations of the full workload")
+        tr = oracle_run(w, iters)
+        rate = oracle_rate(tr)
+        bl = blas_info()
+        out["cpu_baseline"] = {
+            "value": rate["iter_per_s"], "unit": "iter/s",
+            "cores": bl["threads"] or os.cpu_count(), "kind": "oracle",
+            "sample": f"{iters} FP64 oracle iterations of the full {m}x{n} workload "
+                      f"(numpy/{bl['vendor']}, {bl['threads']} threads); value = 1 / median "
+                      f"per-iteration time; {rate['total_s']} s",
+            "host_cpu_count": os.cpu_count(), "blas": bl, "median_s_per_iter":
+                rate["median_s_per_iter"]}
+        if iters == args.steps:
+            log("[bench] errors of both forms against the oracle's run")
+            pv = {"iterations": iters, "bf16_refine": host_errors(w.X, bf, tr)}
+            if fp is not None:
+                pv["fp32_plain"] = host_errors(w.X, fp, tr)
+            out["precision_vs_oracle"] = pv
+        del tr
     print(json.dumps(out), flush=True)
 
 

@@ -44,6 +44,8 @@ R8  L is evaluated through exact identities of Algorithm 1's lines
 
 from dataclasses import dataclass, field
 
+import time
+
 import numpy as np
 
 RANK_TOL_DEFAULT_ULP = 2.0 ** -52
@@ -282,6 +284,7 @@ class GoDecTrace:
     e2: list = field(default_factory=list)             # ||X-L_t-S_t||^2
     supports: list = field(default_factory=list)       # idx arrays, if kept
     thresholds: list = field(default_factory=list)     # |R| of the k-th kept
+    seconds: list = field(default_factory=list)        # wall time of each iteration
 
 
 def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
@@ -310,6 +313,7 @@ def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
     A = np.asarray(A1, dtype=np.float64)[:, :r]
     tr = GoDecTrace(L=X.copy(), S=S, left=None, right=None, r_eff=r)
     for _ in range(iters):
+        t0 = time.perf_counter()
         D = X - S
         res = brp_projection(D, A, q) if lstep == "proj" else brp_power(D, A, q, rank_tol)
         A = res.right if warm else A[:, :res.r_eff]
@@ -326,6 +330,7 @@ def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
         if keep_supports:
             tr.supports.append(idx)
         tr.L, tr.S, tr.left, tr.right, tr.r_eff = L, S, res.left, res.right, res.r_eff
+        tr.seconds.append(time.perf_counter() - t0)
         if eps is not None and e2 / xx <= eps:
             break
     return tr

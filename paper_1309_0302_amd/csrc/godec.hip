@@ -76,6 +76,7 @@ struct godec_ctx {
   unsigned long long* boff;
   double* norm_x2;
   int* nonfinite;
+  double* s2part;          // fixed-order partial sums (selection, norm check)
   // schedule
   int64_t nchunks, rows_per_chunk;
   int64_t kc_a, nct_a, rc_b, nch_b;   // MFMA tiling
@@ -188,6 +189,7 @@ size_t carve(godec_ctx* c, void* base) {
   c->boff = (unsigned long long*)cv.take((size_t)nb * 8);
   c->norm_x2 = (double*)cv.take(8);
   c->nonfinite = (int*)cv.take(8);
+  c->s2part = (double*)cv.take((size_t)std::max(2 * kSelParts, kNormParts) * 8);
   // completion: start of each (row, 256-column block) run of the support
   c->row_ptr = c->completion
                    ? (int64_t*)cv.take((size_t)m * ((c->n + 255) / 256 + 1) * 8)
@@ -452,6 +454,7 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   a.s_idx = c->s_idx[nxt]; a.s_val = c->s_val[nxt]; a.s_x = c->s_x[nxt];
   a.tie_idx = c->tie_idx;
   a.carry = c->carry;
+  a.s2part = c->s2part;
   if (c->prof) {
     a.ev_a = prof_event(c);
     a.ev_b = prof_event(c);
@@ -643,7 +646,7 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   if (e == hipSuccess) e = hipMemsetAsync(c->VL, 0, (size_t)c->ldd * c->rp * c->ta, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->UL, 0, (size_t)c->m * c->rp * c->ta, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
-  launch_norm_check(L, c->f64, X_dev, ldx, m, n, c->norm_x2, c->nonfinite);
+  launch_norm_check(L, c->f64, X_dev, ldx, m, n, c->norm_x2, c->nonfinite, c->s2part);
   e = hipGetLastError();
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
   int bad = 0;

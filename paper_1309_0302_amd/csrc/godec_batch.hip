@@ -56,6 +56,7 @@ struct godec_batch {
   float* zslots = nullptr;
   double* gslots = nullptr;
   unsigned int* seg_count = nullptr;
+  double* dslots = nullptr;            // fixed-order partial sums
   int max_items = 1;
   int* iter = nullptr;
   int* state = nullptr;        // 2 ints per problem: non-finite flag, current rank
@@ -111,6 +112,7 @@ size_t carve_batch(godec_batch* b, void* base) {
   b->zslots = (float*)cv.take(sizeof(float) * zfl);
   b->gslots = (double*)cv.take(sizeof(double) * items * kBatchRP * kBatchRP);
   b->seg_count = (unsigned int*)cv.take(sizeof(unsigned int) * items * 4);
+  b->dslots = (double*)cv.take(sizeof(double) * (2 * items + 64 * (int64_t)b->count));
   b->iter = (int*)cv.take(sizeof(int));
   b->state = (int*)cv.take(sizeof(int) * 2 * b->count);
   b->tab.assign(b->count, BProb{});
@@ -181,6 +183,8 @@ BatchArgs args_of(const godec_batch* b) {
   a.zslots = b->zslots;
   a.gslots = b->gslots;
   a.seg_count = b->seg_count;
+  a.dslots = b->dslots;
+  a.items_cap = b->items_cap;
   a.max_items = b->max_items;
   a.iter = b->iter;
   a.q = b->q;

@@ -50,6 +50,7 @@ struct godec_grebsmo {
   double* part;                // partial triples of the soft pass
   double* stats;               // [0] sum e^2, [1] sum |s|, [2] nnz, [3] ||X||^2
   int* nonfinite;
+  double* nrm_part;            // partial sums of the norm check
   // state
   int rank = 0;
   int stages = 0;
@@ -102,6 +103,7 @@ size_t carve(godec_grebsmo* g, void* base) {
   g->part = (double*)cv.take((size_t)gb_soft_blocks(g->m, g->n) * 3 * 8);
   g->stats = (double*)cv.take(4 * 8);
   g->nonfinite = (int*)cv.take(8);
+  g->nrm_part = (double*)cv.take((size_t)kNormParts * 8);
   return align_up(cv.off, 256);
 }
 
@@ -291,7 +293,7 @@ godec_status godec_grebsmo_init(godec_grebsmo** out, const void* X_dev, godec_dt
   launch_init_d(L, g->f64 ? F64 : F32, g->f64, g->D, ldd, X_dev, ldx, m, n, mpad);
   if (g->Xp) launch_init_d(L, F32, false, g->Xp, ldd, X_dev, ldx, m, n, mpad);
   launch_small_init(L, g->st, 1);
-  launch_norm_check(L, g->f64, X_dev, ldx, m, n, g->stats + 3, g->nonfinite);
+  launch_norm_check(L, g->f64, X_dev, ldx, m, n, g->stats + 3, g->nonfinite, g->nrm_part);
   e = hipGetLastError();
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
   int bad = 0;

@@ -24,6 +24,11 @@ constexpr int kHistBits = 11;         // later digits
 constexpr int kHistBins = 1 << kHistBits0;
 constexpr int kHistReplicas = 8;      // global histogram copies (contention)
 constexpr int kMaxSeg = 4096;         // most candidate segments (waves of a full pass)
+// Fixed-order partial sums: one slot per block of a full selection pass
+// (kSelParts, at most kMaxSeg / 4 + 1 blocks), the same again for the
+// compaction, and one per block of the norm check (kNormParts).
+constexpr int kSelParts = kMaxSeg / 4 + 8;
+constexpr int kNormParts = 2048;
 constexpr int kBlock = 256;
 
 // Supported padded panel widths.
@@ -180,6 +185,7 @@ struct SelectArgs {
   void* s_x;
   int64_t* tie_idx;     // scratch for ties (cap entries)
   SelCarry* carry;      // persists across iterations
+  double* s2part;       // 2 * kSelParts partial sums (pass 0, then compaction)
   hipEvent_t ev_a = nullptr, ev_b = nullptr;  // optional: bracket pass 0
 };
 void launch_select(const Launch& L, bool f64, int rp, const SelectArgs& a);
@@ -198,8 +204,10 @@ void launch_init_d(const Launch& L, DType td, bool xf64, void* D,
 void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
                      const int64_t* idx, const void* val, const void* xv, const SelPlan* plan,
                      int64_t kmax);
+// *out2 = ||X||_F^2 summed in a fixed order through `part` (kNormParts
+// doubles of scratch); *nonfinite |= 1 on a NaN/Inf entry.
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx,
-                       int64_t m, int64_t n, double* out2, int* nonfinite);
+                       int64_t m, int64_t n, double* out2, int* nonfinite, double* part);
 void launch_sort_s(const Launch& L, bool f64, const int64_t* idx,
                    const void* val, const SelPlan* plan, int64_t mn,
                    int64_t kmax, uint32_t* bitmap, uint32_t* wpre,
@@ -312,6 +320,11 @@ struct BatchArgs {
   float* zslots;                       // Gram-pass partials (n x 8 per item)
   double* gslots;                      // FP64 Gram partials of B' (8 x 8 per item)
   int* iter;                           // device iteration counter
+  // fixed-order partial sums: [0, items_cap) sum R^2 per work item,
+  // [items_cap, 2 items_cap) ||X||^2 per work item (init), then 64 per
+  // problem for the compaction's sum S^2
+  double* dslots;
+  int64_t items_cap;
   int q, p;
   int rows_per_item;                   // most rows of a work item
 };

@@ -383,7 +383,8 @@ __device__ __forceinline__ void sel_rows(const SelArgs& A, const ColMap& cm, int
 template <int KIND>
 __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ probs,
                                                    const BItem* __restrict__ items,
-                                                   unsigned int* __restrict__ seg_count) {
+                                                   unsigned int* __restrict__ seg_count,
+                                                   double* __restrict__ s2slot) {
   extern __shared__ __align__(16) unsigned char sel_lds[];
   unsigned int* lh = reinterpret_cast<unsigned int*>(sel_lds);
   float* us = reinterpret_cast<float*>(sel_lds + sizeof(unsigned int) * kHistBins);
@@ -393,7 +394,8 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
   const BProb& b = probs[it.prob];
   BSel* sel = b.sel;
   const int want = KIND == 0 ? BS_HIST : (KIND == 1 ? BS_COLLECT : BS_CARRY);
-  if (sel->mode != want) return;
+  // k == 0 (BS_NONE) problems take the histogram pass for the objective alone
+  if (sel->mode != want && !(KIND == 0 && sel->mode == BS_NONE)) return;
   const int n = (int)b.n;
   const ColMap cm = colmap(n);
   const int rsub = tid / cm.lanes;
@@ -446,7 +448,9 @@ __global__ __launch_bounds__(256) void kb_sel_pass(const BProb* __restrict__ pro
     if (lane == 0) red[wave] = s2;
     if (bad) atomicOr(&sel->nonfinite, 1);
     __syncthreads();
-    if (tid == 0 && A.add_s2) atomicAdd(&sel->sum_r2, red[0] + red[1] + red[2] + red[3]);
+    // per-item partial of sum R^2 (one pass per problem and iteration writes
+    // it); kb_ties adds the problem's items in order
+    if (tid == 0 && A.add_s2) s2slot[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
   }
 }
 
@@ -594,7 +598,7 @@ __global__ __launch_bounds__(256) void kb_cand_hist(const BProb* __restrict__ pr
 __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ probs,
                                                   const BItem* __restrict__ items,
                                                   const unsigned int* __restrict__ seg_count,
-                                                  int cur) {
+                                                  int cur, double* __restrict__ cslot) {
   __shared__ double red[4];
   __shared__ unsigned long long wcnt[2][4];
   __shared__ unsigned long long wbase[2][4];
@@ -692,14 +696,18 @@ __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ prob
   s2 = wave_sum(s2);
   if (lane == 0) red[wave] = s2;
   __syncthreads();
-  if (tid == 0) atomicAdd(&s->sum_sel2, red[0] + red[1] + red[2] + red[3]);
+  // per-block partial of sum S^2; kb_ties adds the problem's blocks in order
+  if (tid == 0)
+    cslot[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Ties: keep the k_rem smallest linear indices among the candidates equal to
 // the threshold (bitonic sort in LDS when they fit, else a radix select on
 // the index).  One workgroup per problem.  Also sets nnz, the threshold and
 // the objective.
-__global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs, int cur) {
+__global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs, int cur,
+                                                const double* __restrict__ s2slot,
+                                                const double* __restrict__ cslot, int cblocks) {
   constexpr int NS = 4096;
   __shared__ unsigned long long sk[NS];     // linear indices
   __shared__ int sp[NS];                    // their tie-list slots
@@ -707,16 +715,23 @@ __global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs,
   __shared__ unsigned long long sh_pref;
   __shared__ long long sh_need;
   __shared__ unsigned int wpos;
+  __shared__ double red[20];
   const BProb& b = probs[blockIdx.x];
   BSel* s = b.sel;
   const int tid = threadIdx.x;
+  // the objective's sums from their partials, in item / block order
+  const double r2 = block_sum_fixed(s2slot + b.item0, b.nitems, red);
+  const double sel_above =
+      block_sum_fixed(cslot + (int64_t)blockIdx.x * cblocks, cblocks, red);
+  if (tid == 0) s->sum_r2 = r2;
   if (s->mode == BS_NONE) {
     if (tid == 0) {
       s->carry_valid = 0;
       s->nnz = 0;
       s->nnz_list[cur] = 0;
       s->threshold = 0.0;
-      s->rel_err_sq = s->norm_x2 > 0.0 ? s->sum_r2 / s->norm_x2 : 0.0;
+      s->sum_sel2 = 0.0;
+      s->rel_err_sq = s->norm_x2 > 0.0 ? r2 / s->norm_x2 : 0.0;
     }
     return;
   }
@@ -817,8 +832,8 @@ __global__ __launch_bounds__(1024) void kb_ties(const BProb* __restrict__ probs,
     s->nnz = nabove + take;
     s->nnz_list[cur] = nabove + take;
     s->threshold = (double)tval;
-    s->sum_sel2 += (double)take * (double)tval * (double)tval;
-    s->rel_err_sq = s->norm_x2 > 0.0 ? (s->sum_r2 - s->sum_sel2) / s->norm_x2 : 0.0;
+    s->sum_sel2 = sel_above + (double)take * (double)tval * (double)tval;
+    s->rel_err_sq = s->norm_x2 > 0.0 ? (r2 - s->sum_sel2) / s->norm_x2 : 0.0;
   }
 }
 
@@ -840,7 +855,8 @@ __global__ __launch_bounds__(256) void kb_update_d(const BProb* __restrict__ pro
 
 // D = X (rows of the item), ||X||_F^2 and the NaN/Inf check.
 __global__ __launch_bounds__(256) void kb_init_d(const BProb* __restrict__ probs,
-                                                 const BItem* __restrict__ items) {
+                                                 const BItem* __restrict__ items,
+                                                 double* __restrict__ nslot) {
   __shared__ double red[4];
   const BItem it = items[blockIdx.x];
   const BProb& b = probs[it.prob];
@@ -862,7 +878,17 @@ __global__ __launch_bounds__(256) void kb_init_d(const BProb* __restrict__ probs
   if ((tid & 63) == 0) red[tid >> 6] = s2;
   if (bad) atomicOr(&b.sel->nonfinite, 1);
   __syncthreads();
-  if (tid == 0) atomicAdd(&b.sel->norm_x2, red[0] + red[1] + red[2] + red[3]);
+  if (tid == 0) nslot[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ||X||_F^2 of each problem from its items' partials, in item order (one
+// workgroup per problem).
+__global__ __launch_bounds__(256) void kb_norm_sum(const BProb* __restrict__ probs,
+                                                   const double* __restrict__ nslot) {
+  __shared__ double red[8];
+  const BProb& b = probs[blockIdx.x];
+  const double s = block_sum_fixed(nslot + b.item0, b.nitems, red);
+  if (threadIdx.x == 0) b.sel->norm_x2 = s;
 }
 
 // Residual R = X - U_L V_L^T of one problem (getter).
@@ -937,13 +963,13 @@ void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
                      sizeof(float) * RP8 * (size_t)std::min(a.rows_per_item, kBatchMaxRows);
   hipLaunchKernelGGL(kb_sel_reset, dim3(np), dim3(256), 0, L.stream, a.probs);
   hipLaunchKernelGGL(kb_sel_pass<2>, dim3((unsigned)a.nitems), dim3(256), lds, L.stream, a.probs,
-                     a.items, a.seg_count);
+                     a.items, a.seg_count, a.dslots);
   hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, -1);
   hipLaunchKernelGGL(kb_sel_pass<0>, dim3((unsigned)a.nitems), dim3(256), lds, L.stream, a.probs,
-                     a.items, a.seg_count);
+                     a.items, a.seg_count, a.dslots);
   hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, 0);
   hipLaunchKernelGGL(kb_sel_pass<1>, dim3((unsigned)a.nitems), dim3(256), lds, L.stream, a.probs,
-                     a.items, a.seg_count);
+                     a.items, a.seg_count, a.dslots);
   hipLaunchKernelGGL(kb_sel_to_refine, dim3((np + 63) / 64), dim3(64), 0, L.stream, a.probs,
                      a.nprob);
   // blocks per problem over its candidate segments
@@ -954,9 +980,11 @@ void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
                        a.seg_count);
     hipLaunchKernelGGL(kb_sel_plan, dim3(np), dim3(256), 0, L.stream, a.probs, level);
   }
+  double* cslot = a.dslots + 2 * (int64_t)a.items_cap;
   hipLaunchKernelGGL(kb_compact, dim3(cb, np), dim3(256), 0, L.stream, a.probs, a.items,
-                     a.seg_count, cur);
-  hipLaunchKernelGGL(kb_ties, dim3(np), dim3(1024), 0, L.stream, a.probs, cur);
+                     a.seg_count, cur, cslot);
+  hipLaunchKernelGGL(kb_ties, dim3(np), dim3(1024), 0, L.stream, a.probs, cur,
+                     (const double*)a.dslots, (const double*)cslot, (int)cb);
 }
 
 void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
@@ -969,8 +997,11 @@ void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
 }
 
 void bl_init(const Launch& L, const BatchArgs& a) {
+  double* nslot = a.dslots + a.items_cap;
   hipLaunchKernelGGL(kb_init_d, dim3((unsigned)a.nitems), dim3(256), 0, L.stream, a.probs,
-                     a.items);
+                     a.items, nslot);
+  hipLaunchKernelGGL(kb_norm_sum, dim3((unsigned)a.nprob), dim3(256), 0, L.stream, a.probs,
+                     (const double*)nslot);
 }
 
 void bl_residual(const Launch& L, const BProb* prob_dev, int64_t m, int64_t n, float* R,

@@ -56,6 +56,28 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sum of p[0 .. n) in an order fixed by n and the block size alone, so a
+// run reproduces its own bits: thread t adds p[t], p[t + B], ... in turn,
+// each wave reduces by the butterfly of wave_sum, and thread 0 adds the wave
+// sums in wave order.  Every thread of the block must call it (it holds two
+// block barriers); the result is returned to every thread.  red: shared
+// scratch of at least blockDim.x / 64 + 1 doubles.
+__device__ inline double block_sum_fixed(const double* __restrict__ p, int64_t n, double* red) {
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) s += p[e];
+  s = wave_sum(s);
+  const int nw = (int)(blockDim.x >> 6);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    red[nw] = t;
+  }
+  __syncthreads();
+  return red[nw];
+}
+
 // Monotone integer key of |x|: the IEEE bits with the sign cleared.
 __device__ __forceinline__ unsigned long long abs_key(float x) {
   return (unsigned long long)(__float_as_uint(x) & 0x7fffffffu);

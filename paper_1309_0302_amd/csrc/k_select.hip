@@ -447,9 +447,22 @@ __global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int6
                                                    int64_t* __restrict__ cand_idx,
                                                    T* __restrict__ cand_val,
                                                    T* __restrict__ cand_x,
-                                                   unsigned int* __restrict__ seg_count) {
-  if (plan->mode != SEL_HIST) return;   // k == 0
+                                                   unsigned int* __restrict__ seg_count,
+                                                   double* __restrict__ s2part) {
   GODEC_SEL_SHARED
+  if (plan->mode != SEL_HIST) {
+    // k == 0 (S_t = 0): only the objective, sum R^2 over every entry
+    const bool vec_ok0 = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
+    PassKeys<T> pk0 = keys_level0<T>();
+    double s20 = 0.0;
+    sel_pass_body<T, RP, false, false, true>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk0, sink,
+                                             vec_ok0, s20);
+    s20 = wave_sum(s20);
+    if (lane == 0) red[wave] = s20;
+    __syncthreads();
+    if (tid == 0) s2part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    return;
+  }
   const int carry = plan->carry_used;
   PassKeys<T> pk = keys_level0<T>();
   if (carry) {
@@ -477,7 +490,8 @@ __global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int6
   s2 = wave_sum(s2);
   if (lane == 0) red[wave] = s2;
   __syncthreads();
-  if (tid == 0) atomicAdd(&plan->sum_r2, red[0] + red[1] + red[2] + red[3]);
+  // per-block partial; k_sel_plan adds them in block order
+  if (tid == 0) s2part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Later passes (first iteration and fall-backs): the level-0 histogram
@@ -568,12 +582,19 @@ __global__ __launch_bounds__(256) void k_cand_hist(SelPlan* __restrict__ plan,
 template <typename T>
 __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
                                                   unsigned long long* __restrict__ hist,
-                                                  int stage) {
+                                                  int stage, const double* __restrict__ s2part,
+                                                  int ns2) {
   constexpr int KB = KeyBits<T>::value;
   __shared__ unsigned long long h[kHistBins];
   __shared__ unsigned long long part[256];
   __shared__ int sel_t;
+  __shared__ double red[8];
   const int tid = threadIdx.x;
+  if (s2part) {
+    // right after pass 0: its per-block sums of R^2, added in block order
+    const double s = block_sum_fixed(s2part, ns2, red);
+    if (tid == 0) plan->sum_r2 = s;
+  }
   const int mode = plan->mode;
   if (stage == 0 && (mode == SEL_COLLECT || mode == SEL_TIES)) {
     if (tid == 0) {
@@ -698,7 +719,8 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
                                                      T* __restrict__ s_val,
                                                      T* __restrict__ s_x,
                                                      int64_t* __restrict__ tie_idx,
-                                                     unsigned long long* __restrict__ counters) {
+                                                     unsigned long long* __restrict__ counters,
+                                                     double* __restrict__ s2sel) {
   __shared__ double red[4];
   __shared__ unsigned int wa[4], wt[4];
   __shared__ unsigned long long base_a, base_t;
@@ -777,7 +799,8 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
   s2 = wave_sum(s2);
   if (lane == 0) red[wave] = s2;
   __syncthreads();
-  if (tid == 0) atomicAdd(&plan->sum_sel2, red[0] + red[1] + red[2] + red[3]);
+  // per-block partial; k_sel_ties adds them in block order
+  if (tid == 0) s2sel[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Resolve ties: keep the k_rem smallest linear indices among the entries
@@ -801,15 +824,20 @@ __global__ __launch_bounds__(1024) void k_sel_ties(SelPlan* __restrict__ plan,
                                                    T* __restrict__ s_val,
                                                    int64_t* __restrict__ tie_idx,
                                                    unsigned long long* __restrict__ counters,
-                                                   SelCarry* __restrict__ carry) {
+                                                   SelCarry* __restrict__ carry,
+                                                   const double* __restrict__ s2sel, int nsel) {
   constexpr int KB = KeyBits<T>::value;
   constexpr int NS = 4096;
   __shared__ int64_t sk[NS];
   __shared__ unsigned long long cnt[256];
   __shared__ unsigned long long sh_pref;
   __shared__ long long sh_need;
+  __shared__ double red[20];
   const int tid = threadIdx.x;
   if (plan->mode != SEL_FINAL) return;
+  // sum of S_t^2 over the entries above the threshold: the compaction's
+  // per-block partials in block order
+  const double sel_above = block_sum_fixed(s2sel, nsel, red);
   const unsigned long long tkey = plan->prefix;
   long long nabove = (long long)counters[0];
   if (nabove > plan->count_above) nabove = plan->count_above;
@@ -886,7 +914,7 @@ __global__ __launch_bounds__(1024) void k_sel_ties(SelPlan* __restrict__ plan,
   if (tid == 0) {
     plan->nnz = nabove + take;
     plan->threshold = (double)tval;
-    plan->sum_sel2 += (double)take * (double)tval * (double)tval;
+    plan->sum_sel2 = sel_above + (double)take * (double)tval * (double)tval;
     carry_update<T>(carry, tkey);
   }
 }
@@ -1268,7 +1296,7 @@ __global__ __launch_bounds__(256) void k_update_d(TD* __restrict__ D, int64_t ld
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_norm_check(const T* __restrict__ X, int64_t ldx,
-                                                    int64_t m, int64_t n, double* out2,
+                                                    int64_t m, int64_t n, double* part,
                                                     int* nonfinite) {
   __shared__ double red[4];
   double s = 0.0;
@@ -1284,7 +1312,15 @@ __global__ __launch_bounds__(256) void k_norm_check(const T* __restrict__ X, int
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out2, red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// out = the sum of part[0 .. n) in a fixed order (one block).
+__global__ __launch_bounds__(256) void k_sum_fixed(const double* __restrict__ part, int64_t n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[8];
+  const double s = block_sum_fixed(part, n, red);
+  if (threadIdx.x == 0) *out = s;
 }
 
 // Ordered output of S: set bits of a bitmap over the linear indices, scan
@@ -1429,7 +1465,7 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
         hipLaunchKernelGGL((k_sel_pass0<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
                            (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VLt, a.ldv, a.m,
                            a.n, a.plan, a.hist, a.cand_idx, (T*)a.cand_val, (T*)a.cand_x,
-                           a.seg_count);
+                           a.seg_count, a.s2part);
         if (a.ev_b) (void)hipEventRecord(a.ev_b, L.stream);
       } else {
         hipLaunchKernelGGL((k_sel_passN<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
@@ -1437,14 +1473,16 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
                            a.n, a.plan, a.hist, a.cand_idx, (T*)a.cand_val, (T*)a.cand_x,
                            a.seg_count);
       }
-      hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 0);
+      hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 0,
+                         pass == 0 ? (const double*)a.s2part : nullptr, (int)g);
     }
   });
   const unsigned cg = (unsigned)(g + 1);   // segments are taken round-robin by blocks
   for (int round = 0; round < levels - 1; ++round) {
     hipLaunchKernelGGL(k_cand_hist<T>, dim3(cg), dim3(256), 0, L.stream, a.plan,
                        (const T*)a.cand_val, (const unsigned int*)a.seg_count, a.hist);
-    hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 1);
+    hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 1,
+                       (const double*)nullptr, 0);
   }
   GODEC_RP_SWITCH(rp, {
     hipLaunchKernelGGL((k_sel_ties_stream<T, RP>), dim3(1), dim3(256), 0, L.stream,
@@ -1456,9 +1494,11 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
   });
   hipLaunchKernelGGL(k_sel_compact<T>, dim3(cg), dim3(256), 0, L.stream, a.plan, a.cand_idx,
                      (const T*)a.cand_val, (const T*)a.cand_x, (const unsigned int*)a.seg_count,
-                     a.s_idx, (T*)a.s_val, (T*)a.s_x, a.tie_idx, a.counters);
+                     a.s_idx, (T*)a.s_val, (T*)a.s_x, a.tie_idx, a.counters,
+                     a.s2part + kSelParts);
   hipLaunchKernelGGL(k_sel_ties<T>, dim3(1), dim3(1024), 0, L.stream, a.plan, a.s_idx,
-                     (T*)a.s_val, a.tie_idx, a.counters, a.carry);
+                     (T*)a.s_val, a.tie_idx, a.counters, a.carry,
+                     (const double*)(a.s2part + kSelParts), (int)cg);
   GODEC_RP_SWITCH(rp, {
     hipLaunchKernelGGL((k_fix_tie_values<T, RP>), dim3(grid_for(a.k, L.num_cu, 2)), dim3(256),
                        0, L.stream, (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL,
@@ -1531,14 +1571,16 @@ void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
 }
 
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx, int64_t m,
-                       int64_t n, double* out2, int* nonfinite) {
-  const unsigned g = grid_for(m * n, L.num_cu, 8);
+                       int64_t n, double* out2, int* nonfinite, double* part) {
+  const unsigned g = std::min<unsigned>(grid_for(m * n, L.num_cu, 8), (unsigned)kNormParts);
   if (f64)
     hipLaunchKernelGGL(k_norm_check<double>, dim3(g), dim3(256), 0, L.stream,
-                       (const double*)X, ldx, m, n, out2, nonfinite);
+                       (const double*)X, ldx, m, n, part, nonfinite);
   else
     hipLaunchKernelGGL(k_norm_check<float>, dim3(g), dim3(256), 0, L.stream, (const float*)X,
-                       ldx, m, n, out2, nonfinite);
+                       ldx, m, n, part, nonfinite);
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, L.stream, (const double*)part,
+                     (int64_t)g, out2);
 }
 
 void launch_sort_s(const Launch& L, bool f64, const int64_t* idx, const void* val,

@@ -38,8 +38,9 @@ torch = pytest.importorskip("torch")
 # (B^T B)^(-1/3) and the orthonormal-range derivative; the r x r algebra is
 # FP64.  Measured 2.1e-6 and 2.6e-6 on two problems of the 4096 x 256
 # workload, below 1e-6 on the 300 x 520 case and up to 5.5e-6 on the
-# 700 x 512, r = 8 case.
-FP32_GRAD_TOL = 1e-4
+# 700 x 512, r = 8 case; the bar is about twice the largest, so that a
+# regression of a few times fails.
+FP32_GRAD_TOL = 1.2e-5
 
 
 def small_case(seed, q):
