@@ -546,7 +546,7 @@ def small_legs(skip_cpu):
     legs = {}
     for w in (workloads.w1(), workloads.w2()):
         m, n = w.X.shape
-        name = f"{w.name}_{m}x{n}_{'f64' if w.X.dtype.itemsize == 8 else 'f32'}"
+        name = w.name
         log(f"[bench] small leg {name}: {w.iters} iterations")
         t, res = run_small_leg(w, GODEC_PREC_NATIVE)
         leg = {"m": m, "n": n, "r": w.r, "k": w.k, "q": w.q, "iterations_per_solve": w.iters,
