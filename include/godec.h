@@ -175,6 +175,30 @@ godec_status godec_solve_tol(const void* X_dev, godec_dtype dtype, int64_t m,
                              int64_t* S_idx_dev, void* S_val_dev,
                              godec_info* info);
 
+/* godec_solve without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The workspace is a device array inside
+ * the library of GODEC_STATIC_SCRATCH_BYTES bytes (128 MiB), one copy per
+ * GPU the library runs on, held until the process ends.  The call allocates
+ * no device memory and calls no allocating routine; the caller still passes
+ * X and the outputs, exactly as for godec_solve.
+ * Limit: problems whose godec_workspace_size exceeds the scratch are
+ * rejected with GODEC_E_UNSUPPORTED (the 500 x 500 FP64 and 25 344 x 200
+ * FP32 workloads fit; 10 000 x 10 000 does not).
+ * Sharing: every call on one GPU uses that GPU's single array, which keeps
+ * the last call's contents; calls that overlap on one GPU (several streams
+ * or host threads) race and must be serialised by the caller.  The call
+ * synchronises opts->stream before returning (as godec_solve does).
+ * Errors as godec_solve, plus GODEC_E_DEVICE if the array's device address
+ * cannot be obtained. */
+#define GODEC_STATIC_SCRATCH_BYTES (128ull << 20)
+godec_status godec_solve_static(const void* X_dev, godec_dtype dtype, int64_t m,
+                                int64_t n, int64_t ldx, int32_t r, int64_t k,
+                                int32_t q, uint64_t seed, int32_t iters,
+                                const godec_opts* opts, void* UL_dev, void* VL_dev,
+                                int64_t* S_idx_dev, void* S_val_dev,
+                                godec_info* info);
+
 /* L = UL * VL^T: UL_dev m x r, VL_dev n x r, row-major, dtype of X.
  * Columns past rank_eff are zero.  Asynchronous. */
 godec_status godec_get_factors(godec_ctx* ctx, void* UL_dev, void* VL_dev);

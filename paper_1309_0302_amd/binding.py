@@ -85,6 +85,9 @@ _SIG = {
                            ctypes.c_uint64, _I32, _P, ctypes.c_size_t,
                            ctypes.POINTER(godec_opts), _P, _P, _P, _P,
                            ctypes.POINTER(godec_info)]),
+    "godec_solve_static": (_I32, [_P, _I32, _I64, _I64, _I64, _I32, _I64, _I32,
+                                  ctypes.c_uint64, _I32, ctypes.POINTER(godec_opts),
+                                  _P, _P, _P, _P, ctypes.POINTER(godec_info)]),
     "godec_solve_tol": (_I32, [_P, _I32, _I64, _I64, _I64, _I32, _I64, _I32,
                                ctypes.c_uint64, _I32, ctypes.c_double, _P, ctypes.c_size_t,
                                ctypes.POINTER(godec_opts), _P, _P, _P, _P,
@@ -296,6 +299,28 @@ def godec_solve(X, r, k, q, seed, iters, opts=None):
                               seed, iters, base, ws_bytes, ctypes.byref(opts),
                               UL.data_ptr(), VL.data_ptr(), sidx.data_ptr(),
                               sval.data_ptr(), ctypes.byref(info)))
+    nnz = info.nnz
+    return UL, VL, sidx[:nnz], sval[:nnz], info.as_dict()
+
+
+GODEC_STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def godec_solve_static(X, r, k, q, seed, iters, opts=None):
+    """godec_solve on the library's own device scratch (no workspace is
+    allocated by the library); returns (UL, VL, S_idx, S_val, info)."""
+    import torch
+    m, n = X.shape
+    dt = _dtype_code(X)
+    opts = opts if opts is not None else make_opts()[0]
+    UL = torch.zeros((m, r), dtype=X.dtype, device=X.device)
+    VL = torch.zeros((n, r), dtype=X.dtype, device=X.device)
+    sidx = torch.zeros(max(k, 1), dtype=torch.int64, device=X.device)
+    sval = torch.zeros(max(k, 1), dtype=X.dtype, device=X.device)
+    info = godec_info()
+    _check(load().godec_solve_static(X.data_ptr(), dt, m, n, X.stride(0), r, k, q, seed,
+                                     iters, ctypes.byref(opts), UL.data_ptr(), VL.data_ptr(),
+                                     sidx.data_ptr(), sval.data_ptr(), ctypes.byref(info)))
     nnz = info.nnz
     return UL, VL, sidx[:nnz], sval[:nnz], info.as_dict()
 
