@@ -34,4 +34,10 @@ Pinning status (each function's docstring repeats it):
                                recovery of a noiseless low-rank + sparse X)
     rng_ref.a1_gaussian        pinned (SplitMix64 published test vectors;
                                moments of the Gaussian draw)
+    mse_ref.mse_train          pinned (MSE training, Sec. 4.2.1 / Algorithm 4:
+                               initialisation invariant; label update against
+                               the printed lines, the truncated SVD and the
+                               Thm. 3 bound; one-sweep recovery with disjoint
+                               labels; signed brute-force top-K; label order;
+                               one label = GoDec at q = 0)
 """

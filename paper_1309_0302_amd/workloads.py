@@ -37,6 +37,17 @@ Matrix completion (Sec. 2, fixed support) workload:
 M1  the W3 matrix (10 000 x 10 000 FP32, r = 20, q = 2) with a seeded 10 %
     of its entries unobserved (``missing_support``).
 
+MSE1, MSE2  multi-label training matrices for MSE training (Sec. 4.2.1),
+    standing in for the multi-label datasets of Sec. 5 (not available):
+    n samples x p features; each of k labels is carried by each sample with
+    probability `label_prob` (a sample with none gets one label drawn
+    uniformly); label i has rank r_i ~ U{2 .. rmax} and contributes
+    U_i V_i^T on its rows with U_i, V_i iid N(0, var 1/sqrt(r_i)) (unit
+    variance entries); 2% sparse entries U[-5, 5]; noise std 1e-3;
+    K = the sparse support size.
+    MSE1: n = 2048, p = 128, k = 8, rmax = 6, label_prob 0.2, T = 10.
+    MSE2: n = 65 536, p = 512, k = 32, rmax = 8, label_prob 0.1, T = 10.
+
 G2  25 344 x 500 FP32 video-shaped matrix (144 x 176 pixels x 500 frames,
     the shape of the Hall sequence of Sec. 5.5) from the W2 recipe with 500
     frames; r = 4, dr = 1, K = 10, lam = 0.125, power = 2.
@@ -265,3 +276,55 @@ def missing_support(m: int, n: int, frac: float, seed: int,
         c1 = min(c0 + chunk, total)
         out.append(np.flatnonzero(rng.random(c1 - c0) < frac).astype(np.int64) + c0)
     return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+@dataclass
+class MseWorkload:
+    name: str
+    X: np.ndarray
+    labels: list          # k ascending int64 row sets Omega_i
+    ranks: list           # r_i
+    K: int
+    iters: int
+    seed: int
+    recipe: dict = field(default_factory=dict)
+
+
+def multilabel(n: int, p: int, k: int, *, rmax: int, label_prob: float,
+               support_frac: float = 0.02, amp: float = 5.0,
+               noise_std: float = 1e-3, seed: int, dtype=np.float64,
+               iters: int = 10, name: str | None = None) -> MseWorkload:
+    """X = sum_i (rows Omega_i: U_i V_i^T) + sparse + noise with random label
+    sets (the MSE model of Sec. 4.2.1), built in FP64 and cast once."""
+    rng = np.random.default_rng(seed)
+    Y = rng.random((n, k)) < label_prob
+    none = np.flatnonzero(~Y.any(axis=1))
+    Y[none, rng.integers(0, k, size=none.size)] = True
+    ranks = [int(v) for v in rng.integers(2, rmax + 1, size=k)]
+    X = np.zeros((n, p))
+    labels = []
+    for i in range(k):
+        rows = np.flatnonzero(Y[:, i]).astype(np.int64)
+        std = (1.0 / np.sqrt(ranks[i])) ** 0.5
+        U = rng.standard_normal((rows.size, ranks[i])) * std
+        V = rng.standard_normal((p, ranks[i])) * std
+        X[rows] += U @ V.T
+        labels.append(rows)
+    K = round_half_up(support_frac * n * p)
+    idx = rng.choice(n * p, size=K, replace=False)
+    X.flat[idx] += rng.uniform(-amp, amp, size=K)
+    X += rng.standard_normal((n, p)) * noise_std
+    return MseWorkload(name or f"mse_{n}x{p}_k{k}", X.astype(dtype, copy=False), labels,
+                       ranks, K, iters, seed,
+                       dict(label_prob=label_prob, rmax=rmax, support_frac=support_frac,
+                            amp=amp, noise_std=noise_std, dtype=np.dtype(dtype).name))
+
+
+def mse1(seed: int = 1010, dtype=np.float64) -> MseWorkload:
+    return multilabel(2048, 128, 8, rmax=6, label_prob=0.2, seed=seed, dtype=dtype,
+                      name="mse1_2048x128_k8")
+
+
+def mse2(seed: int = 1011, dtype=np.float32) -> MseWorkload:
+    return multilabel(65536, 512, 32, rmax=8, label_prob=0.1, seed=seed, dtype=dtype,
+                      name="mse2_65536x512_k32")
