@@ -443,6 +443,62 @@ def run_completion(X, w, iters, warmup, frac=0.1, seed=1008):
             "rel_err_sq_observed": info["rel_err_sq"]}
 
 
+def mse_bytes(w):
+    """Algorithmic bytes of one MSE training iteration (Algorithm 4): per
+    label two reads of its rows of the residual (N A1 with N^T Y1 in one
+    read, then N Y2) and one write of them, the sparse step's read of
+    X - sum L, 20 bytes per entry of S for the S write and candidates, and
+    two scattered S updates of the residual (12 bytes each per entry)."""
+    n, p = w.X.shape
+    rows = sum(len(r) for r in w.labels)
+    return 3 * rows * p * 4 + n * p * 4 + 20 * w.K + 24 * w.K
+
+
+def run_mse(warmup, iters=10, skip_cpu=False):
+    """MSE training on the 65 536 x 512 FP32 multi-label workload (32 labels,
+    ranks 2..8, K = 2 % of the entries): `iters` iterations timed on the
+    stream with HIP events; the FP64 oracle's first iteration on the host."""
+    import numpy as np
+    import torch
+    from paper_1309_0302_amd import workloads
+    from paper_1309_0302_amd.binding import GoDecMSE
+    w = workloads.mse2()
+    X = torch.from_numpy(w.X).cuda()
+    stream = torch.cuda.current_stream()
+    ms = []
+    for it in range(warmup + 3):
+        gm = GoDecMSE(X, w.labels, w.ranks, w.K, seed=w.seed)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        gm.step(iters)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            ms.append(e0.elapsed_time(e1))
+        info = gm.info()
+        gm.close()
+    t = float(np.median(ms)) / iters
+    nb = mse_bytes(w)
+    out = {"workload": w.name, "n": int(w.X.shape[0]), "p": int(w.X.shape[1]),
+           "labels": len(w.labels), "label_rows": int(sum(len(r) for r in w.labels)),
+           "K": w.K, "iterations": iters, "ms_per_iteration": round(t, 4),
+           "iter_per_s": round(1e3 / t, 2), "algorithmic_bytes_per_iteration": nb,
+           "achieved_GBps": round(nb / (t * 1e-3) / 1e9, 1),
+           "frac_of_hbm_peak": round(nb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "rel_err_sq": info["rel_err_sq"]}
+    if not skip_cpu:
+        from oracle import mse_ref as M
+        bl = blas_info()
+        tr = M.mse_train(w.X.astype(np.float64), w.labels, w.ranks, w.K, w.seed, 1)
+        out["cpu_baseline"] = {"value": round(1.0 / tr.seconds[0], 4), "unit": "iter/s",
+                               "cores": bl["threads"] or os.cpu_count(), "kind": "oracle",
+                               "sample": f"one FP64 oracle iteration of the full workload "
+                                         f"({tr.seconds[0]:.1f} s)"}
+    return out
+
+
 def run_copy(nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of a known size: the reference against
     which the HBM byte counters of the other kernels are scaled."""
@@ -581,8 +637,9 @@ def main():
     ap.add_argument("--skip-completion", action="store_true")
     ap.add_argument("--skip-projection", action="store_true")
     ap.add_argument("--skip-warm", action="store_true")
+    ap.add_argument("--skip-mse", action="store_true")
     ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo", "completion",
-                                       "small"],
+                                       "small", "mse"],
                     help="run one secondary leg alone (for profiling) and print its JSON")
     ap.add_argument("--size", type=int, default=10000,
                     help="square size (default: the 10000 x 10000 workload)")
@@ -606,6 +663,9 @@ def main():
         return
     if args.only == "copy":
         print(json.dumps(run_copy()), flush=True)
+        return
+    if args.only == "mse":
+        print(json.dumps(run_mse(min(args.warmup, 2), skip_cpu=args.skip_cpu)), flush=True)
         return
     if args.only == "small":
         print(json.dumps(small_legs(args.skip_cpu)), flush=True)
@@ -700,6 +760,10 @@ def main():
         log("[bench] matrix completion: 10000 x 10000, 10 % unobserved")
         out["completion"] = run_completion(X, w, 10, 2)
         log(f"[bench] completion {out['completion']['iter_per_s']} iter/s")
+    if not args.skip_mse:
+        log("[bench] MSE training: 65536 x 512, 32 labels")
+        out["mse"] = run_mse(min(args.warmup, 2), skip_cpu=args.skip_cpu)
+        log(f"[bench] mse {out['mse']['ms_per_iteration']} ms/iteration")
     if not args.skip_grebsmo:
         log("[bench] GreBsmo: 25344 x 500 video-shaped, r = 4")
         out["grebsmo"] = run_grebsmo(min(args.warmup, 2))

@@ -451,6 +451,78 @@ godec_status godec_grebsmo_get_info(godec_grebsmo* g, godec_grebsmo_info* info);
 /* Release the handle (the workspace stays the caller's). */
 godec_status godec_grebsmo_destroy(godec_grebsmo* g);
 
+/* ---------------------------------------------------------------------------
+ * MSE training (Sec. 4.2.1, Algorithm 4): the randomized decomposition of a
+ * multi-label training matrix X (n samples x p features) as
+ *   X = sum_i L^i + S,  rank(L^i_{Omega_i}) <= r_i,  L^i zero outside the
+ *   rows Omega_i of the samples carrying label i,  card(S) <= K.
+ * One iteration updates every label in index order (each sees the others'
+ * latest values): N = rows Omega_i of X - sum_{j != i} L^j - S, A1 a fresh
+ * p x r_i standard Gaussian, Y2 = N^T (N A1), L^i_{Omega_i} = N Q Q^T with
+ * Q = orth(Y2) (= Y1 (A2^T Y1)^{-1} Y2^T with A2 = Y1); then
+ * S = P_Phi(X - sum_j L^j) on the K entries of largest magnitude (signed
+ * residual values; nonzero entries only; ties by row-major index i*p + j).
+ * Initialisation: L^i_{Omega_i} = rows Omega_i of D^{-1} X (D = number of
+ * labels of each sample, rows without a label are left to S and the
+ * residual), S = 0.  A1 of iteration t (from 0) and label i is
+ * godec_draw_a1(seed + t*k + i, p, r_i).  A dependent direction of Y2
+ * (|Omega_i| < r_i or a rank-deficient N) gives a zero column of Q.
+ * Conventions as for godec_init (caller workspace, X borrowed, stream).
+ * Limits: r_i <= 8; p <= 512 (FP32) or 256 (FP64); labels may be empty.
+ * ------------------------------------------------------------------------- */
+typedef struct godec_mse godec_mse;
+
+typedef struct {
+  int64_t iters;          /* iterations completed */
+  int64_t nnz;            /* nonzeros of S */
+  double rel_err_sq;      /* ||X - sum L - S||_F^2 / ||X||_F^2 (Sec. 5) */
+  double threshold;       /* |value| of the K-th kept entry of S */
+  double sum_r2;          /* ||X - sum L||_F^2 before the last sparse step */
+  double norm_x2;         /* ||X||_F^2 */
+} godec_mse_info;
+
+/* Workspace bytes.  label_ptr_host: k + 1 offsets into the concatenated row
+ * lists (label i's rows are label_rows[label_ptr[i] .. label_ptr[i+1]));
+ * ranks_host: r_i.  Errors: GODEC_E_INVAL for bad sizes or ranks,
+ * GODEC_E_UNSUPPORTED beyond the limits above. */
+godec_status godec_mse_workspace_size(int64_t n, int64_t p, int32_t k,
+                                      const int32_t* ranks_host,
+                                      const int64_t* label_ptr_host, int64_t K,
+                                      godec_dtype dtype, size_t* bytes);
+
+/* Set up training on X_dev (n x p, leading dimension ldx >= p).
+ * label_rows_host: the concatenated row lists, each strictly ascending
+ * within [0, n) (checked: GODEC_E_INVAL).  Computes the initial residual
+ * and ||X||_F^2 on `stream` (a hipStream_t, NULL = default); checks X for
+ * NaN/Inf (GODEC_E_NUMERIC, synchronises once). */
+godec_status godec_mse_init(godec_mse** out, const void* X_dev, godec_dtype dtype,
+                            int64_t n, int64_t p, int64_t ldx, int32_t k,
+                            const int32_t* ranks_host, const int64_t* label_ptr_host,
+                            const int64_t* label_rows_host, int64_t K, uint64_t seed,
+                            void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Run `iters` iterations (asynchronous; A1 draws are staged through a
+ * pinned host buffer of the handle). */
+godec_status godec_mse_step(godec_mse* m, int32_t iters);
+
+/* Label i's factors: L^i_{Omega_i} = U V^T with U_dev (n_i x r_i, rows in the
+ * order of the label's row list) and V_dev (p x r_i, orthonormal columns,
+ * zero past the numerical rank; V^T is C^i of Algorithm 4's output).
+ * GODEC_E_STATE before the first iteration.  Asynchronous. */
+godec_status godec_mse_get_factors(godec_mse* m, int32_t i, void* U_dev, void* V_dev);
+
+/* S as ascending linear indices i*p + j (int64, capacity K) and values
+ * (dtype of X); *nnz receives the count.  Synchronises the stream. */
+godec_status godec_mse_get_S(godec_mse* m, int64_t* idx_dev, void* val_dev, int64_t* nnz);
+
+/* The residual E = X - sum_j L^j - S into E_dev (n x ldo, ldo >= p). */
+godec_status godec_mse_get_residual(godec_mse* m, void* E_dev, int64_t ldo);
+
+godec_status godec_mse_get_info(godec_mse* m, godec_mse_info* info);
+
+/* Release the handle and its pinned staging buffer. */
+godec_status godec_mse_destroy(godec_mse* m);
+
 /* Build information string (static storage). */
 const char* godec_version(void);
 

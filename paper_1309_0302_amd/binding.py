@@ -62,6 +62,15 @@ class godec_grebsmo_info(ctypes.Structure):
                 ("rel_err_sq", ctypes.c_double), ("l1", ctypes.c_double)]
 
 
+class godec_mse_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rel_err_sq", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("sum_r2", ctypes.c_double), ("norm_x2", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class GodecError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -140,6 +149,17 @@ _SIG = {
     "godec_grebsmo_get_S": (_I32, [_P, _P, _I64]),
     "godec_grebsmo_get_info": (_I32, [_P, ctypes.POINTER(godec_grebsmo_info)]),
     "godec_grebsmo_destroy": (_I32, [_P]),
+    "godec_mse_workspace_size": (_I32, [_I64, _I64, _I32, _P, _P, _I64, _I32,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "godec_mse_init": (_I32, [ctypes.POINTER(ctypes.c_void_p), _P, _I32, _I64, _I64, _I64,
+                              _I32, _P, _P, _P, _I64, ctypes.c_uint64, _P, ctypes.c_size_t,
+                              _P]),
+    "godec_mse_step": (_I32, [_P, _I32]),
+    "godec_mse_get_factors": (_I32, [_P, _I32, _P, _P]),
+    "godec_mse_get_S": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
+    "godec_mse_get_residual": (_I32, [_P, _P, _I64]),
+    "godec_mse_get_info": (_I32, [_P, ctypes.POINTER(godec_mse_info)]),
+    "godec_mse_destroy": (_I32, [_P]),
 }
 
 
@@ -822,6 +842,103 @@ class GreBsmo:
         if getattr(self, "h", None) is not None:
             godec_grebsmo_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- MSE training (Sec. 4.2.1, Algorithm 4) ---------------------------------
+
+def _label_arrays(labels, ranks):
+    k = len(labels)
+    lptr = np.zeros(k + 1, dtype=np.int64)
+    lptr[1:] = np.cumsum([len(r) for r in labels])
+    rows = (np.concatenate([np.asarray(r, dtype=np.int64) for r in labels])
+            if lptr[-1] > 0 else np.zeros(1, np.int64))
+    rk = np.ascontiguousarray(ranks, dtype=np.int32)
+    return lptr, np.ascontiguousarray(rows), rk
+
+
+def godec_mse_workspace_size(n, p, labels, ranks, K, dtype):
+    lptr, _, rk = _label_arrays(labels, ranks)
+    out = ctypes.c_size_t(0)
+    _check(load().godec_mse_workspace_size(n, p, len(labels), rk.ctypes.data,
+                                           lptr.ctypes.data, K, dtype, ctypes.byref(out)))
+    return out.value
+
+
+class GoDecMSE:
+    """MSE training of a device matrix X (n samples x p features) with label
+    row sets `labels` (list of ascending integer arrays), ranks r_i and the
+    cardinality K of S."""
+
+    def __init__(self, X, labels, ranks, K, seed=0, stream=None):
+        import torch
+        if not X.is_cuda or X.stride(1) != 1:
+            raise ValueError("X must be a row-major device tensor")
+        self.X = X
+        self.n, self.p = X.shape
+        self.k = len(labels)
+        self.labels = [np.asarray(r, dtype=np.int64) for r in labels]
+        self.ranks = [int(r) for r in ranks]
+        self.K, self.seed = K, seed
+        self.dtype = _dtype_code(X)
+        if stream is None:
+            stream = torch.cuda.current_stream(X.device).cuda_stream
+        self.stream = stream
+        lptr, rows, rk = _label_arrays(self.labels, self.ranks)
+        self.ws_bytes = godec_mse_workspace_size(self.n, self.p, self.labels, self.ranks, K,
+                                                 self.dtype)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=X.device)
+        base = (self.ws.data_ptr() + 255) // 256 * 256
+        ctx = ctypes.c_void_p()
+        _check(load().godec_mse_init(ctypes.byref(ctx), X.data_ptr(), self.dtype, self.n,
+                                     self.p, X.stride(0), self.k, rk.ctypes.data,
+                                     lptr.ctypes.data, rows.ctypes.data, K, seed, base,
+                                     self.ws_bytes, stream))
+        self.ctx = ctx
+
+    def step(self, iters=1):
+        _check(load().godec_mse_step(self.ctx, iters))
+
+    def factors(self, i):
+        """(U, V): L^i on the label's rows is U V^T (U n_i x r_i, V p x r_i)."""
+        import torch
+        U = torch.empty((len(self.labels[i]), self.ranks[i]), dtype=self.X.dtype,
+                        device=self.X.device)
+        V = torch.empty((self.p, self.ranks[i]), dtype=self.X.dtype, device=self.X.device)
+        _check(load().godec_mse_get_factors(self.ctx, i, U.data_ptr() if U.numel() else
+                                            V.data_ptr(), V.data_ptr()))
+        return U, V
+
+    def S(self):
+        import torch
+        kk = max(self.K, 1)
+        idx = torch.empty(kk, dtype=torch.int64, device=self.X.device)
+        val = torch.empty(kk, dtype=self.X.dtype, device=self.X.device)
+        nnz = _I64(0)
+        _check(load().godec_mse_get_S(self.ctx, idx.data_ptr(), val.data_ptr(),
+                                      ctypes.byref(nnz)))
+        return idx[:nnz.value], val[:nnz.value]
+
+    def residual(self):
+        import torch
+        E = torch.empty((self.n, self.p), dtype=self.X.dtype, device=self.X.device)
+        _check(load().godec_mse_get_residual(self.ctx, E.data_ptr(), self.p))
+        return E
+
+    def info(self):
+        info = godec_mse_info()
+        _check(load().godec_mse_get_info(self.ctx, ctypes.byref(info)))
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            load().godec_mse_destroy(self.ctx)
+            self.ctx = None
 
     def __del__(self):
         try:

@@ -463,4 +463,37 @@ void gb_reduce_zt(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd,
 void gb_put_cols(const Launch& L, bool f64, int rp, const void* P, int64_t rows, int c0,
                  int cnt, void* Vt);
 
+
+// ---------------------------------------------------------------------------
+// MSE training (Sec. 4.2.1, Algorithm 4): one label update and helpers.
+// ---------------------------------------------------------------------------
+struct MseLabelArgs {
+  void* E;                  // n x lde working residual X - sum L - S
+  int64_t lde;
+  const void* X;            // n x ldx
+  int64_t ldx;
+  const void* cnt;          // n: labels per sample (type of X)
+  const int64_t* rows;      // the label's rows (ascending)
+  int64_t nrows;
+  int64_t p;
+  int S;                    // columns per lane: p <= 64 S, S in {1, 2, 4, 8}
+  int first;                // the label still holds its initial value
+  int r;                    // the label's rank bound (<= 8)
+  int nblk;                 // blocks of the two row passes
+  void* U;                  // nrows x 8 (read, then overwritten)
+  const void* Vold;         // 64 S x 8 current basis
+  void* Vnew;               // 64 S x 8 new basis (output)
+  const void* A1;           // 64 S x 8 random matrix of this update
+  void* part;               // nblk x 64 S x 8 partials
+};
+void launch_mse_label(const Launch& L, bool f64, const MseLabelArgs& a);
+void launch_mse_init_e(const Launch& L, bool f64, void* E, int64_t lde, const void* X,
+                       int64_t ldx, const void* cnt, int64_t n, int64_t p);
+void launch_mse_add_s(const Launch& L, bool f64, void* E, int64_t lde, int64_t p,
+                      const int64_t* idx, const void* val, const SelPlan* plan, int64_t kmax);
+void launch_mse_copy_factors(const Launch& L, bool f64, const void* U, const void* V,
+                             int64_t ni, int64_t p, int r, void* Uo, void* Vo);
+void launch_mse_copy_e(const Launch& L, bool f64, const void* E, int64_t lde, int64_t n,
+                       int64_t p, void* out, int64_t ldo);
+
 }  // namespace godec

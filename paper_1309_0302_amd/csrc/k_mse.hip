@@ -1,0 +1,401 @@
+// MSE training (Sec. 4.2.1, Algorithm 4): kernels of one label update and
+// of the sparse step's bookkeeping.
+//
+// The state is E = X - sum_j L^j - S (n x p, row-major, leading dimension
+// lde, a multiple of 64) and, per label i, L^i_{Omega_i} = U_i V_i^T with U_i
+// (n_i x 8, rows in the order of Omega_i) and V_i (p x 8, orthonormal
+// columns, zero past the label's rank).  Label i's residual is
+// N = E_{Omega_i} + L^i_{Omega_i}: the rows Omega_i of X minus the other
+// labels and S.  Before a label's first update L^i is the initial
+// Z_{Omega_i} = (D^{-1} X)_{Omega_i} (D = number of labels of each sample),
+// taken from X directly.
+//
+// The label update (q = 0 bilateral random projection with A2 = Y1) is
+//   km_gram   Y2 partials: per block, sum over its rows of N_row^T (N_row A1)
+//   km_orth   Y2 = the partials added in block order (FP64), then two
+//             Cholesky QR rounds with an FP64 Gram: Q = orth(Y2)
+//   km_update U_row = N_row Q, E_row = N_row - U_row Q^T
+// so that L^i_{Omega_i} = N Q Q^T = Y1 (A2^T Y1)^{-1} Y2^T.
+//
+// A wavefront owns one row at a time: lane l holds columns l + 64 s,
+// s < S (p <= 64 S); dot products over the row are wavefront sums.
+#include "godec_internal.h"
+#include "k_common.h"
+
+namespace godec {
+
+constexpr int kMseRP = 8;          // padded rank of every label
+constexpr int kMseWaves = 4;       // wavefronts per block of the row passes
+
+// N_row of label i: E_row + L^i_row, where L^i_row is U_j V^T (updated
+// label) or X_row / cnt_row (initial value of the label).
+template <typename T, int S>
+__device__ __forceinline__ void mse_load_n(const T* __restrict__ E, int64_t lde,
+                                           const T* __restrict__ X, int64_t ldx,
+                                           const T* __restrict__ cnt, int64_t g, int64_t p,
+                                           int first, const T* __restrict__ Urow,
+                                           const T (&v)[S][kMseRP], int lane, T (&nrow)[S]) {
+  T u[kMseRP];
+  if (!first) {
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) u[t] = Urow[t];
+  }
+  const T c = first ? cnt[g] : T(0);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int64_t col = lane + 64 * s;
+    const bool ok = col < p;
+    const T e = ok ? E[g * lde + col] : T(0);
+    T l = T(0);
+    if (first) {
+      l = (ok && c > T(0)) ? X[g * ldx + col] / c : T(0);
+    } else {
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) l = fma_t(u[t], v[s][t], l);
+    }
+    nrow[s] = e + l;
+  }
+}
+
+// Partial sums of Y2 = N^T (N A1) over the block's rows (rows j = wave
+// index + 4 blk, stepping by 4 gridDim.x); written to part[blockIdx.x] as
+// p_pad x 8.  Each wavefront accumulates its rows in order, then the block
+// adds its four wavefronts in order.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t lde,
+                                               const T* __restrict__ X, int64_t ldx,
+                                               const T* __restrict__ cnt,
+                                               const int64_t* __restrict__ rows, int64_t nrows,
+                                               int64_t p, int first, const T* __restrict__ U,
+                                               const T* __restrict__ V,
+                                               const T* __restrict__ A1,
+                                               T* __restrict__ part) {
+  constexpr int PP = 64 * S;
+  __shared__ T red[kMseWaves][PP * kMseRP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T a[S][kMseRP], v[S][kMseRP], acc[S][kMseRP];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) {
+      const int col = lane + 64 * s;
+      a[s][t] = A1[col * kMseRP + t];
+      v[s][t] = first ? T(0) : V[col * kMseRP + t];
+      acc[s][t] = T(0);
+    }
+  for (int64_t j = (int64_t)blockIdx.x * kMseWaves + wave; j < nrows;
+       j += (int64_t)gridDim.x * kMseWaves) {
+    T nrow[S];
+    mse_load_n<T, S>(E, lde, X, ldx, cnt, rows[j], p, first, U + j * kMseRP, v, lane, nrow);
+    T w[kMseRP];
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) {
+      T d = T(0);
+#pragma unroll
+      for (int s = 0; s < S; ++s) d = fma_t(nrow[s], a[s][t], d);
+      w[t] = wave_sum(d);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) acc[s][t] = fma_t(nrow[s], w[t], acc[s][t]);
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) red[wave][(lane + 64 * s) * kMseRP + t] = acc[s][t];
+  __syncthreads();
+  T* out = part + (int64_t)blockIdx.x * PP * kMseRP;
+  for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
+    T sum = red[0][e];
+#pragma unroll
+    for (int w = 1; w < kMseWaves; ++w) sum += red[w][e];
+    out[e] = sum;
+  }
+}
+
+// One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS): Gram in a
+// fixed order, Cholesky with the dependent-column rule (a pivot at most
+// tau * G_jj marks column j dependent: zero row of R, zero column of the
+// result), Y <- Y R^{-1}.  `act` holds the columns still in use.
+template <int PP>
+__device__ void mse_chol_round(double* Y, int r, double tau, int* act, double* gsh,
+                               double* red) {
+  const int tid = threadIdx.x;
+  // Gram G[a][b], a <= b: thread-local sums over rows tid, tid + 256, ...
+  for (int ab = 0; ab < kMseRP * kMseRP; ++ab) {
+    const int a_ = ab / kMseRP, b_ = ab % kMseRP;
+    double g = 0.0;
+    if (a_ <= b_ && a_ < r && b_ < r)
+      for (int c = tid; c < PP; c += 256) g = fma(Y[c * kMseRP + a_], Y[c * kMseRP + b_], g);
+    g = wave_sum(g);
+    if ((tid & 63) == 0) red[(tid >> 6) * kMseRP * kMseRP + ab] = g;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double G[kMseRP][kMseRP], R[kMseRP][kMseRP];
+    for (int a_ = 0; a_ < kMseRP; ++a_)
+      for (int b_ = 0; b_ < kMseRP; ++b_) {
+        const int lo = a_ < b_ ? a_ : b_, hi = a_ < b_ ? b_ : a_;
+        const int ab = lo * kMseRP + hi;
+        G[a_][b_] = red[ab] + red[kMseRP * kMseRP + ab] + red[2 * kMseRP * kMseRP + ab] +
+                    red[3 * kMseRP * kMseRP + ab];
+        R[a_][b_] = 0.0;
+      }
+    for (int j = 0; j < kMseRP; ++j) {
+      if (j >= r || !act[j]) { act[j] = 0; continue; }
+      double d = G[j][j];
+      for (int l = 0; l < j; ++l) d -= R[l][j] * R[l][j];
+      if (!(d > tau * G[j][j]) || !(G[j][j] > 0.0)) { act[j] = 0; continue; }
+      const double rjj = sqrt(d);
+      R[j][j] = rjj;
+      for (int b_ = j + 1; b_ < kMseRP; ++b_) {
+        double s = G[j][b_];
+        for (int l = 0; l < j; ++l) s -= R[l][j] * R[l][b_];
+        R[j][b_] = s / rjj;
+      }
+    }
+    for (int a_ = 0; a_ < kMseRP; ++a_)
+      for (int b_ = 0; b_ < kMseRP; ++b_) gsh[a_ * kMseRP + b_] = R[a_][b_];
+  }
+  __syncthreads();
+  // Y <- Y R^{-1} on the active columns (forward substitution per row)
+  for (int c = tid; c < PP; c += 256) {
+    double y[kMseRP], q[kMseRP];
+    for (int t = 0; t < kMseRP; ++t) y[t] = Y[c * kMseRP + t];
+    for (int j = 0; j < kMseRP; ++j) {
+      if (!act[j]) { q[j] = 0.0; continue; }
+      double s = y[j];
+      for (int l = 0; l < j; ++l)
+        if (act[l]) s -= q[l] * gsh[l * kMseRP + j];
+      q[j] = s / gsh[j * kMseRP + j];
+    }
+    for (int t = 0; t < kMseRP; ++t) Y[c * kMseRP + t] = q[t];
+  }
+  __syncthreads();
+}
+
+// Q = orth(Y2) with Y2 the block partials added in block order; one block.
+template <typename T, int PP>
+__global__ __launch_bounds__(256) void km_orth(const T* __restrict__ part, int nblk, int r,
+                                               T* __restrict__ Q) {
+  __shared__ double Y[PP * kMseRP];
+  __shared__ double red[4 * kMseRP * kMseRP];
+  __shared__ double gsh[kMseRP * kMseRP];
+  __shared__ int act[kMseRP];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < PP * kMseRP; e += 256) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += (double)part[(int64_t)b * PP * kMseRP + e];
+    Y[e] = s;
+  }
+  if (tid < kMseRP) act[tid] = tid < r ? 1 : 0;
+  __syncthreads();
+  const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+  const double tau = (double)r * fmax(u * u, 0x1p-53);
+  mse_chol_round<PP>(Y, r, tau, act, gsh, red);
+  mse_chol_round<PP>(Y, r, tau, act, gsh, red);
+  for (int e = tid; e < PP * kMseRP; e += 256) Q[e] = (T)Y[e];
+}
+
+// U_row = N_row Q and E_row = N_row - U_row Q^T for every row of the label.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
+                                                 const T* __restrict__ X, int64_t ldx,
+                                                 const T* __restrict__ cnt,
+                                                 const int64_t* __restrict__ rows,
+                                                 int64_t nrows, int64_t p, int first,
+                                                 T* __restrict__ U, const T* __restrict__ V,
+                                                 const T* __restrict__ Q) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T v[S][kMseRP], qq[S][kMseRP];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) {
+      const int col = lane + 64 * s;
+      v[s][t] = first ? T(0) : V[col * kMseRP + t];
+      qq[s][t] = Q[col * kMseRP + t];
+    }
+  for (int64_t j = (int64_t)blockIdx.x * kMseWaves + wave; j < nrows;
+       j += (int64_t)gridDim.x * kMseWaves) {
+    const int64_t g = rows[j];
+    T nrow[S];
+    mse_load_n<T, S>(E, lde, X, ldx, cnt, g, p, first, U + j * kMseRP, v, lane, nrow);
+    T w[kMseRP];
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) {
+      T d = T(0);
+#pragma unroll
+      for (int s = 0; s < S; ++s) d = fma_t(nrow[s], qq[s][t], d);
+      w[t] = wave_sum(d);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int64_t col = lane + 64 * s;
+      T l = T(0);
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) l = fma_t(w[t], qq[s][t], l);
+      if (col < p) E[g * lde + col] = nrow[s] - l;
+    }
+    // every lane holds w; lanes 0..7 store the row of U (after the loads above)
+    T wl = w[0];
+#pragma unroll
+    for (int t = 1; t < kMseRP; ++t) wl = (lane == t) ? w[t] : wl;
+    if (lane < kMseRP) U[j * kMseRP + lane] = wl;
+  }
+}
+
+// E = X - sum_i Z_{Omega_i} with Z = D^{-1} X: each labelled row gets cnt
+// copies of X_row / cnt subtracted, added up in label order.
+template <typename T>
+__global__ __launch_bounds__(256) void km_init_e(T* __restrict__ E, int64_t lde,
+                                                 const T* __restrict__ X, int64_t ldx,
+                                                 const T* __restrict__ cnt, int64_t n,
+                                                 int64_t p) {
+  const int64_t total = n * lde;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t g = e / lde, col = e % lde;
+    T out = T(0);
+    if (col < p) {
+      const T x = X[g * ldx + col];
+      const T c = cnt[g];
+      T acc = T(0);
+      if (c > T(0)) {
+        const T z = x / c;
+        for (int u = 0; u < (int)c; ++u) acc += z;
+      }
+      out = x - acc;
+    }
+    E[e] = out;
+  }
+}
+
+// E[idx] += val for the entries of the previous S (R = E + S before the
+// sparse step).
+template <typename T>
+__global__ __launch_bounds__(256) void km_add_s(T* __restrict__ E, int64_t lde, int64_t p,
+                                                const int64_t* __restrict__ idx,
+                                                const T* __restrict__ val,
+                                                const SelPlan* __restrict__ plan) {
+  const long long cnt = plan->nnz;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
+       e += (long long)gridDim.x * 256) {
+    const int64_t id = idx[e];
+    const int64_t i = id / p, j = id % p;
+    E[i * lde + j] += val[e];
+  }
+}
+
+// Copy of one label's factors without the padding: U (n_i x r), V (p x r).
+template <typename T>
+__global__ __launch_bounds__(256) void km_copy_factors(const T* __restrict__ U,
+                                                       const T* __restrict__ V, int64_t ni,
+                                                       int64_t p, int r, T* __restrict__ Uo,
+                                                       T* __restrict__ Vo) {
+  const int64_t nu = ni * r, nv = p * r;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nu + nv;
+       e += (int64_t)gridDim.x * 256) {
+    if (e < nu)
+      Uo[e] = U[(e / r) * kMseRP + e % r];
+    else
+      Vo[e - nu] = V[((e - nu) / r) * kMseRP + (e - nu) % r];
+  }
+}
+
+// E (lde) -> out (ldo), the first p columns.
+template <typename T>
+__global__ __launch_bounds__(256) void km_copy_e(const T* __restrict__ E, int64_t lde,
+                                                 int64_t n, int64_t p, T* __restrict__ out,
+                                                 int64_t ldo) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * p;
+       e += (int64_t)gridDim.x * 256)
+    out[(e / p) * ldo + e % p] = E[(e / p) * lde + e % p];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+#define GODEC_MSE_S_SWITCH(S_, ...)                  \
+  switch (S_) {                                      \
+    case 1: { constexpr int S = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int S = 2; __VA_ARGS__; } break; \
+    case 4: { constexpr int S = 4; __VA_ARGS__; } break; \
+    case 8: { constexpr int S = 8; __VA_ARGS__; } break; \
+    default: break;                                  \
+  }
+
+template <typename T>
+static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
+  GODEC_MSE_S_SWITCH(a.S, {
+    // FP64 rows are limited to 256 columns (S <= 4): three 8-wide FP64
+    // panels of 8 columns per lane fill the register file
+    if constexpr (!(sizeof(T) == 8 && S == 8)) {
+      hipLaunchKernelGGL((km_gram<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
+                         (const T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt, a.rows,
+                         a.nrows, a.p, a.first, (const T*)a.U, (const T*)a.Vold,
+                         (const T*)a.A1, (T*)a.part);
+      hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(256), 0, L.stream,
+                         (const T*)a.part, a.nblk, a.r, (T*)a.Vnew);
+      hipLaunchKernelGGL((km_update<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
+                         (T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt, a.rows,
+                         a.nrows, a.p, a.first, (T*)a.U, (const T*)a.Vold, (const T*)a.Vnew);
+    }
+  });
+}
+
+void launch_mse_label(const Launch& L, bool f64, const MseLabelArgs& a) {
+  if (f64) mse_label_t<double>(L, a);
+  else mse_label_t<float>(L, a);
+}
+
+void launch_mse_init_e(const Launch& L, bool f64, void* E, int64_t lde, const void* X,
+                       int64_t ldx, const void* cnt, int64_t n, int64_t p) {
+  int64_t g = (n * lde + 255) / 256;
+  g = g > (int64_t)L.num_cu * 16 ? (int64_t)L.num_cu * 16 : (g < 1 ? 1 : g);
+  if (f64)
+    hipLaunchKernelGGL(km_init_e<double>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (double*)E, lde, (const double*)X, ldx, (const double*)cnt, n, p);
+  else
+    hipLaunchKernelGGL(km_init_e<float>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (float*)E, lde, (const float*)X, ldx, (const float*)cnt, n, p);
+}
+
+void launch_mse_add_s(const Launch& L, bool f64, void* E, int64_t lde, int64_t p,
+                      const int64_t* idx, const void* val, const SelPlan* plan, int64_t kmax) {
+  int64_t g = (kmax + 255) / 256;
+  g = g > (int64_t)L.num_cu * 4 ? (int64_t)L.num_cu * 4 : (g < 1 ? 1 : g);
+  if (f64)
+    hipLaunchKernelGGL(km_add_s<double>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (double*)E, lde, p, idx, (const double*)val, plan);
+  else
+    hipLaunchKernelGGL(km_add_s<float>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (float*)E, lde, p, idx, (const float*)val, plan);
+}
+
+void launch_mse_copy_factors(const Launch& L, bool f64, const void* U, const void* V,
+                             int64_t ni, int64_t p, int r, void* Uo, void* Vo) {
+  int64_t g = ((ni + p) * r + 255) / 256;
+  g = g > (int64_t)L.num_cu * 4 ? (int64_t)L.num_cu * 4 : (g < 1 ? 1 : g);
+  if (f64)
+    hipLaunchKernelGGL(km_copy_factors<double>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (const double*)U, (const double*)V, ni, p, r, (double*)Uo, (double*)Vo);
+  else
+    hipLaunchKernelGGL(km_copy_factors<float>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (const float*)U, (const float*)V, ni, p, r, (float*)Uo, (float*)Vo);
+}
+
+void launch_mse_copy_e(const Launch& L, bool f64, const void* E, int64_t lde, int64_t n,
+                       int64_t p, void* out, int64_t ldo) {
+  int64_t g = (n * p + 255) / 256;
+  g = g > (int64_t)L.num_cu * 16 ? (int64_t)L.num_cu * 16 : (g < 1 ? 1 : g);
+  if (f64)
+    hipLaunchKernelGGL(km_copy_e<double>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (const double*)E, lde, n, p, (double*)out, ldo);
+  else
+    hipLaunchKernelGGL(km_copy_e<float>, dim3((unsigned)g), dim3(256), 0, L.stream,
+                       (const float*)E, lde, n, p, (float*)out, ldo);
+}
+
+}  // namespace godec

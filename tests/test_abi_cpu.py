@@ -181,3 +181,34 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+# ---- MSE training: host-side argument checks (no device work) ---------------
+
+def _mse_status(n, p, labels, ranks, K, dtype=b.GODEC_F32):
+    import ctypes as C
+    lptr, rows, rk = b._label_arrays(labels, ranks)
+    ctx = C.c_void_p()
+    # fake, aligned, non-null pointers: every check below fails before any
+    # device access
+    return b.load().godec_mse_init(C.byref(ctx), 256, dtype, n, p, p, len(labels),
+                                   rk.ctypes.data, lptr.ctypes.data, rows.ctypes.data, K, 1,
+                                   256, 1 << 40, None)
+
+
+def test_mse_rejects_bad_arguments():
+    ok = [np.arange(0, 10, 2), np.arange(5)]
+    assert b.STATUS[_mse_status(20, 16, [np.array([3, 1])], [2], 5)] == "GODEC_E_INVAL"
+    assert b.STATUS[_mse_status(20, 16, [np.array([1, 1])], [2], 5)] == "GODEC_E_INVAL"
+    assert b.STATUS[_mse_status(20, 16, [np.array([25])], [2], 5)] == "GODEC_E_INVAL"
+    assert b.STATUS[_mse_status(20, 16, ok, [2, 9], 5)] == "GODEC_E_UNSUPPORTED"
+    assert b.STATUS[_mse_status(20, 16, ok, [2, 0], 5)] == "GODEC_E_INVAL"
+    assert b.STATUS[_mse_status(20, 600, ok, [2, 2], 5)] == "GODEC_E_UNSUPPORTED"
+    assert b.STATUS[_mse_status(20, 300, ok, [2, 2], 5, b.GODEC_F64)] == "GODEC_E_UNSUPPORTED"
+    assert b.STATUS[_mse_status(20, 16, ok, [2, 2], 20 * 16 + 1)] == "GODEC_E_INVAL"
+
+
+def test_mse_workspace_size_grows_with_rows():
+    a = b.godec_mse_workspace_size(1000, 100, [np.arange(10)], [2], 50, b.GODEC_F32)
+    c = b.godec_mse_workspace_size(1000, 100, [np.arange(900)], [2], 50, b.GODEC_F32)
+    assert c > a > 1000 * 100 * 4
