@@ -21,6 +21,7 @@
 
 #include "../../include/godec.h"
 #include "godec_internal.h"
+#include "k_mmb.h"
 #include "host_common.h"
 
 using namespace godec;
@@ -147,7 +148,7 @@ size_t carve(godec_ctx* c, void* base) {
     c->Zt = cv.take((size_t)32 * ldd * 4);
     c->Wt = cv.take((size_t)32 * mpad * 4);
     c->Wtpart = (float*)cv.take((size_t)c->nct_a * 32 * mpad * 4);
-    c->Zpart32 = (float*)cv.take((size_t)c->nch_b * ldd * 32 * 4);
+    c->Zpart32 = (float*)cv.take((size_t)c->nch_b * ldd * zpart_stride(c->rp) * 4);
   } else {
     c->Zt = c->Wt = nullptr;
     c->Wtpart = c->Zpart32 = nullptr;
@@ -335,7 +336,8 @@ void gram_pass(godec_ctx* c, DType td, const void* Dsrc, const void* in, bool zt
     mfma_apply(c, td, Dsrc, in, zt_ready, c->Wt, nullptr);
     {
       ProfScope ps(c, b16 ? PC_APPLY_T_BF16 : PC_APPLY_T, true);
-      mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b, ps.a, ps.b);
+      mfma_mm_b(L, b16, Dsrc, c->ldd, c->mpad, c->Wt, c->Zpart32, c->rc_b, c->nch_b, c->rp, ps.a,
+                ps.b);
     }
     if (!defer_sum) mfma_reduce_z(L, c->Zpart32, c->nch_b, c->ldd, c->rp, (float*)out);
     return;

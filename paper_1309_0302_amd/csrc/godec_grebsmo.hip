@@ -128,7 +128,7 @@ void gram_orth(godec_grebsmo* g, const void* src) {
     mfma_to_t(L, false, g->P0, ldd, g->rp, g->Zt);
     mfma_mm_a(L, false, src, ldd, mpad, g->Zt, g->Wtpart, g->pl.kc_a);
     mfma_reduce_w(L, false, g->Wtpart, (int)g->pl.nct_a, mpad, g->m, g->rp, g->Wt, nullptr);
-    mfma_mm_b(L, false, src, ldd, mpad, g->Wt, g->Zpart32, g->pl.rc_b, g->pl.nch_b);
+    mfma_mm_b(L, false, src, ldd, mpad, g->Wt, g->Zpart32, g->pl.rc_b, g->pl.nch_b, g->rp);
     mfma_reduce_z(L, g->Zpart32, g->pl.nch_b, ldd, g->rp, (float*)g->P1);
   }
   launch_gram_tree(L, g->f64, g->rp, g->P1, ldd, g->Gpart, g->gram_ctl, 1, g->st, nullptr, 0, 0);
@@ -185,7 +185,7 @@ void inner_step(godec_grebsmo* g, bool last) {
     launch_apply_t(L, F64, g->rp, g->D, ldd, m, g->U, g->Zpart, g->pl.rpc, g->pl.nchunks);
     launch_reduce_chunks(L, true, g->rp, g->Zpart, g->pl.nchunks, ldd, g->Vt);
   } else {
-    mfma_mm_b(L, false, g->D, ldd, mpad, g->Wt, g->Zpart32, g->pl.rc_b, g->pl.nch_b);
+    mfma_mm_b(L, false, g->D, ldd, mpad, g->Wt, g->Zpart32, g->pl.rc_b, g->pl.nch_b, g->rp);
     if (fuse)   // the fused soft pass below reads V^T transposed
       gb_reduce_zt(L, g->Zpart32, g->pl.nch_b, ldd, g->rp, (float*)g->Vt, (float*)g->Zt);
     else

@@ -221,9 +221,10 @@ void mfma_mm_a(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t m
                hipEvent_t ev_b = nullptr);
 void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int64_t mpad,
                    int64_t m, int rp, void* Wt, float* Wrow);
+// Row-chunk partials Zpart[ch] are ldd x zpart_stride(rp) floats.
 void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
-               const void* Wt, float* Zpart, int64_t RC, int64_t nch, hipEvent_t ev_a = nullptr,
-               hipEvent_t ev_b = nullptr);
+               const void* Wt, float* Zpart, int64_t RC, int64_t nch, int rp,
+               hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr);
 void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,
                    float* Zo);
 // GreBsmo: D <- Xp - S_lambda(Xp - U V) (Xp: X zero padded to mpad x ldd, U

@@ -7,6 +7,7 @@
 
 #include "godec_internal.h"
 #include "k_common.h"
+#include "k_mmb.h"
 
 namespace godec {
 
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256) void kg_put_cols(const TA* __restrict__ P, int
   Vt[i * RP + c0 + c] = P[i * RP + c];
 }
 
-// V^T (ldd x rp) = sum_ch Zpart[ch] (ldd x 32), and its transpose into rows
+// V^T (ldd x rp) = sum_ch Zpart[ch] (ldd x zpart_stride(rp)), and its transpose into rows
 // j < rp of Zt (32 x ldd, the B operand of the next matrix-core pass).  One
 // block per 16 consecutive outputs e = c * rp + j; each of 16 chunk lanes
 // adds every 16th chunk (ascending), then the lane sums are added in lane
@@ -135,8 +136,9 @@ __global__ __launch_bounds__(256) void kg_reduce_zt(const float* __restrict__ Zp
   const bool live = e < ldd * rp;
   float s = 0.f;
   if (live) {
-    const float* p = Zpart + (e / rp) * 32 + (e % rp);
-    const int64_t step = ldd * 32;
+    const int zs = zpart_stride(rp);
+    const float* p = Zpart + (e / rp) * zs + (e % rp);
+    const int64_t step = ldd * zs;
     for (int64_t h = hl; h < nch; h += kZtLanes) s += p[h * step];
   }
   red[hl][v] = s;

@@ -19,27 +19,9 @@
 
 #include "godec_internal.h"
 #include "k_common.h"
+#include "k_mmb.h"
 
 namespace godec {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int acc_row(int v, int lane) {
-  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-}
-
-__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) {
-  return __builtin_bit_cast(bf16x8, v);
-}
-
-__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
 
 // ---------------------------------------------------------------------------
 // k_mm_a: Wtpart[ct] = (D[:, tile ct] Z[tile ct, :])^T.
@@ -268,50 +250,26 @@ __global__ __launch_bounds__(256) void k_soft_mm_a_f32(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// k_mm_b: Zpart[ch] (ldd x 32, row = column of D) = (W^T D[rows of ch, :])^T.
+// k_mm_b: Zpart[ch] (ldd x zs, row = column of D) = (W^T D[rows of ch, :])^T.
 // Block = 4 waves on the same 128-column strip [blockIdx.x*128, +128): lane n
 // holds columns 4n .. 4n+3 of the strip, one per 32-column MFMA tile, so a
 // wave reads each row as one contiguous run.  The waves split the rows of
-// the chunk into four ranges and add their tiles through LDS at the end.
+// the chunk into four ranges and add their tiles through LDS at the end;
+// only the zs = zpart_stride(rp) leading entries of each output row are
+// stored (the rest of the 32-wide tile is padding).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_reduce_store(f32x16 (&acc)[4], float* lds, int wave,
-                                                   int lane, float* __restrict__ Zpart,
-                                                   int64_t row0) {
-  // waves 2,3 -> LDS; waves 0,1 add; wave 1 -> LDS; wave 0 adds and stores
-  float* mine = lds + (int64_t)(wave & 1) * 64 * 64;
-  if (wave >= 2) {
+__device__ __forceinline__ void mmb_store(const f32x16 (&acc)[4], int lane, int zs,
+                                          float* __restrict__ Zpart, int64_t row0) {
+  const int n = lane & 31;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 4; ++t) {
+    float* out = Zpart + (row0 + 4 * n + t) * zs;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) mine[(t * 16 + v) * 64 + lane] = acc[t][v];
-  }
-  __syncthreads();
-  if (wave < 2) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[t][v] += mine[(t * 16 + v) * 64 + lane];
-  }
-  __syncthreads();
-  if (wave == 1) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) lds[(t * 16 + v) * 64 + lane] = acc[t][v];
-  }
-  __syncthreads();
-  if (wave == 0) {
-    const int n = lane & 31;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      float* out = Zpart + (row0 + 4 * n + t) * 32;
-#pragma unroll
-      for (int v = 0; v < 16; v += 4) {
-        const int i0 = acc_row(v, lane);
-        *reinterpret_cast<float4*>(out + i0) = make_float4(
-            acc[t][v] + lds[(t * 16 + v) * 64 + lane], acc[t][v + 1] + lds[(t * 16 + v + 1) * 64 + lane],
-            acc[t][v + 2] + lds[(t * 16 + v + 2) * 64 + lane], acc[t][v + 3] + lds[(t * 16 + v + 3) * 64 + lane]);
-      }
+    for (int v = 0; v < 16; v += 4) {
+      const int i0 = acc_row(v, lane);
+      if (i0 < zs)
+        *reinterpret_cast<float4*>(out + i0) =
+            make_float4(acc[t][v], acc[t][v + 1], acc[t][v + 2], acc[t][v + 3]);
     }
   }
 }
@@ -319,75 +277,38 @@ __device__ __forceinline__ void block_reduce_store(f32x16 (&acc)[4], float* lds,
 __global__ __launch_bounds__(256) void k_mm_b_bf16(const uint16_t* __restrict__ D, int64_t ldd,
                                                    int64_t mpad,
                                                    const uint16_t* __restrict__ Wt,
-                                                   float* __restrict__ Zpart, int64_t RC) {
+                                                   float* __restrict__ Zpart, int64_t RC,
+                                                   int zs) {
   __shared__ float lds[2 * 64 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t cw = (int64_t)blockIdx.x * 128;
   const int64_t kc0 = (int64_t)blockIdx.y * RC;
   const int64_t kc1 = (kc0 + RC) < mpad ? (kc0 + RC) : mpad;
-  const int64_t q = ((kc1 - kc0) / 4 + 15) / 16 * 16;   // rows per wave, multiple of 16
-  const int64_t k0 = kc0 + q * wave;
-  const int64_t k1 = (k0 + q) < kc1 ? (k0 + q) : kc1;
-  const int n = lane & 31, g = lane >> 5;
-  const uint16_t* pd = D + (8 * g) * ldd + cw + 4 * n;
-  const uint16_t* pw = Wt + (int64_t)n * mpad + 8 * g;
+  int64_t k0, k1;
+  mmb_wave_rows(kc0, kc1, wave, 16, k0, k1);
   f32x16 acc[4] = {};
-  for (int64_t kk = k0; kk < k1; kk += 16) {
-    // A: W^T[n][kk + 8g .. +7]
-    const u32x4 a = *reinterpret_cast<const u32x4*>(pw + kk);
-    // B: 8 rows (kk + 8g + s) x 4 columns
-    uint2 d[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) d[s] = *reinterpret_cast<const uint2*>(pd + (kk + s) * ldd);
-    // repack: tile t gets column 4n + t of the 8 rows (bf16 pairs)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      u32x4 b;
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const uint32_t x0 = (t < 2) ? d[2 * h].x : d[2 * h].y;
-        const uint32_t x1 = (t < 2) ? d[2 * h + 1].x : d[2 * h + 1].y;
-        const uint32_t lo = (t & 1) ? (x0 >> 16) : (x0 & 0xffffu);
-        const uint32_t hi = (t & 1) ? (x1 >> 16) : (x1 & 0xffffu);
-        b[h] = lo | (hi << 16);
-      }
-      acc[t] = mfma_bf16(as_bf16x8(a), as_bf16x8(b), acc[t]);
-    }
-  }
-  block_reduce_store(acc, lds, wave, lane, Zpart, (int64_t)blockIdx.y * ldd + cw);
+  mmb_loop_bf16(D, ldd, mpad, Wt, cw, k0, k1, lane, acc);
+  mmb_block_reduce(acc, lds, wave, lane);
+  if (wave == 0) mmb_store(acc, lane, zs, Zpart, (int64_t)blockIdx.y * ldd + cw);
 }
 
 __global__ __launch_bounds__(256) void k_mm_b_f32(const float* __restrict__ D, int64_t ldd,
                                                   int64_t mpad, const float* __restrict__ Wt,
-                                                  float* __restrict__ Zpart, int64_t RC) {
+                                                  float* __restrict__ Zpart, int64_t RC,
+                                                  int zs) {
   __shared__ float lds[2 * 64 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t cw = (int64_t)blockIdx.x * 128;
   const int64_t kc0 = (int64_t)blockIdx.y * RC;
   const int64_t kc1 = (kc0 + RC) < mpad ? (kc0 + RC) : mpad;
-  const int64_t q = ((kc1 - kc0) / 4 + 7) / 8 * 8;      // rows per wave, multiple of 8
-  const int64_t k0 = kc0 + q * wave;
-  const int64_t k1 = (k0 + q) < kc1 ? (k0 + q) : kc1;
-  const int n = lane & 31, g = lane >> 5;
-  const float* pd = D + (4 * g) * ldd + cw + 4 * n;
-  const float* pw = Wt + (int64_t)n * mpad + 4 * g;
+  int64_t k0, k1;
+  mmb_wave_rows(kc0, kc1, wave, 8, k0, k1);
   f32x16 acc[4] = {};
-  for (int64_t kk = k0; kk < k1; kk += 8) {
-    // slot s pairs row kk + 4g + s on both operands
-    const float4 a = *reinterpret_cast<const float4*>(pw + kk);
-    const float av[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float4 d = *reinterpret_cast<const float4*>(pd + (kk + s) * ldd);
-      acc[0] = mfma_f32(av[s], d.x, acc[0]);
-      acc[1] = mfma_f32(av[s], d.y, acc[1]);
-      acc[2] = mfma_f32(av[s], d.z, acc[2]);
-      acc[3] = mfma_f32(av[s], d.w, acc[3]);
-    }
-  }
-  block_reduce_store(acc, lds, wave, lane, Zpart, (int64_t)blockIdx.y * ldd + cw);
+  mmb_loop_f32(D, ldd, mpad, Wt, cw, k0, k1, lane, acc);
+  mmb_block_reduce(acc, lds, wave, lane);
+  if (wave == 0) mmb_store(acc, lane, zs, Zpart, (int64_t)blockIdx.y * ldd + cw);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,8 +366,9 @@ __global__ __launch_bounds__(256) void k_reduce_z(const float* __restrict__ Zpar
   const bool live = e < ldd * rp;
   float s = 0.f;
   if (live) {
-    const float* p = Zpart + (e / rp) * 32 + (e % rp);
-    const int64_t step = ldd * 32;
+    const int zs = zpart_stride(rp);
+    const float* p = Zpart + (e / rp) * zs + (e % rp);
+    const int64_t step = ldd * zs;
     int64_t h = hl;
     for (; h + 3 * kRzLanes < nch; h += 4 * kRzLanes) {
       const float a0 = p[h * step];
@@ -509,15 +431,16 @@ void mfma_reduce_w(const Launch& L, bool bf16, const float* Wtpart, int nct, int
 }
 
 void mfma_mm_b(const Launch& L, bool bf16, const void* D, int64_t ldd, int64_t mpad,
-               const void* Wt, float* Zpart, int64_t RC, int64_t nch, hipEvent_t ev_a,
+               const void* Wt, float* Zpart, int64_t RC, int64_t nch, int rp, hipEvent_t ev_a,
                hipEvent_t ev_b) {
   dim3 grid((unsigned)(ldd / 128), (unsigned)nch);
+  const int zs = zpart_stride(rp);
   if (bf16)
     hipExtLaunchKernelGGL(k_mm_b_bf16, grid, dim3(256), 0, L.stream, ev_a, ev_b, 0,
-                          (const uint16_t*)D, ldd, mpad, (const uint16_t*)Wt, Zpart, RC);
+                          (const uint16_t*)D, ldd, mpad, (const uint16_t*)Wt, Zpart, RC, zs);
   else
     hipExtLaunchKernelGGL(k_mm_b_f32, grid, dim3(256), 0, L.stream, ev_a, ev_b, 0,
-                          (const float*)D, ldd, mpad, (const float*)Wt, Zpart, RC);
+                          (const float*)D, ldd, mpad, (const float*)Wt, Zpart, RC, zs);
 }
 
 void mfma_reduce_z(const Launch& L, const float* Zpart, int64_t nch, int64_t ldd, int rp,

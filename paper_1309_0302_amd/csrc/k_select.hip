@@ -43,17 +43,19 @@ __device__ __forceinline__ T resid(T x, const T* __restrict__ u, const T (&v)[RP
 // ---------------------------------------------------------------------------
 // FP32 residual tiles: L = U_L V_L^T over rows [r0, r0 + 16) and columns
 // [c0, c0 + 16) (r0, c0 multiples of 16) by one wavefront with
-// v_mfma_f32_16x16x4f32, k-steps of four rank columns in ascending order.
-// Lane l supplies U_L[r0 + l%16][4s + l/16] and V_L[c0 + l%16][4s + l/16]
-// (zero past m, n or RP) and receives L at column c0 + l%16 and rows
-// r0 + res_row(v, l), v < 4.
+// v_mfma_f32_16x16x4f32 evaluating the transposed tile V_L U_L^T, k-steps of
+// four rank columns in ascending order.  Lane l supplies
+// V_L[c0 + l%16][4s + l/16] (A operand) and U_L[r0 + l%16][4s + l/16]
+// (B operand), zero past m, n or RP, and receives L at row r0 + l%16 and
+// columns c0 + res_col(v, l), v < 4: four consecutive columns of one row, so
+// that a lane reads its four X entries with one 16-byte load.
 // ---------------------------------------------------------------------------
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 template <int RP>
 struct ResK { static constexpr int KS = (RP + 3) / 4; };
 
-__device__ __forceinline__ int res_row(int v, int lane) { return 4 * (lane >> 4) + v; }
+__device__ __forceinline__ int res_col(int v, int lane) { return 4 * (lane >> 4) + v; }
 
 template <int RP>
 __device__ __forceinline__ void res_load_u(const float* __restrict__ UL, int64_t m, int64_t r0,
@@ -94,13 +96,15 @@ __device__ __forceinline__ void res_load_v(const float* __restrict__ VL, int64_t
   }
 }
 
+// u: the U_L operand (res_load_u), v: the V_L operand (res_load_vt or
+// res_load_v).
 template <int RP>
-__device__ __forceinline__ f32x4_t res_tile(const float (&a)[ResK<RP>::KS],
-                                            const float (&b)[ResK<RP>::KS]) {
+__device__ __forceinline__ f32x4_t res_tile(const float (&u)[ResK<RP>::KS],
+                                            const float (&v)[ResK<RP>::KS]) {
   f32x4_t acc = {};
 #pragma unroll
   for (int s = 0; s < ResK<RP>::KS; ++s)
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[s], u[s], acc, 0, 0, 0);
   return acc;
 }
 
@@ -281,9 +285,83 @@ __device__ __forceinline__ void sel_tile(const T* __restrict__ X, int64_t ldx, i
 // unit as 16 tiles, left to right, so the candidates it appends lie in one
 // 16 x 256 region (row-local order for the later scattered updates of D).
 // The U_L operand stays in registers for the unit; the V_L operand and the X
-// entries of the next tile are loaded before the current tile is processed.
+// entries of the next tiles are loaded before the current tile is
+// processed.  Units wholly inside the matrix (and a 16-byte aligned X) take
+// a path without bounds checks; in the carried-window pass (HIST and TAKE
+// together, whose key windows coincide) one comparison serves both.
 constexpr int kResUnitCols = 1024;
 constexpr int kResSlots = 4;   // tiles of a wave's X and V_L operands in registers
+
+template <int RP, bool HIST, bool TAKE, bool S2, bool FULL>
+__device__ __forceinline__ void sel_unit_mfma(const float* __restrict__ X, int64_t ldx,
+                                              const float* __restrict__ VLt, int64_t ldv,
+                                              int64_t m, int64_t n, int64_t r0, int64_t cw,
+                                              int nt, const float (&a)[ResK<RP>::KS],
+                                              unsigned int* lh, const PassKeys<float>& pk,
+                                              SegSink<float>& sink, double& s2, bool vec_ok) {
+  using K = uint32_t;
+  constexpr int KS = ResK<RP>::KS;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = r0 + (lane & 15);
+  const bool rowok = FULL || row < m;
+  const int cg = res_col(0, lane);
+  const float* xrow = X + (rowok ? row : 0) * ldx;
+  float b[kResSlots][KS], x[kResSlots][4];
+  auto load_tile = [&](int t, float (&bb)[KS], float (&xx)[4]) {
+    const int64_t c0 = cw + 16 * t;
+    res_load_vt<RP>(VLt, ldv, n, c0, lane, bb);
+    const int64_t col = c0 + cg;
+    if (FULL) {
+      const float4 q = *reinterpret_cast<const float4*>(xrow + col);
+      xx[0] = q.x; xx[1] = q.y; xx[2] = q.z; xx[3] = q.w;
+    } else if (vec_ok && rowok && col + 3 < n) {
+      const float4 q = *reinterpret_cast<const float4*>(xrow + col);
+      xx[0] = q.x; xx[1] = q.y; xx[2] = q.z; xx[3] = q.w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xx[v] = (rowok && col + v < n) ? xrow[col + v] : 0.f;
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < kResSlots - 1; ++u)
+    if (u < nt) load_tile(u, b[u], x[u]);
+  for (int t0 = 0; t0 < nt; t0 += kResSlots) {
+#pragma unroll
+    for (int u = 0; u < kResSlots; ++u) {
+      const int t = t0 + u;
+      if (t < nt) {
+        // the slot freed by the previous tile takes tile t + kResSlots - 1
+        const int up = (u + kResSlots - 1) % kResSlots;
+        if (t + kResSlots - 1 < nt) load_tile(t + kResSlots - 1, b[up], x[up]);
+        const int64_t col0 = cw + 16 * t + cg;
+        const f32x4_t L = res_tile<RP>(a, b[u]);
+        double t2 = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool ok = FULL || (rowok && col0 + v < n);
+          const float r = x[u][v] - L[v];
+          const K key = (K)abs_key(r);
+          if constexpr (S2) {
+            if (ok) t2 = fma((double)r, (double)r, t2);
+          }
+          if constexpr (HIST && TAKE) {
+            const bool c = ok && key >= pk.kmin;
+            if (c) atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+            seg_push(sink, c, row * n + col0 + v, r, x[u][v]);
+          } else {
+            if constexpr (HIST) {
+              if (ok && (K)(key - pk.klo) < pk.kspan)
+                atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+            }
+            if constexpr (TAKE)
+              seg_push(sink, ok && key >= pk.kmin, row * n + col0 + v, r, x[u][v]);
+          }
+        }
+        if constexpr (S2) s2 += t2;
+      }
+    }
+  }
+}
 
 template <int RP, bool HIST, bool TAKE, bool S2>
 __device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64_t ldx,
@@ -291,8 +369,7 @@ __device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64
                                               const float* __restrict__ VLt, int64_t ldv,
                                               int64_t m, int64_t n, unsigned int* lh,
                                               const PassKeys<float>& pk, SegSink<float>& sink,
-                                              double& s2) {
-  using K = uint32_t;
+                                              double& s2, bool vec_ok) {
   constexpr int KS = ResK<RP>::KS;
   constexpr int WT = kResUnitCols / 4 / 16;   // tiles per wave per unit
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -306,53 +383,14 @@ __device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64
     if (cw >= n) continue;   // wave-uniform
     float a[KS];
     res_load_u<RP>(UL, m, r0, lane, a);
-    // Tiles cycle through kResSlots register slots: the loads of tiles
-    // t + 1 .. t + kResSlots - 1 are in flight while tile t is processed
-    // (slot indices are compile-time; the tile loop is unrolled by the slot
-    // count).
-    float b[kResSlots][KS], x[kResSlots][4];
-    auto load_tile = [&](int t, float (&bb)[KS], float (&xx)[4]) {
-      const int64_t c0 = cw + 16 * t;
-      const int64_t col = c0 + (lane & 15);
-      res_load_vt<RP>(VLt, ldv, n, c0, lane, bb);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + res_row(v, lane);
-        xx[v] = (col < n && row < m) ? X[row * ldx + col] : 0.f;
-      }
-    };
     const int nt = (int)(((n - cw) + 15) / 16 < WT ? ((n - cw) + 15) / 16 : WT);
-#pragma unroll
-    for (int u = 0; u < kResSlots - 1; ++u)
-      if (u < nt) load_tile(u, b[u], x[u]);
-    for (int t0 = 0; t0 < nt; t0 += kResSlots) {
-#pragma unroll
-      for (int u = 0; u < kResSlots; ++u) {
-        const int t = t0 + u;
-        if (t < nt) {
-          // the slot freed by the previous tile takes tile t + kResSlots - 1
-          const int up = (u + kResSlots - 1) % kResSlots;
-          if (t + kResSlots - 1 < nt) load_tile(t + kResSlots - 1, b[up], x[up]);
-          const int64_t col = cw + 16 * t + (lane & 15);
-          const f32x4_t L = res_tile<RP>(a, b[u]);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t row = r0 + res_row(v, lane);
-            const bool ok = col < n && row < m;
-            const float r = x[u][v] - L[v];
-            const K key = (K)abs_key(r);
-            if constexpr (S2) {
-              if (ok) s2 += (double)r * (double)r;
-            }
-            if constexpr (HIST) {
-              if (ok && (K)(key - pk.klo) < pk.kspan)
-                atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
-            }
-            if constexpr (TAKE) seg_push(sink, ok && key >= pk.kmin, row * n + col, r, x[u][v]);
-          }
-        }
-      }
-    }
+    const bool full = vec_ok && r0 + 16 <= m && cw + 16 * WT <= n;   // wave-uniform
+    if (full)
+      sel_unit_mfma<RP, HIST, TAKE, S2, true>(X, ldx, VLt, ldv, m, n, r0, cw, nt, a, lh, pk,
+                                              sink, s2, vec_ok);
+    else
+      sel_unit_mfma<RP, HIST, TAKE, S2, false>(X, ldx, VLt, ldv, m, n, r0, cw, nt, a, lh, pk,
+                                               sink, s2, vec_ok);
   }
 }
 
@@ -364,7 +402,7 @@ __device__ __forceinline__ void sel_pass_body(const T* __restrict__ X, int64_t l
                                               const PassKeys<T>& pk, SegSink<T>& sink,
                                               bool vec_ok, double& s2) {
   if constexpr (sizeof(T) == 4) {
-    sel_pass_mfma<RP, HIST, TAKE, S2>(X, ldx, UL, VLt, ldv, m, n, lh, pk, sink, s2);
+    sel_pass_mfma<RP, HIST, TAKE, S2>(X, ldx, UL, VLt, ldv, m, n, lh, pk, sink, s2, vec_ok);
   } else {
   constexpr int CPT = sel_cpt<T, RP>();
   constexpr int TW = 256 * CPT;
@@ -924,7 +962,9 @@ __global__ __launch_bounds__(1024) void k_sel_ties(SelPlan* __restrict__ plan,
 // scanning all of X.
 // FP32 form of the index-ordered tie scan: bands of 16 rows; the hits of
 // each band are counted per row, the rows that fit are taken whole and the
-// first row that does not fit is taken in column order by one wavefront.
+// first row that does not fit is taken in column order by one wavefront
+// (the four lanes holding that row of a tile hold its columns 4g .. 4g+3,
+// g = lane / 16, so column order is lane-group order, then register order).
 // Returns the number of tied entries written at s_idx[base ..].
 template <int RP>
 __device__ long long ties_scan_mfma(const float* __restrict__ X, int64_t ldx,
@@ -947,16 +987,16 @@ __device__ long long ties_scan_mfma(const float* __restrict__ X, int64_t ldx,
     __syncthreads();
     float a[KS];
     res_load_u<RP>(UL, m, r0, lane, a);
+    const int lr = lane & 15;
+    const int64_t row = r0 + lr;
     // hits per row of the band
     for (int64_t c0 = 16 * wave; c0 < n; c0 += 64) {
       float b[KS];
       res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
       const f32x4_t L = res_tile<RP>(a, b);
-      const int64_t col = c0 + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int lr = res_row(v, lane);
-        const int64_t row = r0 + lr;
+        const int64_t col = c0 + res_col(v, lane);
         if (col < n && row < m && (uint32_t)abs_key(X[row * ldx + col] - L[v]) == tkey)
           atomicAdd(&rowcnt[lr], 1u);
       }
@@ -984,11 +1024,9 @@ __device__ long long ties_scan_mfma(const float* __restrict__ X, int64_t ldx,
         float b[KS];
         res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
         const f32x4_t L = res_tile<RP>(a, b);
-        const int64_t col = c0 + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int lr = res_row(v, lane);
-          const int64_t row = r0 + lr;
+          const int64_t col = c0 + res_col(v, lane);
           if (lr < cut && col < n && row < m &&
               (uint32_t)abs_key(X[row * ldx + col] - L[v]) == tkey) {
             const unsigned int p = atomicAdd(&wpos, 1u);
@@ -998,30 +1036,47 @@ __device__ long long ties_scan_mfma(const float* __restrict__ X, int64_t ldx,
         }
       }
     }
-    // the cut row: its first cut_q hits in column order (lanes 16 gcut ..
-    // 16 gcut + 15 hold its 16 columns of a tile, in order)
+    // the cut row: its first cut_q hits in column order (lanes cut + 16 g
+    // hold its columns 4g .. 4g+3 of a tile)
     if (cut < 16 && wave == 0) {
       const unsigned int q = cut_q;
-      const int gcut = cut >> 2, vcut = cut & 3;
-      const int64_t row = r0 + cut;
+      const int64_t crow = r0 + cut;
       unsigned int got = 0;
       for (int64_t c0 = 0; c0 < n && got < q; c0 += 16) {
         float b[KS];
         res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
         const f32x4_t L = res_tile<RP>(a, b);
-        const int64_t col = c0 + (lane & 15);
-        bool hit = false;
-        if ((lane >> 4) == gcut && col < n && row < m)
-          hit = (uint32_t)abs_key(X[row * ldx + col] - res_pick(L, vcut)) == tkey;
-        const unsigned long long mask = __ballot(hit);
-        const unsigned int rank = __builtin_amdgcn_mbcnt_hi(
-            (unsigned int)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)mask, 0u));
-        if (hit && got + rank < q) {
-          s_idx[at + full_cnt + got + rank] = row * n + col;
-          s_val[at + full_cnt + got + rank] = 0.f;
+        unsigned int hits = 0u;   // bit v: column c0 + 4g + v is a hit
+        if (lr == cut && crow < m) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t col = c0 + res_col(v, lane);
+            if (col < n && (uint32_t)abs_key(X[crow * ldx + col] - L[v]) == tkey)
+              hits |= 1u << v;
+          }
         }
-        const unsigned int c = (unsigned int)__popcll(mask);
-        got = (got + c < q) ? got + c : q;
+        // hits of the lanes cut + 16 g' for g' < g come first
+        unsigned int before = 0u, total = 0u;
+#pragma unroll
+        for (int g2 = 0; g2 < 4; ++g2) {
+          const unsigned int h = (unsigned int)__popc(__shfl(hits, cut + 16 * g2, 64));
+          if (g2 < (lane >> 4)) before += h;
+          total += h;
+        }
+        if (lr == cut) {
+          unsigned int rank = before;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if ((hits >> v) & 1u) {
+              if (got + rank < q) {
+                s_idx[at + full_cnt + got + rank] = crow * n + c0 + res_col(v, lane);
+                s_val[at + full_cnt + got + rank] = 0.f;
+              }
+              ++rank;
+            }
+          }
+        }
+        got = (got + total < q) ? got + total : q;
       }
     }
     __syncthreads();
@@ -1151,9 +1206,9 @@ __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X,
       res_load_vt<RP>(VLt, ldv, n, c0, lane, b);
       const f32x4_t L = res_tile<RP>(a, b);
       const int li = (int)(i - r0), lj = (int)(j - c0);
-      if (lane == lj + 16 * (li >> 2)) {
+      if (lane == li + 16 * (lj >> 2)) {
         const float x = X[i * ldx + j];
-        s_val[e] = x - res_pick(L, li & 3);
+        s_val[e] = x - res_pick(L, lj & 3);
         s_x[e] = x;
       }
     }
@@ -1223,12 +1278,12 @@ __global__ __launch_bounds__(256) void k_residual_f32(const float* __restrict__ 
   res_load_u<RP>(UL, m, r0, lane, a);
   res_load_v<RP>(VL, n, c0, lane, b);
   const f32x4_t L = res_tile<RP>(a, b);
-  const int64_t col = c0 + (lane & 15);
-  if (col >= n) return;
+  const int64_t row = r0 + (lane & 15);
+  if (row >= m) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int64_t row = r0 + res_row(v, lane);
-    if (row >= m) continue;
+    const int64_t col = c0 + res_col(v, lane);
+    if (col >= n) continue;
     R[row * ldr + col] = dense_l ? 0.f - (0.f - L[v]) : X[row * ldx + col] - L[v];
   }
 }

@@ -13,6 +13,7 @@
 // the eigen-decomposition of B^T B, so that U_L = B K and V_L = Q2.
 #include "godec_internal.h"
 #include "k_common.h"
+#include "k_mmb.h"
 
 namespace godec {
 
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
           float v[kGramMaxChunks];
 #pragma unroll
           for (int h = 0; h < kGramMaxChunks; ++h)
-            v[h] = h < nch ? Zpart[((int64_t)h * rows + i0 + row) * 32 + c] : 0.f;
+            v[h] = h < nch ? Zpart[((int64_t)h * rows + i0 + row) * zpart_stride(RP) + c] : 0.f;
           float z = 0.f;
 #pragma unroll
           for (int h = 0; h < kGramMaxChunks; ++h)
@@ -723,6 +724,7 @@ void launch_gram_tree(const Launch& L, bool f64, int rp, const void* P, int64_t 
                          normalise, Zpart, nch);
   });
 }
+
 
 void launch_core(const Launch& L, bool f64, int rp, const double* Gpart,
                  int nparts, SmallState* st, int p, double rank_tol,
