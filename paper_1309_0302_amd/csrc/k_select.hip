@@ -138,11 +138,15 @@ constexpr int sel_cpt() {
 // segment number b * kSelWaves + w, entries [seg * seg_cap, (seg + 1) *
 // seg_cap) of the candidate arrays.  Its fill is wave-uniform (kept in a
 // scalar register and advanced by ballot counts), so appending needs no
-// atomics; entries beyond a full segment go to the spill region
-// [cap, 2 * cap) through the global counter plan->ncand.  Whenever the total
-// fits in cap, every entry is kept.  Each wave publishes its segment fill in
-// seg_count[seg] at the end of the pass.
+// atomics.  Appended entries first go to the wave's ring of kSegRing slots
+// in LDS; whenever 64 are pending they leave as one fully populated store
+// per array (lane l writes logical position flushed + l).  Positions at or
+// beyond a full segment go to the spill region [cap, 2 * cap) through the
+// global counter plan->ncand.  Whenever the total fits in cap, every entry
+// is kept.  Each wave publishes its segment fill in seg_count[seg] at the
+// end of the pass (seg_close writes out the last pending entries first).
 constexpr int kSelWaves = 4;   // waves per block of the full-data passes
+constexpr int kSegRing = 128;  // ring slots per wave (at most 63 pending + 64 new)
 
 template <typename T>
 struct SegSink {
@@ -151,10 +155,35 @@ struct SegSink {
   T* xv;
   long long base;           // first entry of the wave's segment
   unsigned int cap;         // segment capacity
-  unsigned int fill;        // wave-uniform fill
+  unsigned int fill;        // wave-uniform fill (logical positions handed out)
   unsigned long long* sp_cnt;  // spill fill counter
   long long sp_cap;         // spill capacity (= cap; the spill starts at cap)
+  int64_t* ring_i;          // this wave's LDS ring
+  T* ring_v;
+  T* ring_x;
+  unsigned int flushed;     // wave-uniform: logical positions already stored
 };
+
+// Store the ring entry of logical position e (lanes with act).
+template <typename T>
+__device__ __forceinline__ void seg_emit(SegSink<T>& s, bool act, unsigned int e) {
+  if (!act) return;
+  const unsigned int slot = e & (kSegRing - 1);
+  const int64_t i = s.ring_i[slot];
+  const T v = s.ring_v[slot], x = s.ring_x[slot];
+  long long pos;
+  if (e < s.cap) {
+    pos = s.base + e;
+  } else {
+    const unsigned long long q = atomicAdd(s.sp_cnt, 1ull);
+    pos = (long long)q < s.sp_cap ? s.sp_cap + (long long)q : -1;
+  }
+  if (pos >= 0) {
+    s.idx[pos] = i;
+    s.val[pos] = v;
+    s.xv[pos] = x;
+  }
+}
 
 // Called by every lane of the wave (uniform control flow); lanes with
 // `take` append (idx, r, x).  Positions follow lane order within the wave.
@@ -164,21 +193,30 @@ __device__ __forceinline__ void seg_push(SegSink<T>& s, bool take, int64_t idx, 
   if (mask == 0ull) return;
   const unsigned int lo = (unsigned int)mask, hi = (unsigned int)(mask >> 32);
   const unsigned int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-  const unsigned int p = s.fill + rank;
+  if (take) {
+    const unsigned int slot = (s.fill + rank) & (kSegRing - 1);
+    s.ring_i[slot] = idx;
+    s.ring_v[slot] = r;
+    s.ring_x[slot] = x;
+  }
   s.fill += (unsigned int)__popcll(mask);
-  if (!take) return;
-  long long pos;
-  if (p < s.cap) {
-    pos = s.base + p;
-  } else {
-    const unsigned long long q = atomicAdd(s.sp_cnt, 1ull);
-    pos = (long long)q < s.sp_cap ? s.sp_cap + (long long)q : -1;
+  if (s.fill - s.flushed >= 64u) {
+    // the ring's writes above precede these reads (LDS is in order within a
+    // wave; the barrier keeps the compiler from moving them across)
+    __builtin_amdgcn_wave_barrier();
+    seg_emit(s, true, s.flushed + (threadIdx.x & 63));
+    s.flushed += 64u;
+    __builtin_amdgcn_wave_barrier();
   }
-  if (pos >= 0) {
-    s.idx[pos] = idx;
-    s.val[pos] = r;
-    s.xv[pos] = x;
-  }
+}
+
+// End of a collecting pass: store the entries still in the ring.
+template <typename T>
+__device__ __forceinline__ void seg_close(SegSink<T>& s) {
+  __builtin_amdgcn_wave_barrier();
+  const unsigned int l = threadIdx.x & 63;
+  seg_emit(s, l < s.fill - s.flushed, s.flushed + l);
+  s.flushed = s.fill;
 }
 
 // Range of candidate segment sg (sg == nseg is the spill region).
@@ -466,11 +504,15 @@ __device__ __forceinline__ PassKeys<T> keys_level0() {
   const long long ccap = plan->cap;                                           \
   const unsigned int seg_cap = (unsigned int)(ccap / ((long long)gridDim.x * kSelWaves)); \
   const int seg = (int)blockIdx.x * kSelWaves + wave;                         \
+  __shared__ int64_t ring_i[kSelWaves * kSegRing];                            \
+  __shared__ T ring_v[kSelWaves * kSegRing], ring_x[kSelWaves * kSegRing];    \
   SegSink<T> sink{cand_idx, cand_val, cand_x, (long long)seg * seg_cap, seg_cap, 0u, \
-                  (unsigned long long*)&plan->ncand, ccap};
+                  (unsigned long long*)&plan->ncand, ccap, ring_i + wave * kSegRing, \
+                  ring_v + wave * kSegRing, ring_x + wave * kSegRing, 0u};
 
 // Closing of a collecting pass: publish the wave's segment fill.
 #define GODEC_SEL_SEG_CLOSE                                                   \
+  seg_close(sink);                                                            \
   if (lane == 0) seg_count[seg] = sink.fill < seg_cap ? sink.fill : seg_cap;
 
 // Pass 0: the carried-window pass (steady state) or the full level-0
