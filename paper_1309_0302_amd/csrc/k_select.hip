@@ -57,15 +57,21 @@ struct ResK { static constexpr int KS = (RP + 3) / 4; };
 
 __device__ __forceinline__ int res_col(int v, int lane) { return 4 * (lane >> 4) + v; }
 
+// The loaders read a clamped in-bounds address on every lane and zero the
+// padding afterwards, so no load sits behind a lane-dependent branch (m, n
+// and RP are at least 1).
 template <int RP>
 __device__ __forceinline__ void res_load_u(const float* __restrict__ UL, int64_t m, int64_t r0,
                                            int lane, float (&a)[ResK<RP>::KS]) {
   const int64_t row = r0 + (lane & 15);
+  const int64_t rowc = row < m ? row : m - 1;
   const int g = lane >> 4;
 #pragma unroll
   for (int s = 0; s < ResK<RP>::KS; ++s) {
     const int k = 4 * s + g;
-    a[s] = (k < RP && row < m) ? UL[row * RP + k] : 0.f;
+    const int kc = k < RP ? k : RP - 1;
+    const float u = UL[rowc * RP + kc];
+    a[s] = (k < RP && row < m) ? u : 0.f;
   }
 }
 
@@ -75,11 +81,14 @@ __device__ __forceinline__ void res_load_vt(const float* __restrict__ VLt, int64
                                             int64_t n, int64_t c0, int lane,
                                             float (&b)[ResK<RP>::KS]) {
   const int64_t col = c0 + (lane & 15);
+  const int64_t colc = col < n ? col : n - 1;
   const int g = lane >> 4;
 #pragma unroll
   for (int s = 0; s < ResK<RP>::KS; ++s) {
     const int k = 4 * s + g;
-    b[s] = (k < RP && col < n) ? VLt[k * ldv + col] : 0.f;
+    const int kc = k < RP ? k : RP - 1;
+    const float v = VLt[kc * ldv + colc];
+    b[s] = (k < RP && col < n) ? v : 0.f;
   }
 }
 
@@ -88,11 +97,14 @@ template <int RP>
 __device__ __forceinline__ void res_load_v(const float* __restrict__ VL, int64_t n, int64_t c0,
                                            int lane, float (&b)[ResK<RP>::KS]) {
   const int64_t col = c0 + (lane & 15);
+  const int64_t colc = col < n ? col : n - 1;
   const int g = lane >> 4;
 #pragma unroll
   for (int s = 0; s < ResK<RP>::KS; ++s) {
     const int k = 4 * s + g;
-    b[s] = (k < RP && col < n) ? VL[col * RP + k] : 0.f;
+    const int kc = k < RP ? k : RP - 1;
+    const float v = VL[colc * RP + kc];
+    b[s] = (k < RP && col < n) ? v : 0.f;
   }
 }
 
@@ -199,13 +211,25 @@ __device__ __forceinline__ void seg_push(SegSink<T>& s, bool take, int64_t idx, 
     s.ring_v[slot] = r;
     s.ring_x[slot] = x;
   }
-  s.fill += (unsigned int)__popcll(mask);
+  // the fill is wave-uniform: keep it in a scalar register
+  s.fill = __builtin_amdgcn_readfirstlane(s.fill + (unsigned int)__popcll(mask));
   if (s.fill - s.flushed >= 64u) {
     // the ring's writes above precede these reads (LDS is in order within a
     // wave; the barrier keeps the compiler from moving them across)
     __builtin_amdgcn_wave_barrier();
-    seg_emit(s, true, s.flushed + (threadIdx.x & 63));
-    s.flushed += 64u;
+    const unsigned int e = s.flushed + (threadIdx.x & 63);
+    if (s.flushed + 64u <= s.cap) {
+      // wave-uniform common case: the 64 entries stay in the segment (no
+      // atomic whose returned value would hold up the loads in flight)
+      const unsigned int slot = e & (kSegRing - 1);
+      const long long pos = s.base + e;
+      s.idx[pos] = s.ring_i[slot];
+      s.val[pos] = s.ring_v[slot];
+      s.xv[pos] = s.ring_x[slot];
+    } else {
+      seg_emit(s, true, e);
+    }
+    s.flushed = __builtin_amdgcn_readfirstlane(s.flushed + 64u);
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -318,85 +342,89 @@ __device__ __forceinline__ void sel_tile(const T* __restrict__ X, int64_t ldx, i
   }
 }
 
-// FP32 full-data pass on the matrix cores.  Work unit = a band of 16 rows x
-// 1024 columns; wave w takes the 256 columns [256 w, 256 w + 256) of the
-// unit as 16 tiles, left to right, so the candidates it appends lie in one
-// 16 x 256 region (row-local order for the later scattered updates of D).
-// The U_L operand stays in registers for the unit; the V_L operand and the X
-// entries of the next tiles are loaded before the current tile is
-// processed.  Units wholly inside the matrix (and a 16-byte aligned X) take
-// a path without bounds checks; in the carried-window pass (HIST and TAKE
-// together, whose key windows coincide) one comparison serves both.
-constexpr int kResUnitCols = 1024;
-constexpr int kResSlots = 4;   // tiles of a wave's X and V_L operands in registers
+// FP32 full-data pass on the matrix cores.  The matrix is cut into column
+// strips of 4 * 16 * WT columns (wave w owns the WT 16-column tiles
+// [16 WT w, 16 WT (w + 1)) of a strip) and 16-row bands; work unit = one
+// (strip, band) pair, in strip-major order, and block b takes the units
+// [W b / G, W (b + 1) / G) of the W units (G blocks).  A wave keeps the V_L
+// operand of its WT tiles in registers while it walks down the bands of a
+// strip, so per band it loads only the U_L operand and the band's X entries
+// (all WT tiles issued before the first is used).  The candidates a wave
+// appends lie in one 16 WT-column strip, in band order (local for the later
+// scattered updates of D).  Bands wholly inside the matrix (and a 16-byte
+// aligned X) take a path without bounds checks; in the carried-window pass
+// (HIST and TAKE together, whose key windows coincide) one comparison serves
+// both.
+template <int RP> struct ResStrip {
+  // four tiles per wave keep the pass within 128 registers (four waves per
+  // SIMD at four blocks per CU)
+  static constexpr int WT = 4;               // tiles per wave
+  static constexpr int COLS = 4 * 16 * WT;   // columns per strip
+};
 
 template <int RP, bool HIST, bool TAKE, bool S2, bool FULL>
-__device__ __forceinline__ void sel_unit_mfma(const float* __restrict__ X, int64_t ldx,
-                                              const float* __restrict__ VLt, int64_t ldv,
+__device__ __forceinline__ void sel_band_mfma(const float* __restrict__ X, int64_t ldx,
                                               int64_t m, int64_t n, int64_t r0, int64_t cw,
                                               int nt, const float (&a)[ResK<RP>::KS],
+                                              const float (&b)[ResStrip<RP>::WT][ResK<RP>::KS],
                                               unsigned int* lh, const PassKeys<float>& pk,
                                               SegSink<float>& sink, double& s2, bool vec_ok) {
   using K = uint32_t;
-  constexpr int KS = ResK<RP>::KS;
+  constexpr int WT = ResStrip<RP>::WT;
   const int lane = threadIdx.x & 63;
   const int64_t row = r0 + (lane & 15);
   const bool rowok = FULL || row < m;
   const int cg = res_col(0, lane);
   const float* xrow = X + (rowok ? row : 0) * ldx;
-  float b[kResSlots][KS], x[kResSlots][4];
-  auto load_tile = [&](int t, float (&bb)[KS], float (&xx)[4]) {
-    const int64_t c0 = cw + 16 * t;
-    res_load_vt<RP>(VLt, ldv, n, c0, lane, bb);
-    const int64_t col = c0 + cg;
-    if (FULL) {
-      const float4 q = *reinterpret_cast<const float4*>(xrow + col);
-      xx[0] = q.x; xx[1] = q.y; xx[2] = q.z; xx[3] = q.w;
-    } else if (vec_ok && rowok && col + 3 < n) {
-      const float4 q = *reinterpret_cast<const float4*>(xrow + col);
-      xx[0] = q.x; xx[1] = q.y; xx[2] = q.z; xx[3] = q.w;
-    } else {
+  const int ntt = FULL ? WT : nt;
+  float x[WT][4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xx[v] = (rowok && col + v < n) ? xrow[col + v] : 0.f;
-    }
-  };
-#pragma unroll
-  for (int u = 0; u < kResSlots - 1; ++u)
-    if (u < nt) load_tile(u, b[u], x[u]);
-  for (int t0 = 0; t0 < nt; t0 += kResSlots) {
-#pragma unroll
-    for (int u = 0; u < kResSlots; ++u) {
-      const int t = t0 + u;
-      if (t < nt) {
-        // the slot freed by the previous tile takes tile t + kResSlots - 1
-        const int up = (u + kResSlots - 1) % kResSlots;
-        if (t + kResSlots - 1 < nt) load_tile(t + kResSlots - 1, b[up], x[up]);
-        const int64_t col0 = cw + 16 * t + cg;
-        const f32x4_t L = res_tile<RP>(a, b[u]);
-        double t2 = 0.0;
+  for (int t = 0; t < WT; ++t) {
+    if (t < ntt) {
+      const int64_t col = cw + 16 * t + cg;
+      if (FULL) {
+        const float4 q = *reinterpret_cast<const float4*>(xrow + col);
+        x[t][0] = q.x; x[t][1] = q.y; x[t][2] = q.z; x[t][3] = q.w;
+      } else if (vec_ok && rowok && col + 3 < n) {
+        const float4 q = *reinterpret_cast<const float4*>(xrow + col);
+        x[t][0] = q.x; x[t][1] = q.y; x[t][2] = q.z; x[t][3] = q.w;
+      } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const bool ok = FULL || (rowok && col0 + v < n);
-          const float r = x[u][v] - L[v];
-          const K key = (K)abs_key(r);
-          if constexpr (S2) {
-            if (ok) t2 = fma((double)r, (double)r, t2);
-          }
-          if constexpr (HIST && TAKE) {
-            const bool c = ok && key >= pk.kmin;
-            if (c) atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
-            seg_push(sink, c, row * n + col0 + v, r, x[u][v]);
-          } else {
-            if constexpr (HIST) {
-              if (ok && (K)(key - pk.klo) < pk.kspan)
-                atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
-            }
-            if constexpr (TAKE)
-              seg_push(sink, ok && key >= pk.kmin, row * n + col0 + v, r, x[u][v]);
-          }
+          const float xv = xrow[col + v < n ? col + v : n - 1];
+          x[t][v] = (rowok && col + v < n) ? xv : 0.f;
         }
-        if constexpr (S2) s2 += t2;
       }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < WT; ++t) {
+    if (t < ntt) {
+      const int64_t col0 = cw + 16 * t + cg;
+      const f32x4_t L = res_tile<RP>(a, b[t]);
+      double t2 = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool ok = FULL || (rowok && col0 + v < n);
+        const float r = x[t][v] - L[v];
+        const K key = (K)abs_key(r);
+        if constexpr (S2) {
+          if (ok) t2 = fma((double)r, (double)r, t2);
+        }
+        if constexpr (HIST && TAKE) {
+          const bool c = ok && key >= pk.kmin;
+          if (c) atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+          seg_push(sink, c, row * n + col0 + v, r, x[t][v]);
+        } else {
+          if constexpr (HIST) {
+            if (ok && (K)(key - pk.klo) < pk.kspan)
+              atomicAdd(&lh[(key >> pk.shift) & pk.mask], 1u);
+          }
+          if constexpr (TAKE)
+            seg_push(sink, ok && key >= pk.kmin, row * n + col0 + v, r, x[t][v]);
+        }
+      }
+      if constexpr (S2) s2 += t2;
     }
   }
 }
@@ -409,26 +437,37 @@ __device__ __forceinline__ void sel_pass_mfma(const float* __restrict__ X, int64
                                               const PassKeys<float>& pk, SegSink<float>& sink,
                                               double& s2, bool vec_ok) {
   constexpr int KS = ResK<RP>::KS;
-  constexpr int WT = kResUnitCols / 4 / 16;   // tiles per wave per unit
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t ncs = (n + kResUnitCols - 1) / kResUnitCols;
-  const int64_t nrb = (m + 15) / 16;
-  const int64_t units = ncs * nrb;
-  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    const int64_t cs = u % ncs, rb = u / ncs;
-    const int64_t r0 = rb * 16;
-    const int64_t cw = cs * kResUnitCols + (int64_t)(kResUnitCols / 4) * wave;
+  constexpr int WT = ResStrip<RP>::WT;
+  constexpr int SC = 16 * WT;   // columns per wave
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform (SGPR)
+  const int64_t nstrip = (n + ResStrip<RP>::COLS - 1) / ResStrip<RP>::COLS;
+  const int64_t nband = (m + 15) / 16;
+  const int64_t units = nstrip * nband;
+  const int64_t u0 = units * blockIdx.x / gridDim.x;
+  const int64_t u1 = units * (blockIdx.x + 1) / gridDim.x;
+  float b[WT][KS];
+  int64_t have = -1;   // strip whose V_L operand b holds
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t st = u / nband, band = u - st * nband;
+    const int64_t cw = st * ResStrip<RP>::COLS + (int64_t)SC * wave;
     if (cw >= n) continue;   // wave-uniform
+    if (st != have) {
+#pragma unroll
+      for (int t = 0; t < WT; ++t) res_load_vt<RP>(VLt, ldv, n, cw + 16 * t, lane, b[t]);
+      have = st;
+    }
+    const int64_t r0 = band * 16;
     float a[KS];
     res_load_u<RP>(UL, m, r0, lane, a);
     const int nt = (int)(((n - cw) + 15) / 16 < WT ? ((n - cw) + 15) / 16 : WT);
-    const bool full = vec_ok && r0 + 16 <= m && cw + 16 * WT <= n;   // wave-uniform
+    const bool full = vec_ok && r0 + 16 <= m && cw + SC <= n;   // wave-uniform
     if (full)
-      sel_unit_mfma<RP, HIST, TAKE, S2, true>(X, ldx, VLt, ldv, m, n, r0, cw, nt, a, lh, pk,
-                                              sink, s2, vec_ok);
+      sel_band_mfma<RP, HIST, TAKE, S2, true>(X, ldx, m, n, r0, cw, nt, a, b, lh, pk, sink, s2,
+                                              vec_ok);
     else
-      sel_unit_mfma<RP, HIST, TAKE, S2, false>(X, ldx, VLt, ldv, m, n, r0, cw, nt, a, lh, pk,
-                                               sink, s2, vec_ok);
+      sel_band_mfma<RP, HIST, TAKE, S2, false>(X, ldx, m, n, r0, cw, nt, a, b, lh, pk, sink,
+                                               s2, vec_ok);
   }
 }
 
@@ -499,7 +538,8 @@ __device__ __forceinline__ PassKeys<T> keys_level0() {
   __shared__ T us[kRowsPerTile * RP];                                         \
   __shared__ double red[4];                                                   \
   const int tid = threadIdx.x;                                                \
-  const int lane = tid & 63, wave = tid >> 6;                                 \
+  const int lane = tid & 63;                                                  \
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);                  \
   (void)KB; (void)red;                                                        \
   const long long ccap = plan->cap;                                           \
   const unsigned int seg_cap = (unsigned int)(ccap / ((long long)gridDim.x * kSelWaves)); \
@@ -1533,7 +1573,9 @@ template <typename T>
 static int64_t sel_grid(int rp, int64_t m, int64_t n, int num_cu) {
   int64_t g = 1;
   if (sizeof(T) == 4) {
-    g = ((n + kResUnitCols - 1) / kResUnitCols) * ((m + 15) / 16);
+    int64_t cols = 512;
+    GODEC_RP_SWITCH(rp, { cols = ResStrip<RP>::COLS; });
+    g = ((n + cols - 1) / cols) * ((m + 15) / 16);
     g = std::min<int64_t>(g, (int64_t)num_cu * 4);
   } else {
     GODEC_RP_SWITCH(rp, {
