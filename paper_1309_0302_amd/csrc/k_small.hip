@@ -198,22 +198,40 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
     const int nr = (r1 - i0) < CH ? (int)(r1 - i0) : CH;
     __syncthreads();
     if (Zpart != nullptr) {
-      for (int e = tid; e < CH * RW; e += 256) {
+      // every entry of the thread and every chunk partial in flight at once;
+      // the partials are added in ascending chunk order
+      constexpr int PER = (CH * RW + 255) / 256;
+      float z[PER];
+      bool ok[PER];
+      int64_t off[PER];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int e = tid + 256 * j;
         const int row = e / RW, c = e % RW;
-        double val = 0.0;
-        if (row < nr && c < RP) {
-          float v[kGramMaxChunks];
+        ok[j] = e < CH * RW && row < nr && c < RP;
+        off[j] = ok[j] ? (i0 + row) * zpart_stride(RP) + c : 0;
+        z[j] = 0.f;
+      }
+      const int64_t hstride = rows * zpart_stride(RP);
+      float v[kGramMaxChunks][PER];
 #pragma unroll
-          for (int h = 0; h < kGramMaxChunks; ++h)
-            v[h] = h < nch ? Zpart[((int64_t)h * rows + i0 + row) * zpart_stride(RP) + c] : 0.f;
-          float z = 0.f;
+      for (int h = 0; h < kGramMaxChunks; ++h)
 #pragma unroll
-          for (int h = 0; h < kGramMaxChunks; ++h)
-            if (h < nch) z += v[h];
-          const_cast<TA*>(P)[(i0 + row) * RP + c] = (TA)z;
-          val = (double)z;
+        for (int j = 0; j < PER; ++j)
+          v[h][j] = (h < nch && ok[j]) ? Zpart[h * hstride + off[j]] : 0.f;
+#pragma unroll
+      for (int h = 0; h < kGramMaxChunks; ++h)
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+          if (h < nch) z[j] += v[h][j];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int e = tid + 256 * j;
+        if (e < CH * RW) {
+          const int row = e / RW, c = e % RW;
+          if (ok[j]) const_cast<TA*>(P)[(i0 + row) * RP + c] = (TA)z[j];
+          ps[e] = ok[j] ? (double)z[j] : 0.0;
         }
-        ps[e] = val;
       }
     } else {
       for (int e = tid; e < CH * RW; e += 256) {
@@ -308,69 +326,83 @@ __device__ __forceinline__ void rr_pair(int round, int k, int N, int& a, int& b)
   b = pos(N - 1 - k);
 }
 
-// Two-sided cyclic Jacobi on the symmetric n x n matrix A (LDS, stride LD),
-// accumulating V <- V J.  Parallel over disjoint pairs in each round: the
-// rotations of a round are computed first, then one pass applies them, a
-// thread per 2 x 2 block of A (the column rotation of the block's column
-// pair, then the row rotation of its row pair) and a thread per (row, pair)
-// of V.
+// Two-sided cyclic Jacobi on the symmetric matrix A (LDS, stride LD),
+// accumulating V <- V J.  A is zero outside its leading n x n block and V is
+// the identity there, so the sweeps run over the full RP x RP at compile-time
+// sizes: a pair that touches the padding has a_pq = 0 and is never rotated.
+// Parallel over disjoint pairs in each round: the rotations of a round are
+// computed first, then one pass applies them, a thread per 2 x 2 block of A
+// (the column rotation of the block's column pair, then the row rotation of
+// its row pair) and a thread per (row, pair) of V.
 template <int RP>
 __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
   constexpr int LD = RP + 1;
-  const int N = (n + 1) & ~1;
-  const int npairs = N / 2;
-  const int nblk = npairs * npairs;
-  int* big = rot + 1;
+  constexpr int N = (RP + 1) & ~1;
+  constexpr int NP = N / 2;
+  constexpr int NBLK = NP * NP;
+  __shared__ int pq[2 * NP];
+  (void)n;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (threadIdx.x == 0) { rot[0] = 0; big[0] = 0; }
-    __syncthreads();
+    int nrot = 0, nbig = 0;   // wave 0's counts (every pair lives in wave 0)
     for (int round = 0; round < N - 1; ++round) {
-      if (threadIdx.x < npairs) {
-        int p, q;
-        rr_pair(round, threadIdx.x, N, p, q);
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p * LD + q];
-          const double app = A[p * LD + p], aqq = A[q * LD + q];
-          const double scale = sqrt(fabs(app * aqq));
-          if (fabs(apq) > kJacobiTol * scale && apq != 0.0) {
-            // tan of the rotation t = sgn(d) h / (|d| + r), d = a_qq - a_pp,
-            // h = 2 a_pq, r = hypot(d, h); with w = sqrt(2 r (r + |d|)):
-            // c = (r + |d|) / w, s = sgn(d) h / w.
-            const double d = aqq - app, h = 2.0 * apq;
-            const double mx = fmax(fabs(d), fabs(h));
-            if (mx > 0x1p-450 && mx < 0x1p450) {
-              const double r = sqrt(d * d + h * h);
-              const double iw = 1.0 / sqrt(2.0 * r * (r + fabs(d)));
-              c = (r + fabs(d)) * iw;
-              s = (d >= 0.0 ? h : -h) * iw;
-            } else {
-              const double th = d / h;
-              const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-              c = 1.0 / sqrt(t * t + 1.0);
-              s = t * c;
+      if (threadIdx.x < 64) {
+        const int k = threadIdx.x;
+        bool did = false, big = false;
+        if (k < NP) {
+          // circle method: position i plays at 0 (fixed) or 1 + (i - 1 + round) mod (N - 1)
+          auto pos = [&](int i) {
+            if (i == 0) return 0;
+            int x = i - 1 + round;
+            if (x >= N - 1) x -= N - 1;
+            return 1 + x;
+          };
+          int p = pos(k), q = pos(N - 1 - k);
+          if (p > q) { const int t = p; p = q; q = t; }
+          double c = 1.0, sn = 0.0;
+          if (q < RP) {
+            const double apq = A[p * LD + q];
+            const double app = A[p * LD + p], aqq = A[q * LD + q];
+            const double scale = sqrt(fabs(app * aqq));
+            if (fabs(apq) > kJacobiTol * scale && apq != 0.0) {
+              // tan of the rotation t = sgn(d) h / (|d| + r), d = a_qq - a_pp,
+              // h = 2 a_pq, r = hypot(d, h); with w = sqrt(2 r (r + |d|)):
+              // c = (r + |d|) / w, s = sgn(d) h / w.
+              const double d = aqq - app, h = 2.0 * apq;
+              const double mx = fmax(fabs(d), fabs(h));
+              if (mx > 0x1p-450 && mx < 0x1p450) {
+                const double r = sqrt(d * d + h * h);
+                const double iw = 1.0 / sqrt(2.0 * r * (r + fabs(d)));
+                c = (r + fabs(d)) * iw;
+                sn = (d >= 0.0 ? h : -h) * iw;
+              } else {
+                const double th = d / h;
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                c = 1.0 / sqrt(t * t + 1.0);
+                sn = t * c;
+              }
+              did = true;
+              big = fabs(apq) > kJacobiQuad * scale;
             }
-            atomicAdd(rot, 1);
-            if (fabs(apq) > kJacobiQuad * scale) atomicAdd(big, 1);
           }
+          cs[2 * k + 0] = c;
+          cs[2 * k + 1] = sn;
+          pq[2 * k + 0] = p;
+          pq[2 * k + 1] = q;
         }
-        cs[4 * threadIdx.x + 0] = c;
-        cs[4 * threadIdx.x + 1] = s;
-        cs[4 * threadIdx.x + 2] = (double)p;
-        cs[4 * threadIdx.x + 3] = (double)q;
+        nrot += __popcll(__ballot(did));
+        nbig += __popcll(__ballot(big));
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < nblk + n * npairs; e += blockDim.x) {
-        if (e < nblk) {
+      for (int e = threadIdx.x; e < NBLK + RP * NP; e += blockDim.x) {
+        if (e < NBLK) {
           // A <- J^T A J on the block (row pair k1) x (column pair k2)
-          const int k1 = e / npairs, k2 = e % npairs;
-          const double c1 = cs[4 * k1], s1 = cs[4 * k1 + 1];
-          const double c2 = cs[4 * k2], s2 = cs[4 * k2 + 1];
+          const int k1 = e / NP, k2 = e % NP;
+          const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1];
+          const double c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
           if (s1 == 0.0 && s2 == 0.0) continue;
-          const int p1 = (int)cs[4 * k1 + 2], q1 = (int)cs[4 * k1 + 3];
-          const int p2 = (int)cs[4 * k2 + 2], q2 = (int)cs[4 * k2 + 3];
-          const bool rq = q1 < n, cq = q2 < n;   // the partner may be the padding index
+          const int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1];
+          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+          const bool rq = q1 < RP, cq = q2 < RP;   // the partner may be the padding index
           double a = A[p1 * LD + p2];
           double b = cq ? A[p1 * LD + q2] : 0.0;
           double cc = rq ? A[q1 * LD + p2] : 0.0;
@@ -391,19 +423,21 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
           if (rq && cq) A[q1 * LD + q2] = d;
         } else {
           // V <- V J
-          const int f = e - nblk;
-          const int i = f / npairs, k = f % npairs;
-          const double c = cs[4 * k], s = cs[4 * k + 1];
-          const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
-          if (q >= n || s == 0.0) continue;
+          const int f = e - NBLK;
+          const int i = f / NP, k = f % NP;
+          const double c = cs[2 * k], sn = cs[2 * k + 1];
+          const int p = pq[2 * k], q = pq[2 * k + 1];
+          if (q >= RP || sn == 0.0) continue;
           const double vip = V[i * LD + p], viq = V[i * LD + q];
-          V[i * LD + p] = c * vip - s * viq;
-          V[i * LD + q] = s * vip + c * viq;
+          V[i * LD + p] = c * vip - sn * viq;
+          V[i * LD + q] = sn * vip + c * viq;
         }
       }
       __syncthreads();
     }
-    if (rot[0] == 0 || big[0] == 0) break;
+    if (threadIdx.x == 0) rot[0] = (nrot == 0 || nbig == 0) ? 1 : 0;
+    __syncthreads();
+    if (rot[0]) break;
     __syncthreads();
   }
 }
