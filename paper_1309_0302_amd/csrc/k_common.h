@@ -56,6 +56,23 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// q = a / b and r = a % b for 0 <= a < 2^52 and b >= 1, with rb = 1 / b in
+// double precision: the product a * rb is within one of the quotient (its
+// relative error is at most 2^-52), so one correction step makes it exact.
+// Cheaper than a 64-bit integer division by a runtime divisor.
+__device__ __forceinline__ void divmod_nn(int64_t a, int64_t b, double rb, int64_t& q,
+                                          int64_t& r) {
+  q = (int64_t)((double)a * rb);
+  r = a - q * b;
+  if (r < 0) {
+    q -= 1;
+    r += b;
+  } else if (r >= b) {
+    q += 1;
+    r -= b;
+  }
+}
+
 // Sum of p[0 .. n) in an order fixed by n and the block size alone, so a
 // run reproduces its own bits: thread t adds p[t], p[t + B], ... in turn,
 // each wave reduces by the butterfly of wave_sum, and thread 0 adds the wave

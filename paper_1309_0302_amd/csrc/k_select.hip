@@ -1422,10 +1422,12 @@ __global__ __launch_bounds__(256) void k_update_d(TD* __restrict__ D, int64_t ld
                                                   const TX* __restrict__ xv,
                                                   const SelPlan* __restrict__ plan) {
   const long long cnt = plan->nnz;
+  const double rn = 1.0 / (double)n;
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
        e += (long long)gridDim.x * 256) {
     const int64_t id = idx[e];
-    const int64_t i = id / n, j = id % n;
+    int64_t i, j;
+    divmod_nn(id, n, rn, i, j);
     const TX x = xv[e];
     D[i * ldd + j] = to_store<TD, TX>(val ? (TX)(x - val[e]) : x);
   }

@@ -88,13 +88,29 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Global inputs of wave_chol (the active width and, lane j, column j of the
+// accumulated factor), loaded ahead so that their latency overlaps other work.
+template <int RP> struct CholIn {
+  int reff;
+  double b[RP];
+};
+template <int RP>
+__device__ __forceinline__ void chol_prefetch(CholIn<RP>& in, const SmallState* st,
+                                              const double* acc, int reset_acc) {
+  const int lane = threadIdx.x & 63;
+  in.reff = st->r_eff;
+#pragma unroll
+  for (int l = 0; l < RP; ++l)
+    in.b[l] = (acc != nullptr && !reset_acc && lane < RP) ? acc[l * RP + lane] : 0.0;
+}
+
 // One wavefront (lanes 0..63); G is RP x RP row-major in LDS.
 template <typename TA, int RP>
 __device__ void wave_chol(const double* G, SmallState* st, double* acc, int reset_acc,
-                          int normalise) {
+                          int normalise, const CholIn<RP>& in) {
   const int lane = threadIdx.x & 63;
   const bool col = lane < RP;
-  const int reff = st->r_eff;
+  const int reff = in.reff;
   double g[RP];
 #pragma unroll
   for (int i = 0; i < RP; ++i) g[i] = col ? G[i * RP + lane] : 0.0;
@@ -134,14 +150,11 @@ __device__ void wave_chol(const double* G, SmallState* st, double* acc, int rese
 #pragma unroll
     for (int i = 0; i < RP; ++i) a[i] = rcol[i];
   } else {
-    double b[RP];
-#pragma unroll
-    for (int l = 0; l < RP; ++l) b[l] = col ? acc[l * RP + lane] : 0.0;
 #pragma unroll
     for (int i = 0; i < RP; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int l = i; l < RP; ++l) s += lane_bcast(rcol[i], l) * b[l];
+      for (int l = i; l < RP; ++l) s += lane_bcast(rcol[i], l) * in.b[l];
       a[i] = s;
     }
   }
@@ -162,6 +175,14 @@ __device__ void wave_chol(const double* G, SmallState* st, double* acc, int rese
 #pragma unroll
     for (int i = 0; i < RP; ++i) acc[i * RP + lane] = a[i];
   }
+}
+
+template <typename TA, int RP>
+__device__ void wave_chol(const double* G, SmallState* st, double* acc, int reset_acc,
+                          int normalise) {
+  CholIn<RP> in;
+  chol_prefetch<RP>(in, st, acc, reset_acc);
+  wave_chol<TA, RP>(G, st, acc, reset_acc, normalise, in);
 }
 
 // With Zpart (FP32 panels only), the panel is first formed here: row i,
@@ -292,6 +313,9 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
   }
   __syncthreads();
   if (!flag) return;
+  // the Cholesky step's global inputs, in flight during the fetch below
+  CholIn<RP> cin;
+  if (chol && tid < 64) chol_prefetch<RP>(cin, st, acc, reset_acc);
   double* Gs = ps;   // E <= 1024 doubles fit in ps
   for (int e = tid; e < E; e += 256) {
     double v[kGramMaxBlocks / kGramGroup];
@@ -308,7 +332,7 @@ __global__ __launch_bounds__(256) void k_gram_tree(const TA* __restrict__ P, int
   if (!chol) return;
   __syncthreads();
   if (tid >= 64) return;
-  wave_chol<TA, RP>(Gs, st, acc, reset_acc, normalise);
+  wave_chol<TA, RP>(Gs, st, acc, reset_acc, normalise, cin);
 }
 
 // Rotation threshold of the Jacobi sweeps: an off-diagonal entry below
