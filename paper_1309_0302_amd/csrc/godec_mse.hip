@@ -52,6 +52,7 @@ struct godec_mse {
   void* V = nullptr;               // k x 2 x pp x 8
   void* A1dev = nullptr;           // 2 x kChunk x k x pp x 8
   void* part = nullptr;            // kMaxBlk x pp x 8
+  double* y2 = nullptr;            // pp x 8 (FP64)
   void *UL0, *VL0, *VLt0;          // zero factors for the selection
   SelPlan* plan[2];
   unsigned long long* hist;
@@ -99,6 +100,7 @@ size_t carve_mse(godec_mse* m, void* base) {
   m->V = cv.take((size_t)m->k * 2 * pp * kRP * ta);
   m->A1dev = cv.take(2 * slot_elems(m) * ta);
   m->part = cv.take((size_t)kMaxBlk * pp * kRP * ta);
+  m->y2 = (double*)cv.take((size_t)pp * kRP * 8);
   m->UL0 = cv.take((size_t)n * ta);
   m->VL0 = cv.take((size_t)pp * ta);
   m->VLt0 = cv.take((size_t)pp * ta);
@@ -222,6 +224,7 @@ void run_iteration(godec_mse* m, const char* a1_base) {
     a.Vnew = (char*)m->V + ((size_t)i * 2 + (vc ^ 1)) * vsz;
     a.A1 = a1_base + (size_t)i * vsz;
     a.part = m->part;
+    a.y2 = m->y2;
     launch_mse_label(L, m->f64, a);
     m->vcur[i] = vc ^ 1;
     m->inited[i] = 1;

@@ -12,8 +12,9 @@
 //
 // The label update (q = 0 bilateral random projection with A2 = Y1) is
 //   km_gram   Y2 partials: per block, sum over its rows of N_row^T (N_row A1)
-//   km_orth   Y2 = the partials added in block order (FP64), then two
-//             Cholesky QR rounds with an FP64 Gram: Q = orth(Y2)
+//   km_reduce Y2 = the partials added in block order (FP64), a thread per
+//             entry of Y2
+//   km_orth   two Cholesky QR rounds with an FP64 Gram: Q = orth(Y2)
 //   km_update U_row = N_row Q, E_row = N_row - U_row Q^T
 // so that L^i_{Omega_i} = N Q Q^T = Y1 (A2^T Y1)^{-1} Y2^T.
 //
@@ -175,20 +176,37 @@ __device__ void mse_chol_round(double* Y, int r, double tau, int* act, double* g
   __syncthreads();
 }
 
-// Q = orth(Y2) with Y2 the block partials added in block order; one block.
+// Y2 = the block partials added in ascending block order (FP64); thread e
+// owns entry e and keeps 16 partials in flight.
 template <typename T, int PP>
-__global__ __launch_bounds__(256) void km_orth(const T* __restrict__ part, int nblk, int r,
+__global__ __launch_bounds__(256) void km_reduce(const T* __restrict__ part, int nblk,
+                                                 double* __restrict__ y2) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= PP * kMseRP) return;
+  constexpr int F = 16;
+  double s = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += F) {
+    T v[F];
+#pragma unroll
+    for (int j = 0; j < F; ++j)
+      v[j] = (b0 + j < nblk) ? part[(int64_t)(b0 + j) * PP * kMseRP + e] : T(0);
+#pragma unroll
+    for (int j = 0; j < F; ++j)
+      if (b0 + j < nblk) s += (double)v[j];
+  }
+  y2[e] = s;
+}
+
+// Q = orth(Y2); one block.
+template <typename T, int PP>
+__global__ __launch_bounds__(256) void km_orth(const double* __restrict__ y2, int r,
                                                T* __restrict__ Q) {
   __shared__ double Y[PP * kMseRP];
   __shared__ double red[4 * kMseRP * kMseRP];
   __shared__ double gsh[kMseRP * kMseRP];
   __shared__ int act[kMseRP];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PP * kMseRP; e += 256) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += (double)part[(int64_t)b * PP * kMseRP + e];
-    Y[e] = s;
-  }
+  for (int e = tid; e < PP * kMseRP; e += 256) Y[e] = y2[e];
   if (tid < kMseRP) act[tid] = tid < r ? 1 : 0;
   __syncthreads();
   const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
@@ -336,8 +354,10 @@ static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
                          (const T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt, a.rows,
                          a.nrows, a.p, a.first, (const T*)a.U, (const T*)a.Vold,
                          (const T*)a.A1, (T*)a.part);
+      hipLaunchKernelGGL((km_reduce<T, 64 * S>), dim3((64 * S * kMseRP + 255) / 256),
+                         dim3(256), 0, L.stream, (const T*)a.part, a.nblk, a.y2);
       hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(256), 0, L.stream,
-                         (const T*)a.part, a.nblk, a.r, (T*)a.Vnew);
+                         (const double*)a.y2, a.r, (T*)a.Vnew);
       hipLaunchKernelGGL((km_update<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
                          (T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt, a.rows,
                          a.nrows, a.p, a.first, (T*)a.U, (const T*)a.Vold, (const T*)a.Vnew);
