@@ -480,7 +480,7 @@ struct MseLabelArgs {
   int S;                    // columns per lane: p <= 64 S, S in {1, 2, 4, 8}
   int first;                // the label still holds its initial value
   int r;                    // the label's rank bound (<= 8)
-  int nblk;                 // blocks of the two row passes
+  int nblk;                 // blocks of the Y2 row pass (one partial each)
   void* U;                  // nrows x 8 (read, then overwritten)
   const void* Vold;         // 64 S x 8 current basis
   void* Vnew;               // 64 S x 8 new basis (output)

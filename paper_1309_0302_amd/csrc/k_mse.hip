@@ -58,59 +58,111 @@ __device__ __forceinline__ void mse_load_n(const T* __restrict__ E, int64_t lde,
   }
 }
 
+// Rows of a wavefront are processed kMseGroup at a time: the loads of a
+// group are all issued before any of its arithmetic, so a wavefront waits
+// for one memory round trip per group instead of one per row.  Groups keep
+// the rows in their order, so every sum is added in the same order.
+constexpr int kMseGroup = 2;
+
 // Partial sums of Y2 = N^T (N A1) over the block's rows (rows j = wave
 // index + 4 blk, stepping by 4 gridDim.x); written to part[blockIdx.x] as
 // p_pad x 8.  Each wavefront accumulates its rows in order, then the block
-// adds its four wavefronts in order.
-template <typename T, int S>
+// adds its four wavefronts in order.  A1 and V live in LDS, transposed
+// (entry [t][c]), so lane reads are consecutive.
+template <typename T, int S, bool FIRST>
 __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t lde,
                                                const T* __restrict__ X, int64_t ldx,
                                                const T* __restrict__ cnt,
                                                const int64_t* __restrict__ rows, int64_t nrows,
-                                               int64_t p, int first, const T* __restrict__ U,
+                                               int64_t p, const T* __restrict__ U,
                                                const T* __restrict__ V,
                                                const T* __restrict__ A1,
                                                T* __restrict__ part) {
   constexpr int PP = 64 * S;
-  __shared__ T red[kMseWaves][PP * kMseRP];
+  constexpr int G = kMseGroup;
+  constexpr bool first = FIRST;
+  // the panels during the row loop, then the four wavefronts' sums
+  __shared__ T lds[kMseWaves * PP * kMseRP];
+  T* at = lds;                   // A1^T: kMseRP x PP
+  T* vt = lds + PP * kMseRP;     // V^T
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T a[S][kMseRP], v[S][kMseRP], acc[S][kMseRP];
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int t = 0; t < kMseRP; ++t) {
-      const int col = lane + 64 * s;
-      a[s][t] = A1[col * kMseRP + t];
-      v[s][t] = first ? T(0) : V[col * kMseRP + t];
-      acc[s][t] = T(0);
-    }
-  for (int64_t j = (int64_t)blockIdx.x * kMseWaves + wave; j < nrows;
-       j += (int64_t)gridDim.x * kMseWaves) {
-    T nrow[S];
-    mse_load_n<T, S>(E, lde, X, ldx, cnt, rows[j], p, first, U + j * kMseRP, v, lane, nrow);
-    T w[kMseRP];
-#pragma unroll
-    for (int t = 0; t < kMseRP; ++t) {
-      T d = T(0);
-#pragma unroll
-      for (int s = 0; s < S; ++s) d = fma_t(nrow[s], a[s][t], d);
-      w[t] = wave_sum(d);
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int t = 0; t < kMseRP; ++t) acc[s][t] = fma_t(nrow[s], w[t], acc[s][t]);
+  for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
+    const int c = e / kMseRP, t = e % kMseRP;
+    at[t * PP + c] = A1[e];
+    vt[t * PP + c] = first ? T(0) : V[e];
   }
+  __syncthreads();
+  T acc[S][kMseRP];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int t = 0; t < kMseRP; ++t) red[wave][(lane + 64 * s) * kMseRP + t] = acc[s][t];
+    for (int t = 0; t < kMseRP; ++t) acc[s][t] = T(0);
+  const int64_t stride = (int64_t)gridDim.x * kMseWaves;
+  for (int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave; j0 < nrows; j0 += G * stride) {
+    // ---- loads of the group (rows j0, j0 + stride, ...) ----
+    T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+      const int64_t j = j0 + h * stride;
+      const bool rv = j < nrows;   // wavefront-uniform
+      const int64_t g = rv ? rows[j] : 0;
+      c[h] = (first && rv) ? cnt[g] : T(0);
+      if constexpr (!FIRST) {
+#pragma unroll
+        for (int t = 0; t < kMseRP; ++t) u[h][t] = rv ? U[j * kMseRP + t] : T(0);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int64_t col = lane + 64 * s;
+        const bool ok = rv && col < p;
+        e[h][s] = ok ? E[g * lde + col] : T(0);
+        if constexpr (FIRST) xl[h][s] = ok ? X[g * ldx + col] : T(0);
+      }
+    }
+    // ---- N rows, then N A1 and the accumulation, row by row ----
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+      if (j0 + h * stride >= nrows) break;   // wavefront-uniform
+      T nrow[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int col = lane + 64 * s;
+        T l = T(0);
+        if constexpr (FIRST) {
+          l = (col < p && c[h] > T(0)) ? xl[h][s] / c[h] : T(0);
+        } else {
+#pragma unroll
+          for (int t = 0; t < kMseRP; ++t) l = fma_t(u[h][t], vt[t * PP + col], l);
+        }
+        nrow[s] = e[h][s] + l;
+      }
+      T w[kMseRP];
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) {
+        T d = T(0);
+#pragma unroll
+        for (int s = 0; s < S; ++s) d = fma_t(nrow[s], at[t * PP + lane + 64 * s], d);
+        w[t] = wave_sum(d);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int t = 0; t < kMseRP; ++t) acc[s][t] = fma_t(nrow[s], w[t], acc[s][t]);
+    }
+  }
+  __syncthreads();   // the panels are no longer read
+  T* red = lds;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t)
+      red[wave * PP * kMseRP + (lane + 64 * s) * kMseRP + t] = acc[s][t];
   __syncthreads();
   T* out = part + (int64_t)blockIdx.x * PP * kMseRP;
   for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
-    T sum = red[0][e];
+    T sum = red[e];
 #pragma unroll
-    for (int w = 1; w < kMseWaves; ++w) sum += red[w][e];
+    for (int w = 1; w < kMseWaves; ++w) sum += red[w * PP * kMseRP + e];
     out[e] = sum;
   }
 }
@@ -216,51 +268,93 @@ __global__ __launch_bounds__(256) void km_orth(const double* __restrict__ y2, in
   for (int e = tid; e < PP * kMseRP; e += 256) Q[e] = (T)Y[e];
 }
 
-// U_row = N_row Q and E_row = N_row - U_row Q^T for every row of the label.
-template <typename T, int S>
+// U_row = N_row Q and E_row = N_row - U_row Q^T for every row of the label,
+// kMseGroup rows of a wavefront at a time (V in LDS, transposed; Q in
+// registers).
+template <typename T, int S, bool FIRST>
 __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
                                                  const T* __restrict__ X, int64_t ldx,
                                                  const T* __restrict__ cnt,
                                                  const int64_t* __restrict__ rows,
-                                                 int64_t nrows, int64_t p, int first,
+                                                 int64_t nrows, int64_t p,
                                                  T* __restrict__ U, const T* __restrict__ V,
                                                  const T* __restrict__ Q) {
+  constexpr int PP = 64 * S;
+  constexpr int G = kMseGroup;
+  __shared__ T vt[kMseRP * PP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T v[S][kMseRP], qq[S][kMseRP];
+  for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
+    const int c = e / kMseRP, t = e % kMseRP;
+    vt[t * PP + c] = FIRST ? T(0) : V[e];
+  }
+  T qq[S][kMseRP];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int t = 0; t < kMseRP; ++t) {
-      const int col = lane + 64 * s;
-      v[s][t] = first ? T(0) : V[col * kMseRP + t];
-      qq[s][t] = Q[col * kMseRP + t];
+    for (int t = 0; t < kMseRP; ++t) qq[s][t] = Q[(lane + 64 * s) * kMseRP + t];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kMseWaves;
+  for (int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave; j0 < nrows; j0 += G * stride) {
+    T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
+    int64_t gg[G];
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+      const int64_t j = j0 + h * stride;
+      const bool rv = j < nrows;   // wavefront-uniform
+      const int64_t g = rv ? rows[j] : 0;
+      gg[h] = g;
+      c[h] = (FIRST && rv) ? cnt[g] : T(0);
+      if constexpr (!FIRST) {
+#pragma unroll
+        for (int t = 0; t < kMseRP; ++t) u[h][t] = rv ? U[j * kMseRP + t] : T(0);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int64_t col = lane + 64 * s;
+        const bool ok = rv && col < p;
+        e[h][s] = ok ? E[g * lde + col] : T(0);
+        if constexpr (FIRST) xl[h][s] = ok ? X[g * ldx + col] : T(0);
+      }
     }
-  for (int64_t j = (int64_t)blockIdx.x * kMseWaves + wave; j < nrows;
-       j += (int64_t)gridDim.x * kMseWaves) {
-    const int64_t g = rows[j];
-    T nrow[S];
-    mse_load_n<T, S>(E, lde, X, ldx, cnt, g, p, first, U + j * kMseRP, v, lane, nrow);
-    T w[kMseRP];
 #pragma unroll
-    for (int t = 0; t < kMseRP; ++t) {
-      T d = T(0);
+    for (int h = 0; h < G; ++h) {
+      const int64_t j = j0 + h * stride;
+      if (j >= nrows) break;   // wavefront-uniform
+      T nrow[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) d = fma_t(nrow[s], qq[s][t], d);
-      w[t] = wave_sum(d);
+      for (int s = 0; s < S; ++s) {
+        const int col = lane + 64 * s;
+        T l = T(0);
+        if constexpr (FIRST) {
+          l = (col < p && c[h] > T(0)) ? xl[h][s] / c[h] : T(0);
+        } else {
+#pragma unroll
+          for (int t = 0; t < kMseRP; ++t) l = fma_t(u[h][t], vt[t * PP + col], l);
+        }
+        nrow[s] = e[h][s] + l;
+      }
+      T w[kMseRP];
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) {
+        T d = T(0);
+#pragma unroll
+        for (int s = 0; s < S; ++s) d = fma_t(nrow[s], qq[s][t], d);
+        w[t] = wave_sum(d);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int64_t col = lane + 64 * s;
+        T l = T(0);
+#pragma unroll
+        for (int t = 0; t < kMseRP; ++t) l = fma_t(w[t], qq[s][t], l);
+        if (col < p) E[gg[h] * lde + col] = nrow[s] - l;
+      }
+      // every lane holds w; lanes 0..7 store the row of U (its loads are done)
+      T wl = w[0];
+#pragma unroll
+      for (int t = 1; t < kMseRP; ++t) wl = (lane == t) ? w[t] : wl;
+      if (lane < kMseRP) U[j * kMseRP + lane] = wl;
     }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int64_t col = lane + 64 * s;
-      T l = T(0);
-#pragma unroll
-      for (int t = 0; t < kMseRP; ++t) l = fma_t(w[t], qq[s][t], l);
-      if (col < p) E[g * lde + col] = nrow[s] - l;
-    }
-    // every lane holds w; lanes 0..7 store the row of U (after the loads above)
-    T wl = w[0];
-#pragma unroll
-    for (int t = 1; t < kMseRP; ++t) wl = (lane == t) ? w[t] : wl;
-    if (lane < kMseRP) U[j * kMseRP + lane] = wl;
   }
 }
 
@@ -350,17 +444,33 @@ static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
     // FP64 rows are limited to 256 columns (S <= 4): three 8-wide FP64
     // panels of 8 columns per lane fill the register file
     if constexpr (!(sizeof(T) == 8 && S == 8)) {
-      hipLaunchKernelGGL((km_gram<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
-                         (const T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt, a.rows,
-                         a.nrows, a.p, a.first, (const T*)a.U, (const T*)a.Vold,
-                         (const T*)a.A1, (T*)a.part);
+      if (a.first)
+        hipLaunchKernelGGL((km_gram<T, S, true>), dim3((unsigned)a.nblk), dim3(256), 0,
+                           L.stream, (const T*)a.E, a.lde, (const T*)a.X, a.ldx,
+                           (const T*)a.cnt, a.rows, a.nrows, a.p, (const T*)a.U,
+                           (const T*)a.Vold, (const T*)a.A1, (T*)a.part);
+      else
+        hipLaunchKernelGGL((km_gram<T, S, false>), dim3((unsigned)a.nblk), dim3(256), 0,
+                           L.stream, (const T*)a.E, a.lde, (const T*)a.X, a.ldx,
+                           (const T*)a.cnt, a.rows, a.nrows, a.p, (const T*)a.U,
+                           (const T*)a.Vold, (const T*)a.A1, (T*)a.part);
       hipLaunchKernelGGL((km_reduce<T, 64 * S>), dim3((64 * S * kMseRP + 255) / 256),
                          dim3(256), 0, L.stream, (const T*)a.part, a.nblk, a.y2);
       hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(256), 0, L.stream,
                          (const double*)a.y2, a.r, (T*)a.Vnew);
-      hipLaunchKernelGGL((km_update<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
-                         (T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt, a.rows,
-                         a.nrows, a.p, a.first, (T*)a.U, (const T*)a.Vold, (const T*)a.Vnew);
+      // the update writes no partials: a block per 16 rows
+      int64_t nbu = (a.nrows + 15) / 16;
+      nbu = nbu < 1 ? 1 : (nbu > (int64_t)L.num_cu * 8 ? (int64_t)L.num_cu * 8 : nbu);
+      if (a.first)
+        hipLaunchKernelGGL((km_update<T, S, true>), dim3((unsigned)nbu), dim3(256), 0,
+                           L.stream, (T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt,
+                           a.rows, a.nrows, a.p, (T*)a.U, (const T*)a.Vold,
+                           (const T*)a.Vnew);
+      else
+        hipLaunchKernelGGL((km_update<T, S, false>), dim3((unsigned)nbu), dim3(256), 0,
+                           L.stream, (T*)a.E, a.lde, (const T*)a.X, a.ldx, (const T*)a.cnt,
+                           a.rows, a.nrows, a.p, (T*)a.U, (const T*)a.Vold,
+                           (const T*)a.Vnew);
     }
   });
 }
