@@ -29,7 +29,8 @@ namespace {
 
 constexpr int kRP = 8;           // padded rank of every label
 constexpr int kChunk = 4;        // iterations whose A1 draws are staged together
-constexpr int kMaxBlk = 128;     // blocks of a label's row passes
+constexpr int kMaxBlk = 128;     // blocks of a label's Y2 row pass
+constexpr int kY2Split = 8;      // ranges of block partials (km_reduce's kMseSplit)
 
 }  // namespace
 
@@ -52,7 +53,7 @@ struct godec_mse {
   void* V = nullptr;               // k x 2 x pp x 8
   void* A1dev = nullptr;           // 2 x kChunk x k x pp x 8
   void* part = nullptr;            // kMaxBlk x pp x 8
-  double* y2 = nullptr;            // pp x 8 (FP64)
+  double* y2 = nullptr;            // kY2Split x pp x 8 (FP64 partial sums)
   void *UL0, *VL0, *VLt0;          // zero factors for the selection
   SelPlan* plan[2];
   unsigned long long* hist;
@@ -100,7 +101,7 @@ size_t carve_mse(godec_mse* m, void* base) {
   m->V = cv.take((size_t)m->k * 2 * pp * kRP * ta);
   m->A1dev = cv.take(2 * slot_elems(m) * ta);
   m->part = cv.take((size_t)kMaxBlk * pp * kRP * ta);
-  m->y2 = (double*)cv.take((size_t)pp * kRP * 8);
+  m->y2 = (double*)cv.take((size_t)kY2Split * pp * kRP * 8);
   m->UL0 = cv.take((size_t)n * ta);
   m->VL0 = cv.take((size_t)pp * ta);
   m->VLt0 = cv.take((size_t)pp * ta);

@@ -12,8 +12,8 @@
 //
 // The label update (q = 0 bilateral random projection with A2 = Y1) is
 //   km_gram   Y2 partials: per block, sum over its rows of N_row^T (N_row A1)
-//   km_reduce Y2 = the partials added in block order (FP64), a thread per
-//             entry of Y2
+//   km_reduce Y2 = the partials added in two fixed-order stages (FP64), a
+//             thread per entry of Y2 and range of partials
 //   km_orth   two Cholesky QR rounds with an FP64 Gram: Q = orth(Y2)
 //   km_update U_row = N_row Q, E_row = N_row - U_row Q^T
 // so that L^i_{Omega_i} = N Q Q^T = Y1 (A2^T Y1)^{-1} Y2^T.
@@ -170,83 +170,128 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
 // One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS): Gram in a
 // fixed order, Cholesky with the dependent-column rule (a pivot at most
 // tau * G_jj marks column j dependent: zero row of R, zero column of the
-// result), Y <- Y R^{-1}.  `act` holds the columns still in use.
+// result), Y <- Y R^{-1}.  `act` holds the columns still in use.  Every
+// loop over the 8 columns is unrolled so that all small arrays stay in
+// registers.
 template <int PP>
-__device__ void mse_chol_round(double* Y, int r, double tau, int* act, double* gsh,
+__device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int* act, double* gsh,
                                double* red) {
+  constexpr int R8 = kMseRP;
+  constexpr int NE = R8 * (R8 + 1) / 2;   // entries a <= b
   const int tid = threadIdx.x;
-  // Gram G[a][b], a <= b: thread-local sums over rows tid, tid + 256, ...
-  for (int ab = 0; ab < kMseRP * kMseRP; ++ab) {
-    const int a_ = ab / kMseRP, b_ = ab % kMseRP;
-    double g = 0.0;
-    if (a_ <= b_ && a_ < r && b_ < r)
-      for (int c = tid; c < PP; c += 256) g = fma(Y[c * kMseRP + a_], Y[c * kMseRP + b_], g);
-    g = wave_sum(g);
-    if ((tid & 63) == 0) red[(tid >> 6) * kMseRP * kMseRP + ab] = g;
+  // Gram G[a][b], a <= b: thread-local sums over rows tid, tid + 256, ...,
+  // then a wavefront sum, then the four wavefronts in order
+  double g[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) g[q] = 0.0;
+  for (int c = tid; c < PP; c += 256) {
+    double y[R8];
+#pragma unroll
+    for (int t = 0; t < R8; ++t) y[t] = Y[c * R8 + t];
+    int q = 0;
+#pragma unroll
+    for (int a_ = 0; a_ < R8; ++a_)
+#pragma unroll
+      for (int b_ = a_; b_ < R8; ++b_, ++q)
+        if (a_ < r && b_ < r) g[q] = fma(y[a_], y[b_], g[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    const double v = wave_sum(g[q]);
+    if ((tid & 63) == 0) red[(tid >> 6) * NE + q] = v;
   }
   __syncthreads();
   if (tid == 0) {
-    double G[kMseRP][kMseRP], R[kMseRP][kMseRP];
-    for (int a_ = 0; a_ < kMseRP; ++a_)
-      for (int b_ = 0; b_ < kMseRP; ++b_) {
-        const int lo = a_ < b_ ? a_ : b_, hi = a_ < b_ ? b_ : a_;
-        const int ab = lo * kMseRP + hi;
-        G[a_][b_] = red[ab] + red[kMseRP * kMseRP + ab] + red[2 * kMseRP * kMseRP + ab] +
-                    red[3 * kMseRP * kMseRP + ab];
-        R[a_][b_] = 0.0;
+    // packed upper triangle, entry (a, b) at tri(a, b); G becomes R in place
+    // (row j of R needs only rows l < j of R and row j of G)
+    auto tri = [](int a_, int b_) { return a_ * R8 - a_ * (a_ - 1) / 2 + (b_ - a_); };
+    double T[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) T[q] = red[q] + red[NE + q] + red[2 * NE + q] + red[3 * NE + q];
+    int am = 0;
+#pragma unroll
+    for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
+#pragma unroll
+    for (int j = 0; j < R8; ++j) {
+      const double gjj = T[tri(j, j)];
+      double d = gjj;
+#pragma unroll
+      for (int l = 0; l < j; ++l) d -= T[tri(l, j)] * T[tri(l, j)];
+      const bool on = j < r && ((am >> j) & 1) && (d > tau * gjj) && (gjj > 0.0);
+      if (!on) {
+        am &= ~(1 << j);
+#pragma unroll
+        for (int b_ = j; b_ < R8; ++b_) T[tri(j, b_)] = 0.0;
+        continue;
       }
-    for (int j = 0; j < kMseRP; ++j) {
-      if (j >= r || !act[j]) { act[j] = 0; continue; }
-      double d = G[j][j];
-      for (int l = 0; l < j; ++l) d -= R[l][j] * R[l][j];
-      if (!(d > tau * G[j][j]) || !(G[j][j] > 0.0)) { act[j] = 0; continue; }
       const double rjj = sqrt(d);
-      R[j][j] = rjj;
-      for (int b_ = j + 1; b_ < kMseRP; ++b_) {
-        double s = G[j][b_];
-        for (int l = 0; l < j; ++l) s -= R[l][j] * R[l][b_];
-        R[j][b_] = s / rjj;
+#pragma unroll
+      for (int b_ = j + 1; b_ < R8; ++b_) {
+        double sv = T[tri(j, b_)];
+#pragma unroll
+        for (int l = 0; l < j; ++l) sv -= T[tri(l, j)] * T[tri(l, b_)];
+        T[tri(j, b_)] = sv / rjj;
       }
+      T[tri(j, j)] = rjj;
     }
-    for (int a_ = 0; a_ < kMseRP; ++a_)
-      for (int b_ = 0; b_ < kMseRP; ++b_) gsh[a_ * kMseRP + b_] = R[a_][b_];
+#pragma unroll
+    for (int j = 0; j < R8; ++j) act[j] = (am >> j) & 1;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) gsh[q] = T[q];
   }
   __syncthreads();
   // Y <- Y R^{-1} on the active columns (forward substitution per row)
+  auto tri = [](int a_, int b_) { return a_ * R8 - a_ * (a_ - 1) / 2 + (b_ - a_); };
+  int am = 0;
+#pragma unroll
+  for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
+  double rr[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) rr[q] = gsh[q];
   for (int c = tid; c < PP; c += 256) {
-    double y[kMseRP], q[kMseRP];
-    for (int t = 0; t < kMseRP; ++t) y[t] = Y[c * kMseRP + t];
-    for (int j = 0; j < kMseRP; ++j) {
-      if (!act[j]) { q[j] = 0.0; continue; }
+    double y[R8], qv[R8];
+#pragma unroll
+    for (int t = 0; t < R8; ++t) y[t] = Y[c * R8 + t];
+#pragma unroll
+    for (int j = 0; j < R8; ++j) {
+      if (!((am >> j) & 1)) { qv[j] = 0.0; continue; }
       double s = y[j];
+#pragma unroll
       for (int l = 0; l < j; ++l)
-        if (act[l]) s -= q[l] * gsh[l * kMseRP + j];
-      q[j] = s / gsh[j * kMseRP + j];
+        if ((am >> l) & 1) s -= qv[l] * rr[tri(l, j)];
+      qv[j] = s / rr[tri(j, j)];
     }
-    for (int t = 0; t < kMseRP; ++t) Y[c * kMseRP + t] = q[t];
+#pragma unroll
+    for (int t = 0; t < R8; ++t) Y[c * R8 + t] = qv[t];
   }
   __syncthreads();
 }
 
-// Y2 = the block partials added in ascending block order (FP64); thread e
-// owns entry e and keeps 16 partials in flight.
+// Y2 from the block partials in two fixed-order stages: block (x, y) adds
+// the partials of its range y of kMseSplit consecutive ranges in ascending
+// order (a thread per entry, 16 partials in flight) into sub[y]; km_orth
+// then adds sub[0], sub[1], ... in order.
+constexpr int kMseSplit = 8;
 template <typename T, int PP>
 __global__ __launch_bounds__(256) void km_reduce(const T* __restrict__ part, int nblk,
-                                                 double* __restrict__ y2) {
+                                                 double* __restrict__ sub) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= PP * kMseRP) return;
+  const int per = (nblk + kMseSplit - 1) / kMseSplit;
+  const int b0 = blockIdx.y * per;
+  const int b1 = (b0 + per) < nblk ? (b0 + per) : nblk;
   constexpr int F = 16;
   double s = 0.0;
-  for (int b0 = 0; b0 < nblk; b0 += F) {
+  for (int c0 = b0; c0 < b1; c0 += F) {
     T v[F];
 #pragma unroll
     for (int j = 0; j < F; ++j)
-      v[j] = (b0 + j < nblk) ? part[(int64_t)(b0 + j) * PP * kMseRP + e] : T(0);
+      v[j] = (c0 + j < b1) ? part[(int64_t)(c0 + j) * PP * kMseRP + e] : T(0);
 #pragma unroll
     for (int j = 0; j < F; ++j)
-      if (b0 + j < nblk) s += (double)v[j];
+      if (c0 + j < b1) s += (double)v[j];
   }
-  y2[e] = s;
+  sub[(int64_t)blockIdx.y * PP * kMseRP + e] = s;
 }
 
 // Q = orth(Y2); one block.
@@ -258,7 +303,15 @@ __global__ __launch_bounds__(256) void km_orth(const double* __restrict__ y2, in
   __shared__ double gsh[kMseRP * kMseRP];
   __shared__ int act[kMseRP];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PP * kMseRP; e += 256) Y[e] = y2[e];
+  for (int e = tid; e < PP * kMseRP; e += 256) {
+    double v[kMseSplit];
+#pragma unroll
+    for (int y = 0; y < kMseSplit; ++y) v[y] = y2[(int64_t)y * PP * kMseRP + e];
+    double sum = v[0];
+#pragma unroll
+    for (int y = 1; y < kMseSplit; ++y) sum += v[y];
+    Y[e] = sum;
+  }
   if (tid < kMseRP) act[tid] = tid < r ? 1 : 0;
   __syncthreads();
   const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
@@ -454,8 +507,9 @@ static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
                            L.stream, (const T*)a.E, a.lde, (const T*)a.X, a.ldx,
                            (const T*)a.cnt, a.rows, a.nrows, a.p, (const T*)a.U,
                            (const T*)a.Vold, (const T*)a.A1, (T*)a.part);
-      hipLaunchKernelGGL((km_reduce<T, 64 * S>), dim3((64 * S * kMseRP + 255) / 256),
-                         dim3(256), 0, L.stream, (const T*)a.part, a.nblk, a.y2);
+      hipLaunchKernelGGL((km_reduce<T, 64 * S>),
+                         dim3((64 * S * kMseRP + 255) / 256, kMseSplit), dim3(256), 0,
+                         L.stream, (const T*)a.part, a.nblk, a.y2);
       hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(256), 0, L.stream,
                          (const double*)a.y2, a.r, (T*)a.Vnew);
       // the update writes no partials: a block per 16 rows
