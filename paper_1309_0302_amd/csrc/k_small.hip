@@ -104,9 +104,22 @@ __device__ __forceinline__ void chol_prefetch(CholIn<RP>& in, const SmallState* 
     in.b[l] = (acc != nullptr && !reset_acc && lane < RP) ? acc[l * RP + lane] : 0.0;
 }
 
-// One wavefront (lanes 0..63); G is RP x RP row-major in LDS.
+// 1 / sqrt(x) for x > 0 from the hardware estimate and two Newton steps
+// (each roughly doubles the correct bits), within an ulp or two of the
+// correctly rounded value: one short dependent chain where sqrt and a
+// division would be two long ones.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// One wavefront (lanes 0..63); G is RP x RP row-major in LDS, and is
+// overwritten with R (LDS scratch for the broadcast reads of R below).
 template <typename TA, int RP>
-__device__ void wave_chol(const double* G, SmallState* st, double* acc, int reset_acc,
+__device__ void wave_chol(double* G, SmallState* st, double* acc, int reset_acc,
                           int normalise, const CholIn<RP>& in) {
   const int lane = threadIdx.x & 63;
   const bool col = lane < RP;
@@ -127,8 +140,8 @@ __device__ void wave_chol(const double* G, SmallState* st, double* acc, int rese
     const int actk = __builtin_amdgcn_readlane(act, k) && piv > tau * g0k;
     if (lane == k) act = actk;
     if (actk) {
-      const double rkk = sqrt(piv);
-      const double inv = 1.0 / rkk;
+      const double inv = rsqrt_nr(piv);
+      const double rkk = piv * inv;
       const double rkj = lane > k ? g[k] * inv : (lane == k ? rkk : 0.0);
       if (lane == k) rdiag = rkk;
       rcol[k] = rkj;
@@ -150,11 +163,19 @@ __device__ void wave_chol(const double* G, SmallState* st, double* acc, int rese
 #pragma unroll
     for (int i = 0; i < RP; ++i) a[i] = rcol[i];
   } else {
+    // R through LDS (G is no longer needed): every lane reads R[i][l] at the
+    // same address, a broadcast, instead of a readlane pair per term
+    __builtin_amdgcn_wave_barrier();
+    if (col) {
+#pragma unroll
+      for (int i = 0; i < RP; ++i) G[i * RP + lane] = rcol[i];
+    }
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int i = 0; i < RP; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int l = i; l < RP; ++l) s += lane_bcast(rcol[i], l) * in.b[l];
+      for (int l = i; l < RP; ++l) s += G[i * RP + l] * in.b[l];
       a[i] = s;
     }
   }
@@ -178,7 +199,7 @@ __device__ void wave_chol(const double* G, SmallState* st, double* acc, int rese
 }
 
 template <typename TA, int RP>
-__device__ void wave_chol(const double* G, SmallState* st, double* acc, int reset_acc,
+__device__ void wave_chol(double* G, SmallState* st, double* acc, int reset_acc,
                           int normalise) {
   CholIn<RP> in;
   chol_prefetch<RP>(in, st, acc, reset_acc);
