@@ -17,7 +17,7 @@
 
 namespace godec {
 
-constexpr int kSmallThreads = 256;
+constexpr int kSmallThreads = 384;   // the core: one thread per Jacobi item of a round (r = 20: 300)
 
 // Sum of entry e over nparts partial matrices of `stride` doubles, with
 // independent accumulators so the loads overlap.
@@ -378,7 +378,9 @@ __device__ __forceinline__ void rr_pair(int round, int k, int N, int& a, int& b)
 // Parallel over disjoint pairs in each round: the rotations of a round are
 // computed first, then one pass applies them, a thread per 2 x 2 block of A
 // (the column rotation of the block's column pair, then the row rotation of
-// its row pair) and a thread per (row, pair) of V.
+// its row pair) and a thread per (row, pair) of V.  The rotation itself is
+// one short FP64 chain (reciprocal square roots refined by Newton steps,
+// thresholds compared on squares): the rounds are latency-bound.
 template <int RP>
 __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
   constexpr int LD = RP + 1;
@@ -387,6 +389,12 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
   constexpr int NBLK = NP * NP;
   __shared__ int pq[2 * NP];
   (void)n;
+  auto pos = [](int i, int round) {
+    if (i == 0) return 0;
+    int x = i - 1 + round;
+    if (x >= N - 1) x -= N - 1;
+    return 1 + x;
+  };
   for (int sweep = 0; sweep < 40; ++sweep) {
     int nrot = 0, nbig = 0;   // wave 0's counts (every pair lives in wave 0)
     for (int round = 0; round < N - 1; ++round) {
@@ -395,28 +403,24 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
         bool did = false, big = false;
         if (k < NP) {
           // circle method: position i plays at 0 (fixed) or 1 + (i - 1 + round) mod (N - 1)
-          auto pos = [&](int i) {
-            if (i == 0) return 0;
-            int x = i - 1 + round;
-            if (x >= N - 1) x -= N - 1;
-            return 1 + x;
-          };
-          int p = pos(k), q = pos(N - 1 - k);
+          int p = pos(k, round), q = pos(N - 1 - k, round);
           if (p > q) { const int t = p; p = q; q = t; }
           double c = 1.0, sn = 0.0;
           if (q < RP) {
             const double apq = A[p * LD + q];
             const double app = A[p * LD + p], aqq = A[q * LD + q];
-            const double scale = sqrt(fabs(app * aqq));
-            if (fabs(apq) > kJacobiTol * scale && apq != 0.0) {
+            // |a_pq| > tol sqrt(|a_pp a_qq|), compared on squares
+            const double prod = fabs(app * aqq), apq2 = apq * apq;
+            if (apq2 > kJacobiTol * kJacobiTol * prod && apq != 0.0) {
               // tan of the rotation t = sgn(d) h / (|d| + r), d = a_qq - a_pp,
               // h = 2 a_pq, r = hypot(d, h); with w = sqrt(2 r (r + |d|)):
               // c = (r + |d|) / w, s = sgn(d) h / w.
               const double d = aqq - app, h = 2.0 * apq;
               const double mx = fmax(fabs(d), fabs(h));
               if (mx > 0x1p-450 && mx < 0x1p450) {
-                const double r = sqrt(d * d + h * h);
-                const double iw = 1.0 / sqrt(2.0 * r * (r + fabs(d)));
+                const double r2 = d * d + h * h;
+                const double r = r2 * rsqrt_nr(r2);
+                const double iw = rsqrt_nr(2.0 * r * (r + fabs(d)));
                 c = (r + fabs(d)) * iw;
                 sn = (d >= 0.0 ? h : -h) * iw;
               } else {
@@ -426,7 +430,7 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
                 sn = t * c;
               }
               did = true;
-              big = fabs(apq) > kJacobiQuad * scale;
+              big = apq2 > kJacobiQuad * kJacobiQuad * prod;
             }
           }
           cs[2 * k + 0] = c;
@@ -439,34 +443,7 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
       }
       __syncthreads();
       for (int e = threadIdx.x; e < NBLK + RP * NP; e += blockDim.x) {
-        if (e < NBLK) {
-          // A <- J^T A J on the block (row pair k1) x (column pair k2)
-          const int k1 = e / NP, k2 = e % NP;
-          const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1];
-          const double c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
-          if (s1 == 0.0 && s2 == 0.0) continue;
-          const int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1];
-          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
-          const bool rq = q1 < RP, cq = q2 < RP;   // the partner may be the padding index
-          double a = A[p1 * LD + p2];
-          double b = cq ? A[p1 * LD + q2] : 0.0;
-          double cc = rq ? A[q1 * LD + p2] : 0.0;
-          double d = (rq && cq) ? A[q1 * LD + q2] : 0.0;
-          if (s2 != 0.0) {
-            const double a2 = c2 * a - s2 * b, b2 = s2 * a + c2 * b;
-            const double c3 = c2 * cc - s2 * d, d2 = s2 * cc + c2 * d;
-            a = a2; b = b2; cc = c3; d = d2;
-          }
-          if (s1 != 0.0) {
-            const double a2 = c1 * a - s1 * cc, c3 = s1 * a + c1 * cc;
-            const double b2 = c1 * b - s1 * d, d2 = s1 * b + c1 * d;
-            a = a2; cc = c3; b = b2; d = d2;
-          }
-          A[p1 * LD + p2] = a;
-          if (cq) A[p1 * LD + q2] = b;
-          if (rq) A[q1 * LD + p2] = cc;
-          if (rq && cq) A[q1 * LD + q2] = d;
-        } else {
+        if (e >= NBLK) {
           // V <- V J
           const int f = e - NBLK;
           const int i = f / NP, k = f % NP;
@@ -476,7 +453,34 @@ __device__ void jacobi_eig(double* A, double* V, int n, double* cs, int* rot) {
           const double vip = V[i * LD + p], viq = V[i * LD + q];
           V[i * LD + p] = c * vip - sn * viq;
           V[i * LD + q] = sn * vip + c * viq;
+          continue;
         }
+        // A <- J^T A J on the block (row pair k1) x (column pair k2)
+        const int k1 = e / NP, k2 = e % NP;
+        const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1];
+        const double c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1];
+        const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+        const bool rq = q1 < RP, cq = q2 < RP;   // the partner may be the padding index
+        double a = A[p1 * LD + p2];
+        double b = cq ? A[p1 * LD + q2] : 0.0;
+        double cc = rq ? A[q1 * LD + p2] : 0.0;
+        double d = (rq && cq) ? A[q1 * LD + q2] : 0.0;
+        if (s2 != 0.0) {
+          const double a2 = c2 * a - s2 * b, b2 = s2 * a + c2 * b;
+          const double c3 = c2 * cc - s2 * d, d2 = s2 * cc + c2 * d;
+          a = a2; b = b2; cc = c3; d = d2;
+        }
+        if (s1 != 0.0) {
+          const double a2 = c1 * a - s1 * cc, c3 = s1 * a + c1 * cc;
+          const double b2 = c1 * b - s1 * d, d2 = s1 * b + c1 * d;
+          a = a2; cc = c3; b = b2; d = d2;
+        }
+        A[p1 * LD + p2] = a;
+        if (cq) A[p1 * LD + q2] = b;
+        if (rq) A[q1 * LD + p2] = cc;
+        if (rq && cq) A[q1 * LD + q2] = d;
       }
       __syncthreads();
     }
@@ -566,7 +570,7 @@ __device__ void core_body(const double* __restrict__ Gpart, int nparts, SmallSta
   __shared__ int rot[2];
   __shared__ int sh_keep;
   __shared__ double red[4];
-  __shared__ double redA[4], redB[4];
+  __shared__ double redA[kSmallThreads / 64], redB[kSmallThreads / 64];
   const int tid = threadIdx.x;
   const int n = st->r_eff;             // active leading columns
   for (int e = tid; e < RP * RP; e += blockDim.x) {
