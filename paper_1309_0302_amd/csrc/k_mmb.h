@@ -72,6 +72,9 @@ __device__ __forceinline__ void mmb_loop_bf16(const uint16_t* __restrict__ D, in
 }
 
 // FP32 form: 8 rows per step; slot s pairs row kk + 4g + s on both operands.
+// A step's 16 MFMAs take about as long as its loads, so the loads of the
+// next step are issued before the MFMAs of the current one (two register
+// buffers).
 __device__ __forceinline__ void mmb_loop_f32(const float* __restrict__ D, int64_t ldd,
                                              int64_t mpad, const float* __restrict__ Wt,
                                              int64_t cw, int64_t k0, int64_t k1, int lane,
@@ -79,16 +82,27 @@ __device__ __forceinline__ void mmb_loop_f32(const float* __restrict__ D, int64_
   const int n = lane & 31, g = lane >> 5;
   const float* pd = D + (4 * g) * ldd + cw + 4 * n;
   const float* pw = Wt + (int64_t)n * mpad + 4 * g;
+  if (k0 >= k1) return;
+  float4 a = *reinterpret_cast<const float4*>(pw + k0);
+  float4 d[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) d[s] = *reinterpret_cast<const float4*>(pd + (k0 + s) * ldd);
   for (int64_t kk = k0; kk < k1; kk += 8) {
-    const float4 a = *reinterpret_cast<const float4*>(pw + kk);
     const float av[4] = {a.x, a.y, a.z, a.w};
+    float4 dc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dc[s] = d[s];
+    if (kk + 8 < k1) {   // uniform
+      a = *reinterpret_cast<const float4*>(pw + kk + 8);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) d[s] = *reinterpret_cast<const float4*>(pd + (kk + 8 + s) * ldd);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const float4 d = *reinterpret_cast<const float4*>(pd + (kk + s) * ldd);
-      acc[0] = mfma_f32(av[s], d.x, acc[0]);
-      acc[1] = mfma_f32(av[s], d.y, acc[1]);
-      acc[2] = mfma_f32(av[s], d.z, acc[2]);
-      acc[3] = mfma_f32(av[s], d.w, acc[3]);
+      acc[0] = mfma_f32(av[s], dc[s].x, acc[0]);
+      acc[1] = mfma_f32(av[s], dc[s].y, acc[1]);
+      acc[2] = mfma_f32(av[s], dc[s].z, acc[2]);
+      acc[3] = mfma_f32(av[s], dc[s].w, acc[3]);
     }
   }
 }
