@@ -121,7 +121,11 @@ __global__ __launch_bounds__(256) void k_mm_a_f32(const float* __restrict__ D, i
   const int64_t c1 = (c0 + KC) < ldd ? (c0 + KC) : ldd;
   const int row = 32 * wave + i;
   u32x4 st[4], sz;
-  f32x16 acc = {};
+  // four independent accumulators (one per slot e of a 16-byte chunk), so
+  // consecutive MFMAs do not wait on each other; added in a fixed order
+  f32x16 acc4[4];
+#pragma unroll
+  for (int a_ = 0; a_ < 4; ++a_) acc4[a_] = f32x16{};
   mma_gload(D, ldd, mpad, Zt, rb, c0, lr, lc, st, sz);
   mma_sstore(tD[0], tZ[0], lr, lc, st, sz);
   __syncthreads();
@@ -136,12 +140,16 @@ __global__ __launch_bounds__(256) void k_mm_a_f32(const float* __restrict__ D, i
       const u32x4 bv = tZ[buf][i * 8 + (ch ^ (i & 7))];
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        acc = mfma_f32(__uint_as_float(av[e]), __uint_as_float(bv[e]), acc);
+        acc4[(4 * q + e) % 4] = mfma_f32(__uint_as_float(av[e]), __uint_as_float(bv[e]),
+                                         acc4[(4 * q + e) % 4]);
     }
     if (more) mma_sstore(tD[buf ^ 1], tZ[buf ^ 1], lr, lc, st, sz);
     __syncthreads();
     buf ^= 1;
   }
+  f32x16 acc = acc4[0];
+#pragma unroll
+  for (int a_ = 1; a_ < 4; ++a_) acc += acc4[a_];
   mma_store_w(Wtpart, mpad, rb + 32 * wave, lane, acc);
 }
 
@@ -217,7 +225,9 @@ __global__ __launch_bounds__(256) void k_soft_mm_a_f32(const float* __restrict__
     for (int c = 0; c < RP; ++c) u[h][c] = r < mpad ? U[r * RP + c] : 0.f;
   }
   u32x4 st[4], sz;
-  f32x16 acc = {};
+  f32x16 acc4[4];   // independent accumulators (as k_mm_a_f32)
+#pragma unroll
+  for (int a_ = 0; a_ < 4; ++a_) acc4[a_] = f32x16{};
   mma_gload(Xp, ldd, mpad, Zt, rb, c0, lr, lc, st, sz);
   soft_load_v<RP>(Vt, c0 + 4 * lc, v);
   soft_chunks<RP>(st, u, v, lam, D, ldd, mpad, rb + lr, c0 + 4 * lc);
@@ -237,7 +247,8 @@ __global__ __launch_bounds__(256) void k_soft_mm_a_f32(const float* __restrict__
       const u32x4 bv = tZ[buf][i * 8 + (ch ^ (i & 7))];
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        acc = mfma_f32(__uint_as_float(av[e]), __uint_as_float(bv[e]), acc);
+        acc4[(4 * q + e) % 4] = mfma_f32(__uint_as_float(av[e]), __uint_as_float(bv[e]),
+                                         acc4[(4 * q + e) % 4]);
     }
     if (more) {
       soft_chunks<RP>(st, u, v, lam, D, ldd, mpad, rb + lr, kk + 32 + 4 * lc);
@@ -246,6 +257,9 @@ __global__ __launch_bounds__(256) void k_soft_mm_a_f32(const float* __restrict__
     __syncthreads();
     buf ^= 1;
   }
+  f32x16 acc = acc4[0];
+#pragma unroll
+  for (int a_ = 1; a_ < 4; ++a_) acc += acc4[a_];
   mma_store_w(Wtpart, mpad, rb + 32 * wave, lane, acc);
 }
 
