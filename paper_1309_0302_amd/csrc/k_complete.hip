@@ -27,12 +27,15 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // One pass over X for the whole fixed-support step.  Tiles of 64 rows x 256
 // columns (tile t: row block t % nrb, column block t / nrb) are walked
 // grid-stride; a thread owns one column and keeps its row of V_L in
-// registers (the row of U_L is the same for the whole block).  For every
-// row of a tile the residuals r = X - (U_L V_L^T) go to LDS; the support
-// entries of that row inside the tile's columns -- the contiguous run
-// [row_ptr[i][cb], row_ptr[i][cb + 1]) of the ascending list -- then take
-// theirs: s_idx, s_val = r, s_x = X, and mark their columns so that the
-// block partials pall / psel sum r^2 off / on the support separately.
+// registers (the row of U_L is the same for the whole block).  The rows of
+// a tile go in chunks of CR: every thread loads its X entries of the chunk
+// together and puts the residuals r = X - (U_L V_L^T) in LDS; then the
+// support entries of the chunk's rows inside the tile's columns -- per row
+// the contiguous run [row_ptr[i][cb], row_ptr[i][cb + 1]) of the ascending
+// list -- are taken by the block in one pass: s_idx, s_val = r, s_x = X, and
+// their columns are marked, so that the block partials pall / psel sum r^2
+// off / on the support separately (off the support in row order per
+// thread).
 constexpr int kNormRows = 64;
 
 template <typename T, int RP>
@@ -46,8 +49,11 @@ __global__ __launch_bounds__(256) void kc_pass(const T* __restrict__ X, int64_t 
                                                T* __restrict__ s_val, T* __restrict__ s_x,
                                                double* __restrict__ pall,
                                                double* __restrict__ psel) {
-  __shared__ T rs[256], xs[256];
-  __shared__ int mk[256];
+  constexpr int CR = sizeof(T) == 4 ? 16 : 8;   // rows per chunk (LDS: 2 x CR x 256 x T)
+  __shared__ T rs[CR][256], xs[CR][256];
+  __shared__ unsigned char mk[CR][256];
+  __shared__ int64_t rstart[CR];
+  __shared__ int rpre[CR + 1];
   __shared__ double red[4];
   double acc = 0.0, accs = 0.0;   // sums of r^2 off and on the support
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -60,37 +66,68 @@ __global__ __launch_bounds__(256) void kc_pass(const T* __restrict__ X, int64_t 
 #pragma unroll
     for (int c = 0; c < RP; ++c) v[c] = live ? VL[j * RP + c] : T(0);
     const int64_t i1 = (i0 + kNormRows) < m ? (i0 + kNormRows) : m;
-    for (int64_t i = i0; i < i1; ++i) {
-      const T* u = UL + i * RP;
-      T l = T(0);
+    for (int64_t c0 = i0; c0 < i1; c0 += CR) {
+      const int nr = (i1 - c0) < CR ? (int)(i1 - c0) : CR;
+      // ---- residuals of the chunk (all X loads in flight together) ----
+      T x[CR];
 #pragma unroll
-      for (int c = 0; c < RP; ++c) l = fma_t(u[c], v[c], l);
-      const T x = live ? X[i * ldx + j] : T(0);
-      const T r = x - l;
-      const int64_t* run = row_ptr + i * (ncb + 1) + cb;
-      const int64_t a = run[0], b = run[1];
-      if (a == b) {   // uniform: no support entry in this row and block
-        if (live) acc = fma((double)r, (double)r, acc);
-        continue;
+      for (int rr = 0; rr < CR; ++rr)
+        x[rr] = (live && rr < nr) ? X[(c0 + rr) * ldx + j] : T(0);
+#pragma unroll
+      for (int rr = 0; rr < CR; ++rr) {
+        if (rr < nr) {
+          const T* u = UL + (c0 + rr) * RP;
+          T l = T(0);
+#pragma unroll
+          for (int c = 0; c < RP; ++c) l = fma_t(u[c], v[c], l);
+          rs[rr][threadIdx.x] = x[rr] - l;
+          xs[rr][threadIdx.x] = x[rr];
+        }
+        mk[rr][threadIdx.x] = 0;
       }
-      rs[threadIdx.x] = r;
-      xs[threadIdx.x] = x;
-      mk[threadIdx.x] = 0;
+      if ((int)threadIdx.x < CR) {
+        const int rr = threadIdx.x;
+        int len = 0;
+        int64_t a = 0;
+        if (rr < nr) {
+          const int64_t* run = row_ptr + (c0 + rr) * (ncb + 1) + cb;
+          a = run[0];
+          len = (int)(run[1] - a);
+        }
+        rstart[rr] = a;
+        rpre[rr + 1] = len;
+      }
       __syncthreads();
-      const int64_t base = i * n;
-      if ((int64_t)threadIdx.x < b - a) {
-        const int64_t e = a + threadIdx.x;
-        const int64_t id = support[e];
-        const int q = (int)(id - base - j0);
-        const T rv = rs[q];
-        s_idx[e] = id;
-        s_val[e] = rv;
-        s_x[e] = xs[q];
-        mk[q] = 1;
+      if (threadIdx.x == 0) {
+        rpre[0] = 0;
+        for (int rr = 0; rr < CR; ++rr) rpre[rr + 1] += rpre[rr];
+      }
+      __syncthreads();
+      // ---- the support entries of the chunk, one pass ----
+      const int tot = rpre[CR];
+      for (int e = threadIdx.x; e < tot; e += 256) {
+        int rr = 0;
+        while (rpre[rr + 1] <= e) ++rr;   // at most CR steps
+        const int64_t ent = rstart[rr] + (e - rpre[rr]);
+        const int64_t id = support[ent];
+        const int q = (int)(id - (c0 + rr) * n - j0);
+        const T rv = rs[rr][q];
+        s_idx[ent] = id;
+        s_val[ent] = rv;
+        s_x[ent] = xs[rr][q];
+        mk[rr][q] = 1;
         accs = fma((double)rv, (double)rv, accs);
       }
       __syncthreads();
-      if (live && !mk[threadIdx.x]) acc = fma((double)r, (double)r, acc);
+      // ---- off the support, in row order ----
+      if (live) {
+        for (int rr = 0; rr < nr; ++rr)
+          if (!mk[rr][threadIdx.x]) {
+            const double r = (double)rs[rr][threadIdx.x];
+            acc = fma(r, r, acc);
+          }
+      }
+      __syncthreads();   // the next chunk overwrites the staging arrays
     }
   }
   double tot = block_sum<T>(acc, red);
