@@ -574,10 +574,13 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
     c->completion = true;
     c->support = opts->support_dev;
     c->support_nnz = opts->support_nnz;
-    if (c->support_nnz > 0) {
-      std::vector<int64_t> h((size_t)c->support_nnz);
-      hipError_t e = hipMemcpy(h.data(), c->support, sizeof(int64_t) * h.size(),
-                               hipMemcpyDeviceToHost);
+    // one copy of the support to the host, on the context's stream: it is
+    // checked, then turned into the run starts below
+    std::vector<int64_t> h((size_t)c->support_nnz);
+    if (!h.empty()) {
+      hipError_t e = hipMemcpyAsync(h.data(), c->support, sizeof(int64_t) * h.size(),
+                                    hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) {
         delete c;
         return fail(GODEC_E_DEVICE, hipGetErrorString(e));
@@ -593,26 +596,17 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
     // entry of row i + 1 (blocked CSR, ncb = ceil(n / 256))
     const int64_t ncb = (n + 255) / 256;
     std::vector<int64_t> rp((size_t)(m * (ncb + 1)), 0);
-    {
-      std::vector<int64_t> h((size_t)c->support_nnz);
-      if (!h.empty()) {
-        hipError_t e = hipMemcpy(h.data(), c->support, sizeof(int64_t) * h.size(),
-                                 hipMemcpyDeviceToHost);
-        if (e != hipSuccess) {
-          delete c;
-          return fail(GODEC_E_DEVICE, hipGetErrorString(e));
-        }
+    size_t pos = 0;
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t cb = 0; cb <= ncb; ++cb) {
+        const int64_t key = cb < ncb ? i * n + cb * 256 : (i + 1) * n;
+        while (pos < h.size() && h[pos] < key) ++pos;
+        rp[(size_t)(i * (ncb + 1) + cb)] = (int64_t)pos;
       }
-      size_t pos = 0;
-      for (int64_t i = 0; i < m; ++i)
-        for (int64_t cb = 0; cb <= ncb; ++cb) {
-          const int64_t key = cb < ncb ? i * n + cb * 256 : (i + 1) * n;
-          while (pos < h.size() && h[pos] < key) ++pos;
-          rp[(size_t)(i * (ncb + 1) + cb)] = (int64_t)pos;
-        }
-    }
-    hipError_t e = hipMemcpy(c->row_ptr, rp.data(), sizeof(int64_t) * rp.size(),
-                             hipMemcpyHostToDevice);
+    // the host table must outlive the copy: wait for it before returning
+    hipError_t e = hipMemcpyAsync(c->row_ptr, rp.data(), sizeof(int64_t) * rp.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
       delete c;
       return fail(GODEC_E_DEVICE, hipGetErrorString(e));
