@@ -457,6 +457,16 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
   a.tie_idx = c->tie_idx;
   a.carry = c->carry;
   a.s2part = c->s2part;
+  // the bf16 copy's old support is restored inside pass 0 (after the chain
+  // has read it, before the new support is written below)
+  const bool restore_in_pass = mixed && !c->completion && !c->f64 && c->iters_done > 0;
+  if (restore_in_pass) {
+    a.r16 = (uint16_t*)c->D16;
+    a.ldd16 = c->ldd;
+    a.ridx = c->s_idx[prev];
+    a.rx = (const float*)c->s_x[prev];
+    a.rplan = c->plan[prev];
+  }
   if (c->prof) {
     a.ev_a = prof_event(c);
     a.ev_b = prof_event(c);
@@ -475,7 +485,7 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
     if (upd_native)
       launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
                       c->plan[prev], kk);
-    if (mixed)
+    if (mixed && !restore_in_pass)
       launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
                       c->plan[prev], kk);
   }

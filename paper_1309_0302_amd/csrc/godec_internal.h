@@ -187,6 +187,14 @@ struct SelectArgs {
   SelCarry* carry;      // persists across iterations
   double* s2part;       // 2 * kSelParts partial sums (pass 0, then compaction)
   hipEvent_t ev_a = nullptr, ev_b = nullptr;  // optional: bracket pass 0
+  // optional (FP32 X only): pass 0 also writes bf16(x) at the entries of the
+  // previous S (index list ridx, X values rx, count rplan->nnz) into this
+  // mpad x ldd16 copy, restoring X there
+  uint16_t* r16 = nullptr;
+  int64_t ldd16 = 0;
+  const int64_t* ridx = nullptr;
+  const float* rx = nullptr;
+  const SelPlan* rplan = nullptr;
 };
 void launch_select(const Launch& L, bool f64, int rp, const SelectArgs& a);
 void launch_transpose_panel(const Launch& L, bool f64, const void* VL, int64_t rows, int rp,

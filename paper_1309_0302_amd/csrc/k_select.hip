@@ -556,7 +556,9 @@ __device__ __forceinline__ PassKeys<T> keys_level0() {
   if (lane == 0) seg_count[seg] = sink.fill < seg_cap ? sink.fill : seg_cap;
 
 // Pass 0: the carried-window pass (steady state) or the full level-0
-// histogram (first iteration); both also sum R^2.
+// histogram (first iteration); both also sum R^2.  With r16, the blocks
+// first restore bf16(X) at the previous S's entries of that copy (scattered
+// 2-byte stores that overlap the pass).
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int64_t ldx,
                                                    const T* __restrict__ UL,
@@ -568,8 +570,36 @@ __global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int6
                                                    T* __restrict__ cand_val,
                                                    T* __restrict__ cand_x,
                                                    unsigned int* __restrict__ seg_count,
-                                                   double* __restrict__ s2part) {
+                                                   double* __restrict__ s2part,
+                                                   uint16_t* __restrict__ r16, int64_t ldd16,
+                                                   const int64_t* __restrict__ ridx,
+                                                   const float* __restrict__ rx,
+                                                   const SelPlan* __restrict__ rplan) {
   GODEC_SEL_SHARED
+  if (r16 != nullptr) {
+    // eight entries per thread in flight at once (one round trip per batch)
+    constexpr int B = 8;
+    const long long cnt = rplan->nnz;
+    const double rn = 1.0 / (double)n;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long e0 = (long long)blockIdx.x * 256 + tid; e0 < cnt; e0 += B * stride) {
+      int64_t id[B];
+      float xv[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const long long e = e0 + b * stride;
+        id[b] = e < cnt ? ridx[e] : -1;
+        xv[b] = e < cnt ? rx[e] : 0.f;
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (id[b] < 0) continue;
+        int64_t i, j;
+        divmod_nn(id[b], n, rn, i, j);
+        r16[i * ldd16 + j] = f32_to_bf16(xv[b]);
+      }
+    }
+  }
   if (plan->mode != SEL_HIST) {
     // k == 0 (S_t = 0): only the objective, sum R^2 over every entry
     const bool vec_ok0 = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
@@ -1606,7 +1636,8 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
         hipLaunchKernelGGL((k_sel_pass0<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
                            (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VLt, a.ldv, a.m,
                            a.n, a.plan, a.hist, a.cand_idx, (T*)a.cand_val, (T*)a.cand_x,
-                           a.seg_count, a.s2part);
+                           a.seg_count, a.s2part, sizeof(T) == 4 ? a.r16 : nullptr, a.ldd16,
+                           a.ridx, a.rx, a.rplan);
         if (a.ev_b) (void)hipEventRecord(a.ev_b, L.stream);
       } else {
         hipLaunchKernelGGL((k_sel_passN<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
