@@ -759,15 +759,30 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
   const int dbits = digit_bits(pbits, KB);
   const int bins = 1 << dbits;
   const int per = (bins + 255) / 256;
-  // sum the replicas (and clear them for the next histogram)
-  for (int e = tid; e < bins; e += 256) {
-    unsigned long long acc = 0;
+  // sum the replicas in replica order (and clear them for the next
+  // histogram); every load of the thread is issued before the first add
+  constexpr int MAXPER = (kHistBins + 255) / 256;
+  {
+    unsigned long long v[MAXPER][kHistRep];
 #pragma unroll
-    for (int r = 0; r < kHistRep; ++r) {
-      acc += hist[r * kHistBins + e];
-      hist[r * kHistBins + e] = 0ull;
+    for (int u = 0; u < MAXPER; ++u) {
+      const int e = tid + 256 * u;
+#pragma unroll
+      for (int r = 0; r < kHistRep; ++r) v[u][r] = e < bins ? hist[r * kHistBins + e] : 0ull;
     }
-    h[e] = acc;
+#pragma unroll
+    for (int u = 0; u < MAXPER; ++u) {
+      const int e = tid + 256 * u;
+      if (e < bins) {
+        unsigned long long acc = 0;
+#pragma unroll
+        for (int r = 0; r < kHistRep; ++r) {
+          acc += v[u][r];
+          hist[r * kHistBins + e] = 0ull;
+        }
+        h[e] = acc;
+      }
+    }
   }
   __syncthreads();
   // thread t owns digits [bins - (t+1)*per, bins - t*per): top digits first
