@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kRP = 8;           // padded rank of every label
 constexpr int kChunk = 4;        // iterations whose A1 draws are staged together
-constexpr int kMaxBlk = 128;     // blocks of a label's Y2 row pass
+constexpr int kMaxBlk = 256;     // blocks of a label's Y2 row pass
 constexpr int kY2Split = 8;      // ranges of block partials (km_reduce's kMseSplit)
 
 }  // namespace
@@ -218,7 +218,7 @@ void run_iteration(godec_mse* m, const char* a1_base) {
     a.S = m->S;
     a.first = m->inited[i] ? 0 : 1;
     a.r = m->ranks[i];
-    a.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBlk, (ni + 63) / 64));
+    a.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBlk, (ni + 31) / 32));
     a.U = (char*)m->U + (size_t)m->lptr[i] * kRP * m->ta;
     const int vc = m->vcur[i];
     a.Vold = (const char*)m->V + ((size_t)i * 2 + vc) * vsz;

@@ -56,6 +56,18 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// 1 / sqrt(x) for x > 0 from the hardware estimate and two Newton steps
+// (each roughly doubles the correct bits), within an ulp or two of the
+// correctly rounded value: one short dependent chain where sqrt and a
+// division would be two long ones.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // q = a / b and r = a % b for 0 <= a < 2^52 and b >= 1, with rb = 1 / b in
 // double precision: the product a * rb is within one of the quotient (its
 // relative error is at most 2^-52), so one correction step makes it exact.

@@ -224,15 +224,19 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
         for (int b_ = j; b_ < R8; ++b_) T[tri(j, b_)] = 0.0;
         continue;
       }
-      const double rjj = sqrt(d);
+      // 1 / r_jj from a Newton-refined reciprocal square root: the rows of R
+      // and the substitution below multiply by it instead of dividing
+      const double ir = rsqrt_nr(d);
+      const double rjj = d * ir;
 #pragma unroll
       for (int b_ = j + 1; b_ < R8; ++b_) {
         double sv = T[tri(j, b_)];
 #pragma unroll
         for (int l = 0; l < j; ++l) sv -= T[tri(l, j)] * T[tri(l, b_)];
-        T[tri(j, b_)] = sv / rjj;
+        T[tri(j, b_)] = sv * ir;
       }
       T[tri(j, j)] = rjj;
+      gsh[NE + j] = ir;
     }
 #pragma unroll
     for (int j = 0; j < R8; ++j) act[j] = (am >> j) & 1;
@@ -245,9 +249,11 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
   int am = 0;
 #pragma unroll
   for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
-  double rr[NE];
+  double rr[NE], rinv[R8];
 #pragma unroll
   for (int q = 0; q < NE; ++q) rr[q] = gsh[q];
+#pragma unroll
+  for (int j = 0; j < R8; ++j) rinv[j] = gsh[NE + j];
   for (int c = tid; c < PP; c += 256) {
     double y[R8], qv[R8];
 #pragma unroll
@@ -259,7 +265,7 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
 #pragma unroll
       for (int l = 0; l < j; ++l)
         if ((am >> l) & 1) s -= qv[l] * rr[tri(l, j)];
-      qv[j] = s / rr[tri(j, j)];
+      qv[j] = s * rinv[j];
     }
 #pragma unroll
     for (int t = 0; t < R8; ++t) Y[c * R8 + t] = qv[t];

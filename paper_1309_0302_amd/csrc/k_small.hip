@@ -104,18 +104,6 @@ __device__ __forceinline__ void chol_prefetch(CholIn<RP>& in, const SmallState* 
     in.b[l] = (acc != nullptr && !reset_acc && lane < RP) ? acc[l * RP + lane] : 0.0;
 }
 
-// 1 / sqrt(x) for x > 0 from the hardware estimate and two Newton steps
-// (each roughly doubles the correct bits), within an ulp or two of the
-// correctly rounded value: one short dependent chain where sqrt and a
-// division would be two long ones.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
-
 // One wavefront (lanes 0..63); G is RP x RP row-major in LDS, and is
 // overwritten with R (LDS scratch for the broadcast reads of R below).
 template <typename TA, int RP>
