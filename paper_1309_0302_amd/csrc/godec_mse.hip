@@ -218,7 +218,10 @@ void run_iteration(godec_mse* m, const char* a1_base) {
     a.S = m->S;
     a.first = m->inited[i] ? 0 : 1;
     a.r = m->ranks[i];
-    a.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBlk, (ni + 31) / 32));
+    // one group of rows per wavefront of the Y2 pass: 32 FP32 or 16 FP64
+    // rows per block
+    const int64_t rpb = m->f64 ? 16 : 32;
+    a.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBlk, (ni + rpb - 1) / rpb));
     a.U = (char*)m->U + (size_t)m->lptr[i] * kRP * m->ta;
     const int vc = m->vcur[i];
     a.Vold = (const char*)m->V + ((size_t)i * 2 + vc) * vsz;

@@ -28,6 +28,51 @@ namespace godec {
 constexpr int kMseRP = 8;          // padded rank of every label
 constexpr int kMseWaves = 4;       // wavefronts per block of the row passes
 
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The eight sums over the wavefront's 64 lanes of the per-lane values
+// d[0..7], returned to every lane in d.  Three halving steps (partners
+// whose lane bit 5, 4, 3 differs exchange the half of their values that
+// the partner keeps), three butterfly steps on the one value left, then
+// every lane reads the eight sums from the lanes that hold them: ten
+// exchanges where eight separate butterflies take 48.  The order of the
+// additions is fixed by the lane indices, so the sums are reproducible.
+template <typename T>
+__device__ __forceinline__ void wave_sum8(T (&d)[kMseRP]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+  T a4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T keep = h5 ? d[i + 4] : d[i];
+    const T give = h5 ? d[i] : d[i + 4];
+    a4[i] = keep + __shfl_xor(give, 32, 64);
+  }
+  T a2[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const T keep = h4 ? a4[i + 2] : a4[i];
+    const T give = h4 ? a4[i] : a4[i + 2];
+    a2[i] = keep + __shfl_xor(give, 16, 64);
+  }
+  T a1 = (h3 ? a2[1] : a2[0]) + __shfl_xor(h3 ? a2[0] : a2[1], 8, 64);
+  a1 += __shfl_xor(a1, 4, 64);
+  a1 += __shfl_xor(a1, 2, 64);
+  a1 += __shfl_xor(a1, 1, 64);
+  // lane 32 b2 + 16 b1 + 8 b0 holds the sum of index 4 b2 + 2 b1 + b0
+#pragma unroll
+  for (int t = 0; t < kMseRP; ++t)
+    d[t] = lane_read(a1, ((t >> 2) << 5) | (((t >> 1) & 1) << 4) | ((t & 1) << 3));
+}
+
 // N_row of label i: E_row + L^i_row, where L^i_row is U_j V^T (updated
 // label) or X_row / cnt_row (initial value of the label).
 template <typename T, int S>
@@ -58,17 +103,25 @@ __device__ __forceinline__ void mse_load_n(const T* __restrict__ E, int64_t lde,
   }
 }
 
-// Rows of a wavefront are processed kMseGroup at a time: the loads of a
-// group are all issued before any of its arithmetic, so a wavefront waits
-// for one memory round trip per group instead of one per row.  Groups keep
-// the rows in their order, so every sum is added in the same order.
-constexpr int kMseGroup = 2;
+// Rows of a wavefront are processed in groups: the loads of a group are all
+// issued before any of its arithmetic, so a wavefront waits for one memory
+// round trip per group instead of one per row.  Groups keep the rows in
+// their order, so every sum is added in the same order.  The Y2 pass takes
+// 8 FP32 (4 FP64) rows per group and the update pass 4; a block of the Y2
+// pass covers kMseWaves groups.
+template <typename T>
+struct MseGroup {
+  static constexpr int gram = sizeof(T) == 4 ? 8 : 4;
+  static constexpr int update = 4;
+};
 
-// Partial sums of Y2 = N^T (N A1) over the block's rows (rows j = wave
-// index + 4 blk, stepping by 4 gridDim.x); written to part[blockIdx.x] as
-// p_pad x 8.  Each wavefront accumulates its rows in order, then the block
-// adds its four wavefronts in order.  A1 and V live in LDS, transposed
-// (entry [t][c]), so lane reads are consecutive.
+// Partial sums of Y2 = N^T (N A1) over the block's rows (group h of
+// wavefront w holds rows j0 + h * stride, j0 = w + 4 blk, stride =
+// 4 gridDim.x); written to part[blockIdx.x] as p_pad x 8.  Each wavefront
+// accumulates its rows in order, then the block adds its four wavefronts in
+// order.  A1 and V live in LDS, transposed (entry [t][c]), so lane reads
+// are consecutive.  The first group's loads are issued before the panels
+// are staged.
 template <typename T, int S, bool FIRST>
 __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t lde,
                                                const T* __restrict__ X, int64_t ldx,
@@ -79,34 +132,22 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
                                                const T* __restrict__ A1,
                                                T* __restrict__ part) {
   constexpr int PP = 64 * S;
-  constexpr int G = kMseGroup;
-  constexpr bool first = FIRST;
+  constexpr int G = MseGroup<T>::gram;
   // the panels during the row loop, then the four wavefronts' sums
   __shared__ T lds[kMseWaves * PP * kMseRP];
   T* at = lds;                   // A1^T: kMseRP x PP
   T* vt = lds + PP * kMseRP;     // V^T
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
-    const int c = e / kMseRP, t = e % kMseRP;
-    at[t * PP + c] = A1[e];
-    vt[t * PP + c] = first ? T(0) : V[e];
-  }
-  __syncthreads();
-  T acc[S][kMseRP];
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int t = 0; t < kMseRP; ++t) acc[s][t] = T(0);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t stride = (int64_t)gridDim.x * kMseWaves;
-  for (int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave; j0 < nrows; j0 += G * stride) {
-    // ---- loads of the group (rows j0, j0 + stride, ...) ----
-    T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
+  T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
+  auto load_group = [&](int64_t j0) {
 #pragma unroll
     for (int h = 0; h < G; ++h) {
       const int64_t j = j0 + h * stride;
       const bool rv = j < nrows;   // wavefront-uniform
       const int64_t g = rv ? rows[j] : 0;
-      c[h] = (first && rv) ? cnt[g] : T(0);
+      c[h] = (FIRST && rv) ? cnt[g] : T(0);
       if constexpr (!FIRST) {
 #pragma unroll
         for (int t = 0; t < kMseRP; ++t) u[h][t] = rv ? U[j * kMseRP + t] : T(0);
@@ -119,6 +160,33 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
         if constexpr (FIRST) xl[h][s] = ok ? X[g * ldx + col] : T(0);
       }
     }
+  };
+  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
+  if (j0 < nrows) load_group(j0);
+  {
+    // every panel load in flight at once, then the transposed LDS stores
+    constexpr int NST = PP * kMseRP / 256;
+    T av[NST], vv[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      av[k] = A1[k * 256 + threadIdx.x];
+      vv[k] = FIRST ? T(0) : V[k * 256 + threadIdx.x];
+    }
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      const int q = k * 256 + threadIdx.x;
+      const int cc = q / kMseRP, t = q % kMseRP;
+      at[t * PP + cc] = av[k];
+      vt[t * PP + cc] = vv[k];
+    }
+  }
+  __syncthreads();
+  T acc[S][kMseRP];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) acc[s][t] = T(0);
+  for (; j0 < nrows; j0 += G * stride) {
     // ---- N rows, then N A1 and the accumulation, row by row ----
 #pragma unroll
     for (int h = 0; h < G; ++h) {
@@ -142,13 +210,15 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
         T d = T(0);
 #pragma unroll
         for (int s = 0; s < S; ++s) d = fma_t(nrow[s], at[t * PP + lane + 64 * s], d);
-        w[t] = wave_sum(d);
+        w[t] = d;
       }
+      wave_sum8(w);
 #pragma unroll
       for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int t = 0; t < kMseRP; ++t) acc[s][t] = fma_t(nrow[s], w[t], acc[s][t]);
     }
+    if (j0 + G * stride < nrows) load_group(j0 + G * stride);
   }
   __syncthreads();   // the panels are no longer read
   T* red = lds;
@@ -159,55 +229,63 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
       red[wave * PP * kMseRP + (lane + 64 * s) * kMseRP + t] = acc[s][t];
   __syncthreads();
   T* out = part + (int64_t)blockIdx.x * PP * kMseRP;
-  for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
-    T sum = red[e];
+  for (int q = threadIdx.x; q < PP * kMseRP; q += 256) {
+    T sum = red[q];
 #pragma unroll
-    for (int w = 1; w < kMseWaves; ++w) sum += red[w * PP * kMseRP + e];
-    out[e] = sum;
+    for (int w = 1; w < kMseWaves; ++w) sum += red[w * PP * kMseRP + q];
+    out[q] = sum;
   }
 }
 
-// One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS): Gram in a
-// fixed order, Cholesky with the dependent-column rule (a pivot at most
-// tau * G_jj marks column j dependent: zero row of R, zero column of the
-// result), Y <- Y R^{-1}.  `act` holds the columns still in use.  Every
-// loop over the 8 columns is unrolled so that all small arrays stay in
-// registers.
+// One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS, row-major) by
+// a block of kOrthThreads: Gram in a fixed order, Cholesky with the
+// dependent-column rule (a pivot at most tau * G_jj marks column j
+// dependent: zero row of R, zero column of the result), Y <- Y R^{-1}.
+// `act` holds the columns still in use.  The Gram takes no cross-lane
+// sums: thread (seg, a, b) adds Y[c][a] Y[c][b] over the rows c of segment
+// seg (four interleaved accumulators), then 64 threads add the eight
+// segments in order.  Every loop over the 8 columns is unrolled so that
+// all small arrays stay in registers.
+constexpr int kOrthThreads = 512;
 template <int PP>
 __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int* act, double* gsh,
                                double* red) {
   constexpr int R8 = kMseRP;
   constexpr int NE = R8 * (R8 + 1) / 2;   // entries a <= b
+  constexpr int NSEG = kOrthThreads / (R8 * R8);
+  constexpr int SEG = PP / NSEG;
+  static_assert(SEG % 4 == 0, "segment length");
+  auto tri = [](int a_, int b_) { return a_ * R8 - a_ * (a_ - 1) / 2 + (b_ - a_); };
   const int tid = threadIdx.x;
-  // Gram G[a][b], a <= b: thread-local sums over rows tid, tid + 256, ...,
-  // then a wavefront sum, then the four wavefronts in order
-  double g[NE];
+  {
+    const int ab = tid & (R8 * R8 - 1);
+    const int seg = tid / (R8 * R8);
+    const int a_ = ab / R8, b_ = ab % R8;
+    double g4[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* y = Y + seg * SEG * R8;
+#pragma unroll 4
+    for (int c = 0; c < SEG; c += 4) {
 #pragma unroll
-  for (int q = 0; q < NE; ++q) g[q] = 0.0;
-  for (int c = tid; c < PP; c += 256) {
-    double y[R8];
-#pragma unroll
-    for (int t = 0; t < R8; ++t) y[t] = Y[c * R8 + t];
-    int q = 0;
-#pragma unroll
-    for (int a_ = 0; a_ < R8; ++a_)
-#pragma unroll
-      for (int b_ = a_; b_ < R8; ++b_, ++q)
-        if (a_ < r && b_ < r) g[q] = fma(y[a_], y[b_], g[q]);
+      for (int k = 0; k < 4; ++k) g4[k] = fma(y[(c + k) * R8 + a_], y[(c + k) * R8 + b_], g4[k]);
+    }
+    const double gv = (a_ < r && b_ < r) ? (g4[0] + g4[1]) + (g4[2] + g4[3]) : 0.0;
+    red[seg * R8 * R8 + ab] = gv;
   }
+  __syncthreads();
+  if (tid < R8 * R8) {
+    double t = red[tid];
 #pragma unroll
-  for (int q = 0; q < NE; ++q) {
-    const double v = wave_sum(g[q]);
-    if ((tid & 63) == 0) red[(tid >> 6) * NE + q] = v;
+    for (int sg = 1; sg < NSEG; ++sg) t += red[sg * R8 * R8 + tid];
+    const int a_ = tid / R8, b_ = tid % R8;
+    if (a_ <= b_) gsh[tri(a_, b_)] = t;
   }
   __syncthreads();
   if (tid == 0) {
     // packed upper triangle, entry (a, b) at tri(a, b); G becomes R in place
     // (row j of R needs only rows l < j of R and row j of G)
-    auto tri = [](int a_, int b_) { return a_ * R8 - a_ * (a_ - 1) / 2 + (b_ - a_); };
     double T[NE];
 #pragma unroll
-    for (int q = 0; q < NE; ++q) T[q] = red[q] + red[NE + q] + red[2 * NE + q] + red[3 * NE + q];
+    for (int q = 0; q < NE; ++q) T[q] = gsh[q];
     int am = 0;
 #pragma unroll
     for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
@@ -222,6 +300,7 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
         am &= ~(1 << j);
 #pragma unroll
         for (int b_ = j; b_ < R8; ++b_) T[tri(j, b_)] = 0.0;
+        gsh[NE + j] = 0.0;
         continue;
       }
       // 1 / r_jj from a Newton-refined reciprocal square root: the rows of R
@@ -245,7 +324,6 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
   }
   __syncthreads();
   // Y <- Y R^{-1} on the active columns (forward substitution per row)
-  auto tri = [](int a_, int b_) { return a_ * R8 - a_ * (a_ - 1) / 2 + (b_ - a_); };
   int am = 0;
 #pragma unroll
   for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
@@ -254,18 +332,18 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
   for (int q = 0; q < NE; ++q) rr[q] = gsh[q];
 #pragma unroll
   for (int j = 0; j < R8; ++j) rinv[j] = gsh[NE + j];
-  for (int c = tid; c < PP; c += 256) {
+  for (int c = tid; c < PP; c += kOrthThreads) {
     double y[R8], qv[R8];
 #pragma unroll
     for (int t = 0; t < R8; ++t) y[t] = Y[c * R8 + t];
 #pragma unroll
     for (int j = 0; j < R8; ++j) {
       if (!((am >> j) & 1)) { qv[j] = 0.0; continue; }
-      double s = y[j];
+      double sv = y[j];
 #pragma unroll
       for (int l = 0; l < j; ++l)
-        if ((am >> l) & 1) s -= qv[l] * rr[tri(l, j)];
-      qv[j] = s * rinv[j];
+        if ((am >> l) & 1) sv -= qv[l] * rr[tri(l, j)];
+      qv[j] = sv * rinv[j];
     }
 #pragma unroll
     for (int t = 0; t < R8; ++t) Y[c * R8 + t] = qv[t];
@@ -275,7 +353,7 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
 
 // Y2 from the block partials in two fixed-order stages: block (x, y) adds
 // the partials of its range y of kMseSplit consecutive ranges in ascending
-// order (a thread per entry, 16 partials in flight) into sub[y]; km_orth
+// order (a thread per entry, 32 partials in flight) into sub[y]; km_orth
 // then adds sub[0], sub[1], ... in order.
 constexpr int kMseSplit = 8;
 template <typename T, int PP>
@@ -286,7 +364,7 @@ __global__ __launch_bounds__(256) void km_reduce(const T* __restrict__ part, int
   const int per = (nblk + kMseSplit - 1) / kMseSplit;
   const int b0 = blockIdx.y * per;
   const int b1 = (b0 + per) < nblk ? (b0 + per) : nblk;
-  constexpr int F = 16;
+  constexpr int F = 32;
   double s = 0.0;
   for (int c0 = b0; c0 < b1; c0 += F) {
     T v[F];
@@ -300,23 +378,31 @@ __global__ __launch_bounds__(256) void km_reduce(const T* __restrict__ part, int
   sub[(int64_t)blockIdx.y * PP * kMseRP + e] = s;
 }
 
-// Q = orth(Y2); one block.
+// Q = orth(Y2); one block of kOrthThreads.  Every thread loads all of its
+// entries' kMseSplit sub-sums at once (one memory round trip).
 template <typename T, int PP>
-__global__ __launch_bounds__(256) void km_orth(const double* __restrict__ y2, int r,
-                                               T* __restrict__ Q) {
+__global__ __launch_bounds__(kOrthThreads) void km_orth(const double* __restrict__ y2, int r,
+                                                        T* __restrict__ Q) {
+  constexpr int PER = PP * kMseRP / kOrthThreads;
   __shared__ double Y[PP * kMseRP];
-  __shared__ double red[4 * kMseRP * kMseRP];
+  __shared__ double red[kOrthThreads];
   __shared__ double gsh[kMseRP * kMseRP];
   __shared__ int act[kMseRP];
   const int tid = threadIdx.x;
-  for (int e = tid; e < PP * kMseRP; e += 256) {
-    double v[kMseSplit];
+  {
+    double v[PER][kMseSplit];
 #pragma unroll
-    for (int y = 0; y < kMseSplit; ++y) v[y] = y2[(int64_t)y * PP * kMseRP + e];
-    double sum = v[0];
+    for (int q = 0; q < PER; ++q)
 #pragma unroll
-    for (int y = 1; y < kMseSplit; ++y) sum += v[y];
-    Y[e] = sum;
+      for (int y = 0; y < kMseSplit; ++y)
+        v[q][y] = y2[(int64_t)y * PP * kMseRP + q * kOrthThreads + tid];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      double sum = v[q][0];
+#pragma unroll
+      for (int y = 1; y < kMseSplit; ++y) sum += v[q][y];
+      Y[q * kOrthThreads + tid] = sum;
+    }
   }
   if (tid < kMseRP) act[tid] = tid < r ? 1 : 0;
   __syncthreads();
@@ -324,12 +410,13 @@ __global__ __launch_bounds__(256) void km_orth(const double* __restrict__ y2, in
   const double tau = (double)r * fmax(u * u, 0x1p-53);
   mse_chol_round<PP>(Y, r, tau, act, gsh, red);
   mse_chol_round<PP>(Y, r, tau, act, gsh, red);
-  for (int e = tid; e < PP * kMseRP; e += 256) Q[e] = (T)Y[e];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) Q[q * kOrthThreads + tid] = (T)Y[q * kOrthThreads + tid];
 }
 
 // U_row = N_row Q and E_row = N_row - U_row Q^T for every row of the label,
-// kMseGroup rows of a wavefront at a time (V in LDS, transposed; Q in
-// registers).
+// a group of rows of a wavefront at a time (V in LDS, transposed; Q in
+// registers); the first group's loads are issued before V is staged.
 template <typename T, int S, bool FIRST>
 __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
                                                  const T* __restrict__ X, int64_t ldx,
@@ -339,23 +426,14 @@ __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
                                                  T* __restrict__ U, const T* __restrict__ V,
                                                  const T* __restrict__ Q) {
   constexpr int PP = 64 * S;
-  constexpr int G = kMseGroup;
+  constexpr int G = MseGroup<T>::update;
   __shared__ T vt[kMseRP * PP];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < PP * kMseRP; e += 256) {
-    const int c = e / kMseRP, t = e % kMseRP;
-    vt[t * PP + c] = FIRST ? T(0) : V[e];
-  }
-  T qq[S][kMseRP];
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int t = 0; t < kMseRP; ++t) qq[s][t] = Q[(lane + 64 * s) * kMseRP + t];
-  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t stride = (int64_t)gridDim.x * kMseWaves;
-  for (int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave; j0 < nrows; j0 += G * stride) {
-    T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
-    int64_t gg[G];
+  T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
+  int64_t gg[G];
+  auto load_group = [&](int64_t j0) {
 #pragma unroll
     for (int h = 0; h < G; ++h) {
       const int64_t j = j0 + h * stride;
@@ -375,6 +453,27 @@ __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
         if constexpr (FIRST) xl[h][s] = ok ? X[g * ldx + col] : T(0);
       }
     }
+  };
+  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
+  if (j0 < nrows) load_group(j0);
+  {
+    constexpr int NST = PP * kMseRP / 256;
+    T vv[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) vv[k] = FIRST ? T(0) : V[k * 256 + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      const int q = k * 256 + threadIdx.x;
+      vt[(q % kMseRP) * PP + q / kMseRP] = vv[k];
+    }
+  }
+  T qq[S][kMseRP];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) qq[s][t] = Q[(lane + 64 * s) * kMseRP + t];
+  __syncthreads();
+  for (; j0 < nrows; j0 += G * stride) {
 #pragma unroll
     for (int h = 0; h < G; ++h) {
       const int64_t j = j0 + h * stride;
@@ -398,8 +497,9 @@ __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
         T d = T(0);
 #pragma unroll
         for (int s = 0; s < S; ++s) d = fma_t(nrow[s], qq[s][t], d);
-        w[t] = wave_sum(d);
+        w[t] = d;
       }
+      wave_sum8(w);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int64_t col = lane + 64 * s;
@@ -414,6 +514,7 @@ __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
       for (int t = 1; t < kMseRP; ++t) wl = (lane == t) ? w[t] : wl;
       if (lane < kMseRP) U[j * kMseRP + lane] = wl;
     }
+    if (j0 + G * stride < nrows) load_group(j0 + G * stride);
   }
 }
 
@@ -516,7 +617,7 @@ static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
       hipLaunchKernelGGL((km_reduce<T, 64 * S>),
                          dim3((64 * S * kMseRP + 255) / 256, kMseSplit), dim3(256), 0,
                          L.stream, (const T*)a.part, a.nblk, a.y2);
-      hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(256), 0, L.stream,
+      hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(kOrthThreads), 0, L.stream,
                          (const double*)a.y2, a.r, (T*)a.Vnew);
       // the update writes no partials: a block per 16 rows
       int64_t nbu = (a.nrows + 15) / 16;
