@@ -243,7 +243,15 @@ __device__ __forceinline__ void seg_close(SegSink<T>& s) {
   s.flushed = s.fill;
 }
 
-// Range of candidate segment sg (sg == nseg is the spill region).
+// Candidate segments: the nseg wave segments, then the spill region cut
+// into chunks of kSpillChunk entries, so that data whose candidates crowd a
+// few waves (clustered outliers) spreads its spill over many readers.
+constexpr long long kSpillChunk = 1024;
+__device__ __forceinline__ int seg_total(const SelPlan* plan) {
+  const long long sp = plan->ncand < plan->cap ? plan->ncand : plan->cap;
+  return plan->nseg + (int)((sp + kSpillChunk - 1) / kSpillChunk);
+}
+// Range of candidate segment sg < seg_total(plan).
 __device__ __forceinline__ void seg_range(const SelPlan* plan, const unsigned int* seg_count,
                                           int sg, long long& base, long long& cnt) {
   const int nseg = plan->nseg;
@@ -252,8 +260,11 @@ __device__ __forceinline__ void seg_range(const SelPlan* plan, const unsigned in
     base = (long long)sg * (cap / nseg);
     cnt = (long long)seg_count[sg];
   } else {
-    base = cap;
-    cnt = plan->ncand < cap ? plan->ncand : cap;
+    const long long sp = plan->ncand < cap ? plan->ncand : cap;
+    const long long o = (long long)(sg - nseg) * kSpillChunk;
+    base = cap + o;
+    const long long left = sp - o;
+    cnt = left < 0 ? 0 : (left < kSpillChunk ? left : kSpillChunk);
   }
 }
 
@@ -709,7 +720,8 @@ __global__ __launch_bounds__(256) void k_cand_hist(SelPlan* __restrict__ plan,
   const int dbits = digit_bits(pbits, KB);
   for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
   __syncthreads();
-  for (int sg = blockIdx.x; sg <= plan->nseg; sg += gridDim.x) {
+  const int ntot = seg_total(plan);
+  for (int sg = blockIdx.x; sg < ntot; sg += gridDim.x) {
     long long base, cnt;
     seg_range(plan, seg_count, sg, base, cnt);
     for (long long c = base + threadIdx.x; c < base + cnt; c += 256) {
@@ -895,12 +907,12 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
   const unsigned long long kcap = (unsigned long long)(plan->count_above + plan->k_rem);
   const unsigned long long tcap = (unsigned long long)plan->cap;
   const unsigned long long below = (1ull << lane) - 1ull;
-  const int nseg = plan->nseg;
+  const int ntot = seg_total(plan);
   const int wstride = 4 * (int)gridDim.x;
   const int w0 = 4 * (int)blockIdx.x + wave;
   // phase 1: per-wave counts, one reservation per block and list
   unsigned int na = 0, nt = 0;
-  for (int sg = w0; sg <= nseg; sg += wstride) {
+  for (int sg = w0; sg < ntot; sg += wstride) {
     long long c0, cnt;
     seg_range(plan, seg_count, sg, c0, cnt);
     for (long long c = c0 + lane; c < c0 + cnt; c += 64) {
@@ -924,7 +936,7 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
   for (int w = 0; w < wave; ++w) { ba += wa[w]; bt += wt[w]; }
   // phase 2: each wave writes its segments in order, four loads in flight
   double s2 = 0.0;
-  for (int sg = w0; sg <= nseg; sg += wstride) {
+  for (int sg = w0; sg < ntot; sg += wstride) {
     long long c0, cnt;
     seg_range(plan, seg_count, sg, c0, cnt);
     const long long c1 = c0 + cnt;
@@ -1239,7 +1251,8 @@ __global__ __launch_bounds__(256) void k_sel_ties_stream(const T* __restrict__ X
   const long long nabove = plan->count_above;
   double s2 = 0.0;
   long long out = 0;
-  for (int sg = 0; sg <= plan->nseg; ++sg) {
+  const int ntot = seg_total(plan);
+  for (int sg = 0; sg < ntot; ++sg) {
     long long base, cnt;
     seg_range(plan, seg_count, sg, base, cnt);
     for (long long e = tid; e < cnt; e += 256) {
