@@ -237,6 +237,199 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
   }
 }
 
+// The 64 sums over the wavefront's lanes of the per-lane values v[0..63]:
+// six halving steps (partners whose lane bit 5, 4, ..., 0 differs exchange
+// the half that the partner keeps), after which lane l holds the sum of
+// index l.  The order of the additions is fixed by the lane indices.
+template <int H, typename T>
+__device__ __forceinline__ void halving_step(T (&v)[64], int lane) {
+  const bool up = (lane & H) != 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const T keep = up ? v[i + H] : v[i];
+    const T give = up ? v[i] : v[i + H];
+    v[i] = keep + __shfl_xor(give, H, 64);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T wave_reduce_scatter64(T (&v)[64]) {
+  const int lane = threadIdx.x & 63;
+  halving_step<32>(v, lane);
+  halving_step<16>(v, lane);
+  halving_step<8>(v, lane);
+  halving_step<4>(v, lane);
+  halving_step<2>(v, lane);
+  halving_step<1>(v, lane);
+  return v[0];
+}
+
+// Y2 pass of a label that has been updated before (L^i = U V^T).  With
+// N = E + U V^T,
+//   W_row = N_row A1 = E_row A1 + U_row P,                 P = V^T A1 (8 x 8)
+//   Y2 = sum_rows N_row^T W_row = sum_rows E_row^T W_row + V M,
+//   M = sum_rows U_row^T W_row (8 x 8),
+// so the row loop multiplies each entry of E by A1 and by W only; L^i is
+// never formed.  Lane l keeps the A1 rows of its columns in registers and
+// the entry (l & 7, l >> 3) of P and of M: in the eight-sum reduction of W
+// (see wave_sum8) lane l holds, before the last three butterfly steps, a
+// partial of W_row[l >> 3] over a set of lanes disjoint from those of the
+// other seven lanes of its group, so adding u[l & 7] P[l & 7][l >> 3] there
+// adds U_row P exactly once; after them it holds W_row[l >> 3] itself, the
+// factor of M's entry.  The block writes its partial of Y2 (its rows'
+// E^T W sums plus V M over its rows) to part[blockIdx.x]; row and group
+// order as in km_gram.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_t lde,
+                                                 const int64_t* __restrict__ rows,
+                                                 int64_t nrows, int64_t p,
+                                                 const T* __restrict__ U,
+                                                 const T* __restrict__ V,
+                                                 const T* __restrict__ A1,
+                                                 T* __restrict__ part) {
+  constexpr int PP = 64 * S;
+  constexpr int G = MseGroup<T>::gram;
+  __shared__ T red[kMseWaves * PP * kMseRP];
+  __shared__ T pm[kMseWaves * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t stride = (int64_t)gridDim.x * kMseWaves;
+  T e[G][S], ul[G];
+  auto load_group = [&](int64_t j0) {
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+      const int64_t j = j0 + h * stride;
+      const bool rv = j < nrows;   // wavefront-uniform
+      const int64_t g = rv ? rows[j] : 0;
+      ul[h] = rv ? U[j * kMseRP + (lane & 7)] : T(0);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int64_t col = lane + 64 * s;
+        e[h][s] = (rv && col < p) ? E[g * lde + col] : T(0);
+      }
+    }
+  };
+  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
+  if (j0 < nrows) load_group(j0);
+  // A1 rows of the lane's columns (zero past p)
+  T a1r[S][kMseRP];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) a1r[s][t] = A1[(int64_t)(lane + 64 * s) * kMseRP + t];
+  // P = V^T A1: wavefront w takes the columns of slices s = w, w + 4, ...
+  {
+    T pv[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) pv[i] = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (s % kMseWaves != wave) continue;   // wavefront-uniform
+      T vr[kMseRP];
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) vr[t] = V[(int64_t)(lane + 64 * s) * kMseRP + t];
+#pragma unroll
+      for (int t1 = 0; t1 < kMseRP; ++t1)
+#pragma unroll
+        for (int t2 = 0; t2 < kMseRP; ++t2)
+          pv[t1 * kMseRP + t2] = fma_t(vr[t1], a1r[s][t2], pv[t1 * kMseRP + t2]);
+    }
+    pm[wave * 64 + lane] = wave_reduce_scatter64(pv);   // P_w[t1 * 8 + t2] on lane t1 * 8 + t2
+  }
+  __syncthreads();
+  T pl;
+  {
+    const int q = (lane & 7) * kMseRP + (lane >> 3);   // P[l & 7][l >> 3]
+    pl = pm[q];
+#pragma unroll
+    for (int w = 1; w < kMseWaves; ++w) pl += pm[w * 64 + q];
+  }
+  T acc[S][kMseRP];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) acc[s][t] = T(0);
+  T macc = T(0);
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+  for (; j0 < nrows; j0 += G * stride) {
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+      if (j0 + h * stride >= nrows) break;   // wavefront-uniform
+      T d[kMseRP];
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t) {
+        T x = T(0);
+#pragma unroll
+        for (int s = 0; s < S; ++s) x = fma_t(e[h][s], a1r[s][t], x);
+        d[t] = x;
+      }
+      // the halving steps of wave_sum8
+      T a4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T keep = h5 ? d[i + 4] : d[i];
+        const T give = h5 ? d[i] : d[i + 4];
+        a4[i] = keep + __shfl_xor(give, 32, 64);
+      }
+      T a2[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const T keep = h4 ? a4[i + 2] : a4[i];
+        const T give = h4 ? a4[i] : a4[i + 2];
+        a2[i] = keep + __shfl_xor(give, 16, 64);
+      }
+      T a1 = (h3 ? a2[1] : a2[0]) + __shfl_xor(h3 ? a2[0] : a2[1], 8, 64);
+      a1 = fma_t(ul[h], pl, a1);   // + u[l & 7] P[l & 7][l >> 3]
+      a1 += __shfl_xor(a1, 4, 64);
+      a1 += __shfl_xor(a1, 2, 64);
+      a1 += __shfl_xor(a1, 1, 64);
+      macc = fma_t(ul[h], a1, macc);   // M[l & 7][l >> 3] += u[l & 7] W[l >> 3]
+      T w[kMseRP];
+#pragma unroll
+      for (int t = 0; t < kMseRP; ++t)
+        w[t] = lane_read(a1, ((t >> 2) << 5) | (((t >> 1) & 1) << 4) | ((t & 1) << 3));
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int t = 0; t < kMseRP; ++t) acc[s][t] = fma_t(e[h][s], w[t], acc[s][t]);
+    }
+    if (j0 + G * stride < nrows) load_group(j0 + G * stride);
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t)
+      red[wave * PP * kMseRP + (lane + 64 * s) * kMseRP + t] = acc[s][t];
+  pm[wave * 64 + lane] = macc;   // M_w[t1][t2] on lane t2 * 8 + t1 (pm is free again)
+  __syncthreads();
+  T mm[kMseRP][kMseRP];   // the block's M, added over the wavefronts in order
+#pragma unroll
+  for (int t1 = 0; t1 < kMseRP; ++t1)
+#pragma unroll
+    for (int t2 = 0; t2 < kMseRP; ++t2) {
+      const int q = t2 * kMseRP + t1;
+      T m = pm[q];
+#pragma unroll
+      for (int w = 1; w < kMseWaves; ++w) m += pm[w * 64 + q];
+      mm[t1][t2] = m;
+    }
+  T* out = part + (int64_t)blockIdx.x * PP * kMseRP;
+  for (int c = threadIdx.x; c < PP; c += 256) {
+    T vr[kMseRP];
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) vr[t] = V[(int64_t)c * kMseRP + t];
+#pragma unroll
+    for (int t2 = 0; t2 < kMseRP; ++t2) {
+      T sum = red[c * kMseRP + t2];
+#pragma unroll
+      for (int w = 1; w < kMseWaves; ++w) sum += red[w * PP * kMseRP + c * kMseRP + t2];
+      T vm = T(0);
+#pragma unroll
+      for (int t1 = 0; t1 < kMseRP; ++t1) vm = fma_t(vr[t1], mm[t1][t2], vm);
+      out[c * kMseRP + t2] = sum + vm;
+    }
+  }
+}
+
 // One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS, row-major) by
 // a block of kOrthThreads: Gram in a fixed order, Cholesky with the
 // dependent-column rule (a pivot at most tau * G_jj marks column j
@@ -610,9 +803,8 @@ static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
                            (const T*)a.cnt, a.rows, a.nrows, a.p, (const T*)a.U,
                            (const T*)a.Vold, (const T*)a.A1, (T*)a.part);
       else
-        hipLaunchKernelGGL((km_gram<T, S, false>), dim3((unsigned)a.nblk), dim3(256), 0,
-                           L.stream, (const T*)a.E, a.lde, (const T*)a.X, a.ldx,
-                           (const T*)a.cnt, a.rows, a.nrows, a.p, (const T*)a.U,
+        hipLaunchKernelGGL((km_gram_v<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
+                           (const T*)a.E, a.lde, a.rows, a.nrows, a.p, (const T*)a.U,
                            (const T*)a.Vold, (const T*)a.A1, (T*)a.part);
       hipLaunchKernelGGL((km_reduce<T, 64 * S>),
                          dim3((64 * S * kMseRP + 255) / 256, kMseSplit), dim3(256), 0,
