@@ -38,69 +38,99 @@ __device__ __forceinline__ double lane_read(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Register-only lane exchanges (no LDS crossbar, no address operand):
+//   swap32 / swap16: the gfx950 lane-half swaps.  For a pair (x, y) with
+//     x kept by lanes whose bit 5 (4) is clear and y by the others, x + y
+//     of the two returned registers is the kept value plus the partner's
+//     (lane l ^ 32, l ^ 16) copy of it.
+//   dpp<CTRL>: the value of a partner lane through a DPP move: row_ror:8
+//     (lane l ^ 8), row_half_mirror (l ^ 7 within eight lanes), quad_perm
+//     swaps (l ^ 2, l ^ 1).
+constexpr int kDppRor8 = 0x128;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppXor1 = 0xB1;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <bool S32>
+__device__ __forceinline__ float swap_sum(float x, float y) {
+  const auto r = S32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y),
+                                                         false, false)
+                     : __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y),
+                                                         false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <bool S32>
+__device__ __forceinline__ double swap_sum(double x, double y) {
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+  const auto lo = S32 ? __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false)
+                      : __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = S32 ? __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32),
+                                                          (unsigned)(by >> 32), false, false)
+                      : __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32),
+                                                          (unsigned)(by >> 32), false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  const double b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  return a + b;
+}
+// One halving step through a DPP partner: the lane keeps index `up ? y : x`
+// and adds the partner's copy of it.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_halve(T x, T y, bool up) {
+  return (up ? y : x) + dpp<CTRL>(up ? x : y);
+}
+
 // The eight sums over the wavefront's 64 lanes of the per-lane values
-// d[0..7], returned to every lane in d.  Three halving steps (partners
-// whose lane bit 5, 4, 3 differs exchange the half of their values that
-// the partner keeps), three butterfly steps on the one value left, then
-// every lane reads the eight sums from the lanes that hold them: ten
-// exchanges where eight separate butterflies take 48.  The order of the
-// additions is fixed by the lane indices, so the sums are reproducible.
+// d[0..7], in three parts:
+//   wave_halve8: three halving steps (partners whose lane bit 5, 4, 3
+//     differs exchange the half of their values that the partner keeps);
+//     lane l is left with a partial of index l >> 3 over the eight lanes
+//     that share its bits 2..0, a set disjoint from those of the seven
+//     other lanes of its group of eight;
+//   wave_bfly8: three butterfly steps over the group (pairs l ^ 7, l ^ 2,
+//     l ^ 1), after which every lane l holds the sum of index l >> 3;
+//   wave_bcast8: every lane reads the eight sums.
+// Ten exchanges where eight separate butterflies take 48, all in registers.
+// The order of the additions is fixed by the lane indices, so the sums are
+// reproducible.
 template <typename T>
-__device__ __forceinline__ void wave_sum8(T (&d)[kMseRP]) {
+__device__ __forceinline__ T wave_halve8(const T (&d)[kMseRP]) {
   const int lane = threadIdx.x & 63;
-  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
   T a4[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const T keep = h5 ? d[i + 4] : d[i];
-    const T give = h5 ? d[i] : d[i + 4];
-    a4[i] = keep + __shfl_xor(give, 32, 64);
-  }
+  for (int i = 0; i < 4; ++i) a4[i] = swap_sum<true>(d[i], d[i + 4]);
   T a2[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const T keep = h4 ? a4[i + 2] : a4[i];
-    const T give = h4 ? a4[i] : a4[i + 2];
-    a2[i] = keep + __shfl_xor(give, 16, 64);
-  }
-  T a1 = (h3 ? a2[1] : a2[0]) + __shfl_xor(h3 ? a2[0] : a2[1], 8, 64);
-  a1 += __shfl_xor(a1, 4, 64);
-  a1 += __shfl_xor(a1, 2, 64);
-  a1 += __shfl_xor(a1, 1, 64);
+  for (int i = 0; i < 2; ++i) a2[i] = swap_sum<false>(a4[i], a4[i + 2]);
+  return dpp_halve<kDppRor8>(a2[0], a2[1], (lane & 8) != 0);
+}
+template <typename T>
+__device__ __forceinline__ T wave_bfly8(T a) {
+  a += dpp<kDppHalfMirror>(a);
+  a += dpp<kDppXor2>(a);
+  a += dpp<kDppXor1>(a);
+  return a;
+}
+template <typename T>
+__device__ __forceinline__ void wave_bcast8(T a, T (&d)[kMseRP]) {
   // lane 32 b2 + 16 b1 + 8 b0 holds the sum of index 4 b2 + 2 b1 + b0
 #pragma unroll
   for (int t = 0; t < kMseRP; ++t)
-    d[t] = lane_read(a1, ((t >> 2) << 5) | (((t >> 1) & 1) << 4) | ((t & 1) << 3));
+    d[t] = lane_read(a, ((t >> 2) << 5) | (((t >> 1) & 1) << 4) | ((t & 1) << 3));
 }
-
-// N_row of label i: E_row + L^i_row, where L^i_row is U_j V^T (updated
-// label) or X_row / cnt_row (initial value of the label).
-template <typename T, int S>
-__device__ __forceinline__ void mse_load_n(const T* __restrict__ E, int64_t lde,
-                                           const T* __restrict__ X, int64_t ldx,
-                                           const T* __restrict__ cnt, int64_t g, int64_t p,
-                                           int first, const T* __restrict__ Urow,
-                                           const T (&v)[S][kMseRP], int lane, T (&nrow)[S]) {
-  T u[kMseRP];
-  if (!first) {
-#pragma unroll
-    for (int t = 0; t < kMseRP; ++t) u[t] = Urow[t];
-  }
-  const T c = first ? cnt[g] : T(0);
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int64_t col = lane + 64 * s;
-    const bool ok = col < p;
-    const T e = ok ? E[g * lde + col] : T(0);
-    T l = T(0);
-    if (first) {
-      l = (ok && c > T(0)) ? X[g * ldx + col] / c : T(0);
-    } else {
-#pragma unroll
-      for (int t = 0; t < kMseRP; ++t) l = fma_t(u[t], v[s][t], l);
-    }
-    nrow[s] = e + l;
-  }
+template <typename T>
+__device__ __forceinline__ void wave_sum8(T (&d)[kMseRP]) {
+  wave_bcast8(wave_bfly8(wave_halve8(d)), d);
 }
 
 // Rows of a wavefront are processed in groups: the loads of a group are all
@@ -241,26 +271,26 @@ __global__ __launch_bounds__(256) void km_gram(const T* __restrict__ E, int64_t 
 // six halving steps (partners whose lane bit 5, 4, ..., 0 differs exchange
 // the half that the partner keeps), after which lane l holds the sum of
 // index l.  The order of the additions is fixed by the lane indices.
-template <int H, typename T>
-__device__ __forceinline__ void halving_step(T (&v)[64], int lane) {
-  const bool up = (lane & H) != 0;
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const T keep = up ? v[i + H] : v[i];
-    const T give = up ? v[i] : v[i + H];
-    v[i] = keep + __shfl_xor(give, H, 64);
-  }
-}
+// The 64 sums over the wavefront's lanes of the per-lane values v[0..63]:
+// six halving steps (partners l ^ 32, l ^ 16, l ^ 8 through the register
+// exchanges above, then l ^ 7, l ^ 2, l ^ 1 within groups of eight; at the
+// step on lane bit b the lane keeps the upper half of the indices when its
+// bit b is set), after which lane l holds the sum of index l.  The order
+// of the additions is fixed by the lane indices.
 template <typename T>
 __device__ __forceinline__ T wave_reduce_scatter64(T (&v)[64]) {
   const int lane = threadIdx.x & 63;
-  halving_step<32>(v, lane);
-  halving_step<16>(v, lane);
-  halving_step<8>(v, lane);
-  halving_step<4>(v, lane);
-  halving_step<2>(v, lane);
-  halving_step<1>(v, lane);
-  return v[0];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) v[i] = swap_sum<true>(v[i], v[i + 32]);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = swap_sum<false>(v[i], v[i + 16]);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = dpp_halve<kDppRor8>(v[i], v[i + 8], (lane & 8) != 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = dpp_halve<kDppHalfMirror>(v[i], v[i + 4], (lane & 4) != 0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) v[i] = dpp_halve<kDppXor2>(v[i], v[i + 2], (lane & 2) != 0);
+  return dpp_halve<kDppXor1>(v[0], v[1], (lane & 1) != 0);
 }
 
 // Y2 pass of a label that has been updated before (L^i = U V^T).  With
@@ -294,45 +324,69 @@ __global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t stride = (int64_t)gridDim.x * kMseWaves;
   T e[G][S], ul[G];
+  // Branch-free loads (rows past the end read the last row and are zeroed;
+  // E is zero in its padding columns p..p_pad-1), so that all of a group's
+  // loads are issued back to back.
   auto load_group = [&](int64_t j0) {
+    int64_t g[G];
+#pragma unroll
+    for (int h = 0; h < G; ++h) {
+      const int64_t j = j0 + h * stride;
+      g[h] = rows[j < nrows ? j : nrows - 1];
+    }
 #pragma unroll
     for (int h = 0; h < G; ++h) {
       const int64_t j = j0 + h * stride;
       const bool rv = j < nrows;   // wavefront-uniform
-      const int64_t g = rv ? rows[j] : 0;
-      ul[h] = rv ? U[j * kMseRP + (lane & 7)] : T(0);
+      const T uv = U[(rv ? j : nrows - 1) * kMseRP + (lane & 7)];
+      ul[h] = rv ? uv : T(0);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const int64_t col = lane + 64 * s;
-        e[h][s] = (rv && col < p) ? E[g * lde + col] : T(0);
+        const T ev = E[g[h] * lde + lane + 64 * s];
+        e[h][s] = rv ? ev : T(0);
       }
     }
   };
-  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
-  if (j0 < nrows) load_group(j0);
+  // the panels are loaded first: the memory counters complete in issue
+  // order, so P can be formed, and the rows processed one by one, while
+  // later rows are still arriving.
   // A1 rows of the lane's columns (zero past p)
   T a1r[S][kMseRP];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int t = 0; t < kMseRP; ++t) a1r[s][t] = A1[(int64_t)(lane + 64 * s) * kMseRP + t];
+  // V and A1 rows of the slices s = wave + 4 k (the columns c = threadIdx.x +
+  // 256 k; zero for s >= S): P here, and V again for V M at the end
+  constexpr int NV = (S + kMseWaves - 1) / kMseWaves;
+  T vr[NV][kMseRP], ar[NV][kMseRP];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int s = wave + kMseWaves * k;
+    const bool ok = s < S;   // wavefront-uniform
+    const int64_t c = lane + 64 * (ok ? s : S - 1);
+#pragma unroll
+    for (int t = 0; t < kMseRP; ++t) {
+      const T vv = V[c * kMseRP + t];
+      const T av = A1[c * kMseRP + t];
+      vr[k][t] = ok ? vv : T(0);
+      ar[k][t] = ok ? av : T(0);
+    }
+  }
+  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
+  if (j0 < nrows) load_group(j0);
   // P = V^T A1: wavefront w takes the columns of slices s = w, w + 4, ...
   {
     T pv[64];
 #pragma unroll
     for (int i = 0; i < 64; ++i) pv[i] = T(0);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s % kMseWaves != wave) continue;   // wavefront-uniform
-      T vr[kMseRP];
-#pragma unroll
-      for (int t = 0; t < kMseRP; ++t) vr[t] = V[(int64_t)(lane + 64 * s) * kMseRP + t];
+    for (int k = 0; k < NV; ++k)
 #pragma unroll
       for (int t1 = 0; t1 < kMseRP; ++t1)
 #pragma unroll
         for (int t2 = 0; t2 < kMseRP; ++t2)
-          pv[t1 * kMseRP + t2] = fma_t(vr[t1], a1r[s][t2], pv[t1 * kMseRP + t2]);
-    }
+          pv[t1 * kMseRP + t2] = fma_t(vr[k][t1], ar[k][t2], pv[t1 * kMseRP + t2]);
     pm[wave * 64 + lane] = wave_reduce_scatter64(pv);   // P_w[t1 * 8 + t2] on lane t1 * 8 + t2
   }
   __syncthreads();
@@ -349,7 +403,6 @@ __global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_
 #pragma unroll
     for (int t = 0; t < kMseRP; ++t) acc[s][t] = T(0);
   T macc = T(0);
-  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
   for (; j0 < nrows; j0 += G * stride) {
 #pragma unroll
     for (int h = 0; h < G; ++h) {
@@ -362,31 +415,12 @@ __global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_
         for (int s = 0; s < S; ++s) x = fma_t(e[h][s], a1r[s][t], x);
         d[t] = x;
       }
-      // the halving steps of wave_sum8
-      T a4[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const T keep = h5 ? d[i + 4] : d[i];
-        const T give = h5 ? d[i] : d[i + 4];
-        a4[i] = keep + __shfl_xor(give, 32, 64);
-      }
-      T a2[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const T keep = h4 ? a4[i + 2] : a4[i];
-        const T give = h4 ? a4[i] : a4[i + 2];
-        a2[i] = keep + __shfl_xor(give, 16, 64);
-      }
-      T a1 = (h3 ? a2[1] : a2[0]) + __shfl_xor(h3 ? a2[0] : a2[1], 8, 64);
+      T a1 = wave_halve8(d);
       a1 = fma_t(ul[h], pl, a1);   // + u[l & 7] P[l & 7][l >> 3]
-      a1 += __shfl_xor(a1, 4, 64);
-      a1 += __shfl_xor(a1, 2, 64);
-      a1 += __shfl_xor(a1, 1, 64);
+      a1 = wave_bfly8(a1);
       macc = fma_t(ul[h], a1, macc);   // M[l & 7][l >> 3] += u[l & 7] W[l >> 3]
       T w[kMseRP];
-#pragma unroll
-      for (int t = 0; t < kMseRP; ++t)
-        w[t] = lane_read(a1, ((t >> 2) << 5) | (((t >> 1) & 1) << 4) | ((t & 1) << 3));
+      wave_bcast8(a1, w);
 #pragma unroll
       for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -413,10 +447,10 @@ __global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_
       mm[t1][t2] = m;
     }
   T* out = part + (int64_t)blockIdx.x * PP * kMseRP;
-  for (int c = threadIdx.x; c < PP; c += 256) {
-    T vr[kMseRP];
 #pragma unroll
-    for (int t = 0; t < kMseRP; ++t) vr[t] = V[(int64_t)c * kMseRP + t];
+  for (int k = 0; k < NV; ++k) {
+    const int c = threadIdx.x + 256 * k;
+    if (c >= PP) break;
 #pragma unroll
     for (int t2 = 0; t2 < kMseRP; ++t2) {
       T sum = red[c * kMseRP + t2];
@@ -424,7 +458,7 @@ __global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_
       for (int w = 1; w < kMseWaves; ++w) sum += red[w * PP * kMseRP + c * kMseRP + t2];
       T vm = T(0);
 #pragma unroll
-      for (int t1 = 0; t1 < kMseRP; ++t1) vm = fma_t(vr[t1], mm[t1][t2], vm);
+      for (int t1 = 0; t1 < kMseRP; ++t1) vm = fma_t(vr[k][t1], mm[t1][t2], vm);
       out[c * kMseRP + t2] = sum + vm;
     }
   }
@@ -610,8 +644,10 @@ __global__ __launch_bounds__(kOrthThreads) void km_orth(const double* __restrict
 // U_row = N_row Q and E_row = N_row - U_row Q^T for every row of the label,
 // a group of rows of a wavefront at a time (V in LDS, transposed; Q in
 // registers); the first group's loads are issued before V is staged.
+// Two wavefronts per SIMD (at most 256 registers): two blocks per CU, so
+// that a label's blocks (one per 16 rows) run in one round.
 template <typename T, int S, bool FIRST>
-__global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
+__global__ __launch_bounds__(256, 2) void km_update(T* __restrict__ E, int64_t lde,
                                                  const T* __restrict__ X, int64_t ldx,
                                                  const T* __restrict__ cnt,
                                                  const int64_t* __restrict__ rows,
@@ -624,47 +660,57 @@ __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t stride = (int64_t)gridDim.x * kMseWaves;
-  T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G][kMseRP], c[G];
+  // u: lane l holds entry l & 7 of the row of U (read out as scalars)
+  T e[G][S], xl[FIRST ? G : 1][FIRST ? S : 1], u[FIRST ? 1 : G], c[G];
   int64_t gg[G];
+  // branch-free loads, as in km_gram_v; X past column p is not read
   auto load_group = [&](int64_t j0) {
 #pragma unroll
     for (int h = 0; h < G; ++h) {
       const int64_t j = j0 + h * stride;
-      const bool rv = j < nrows;   // wavefront-uniform
-      const int64_t g = rv ? rows[j] : 0;
-      gg[h] = g;
-      c[h] = (FIRST && rv) ? cnt[g] : T(0);
-      if constexpr (!FIRST) {
+      gg[h] = rows[j < nrows ? j : nrows - 1];
+    }
 #pragma unroll
-        for (int t = 0; t < kMseRP; ++t) u[h][t] = rv ? U[j * kMseRP + t] : T(0);
+    for (int h = 0; h < G; ++h) {
+      const int64_t j = j0 + h * stride;
+      const bool rv = j < nrows;   // wavefront-uniform
+      const int64_t jc = rv ? j : nrows - 1;
+      const int64_t g = gg[h];
+      if constexpr (FIRST) {
+        const T cv = cnt[g];
+        c[h] = rv ? cv : T(0);
+      } else {
+        c[h] = T(0);
+        const T uv = U[jc * kMseRP + (lane & 7)];
+        u[h] = rv ? uv : T(0);
       }
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int64_t col = lane + 64 * s;
-        const bool ok = rv && col < p;
-        e[h][s] = ok ? E[g * lde + col] : T(0);
-        if constexpr (FIRST) xl[h][s] = ok ? X[g * ldx + col] : T(0);
+        const T ev = E[g * lde + col];
+        e[h][s] = rv ? ev : T(0);
+        if constexpr (FIRST) xl[h][s] = (rv && col < p) ? X[g * ldx + col] : T(0);
       }
     }
   };
-  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
-  if (j0 < nrows) load_group(j0);
-  {
-    constexpr int NST = PP * kMseRP / 256;
-    T vv[NST];
+  // the panels are loaded before the rows (the memory counters complete in
+  // issue order), so the rows can be processed while later ones arrive
+  constexpr int NST = PP * kMseRP / 256;
+  T vv[NST];
 #pragma unroll
-    for (int k = 0; k < NST; ++k) vv[k] = FIRST ? T(0) : V[k * 256 + threadIdx.x];
-#pragma unroll
-    for (int k = 0; k < NST; ++k) {
-      const int q = k * 256 + threadIdx.x;
-      vt[(q % kMseRP) * PP + q / kMseRP] = vv[k];
-    }
-  }
+  for (int k = 0; k < NST; ++k) vv[k] = FIRST ? T(0) : V[k * 256 + threadIdx.x];
   T qq[S][kMseRP];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int t = 0; t < kMseRP; ++t) qq[s][t] = Q[(lane + 64 * s) * kMseRP + t];
+  int64_t j0 = (int64_t)blockIdx.x * kMseWaves + wave;
+  if (j0 < nrows) load_group(j0);
+#pragma unroll
+  for (int k = 0; k < NST; ++k) {
+    const int q = k * 256 + threadIdx.x;
+    vt[(q % kMseRP) * PP + q / kMseRP] = vv[k];
+  }
   __syncthreads();
   for (; j0 < nrows; j0 += G * stride) {
 #pragma unroll
@@ -680,7 +726,7 @@ __global__ __launch_bounds__(256) void km_update(T* __restrict__ E, int64_t lde,
           l = (col < p && c[h] > T(0)) ? xl[h][s] / c[h] : T(0);
         } else {
 #pragma unroll
-          for (int t = 0; t < kMseRP; ++t) l = fma_t(u[h][t], vt[t * PP + col], l);
+          for (int t = 0; t < kMseRP; ++t) l = fma_t(lane_read(u[h], t), vt[t * PP + col], l);
         }
         nrow[s] = e[h][s] + l;
       }
