@@ -494,7 +494,8 @@ struct MseLabelArgs {
   void* Vnew;               // 64 S x 8 new basis (output)
   const void* A1;           // 64 S x 8 random matrix of this update
   void* part;               // nblk x 64 S x 8 partials
-  double* y2;               // 8 x 64 S x 8: sums of 8 ranges of partials (FP64)
+  double* y2;               // 64 S x 8: Y2 (FP64)
+  unsigned int* ctl;        // arrival counter of km_reduce_orth (zero between launches)
 };
 void launch_mse_label(const Launch& L, bool f64, const MseLabelArgs& a);
 void launch_mse_init_e(const Launch& L, bool f64, void* E, int64_t lde, const void* X,

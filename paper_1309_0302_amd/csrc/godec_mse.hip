@@ -29,8 +29,7 @@ namespace {
 
 constexpr int kRP = 8;           // padded rank of every label
 constexpr int kChunk = 4;        // iterations whose A1 draws are staged together
-constexpr int kMaxBlk = 256;     // blocks of a label's Y2 row pass
-constexpr int kY2Split = 8;      // ranges of block partials (km_reduce's kMseSplit)
+constexpr int kMaxBlk = 256;     // blocks of a label's Y2 row pass (km_reduce takes <= 256)
 
 }  // namespace
 
@@ -53,7 +52,8 @@ struct godec_mse {
   void* V = nullptr;               // k x 2 x pp x 8
   void* A1dev = nullptr;           // 2 x kChunk x k x pp x 8
   void* part = nullptr;            // kMaxBlk x pp x 8
-  double* y2 = nullptr;            // kY2Split x pp x 8 (FP64 partial sums)
+  double* y2 = nullptr;            // pp x 8: Y2 of the label being updated (FP64)
+  unsigned int* ctl = nullptr;     // arrival counter of the Y2 reduction
   void *UL0, *VL0, *VLt0;          // zero factors for the selection
   SelPlan* plan[2];
   unsigned long long* hist;
@@ -101,7 +101,8 @@ size_t carve_mse(godec_mse* m, void* base) {
   m->V = cv.take((size_t)m->k * 2 * pp * kRP * ta);
   m->A1dev = cv.take(2 * slot_elems(m) * ta);
   m->part = cv.take((size_t)kMaxBlk * pp * kRP * ta);
-  m->y2 = (double*)cv.take((size_t)kY2Split * pp * kRP * 8);
+  m->y2 = (double*)cv.take((size_t)pp * kRP * 8);
+  m->ctl = (unsigned int*)cv.take(256);
   m->UL0 = cv.take((size_t)n * ta);
   m->VL0 = cv.take((size_t)pp * ta);
   m->VLt0 = cv.take((size_t)pp * ta);
@@ -229,6 +230,7 @@ void run_iteration(godec_mse* m, const char* a1_base) {
     a.A1 = a1_base + (size_t)i * vsz;
     a.part = m->part;
     a.y2 = m->y2;
+    a.ctl = m->ctl;
     launch_mse_label(L, m->f64, a);
     m->vcur[i] = vc ^ 1;
     m->inited[i] = 1;
@@ -345,6 +347,7 @@ godec_status godec_mse_init(godec_mse** out, const void* X_dev, godec_dtype dtyp
   if (e == hipSuccess) e = hipMemsetAsync(m->plan[1], 0, sizeof(SelPlan), m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->carry, 0, sizeof(SelCarry), m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->nonfinite, 0, 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->ctl, 0, 256, m->stream);
   if (e != hipSuccess) return bail(GODEC_E_DEVICE, hipGetErrorString(e));
   launch_mse_init_e(L, m->f64, m->E, m->lde, X_dev, ldx, m->cnt, n, p);
   launch_norm_check(L, m->f64, X_dev, ldx, n, p, m->norm_x2, m->nonfinite, m->s2part);

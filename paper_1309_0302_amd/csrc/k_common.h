@@ -56,6 +56,25 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Cross-block hand-off without a device-wide cache write-back: partial
+// results are stored write-through at device (agent) scope and read back
+// with device-scope loads; a block waits for its stores to complete before
+// it signals arrival with a device-scope atomic.
+__device__ __forceinline__ void publish(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void publish_u32(unsigned int* p, unsigned int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double fetch(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned int arrive(unsigned int* p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt left at their maxima)
+__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // 1 / sqrt(x) for x > 0 from the hardware estimate and two Newton steps
 // (each roughly doubles the correct bits), within an ulp or two of the
 // correctly rounded value: one short dependent chain where sqrt and a

@@ -11,11 +11,12 @@
 // taken from X directly.
 //
 // The label update (q = 0 bilateral random projection with A2 = Y1) is
-//   km_gram   Y2 partials: per block, sum over its rows of N_row^T (N_row A1)
-//   km_reduce Y2 = the partials added in two fixed-order stages (FP64), a
-//             thread per entry of Y2 and range of partials
-//   km_orth   two Cholesky QR rounds with an FP64 Gram: Q = orth(Y2)
-//   km_update U_row = N_row Q, E_row = N_row - U_row Q^T
+//   km_gram / km_gram_v  Y2 partials: per block, sum over its rows of
+//                  N_row^T (N_row A1) (first update / updated label)
+//   km_reduce_orth Y2 = the partials added in a fixed order (FP64), then,
+//                  in the last block to finish, two Cholesky QR rounds with
+//                  an FP64 Gram: Q = orth(Y2)
+//   km_update      U_row = N_row Q, E_row = N_row - U_row Q^T
 // so that L^i_{Omega_i} = N Q Q^T = Y1 (A2^T Y1)^{-1} Y2^T.
 //
 // A wavefront owns one row at a time: lane l holds columns l + 64 s,
@@ -578,58 +579,63 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
   __syncthreads();
 }
 
-// Y2 from the block partials in two fixed-order stages: block (x, y) adds
-// the partials of its range y of kMseSplit consecutive ranges in ascending
-// order (a thread per entry, 32 partials in flight) into sub[y]; km_orth
-// then adds sub[0], sub[1], ... in order.
-constexpr int kMseSplit = 8;
+// Y2 from the block partials, in FP64 and a fixed order, then Q = orth(Y2).
+// A block of kOrthThreads takes 32 entries of Y2: thread (g, e) adds the
+// partials g, g + 16, g + 32, ... of entry e in ascending order (all its
+// loads in flight at once), then the sixteen group sums of each entry are
+// added in group order and stored write-through at device scope.  The last
+// block to arrive (a device-scope counter, reset by that block) reads all
+// of Y2 back with device-scope loads and runs the two Cholesky QR rounds.
+constexpr int kMseRedEntries = 32;
+constexpr int kMseRedGroups = kOrthThreads / kMseRedEntries;
 template <typename T, int PP>
-__global__ __launch_bounds__(256) void km_reduce(const T* __restrict__ part, int nblk,
-                                                 double* __restrict__ sub) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= PP * kMseRP) return;
-  const int per = (nblk + kMseSplit - 1) / kMseSplit;
-  const int b0 = blockIdx.y * per;
-  const int b1 = (b0 + per) < nblk ? (b0 + per) : nblk;
-  constexpr int F = 32;
-  double s = 0.0;
-  for (int c0 = b0; c0 < b1; c0 += F) {
-    T v[F];
-#pragma unroll
-    for (int j = 0; j < F; ++j)
-      v[j] = (c0 + j < b1) ? part[(int64_t)(c0 + j) * PP * kMseRP + e] : T(0);
-#pragma unroll
-    for (int j = 0; j < F; ++j)
-      if (c0 + j < b1) s += (double)v[j];
-  }
-  sub[(int64_t)blockIdx.y * PP * kMseRP + e] = s;
-}
-
-// Q = orth(Y2); one block of kOrthThreads.  Every thread loads all of its
-// entries' kMseSplit sub-sums at once (one memory round trip).
-template <typename T, int PP>
-__global__ __launch_bounds__(kOrthThreads) void km_orth(const double* __restrict__ y2, int r,
-                                                        T* __restrict__ Q) {
+__global__ __launch_bounds__(kOrthThreads) void km_reduce_orth(const T* __restrict__ part,
+                                                               int nblk, int r,
+                                                               double* __restrict__ y2,
+                                                               unsigned int* __restrict__ ctl,
+                                                               T* __restrict__ Q) {
+  constexpr int F = 16;   // partials per group: nblk <= F * kMseRedGroups
   constexpr int PER = PP * kMseRP / kOrthThreads;
   __shared__ double Y[PP * kMseRP];
   __shared__ double red[kOrthThreads];
   __shared__ double gsh[kMseRP * kMseRP];
   __shared__ int act[kMseRP];
+  __shared__ int last;
   const int tid = threadIdx.x;
   {
-    double v[PER][kMseSplit];
+    const int el = tid % kMseRedEntries, gq = tid / kMseRedEntries;
+    const int e = blockIdx.x * kMseRedEntries + el;
+    T v[F];
 #pragma unroll
-    for (int q = 0; q < PER; ++q)
-#pragma unroll
-      for (int y = 0; y < kMseSplit; ++y)
-        v[q][y] = y2[(int64_t)y * PP * kMseRP + q * kOrthThreads + tid];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      double sum = v[q][0];
-#pragma unroll
-      for (int y = 1; y < kMseSplit; ++y) sum += v[q][y];
-      Y[q * kOrthThreads + tid] = sum;
+    for (int k = 0; k < F; ++k) {
+      const int b = gq + kMseRedGroups * k;
+      v[k] = b < nblk ? part[(int64_t)b * PP * kMseRP + e] : T(0);
     }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < F; ++k)
+      if (gq + kMseRedGroups * k < nblk) sum += (double)v[k];
+    red[gq * kMseRedEntries + el] = sum;
+  }
+  __syncthreads();
+  if (tid < kMseRedEntries) {
+    double y = red[tid];
+#pragma unroll
+    for (int g = 1; g < kMseRedGroups; ++g) y += red[g * kMseRedEntries + tid];
+    publish(y2 + blockIdx.x * kMseRedEntries + tid, y);
+  }
+  stores_done();
+  __syncthreads();
+  if (tid == 0) last = arrive(ctl) == gridDim.x - 1u;
+  __syncthreads();
+  if (!last) return;
+  if (tid == 0) publish_u32(ctl, 0u);
+  {
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = fetch(y2 + q * kOrthThreads + tid);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) Y[q * kOrthThreads + tid] = v[q];
   }
   if (tid < kMseRP) act[tid] = tid < r ? 1 : 0;
   __syncthreads();
@@ -852,11 +858,9 @@ static void mse_label_t(const Launch& L, const MseLabelArgs& a) {
         hipLaunchKernelGGL((km_gram_v<T, S>), dim3((unsigned)a.nblk), dim3(256), 0, L.stream,
                            (const T*)a.E, a.lde, a.rows, a.nrows, a.p, (const T*)a.U,
                            (const T*)a.Vold, (const T*)a.A1, (T*)a.part);
-      hipLaunchKernelGGL((km_reduce<T, 64 * S>),
-                         dim3((64 * S * kMseRP + 255) / 256, kMseSplit), dim3(256), 0,
-                         L.stream, (const T*)a.part, a.nblk, a.y2);
-      hipLaunchKernelGGL((km_orth<T, 64 * S>), dim3(1), dim3(kOrthThreads), 0, L.stream,
-                         (const double*)a.y2, a.r, (T*)a.Vnew);
+      hipLaunchKernelGGL((km_reduce_orth<T, 64 * S>),
+                         dim3(64 * S * kMseRP / kMseRedEntries), dim3(kOrthThreads), 0,
+                         L.stream, (const T*)a.part, a.nblk, a.r, a.y2, a.ctl, (T*)a.Vnew);
       // the update writes no partials: a block per 16 rows
       int64_t nbu = (a.nrows + 15) / 16;
       nbu = nbu < 1 ? 1 : (nbu > (int64_t)L.num_cu * 8 ? (int64_t)L.num_cu * 8 : nbu);

@@ -56,25 +56,6 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ P, int np
 // dinv = 0, so the orthonormalised panel has a zero column, which stays zero
 // in every later product.
 // ---------------------------------------------------------------------------
-// Cross-block hand-off without a device-wide cache write-back: partial
-// results are stored write-through at device (agent) scope and read back
-// with device-scope loads; a block waits for its stores to complete before
-// it signals arrival with a device-scope atomic.
-__device__ __forceinline__ void publish(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void publish_u32(unsigned int* p, unsigned int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double fetch(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned int arrive(unsigned int* p) {
-  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt left at their maxima)
-__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
 __device__ __forceinline__ double lane_bcast(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
