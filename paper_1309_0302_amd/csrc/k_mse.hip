@@ -29,6 +29,15 @@ namespace godec {
 constexpr int kMseRP = 8;          // padded rank of every label
 constexpr int kMseWaves = 4;       // wavefronts per block of the row passes
 
+// The update pass stores E and U write-through to memory (device scope), so
+// that the kernel's end finds no dirty lines to write back (measured faster
+// for its full-row stores; the Y2 pass's partials are stored normally,
+// where the 16-byte stores the compiler forms pay more).
+template <typename T>
+__device__ __forceinline__ void store_wt(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ float lane_read(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -751,13 +760,13 @@ __global__ __launch_bounds__(256, 2) void km_update(T* __restrict__ E, int64_t l
         T l = T(0);
 #pragma unroll
         for (int t = 0; t < kMseRP; ++t) l = fma_t(w[t], qq[s][t], l);
-        if (col < p) E[gg[h] * lde + col] = nrow[s] - l;
+        if (col < p) store_wt(E + gg[h] * lde + col, nrow[s] - l);
       }
       // every lane holds w; lanes 0..7 store the row of U (its loads are done)
       T wl = w[0];
 #pragma unroll
       for (int t = 1; t < kMseRP; ++t) wl = (lane == t) ? w[t] : wl;
-      if (lane < kMseRP) U[j * kMseRP + lane] = wl;
+      if (lane < kMseRP) store_wt(U + j * kMseRP + lane, wl);
     }
     if (j0 + G * stride < nrows) load_group(j0 + G * stride);
   }
