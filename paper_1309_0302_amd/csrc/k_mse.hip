@@ -474,20 +474,26 @@ __global__ __launch_bounds__(256) void km_gram_v(const T* __restrict__ E, int64_
   }
 }
 
-// One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS, row-major) by
-// a block of kOrthThreads: Gram in a fixed order, Cholesky with the
-// dependent-column rule (a pivot at most tau * G_jj marks column j
+// One Cholesky QR round on the p_pad x 8 panel Y (FP64, LDS, rows padded to
+// kOrthLd doubles so that a wavefront's row reads do not collide in the
+// banks) by a block of kOrthThreads: Gram in a fixed order, Cholesky with
+// the dependent-column rule (a pivot at most tau * G_jj marks column j
 // dependent: zero row of R, zero column of the result), Y <- Y R^{-1}.
 // `act` holds the columns still in use.  The Gram takes no cross-lane
 // sums: thread (seg, a, b) adds Y[c][a] Y[c][b] over the rows c of segment
 // seg (four interleaved accumulators), then 64 threads add the eight
-// segments in order.  Every loop over the 8 columns is unrolled so that
-// all small arrays stay in registers.
+// segments in order.  The Cholesky factorisation and the substitution are
+// right-looking (each finished column is subtracted from all later ones at
+// once), which performs the same additions in the same order as the
+// column-by-column form with far shorter dependent chains.  Every loop over
+// the 8 columns is unrolled so that all small arrays stay in registers.
 constexpr int kOrthThreads = 512;
+constexpr int kOrthLd = kMseRP + 1;
 template <int PP>
 __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int* act, double* gsh,
                                double* red) {
   constexpr int R8 = kMseRP;
+  constexpr int LD = kOrthLd;
   constexpr int NE = R8 * (R8 + 1) / 2;   // entries a <= b
   constexpr int NSEG = kOrthThreads / (R8 * R8);
   constexpr int SEG = PP / NSEG;
@@ -499,11 +505,11 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
     const int seg = tid / (R8 * R8);
     const int a_ = ab / R8, b_ = ab % R8;
     double g4[4] = {0.0, 0.0, 0.0, 0.0};
-    const double* y = Y + seg * SEG * R8;
+    const double* y = Y + seg * SEG * LD;
 #pragma unroll 4
     for (int c = 0; c < SEG; c += 4) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) g4[k] = fma(y[(c + k) * R8 + a_], y[(c + k) * R8 + b_], g4[k]);
+      for (int k = 0; k < 4; ++k) g4[k] = fma(y[(c + k) * LD + a_], y[(c + k) * LD + b_], g4[k]);
     }
     const double gv = (a_ < r && b_ < r) ? (g4[0] + g4[1]) + (g4[2] + g4[3]) : 0.0;
     red[seg * R8 * R8 + ab] = gv;
@@ -519,20 +525,19 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
   __syncthreads();
   if (tid == 0) {
     // packed upper triangle, entry (a, b) at tri(a, b); G becomes R in place
-    // (row j of R needs only rows l < j of R and row j of G)
-    double T[NE];
+    double T[NE], gd[R8];
 #pragma unroll
     for (int q = 0; q < NE; ++q) T[q] = gsh[q];
+#pragma unroll
+    for (int j = 0; j < R8; ++j) gd[j] = T[tri(j, j)];
     int am = 0;
 #pragma unroll
     for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
 #pragma unroll
     for (int j = 0; j < R8; ++j) {
-      const double gjj = T[tri(j, j)];
-      double d = gjj;
-#pragma unroll
-      for (int l = 0; l < j; ++l) d -= T[tri(l, j)] * T[tri(l, j)];
-      const bool on = j < r && ((am >> j) & 1) && (d > tau * gjj) && (gjj > 0.0);
+      // T[j][j..] already has the rows l < j of R subtracted
+      const double d = T[tri(j, j)];
+      const bool on = j < r && ((am >> j) & 1) && (d > tau * gd[j]) && (gd[j] > 0.0);
       if (!on) {
         am &= ~(1 << j);
 #pragma unroll
@@ -543,15 +548,13 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
       // 1 / r_jj from a Newton-refined reciprocal square root: the rows of R
       // and the substitution below multiply by it instead of dividing
       const double ir = rsqrt_nr(d);
-      const double rjj = d * ir;
+      T[tri(j, j)] = d * ir;
 #pragma unroll
-      for (int b_ = j + 1; b_ < R8; ++b_) {
-        double sv = T[tri(j, b_)];
+      for (int b_ = j + 1; b_ < R8; ++b_) T[tri(j, b_)] *= ir;
 #pragma unroll
-        for (int l = 0; l < j; ++l) sv -= T[tri(l, j)] * T[tri(l, b_)];
-        T[tri(j, b_)] = sv * ir;
-      }
-      T[tri(j, j)] = rjj;
+      for (int a_ = j + 1; a_ < R8; ++a_)
+#pragma unroll
+        for (int b_ = a_; b_ < R8; ++b_) T[tri(a_, b_)] -= T[tri(j, a_)] * T[tri(j, b_)];
       gsh[NE + j] = ir;
     }
 #pragma unroll
@@ -560,7 +563,8 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
     for (int q = 0; q < NE; ++q) gsh[q] = T[q];
   }
   __syncthreads();
-  // Y <- Y R^{-1} on the active columns (forward substitution per row)
+  // Y <- Y R^{-1} on the active columns (forward substitution per row; an
+  // inactive column has a zero row of R and a zero result)
   int am = 0;
 #pragma unroll
   for (int j = 0; j < R8; ++j) am |= act[j] ? (1 << j) : 0;
@@ -570,20 +574,18 @@ __device__ __forceinline__ void mse_chol_round(double* Y, int r, double tau, int
 #pragma unroll
   for (int j = 0; j < R8; ++j) rinv[j] = gsh[NE + j];
   for (int c = tid; c < PP; c += kOrthThreads) {
-    double y[R8], qv[R8];
+    double sv[R8];
 #pragma unroll
-    for (int t = 0; t < R8; ++t) y[t] = Y[c * R8 + t];
+    for (int t = 0; t < R8; ++t) sv[t] = Y[c * LD + t];
 #pragma unroll
     for (int j = 0; j < R8; ++j) {
-      if (!((am >> j) & 1)) { qv[j] = 0.0; continue; }
-      double sv = y[j];
+      const double qj = ((am >> j) & 1) ? sv[j] * rinv[j] : 0.0;
+      sv[j] = qj;
 #pragma unroll
-      for (int l = 0; l < j; ++l)
-        if ((am >> l) & 1) sv -= qv[l] * rr[tri(l, j)];
-      qv[j] = sv * rinv[j];
+      for (int b_ = j + 1; b_ < R8; ++b_) sv[b_] -= qj * rr[tri(j, b_)];
     }
 #pragma unroll
-    for (int t = 0; t < R8; ++t) Y[c * R8 + t] = qv[t];
+    for (int t = 0; t < R8; ++t) Y[c * LD + t] = sv[t];
   }
   __syncthreads();
 }
@@ -605,7 +607,7 @@ __global__ __launch_bounds__(kOrthThreads) void km_reduce_orth(const T* __restri
                                                                T* __restrict__ Q) {
   constexpr int F = 16;   // partials per group: nblk <= F * kMseRedGroups
   constexpr int PER = PP * kMseRP / kOrthThreads;
-  __shared__ double Y[PP * kMseRP];
+  __shared__ double Y[PP * kOrthLd];
   __shared__ double red[kOrthThreads];
   __shared__ double gsh[kMseRP * kMseRP];
   __shared__ int act[kMseRP];
@@ -644,7 +646,10 @@ __global__ __launch_bounds__(kOrthThreads) void km_reduce_orth(const T* __restri
 #pragma unroll
     for (int q = 0; q < PER; ++q) v[q] = fetch(y2 + q * kOrthThreads + tid);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) Y[q * kOrthThreads + tid] = v[q];
+    for (int q = 0; q < PER; ++q) {
+      const int e = q * kOrthThreads + tid;
+      Y[(e / kMseRP) * kOrthLd + e % kMseRP] = v[q];
+    }
   }
   if (tid < kMseRP) act[tid] = tid < r ? 1 : 0;
   __syncthreads();
@@ -653,7 +658,10 @@ __global__ __launch_bounds__(kOrthThreads) void km_reduce_orth(const T* __restri
   mse_chol_round<PP>(Y, r, tau, act, gsh, red);
   mse_chol_round<PP>(Y, r, tau, act, gsh, red);
 #pragma unroll
-  for (int q = 0; q < PER; ++q) Q[q * kOrthThreads + tid] = (T)Y[q * kOrthThreads + tid];
+  for (int q = 0; q < PER; ++q) {
+    const int e = q * kOrthThreads + tid;
+    Q[e] = (T)Y[(e / kMseRP) * kOrthLd + e % kMseRP];
+  }
 }
 
 // U_row = N_row Q and E_row = N_row - U_row Q^T for every row of the label,
