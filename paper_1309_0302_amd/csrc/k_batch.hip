@@ -844,12 +844,34 @@ __global__ __launch_bounds__(256) void kb_update_d(const BProb* __restrict__ pro
   const BProb& b = probs[blockIdx.y];
   if (restore && *iter == 0) return;
   const long long nnz = b.sel->nnz_list[list];
-  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nnz;
-       e += (long long)gridDim.x * 256) {
-    const int64_t idx = b.s_idx[list][e];
-    const int64_t i = idx / b.n, j = idx % b.n;
-    const float x = b.s_x[list][e];
-    b.D[i * b.ldd + j] = restore ? x : x - b.s_val[list][e];
+  const int64_t n = b.n;
+  const double rn = 1.0 / (double)n;
+  const int64_t* __restrict__ sidx = b.s_idx[list];
+  const float* __restrict__ sx = b.s_x[list];
+  const float* __restrict__ sv = b.s_val[list];
+  float* __restrict__ D = b.D;
+  const int64_t ldd = b.ldd;
+  // U entries per thread and round, all loads in flight before the stores
+  constexpr int U = 4;
+  const long long step = (long long)gridDim.x * 256;
+  for (long long e0 = (long long)blockIdx.x * 256 + threadIdx.x; e0 < nnz; e0 += U * step) {
+    int64_t idx[U];
+    float x[U], v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long e = e0 + u * step;
+      const bool ok = e < nnz;
+      idx[u] = ok ? sidx[e] : -1;
+      x[u] = ok ? sx[e] : 0.f;
+      v[u] = (ok && !restore) ? sv[e] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (idx[u] < 0) continue;
+      int64_t i, j;
+      divmod_nn(idx[u], n, rn, i, j);
+      D[i * ldd + j] = restore ? x[u] : x[u] - v[u];
+    }
   }
 }
 
