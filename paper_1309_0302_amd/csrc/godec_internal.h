@@ -73,6 +73,8 @@ struct SelPlan {
   double sum_sel2;             // sum of R^2 over the selected entries
   double threshold;            // |R| of the threshold key
   double sum_obs2;             // fixed support only: sum of R^2 off the support
+  unsigned int arrivals;       // blocks of a pass that finished (its last one plans)
+  int spare;
 };
 
 // Threshold carried between iterations: the level-0 digit window start.

@@ -658,109 +658,42 @@ __global__ __launch_bounds__(256) void k_sel_pass0(const T* __restrict__ X, int6
 // Later passes (first iteration and fall-backs): the level-0 histogram
 // again (after a missed carry), deeper digits, collection from the bucket,
 // or collection above a resolved threshold whose ties overflow the buffer.
-template <typename T, int RP>
-__global__ __launch_bounds__(256) void k_sel_passN(const T* __restrict__ X, int64_t ldx,
-                                                   const T* __restrict__ UL,
-                                                   const T* __restrict__ VLt, int64_t ldv,
-                                                   int64_t m, int64_t n,
-                                                   SelPlan* __restrict__ plan,
-                                                   unsigned long long* __restrict__ hist,
-                                                   int64_t* __restrict__ cand_idx,
-                                                   T* __restrict__ cand_val,
-                                                   T* __restrict__ cand_x,
-                                                   unsigned int* __restrict__ seg_count) {
-  const int mode = plan->mode;
-  if (mode != SEL_HIST && mode != SEL_COLLECT && mode != SEL_TIES) return;
-  GODEC_SEL_SHARED
-  const unsigned long long prefix = plan->prefix;
-  const int pbits = plan->pbits;
-  const int dbits = digit_bits(pbits, KB);
-  const bool do_hist = (mode == SEL_HIST);
-  PassKeys<T> pk = keys_level0<T>();
-  if (pbits > 0) {
-    pk.klo = (K)(prefix << (KB - pbits));
-    pk.kspan = (K)(K(1) << (KB - pbits));
-    pk.shift = KB - pbits - dbits;
-    pk.mask = (K)((K(1) << dbits) - 1);
-    pk.kmin = pk.klo > 0 ? pk.klo : K(1);
-  }
-  if (mode == SEL_TIES) pk.kmin = (K)prefix + 1;   // prefix is the full threshold key
-  if (do_hist)
-    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
-  const bool vec_ok = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
-  __syncthreads();
-  double s2 = 0.0;
-  if (do_hist)
-    sel_pass_body<T, RP, true, false, false>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
-                                             vec_ok, s2);
-  else
-    sel_pass_body<T, RP, false, true, false>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
-                                             vec_ok, s2);
-  __syncthreads();
-  if (!do_hist) { GODEC_SEL_SEG_CLOSE }
-  if (do_hist) {
-    const int bins = 1 << dbits;
-    unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
-    for (int e = tid; e < bins; e += 256)
-      if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
-  }
-}
-
-// Histogram of the next digit over the candidates inside the bucket.
-template <typename T>
-__global__ __launch_bounds__(256) void k_cand_hist(SelPlan* __restrict__ plan,
-                                                   const T* __restrict__ cand_val,
-                                                   const unsigned int* __restrict__ seg_count,
-                                                   unsigned long long* __restrict__ hist) {
-  constexpr int KB = KeyBits<T>::value;
-  __shared__ unsigned int lh[kHistBins];
-  if (plan->mode != SEL_REFINE) return;
-  const unsigned long long prefix = plan->prefix;
-  const int pbits = plan->pbits;
-  const int dbits = digit_bits(pbits, KB);
-  for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
-  __syncthreads();
-  const int ntot = seg_total(plan);
-  for (int sg = blockIdx.x; sg < ntot; sg += gridDim.x) {
-    long long base, cnt;
-    seg_range(plan, seg_count, sg, base, cnt);
-    for (long long c = base + threadIdx.x; c < base + cnt; c += 256) {
-      const unsigned long long key = abs_key(cand_val[c]);
-      if ((key >> (KB - pbits)) == prefix)
-        atomicAdd(&lh[(key >> (KB - pbits - dbits)) & ((1ull << dbits) - 1)], 1u);
-    }
-  }
-  __syncthreads();
-  unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
-  for (int e = threadIdx.x; e < (1 << dbits); e += 256)
-    if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
-}
-
 // Advance the plan.  One block.  stage 0 follows a full-data pass (which
 // histogrammed in SEL_HIST or collected in SEL_COLLECT); stage 1 follows a
 // candidate histogram (SEL_REFINE).  In any other combination the preceding
 // kernel did nothing and neither does this one.  The digit holding the
 // k_rem-th largest key is found with a block-wide suffix scan.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
-                                                  unsigned long long* __restrict__ hist,
-                                                  int stage, const double* __restrict__ s2part,
-                                                  int ns2) {
+//
+// sel_plan_core runs either as the kernel k_sel_plan (COH = false) or in
+// the last block to finish the pass or candidate histogram it follows
+// (COH = true): then the histogram, which the pass's blocks added to with
+// device-scope atomics, and the spill counter are read with device-scope
+// loads, and the bins are counted in 32 bits in the pass's own LDS (the
+// host uses this form only when m n < 2^32).
+template <bool COH>
+__device__ __forceinline__ unsigned long long hist_load(const unsigned long long* p) {
+  if constexpr (COH)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool COH>
+__device__ __forceinline__ long long ncand_load(const SelPlan* plan) {
+  if constexpr (COH)
+    return __hip_atomic_load(&plan->ncand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return plan->ncand;
+}
+
+template <typename T, typename HT, bool COH>
+__device__ void sel_plan_core(SelPlan* __restrict__ plan, unsigned long long* __restrict__ hist,
+                              int stage, HT* h, unsigned long long* part, int* sel_t) {
   constexpr int KB = KeyBits<T>::value;
-  __shared__ unsigned long long h[kHistBins];
-  __shared__ unsigned long long part[256];
-  __shared__ int sel_t;
-  __shared__ double red[8];
   const int tid = threadIdx.x;
-  if (s2part) {
-    // right after pass 0: its per-block sums of R^2, added in block order
-    const double s = block_sum_fixed(s2part, ns2, red);
-    if (tid == 0) plan->sum_r2 = s;
-  }
   const int mode = plan->mode;
   if (stage == 0 && (mode == SEL_COLLECT || mode == SEL_TIES)) {
     if (tid == 0) {
-      if (plan->ncand > plan->cap) plan->overflow = 1;
+      if (ncand_load<COH>(plan) > plan->cap) plan->overflow = 1;
       if (mode == SEL_TIES) plan->mode = SEL_TSCAN;
       else plan->mode = (plan->pbits == KB) ? SEL_FINAL : SEL_REFINE;
     }
@@ -772,19 +705,23 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
   const int bins = 1 << dbits;
   const int per = (bins + 255) / 256;
   // sum the replicas in replica order (and clear them for the next
-  // histogram); every load of the thread is issued before the first add
+  // histogram); every load of a batch is issued before the first add: all
+  // of the thread's bins at once in the kernel, UB bins at a time in the
+  // last block of a pass (whose register budget is the pass's)
   constexpr int MAXPER = (kHistBins + 255) / 256;
-  {
-    unsigned long long v[MAXPER][kHistRep];
+  constexpr int UB = COH ? 2 : MAXPER;
+  for (int u0 = 0; u0 < MAXPER; u0 += UB) {
+    unsigned long long v[UB][kHistRep];
 #pragma unroll
-    for (int u = 0; u < MAXPER; ++u) {
-      const int e = tid + 256 * u;
+    for (int u = 0; u < UB; ++u) {
+      const int e = tid + 256 * (u0 + u);
 #pragma unroll
-      for (int r = 0; r < kHistRep; ++r) v[u][r] = e < bins ? hist[r * kHistBins + e] : 0ull;
+      for (int r = 0; r < kHistRep; ++r)
+        v[u][r] = e < bins ? hist_load<COH>(hist + r * kHistBins + e) : 0ull;
     }
 #pragma unroll
-    for (int u = 0; u < MAXPER; ++u) {
-      const int e = tid + 256 * u;
+    for (int u = 0; u < UB; ++u) {
+      const int e = tid + 256 * (u0 + u);
       if (e < bins) {
         unsigned long long acc = 0;
 #pragma unroll
@@ -792,7 +729,7 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
           acc += v[u][r];
           hist[r * kHistBins + e] = 0ull;
         }
-        h[e] = acc;
+        h[e] = (HT)acc;
       }
     }
   }
@@ -804,7 +741,7 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
     if (d >= 0) s += h[d];
   }
   part[tid] = s;
-  if (tid == 0) sel_t = -1;
+  if (tid == 0) *sel_t = -1;
   __syncthreads();
   // inclusive scan of part[] (Hillis-Steele)
   for (int off = 1; off < 256; off <<= 1) {
@@ -815,15 +752,15 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
   }
   const long long k_rem = plan->k_rem;
   const unsigned long long before = tid > 0 ? part[tid - 1] : 0ull;
-  if (before < (unsigned long long)k_rem && part[tid] >= (unsigned long long)k_rem) sel_t = tid;
+  if (before < (unsigned long long)k_rem && part[tid] >= (unsigned long long)k_rem) *sel_t = tid;
   __syncthreads();
   if (tid == 0) {
     int dsel = -1;
     unsigned long long cum = 0;
-    if (sel_t >= 0) {
-      cum = sel_t > 0 ? part[sel_t - 1] : 0ull;
+    if (*sel_t >= 0) {
+      cum = *sel_t > 0 ? part[*sel_t - 1] : 0ull;
       for (int u = 0; u < per; ++u) {
-        const int d = bins - 1 - (sel_t * per + u);
+        const int d = bins - 1 - (*sel_t * per + u);
         if (d < 0) break;
         if (cum + h[d] >= (unsigned long long)k_rem) { dsel = d; break; }
         cum += h[d];
@@ -833,7 +770,7 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
       // pass 0 histogrammed and collected only digits >= carry_dlo: accept
       // when the k-th key lies there and every candidate was kept;
       // otherwise fall back to the full level-0 histogram in the next pass
-      if (dsel < 0 || plan->ncand > plan->cap) {
+      if (dsel < 0 || ncand_load<COH>(plan) > plan->cap) {
         plan->carry_used = 0;
         plan->ncand = 0;
         plan->slow = 1;
@@ -878,6 +815,126 @@ __global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
     }
     plan->mode = next;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sel_plan(SelPlan* __restrict__ plan,
+                                                  unsigned long long* __restrict__ hist,
+                                                  int stage, const double* __restrict__ s2part,
+                                                  int ns2) {
+  __shared__ unsigned long long h[kHistBins];
+  __shared__ unsigned long long part[256];
+  __shared__ int sel_t;
+  __shared__ double red[8];
+  if (s2part) {
+    // right after pass 0: its per-block sums of R^2, added in block order
+    const double s = block_sum_fixed(s2part, ns2, red);
+    if (threadIdx.x == 0) plan->sum_r2 = s;
+  }
+  sel_plan_core<T, unsigned long long, false>(plan, hist, stage, h, part, &sel_t);
+}
+
+// End of a pass or candidate histogram that plans in its last block: every
+// block waits for its histogram atomics and stores to complete and signals
+// arrival; the last one resets the counter and advances the plan in the
+// LDS the pass no longer needs (h: kHistBins 32-bit bins, part: 256 u64).
+template <typename T>
+__device__ __forceinline__ void plan_in_last_block(SelPlan* __restrict__ plan,
+                                                   unsigned long long* __restrict__ hist,
+                                                   int stage, unsigned int* h,
+                                                   unsigned long long* part, int* flags) {
+  stores_done();
+  __syncthreads();
+  if (threadIdx.x == 0) flags[0] = arrive(&plan->arrivals) == gridDim.x - 1u;
+  __syncthreads();
+  if (!flags[0]) return;
+  if (threadIdx.x == 0) publish_u32(&plan->arrivals, 0u);
+  sel_plan_core<T, unsigned int, true>(plan, hist, stage, h, part, flags + 1);
+}
+
+template <typename T, int RP>
+__global__ __launch_bounds__(256) void k_sel_passN(const T* __restrict__ X, int64_t ldx,
+                                                   const T* __restrict__ UL,
+                                                   const T* __restrict__ VLt, int64_t ldv,
+                                                   int64_t m, int64_t n,
+                                                   SelPlan* __restrict__ plan,
+                                                   unsigned long long* __restrict__ hist,
+                                                   int64_t* __restrict__ cand_idx,
+                                                   T* __restrict__ cand_val,
+                                                   T* __restrict__ cand_x,
+                                                   unsigned int* __restrict__ seg_count,
+                                                   int fuse_plan) {
+  const int mode = plan->mode;
+  if (mode != SEL_HIST && mode != SEL_COLLECT && mode != SEL_TIES) return;
+  GODEC_SEL_SHARED
+  __shared__ int pl_flags[2];
+  const unsigned long long prefix = plan->prefix;
+  const int pbits = plan->pbits;
+  const int dbits = digit_bits(pbits, KB);
+  const bool do_hist = (mode == SEL_HIST);
+  PassKeys<T> pk = keys_level0<T>();
+  if (pbits > 0) {
+    pk.klo = (K)(prefix << (KB - pbits));
+    pk.kspan = (K)(K(1) << (KB - pbits));
+    pk.shift = KB - pbits - dbits;
+    pk.mask = (K)((K(1) << dbits) - 1);
+    pk.kmin = pk.klo > 0 ? pk.klo : K(1);
+  }
+  if (mode == SEL_TIES) pk.kmin = (K)prefix + 1;   // prefix is the full threshold key
+  if (do_hist)
+    for (int e = tid; e < kHistBins; e += 256) lh[e] = 0u;
+  const bool vec_ok = (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0);
+  __syncthreads();
+  double s2 = 0.0;
+  if (do_hist)
+    sel_pass_body<T, RP, true, false, false>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
+                                             vec_ok, s2);
+  else
+    sel_pass_body<T, RP, false, true, false>(X, ldx, UL, VLt, ldv, m, n, lh, us, pk, sink,
+                                             vec_ok, s2);
+  __syncthreads();
+  if (!do_hist) { GODEC_SEL_SEG_CLOSE }
+  if (do_hist) {
+    const int bins = 1 << dbits;
+    unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
+    for (int e = tid; e < bins; e += 256)
+      if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
+  }
+  // the plan step in the last block (its LDS: lh for the bins, the index
+  // ring for the scan)
+  if (fuse_plan)
+    plan_in_last_block<T>(plan, hist, 0, lh, reinterpret_cast<unsigned long long*>(ring_i),
+                          pl_flags);
+}
+
+// Histogram of the next digit over the candidates inside the bucket.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cand_hist(SelPlan* __restrict__ plan,
+                                                   const T* __restrict__ cand_val,
+                                                   const unsigned int* __restrict__ seg_count,
+                                                   unsigned long long* __restrict__ hist) {
+  constexpr int KB = KeyBits<T>::value;
+  __shared__ unsigned int lh[kHistBins];
+  if (plan->mode != SEL_REFINE) return;
+  const unsigned long long prefix = plan->prefix;
+  const int pbits = plan->pbits;
+  const int dbits = digit_bits(pbits, KB);
+  for (int e = threadIdx.x; e < (1 << dbits); e += 256) lh[e] = 0u;
+  __syncthreads();
+  const int ntot = seg_total(plan);
+  for (int sg = blockIdx.x; sg < ntot; sg += gridDim.x) {
+    long long base, cnt;
+    seg_range(plan, seg_count, sg, base, cnt);
+    for (long long c = base + threadIdx.x; c < base + cnt; c += 256) {
+      const unsigned long long key = abs_key(cand_val[c]);
+      if ((key >> (KB - pbits)) == prefix)
+        atomicAdd(&lh[(key >> (KB - pbits - dbits)) & ((1ull << dbits) - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  unsigned long long* hrep = hist + (int64_t)(blockIdx.x % kHistRep) * kHistBins;
+  for (int e = threadIdx.x; e < (1 << dbits); e += 256)
+    if (lh[e]) atomicAdd(&hrep[e], (unsigned long long)lh[e]);
 }
 
 // FINAL: write S from the candidates.  Entries above the threshold key go
@@ -1385,6 +1442,7 @@ __global__ void k_sel_reset(SelPlan* plan, unsigned long long* hist,
     plan->sum_r2 = 0.0; plan->sum_sel2 = 0.0; plan->threshold = 0.0;
     plan->carry_used = carry->valid ? 1 : 0;
     plan->carry_dlo = carry->dlo;
+    plan->arrivals = 0u;
     counters[0] = 0; counters[1] = 0;
   }
 }
@@ -1653,6 +1711,10 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
   const int levels = 1 + (KB - kHistBits0 + kHistBits - 1) / kHistBits;
   const int64_t g = sel_grid<T>(rp, a.m, a.n, L.num_cu);
   const int nseg = (int)g * kSelWaves;
+  // the passes after pass 0 advance the plan in their last block (32-bit
+  // bin counts: m n < 2^32), so a pass with nothing to do costs one launch;
+  // otherwise, and after pass 0 and the candidate histograms, k_sel_plan
+  const bool fuse = (uint64_t)a.m * (uint64_t)a.n < (1ull << 32);
   hipLaunchKernelGGL(k_sel_reset<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist,
                      a.counters, a.seg_count, (long long)a.k, (long long)a.cap, nseg, a.carry);
   GODEC_RP_SWITCH(rp, {
@@ -1671,10 +1733,11 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
         hipLaunchKernelGGL((k_sel_passN<T, RP>), dim3((unsigned)g), dim3(256), 0, L.stream,
                            (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VLt, a.ldv, a.m,
                            a.n, a.plan, a.hist, a.cand_idx, (T*)a.cand_val, (T*)a.cand_x,
-                           a.seg_count);
+                           a.seg_count, fuse ? 1 : 0);
       }
-      hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 0,
-                         pass == 0 ? (const double*)a.s2part : nullptr, (int)g);
+      if (pass == 0 || !fuse)
+        hipLaunchKernelGGL(k_sel_plan<T>, dim3(1), dim3(256), 0, L.stream, a.plan, a.hist, 0,
+                           pass == 0 ? (const double*)a.s2part : nullptr, (int)g);
     }
   });
   const unsigned cg = (unsigned)(g + 1);   // segments are taken round-robin by blocks
