@@ -255,6 +255,22 @@ godec_status godec_profile(godec_ctx* ctx, int32_t enable);
 godec_status godec_profile_read(godec_ctx* ctx, godec_kernel_stat* out,
                                 int32_t cap, int32_t* count);
 
+/* ---- Graph replay of the iteration -------------------------------------
+ * enable != 0: godec_step records each steady iteration shape (the two
+ * parities of the double-buffered S lists, with or without the FP32 copy of
+ * D in step) once into a HIP graph, on a private stream of the context, and
+ * from then on launches that graph on the context's stream: the same kernels
+ * with the same arguments and results, one host call per iteration and a
+ * shorter dispatch gap between kernels (measured on MI355X: about 1.5 us per
+ * kernel against 2.4 us launched one by one).  The first iteration, the
+ * refinement iterations of GODEC_PREC_BF16_REFINE and iterations run while
+ * per-kernel timing is enabled are launched directly.  Recording and
+ * instantiating allocate host and device memory: a caller that must not
+ * allocate leaves replay off, the default.  An error while recording leaves
+ * the context unusable (destroy it).  Not to be called concurrently with other
+ * calls on the same context. */
+godec_status godec_set_graphs(godec_ctx* ctx, int32_t enable);
+
 /* ---- Batched form: many independent FP32 problems ----------------------
  * Runs Algorithm 1 (Sec. 3.1.3) on `count` independent problems at once: every
  * phase of an iteration (the Gram passes of the power scheme, Eq. 6-9; the

@@ -90,6 +90,7 @@ _SIG = {
                           _I64, _I32, ctypes.c_uint64, _P, ctypes.c_size_t,
                           ctypes.POINTER(godec_opts)]),
     "godec_step": (_I32, [_P, _I32, _I32]),
+    "godec_set_graphs": (_I32, [_P, _I32]),
     "godec_solve": (_I32, [_P, _I32, _I64, _I64, _I64, _I32, _I64, _I32,
                            ctypes.c_uint64, _I32, _P, ctypes.c_size_t,
                            ctypes.POINTER(godec_opts), _P, _P, _P, _P,
@@ -402,6 +403,10 @@ class GoDec:
 
     def step(self, iters=1, total_iters=0):
         godec_step(self.ctx, iters, total_iters)
+
+    def graphs(self, enable=True):
+        """Replay steady iterations from recorded HIP graphs (godec_set_graphs)."""
+        _check(load().godec_set_graphs(self.ctx, 1 if enable else 0))
 
     def factors(self):
         import torch

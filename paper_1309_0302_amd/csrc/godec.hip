@@ -95,6 +95,12 @@ struct godec_ctx {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
+  // graph replay (godec_set_graphs): one executable graph per steady
+  // iteration shape, recorded on a private stream, launched on `stream`
+  bool graphs = false;
+  hipStream_t cap_stream = nullptr;
+  struct GraphEntry { int key; hipGraphExec_t exec; };
+  std::vector<GraphEntry> gcache;
 };
 
 PanelPlan godec_host::plan_sizes(int64_t m, int64_t n, int64_t k, int num_cu) {
@@ -664,14 +670,71 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   return GODEC_OK;
 }
 
+// Record one iteration on the capture stream (run_iteration advances the
+// host state as it records) and instantiate it.
+godec_status capture_iteration(godec_ctx* c, int64_t t, int64_t total, hipGraphExec_t* out) {
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->stream = user;
+    return fail(GODEC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  godec_status s = run_iteration(c, t, total);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  c->stream = user;
+  if (s != GODEC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(GODEC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(GODEC_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return GODEC_OK;
+}
+
 godec_status godec_step(godec_ctx* c, int32_t iters, int32_t total_iters) {
   if (!c) return fail(GODEC_E_INVAL, "ctx is NULL");
   if (iters < 0) return fail(GODEC_E_INVAL, "iters < 0");
   int64_t total = total_iters > 0 ? total_iters : c->iters_done + iters;
+  const bool mixed = c->prec == GODEC_PREC_BF16_REFINE;
   for (int32_t i = 0; i < iters; ++i) {
-    godec_status s = run_iteration(c, c->iters_done, total);
-    if (s != GODEC_OK) return s;
+    const int64_t t = c->iters_done;
+    const bool refine = mixed && total > 0 && t >= total - c->refine_iters;
+    // the first iteration, the refinement iterations (which rebuild the FP32
+    // copy of D once) and traced iterations run eagerly; every other
+    // iteration's launches depend only on the S-list parity and on whether
+    // the FP32 copy of D is kept in step
+    if (!c->graphs || c->prof || t == 0 || refine) {
+      godec_status s = run_iteration(c, t, total);
+      if (s != GODEC_OK) return s;
+      continue;
+    }
+    const int key = c->cur | (c->d_native_valid ? 2 : 0);
+    hipGraphExec_t exec = nullptr;
+    for (const auto& ge : c->gcache)
+      if (ge.key == key) exec = ge.exec;
+    if (!exec) {
+      godec_status s = capture_iteration(c, t, total, &exec);
+      if (s != GODEC_OK) return s;
+      c->gcache.push_back({key, exec});
+    } else {
+      // the host state a recorded iteration advances
+      c->cur ^= 1;
+      c->iters_done += 1;
+    }
+    HIP_TRY(hipGraphLaunch(exec, c->stream));
   }
+  return GODEC_OK;
+}
+
+godec_status godec_set_graphs(godec_ctx* c, int32_t enable) {
+  if (!c) return fail(GODEC_E_INVAL, "ctx is NULL");
+  if (enable && !c->cap_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  c->graphs = enable != 0;
   return GODEC_OK;
 }
 
@@ -754,6 +817,9 @@ godec_status godec_get_info(godec_ctx* c, godec_info* info) {
 
 godec_status godec_destroy(godec_ctx* c) {
   if (c) {
+    if (!c->gcache.empty()) (void)hipStreamSynchronize(c->stream);
+    for (const auto& ge : c->gcache) (void)hipGraphExecDestroy(ge.exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
   }
