@@ -435,12 +435,31 @@ def run_completion(X, w, iters, warmup, frac=0.1, seed=1008):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     info = gd.info()
+    UL, VL = gd.factors()
     gd.close()
-    return {"workload": f"m1_{m}x{n}_r{w.r}_q{w.q}_missing{frac:g}_f32",
-            "unobserved": int(sup.numel()), "iterations": iters,
-            "ms_per_iteration": round(ms / iters, 4),
-            "iter_per_s": round(iters * 1e3 / ms, 2),
-            "rel_err_sq_observed": info["rel_err_sq"]}
+    out = {"workload": f"m1_{m}x{n}_r{w.r}_q{w.q}_missing{frac:g}_f32",
+           "unobserved": int(sup.numel()), "iterations": iters,
+           "ms_per_iteration": round(ms / iters, 4),
+           "iter_per_s": round(iters * 1e3 / ms, 2),
+           "rel_err_sq_observed": info["rel_err_sq"]}
+    # the BF16 panel form (last iteration refined in FP32), same solve
+    from paper_1309_0302_amd.binding import GODEC_PREC_BF16_REFINE
+    gb = GoDec(X, w.r, int(sup.numel()), w.q, seed=w.seed, support=sup,
+               prec=GODEC_PREC_BF16_REFINE)
+    torch.cuda.synchronize()
+    e0.record()
+    gb.step(iters, iters)
+    e1.record()
+    torch.cuda.synchronize()
+    msb = e0.elapsed_time(e1)
+    infob = gb.info()
+    ULb, VLb = gb.factors()
+    gb.close()
+    out["bf16_refine"] = {"ms_per_iteration": round(msb / iters, 4),
+                          "iter_per_s": round(iters * 1e3 / msb, 2),
+                          "rel_err_sq_observed": infob["rel_err_sq"],
+                          "rel_diff_L_vs_f32": rel_diff_factors(ULb, VLb, UL, VL)}
+    return out
 
 
 def mse_bytes(w):

@@ -88,9 +88,11 @@ typedef struct {
    * i*n + j at support_dev (device memory, strictly ascending, in [0, m*n),
    * borrowed and unmodified until destroy; checked during godec_init).  The
    * support is the set of unobserved entries: D = X - S_t then holds X on
-   * the observed entries and L_t on the others.  Requires k == support_nnz
-   * and prec NATIVE.  info.rel_err_sq is the squared error on the observed
-   * entries over ||X||_F^2; info.threshold is 0. */
+   * the observed entries and L_t on the others.  Requires k == support_nnz;
+   * either precision form (with BF16_REFINE the bf16 copy of D is rewritten
+   * on the support every iteration and the refinement iterations rebuild
+   * the FP32 copy from X and S).  info.rel_err_sq is the squared error on
+   * the observed entries over ||X||_F^2; info.threshold is 0. */
   const int64_t* support_dev;
   int64_t support_nnz;
   /* 1: every power chain after the first starts from the previous

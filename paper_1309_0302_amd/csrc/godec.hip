@@ -228,8 +228,6 @@ godec_status validate(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
       if (o->support_nnz > 0 && o->support_dev == nullptr)
         return fail(GODEC_E_INVAL, "support_dev is NULL");
       if (o->support_nnz != k) return fail(GODEC_E_INVAL, "completion needs k == support_nnz");
-      if (o->prec != GODEC_PREC_NATIVE)
-        return fail(GODEC_E_UNSUPPORTED, "completion runs in the NATIVE precision form");
     }
   }
   return GODEC_OK;
