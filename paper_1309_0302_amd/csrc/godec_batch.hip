@@ -245,6 +245,7 @@ void enqueue_iteration(godec_batch* b, int cur) {
     in = 0;
   }
   bl_pass(L, a, in, 1);
+  bl_restore_d(L, a, cur, b->max_k);   // the last read of D in this iteration is done
   bl_core(L, a, b->q == 0 ? 1 : 0);
   bl_apply_k(L, a, b->max_m);
   bl_select(L, a, cur, b->max_k);

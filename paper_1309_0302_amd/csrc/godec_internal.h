@@ -355,7 +355,11 @@ void bl_apply_k(const Launch& L, const BatchArgs& a, int64_t max_m);
 void bl_reduce_slots(const Launch& L, const BatchArgs& a, int64_t max_n);
 // sparse step
 void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
-// (bl_update_d also advances the device iteration counter)
+// D = X on the old S list (after the last pass that reads D; the selection
+// reads X); kb_compact then writes X - S on the new list's entries above the
+// threshold and bl_update_d on its ties (and advances the device iteration
+// counter)
+void bl_restore_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k);
 void bl_init(const Launch& L, const BatchArgs& a);   // D = X, norms, state
 void bl_copy_lists(const Launch& L, const BProb* probs_dev, int nprob, int list, int64_t kmax,

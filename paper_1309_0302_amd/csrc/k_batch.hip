@@ -608,6 +608,7 @@ __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ prob
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tkey = (uint32_t)s->prefix;
   const long long kcap = s->count_above;
+  const double rn = 1.0 / (double)b.n;
   const ColMap cm = colmap((int)b.n);
   const int nseg = b.nitems * 4;
   const int item0 = b.item0;
@@ -676,10 +677,17 @@ __global__ __launch_bounds__(256) void kb_compact(const BProb* __restrict__ prob
         if (above) {
           const unsigned long long pos = pa + rank;
           if ((long long)pos < kcap) {
-            sidx[pos] = (int64_t)cidx[c];
+            const int32_t li = cidx[c];
+            const float xv = cxv[c];
+            sidx[pos] = (int64_t)li;
             sval[pos] = v;
-            sx[pos] = cxv[c];
+            sx[pos] = xv;
             s2 += (double)v * (double)v;
+            // the working copy: D = X - S on the new support (its old
+            // support was restored before the selection)
+            int64_t i, j;
+            divmod_nn((int64_t)li, b.n, rn, i, j);
+            b.D[i * b.ldd + j] = xv - v;
           }
         }
         pa += (unsigned long long)__popcll(ma);
@@ -844,6 +852,9 @@ __global__ __launch_bounds__(256) void kb_update_d(const BProb* __restrict__ pro
   const BProb& b = probs[blockIdx.y];
   if (restore && *iter == 0) return;
   const long long nnz = b.sel->nnz_list[list];
+  // restore: the whole old list; otherwise the new list's tie entries (the
+  // entries above the threshold were written by kb_compact)
+  const long long e_begin = restore ? 0 : b.sel->count_above;
   const int64_t n = b.n;
   const double rn = 1.0 / (double)n;
   const int64_t* __restrict__ sidx = b.s_idx[list];
@@ -854,7 +865,8 @@ __global__ __launch_bounds__(256) void kb_update_d(const BProb* __restrict__ pro
   // U entries per thread and round, all loads in flight before the stores
   constexpr int U = 4;
   const long long step = (long long)gridDim.x * 256;
-  for (long long e0 = (long long)blockIdx.x * 256 + threadIdx.x; e0 < nnz; e0 += U * step) {
+  for (long long e0 = e_begin + (long long)blockIdx.x * 256 + threadIdx.x; e0 < nnz;
+       e0 += U * step) {
     int64_t idx[U];
     float x[U], v[U];
 #pragma unroll
@@ -1009,11 +1021,16 @@ void bl_select(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
                      (const double*)a.dslots, (const double*)cslot, (int)cb);
 }
 
-void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
+void bl_restore_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
   const unsigned g = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, (max_k + 255) / 256));
   hipLaunchKernelGGL(kb_update_d, dim3(g, (unsigned)a.nprob), dim3(256), 0, L.stream, a.probs,
                      a.iter, cur ^ 1, 1);
-  hipLaunchKernelGGL(kb_update_d, dim3(g, (unsigned)a.nprob), dim3(256), 0, L.stream, a.probs,
+}
+
+void bl_update_d(const Launch& L, const BatchArgs& a, int cur, int64_t max_k) {
+  (void)max_k;
+  // the tie slice of the new list only: a few entries per problem
+  hipLaunchKernelGGL(kb_update_d, dim3(1, (unsigned)a.nprob), dim3(256), 0, L.stream, a.probs,
                      a.iter, cur, 0);
   hipLaunchKernelGGL(kb_iter_inc, dim3(1), dim3(64), 0, L.stream, a.iter);
 }
