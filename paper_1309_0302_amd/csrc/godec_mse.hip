@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kRP = 8;           // padded rank of every label
 constexpr int kChunk = 4;        // iterations whose A1 draws are staged together
-constexpr int kMaxBlk = 256;     // blocks of a label's Y2 row pass (km_reduce takes <= 256)
+constexpr int kMaxBlk = 256;     // blocks of a label's Y2 row pass (km_reduce_orth adds <= 256)
 
 }  // namespace
 

@@ -157,7 +157,9 @@ struct MseGroup {
 
 // Partial sums of Y2 = N^T (N A1) over the block's rows (group h of
 // wavefront w holds rows j0 + h * stride, j0 = w + 4 blk, stride =
-// 4 gridDim.x); written to part[blockIdx.x] as p_pad x 8.  Each wavefront
+// 4 gridDim.x); written to part[blockIdx.x] as p_pad x 8.  The launcher
+// uses it for a label's first update (FIRST, N from X / D); km_gram_v below
+// takes the labels updated before.  Each wavefront
 // accumulates its rows in order, then the block adds its four wavefronts in
 // order.  A1 and V live in LDS, transposed (entry [t][c]), so lane reads
 // are consecutive.  The first group's loads are issued before the panels
