@@ -476,13 +476,9 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
     a.ev_b = prof_event(c);
     if (a.ev_a && a.ev_b) c->recs.push_back({PC_SEL_PASS, a.ev_a, a.ev_b});
   }
-  if (c->completion)
-    launch_fixed_support(L, c->f64, c->rp, c->X, c->ldx, c->UL, c->VL, c->m, c->n, c->support,
-                         c->row_ptr, c->support_nnz, c->s_idx[nxt], c->s_val[nxt],
-                         c->s_x[nxt], c->plan[nxt], (double*)c->hist);
-  else
-    launch_select(L, c->f64, c->rp, a);
-  // ---- D update: restore X on the old support, X - S on the new one ----
+  // ---- D update, old support: X is restored there before the selection
+  // (the chain has finished reading D and the selection reads X), so that
+  // the compaction can write X - S on the new support as it takes it ----
   const bool upd_native = c->d_native_valid;
   // a fixed support is rewritten in place: no restore of the old one
   if (c->iters_done > 0 && !c->completion) {
@@ -493,12 +489,28 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
       launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[prev], nullptr, c->s_x[prev],
                       c->plan[prev], kk);
   }
+  const bool fused_d = !c->completion;
+  if (fused_d) {
+    a.dwn = upd_native ? c->D : nullptr;
+    a.dw16 = mixed ? (uint16_t*)c->D16 : nullptr;
+    a.lddw = c->ldd;
+  }
+  if (c->completion)
+    launch_fixed_support(L, c->f64, c->rp, c->X, c->ldx, c->UL, c->VL, c->m, c->n, c->support,
+                         c->row_ptr, c->support_nnz, c->s_idx[nxt], c->s_val[nxt],
+                         c->s_x[nxt], c->plan[nxt], (double*)c->hist);
+  else
+    launch_select(L, c->f64, c->rp, a);
+  // ---- D update, new support: X - S at the entries the compaction did not
+  // write (the ties; every entry after a threshold scan or on a fixed
+  // support) ----
+  const unsigned long long* from = fused_d ? c->counters : nullptr;
   if (upd_native)
     launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
-                    c->plan[nxt], kk);
+                    c->plan[nxt], kk, from);
   if (mixed)
     launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
-                    c->plan[nxt], kk);
+                    c->plan[nxt], kk, from);
   c->cur = nxt;
   c->iters_done += 1;
   HIP_TRY(hipGetLastError());

@@ -954,7 +954,10 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
                                                      T* __restrict__ s_x,
                                                      int64_t* __restrict__ tie_idx,
                                                      unsigned long long* __restrict__ counters,
-                                                     double* __restrict__ s2sel) {
+                                                     double* __restrict__ s2sel,
+                                                     T* __restrict__ dwn,
+                                                     uint16_t* __restrict__ dw16,
+                                                     int64_t lddw, int64_t ncols) {
   __shared__ double red[4];
   __shared__ unsigned int wa[4], wt[4];
   __shared__ unsigned long long base_a, base_t;
@@ -962,6 +965,8 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long tkey = plan->prefix;
   const unsigned long long kcap = (unsigned long long)(plan->count_above + plan->k_rem);
+  const long long dkeep = plan->count_above;
+  const double rcols = 1.0 / (double)(ncols > 0 ? ncols : 1);
   const unsigned long long tcap = (unsigned long long)plan->cap;
   const unsigned long long below = (1ull << lane) - 1ull;
   const int ntot = seg_total(plan);
@@ -1015,10 +1020,22 @@ __global__ __launch_bounds__(256) void k_sel_compact(SelPlan* __restrict__ plan,
         if (above) {
           const unsigned long long pos = ba + __popcll(ma & below);
           if (pos < kcap) {
-            s_idx[pos] = cand_idx[c];
+            const int64_t id = cand_idx[c];
+            const T xv = cand_x[c];
+            s_idx[pos] = id;
             s_val[pos] = v[h];
-            s_x[pos] = cand_x[c];
+            s_x[pos] = xv;
             s2 += (double)v[h] * (double)v[h];
+            // D = X - S at the entries surely kept (the tie list may
+            // replace positions from count_above on)
+            if ((dwn != nullptr || dw16 != nullptr) && (long long)pos < dkeep) {
+              int64_t i, j;
+              divmod_nn(id, ncols, rcols, i, j);
+              const T dv = (T)(xv - v[h]);
+              if (dwn) dwn[i * lddw + j] = dv;
+              if constexpr (sizeof(T) == 4)
+                if (dw16) dw16[i * lddw + j] = f32_to_bf16(dv);
+            }
           }
         }
         if (tie) {
@@ -1536,10 +1553,16 @@ __global__ __launch_bounds__(256) void k_update_d(TD* __restrict__ D, int64_t ld
                                                   const int64_t* __restrict__ idx,
                                                   const TX* __restrict__ val,
                                                   const TX* __restrict__ xv,
-                                                  const SelPlan* __restrict__ plan) {
+                                                  const SelPlan* __restrict__ plan,
+                                                  const unsigned long long* __restrict__ start) {
   const long long cnt = plan->nnz;
+  long long e0 = 0;
+  if (start != nullptr) {
+    e0 = (long long)start[0];
+    if (e0 > plan->count_above) e0 = plan->count_above;
+  }
   const double rn = 1.0 / (double)n;
-  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
+  for (long long e = e0 + (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
        e += (long long)gridDim.x * 256) {
     const int64_t id = idx[e];
     int64_t i, j;
@@ -1758,7 +1781,8 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
   hipLaunchKernelGGL(k_sel_compact<T>, dim3(cg), dim3(256), 0, L.stream, a.plan, a.cand_idx,
                      (const T*)a.cand_val, (const T*)a.cand_x, (const unsigned int*)a.seg_count,
                      a.s_idx, (T*)a.s_val, (T*)a.s_x, a.tie_idx, a.counters,
-                     a.s2part + kSelParts);
+                     a.s2part + kSelParts, (T*)a.dwn, sizeof(T) == 4 ? a.dw16 : nullptr,
+                     a.lddw, a.n);
   hipLaunchKernelGGL(k_sel_ties<T>, dim3(1), dim3(1024), 0, L.stream, a.plan, a.s_idx,
                      (T*)a.s_val, a.tie_idx, a.counters, a.carry,
                      (const double*)(a.s2part + kSelParts), (int)cg);
@@ -1820,17 +1844,19 @@ void launch_init_d(const Launch& L, DType td, bool xf64, void* D, int64_t ldd,
 
 void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
                      const int64_t* idx, const void* val, const void* xv, const SelPlan* plan,
-                     int64_t kmax) {
+                     int64_t kmax, const unsigned long long* start) {
   const unsigned g = grid_for(kmax, L.num_cu, 4);
   if (td == F64)
     hipLaunchKernelGGL((k_update_d<double, double>), dim3(g), dim3(256), 0, L.stream,
-                       (double*)D, ldd, n, idx, (const double*)val, (const double*)xv, plan);
+                       (double*)D, ldd, n, idx, (const double*)val, (const double*)xv, plan,
+                       start);
   else if (td == F32)
     hipLaunchKernelGGL((k_update_d<float, float>), dim3(g), dim3(256), 0, L.stream, (float*)D,
-                       ldd, n, idx, (const float*)val, (const float*)xv, plan);
+                       ldd, n, idx, (const float*)val, (const float*)xv, plan, start);
   else
     hipLaunchKernelGGL((k_update_d<uint16_t, float>), dim3(g), dim3(256), 0, L.stream,
-                       (uint16_t*)D, ldd, n, idx, (const float*)val, (const float*)xv, plan);
+                       (uint16_t*)D, ldd, n, idx, (const float*)val, (const float*)xv, plan,
+                       start);
 }
 
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx, int64_t m,
