@@ -501,16 +501,16 @@ godec_status run_iteration(godec_ctx* c, int64_t t, int64_t total) {
                          c->s_x[nxt], c->plan[nxt], (double*)c->hist);
   else
     launch_select(L, c->f64, c->rp, a);
-  // ---- D update, new support: X - S at the entries the compaction did not
-  // write (the ties; every entry after a threshold scan or on a fixed
-  // support) ----
-  const unsigned long long* from = fused_d ? c->counters : nullptr;
-  if (upd_native)
-    launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
-                    c->plan[nxt], kk, from);
-  if (mixed)
-    launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt], c->s_x[nxt],
-                    c->plan[nxt], kk, from);
+  // ---- D update, new support: X - S (written inside the selection; on a
+  // fixed support here) ----
+  if (!fused_d) {
+    if (upd_native)
+      launch_update_d(L, native, c->D, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt],
+                      c->s_x[nxt], c->plan[nxt], kk);
+    if (mixed)
+      launch_update_d(L, BF16, c->D16, c->ldd, c->n, c->s_idx[nxt], c->s_val[nxt],
+                      c->s_x[nxt], c->plan[nxt], kk);
+  }
   c->cur = nxt;
   c->iters_done += 1;
   HIP_TRY(hipGetLastError());

@@ -197,11 +197,11 @@ struct SelectArgs {
   const int64_t* ridx = nullptr;
   const float* rx = nullptr;
   const SelPlan* rplan = nullptr;
-  // optional: the compaction also writes x - s into these working copies of
-  // D (ldd x n, row-major; the bf16 copy for FP32 X only) at the entries it
-  // takes below the plan's count_above; the rest of the S list (the ties, or
-  // every entry when the threshold scan wrote it) is left to
-  // launch_update_d with start = counters (after the selection)
+  // optional: x - s is written into these working copies of D (ldd x n,
+  // row-major; the bf16 copy for FP32 X only) at every entry of the new S:
+  // by the compaction for the entries it takes below the plan's
+  // count_above, by the tie-value pass for the rest (the ties, or every
+  // entry when the threshold scan wrote the list)
   void* dwn = nullptr;      // in the type of X
   uint16_t* dw16 = nullptr;
   int64_t lddw = 0;
@@ -218,12 +218,10 @@ void launch_init_d(const Launch& L, DType td, bool xf64, void* D,
                    int64_t ldd, const void* X, int64_t ldx, int64_t m,
                    int64_t n, int64_t mpad);
 // D[idx] <- x - val (val != nullptr) or x, for the plan's nnz entries, with
-// x the stored value of X at idx; with `start` set, only the entries from
-// min(start[0], plan->count_above) on (those a compaction that wrote D did
-// not take).
+// x the stored value of X at idx.
 void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
                      const int64_t* idx, const void* val, const void* xv, const SelPlan* plan,
-                     int64_t kmax, const unsigned long long* start = nullptr);
+                     int64_t kmax);
 // *out2 = ||X||_F^2 summed in a fixed order through `part` (kNormParts
 // doubles of scratch); *nonfinite |= 1 on a NaN/Inf entry.
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx,

@@ -1402,18 +1402,35 @@ __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X,
                                                         const unsigned long long* __restrict__ counters,
                                                         int64_t* __restrict__ s_idx,
                                                         T* __restrict__ s_val,
-                                                        T* __restrict__ s_x) {
-  const long long start = (long long)counters[0];
+                                                        T* __restrict__ s_x,
+                                                        T* __restrict__ dwn,
+                                                        uint16_t* __restrict__ dw16,
+                                                        int64_t lddw) {
+  // the entries the compaction did not write: the ties (from where the tie
+  // list starts), or every entry after a threshold scan (counters[0] = 0)
+  long long start = (long long)counters[0];
+  if (start > plan->count_above) start = plan->count_above;
   const long long nnz = plan->nnz;
+  const bool dupd = dwn != nullptr || dw16 != nullptr;
+  // D = X - S at entry (i, j) of the working copies
+  auto put_d = [&](int64_t i, int64_t j, T x, T v) {
+    const T dv = (T)(x - v);
+    if (dwn) dwn[i * lddw + j] = dv;
+    if constexpr (sizeof(T) == 4)
+      if (dw16) dw16[i * lddw + j] = f32_to_bf16(dv);
+  };
   if constexpr (sizeof(T) == 4) {
     constexpr int KS = ResK<RP>::KS;
     const int lane = threadIdx.x & 63;
     const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
     for (long long e = start + (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
          e < nnz; e += nw) {
-      if (s_val[e] != 0.f) continue;   // the whole wavefront reads the same entry
       const int64_t idx = s_idx[e];
       const int64_t i = idx / n, j = idx % n;
+      if (s_val[e] != 0.f) {   // the whole wavefront reads the same entry
+        if (dupd && lane == 0) put_d(i, j, s_x[e], s_val[e]);
+        continue;
+      }
       const int64_t r0 = i - i % 16, c0 = j - j % 16;
       float a[KS], b[KS];
       res_load_u<RP>(UL, m, r0, lane, a);
@@ -1422,23 +1439,30 @@ __global__ __launch_bounds__(256) void k_fix_tie_values(const T* __restrict__ X,
       const int li = (int)(i - r0), lj = (int)(j - c0);
       if (lane == li + 16 * (lj >> 2)) {
         const float x = X[i * ldx + j];
-        s_val[e] = x - res_pick(L, lj & 3);
+        const float sv = x - res_pick(L, lj & 3);
+        s_val[e] = sv;
         s_x[e] = x;
+        if (dupd) put_d(i, j, x, sv);
       }
     }
     return;
   }
   for (long long e = start + (long long)blockIdx.x * 256 + threadIdx.x; e < nnz;
        e += (long long)gridDim.x * 256) {
-    if (s_val[e] != T(0)) continue;
     const int64_t idx = s_idx[e];
     const int64_t i = idx / n, j = idx % n;
+    if (s_val[e] != T(0)) {
+      if (dupd) put_d(i, j, s_x[e], s_val[e]);
+      continue;
+    }
     T u[RP], v[RP];
 #pragma unroll
     for (int c = 0; c < RP; ++c) { u[c] = UL[i * RP + c]; v[c] = VL[j * RP + c]; }
     const T x = X[i * ldx + j];
-    s_val[e] = resid<T, RP>(x, u, v);
+    const T sv = resid<T, RP>(x, u, v);
+    s_val[e] = sv;
     s_x[e] = x;
+    if (dupd) put_d(i, j, x, sv);
   }
 }
 
@@ -1553,16 +1577,10 @@ __global__ __launch_bounds__(256) void k_update_d(TD* __restrict__ D, int64_t ld
                                                   const int64_t* __restrict__ idx,
                                                   const TX* __restrict__ val,
                                                   const TX* __restrict__ xv,
-                                                  const SelPlan* __restrict__ plan,
-                                                  const unsigned long long* __restrict__ start) {
+                                                  const SelPlan* __restrict__ plan) {
   const long long cnt = plan->nnz;
-  long long e0 = 0;
-  if (start != nullptr) {
-    e0 = (long long)start[0];
-    if (e0 > plan->count_above) e0 = plan->count_above;
-  }
   const double rn = 1.0 / (double)n;
-  for (long long e = e0 + (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < cnt;
        e += (long long)gridDim.x * 256) {
     const int64_t id = idx[e];
     int64_t i, j;
@@ -1790,7 +1808,8 @@ static void select_t(const Launch& L, int rp, const SelectArgs& a) {
     hipLaunchKernelGGL((k_fix_tie_values<T, RP>), dim3(grid_for(a.k, L.num_cu, 2)), dim3(256),
                        0, L.stream, (const T*)a.X, a.ldx, (const T*)a.UL, (const T*)a.VL,
                        (const T*)a.VLt, a.ldv, a.m, a.n, a.plan, a.counters, a.s_idx,
-                       (T*)a.s_val, (T*)a.s_x);
+                       (T*)a.s_val, (T*)a.s_x, (T*)a.dwn,
+                       sizeof(T) == 4 ? a.dw16 : nullptr, a.lddw);
   });
 }
 
@@ -1844,19 +1863,17 @@ void launch_init_d(const Launch& L, DType td, bool xf64, void* D, int64_t ldd,
 
 void launch_update_d(const Launch& L, DType td, void* D, int64_t ldd, int64_t n,
                      const int64_t* idx, const void* val, const void* xv, const SelPlan* plan,
-                     int64_t kmax, const unsigned long long* start) {
+                     int64_t kmax) {
   const unsigned g = grid_for(kmax, L.num_cu, 4);
   if (td == F64)
     hipLaunchKernelGGL((k_update_d<double, double>), dim3(g), dim3(256), 0, L.stream,
-                       (double*)D, ldd, n, idx, (const double*)val, (const double*)xv, plan,
-                       start);
+                       (double*)D, ldd, n, idx, (const double*)val, (const double*)xv, plan);
   else if (td == F32)
     hipLaunchKernelGGL((k_update_d<float, float>), dim3(g), dim3(256), 0, L.stream, (float*)D,
-                       ldd, n, idx, (const float*)val, (const float*)xv, plan, start);
+                       ldd, n, idx, (const float*)val, (const float*)xv, plan);
   else
     hipLaunchKernelGGL((k_update_d<uint16_t, float>), dim3(g), dim3(256), 0, L.stream,
-                       (uint16_t*)D, ldd, n, idx, (const float*)val, (const float*)xv, plan,
-                       start);
+                       (uint16_t*)D, ldd, n, idx, (const float*)val, (const float*)xv, plan);
 }
 
 void launch_norm_check(const Launch& L, bool f64, const void* X, int64_t ldx, int64_t m,
