@@ -3,7 +3,8 @@ support set) against the FP64 oracle, through the C ABI.
 
 Per step: the GPU's own S_{t-1} is fed to the oracle's L update with the
 oracle's A1, and L_t must match within 1e-10 (FP64) / 1e-5 (FP32), the
-relative Frobenius bars of the BRP path.  The S list must be the given
+relative Frobenius bars of the BRP path (BF16 panels: 2e-3, then 1e-5 in the
+refinement iteration).  The S list must be the given
 support, bit for bit, and its values the GPU's own residual at those
 entries, bit for bit.  Trajectories: a rank-3 matrix with 30 % of its entries
 missing is completed to 1e-10 by both the GPU and the oracle.
