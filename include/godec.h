@@ -100,7 +100,17 @@ typedef struct {
    * outside the paper that lets a smaller q reach the same fixed point;
    * 0 (default): A1 every iteration, as Algorithm 1. */
   int32_t warm_start;
-  int32_t reserved1;
+  /* 1: iteration t (counted from 0 over the context's life) draws its own
+   * A1 from the seed seed + t with the generator of godec_draw_a1, as the
+   * MSE training of Algorithm 4 redraws it every iteration; after a rank
+   * drop to r' the first r' columns of each new draw are used.  Iteration 0
+   * uses the seed's own draw, so the first step equals that of the default
+   * mode.  0 (default): A1 is drawn once from the seed and kept (Algorithm 1
+   * does not redraw it).  The draws are made on the host and staged through
+   * pinned host memory while the device runs the previous iteration.
+   * Excludes warm_start and a1_host; single-problem contexts only (the
+   * batched form, the layer and godec_solve_static reject it). */
+  int32_t redraw_a1;
 } godec_opts;
 
 typedef struct {
@@ -186,7 +196,8 @@ godec_status godec_solve_tol(const void* X_dev, godec_dtype dtype, int64_t m,
  * X and the outputs, exactly as for godec_solve.
  * Limit: problems whose godec_workspace_size exceeds the scratch are
  * rejected with GODEC_E_UNSUPPORTED (the 500 x 500 FP64 and 25 344 x 200
- * FP32 workloads fit; 10 000 x 10 000 does not).
+ * FP32 workloads fit; 10 000 x 10 000 does not), and so is
+ * opts->redraw_a1 (its draws are staged in pinned host memory).
  * Sharing: every call on one GPU uses that GPU's single array, which keeps
  * the last call's contents; calls that overlap on one GPU (several streams
  * or host threads) race and must be serialised by the caller.  The call
@@ -218,7 +229,9 @@ godec_status godec_get_S(godec_ctx* ctx, int64_t* idx_dev, void* val_dev,
  * FP32 in BF16_REFINE mode).  Asynchronous. */
 godec_status godec_get_residual(godec_ctx* ctx, void* R_dev, int64_t ldr);
 
-/* Copy the n x r A1 in use (FP64, row-major) to the host.  Synchronous. */
+/* Copy the n x r A1 in use (FP64, row-major) to the host: with redraw_a1,
+ * the draw of the last iteration run (of iteration 0 before any).
+ * Synchronous. */
 godec_status godec_get_A1(godec_ctx* ctx, double* a1_host);
 
 /* Synchronise the stream and report the state. */

@@ -40,6 +40,10 @@ R8  L is evaluated through exact identities of Algorithm 1's lines
     (A2^T Y1 = R2^T R2 and the R factor of Y1 = L~ Y2) instead of forming the
     graded products Y1, Y2 literally; see ``brp_power``.  The literal lines
     are kept in ``brp_power_literal`` and pin it where they are accurate.
+R15 With a redrawn A1 (an option of the library; the MSE training of
+    Algorithm 4 draws a new A1 every iteration), iteration t uses the first
+    r' columns of its own draw A1(t), r' being the rank kept after the
+    earlier iterations (R5).
 """
 
 from dataclasses import dataclass, field
@@ -299,7 +303,8 @@ def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
     chain after the first from the previous iteration's right factor (whose
     span is that of Q2) instead of A1: a variant outside the paper (Q2 of
     the last step in the role of A1 of Sec. 3.1.1), pinned by its fixed
-    point.
+    point.  A1 may be a function of the iteration index t (from 0) that
+    returns that iteration's draw (reading R15).
 
     Pinned by: on the 500 x 500 workload its trajectory equals that of the
     naive SVD GoDec (Eq. 4); the S-step half of Theorem 1 (monotone
@@ -310,10 +315,13 @@ def godec_brp(X: np.ndarray, r: int, k: int, q: int, A1: np.ndarray,
     m, n = X.shape
     S = np.zeros_like(X)
     xx = float(np.sum(X * X))
-    A = np.asarray(A1, dtype=np.float64)[:, :r]
+    redraw = callable(A1)
+    A = np.asarray(A1(0) if redraw else A1, dtype=np.float64)[:, :r]
     tr = GoDecTrace(L=X.copy(), S=S, left=None, right=None, r_eff=r)
-    for _ in range(iters):
+    for t in range(iters):
         t0 = time.perf_counter()
+        if redraw and t > 0:
+            A = np.asarray(A1(t), dtype=np.float64)[:, :A.shape[1]]
         D = X - S
         res = brp_projection(D, A, q) if lstep == "proj" else brp_power(D, A, q, rank_tol)
         A = res.right if warm else A[:, :res.r_eff]

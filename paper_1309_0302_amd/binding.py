@@ -30,7 +30,7 @@ class godec_opts(ctypes.Structure):
                 ("rank_tol", ctypes.c_double), ("a1_host", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("support_dev", ctypes.c_void_p),
                 ("support_nnz", ctypes.c_int64), ("warm_start", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32)]
+                ("redraw_a1", ctypes.c_int32)]
 
 
 class godec_info(ctypes.Structure):
@@ -198,14 +198,16 @@ def _dtype_code(t):
 
 
 def make_opts(prec=GODEC_PREC_NATIVE, refine_iters=1, rank_tol=0.0, a1=None,
-              stream=None, support=None, lstep=0, warm_start=0):
+              stream=None, support=None, lstep=0, warm_start=0, redraw_a1=0):
     """support: optional int64 device tensor of strictly ascending linear
-    indices (matrix completion: the fixed support of S)."""
+    indices (matrix completion: the fixed support of S).  redraw_a1 = 1:
+    iteration t draws its own A1 from seed + t."""
     o = godec_opts()
     load().godec_opts_default(ctypes.byref(o))
     o.prec = prec
     o.lstep = lstep
     o.warm_start = warm_start
+    o.redraw_a1 = redraw_a1
     o.refine_iters = refine_iters
     o.rank_tol = rank_tol
     keep = None
@@ -376,7 +378,7 @@ class GoDec:
 
     def __init__(self, X, r, k, q, seed=0, prec=GODEC_PREC_NATIVE,
                  refine_iters=1, rank_tol=0.0, a1=None, stream=None, support=None,
-                 lstep=0, warm_start=0):
+                 lstep=0, warm_start=0, redraw_a1=0):
         import torch
         if not X.is_cuda:
             raise ValueError("X must be a device tensor")
@@ -391,7 +393,8 @@ class GoDec:
             stream = torch.cuda.current_stream(X.device).cuda_stream
         self.support = support
         self.opts, self._a1_keep = make_opts(prec, refine_iters, rank_tol, a1,
-                                             stream, support, lstep, warm_start)
+                                             stream, support, lstep, warm_start,
+                                             redraw_a1)
         self.ws_bytes = godec_workspace_size(self.m, self.n, r, k, q,
                                              self.dtype, self.opts)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,

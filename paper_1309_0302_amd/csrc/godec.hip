@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/godec.h"
@@ -44,6 +45,13 @@ struct godec_ctx {
   int num_cu;
   int lstep = 0;                      // 1: projection form of the L update
   bool warm = false;                  // chains start from the previous Q2
+  // redraw_a1: iteration t draws A1 from seed + t; the draws are staged in
+  // two pinned host slots, each reused once the copy recorded after its
+  // last use has finished
+  bool redraw = false;
+  double* a1_pin[2] = {nullptr, nullptr};
+  hipEvent_t a1_ev[2] = {nullptr, nullptr};
+  bool a1_ev_used[2] = {false, false};
   const int64_t* support = nullptr;   // completion: fixed support of S
   int64_t support_nnz = 0;
   int64_t* row_ptr = nullptr;         // completion: m x (ncb + 1) run starts (see init)
@@ -222,6 +230,12 @@ godec_status validate(int64_t m, int64_t n, int32_t r, int64_t k, int32_t q,
     if (o->lstep != 0 && o->lstep != 1) return fail(GODEC_E_INVAL, "opts.lstep must be 0 or 1");
     if (o->warm_start != 0 && o->warm_start != 1)
       return fail(GODEC_E_INVAL, "opts.warm_start must be 0 or 1");
+    if (o->redraw_a1 != 0 && o->redraw_a1 != 1)
+      return fail(GODEC_E_INVAL, "opts.redraw_a1 must be 0 or 1");
+    if (o->redraw_a1 && o->warm_start)
+      return fail(GODEC_E_INVAL, "redraw_a1 and warm_start exclude each other");
+    if (o->redraw_a1 && o->a1_host)
+      return fail(GODEC_E_INVAL, "redraw_a1 draws every A1 itself: a1_host must be NULL");
     if (o->support_dev != nullptr || o->support_nnz != 0) {
       if (o->support_nnz < 0 || o->support_nnz > m * n)
         return fail(GODEC_E_INVAL, "need 0 <= support_nnz <= m*n");
@@ -535,7 +549,19 @@ void godec_opts_default(godec_opts* o) {
 godec_status godec_draw_a1(uint64_t seed, int64_t n, int32_t r, double* a1_host) {
   if (n < 1 || r < 1 || !a1_host) return fail(GODEC_E_INVAL, "bad arguments");
   const uint64_t total = (uint64_t)n * (uint64_t)r;
-  for (uint64_t j = 0; j < total; ++j) a1_host[j] = gaussian(seed, j);
+  // entry j depends on (seed, j) only, so large draws are split over
+  // threads in contiguous ranges (same values as one thread)
+  unsigned nth = 1;
+  if (total >= (1u << 16))
+    nth = std::max(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
+  auto work = [&](unsigned w) {
+    const uint64_t j0 = total * w / nth, j1 = total * (w + 1) / nth;
+    for (uint64_t j = j0; j < j1; ++j) a1_host[j] = gaussian(seed, j);
+  };
+  std::vector<std::thread> th;
+  for (unsigned w = 1; w < nth; ++w) th.emplace_back(work, w);
+  work(0);
+  for (auto& t : th) t.join();
   return GODEC_OK;
 }
 
@@ -583,6 +609,7 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   c->X = X_dev;
   c->lstep = opts ? opts->lstep : 0;
   c->warm = opts && opts->warm_start;
+  c->redraw = opts && opts->redraw_a1;
   c->stream = opts ? (hipStream_t)opts->stream : nullptr;
   const size_t need = carve(c, nullptr);
   if (ws_bytes < need) {
@@ -705,6 +732,26 @@ godec_status capture_iteration(godec_ctx* c, int64_t t, int64_t total, hipGraphE
   return GODEC_OK;
 }
 
+// redraw_a1: draw A1 of iteration t (from seed + t) into a pinned slot and
+// queue its copy to the device A1 ahead of the iteration.  The draw runs on
+// the host while the device works through the iterations already queued.
+static godec_status stage_a1(godec_ctx* c, int64_t t) {
+  const size_t bytes = sizeof(double) * (size_t)c->n * c->r;
+  const int s = (int)(t & 1);
+  if (!c->a1_pin[s]) {
+    HIP_TRY(hipHostMalloc((void**)&c->a1_pin[s], bytes, hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&c->a1_ev[s], hipEventDisableTiming));
+  }
+  // the slot's previous copy has left the host buffer
+  if (c->a1_ev_used[s]) HIP_TRY(hipEventSynchronize(c->a1_ev[s]));
+  godec_status st = godec_draw_a1(c->seed + (uint64_t)t, c->n, c->r, c->a1_pin[s]);
+  if (st != GODEC_OK) return st;
+  HIP_TRY(hipMemcpyAsync(c->A1, c->a1_pin[s], bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->a1_ev[s], c->stream));
+  c->a1_ev_used[s] = true;
+  return GODEC_OK;
+}
+
 godec_status godec_step(godec_ctx* c, int32_t iters, int32_t total_iters) {
   if (!c) return fail(GODEC_E_INVAL, "ctx is NULL");
   if (iters < 0) return fail(GODEC_E_INVAL, "iters < 0");
@@ -713,6 +760,12 @@ godec_status godec_step(godec_ctx* c, int32_t iters, int32_t total_iters) {
   for (int32_t i = 0; i < iters; ++i) {
     const int64_t t = c->iters_done;
     const bool refine = mixed && total > 0 && t >= total - c->refine_iters;
+    // iteration 0 uses the draw of godec_init (seed + 0); the copy of a
+    // later draw is queued ahead of the iteration, outside any graph
+    if (c->redraw && t > 0) {
+      godec_status s = stage_a1(c, t);
+      if (s != GODEC_OK) return s;
+    }
     // the first iteration, the refinement iterations (which rebuild the FP32
     // copy of D once) and traced iterations run eagerly; every other
     // iteration's launches depend only on the S-list parity and on whether
@@ -793,6 +846,9 @@ godec_status godec_get_S(godec_ctx* c, int64_t* idx_dev, void* val_dev, int64_t*
 
 godec_status godec_get_A1(godec_ctx* c, double* a1_host) {
   if (!c || !a1_host) return fail(GODEC_E_INVAL, "NULL argument");
+  // redraw_a1: the A1 of the last iteration run (of iteration 0 before any)
+  const int64_t t = c->iters_done > 0 ? c->iters_done - 1 : 0;
+  if (c->redraw && t > 0) return godec_draw_a1(c->seed + (uint64_t)t, c->n, c->r, a1_host);
   std::memcpy(a1_host, c->a1_host.data(), sizeof(double) * c->n * c->r);
   return GODEC_OK;
 }
@@ -831,6 +887,13 @@ godec_status godec_destroy(godec_ctx* c) {
     for (const auto& ge : c->gcache) (void)hipGraphExecDestroy(ge.exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    for (int s = 0; s < 2; ++s) {
+      if (c->a1_ev[s]) {
+        (void)hipEventSynchronize(c->a1_ev[s]);
+        (void)hipEventDestroy(c->a1_ev[s]);
+      }
+      if (c->a1_pin[s]) (void)hipHostFree(c->a1_pin[s]);
+    }
     delete c;
   }
   return GODEC_OK;

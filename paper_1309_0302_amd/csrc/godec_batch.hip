@@ -81,6 +81,8 @@ godec_status validate_batch(const godec_problem* probs, int32_t count, int32_t q
     return fail(GODEC_E_UNSUPPORTED, "the batched form runs the root-form L update");
   if (opts && opts->warm_start != 0)
     return fail(GODEC_E_UNSUPPORTED, "the batched form starts every chain from A1");
+  if (opts && opts->redraw_a1 != 0)
+    return fail(GODEC_E_UNSUPPORTED, "the batched form draws A1 once per problem");
   for (int i = 0; i < count; ++i) {
     const godec_problem& P = probs[i];
     const std::string at = " (problem " + std::to_string(i) + ")";

@@ -447,6 +447,8 @@ godec_status godec_layer_forward(godec_layer** out, const void* X_dev, godec_dty
     return fail(GODEC_E_UNSUPPORTED, "the layer differentiates the root-form L update");
   if (opts && opts->warm_start != 0)
     return fail(GODEC_E_UNSUPPORTED, "the layer starts every chain from A1");
+  if (opts && opts->redraw_a1 != 0)
+    return fail(GODEC_E_UNSUPPORTED, "the layer draws A1 once per problem");
   godec_layer* l = new godec_layer;
   fill_layer(l, batch, m, n, r, k, q, T, dtype);
   s = sub_workspace(l, &l->sub_ws);

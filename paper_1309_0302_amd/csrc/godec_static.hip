@@ -56,6 +56,10 @@ extern "C" godec_status godec_solve_static(const void* X_dev, godec_dtype dtype,
                                            const godec_opts* opts, void* UL_dev, void* VL_dev,
                                            int64_t* S_idx_dev, void* S_val_dev,
                                            godec_info* info) {
+  // the per-iteration draws of redraw_a1 are staged in pinned host memory,
+  // which this entry point does not allocate
+  if (opts && opts->size == sizeof(godec_opts) && opts->redraw_a1)
+    return fail(GODEC_E_UNSUPPORTED, "godec_solve_static does not support redraw_a1");
   // size check first: host arithmetic only
   size_t need = 0;
   godec_status s = godec_workspace_size(m, n, r, k, q, dtype, opts, &need);

@@ -48,7 +48,9 @@ def test_version_string(lib):
     assert b"gfx950" in lib.godec_version()
 
 
-@pytest.mark.parametrize("seed,n,r", [(0, 7, 3), (1234567, 50, 4), (2 ** 63 + 5, 33, 1)])
+# the last case is large enough for the draw to be split over threads
+@pytest.mark.parametrize("seed,n,r", [(0, 7, 3), (1234567, 50, 4), (2 ** 63 + 5, 33, 1),
+                                      (99, 3301, 20)])
 def test_host_a1_matches_oracle_bitwise(seed, n, r):
     from oracle.rng_ref import a1_gaussian
     got = b.godec_draw_a1(seed, n, r)
@@ -113,6 +115,17 @@ def test_warm_start_checked(lib):
     with pytest.raises(b.GodecError) as ei:
         _ws(100, 100, 4, 10, 1, opts=o)
     assert ei.value.status == 1
+
+
+def test_redraw_a1_checked(lib):
+    o, _ = b.make_opts(redraw_a1=1)
+    assert _ws(100, 100, 4, 10, 1, opts=o) == _ws(100, 100, 4, 10, 1)
+    for kw in ({"redraw_a1": 2}, {"redraw_a1": 1, "warm_start": 1},
+               {"redraw_a1": 1, "a1": np.zeros((100, 4))}):
+        o, _keep = b.make_opts(**kw)
+        with pytest.raises(b.GodecError) as ei:
+            _ws(100, 100, 4, 10, 1, opts=o)
+        assert ei.value.status == 1
 
 
 def test_k_extremes_accepted(lib):

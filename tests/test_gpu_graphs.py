@@ -36,28 +36,31 @@ def same_bits(a, b):
             assert x == y
 
 
-@pytest.mark.parametrize("dtype,prec,q,warm", [
-    (np.float32, 0, 1, 0),
-    (np.float32, 1, 2, 0),     # BF16 panels + FP32 refinement
-    (np.float64, 0, 1, 0),
-    (np.float32, 0, 1, 1),     # warm-started chains (a device copy in the graph)
+@pytest.mark.parametrize("dtype,prec,q,warm,redraw", [
+    (np.float32, 0, 1, 0, 0),
+    (np.float32, 1, 2, 0, 0),     # BF16 panels + FP32 refinement
+    (np.float64, 0, 1, 0, 0),
+    (np.float32, 0, 1, 1, 0),     # warm-started chains (a device copy in the graph)
+    (np.float32, 1, 2, 0, 1),     # a new A1 per iteration, copied in ahead of each replay
 ])
-def test_graph_replay_matches_direct_launches(dtype, prec, q, warm):
+def test_graph_replay_matches_direct_launches(dtype, prec, q, warm, redraw):
     from paper_1309_0302_amd.binding import GoDec
     w = wl.tiny(1500, 700, 6, rho=0.04, seed=31, dtype=dtype)
     X = torch.from_numpy(np.ascontiguousarray(w.X)).cuda()
     T = 9
-    print(f"\n[graphs] dtype={np.dtype(dtype).name} prec={prec} q={q} warm={warm} T={T}",
-          flush=True)
+    print(f"\n[graphs] dtype={np.dtype(dtype).name} prec={prec} q={q} warm={warm} "
+          f"redraw={redraw} T={T}", flush=True)
     ref = []
-    g0 = GoDec(X, w.r, w.k, q, seed=5, prec=prec, warm_start=warm)
+    g0 = GoDec(X, w.r, w.k, q, seed=5, prec=prec, warm_start=warm,
+               redraw_a1=redraw)
     try:
         for _ in range(T):
             g0.step(1, T)
             ref.append(snapshot(g0))
     finally:
         g0.close()
-    g1 = GoDec(X, w.r, w.k, q, seed=5, prec=prec, warm_start=warm)
+    g1 = GoDec(X, w.r, w.k, q, seed=5, prec=prec, warm_start=warm,
+               redraw_a1=redraw)
     try:
         g1.graphs(True)
         for t in range(T):

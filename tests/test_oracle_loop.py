@@ -90,3 +90,50 @@ def test_table1_row500_regime():
     for got, ref in ((rx, pg["rel_err_X"]), (rl, pg["rel_err_L"]),
                      (rs, pg["rel_err_S"])):
         assert ref / 30 <= got <= ref * 30
+
+
+@pytest.mark.parametrize("iters", [1, 2, 3, 4])
+def test_redrawn_a1_is_used_at_its_own_iteration(iters):
+    """Reading R15: iteration t takes A1(t).  Draw t >= 1 has its columns
+    r - t .. r - 1 set to zero; a zero column of A1 gives a zero column of
+    Y2 = (D^T D)^p A1, so the rank check of iteration t keeps exactly r - t
+    directions (the other columns are Gaussian, hence independent), and the
+    kept rank after `iters` iterations is r - (iters - 1).  An oracle that
+    kept A1(0), or took the draw of another iteration, ends at another rank."""
+    rng = np.random.default_rng(61)
+    X = rng.standard_normal((60, 50))
+    r = 5
+
+    def draw(t):
+        A = a1_gaussian(100 + t, 50, r)
+        if t > 0:
+            A[:, r - t:] = 0.0
+        return A
+
+    tb = g.godec_brp(X, r, 0, 1, draw, iters)
+    assert tb.r_eff == r - (iters - 1)
+    assert tb.left.shape[1] == tb.r_eff
+    fixed = g.godec_brp(X, r, 0, 1, draw(0), iters)
+    assert fixed.r_eff == r
+
+
+def test_redrawn_a1_first_iteration_is_the_fixed_one():
+    w = wl.tiny(80, 60, 3, rho=0.03, seed=7)
+    A0 = a1_gaussian(11, 60, 3)
+    a = g.godec_brp(w.X, 3, w.k, 1, lambda t: a1_gaussian(11 + t, 60, 3), 1)
+    b = g.godec_brp(w.X, 3, w.k, 1, A0, 1)
+    assert np.array_equal(a.L, b.L) and np.array_equal(a.S, b.S)
+
+
+def test_w1_redrawn_trajectory_equals_naive_svd_godec(w1_runs):
+    """P3 with a new A1 every iteration: on the 500 x 500 workload every
+    step of Algorithm 1 is the truncated SVD to rounding whatever A1 is, so
+    the redrawn run selects the naive GoDec's supports in every iteration."""
+    w, _, tn = w1_runs
+    n = w.X.shape[1]
+    tr = g.godec_brp(w.X, w.r, w.k, w.q, lambda t: a1_gaussian(w.seed + t, n, w.r), w.iters,
+                     keep_supports=True)
+    for a, b in zip(tr.supports, tn.supports):
+        assert np.array_equal(a, b)
+    assert g.rel_fro(tr.L, tn.L) < 1e-12
+    assert g.rel_fro(tr.S, tn.S) < 1e-12
