@@ -63,22 +63,23 @@ def rel_diff_factors(a_l, a_r, b_l, b_r):
     return max(aa - 2 * ab + bb, 0.0) ** 0.5 / bb ** 0.5
 
 
-def run_form(X, w, prec, steps, warmup, seed, lstep=0, warm_start=0, q=None):
+def run_form(X, w, prec, steps, warmup, seed, lstep=0, warm_start=0, q=None, redraw_a1=0):
     """Time `steps` iterations (one solve); returns timing, stats, factors.
     lstep = 1 takes the projection form of the L update; warm_start = 1
-    starts each power chain from the previous Q2; q overrides w.q."""
+    starts each power chain from the previous Q2; redraw_a1 = 1 draws a new
+    A1 every iteration; q overrides w.q."""
     q = w.q if q is None else q
     import torch
     from paper_1309_0302_amd.binding import GoDec
     stream = torch.cuda.current_stream()
     if warmup > 0:
         g = GoDec(X, w.r, w.k, q, seed=seed, prec=prec, refine_iters=1, lstep=lstep,
-                  warm_start=warm_start)
+                  warm_start=warm_start, redraw_a1=redraw_a1)
         g.step(warmup, warmup)
         g.info()
         g.close()
     g = GoDec(X, w.r, w.k, q, seed=seed, prec=prec, refine_iters=1, lstep=lstep,
-              warm_start=warm_start)
+              warm_start=warm_start, redraw_a1=redraw_a1)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -95,7 +96,7 @@ def run_form(X, w, prec, steps, warmup, seed, lstep=0, warm_start=0, q=None):
     g.close()
     # the same solve again with per-kernel event timing switched on
     g = GoDec(X, w.r, w.k, q, seed=seed, prec=prec, refine_iters=1, lstep=lstep,
-              warm_start=warm_start)
+              warm_start=warm_start, redraw_a1=redraw_a1)
     g.profile(True)
     g.step(steps, steps)
     stats = g.profile_read()
@@ -656,6 +657,7 @@ def main():
     ap.add_argument("--skip-completion", action="store_true")
     ap.add_argument("--skip-projection", action="store_true")
     ap.add_argument("--skip-warm", action="store_true")
+    ap.add_argument("--skip-redraw", action="store_true")
     ap.add_argument("--skip-mse", action="store_true")
     ap.add_argument("--only", choices=["batch", "layer", "copy", "grebsmo", "completion",
                                        "small", "mse"],
@@ -775,6 +777,16 @@ def main():
             "final_rel_err_sq": wm["info"]["rel_err_sq"],
             "rel_diff_L_vs_cold_q2": rel_diff_factors(wm["UL"], wm["VL"], bf["UL"], bf["VL"])}
         log(f"[bench] warm start q=1 {out['warm_start_q1']['value']} iter/s")
+    if not args.skip_redraw:
+        log("[bench] a new A1 every iteration, bf16 + refinement")
+        rd = run_form(X, w, GODEC_PREC_BF16_REFINE, args.steps, args.warmup, args.seed,
+                      redraw_a1=1)
+        out["redraw_a1"] = {
+            "value": round(args.steps / (rd["ms"] * 1e-3), 2), "unit": "iter/s",
+            "ms_per_step": round(rd["ms"] / args.steps, 4),
+            "final_rel_err_sq": rd["info"]["rel_err_sq"],
+            "rel_diff_L_vs_fixed_a1": rel_diff_factors(rd["UL"], rd["VL"], bf["UL"], bf["VL"])}
+        log(f"[bench] redraw_a1 {out['redraw_a1']['value']} iter/s")
     if not args.skip_completion:
         log("[bench] matrix completion: 10000 x 10000, 10 % unobserved")
         out["completion"] = run_completion(X, w, 10, 2)
