@@ -106,8 +106,10 @@ typedef struct {
    * drop to r' the first r' columns of each new draw are used.  Iteration 0
    * uses the seed's own draw, so the first step equals that of the default
    * mode.  0 (default): A1 is drawn once from the seed and kept (Algorithm 1
-   * does not redraw it).  The draws are made on the host and staged through
-   * pinned host memory while the device runs the previous iteration.
+   * does not redraw it).  The draws are made on the host, four iterations at
+   * a time, into pinned host memory while the device runs the iterations
+   * queued before, and each is copied to the device ahead of its iteration;
+   * godec_init allocates that memory and draws iterations 1 .. 4.
    * Excludes warm_start and a1_host; single-problem contexts only (the
    * batched form, the layer and godec_solve_static reject it). */
   int32_t redraw_a1;

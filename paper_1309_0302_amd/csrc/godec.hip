@@ -45,13 +45,18 @@ struct godec_ctx {
   int num_cu;
   int lstep = 0;                      // 1: projection form of the L update
   bool warm = false;                  // chains start from the previous Q2
-  // redraw_a1: iteration t draws A1 from seed + t; the draws are staged in
-  // two pinned host slots, each reused once the copy recorded after its
-  // last use has finished
+  // redraw_a1: iteration t draws A1 from seed + t.  The draws of
+  // kA1Chunk consecutive iterations are made together into one of two
+  // pinned host slots (a1_t0[s] = first iteration held, a1_cnt[s] = count);
+  // a slot is refilled once the copy recorded after its last use is done.
   bool redraw = false;
   double* a1_pin[2] = {nullptr, nullptr};
   hipEvent_t a1_ev[2] = {nullptr, nullptr};
   bool a1_ev_used[2] = {false, false};
+  int64_t a1_t0[2] = {-1, -1};
+  int a1_cnt[2] = {0, 0};
+  int a1_next = 0;
+  static constexpr int kA1Chunk = 4;
   const int64_t* support = nullptr;   // completion: fixed support of S
   int64_t support_nnz = 0;
   int64_t* row_ptr = nullptr;         // completion: m x (ncb + 1) run starts (see init)
@@ -286,6 +291,50 @@ double gaussian(uint64_t seed, uint64_t j) {
   const double rad = std::sqrt(-2.0 * std::log(u1));
   const double ang = (2.0 * M_PI) * u2;
   return rad * ((j % 2 == 0) ? std::cos(ang) : std::sin(ang));
+}
+
+// Gaussians j0 .. j1-1 of the stream of `seed` into out[0 .. j1-j0): the
+// same values as gaussian(seed, j), with each Box-Muller pair's logarithm
+// and square root taken once for both of its members.
+void gaussians(uint64_t seed, uint64_t j0, uint64_t j1, double* out) {
+  uint64_t j = j0;
+  if (j < j1 && (j & 1)) {
+    out[0] = gaussian(seed, j);
+    ++j;
+  }
+  for (; j + 1 < j1; j += 2) {
+    const double u1 = uniform53(seed, j);
+    const double u2 = uniform53(seed, j + 1);
+    const double rad = std::sqrt(-2.0 * std::log(u1));
+    const double ang = (2.0 * M_PI) * u2;
+    out[j - j0] = rad * std::cos(ang);
+    out[j + 1 - j0] = rad * std::sin(ang);
+  }
+  if (j < j1) out[j - j0] = gaussian(seed, j);
+}
+
+// count draws of n x r entries, draw d from seed0 + d into out + d n r,
+// split over up to 16 threads in contiguous ranges of the joint index.
+void draw_many(uint64_t seed0, int count, int64_t n, int32_t r, double* out) {
+  const uint64_t per = (uint64_t)n * (uint64_t)r;
+  const uint64_t total = per * (uint64_t)count;
+  unsigned nth = 1;
+  if (total >= (1u << 16))
+    nth = std::max(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
+  auto work = [&](unsigned w) {
+    uint64_t g = total * w / nth;
+    const uint64_t g1 = total * (w + 1) / nth;
+    while (g < g1) {
+      const uint64_t d = g / per, j = g % per;
+      const uint64_t e = std::min(g1 - g, per - j);
+      gaussians(seed0 + d, j, j + e, out + g);
+      g += e;
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned w = 1; w < nth; ++w) th.emplace_back(work, w);
+  work(0);
+  for (auto& t : th) t.join();
 }
 
 Launch launch_of(const godec_ctx* c) { return Launch{c->stream, c->num_cu}; }
@@ -548,20 +597,9 @@ void godec_opts_default(godec_opts* o) {
 
 godec_status godec_draw_a1(uint64_t seed, int64_t n, int32_t r, double* a1_host) {
   if (n < 1 || r < 1 || !a1_host) return fail(GODEC_E_INVAL, "bad arguments");
-  const uint64_t total = (uint64_t)n * (uint64_t)r;
-  // entry j depends on (seed, j) only, so large draws are split over
-  // threads in contiguous ranges (same values as one thread)
-  unsigned nth = 1;
-  if (total >= (1u << 16))
-    nth = std::max(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
-  auto work = [&](unsigned w) {
-    const uint64_t j0 = total * w / nth, j1 = total * (w + 1) / nth;
-    for (uint64_t j = j0; j < j1; ++j) a1_host[j] = gaussian(seed, j);
-  };
-  std::vector<std::thread> th;
-  for (unsigned w = 1; w < nth; ++w) th.emplace_back(work, w);
-  work(0);
-  for (auto& t : th) t.join();
+  // entry j depends on (seed, j) only, so the result does not depend on
+  // how the range is split over threads
+  draw_many(seed, 1, n, r, a1_host);
   return GODEC_OK;
 }
 
@@ -672,12 +710,25 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
     godec_draw_a1(seed, n, r, c->a1_host.data());
   const Launch L = launch_of(c);
   auto cleanup = [&](godec_status st, const std::string& msg) {
-    delete c;
+    godec_destroy(c);   // also frees the pinned staging slots
     return fail(st, msg);
   };
   hipError_t e = hipMemcpyAsync(c->A1, c->a1_host.data(), sizeof(double) * n * r,
                                 hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
+  if (c->redraw) {
+    // both staging slots, and the draws of iterations 1 .. kA1Chunk
+    const size_t slot = sizeof(double) * (size_t)n * r * godec_ctx::kA1Chunk;
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+      e = hipHostMalloc((void**)&c->a1_pin[q], slot, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->a1_ev[q], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
+    draw_many(seed + 1, godec_ctx::kA1Chunk, n, r, c->a1_pin[0]);
+    c->a1_t0[0] = 1;
+    c->a1_cnt[0] = godec_ctx::kA1Chunk;
+    c->a1_next = 1;
+  }
   if (c->D16) {
     launch_init_d(L, BF16, false, c->D16, c->ldd, X_dev, ldx, m, n, c->mpad);
     c->d_native_valid = false;
@@ -732,21 +783,30 @@ godec_status capture_iteration(godec_ctx* c, int64_t t, int64_t total, hipGraphE
   return GODEC_OK;
 }
 
-// redraw_a1: draw A1 of iteration t (from seed + t) into a pinned slot and
-// queue its copy to the device A1 ahead of the iteration.  The draw runs on
-// the host while the device works through the iterations already queued.
-static godec_status stage_a1(godec_ctx* c, int64_t t) {
-  const size_t bytes = sizeof(double) * (size_t)c->n * c->r;
-  const int s = (int)(t & 1);
-  if (!c->a1_pin[s]) {
-    HIP_TRY(hipHostMalloc((void**)&c->a1_pin[s], bytes, hipHostMallocDefault));
-    HIP_TRY(hipEventCreateWithFlags(&c->a1_ev[s], hipEventDisableTiming));
+// redraw_a1: queue the copy of iteration t's A1 (from seed + t) to the
+// device A1 ahead of the iteration.  When no slot holds it, the draws of
+// iterations t .. t + kA1Chunk - 1 (not past the solve's end) are made into
+// the other slot; that happens on the host while the device works through
+// the chunk of iterations queued before.  (godec_init allocates both slots
+// and draws the first chunk, iterations 1 .. kA1Chunk.)
+static godec_status stage_a1(godec_ctx* c, int64_t t, int64_t total) {
+  const size_t one = (size_t)c->n * c->r;
+  int s = -1;
+  for (int q = 0; q < 2; ++q)
+    if (c->a1_t0[q] >= 0 && t >= c->a1_t0[q] && t < c->a1_t0[q] + c->a1_cnt[q]) s = q;
+  if (s < 0) {
+    s = c->a1_next;
+    c->a1_next ^= 1;
+    // every copy out of the slot has left the host buffer
+    if (c->a1_ev_used[s]) HIP_TRY(hipEventSynchronize(c->a1_ev[s]));
+    const int cnt = (int)std::max<int64_t>(1, std::min<int64_t>(godec_ctx::kA1Chunk, total - t));
+    c->a1_t0[s] = -1;
+    draw_many(c->seed + (uint64_t)t, cnt, c->n, c->r, c->a1_pin[s]);
+    c->a1_t0[s] = t;
+    c->a1_cnt[s] = cnt;
   }
-  // the slot's previous copy has left the host buffer
-  if (c->a1_ev_used[s]) HIP_TRY(hipEventSynchronize(c->a1_ev[s]));
-  godec_status st = godec_draw_a1(c->seed + (uint64_t)t, c->n, c->r, c->a1_pin[s]);
-  if (st != GODEC_OK) return st;
-  HIP_TRY(hipMemcpyAsync(c->A1, c->a1_pin[s], bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->A1, c->a1_pin[s] + (size_t)(t - c->a1_t0[s]) * one,
+                         sizeof(double) * one, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipEventRecord(c->a1_ev[s], c->stream));
   c->a1_ev_used[s] = true;
   return GODEC_OK;
@@ -763,7 +823,7 @@ godec_status godec_step(godec_ctx* c, int32_t iters, int32_t total_iters) {
     // iteration 0 uses the draw of godec_init (seed + 0); the copy of a
     // later draw is queued ahead of the iteration, outside any graph
     if (c->redraw && t > 0) {
-      godec_status s = stage_a1(c, t);
+      godec_status s = stage_a1(c, t, total);
       if (s != GODEC_OK) return s;
     }
     // the first iteration, the refinement iterations (which rebuild the FP32
