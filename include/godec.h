@@ -107,9 +107,11 @@ typedef struct {
    * uses the seed's own draw, so the first step equals that of the default
    * mode.  0 (default): A1 is drawn once from the seed and kept (Algorithm 1
    * does not redraw it).  The draws are made on the host, four iterations at
-   * a time, into pinned host memory while the device runs the iterations
-   * queued before, and each is copied to the device ahead of its iteration;
-   * godec_init allocates that memory and draws iterations 1 .. 4.
+   * a time, while the device runs the iterations queued before; each chunk
+   * is uploaded on a stream of the library's own into two workspace slots
+   * (counted by godec_workspace_size), and each draw is copied into place
+   * on opts->stream ahead of its iteration.  godec_init sets this up and
+   * draws iterations 1 .. 4.
    * Excludes warm_start and a1_host; single-problem contexts only (the
    * batched form, the layer and godec_solve_static reject it). */
   int32_t redraw_a1;

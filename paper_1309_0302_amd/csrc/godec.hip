@@ -46,13 +46,20 @@ struct godec_ctx {
   int lstep = 0;                      // 1: projection form of the L update
   bool warm = false;                  // chains start from the previous Q2
   // redraw_a1: iteration t draws A1 from seed + t.  The draws of
-  // kA1Chunk consecutive iterations are made together into one of two
-  // pinned host slots (a1_t0[s] = first iteration held, a1_cnt[s] = count);
-  // a slot is refilled once the copy recorded after its last use is done.
+  // kA1Chunk consecutive iterations are made together into slot s, a pinned
+  // host buffer a1_pin[s] and its device copy in a1_dev (a1_t0[s] = first
+  // iteration held, a1_cnt[s] = count).  The host-to-device copy of a slot
+  // runs on a1_stream (a1_up[s] recorded after it); each iteration's draw
+  // then goes from the device slot to A1 on the caller's stream (a1_rd[s]
+  // recorded after the last such copy out of slot s).
   bool redraw = false;
+  double* a1_dev = nullptr;
   double* a1_pin[2] = {nullptr, nullptr};
-  hipEvent_t a1_ev[2] = {nullptr, nullptr};
-  bool a1_ev_used[2] = {false, false};
+  hipStream_t a1_stream = nullptr;
+  hipEvent_t a1_up[2] = {nullptr, nullptr};
+  hipEvent_t a1_rd[2] = {nullptr, nullptr};
+  bool a1_used[2] = {false, false};
+  bool a1_waited[2] = {false, false};   // the caller's stream waits on a1_up[s]
   int64_t a1_t0[2] = {-1, -1};
   int a1_cnt[2] = {0, 0};
   int a1_next = 0;
@@ -173,6 +180,10 @@ size_t carve(godec_ctx* c, void* base) {
     c->Wtpart = c->Zpart32 = nullptr;
   }
   c->A1 = (double*)cv.take((size_t)c->n * c->r * 8);
+  // redraw_a1: two device slots of kA1Chunk draws each
+  c->a1_dev = c->redraw
+                  ? (double*)cv.take((size_t)2 * godec_ctx::kA1Chunk * c->n * c->r * 8)
+                  : nullptr;
   c->P0 = cv.take((size_t)ldd * rp * ta);
   c->P1 = cv.take((size_t)ldd * rp * ta);
   c->VL = cv.take((size_t)ldd * rp * ta);
@@ -268,6 +279,7 @@ void fill_ctx_params(godec_ctx* c, int64_t m, int64_t n, int32_t r, int64_t k,
   c->cap = s.cap;
   c->kc_a = s.kc_a; c->nct_a = s.nct_a; c->rc_b = s.rc_b; c->nch_b = s.nch_b;
   c->completion = o && (o->support_dev != nullptr || o->support_nnz != 0);
+  c->redraw = o && o->redraw_a1;
 }
 
 // Counter-based SplitMix64 (Steele, Lea, Flood 2014): output i of the stream
@@ -628,6 +640,8 @@ godec_status godec_workspace_size(int64_t m, int64_t n, int32_t r, int64_t k, in
   return GODEC_OK;
 }
 
+static godec_status fill_a1_slot(godec_ctx* c, int s, int64_t t0, int cnt);
+
 godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, int64_t m,
                         int64_t n, int64_t ldx, int32_t r, int64_t k, int32_t q, uint64_t seed,
                         void* ws, size_t ws_bytes, const godec_opts* opts) {
@@ -647,7 +661,6 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
   c->X = X_dev;
   c->lstep = opts ? opts->lstep : 0;
   c->warm = opts && opts->warm_start;
-  c->redraw = opts && opts->redraw_a1;
   c->stream = opts ? (hipStream_t)opts->stream : nullptr;
   const size_t need = carve(c, nullptr);
   if (ws_bytes < need) {
@@ -717,16 +730,21 @@ godec_status godec_init(godec_ctx** out, const void* X_dev, godec_dtype dtype, i
                                 hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
   if (c->redraw) {
-    // both staging slots, and the draws of iterations 1 .. kA1Chunk
+    // both staging slots, the side stream, and the draws of iterations
+    // 1 .. kA1Chunk in slot 0
     const size_t slot = sizeof(double) * (size_t)n * r * godec_ctx::kA1Chunk;
+    e = hipStreamCreateWithFlags(&c->a1_stream, hipStreamNonBlocking);
     for (int q = 0; q < 2 && e == hipSuccess; ++q) {
       e = hipHostMalloc((void**)&c->a1_pin[q], slot, hipHostMallocDefault);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->a1_ev[q], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->a1_up[q], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->a1_rd[q], hipEventDisableTiming);
     }
     if (e != hipSuccess) return cleanup(GODEC_E_DEVICE, hipGetErrorString(e));
-    draw_many(seed + 1, godec_ctx::kA1Chunk, n, r, c->a1_pin[0]);
-    c->a1_t0[0] = 1;
-    c->a1_cnt[0] = godec_ctx::kA1Chunk;
+    godec_status st = fill_a1_slot(c, 0, 1, godec_ctx::kA1Chunk);
+    if (st != GODEC_OK) {
+      godec_destroy(c);
+      return st;
+    }
     c->a1_next = 1;
   }
   if (c->D16) {
@@ -783,12 +801,34 @@ godec_status capture_iteration(godec_ctx* c, int64_t t, int64_t total, hipGraphE
   return GODEC_OK;
 }
 
-// redraw_a1: queue the copy of iteration t's A1 (from seed + t) to the
-// device A1 ahead of the iteration.  When no slot holds it, the draws of
-// iterations t .. t + kA1Chunk - 1 (not past the solve's end) are made into
-// the other slot; that happens on the host while the device works through
-// the chunk of iterations queued before.  (godec_init allocates both slots
-// and draws the first chunk, iterations 1 .. kA1Chunk.)
+// redraw_a1: fill slot s with the draws of iterations t0 .. t0 + cnt - 1
+// and queue their host-to-device copy on the side stream.  The draws are
+// made on the host while the device works through the iterations queued
+// before.
+static godec_status fill_a1_slot(godec_ctx* c, int s, int64_t t0, int cnt) {
+  const size_t one = (size_t)c->n * c->r;
+  // the slot's last upload has left the host buffer
+  if (c->a1_used[s]) HIP_TRY(hipEventSynchronize(c->a1_up[s]));
+  c->a1_t0[s] = -1;
+  draw_many(c->seed + (uint64_t)t0, cnt, c->n, c->r, c->a1_pin[s]);
+  c->a1_t0[s] = t0;
+  c->a1_cnt[s] = cnt;
+  // the device slot is overwritten after the last copy out of it
+  if (c->a1_used[s]) HIP_TRY(hipStreamWaitEvent(c->a1_stream, c->a1_rd[s], 0));
+  HIP_TRY(hipMemcpyAsync(c->a1_dev + (size_t)s * godec_ctx::kA1Chunk * one, c->a1_pin[s],
+                         sizeof(double) * one * cnt, hipMemcpyHostToDevice, c->a1_stream));
+  HIP_TRY(hipEventRecord(c->a1_up[s], c->a1_stream));
+  c->a1_used[s] = true;
+  c->a1_waited[s] = false;
+  return GODEC_OK;
+}
+
+// redraw_a1: queue the copy of iteration t's A1 (from seed + t) into the
+// device A1 ahead of the iteration, on the caller's stream and outside any
+// recorded graph.  When no slot holds it, the draws of iterations t ..
+// t + kA1Chunk - 1 (not past the solve's end) go to the other slot first.
+// (godec_init sets up both slots and fills slot 0 with iterations
+// 1 .. kA1Chunk.)
 static godec_status stage_a1(godec_ctx* c, int64_t t, int64_t total) {
   const size_t one = (size_t)c->n * c->r;
   int s = -1;
@@ -797,18 +837,21 @@ static godec_status stage_a1(godec_ctx* c, int64_t t, int64_t total) {
   if (s < 0) {
     s = c->a1_next;
     c->a1_next ^= 1;
-    // every copy out of the slot has left the host buffer
-    if (c->a1_ev_used[s]) HIP_TRY(hipEventSynchronize(c->a1_ev[s]));
-    const int cnt = (int)std::max<int64_t>(1, std::min<int64_t>(godec_ctx::kA1Chunk, total - t));
-    c->a1_t0[s] = -1;
-    draw_many(c->seed + (uint64_t)t, cnt, c->n, c->r, c->a1_pin[s]);
-    c->a1_t0[s] = t;
-    c->a1_cnt[s] = cnt;
+    const int cnt =
+        (int)std::max<int64_t>(1, std::min<int64_t>(godec_ctx::kA1Chunk, total - t));
+    godec_status st = fill_a1_slot(c, s, t, cnt);
+    if (st != GODEC_OK) return st;
   }
-  HIP_TRY(hipMemcpyAsync(c->A1, c->a1_pin[s] + (size_t)(t - c->a1_t0[s]) * one,
-                         sizeof(double) * one, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipEventRecord(c->a1_ev[s], c->stream));
-  c->a1_ev_used[s] = true;
+  // one wait per fill of the slot; the slot's iterations are staged in
+  // order, so the copy of its last iteration is the last read of it
+  if (!c->a1_waited[s]) {
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->a1_up[s], 0));
+    c->a1_waited[s] = true;
+  }
+  HIP_TRY(hipMemcpyAsync(c->A1,
+                         c->a1_dev + ((size_t)s * godec_ctx::kA1Chunk + (t - c->a1_t0[s])) * one,
+                         sizeof(double) * one, hipMemcpyDeviceToDevice, c->stream));
+  if (t == c->a1_t0[s] + c->a1_cnt[s] - 1) HIP_TRY(hipEventRecord(c->a1_rd[s], c->stream));
   return GODEC_OK;
 }
 
@@ -947,13 +990,13 @@ godec_status godec_destroy(godec_ctx* c) {
     for (const auto& ge : c->gcache) (void)hipGraphExecDestroy(ge.exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    if (c->a1_stream) (void)hipStreamSynchronize(c->a1_stream);
     for (int s = 0; s < 2; ++s) {
-      if (c->a1_ev[s]) {
-        (void)hipEventSynchronize(c->a1_ev[s]);
-        (void)hipEventDestroy(c->a1_ev[s]);
-      }
+      if (c->a1_up[s]) (void)hipEventDestroy(c->a1_up[s]);
+      if (c->a1_rd[s]) (void)hipEventDestroy(c->a1_rd[s]);
       if (c->a1_pin[s]) (void)hipHostFree(c->a1_pin[s]);
     }
+    if (c->a1_stream) (void)hipStreamDestroy(c->a1_stream);
     delete c;
   }
   return GODEC_OK;

@@ -119,7 +119,8 @@ def test_warm_start_checked(lib):
 
 def test_redraw_a1_checked(lib):
     o, _ = b.make_opts(redraw_a1=1)
-    assert _ws(100, 100, 4, 10, 1, opts=o) == _ws(100, 100, 4, 10, 1)
+    # plus two device slots of four n x r FP64 draws
+    assert _ws(100, 100, 4, 10, 1, opts=o) >= _ws(100, 100, 4, 10, 1) + 2 * 4 * 100 * 4 * 8
     for kw in ({"redraw_a1": 2}, {"redraw_a1": 1, "warm_start": 1},
                {"redraw_a1": 1, "a1": np.zeros((100, 4))}):
         o, _keep = b.make_opts(**kw)
