@@ -15,8 +15,9 @@ Readings of the paper (where it is silent or ambiguous) used here:
 R1  The loop test of Algorithm 1 is evaluated after each iteration (with
     L_0 = X and S_0 = 0 it would be false before the first one), and the
     workloads fix the iteration count T instead of a tolerance.
-R2  A1 is drawn once and kept for all iterations; Algorithm 1 then builds A2
-    from Y1 as Sec. 3.1.1 describes, so no independent A2 is used.
+R2  By default A1 is drawn once and kept for all iterations (R15 covers a
+    redrawn A1); Algorithm 1 then builds A2 from Y1 as Sec. 3.1.1 describes,
+    so no independent A2 is used.
 R3  The operator L~ = [(X - S)(X - S)^T]^q (X - S) is never formed: L~ Z is
     evaluated right to left as a chain of products with D and D^T, which is
     the same matrix product by associativity.
