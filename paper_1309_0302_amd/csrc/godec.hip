@@ -344,7 +344,14 @@ void draw_many(uint64_t seed0, int count, int64_t n, int32_t r, double* out) {
     }
   };
   std::vector<std::thread> th;
-  for (unsigned w = 1; w < nth; ++w) th.emplace_back(work, w);
+  for (unsigned w = 1; w < nth; ++w) {
+    // a thread that cannot be started leaves its share to this one
+    try {
+      th.emplace_back(work, w);
+    } catch (...) {
+      work(w);
+    }
+  }
   work(0);
   for (auto& t : th) t.join();
 }

@@ -196,7 +196,14 @@ void draw_chunk(godec_mse* m, int s, int64_t t0, int count) {
     }
   };
   std::vector<std::thread> th;
-  for (unsigned w = 1; w < nth; ++w) th.emplace_back(work, w);
+  for (unsigned w = 1; w < nth; ++w) {
+    // a thread that cannot be started leaves its share to this one
+    try {
+      th.emplace_back(work, w);
+    } catch (...) {
+      work(w);
+    }
+  }
   work(0);
   for (auto& t : th) t.join();
 }
