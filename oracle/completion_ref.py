@@ -48,14 +48,19 @@ def fixed_support_step(R: np.ndarray, support: np.ndarray) -> np.ndarray:
 
 
 def godec_completion(X, r, q, A1, support, iters, eps=None, rank_tol=None):
-    """Algorithm 1 with the S update on a fixed support (readings C1-C3)."""
+    """Algorithm 1 with the S update on a fixed support (readings C1-C3).
+    A1 may be a function of the iteration index t (from 0) that returns that
+    iteration's draw (godec_ref's reading R15)."""
     X = np.asarray(X, dtype=np.float64)
     support = np.asarray(support, dtype=np.int64)
     S = np.zeros_like(X)
     xx = float(np.sum(X * X))
-    A = np.asarray(A1, dtype=np.float64)[:, :r]
+    redraw = callable(A1)
+    A = np.asarray(A1(0) if redraw else A1, dtype=np.float64)[:, :r]
     tr = CompletionTrace(L=X.copy(), S=S, left=None, right=None, r_eff=r)
-    for _ in range(iters):
+    for t in range(iters):
+        if redraw and t > 0:
+            A = np.asarray(A1(t), dtype=np.float64)[:, :A.shape[1]]
         res = godec_ref.brp_power(X - S, A, q, rank_tol)
         A = A[:, :res.r_eff]
         R = X - res.L

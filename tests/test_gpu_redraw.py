@@ -135,3 +135,33 @@ def test_static_entry_rejects_redraw():
     with pytest.raises(bd.GodecError) as ei:
         bd.godec_solve_static(dev(w.X), 3, w.k, 1, 2, 3, opts=o)
     assert "redraw_a1" in str(ei.value)
+
+
+def test_f64_completion_with_redrawn_a1():
+    """The fixed-support S update with a new A1 per iteration against the
+    completion oracle's redrawn run (no discrete decisions on a fixed
+    support, so the FP64 bar is 1e-10 over the whole run), and exact
+    completion of a rank-3 matrix."""
+    from oracle import completion_ref as cr
+    from paper_1309_0302_amd.binding import GoDec
+    rng = np.random.default_rng(66)
+    m, n, r = 150, 110, 3
+    X0 = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    miss = np.sort(rng.choice(m * n, size=int(0.3 * m * n), replace=False))
+    for noise, T in ((1e-2, 10), (0.0, 100)):
+        X = X0 + noise * np.random.default_rng(67).standard_normal((m, n))
+        X.flat[miss] = 0.0
+        sup = torch.from_numpy(miss.astype(np.int64)).cuda()
+        print(f"\n[redraw] completion 150 x 110 FP64 noise={noise} T={T}", flush=True)
+        gd = GoDec(dev(X), r, int(miss.size), 1, seed=21, support=sup, redraw_a1=1)
+        try:
+            gd.step(T)
+            L = gd.L_dense().cpu().numpy()
+            ref = cr.godec_completion(X, r, 1, draws(21, n, r), miss, T)
+            eL = g.rel_fro(L, ref.L)
+            print(f"  L vs oracle {eL:.2e}", flush=True)
+            assert eL < 1e-10
+            if noise == 0.0:
+                assert g.rel_fro(L, X0) < 1e-10
+        finally:
+            gd.close()

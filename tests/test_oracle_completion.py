@@ -7,7 +7,8 @@ constraint replaced by a fixed support set).  CPU only.
 - The imputation invariant: D = X - S_t equals X on the observed entries
   and L_t on the unobserved ones.
 - The S step zeroes the residual on the support (its exact minimiser).
-- With an empty support every iteration equals brp_power on X.
+- With an empty support every iteration equals brp_power on X, also with a
+  new A1 per iteration (the draw of that iteration).
 - Planted mistakes are caught.
 """
 import inspect
@@ -56,6 +57,22 @@ def test_empty_support_is_plain_brp():
     ref = g.brp_power(X, A1, 1)
     assert np.linalg.norm(tr.L - ref.L) <= 1e-12 * np.linalg.norm(ref.L)
     assert not tr.S.any()
+
+
+@pytest.mark.parametrize("iters", [1, 3])
+def test_empty_support_redrawn_a1_uses_the_iterations_draw(iters):
+    """With an empty support S stays 0, so with a new A1 per iteration the
+    last iteration's L is brp_power on X with the last draw, A1(iters - 1);
+    with q = 0 on a noisy X that L depends on A1, so another iteration's
+    draw gives another L."""
+    _, X, _, _ = _case(seed=9)
+    X = X + 0.1 * np.random.default_rng(10).standard_normal(X.shape)
+    draw = lambda t: np.random.default_rng(50 + t).standard_normal((X.shape[1], 3))
+    tr = c.godec_completion(X, 3, 0, draw, np.zeros(0, np.int64), iters)
+    ref = g.brp_power(X, draw(iters - 1), 0)
+    assert np.linalg.norm(tr.L - ref.L) <= 1e-12 * np.linalg.norm(ref.L)
+    other = g.brp_power(X, draw(iters), 0)
+    assert np.linalg.norm(tr.L - other.L) > 1e-6 * np.linalg.norm(ref.L)
 
 
 def _mutant(func, old, new):
