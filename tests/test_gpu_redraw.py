@@ -165,3 +165,29 @@ def test_f64_completion_with_redrawn_a1():
                 assert g.rel_fro(L, X0) < 1e-10
         finally:
             gd.close()
+
+
+def test_solve_tol_with_redrawn_a1():
+    """godec_solve_tol with a new A1 per iteration stops where the oracle's
+    redrawn run first meets the loop test, with the same factors as that
+    many steps of a context (draws are staged for max_iters iterations, so
+    the solve ends with unused draws in flight)."""
+    from paper_1309_0302_amd import binding as bd
+    w = wl.tiny(300, 200, 5, seed=22, dtype=np.float64)
+    n = w.X.shape[1]
+    tr = g.godec_brp(w.X, 5, w.k, 1, draws(99, n, 5), 12)
+    errs = np.asarray(tr.rel_err_sq)
+    assert errs[2] > 1.01 * errs[3]
+    eps = float(np.sqrt(errs[2] * errs[3]))
+    expect = int(np.argmax(errs <= eps)) + 1
+    print(f"\n[redraw] solve_tol: errors {errs[:6]}, eps {eps:.3e}, expect {expect}", flush=True)
+    o, _ = bd.make_opts(redraw_a1=1)
+    UL, VL, _, _, info = bd.godec_solve_tol(dev(w.X), 5, w.k, 1, 99, 12, eps, o)
+    assert info["iters"] == expect
+    gd = bd.GoDec(dev(w.X), 5, w.k, 1, seed=99, redraw_a1=1)
+    try:
+        gd.step(expect)
+        U2, _ = gd.factors()
+        assert np.array_equal(UL.cpu().numpy(), U2.cpu().numpy())
+    finally:
+        gd.close()
